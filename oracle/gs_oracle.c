@@ -1,0 +1,809 @@
+/*
+ * gs_oracle.c -- plain FP64 CPU oracle of the 3D-GS tile-rendering path with
+ * AdaGScale (Jo et al., "AdaGScale: Viewpoint-Adaptive Gaussian Scaling in 3D
+ * Gaussian Splatting to Reduce Gaussian-Tile Pairs").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code with
+ * the HIP path; it is slow on purpose and written so that each step can be
+ * checked against the paper by eye:
+ *
+ *   preprocess   Sec. 2.1 (cull, EWA projection, colour, depth) and, for
+ *                AdaGScale, eq. (10) for Th, the Th > opacity cull of Sec. 3.3
+ *                and the reduced extent used by the tile test (Sec. 3.1, 3.3)
+ *   emit         Sec. 2.1: one (tile, depth, Gaussian) pair per intersected tile
+ *   sort         Sec. 2.1: pairs ordered by depth inside each tile
+ *   ranges       start/end of every tile's run in the sorted list
+ *   blend        eq. (1) and eq. (2) with tau = 1/255 and the 1e-4 early exit,
+ *                original covariance and tau in both modes (dual size, Sec. 3.3)
+ *   backward     analytic adjoint of the above with every discrete decision
+ *                frozen (pair set, skips, stop, clamps)
+ *
+ * Every floating-point value is double.  Compile with -ffp-contract=off so each
+ * expression is rounded exactly as written.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define TILE 16
+#define TAU (1.0 / 255.0)        /* alpha threshold, Sec. 2.1 */
+#define T_STOP 1e-4              /* early-exit transmittance, Sec. 2.1 */
+#define ALPHA_MAX 0.99           /* alpha clamp */
+#define NEAR_Z 0.2               /* near-plane cull */
+#define DILATION 0.3             /* low-pass added to the 2D covariance */
+#define FRUSTUM_SLACK 1.3        /* clamp of x/z and y/z in the EWA Jacobian */
+#define LAMBDA_FLOOR 0.1         /* floor of the eigenvalue discriminant */
+#define LUT_BINS 20              /* T_upper depth bins, Sec. 3.4 */
+#define TWO_PI 6.283185307179586 /* 2*pi rounded to double */
+
+/* ------------------------------------------------------------------------ */
+/* Real spherical harmonics, written from their definition.                  */
+/*                                                                           */
+/*   Y_l^0      = N_l0 P_l(z)                                                */
+/*   Y_l^{+m}   = sqrt(2) N_lm (-1)^m P_l^(m)(z) Re((x+iy)^m)                 */
+/*   Y_l^{-m}   = sqrt(2) N_lm (-1)^m P_l^(m)(z) Im((x+iy)^m)                 */
+/*                                                                           */
+/* with N_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!), P_l the Legendre           */
+/* polynomial, P_l^(m) its m-th derivative (so (-1)^m sin^m(theta) P_l^(m)   */
+/* is the associated Legendre function with the Condon-Shortley phase) and   */
+/* (x, y, z) a unit direction.  Coefficient k = l*l + l + m.                  */
+/* ------------------------------------------------------------------------ */
+#define SH_LMAX 3
+
+static double factorial(int n) { double f = 1.0; for (int i = 2; i <= n; ++i) f *= i; return f; }
+
+/* Coefficients (ascending powers of z) of P_l, from Bonnet's recurrence
+ * (n+1) P_{n+1} = (2n+1) z P_n - n P_{n-1}. */
+static void legendre_coeffs(int l, double c[SH_LMAX + 1]) {
+    double p0[SH_LMAX + 2] = {1.0}, p1[SH_LMAX + 2] = {0.0, 1.0}, p2[SH_LMAX + 2];
+    memset(c, 0, sizeof(double) * (SH_LMAX + 1));
+    if (l == 0) { c[0] = 1.0; return; }
+    for (int n = 1; n < l; ++n) {
+        memset(p2, 0, sizeof(p2));
+        for (int i = 0; i <= n; ++i) p2[i + 1] += (2.0 * n + 1.0) * p1[i];
+        for (int i = 0; i <= n; ++i) p2[i] -= n * p0[i];
+        for (int i = 0; i <= n + 1; ++i) p2[i] /= (n + 1.0);
+        memcpy(p0, p1, sizeof(p0));
+        memcpy(p1, p2, sizeof(p1));
+    }
+    for (int i = 0; i <= l; ++i) c[i] = p1[i];
+}
+
+/* value of d^m/dz^m of P_l at z, and (if dval) of d^{m+1}/dz^{m+1} */
+static double legendre_deriv(int l, int m, double z, double *dval) {
+    double c[SH_LMAX + 1];
+    legendre_coeffs(l, c);
+    for (int k = 0; k < m; ++k) {             /* differentiate m times */
+        for (int i = 0; i < l; ++i) c[i] = c[i + 1] * (i + 1);
+        c[l] = 0.0;
+    }
+    double v = 0.0, dv = 0.0, zp = 1.0;
+    for (int i = 0; i <= l; ++i) { v += c[i] * zp; zp *= z; }
+    zp = 1.0;
+    for (int i = 1; i <= l; ++i) { dv += c[i] * i * zp; zp *= z; }
+    if (dval) *dval = dv;
+    return v;
+}
+
+/* Re and Im of (x + i y)^m, and their partials in x and y. */
+static void zpow(int m, double x, double y, double *re, double *im) {
+    double r = 1.0, i = 0.0;
+    for (int k = 0; k < m; ++k) { double nr = r * x - i * y; i = r * y + i * x; r = nr; }
+    *re = r; *im = i;
+}
+
+/* Basis values Y[k] and (optionally) gradients dY[k][3] with respect to the
+ * Cartesian components, for the unit direction d. */
+void orc_sh_basis(int degree, const double d[3], double *Y, double *dY) {
+    for (int l = 0; l <= degree; ++l) {
+        for (int m = -l; m <= l; ++m) {
+            int am = m < 0 ? -m : m, k = l * l + l + m;
+            double N = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * factorial(l - am) / factorial(l + am));
+            double dq, q = legendre_deriv(l, am, d[2], &dq);
+            double re, im, re1 = 0.0, im1 = 0.0;
+            zpow(am, d[0], d[1], &re, &im);
+            if (am > 0) zpow(am - 1, d[0], d[1], &re1, &im1);
+            double sgn = (am % 2) ? -1.0 : 1.0;
+            double f = (m == 0) ? N : sqrt(2.0) * N * sgn;
+            double ang = (m >= 0) ? re : im;
+            /* d/dx (x+iy)^m = m (x+iy)^(m-1); d/dy = i m (x+iy)^(m-1) */
+            double dang_dx = (m >= 0) ? am * re1 : am * im1;
+            double dang_dy = (m >= 0) ? -am * im1 : am * re1;
+            Y[k] = f * q * ang;
+            if (dY) {
+                dY[3 * k + 0] = f * q * dang_dx;
+                dY[3 * k + 1] = f * q * dang_dy;
+                dY[3 * k + 2] = f * dq * ang;
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* AdaGScale threshold and extent (Sec. 3.2 eq. (10), Sec. 3.3).             */
+/*                                                                           */
+/* The approximated peripheral score of eq. (9) grows linearly in x, so the  */
+/* largest x with PS(x) <= K (eq. (5)) is eq. (10):                          */
+/*     Th = K / (T_up(depth) * 2 pi * sqrt(det(G_cov))) + tau.               */
+/* A Gaussian whose Th reaches its opacity is dropped for this view.  The     */
+/* tile test then uses the region alpha >= Th instead of alpha >= tau.  For   */
+/* a 2D Gaussian, alpha >= t is the ellipse of Mahalanobis radius            */
+/* sqrt(2 ln(sigma/t)), so raising the threshold from tau to Th shrinks every */
+/* axis by s = sqrt(ln(sigma/Th) / ln(sigma/tau)); the plain extent v is      */
+/* scaled by s.                                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Plain extent: 3 standard deviations along the major axis of the 2D
+ * covariance (a, b; b, c), with the discriminant floored as in the original
+ * 3D-GS rasterizer. */
+double orc_plain_extent(double a, double b, double c) {
+    double det = a * c - b * b;
+    double mid = 0.5 * (a + c);
+    double disc = mid * mid - det;
+    if (disc < LAMBDA_FLOOR) disc = LAMBDA_FLOOR;
+    double lam = mid + sqrt(disc);
+    return 3.0 * sqrt(lam);
+}
+
+/* Returns 1 if the Gaussian survives.  Outputs Th (eq. 10) and s. */
+int orc_adagscale(double det, double sigma, double depth, double K, const float *t_upper,
+                  double lut_depth_max, int force_unit_scale, double *th, double *s) {
+    double f = (depth * LUT_BINS) / lut_depth_max;
+    int bin = (f >= LUT_BINS - 1) ? LUT_BINS - 1 : (int)floor(f);
+    double tu = (double)t_upper[bin];
+    if (!(tu > 0.0)) { *th = INFINITY; *s = 0.0; return 0; }
+    double denom = (tu * TWO_PI) * sqrt(det);
+    *th = K / denom + TAU;
+    if (*th >= sigma) { *s = 0.0; return 0; }
+    *s = force_unit_scale ? 1.0 : sqrt(log(sigma / *th) / log(sigma / TAU));
+    return 1;
+}
+
+static int is_finite(double x) { return x == x && fabs(x) <= 1.79769313486231570815e308; }
+
+/* ------------------------------------------------------------------------ */
+/* Preprocess (Sec. 2.1; AdaGScale additions Sec. 3.3).                      */
+/*                                                                           */
+/* Inputs are float32 structure-of-arrays, [C][N]; cam[0..11] is the          */
+/* row-major [R|t] world-to-camera matrix, cam[12..15] = fx, fy, cx, cy.      */
+/* Outputs (double, [N][k]): mean2d[2], conic[3] (inverse 2D covariance      */
+/* entries A, B, C with power = -A dx^2/2 - C dy^2/2 - B dx dy), opacity,     */
+/* rgb[3], depth, cov2d[3] (dilated a, b, c), extent (plain v), th, scale,    */
+/* rect[4] (x0, y0, x1, y1 half-open, tiles), tiles_touched, radius (int).    */
+/* flags: 0 culled, 1 projected (finite, in front), 2 projected with tiles.   */
+/* ------------------------------------------------------------------------ */
+void orc_preprocess(int64_t n, const float *means, const float *log_scales, const float *quats,
+                    const float *opacity_logits, const float *sh, int sh_degree,
+                    const float *cam, int width, int height,
+                    int adagscale, double K, const float *t_upper, double lut_depth_max,
+                    int force_unit_scale,
+                    double *mean2d, double *conic, double *opacity, double *rgb, double *depth,
+                    double *cov2d, double *extent, double *th, double *scale,
+                    int32_t *rect, int64_t *tiles_touched, int32_t *radius, int32_t *flags) {
+    double W[3][3], t[3];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) W[i][j] = cam[4 * i + j];
+        t[i] = cam[4 * i + 3];
+    }
+    double fx = cam[12], fy = cam[13], cx = cam[14], cy = cam[15];
+    int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
+    int nsh = (sh_degree + 1) * (sh_degree + 1);
+    /* camera centre in world coordinates: -R^T t */
+    double campos[3];
+    for (int j = 0; j < 3; ++j) campos[j] = -(W[0][j] * t[0] + W[1][j] * t[1] + W[2][j] * t[2]);
+
+    for (int64_t g = 0; g < n; ++g) {
+        flags[g] = 0; tiles_touched[g] = 0; radius[g] = 0;
+        for (int k = 0; k < 4; ++k) rect[4 * g + k] = 0;
+        double mu[3] = {means[g], means[n + g], means[2 * n + g]};
+
+        /* view transform and near cull */
+        double p[3];
+        for (int i = 0; i < 3; ++i) p[i] = W[i][0] * mu[0] + W[i][1] * mu[1] + W[i][2] * mu[2] + t[i];
+        if (!(p[2] > NEAR_Z)) continue;
+
+        /* 3D covariance  Sigma3 = R S S^T R^T  from scale = exp(log_scale) and the
+           normalised quaternion (w, x, y, z) */
+        double s3[3] = {exp((double)log_scales[g]), exp((double)log_scales[n + g]),
+                        exp((double)log_scales[2 * n + g])};
+        double q[4] = {quats[g], quats[n + g], quats[2 * n + g], quats[3 * n + g]};
+        double qn = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+        if (qn > 0.0) {
+            double r = sqrt(qn);
+            for (int k = 0; k < 4; ++k) q[k] = q[k] / r;
+        } else {
+            q[0] = 1.0; q[1] = q[2] = q[3] = 0.0;
+        }
+        double w = q[0], x = q[1], y = q[2], z = q[3];
+        double R[3][3] = {
+            {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+            {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+            {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+        double M[3][3], S3[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) M[i][j] = R[i][j] * s3[j];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += M[i][k] * M[j][k];
+                S3[i][j] = acc;
+            }
+
+        /* EWA projection: Sigma2 = J W Sigma3 W^T J^T + 0.3 I (the J of the
+           perspective map at the clamped point) */
+        double limx = FRUSTUM_SLACK * ((0.5 * width) / fx);
+        double limy = FRUSTUM_SLACK * ((0.5 * height) / fy);
+        double txz = p[0] / p[2], tyz = p[1] / p[2];
+        if (txz < -limx) txz = -limx;
+        if (txz > limx) txz = limx;
+        if (tyz < -limy) tyz = -limy;
+        if (tyz > limy) tyz = limy;
+        double xc = txz * p[2], yc = tyz * p[2];
+        double J[2][3] = {{fx / p[2], 0.0, -(fx * xc) / (p[2] * p[2])},
+                          {0.0, fy / p[2], -(fy * yc) / (p[2] * p[2])}};
+        double T[2][3], U[2][3], S2[2][2];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += J[i][k] * W[k][j];
+                T[i][j] = acc;
+            }
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += T[i][k] * S3[k][j];
+                U[i][j] = acc;
+            }
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += U[i][k] * T[j][k];
+                S2[i][j] = acc;
+            }
+        double a = S2[0][0] + DILATION, b = S2[0][1], c = S2[1][1] + DILATION;
+
+        /* determinant, conic (eq. 1 uses the inverse of G_cov), mean, depth */
+        double det = a * c - b * b;
+        double u = fx * (p[0] / p[2]) + cx;
+        double v = fy * (p[1] / p[2]) + cy;
+        if (!(is_finite(u) && is_finite(v) && is_finite(a) && is_finite(b) && is_finite(c))) continue;
+        if (!(det > 0.0)) continue;
+        double sigma = 1.0 / (1.0 + exp(-(double)opacity_logits[g]));
+        mean2d[2 * g] = u;
+        mean2d[2 * g + 1] = v;
+        conic[3 * g] = c / det;
+        conic[3 * g + 1] = -b / det;
+        conic[3 * g + 2] = a / det;
+        cov2d[3 * g] = a; cov2d[3 * g + 1] = b; cov2d[3 * g + 2] = c;
+        opacity[g] = sigma;
+        depth[g] = p[2];
+        flags[g] = 1;
+
+        /* tile extent: plain 3-sigma, or scaled by AdaGScale */
+        double ext = orc_plain_extent(a, b, c);
+        extent[g] = ext;
+        th[g] = TAU;
+        scale[g] = 1.0;
+        if (adagscale) {
+            double thv, sv;
+            int keep = orc_adagscale(det, sigma, p[2], K, t_upper, lut_depth_max, force_unit_scale,
+                                     &thv, &sv);
+            th[g] = thv;
+            scale[g] = sv;
+            if (!keep) continue;
+            ext = ext * sv;
+        }
+        double rd = ceil(ext);
+        if (rd > 1073741824.0) rd = 1073741824.0; /* 2^30 px: covers any image */
+        int r = (int)rd;
+        radius[g] = r;
+        if (r <= 0) continue;
+
+        /* axis-aligned rectangle of 16x16 tiles, half-open */
+        double fx0 = floor((u - r) / TILE), fx1 = floor(((u + r) + (TILE - 1)) / TILE);
+        double fy0 = floor((v - r) / TILE), fy1 = floor(((v + r) + (TILE - 1)) / TILE);
+        fx0 = fx0 < 0 ? 0 : (fx0 > TX ? TX : fx0);
+        fx1 = fx1 < 0 ? 0 : (fx1 > TX ? TX : fx1);
+        fy0 = fy0 < 0 ? 0 : (fy0 > TY ? TY : fy0);
+        fy1 = fy1 < 0 ? 0 : (fy1 > TY ? TY : fy1);
+        int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
+        int64_t tiles = (int64_t)(x1 - x0) * (int64_t)(y1 - y0);
+        if (tiles <= 0) continue;
+        rect[4 * g] = x0; rect[4 * g + 1] = y0; rect[4 * g + 2] = x1; rect[4 * g + 3] = y1;
+        tiles_touched[g] = tiles;
+        flags[g] = 2;
+
+        /* view-dependent colour: SH evaluated along the unit direction from the
+           camera centre, offset by 0.5 and clamped at 0 */
+        double dir[3] = {mu[0] - campos[0], mu[1] - campos[1], mu[2] - campos[2]};
+        double len = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+        for (int k = 0; k < 3; ++k) dir[k] /= len;
+        double Y[(SH_LMAX + 1) * (SH_LMAX + 1)];
+        orc_sh_basis(sh_degree, dir, Y, NULL);
+        for (int ch = 0; ch < 3; ++ch) {
+            double acc = 0.0;
+            for (int k = 0; k < nsh; ++k) acc += (double)sh[((int64_t)k * 3 + ch) * n + g] * Y[k];
+            acc += 0.5;
+            rgb[3 * g + ch] = acc < 0.0 ? 0.0 : acc;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pair emission (Sec. 2.1): Gaussians in index order, tile rows outer,       */
+/* columns inner.  key = tile << 32 | bits(float32 depth), value = index.    */
+/* ------------------------------------------------------------------------ */
+int64_t orc_emit(int64_t n, const int32_t *rect, const int64_t *tiles_touched, const float *depth_f32,
+                 int width, uint64_t *keys, uint32_t *vals) {
+    int TX = (width + TILE - 1) / TILE;
+    int64_t p = 0;
+    for (int64_t g = 0; g < n; ++g) {
+        if (tiles_touched[g] <= 0) continue;
+        uint32_t dbits;
+        memcpy(&dbits, &depth_f32[g], 4);
+        for (int ty = rect[4 * g + 1]; ty < rect[4 * g + 3]; ++ty)
+            for (int tx = rect[4 * g]; tx < rect[4 * g + 2]; ++tx) {
+                if (keys) {
+                    keys[p] = ((uint64_t)(uint32_t)(ty * TX + tx) << 32) | dbits;
+                    vals[p] = (uint32_t)g;
+                }
+                ++p;
+            }
+    }
+    return p;
+}
+
+/* Sort (Sec. 2.1): ascending (key, value).  Equal keys keep index order,
+ * which is the emission order, so this equals a stable sort by key. */
+typedef struct { uint64_t k; uint32_t v; } kv_t;
+static int kv_cmp(const void *a, const void *b) {
+    const kv_t *x = (const kv_t *)a, *y = (const kv_t *)b;
+    if (x->k != y->k) return x->k < y->k ? -1 : 1;
+    if (x->v != y->v) return x->v < y->v ? -1 : 1;
+    return 0;
+}
+void orc_sort(int64_t np, uint64_t *keys, uint32_t *vals) {
+    kv_t *a = (kv_t *)malloc(sizeof(kv_t) * (size_t)(np > 0 ? np : 1));
+    for (int64_t i = 0; i < np; ++i) { a[i].k = keys[i]; a[i].v = vals[i]; }
+    qsort(a, (size_t)np, sizeof(kv_t), kv_cmp);
+    for (int64_t i = 0; i < np; ++i) { keys[i] = a[i].k; vals[i] = a[i].v; }
+    free(a);
+}
+
+/* ranges[2t], ranges[2t+1] = first and one-past-last index of tile t. */
+void orc_ranges(int64_t np, const uint64_t *keys, int num_tiles, int64_t *ranges) {
+    for (int t = 0; t < num_tiles; ++t) ranges[2 * t] = ranges[2 * t + 1] = 0;
+    for (int64_t i = 0; i < np; ++i) {
+        int t = (int)(keys[i] >> 32);
+        if (i == 0 || (int)(keys[i - 1] >> 32) != t) ranges[2 * t] = i;
+        if (i == np - 1 || (int)(keys[i + 1] >> 32) != t) ranges[2 * t + 1] = i + 1;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Blending of one pixel, eq. (1)-(2), front to back.                        */
+/*                                                                           */
+/* rec[g*9 .. g*9+8] = mean x, mean y, conic A, B, C, opacity, r, g, b (the   */
+/* float32 record values, here in double).  For each listed Gaussian:         */
+/*   power = -(A dx^2 + C dy^2)/2 - B dx dy; skipped if power > 0;           */
+/*   alpha = min(0.99, opacity * exp(power)); skipped if alpha < tau;        */
+/*   if T (1 - alpha) < 1e-4 the pixel stops before adding this Gaussian;    */
+/*   otherwise colour += alpha T rgb and T *= 1 - alpha.                     */
+/* margin receives the smallest relative distance of any decision to its     */
+/* threshold (used to flag pixels whose float32 result may legitimately      */
+/* take the other branch).                                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double color[3];
+    double T;
+    int64_t last;      /* 1 + list position of the last blended Gaussian, 0 if none */
+    int64_t blended;   /* number of blended Gaussians */
+    int64_t evaluated; /* list entries evaluated before the stop */
+    double margin;
+    uint64_t sig;      /* hash of the blended positions */
+} pix_t;
+
+static void blend_pixel(double px, double py, const uint32_t *list, int64_t len, const double *rec,
+                        pix_t *o) {
+    double T = 1.0, C[3] = {0.0, 0.0, 0.0}, margin = INFINITY;
+    int64_t last = 0, blended = 0, ev = 0;
+    uint64_t sig = 1469598103934665603ull;
+    for (int64_t j = 0; j < len; ++j) {
+        const double *g = rec + 9 * (int64_t)list[j];
+        ++ev;
+        double dx = g[0] - px, dy = g[1] - py;
+        double power = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
+        double scale = 0.5 * (fabs(g[2] * dx * dx) + fabs(g[4] * dy * dy)) + fabs(g[3] * dx * dy);
+        if (scale > 0.0) {
+            double mp = fabs(power) / scale;
+            if (mp < margin) margin = mp;
+        }
+        if (power > 0.0) continue;
+        double alpha = g[5] * exp(power);
+        if (alpha > ALPHA_MAX) alpha = ALPHA_MAX;
+        double ma = fabs(alpha - TAU) / TAU;
+        if (ma < margin) margin = ma;
+        if (alpha < TAU) continue;
+        double Tn = T * (1.0 - alpha);
+        double mt = fabs(Tn - T_STOP) / T_STOP;
+        if (mt < margin) margin = mt;
+        if (Tn < T_STOP) break;
+        for (int ch = 0; ch < 3; ++ch) C[ch] += alpha * T * g[6 + ch];
+        T = Tn;
+        last = j + 1;
+        ++blended;
+        sig = (sig ^ (uint64_t)j) * 1099511628211ull;
+    }
+    for (int ch = 0; ch < 3; ++ch) o->color[ch] = C[ch];
+    o->T = T; o->last = last; o->blended = blended; o->evaluated = ev; o->margin = margin; o->sig = sig;
+}
+
+static void store_pixel(const pix_t *o, int64_t idx, int64_t npix, const double *bg, double *image,
+                        double *final_T, int64_t *n_contrib, double *margin, int64_t *evals,
+                        uint64_t *sig) {
+    for (int ch = 0; ch < 3; ++ch) image[ch * npix + idx] = o->color[ch] + o->T * bg[ch];
+    final_T[idx] = o->T;
+    n_contrib[idx] = o->last;
+    if (margin) margin[idx] = o->margin;
+    if (evals) evals[idx] = o->evaluated;
+    if (sig) sig[idx] = o->sig ^ (uint64_t)o->blended;
+}
+
+/* Tile-list rasterizer: pixel (px, py) lies in tile (px/16, py/16) and blends
+ * that tile's sorted list.  tiles: optional subset of tile ids (n_sel >= 0);
+ * n_sel < 0 blends every tile.  Outputs are [3][H][W] and [H][W]. */
+void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *sorted_vals,
+               const double *rec, const double *bg, const int32_t *tiles, int64_t n_sel,
+               double *image, double *final_T, int64_t *n_contrib, double *margin, int64_t *evals,
+               uint64_t *sig) {
+    int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
+    int64_t npix = (int64_t)width * height;
+    int64_t count = n_sel >= 0 ? n_sel : (int64_t)TX * TY;
+    for (int64_t s = 0; s < count; ++s) {
+        int t = n_sel >= 0 ? tiles[s] : (int)s;
+        int tx = t % TX, ty = t / TX;
+        for (int py = ty * TILE; py < (ty + 1) * TILE && py < height; ++py)
+            for (int px = tx * TILE; px < (tx + 1) * TILE && px < width; ++px) {
+                pix_t o;
+                blend_pixel((double)px, (double)py, sorted_vals + ranges[2 * t],
+                            ranges[2 * t + 1] - ranges[2 * t], rec, &o);
+                store_pixel(&o, (int64_t)py * width + px, npix, bg, image, final_T, n_contrib,
+                            margin, evals, sig);
+            }
+    }
+}
+
+/* Brute-force blenders on small scenes.
+ * mode 1 (tile-restricted): every Gaussian whose tile rectangle contains the
+ *   pixel's tile, ordered by (float32 depth, index) -- must equal orc_blend.
+ * mode 2 (unrestricted): every projected Gaussian (flags >= 1) in the same
+ *   order, whatever its rectangle -- a diagnostic of the mass outside the
+ *   extent. */
+typedef struct { float d; uint32_t i; } di_t;
+static int di_cmp(const void *a, const void *b) {
+    const di_t *x = (const di_t *)a, *y = (const di_t *)b;
+    if (x->d != y->d) return x->d < y->d ? -1 : 1;
+    return x->i < y->i ? -1 : (x->i > y->i);
+}
+void orc_blend_bruteforce(int mode, int64_t n, int width, int height, const int32_t *rect,
+                          const int32_t *flags, const float *depth_f32, const double *rec,
+                          const double *bg, double *image, double *final_T, int64_t *n_contrib) {
+    int TX = (width + TILE - 1) / TILE;
+    int64_t npix = (int64_t)width * height;
+    di_t *cand = (di_t *)malloc(sizeof(di_t) * (size_t)(n > 0 ? n : 1));
+    uint32_t *list = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    for (int py = 0; py < height; ++py)
+        for (int px = 0; px < width; ++px) {
+            int tx = px / TILE, ty = py / TILE;
+            int64_t m = 0;
+            for (int64_t g = 0; g < n; ++g) {
+                int in;
+                if (mode == 1)
+                    in = flags[g] == 2 && rect[4 * g] <= tx && tx < rect[4 * g + 2] &&
+                         rect[4 * g + 1] <= ty && ty < rect[4 * g + 3];
+                else
+                    in = flags[g] >= 1;
+                if (in) { cand[m].d = depth_f32[g]; cand[m].i = (uint32_t)g; ++m; }
+            }
+            qsort(cand, (size_t)m, sizeof(di_t), di_cmp);
+            for (int64_t k = 0; k < m; ++k) list[k] = cand[k].i;
+            pix_t o;
+            blend_pixel((double)px, (double)py, list, m, rec, &o);
+            store_pixel(&o, (int64_t)py * width + px, npix, bg, image, final_T, n_contrib, NULL,
+                        NULL, NULL);
+            (void)TX;
+        }
+    free(cand);
+    free(list);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of the blend with the discrete decisions of the forward pass      */
+/* frozen.  For the blended Gaussians i = 1..n of a pixel, with T_1 = 1,      */
+/* T_{i+1} = T_i (1 - alpha_i) and C = sum alpha_i T_i c_i + T_{n+1} bg:       */
+/*   dC/dc_i     = alpha_i T_i                                               */
+/*   dC/dalpha_i = T_i c_i - (sum_{j>i} alpha_j T_j c_j + T_{n+1} bg)/(1-alpha_i) */
+/* alpha = min(0.99, sigma e^power): a clamped alpha has zero derivative;     */
+/* otherwise dalpha/dsigma = e^power and dalpha/dpower = alpha.              */
+/* Outputs accumulate into g2d[g*9 + (mx, my, A, B, C, sigma, r, g, b)].      */
+/* ------------------------------------------------------------------------ */
+void orc_blend_backward(int width, int height, const int64_t *ranges, const uint32_t *sorted_vals,
+                        const double *rec, const double *bg, const double *dL_dimage, double *g2d) {
+    int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
+    int64_t npix = (int64_t)width * height;
+    int64_t cap = 0;
+    for (int t = 0; t < TX * TY; ++t) {
+        int64_t len = ranges[2 * t + 1] - ranges[2 * t];
+        if (len > cap) cap = len;
+    }
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cap + 1));
+    double *al = (double *)malloc(sizeof(double) * (size_t)(cap + 1));
+    double *ex = (double *)malloc(sizeof(double) * (size_t)(cap + 1));
+    int *cl = (int *)malloc(sizeof(int) * (size_t)(cap + 1));
+    double *Ts = (double *)malloc(sizeof(double) * (size_t)(cap + 2));
+    for (int t = 0; t < TX * TY; ++t) {
+        int tx = t % TX, ty = t / TX;
+        const uint32_t *list = sorted_vals + ranges[2 * t];
+        int64_t len = ranges[2 * t + 1] - ranges[2 * t];
+        for (int py = ty * TILE; py < (ty + 1) * TILE && py < height; ++py)
+            for (int px = tx * TILE; px < (tx + 1) * TILE && px < width; ++px) {
+                /* forward, recording the blended entries */
+                double T = 1.0;
+                int64_t nb = 0;
+                for (int64_t j = 0; j < len; ++j) {
+                    const double *g = rec + 9 * (int64_t)list[j];
+                    double dx = g[0] - px, dy = g[1] - py;
+                    double power = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
+                    if (power > 0.0) continue;
+                    double e = exp(power);
+                    double alpha = g[5] * e;
+                    int clamped = 0;
+                    if (alpha > ALPHA_MAX) { alpha = ALPHA_MAX; clamped = 1; }
+                    if (alpha < TAU) continue;
+                    double Tn = T * (1.0 - alpha);
+                    if (Tn < T_STOP) break;
+                    idx[nb] = j; al[nb] = alpha; ex[nb] = e; cl[nb] = clamped; Ts[nb] = T;
+                    ++nb;
+                    T = Tn;
+                }
+                Ts[nb] = T;
+                int64_t pix = (int64_t)py * width + px;
+                double G[3] = {dL_dimage[pix], dL_dimage[npix + pix], dL_dimage[2 * npix + pix]};
+                /* back to front */
+                double behind[3] = {T * bg[0], T * bg[1], T * bg[2]};
+                for (int64_t k = nb - 1; k >= 0; --k) {
+                    int64_t gid = list[idx[k]];
+                    const double *g = rec + 9 * gid;
+                    double *o = g2d + 9 * gid;
+                    double a = al[k], Ti = Ts[k];
+                    double dLda = 0.0;
+                    for (int ch = 0; ch < 3; ++ch) {
+                        o[6 + ch] += a * Ti * G[ch];
+                        dLda += G[ch] * (Ti * g[6 + ch] - behind[ch] / (1.0 - a));
+                    }
+                    for (int ch = 0; ch < 3; ++ch) behind[ch] += a * Ti * g[6 + ch];
+                    if (cl[k]) continue;
+                    double dx = g[0] - px, dy = g[1] - py;
+                    o[5] += dLda * ex[k];
+                    double dLdp = dLda * a;
+                    o[2] += dLdp * (-0.5 * dx * dx);
+                    o[4] += dLdp * (-0.5 * dy * dy);
+                    o[3] += dLdp * (-dx * dy);
+                    o[0] += dLdp * (-(g[2] * dx + g[3] * dy));
+                    o[1] += dLdp * (-(g[4] * dy + g[3] * dx));
+                }
+            }
+    }
+    free(idx); free(al); free(ex); free(cl); free(Ts);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of the preprocess (per Gaussian), from g2d to the scene           */
+/* parameters.  Frozen: the tile extent (no gradient through Th, s or the    */
+/* rectangle), the EWA clamp branch and the colour clamp at 0.               */
+/* Outputs are [C][N] like the inputs; d_sh is [(d+1)^2][3][N].               */
+/* ------------------------------------------------------------------------ */
+static void rot_partials(const double q[4], double dR[4][3][3]) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    double Rw[3][3] = {{0, -2 * z, 2 * y}, {2 * z, 0, -2 * x}, {-2 * y, 2 * x, 0}};
+    double Rx[3][3] = {{0, 2 * y, 2 * z}, {2 * y, -4 * x, -2 * w}, {2 * z, 2 * w, -4 * x}};
+    double Ry[3][3] = {{-4 * y, 2 * x, 2 * w}, {2 * x, 0, 2 * z}, {-2 * w, 2 * z, -4 * y}};
+    double Rz[3][3] = {{-4 * z, -2 * w, 2 * x}, {2 * w, -4 * z, 2 * y}, {2 * x, 2 * y, 0}};
+    memcpy(dR[0], Rw, sizeof(Rw));
+    memcpy(dR[1], Rx, sizeof(Rx));
+    memcpy(dR[2], Ry, sizeof(Ry));
+    memcpy(dR[3], Rz, sizeof(Rz));
+}
+
+void orc_preprocess_backward(int64_t n, const float *means, const float *log_scales,
+                             const float *quats, const float *opacity_logits, const float *sh,
+                             int sh_degree, const float *cam, int width, int height,
+                             const int32_t *flags, const double *g2d, double *d_means,
+                             double *d_log_scales, double *d_quats, double *d_opacity_logits,
+                             double *d_sh) {
+    double W[3][3], t[3];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) W[i][j] = cam[4 * i + j];
+        t[i] = cam[4 * i + 3];
+    }
+    double fx = cam[12], fy = cam[13];
+    int nsh = (sh_degree + 1) * (sh_degree + 1);
+    double campos[3];
+    for (int j = 0; j < 3; ++j) campos[j] = -(W[0][j] * t[0] + W[1][j] * t[1] + W[2][j] * t[2]);
+
+    for (int64_t g = 0; g < n; ++g) {
+        for (int k = 0; k < 3; ++k) d_means[k * n + g] = d_log_scales[k * n + g] = 0.0;
+        for (int k = 0; k < 4; ++k) d_quats[k * n + g] = 0.0;
+        d_opacity_logits[g] = 0.0;
+        for (int k = 0; k < nsh * 3; ++k) d_sh[(int64_t)k * n + g] = 0.0;
+        if (flags[g] != 2) continue;
+        const double *G = g2d + 9 * g;
+        double mu[3] = {means[g], means[n + g], means[2 * n + g]};
+        double p[3];
+        for (int i = 0; i < 3; ++i) p[i] = W[i][0] * mu[0] + W[i][1] * mu[1] + W[i][2] * mu[2] + t[i];
+
+        /* forward quantities again */
+        double s3[3] = {exp((double)log_scales[g]), exp((double)log_scales[n + g]),
+                        exp((double)log_scales[2 * n + g])};
+        double q0[4] = {quats[g], quats[n + g], quats[2 * n + g], quats[3 * n + g]};
+        double qn = q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3], qr = sqrt(qn);
+        double q[4];
+        int qdegenerate = !(qn > 0.0);
+        for (int k = 0; k < 4; ++k) q[k] = qdegenerate ? (k == 0) : q0[k] / qr;
+        double w = q[0], x = q[1], y = q[2], z = q[3];
+        double R[3][3] = {
+            {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+            {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+            {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+        double M[3][3], S3[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) M[i][j] = R[i][j] * s3[j];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                S3[i][j] = 0.0;
+                for (int k = 0; k < 3; ++k) S3[i][j] += M[i][k] * M[j][k];
+            }
+        double limx = FRUSTUM_SLACK * ((0.5 * width) / fx), limy = FRUSTUM_SLACK * ((0.5 * height) / fy);
+        double txz = p[0] / p[2], tyz = p[1] / p[2];
+        int clx = 0, cly = 0;
+        if (txz < -limx) { txz = -limx; clx = -1; }
+        if (txz > limx) { txz = limx; clx = 1; }
+        if (tyz < -limy) { tyz = -limy; cly = -1; }
+        if (tyz > limy) { tyz = limy; cly = 1; }
+        double xc = txz * p[2], yc = tyz * p[2];
+        double J[2][3] = {{fx / p[2], 0.0, -(fx * xc) / (p[2] * p[2])},
+                          {0.0, fy / p[2], -(fy * yc) / (p[2] * p[2])}};
+        double T[2][3];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 3; ++j) {
+                T[i][j] = 0.0;
+                for (int k = 0; k < 3; ++k) T[i][j] += J[i][k] * W[k][j];
+            }
+        double S2[2][2];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                S2[i][j] = 0.0;
+                for (int k = 0; k < 3; ++k)
+                    for (int l = 0; l < 3; ++l) S2[i][j] += T[i][k] * S3[k][l] * T[j][l];
+            }
+        double a = S2[0][0] + DILATION, b = S2[0][1], c = S2[1][1] + DILATION;
+        double det = a * c - b * b, d2 = det * det;
+
+        double dp[3] = {0.0, 0.0, 0.0};
+        /* mean2d: u = fx p0/p2 + cx, v = fy p1/p2 + cy */
+        dp[0] += G[0] * fx / p[2];
+        dp[1] += G[1] * fy / p[2];
+        dp[2] += -G[0] * fx * p[0] / (p[2] * p[2]) - G[1] * fy * p[1] / (p[2] * p[2]);
+
+        /* conic (A, B, C) = (c, -b, a)/det  ->  dL/d(a, b, c) */
+        double gA = G[2], gB = G[3], gC = G[4];
+        double ga = gA * (-c * c / d2) + gB * (b * c / d2) + gC * (-b * b / d2);
+        double gb = gA * (2.0 * b * c / d2) + gB * (-(a * c + b * b) / d2) + gC * (2.0 * a * b / d2);
+        double gc = gA * (-b * b / d2) + gB * (a * b / d2) + gC * (-a * a / d2);
+        /* symmetric matrix gradient of Sigma2 (b occupies both off-diagonals) */
+        double G2[2][2] = {{ga, 0.5 * gb}, {0.5 * gb, gc}};
+        /* dL/dSigma3 = T^T G2 T ; dL/dT = 2 G2 T Sigma3 */
+        double G3[3][3], GT[2][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                G3[i][j] = 0.0;
+                for (int k = 0; k < 2; ++k)
+                    for (int l = 0; l < 2; ++l) G3[i][j] += T[k][i] * G2[k][l] * T[l][j];
+            }
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 3; ++j) {
+                GT[i][j] = 0.0;
+                for (int k = 0; k < 2; ++k)
+                    for (int l = 0; l < 3; ++l) GT[i][j] += 2.0 * G2[i][k] * T[k][l] * S3[l][j];
+            }
+        /* T = J W  ->  dL/dJ = dL/dT W^T */
+        double GJ[2][3];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 3; ++j) {
+                GJ[i][j] = 0.0;
+                for (int k = 0; k < 3; ++k) GJ[i][j] += GT[i][k] * W[j][k];
+            }
+        /* J00 = fx/p2, J11 = fy/p2; J02 = -fx xc/p2^2 with xc = p0 (unclamped) or
+           +-limx p2 (clamped); likewise J12 */
+        dp[2] += GJ[0][0] * (-fx / (p[2] * p[2])) + GJ[1][1] * (-fy / (p[2] * p[2]));
+        if (clx == 0) {
+            dp[0] += GJ[0][2] * (-fx / (p[2] * p[2]));
+            dp[2] += GJ[0][2] * (2.0 * fx * p[0] / (p[2] * p[2] * p[2]));
+        } else {
+            dp[2] += GJ[0][2] * (fx * clx * limx / (p[2] * p[2]));
+        }
+        if (cly == 0) {
+            dp[1] += GJ[1][2] * (-fy / (p[2] * p[2]));
+            dp[2] += GJ[1][2] * (2.0 * fy * p[1] / (p[2] * p[2] * p[2]));
+        } else {
+            dp[2] += GJ[1][2] * (fy * cly * limy / (p[2] * p[2]));
+        }
+        /* Sigma3 = M M^T -> dL/dM = 2 G3 M ; M = R diag(s) */
+        double GM[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                GM[i][j] = 0.0;
+                for (int k = 0; k < 3; ++k) GM[i][j] += 2.0 * G3[i][k] * M[k][j];
+            }
+        for (int j = 0; j < 3; ++j) {
+            double gs = 0.0;
+            for (int i = 0; i < 3; ++i) gs += GM[i][j] * R[i][j];
+            d_log_scales[j * n + g] = gs * s3[j];
+        }
+        double GR[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) GR[i][j] = GM[i][j] * s3[j];
+        double dR[4][3][3], gq[4];
+        rot_partials(q, dR);
+        for (int k = 0; k < 4; ++k) {
+            gq[k] = 0.0;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) gq[k] += GR[i][j] * dR[k][i][j];
+        }
+        /* normalisation q = q0/|q0|: dq/dq0 = (I - q q^T)/|q0| */
+        if (!qdegenerate) {
+            double qg = gq[0] * q[0] + gq[1] * q[1] + gq[2] * q[2] + gq[3] * q[3];
+            for (int k = 0; k < 4; ++k) d_quats[k * n + g] = (gq[k] - q[k] * qg) / qr;
+        }
+
+        /* opacity: sigma = 1/(1+exp(-o)) */
+        double sg = 1.0 / (1.0 + exp(-(double)opacity_logits[g]));
+        d_opacity_logits[g] = G[5] * sg * (1.0 - sg);
+
+        /* colour */
+        double dv[3] = {mu[0] - campos[0], mu[1] - campos[1], mu[2] - campos[2]};
+        double len = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+        double dir[3] = {dv[0] / len, dv[1] / len, dv[2] / len};
+        double Y[(SH_LMAX + 1) * (SH_LMAX + 1)], dY[3 * (SH_LMAX + 1) * (SH_LMAX + 1)];
+        orc_sh_basis(sh_degree, dir, Y, dY);
+        double gdir[3] = {0.0, 0.0, 0.0};
+        for (int ch = 0; ch < 3; ++ch) {
+            double acc = 0.0;
+            for (int k = 0; k < nsh; ++k) acc += (double)sh[((int64_t)k * 3 + ch) * n + g] * Y[k];
+            if (acc + 0.5 < 0.0) continue; /* clamped channel */
+            double gc_ = G[6 + ch];
+            for (int k = 0; k < nsh; ++k) {
+                d_sh[((int64_t)k * 3 + ch) * n + g] = gc_ * Y[k];
+                for (int e = 0; e < 3; ++e)
+                    gdir[e] += gc_ * (double)sh[((int64_t)k * 3 + ch) * n + g] * dY[3 * k + e];
+            }
+        }
+        /* dir = dv/|dv|: d dir/d dv = (I - dir dir^T)/|dv| */
+        double gd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
+        double gmu[3];
+        for (int e = 0; e < 3; ++e) gmu[e] = (gdir[e] - dir[e] * gd) / len;
+        /* p = W mu + t */
+        for (int j = 0; j < 3; ++j)
+            d_means[j * n + g] = gmu[j] + W[0][j] * dp[0] + W[1][j] * dp[1] + W[2][j] * dp[2];
+    }
+}
+
+/* The oracle's constants, for comparison with the values printed in the paper:
+ * tau, early-exit T, LUT bins, 2 pi, alpha clamp, near plane, dilation,
+ * frustum slack, discriminant floor, tile size. */
+void orc_constants(double *out) {
+    out[0] = TAU; out[1] = T_STOP; out[2] = LUT_BINS; out[3] = TWO_PI; out[4] = ALPHA_MAX;
+    out[5] = NEAR_Z; out[6] = DILATION; out[7] = FRUSTUM_SLACK; out[8] = LAMBDA_FLOOR; out[9] = TILE;
+}

@@ -1,0 +1,349 @@
+"""Python face of the FP64 CPU oracle (``gs_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the HIP path.  The C library is
+built with ``gcc -O2 -ffp-contract=off`` (``build()``); this module only
+marshals numpy arrays and strings the stages together:
+
+    preprocess -> emit -> sort -> ranges -> blend        (Sec. 2.1, eq. 1-2)
+    AdaGScale: eq. (10) threshold, Th >= opacity cull,
+               reduced tile extent (Sec. 3.1-3.3)
+    backward:  analytic adjoint with frozen decisions
+
+It also carries the image metrics (PSNR, SSIM) and the peripheral-score
+helpers (eq. 4, eq. 8-9) used to pin eq. (10).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "gs_oracle.c")
+LIB = os.path.join(HERE, "libgs_oracle.so")
+
+TAU = 1.0 / 255.0
+T_STOP = 1e-4
+TILE = 16
+LUT_BINS = 20
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-ffp-contract=off",
+                               "-fno-fast-math", "-fPIC", "-shared", SRC, "-o", LIB, "-lm"])
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = C.CDLL(LIB)
+        P = C.c_void_p
+        L.orc_sh_basis.argtypes = [C.c_int, P, P, P]
+        L.orc_plain_extent.argtypes = [C.c_double] * 3
+        L.orc_plain_extent.restype = C.c_double
+        L.orc_adagscale.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, P, C.c_double,
+                                    C.c_int, P, P]
+        L.orc_adagscale.restype = C.c_int
+        L.orc_preprocess.argtypes = ([C.c_int64, P, P, P, P, P, C.c_int, P, C.c_int, C.c_int,
+                                      C.c_int, C.c_double, P, C.c_double, C.c_int] + [P] * 13)
+        L.orc_emit.argtypes = [C.c_int64, P, P, P, C.c_int, P, P]
+        L.orc_emit.restype = C.c_int64
+        L.orc_sort.argtypes = [C.c_int64, P, P]
+        L.orc_ranges.argtypes = [C.c_int64, P, C.c_int, P]
+        L.orc_blend.argtypes = [C.c_int, C.c_int, P, P, P, P, P, C.c_int64, P, P, P, P, P, P]
+        L.orc_blend_bruteforce.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_int, P, P, P, P, P, P,
+                                           P, P]
+        L.orc_blend_backward.argtypes = [C.c_int, C.c_int, P, P, P, P, P, P]
+        L.orc_constants.argtypes = [P]
+        L.orc_preprocess_backward.argtypes = [C.c_int64, P, P, P, P, P, C.c_int, P, C.c_int,
+                                              C.c_int, P, P, P, P, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def cam_array(cam) -> np.ndarray:
+    return np.concatenate([np.asarray(cam["viewmat"], np.float32).reshape(12),
+                           np.array([cam["fx"], cam["fy"], cam["cx"], cam["cy"]], np.float32)])
+
+
+def default_lut():
+    return np.ones(LUT_BINS, dtype=np.float32)
+
+
+@dataclass
+class Mode:
+    """Per-call method switch: plain 3D-GS (``adagscale=False``) or AdaGScale
+    with peripheral-loss budget ``K`` and depth LUT ``t_upper`` over
+    [0, ``lut_depth_max``] (Sec. 3.4)."""
+    adagscale: bool = False
+    K: float = 0.0
+    t_upper: np.ndarray = None
+    lut_depth_max: float = 100.0
+    force_unit_scale: bool = False
+
+    def lut(self):
+        return _f32(self.t_upper if self.t_upper is not None else default_lut())
+
+
+@dataclass
+class Preproc:
+    mean2d: np.ndarray
+    conic: np.ndarray
+    opacity: np.ndarray
+    rgb: np.ndarray
+    depth: np.ndarray
+    cov2d: np.ndarray
+    extent: np.ndarray
+    th: np.ndarray
+    scale: np.ndarray
+    rect: np.ndarray
+    tiles_touched: np.ndarray
+    radius: np.ndarray
+    flags: np.ndarray
+
+    def record(self, round_to_f32: bool = True) -> np.ndarray:
+        """Per-Gaussian record used by the blend: mean x, mean y, conic A, B, C,
+        opacity, r, g, b.  The renderer stores it in float32, so by default the
+        values are rounded to float32 (and widened back to double); gradient
+        checks keep the unrounded double values."""
+        rec = np.concatenate([self.mean2d, self.conic, self.opacity[:, None], self.rgb], axis=1)
+        if round_to_f32:
+            rec = rec.astype(np.float32)
+        return np.ascontiguousarray(rec.astype(np.float64))
+
+    @property
+    def depth_f32(self):
+        return self.depth.astype(np.float32)
+
+
+def preprocess(scene, cam, mode: Mode = Mode()) -> Preproc:
+    L = lib()
+    n = scene.n
+    out = Preproc(mean2d=np.zeros((n, 2)), conic=np.zeros((n, 3)), opacity=np.zeros(n),
+                  rgb=np.zeros((n, 3)), depth=np.zeros(n), cov2d=np.zeros((n, 3)),
+                  extent=np.zeros(n), th=np.zeros(n), scale=np.zeros(n),
+                  rect=np.zeros((n, 4), np.int32), tiles_touched=np.zeros(n, np.int64),
+                  radius=np.zeros(n, np.int32), flags=np.zeros(n, np.int32))
+    arrs = [_f32(scene.means), _f32(scene.log_scales), _f32(scene.quats),
+            _f32(scene.opacity_logits), _f32(scene.sh)]
+    ca = cam_array(cam)
+    lut = mode.lut()
+    L.orc_preprocess(n, *[_p(a) for a in arrs], scene.sh_degree, _p(ca), cam["width"],
+                     cam["height"], int(mode.adagscale), float(mode.K), _p(lut),
+                     float(mode.lut_depth_max), int(mode.force_unit_scale),
+                     _p(out.mean2d), _p(out.conic), _p(out.opacity), _p(out.rgb), _p(out.depth),
+                     _p(out.cov2d), _p(out.extent), _p(out.th), _p(out.scale), _p(out.rect),
+                     _p(out.tiles_touched), _p(out.radius), _p(out.flags))
+    return out
+
+
+def num_tiles(cam):
+    return ((cam["width"] + TILE - 1) // TILE) * ((cam["height"] + TILE - 1) // TILE)
+
+
+def emit(pre: Preproc, cam):
+    L = lib()
+    n = pre.rect.shape[0]
+    d32 = _f32(pre.depth_f32)
+    np_ = L.orc_emit(n, _p(pre.rect), _p(pre.tiles_touched), _p(d32), cam["width"], None, None)
+    keys = np.zeros(max(np_, 1), np.uint64)
+    vals = np.zeros(max(np_, 1), np.uint32)
+    L.orc_emit(n, _p(pre.rect), _p(pre.tiles_touched), _p(d32), cam["width"], _p(keys), _p(vals))
+    return keys[:np_], vals[:np_]
+
+
+def sort(keys, vals):
+    k = np.ascontiguousarray(keys, np.uint64).copy()
+    v = np.ascontiguousarray(vals, np.uint32).copy()
+    lib().orc_sort(k.size, _p(k), _p(v))
+    return k, v
+
+
+def ranges(sorted_keys, ntiles):
+    r = np.zeros((ntiles, 2), np.int64)
+    k = np.ascontiguousarray(sorted_keys, np.uint64)
+    lib().orc_ranges(k.size, _p(k), ntiles, _p(r))
+    return r
+
+
+@dataclass
+class Frame:
+    pre: Preproc
+    keys: np.ndarray         # emitted, Gaussian-major
+    vals: np.ndarray
+    sorted_keys: np.ndarray
+    sorted_vals: np.ndarray
+    ranges: np.ndarray
+    image: np.ndarray = None
+    final_T: np.ndarray = None
+    n_contrib: np.ndarray = None
+    margin: np.ndarray = None
+    evals: np.ndarray = None
+    sig: np.ndarray = None
+
+
+def blend(frame_or_parts, cam, bg=(0.0, 0.0, 0.0), tiles=None, rec=None):
+    """Blend every tile (or the tile ids in ``tiles``).  Returns image [3][H][W],
+    final_T [H][W], n_contrib [H][W], per-pixel decision margin, evaluation
+    counts and blend signatures; pixels outside the selected tiles are 0."""
+    f = frame_or_parts
+    W, H = cam["width"], cam["height"]
+    if rec is None:
+        rec = f.pre.record()
+    img = np.zeros((3, H, W))
+    T = np.zeros((H, W))
+    nc = np.zeros((H, W), np.int64)
+    mg = np.full((H, W), np.inf)
+    ev = np.zeros((H, W), np.int64)
+    sg = np.zeros((H, W), np.uint64)
+    bgv = np.asarray(bg, np.float64)
+    rg = np.ascontiguousarray(f.ranges, np.int64)
+    sv = np.ascontiguousarray(f.sorted_vals, np.uint32)
+    if tiles is None:
+        sel, nsel = None, -1
+    else:
+        sel = np.ascontiguousarray(tiles, np.int32)
+        nsel = sel.size
+    lib().orc_blend(W, H, _p(rg), _p(sv), _p(rec), _p(bgv), _p(sel), nsel, _p(img), _p(T),
+                    _p(nc), _p(mg), _p(ev), _p(sg))
+    return img, T, nc, mg, ev, sg
+
+
+def render(scene, cam, mode: Mode = Mode(), bg=(0.0, 0.0, 0.0), tiles=None) -> Frame:
+    pre = preprocess(scene, cam, mode)
+    keys, vals = emit(pre, cam)
+    sk, sv = sort(keys, vals)
+    rg = ranges(sk, num_tiles(cam))
+    fr = Frame(pre, keys, vals, sk, sv, rg)
+    fr.image, fr.final_T, fr.n_contrib, fr.margin, fr.evals, fr.sig = blend(fr, cam, bg, tiles)
+    return fr
+
+
+def blend_bruteforce(pre: Preproc, cam, mode_id=1, bg=(0.0, 0.0, 0.0)):
+    W, H = cam["width"], cam["height"]
+    n = pre.rect.shape[0]
+    img = np.zeros((3, H, W))
+    T = np.zeros((H, W))
+    nc = np.zeros((H, W), np.int64)
+    rec = pre.record()
+    d32 = _f32(pre.depth_f32)
+    bgv = np.asarray(bg, np.float64)
+    lib().orc_blend_bruteforce(mode_id, n, W, H, _p(pre.rect), _p(pre.flags), _p(d32), _p(rec),
+                               _p(bgv), _p(img), _p(T), _p(nc))
+    return img, T, nc
+
+
+def blend_backward(frame: Frame, cam, dL_dimage, bg=(0.0, 0.0, 0.0), rec=None):
+    """Per-Gaussian gradients of the blend: [N][9] = d(mean x, mean y, A, B, C,
+    opacity, r, g, b)."""
+    n = frame.pre.rect.shape[0]
+    if rec is None:
+        rec = frame.pre.record()
+    g2d = np.zeros((n, 9))
+    bgv = np.asarray(bg, np.float64)
+    dL = np.ascontiguousarray(dL_dimage, np.float64)
+    lib().orc_blend_backward(cam["width"], cam["height"], _p(np.ascontiguousarray(frame.ranges)),
+                             _p(np.ascontiguousarray(frame.sorted_vals, np.uint32)), _p(rec),
+                             _p(bgv), _p(dL), _p(g2d))
+    return g2d
+
+
+def preprocess_backward(scene, cam, pre: Preproc, g2d):
+    n, K = scene.n, (scene.sh_degree + 1) ** 2
+    out = dict(means=np.zeros((3, n)), log_scales=np.zeros((3, n)), quats=np.zeros((4, n)),
+               opacity_logits=np.zeros(n), sh=np.zeros((K, 3, n)))
+    arrs = [_f32(scene.means), _f32(scene.log_scales), _f32(scene.quats),
+            _f32(scene.opacity_logits), _f32(scene.sh)]
+    ca = cam_array(cam)
+    lib().orc_preprocess_backward(n, *[_p(a) for a in arrs], scene.sh_degree, _p(ca), cam["width"],
+                                  cam["height"], _p(pre.flags), _p(np.ascontiguousarray(g2d)),
+                                  _p(out["means"]), _p(out["log_scales"]), _p(out["quats"]),
+                                  _p(out["opacity_logits"]), _p(out["sh"]))
+    return out
+
+
+def constants():
+    out = np.zeros(10)
+    lib().orc_constants(_p(out))
+    keys = ["tau", "t_stop", "lut_bins", "two_pi", "alpha_max", "near_z", "dilation",
+            "frustum_slack", "lambda_floor", "tile"]
+    return dict(zip(keys, out.tolist()))
+
+
+def sh_basis(degree, d, with_grad=False):
+    d = np.ascontiguousarray(d, np.float64)
+    k = (degree + 1) ** 2
+    Y = np.zeros(k)
+    dY = np.zeros((k, 3)) if with_grad else None
+    lib().orc_sh_basis(degree, _p(d), _p(Y), _p(dY))
+    return (Y, dY) if with_grad else Y
+
+
+def plain_extent(a, b, c):
+    return lib().orc_plain_extent(a, b, c)
+
+
+def adagscale(det, sigma, depth, K, t_upper=None, lut_depth_max=100.0, force_unit_scale=False):
+    lut = _f32(t_upper if t_upper is not None else default_lut())
+    th = np.zeros(1)
+    s = np.zeros(1)
+    keep = lib().orc_adagscale(det, sigma, depth, K, _p(lut), lut_depth_max,
+                               int(force_unit_scale), _p(th), _p(s))
+    return bool(keep), float(th[0]), float(s[0])
+
+
+# ---------------------------------------------------------------------------
+# Image metrics (AdaGScale is compared with the plain render; Sec. 4.1 uses PSNR)
+# ---------------------------------------------------------------------------
+def psnr(a, b):
+    a = np.clip(np.asarray(a, np.float64), 0, 1)
+    b = np.clip(np.asarray(b, np.float64), 0, 1)
+    mse = np.mean((a - b) ** 2)
+    return float("inf") if mse == 0 else float(10 * np.log10(1.0 / mse))
+
+
+def _gauss_window(size=11, sigma=1.5):
+    x = np.arange(size) - (size - 1) / 2
+    g = np.exp(-x ** 2 / (2 * sigma ** 2))
+    g /= g.sum()
+    return np.outer(g, g)
+
+
+def ssim(a, b, k1=0.01, k2=0.03):
+    """SSIM of Wang et al. (2004): 11x11 Gaussian window (sigma 1.5), valid
+    region, C1 = (k1)^2, C2 = (k2)^2 for unit dynamic range, mean over channels."""
+    from scipy.signal import correlate2d
+    a = np.clip(np.asarray(a, np.float64), 0, 1)
+    b = np.clip(np.asarray(b, np.float64), 0, 1)
+    w = _gauss_window()
+    c1, c2 = k1 ** 2, k2 ** 2
+    vals = []
+    for ch in range(a.shape[0]):
+        x, y = a[ch], b[ch]
+        f = lambda z: correlate2d(z, w, mode="valid")
+        mx, my = f(x), f(y)
+        sxx = f(x * x) - mx * mx
+        syy = f(y * y) - my * my
+        sxy = f(x * y) - mx * my
+        m = ((2 * mx * my + c1) * (2 * sxy + c2)) / ((mx * mx + my * my + c1) * (sxx + syy + c2))
+        vals.append(m.mean())
+    return float(np.mean(vals))

@@ -1,0 +1,270 @@
+"""Seeded synthetic scenes and cameras for the 3D-GS tile-rendering hot path.
+
+This module only draws inputs. It holds none of the rendering method's
+arithmetic (no projection, no blending, no AdaGScale threshold), so both the
+HIP path and the CPU oracle can consume its arrays without sharing code.
+
+Layouts (all float32, structure-of-arrays, ``[C][N]`` contiguous):
+
+* ``means``          ``[3][N]``            world-space centres
+* ``log_scales``     ``[3][N]``            per-axis log standard deviations
+* ``quats``          ``[4][N]``            rotation quaternion, order (w, x, y, z)
+* ``opacity_logits`` ``[N]``               opacity before the sigmoid
+* ``sh``             ``[(d+1)^2][3][N]``   spherical-harmonic colour coefficients
+
+A camera is a dict with ``viewmat`` (12 float32, row-major ``[R | t]`` mapping
+world to camera coordinates, OpenCV axes: x right, y down, z forward), the
+pinhole intrinsics ``fx, fy, cx, cy`` and the image ``width, height``.
+
+The recipes stand in for the paper's datasets (Tanks&Temples, DeepBlending,
+Mip-NeRF360, Mill-19, UrbanScene3D; Sec. 4.1 and Table I), which are not
+available: shapes, sizes and distributions follow the five workloads the
+build targets (tiny 2K / mid 500K / city 6M at 4608x3456 / differentiable 1M /
+64 batched views of mixed resolution).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "Scene", "make_camera", "look_camera", "tiny_scene", "mid_scene", "city_scene",
+    "diff_workload", "batched_workload", "workload", "target_image", "WORKLOADS",
+]
+
+
+@dataclass
+class Scene:
+    means: np.ndarray
+    log_scales: np.ndarray
+    quats: np.ndarray
+    opacity_logits: np.ndarray
+    sh: np.ndarray
+    sh_degree: int
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[1])
+
+    def subset(self, idx) -> "Scene":
+        idx = np.asarray(idx)
+        return Scene(np.ascontiguousarray(self.means[:, idx]),
+                     np.ascontiguousarray(self.log_scales[:, idx]),
+                     np.ascontiguousarray(self.quats[:, idx]),
+                     np.ascontiguousarray(self.opacity_logits[idx]),
+                     np.ascontiguousarray(self.sh[:, :, idx]),
+                     self.sh_degree)
+
+
+def make_camera(R, t, width, height, fovx_deg=60.0):
+    """Pinhole camera with square pixels and the principal point at the image centre.
+
+    fx = (W/2) / tan(fovx/2), fy = fx, cx = (W-1)/2, cy = (H-1)/2 (pixel centres at
+    integer coordinates)."""
+    R = np.asarray(R, dtype=np.float64).reshape(3, 3)
+    t = np.asarray(t, dtype=np.float64).reshape(3)
+    fx = (width / 2.0) / math.tan(math.radians(fovx_deg) / 2.0)
+    vm = np.concatenate([R, t[:, None]], axis=1).astype(np.float32).reshape(12)
+    return {"viewmat": vm, "fx": np.float32(fx), "fy": np.float32(fx),
+            "cx": np.float32((width - 1) / 2.0), "cy": np.float32((height - 1) / 2.0),
+            "width": int(width), "height": int(height)}
+
+
+def look_camera(eye, forward, up, width, height, fovx_deg=60.0):
+    """Camera at ``eye`` looking along ``forward``; ``up`` fixes the roll.
+
+    Rows of R are the camera axes in world coordinates: right = f x up,
+    down = f x right, forward = f; t = -R eye."""
+    f = np.asarray(forward, dtype=np.float64)
+    f = f / np.linalg.norm(f)
+    r = np.cross(f, np.asarray(up, dtype=np.float64))
+    r = r / np.linalg.norm(r)
+    d = np.cross(f, r)
+    R = np.stack([r, d, f])
+    t = -R @ np.asarray(eye, dtype=np.float64)
+    return make_camera(R, t, width, height, fovx_deg)
+
+
+def _quats(rng, n):
+    q = rng.standard_normal((4, n), dtype=np.float32)
+    q /= np.linalg.norm(q, axis=0, keepdims=True)
+    return q
+
+
+def _sh(rng, n, degree, dc_std, rest_std):
+    k = (degree + 1) ** 2
+    sh = np.empty((k, 3, n), dtype=np.float32)
+    sh[0] = rng.standard_normal((3, n), dtype=np.float32) * np.float32(dc_std)
+    if k > 1:
+        sh[1:] = rng.standard_normal((k - 1, 3, n), dtype=np.float32) * np.float32(rest_std)
+    return sh
+
+
+def tiny_scene(n=2000, seed=0, sh_degree=0):
+    """2K Gaussians in a 4x4x4 box 3-7 units in front of an identity-pose camera.
+
+    means: x, y ~ U[-2, 2], z ~ U[3, 7]; log-scales ~ N(-3.5, 0.5) per axis;
+    quaternions normalised N(0, I); opacity logits ~ N(0, 1.5); SH DC ~ N(0, 0.5)
+    (higher bands, if asked for, ~ N(0, 0.1)). Camera: 128x128, fov 60 deg."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    means = np.empty((3, n), dtype=np.float32)
+    means[0] = rng.uniform(-2, 2, n)
+    means[1] = rng.uniform(-2, 2, n)
+    means[2] = rng.uniform(3, 7, n)
+    ls = (rng.standard_normal((3, n), dtype=np.float32) * 0.5 - 3.5).astype(np.float32)
+    q = _quats(rng, n)
+    op = (rng.standard_normal(n, dtype=np.float32) * 1.5).astype(np.float32)
+    sh = _sh(rng, n, sh_degree, 0.5, 0.1)
+    cam = make_camera(np.eye(3), np.zeros(3), 128, 128)
+    return Scene(means, ls, q, op, sh, sh_degree), cam
+
+
+def mid_scene(n=500_000, seed=0, sh_degree=3, width=1920, height=1080):
+    """Clustered mid-size scene.
+
+    95% of the Gaussians sit in 200 isotropic clusters (centres uniform in
+    [-20,20]x[-5,5]x[-20,20], offsets N(0, 0.5^2 I)) with heavy-tailed log-scales
+    -4 + t_3 (Student t, 3 dof) clipped to [-9, 0]; 5% are large background
+    Gaussians on a far shell of radius 100 with log-scales ~ N(1, 0.5).
+    Opacity logits ~ N(0, 2); SH degree 3 with DC ~ N(0, 0.5) and higher bands
+    ~ N(0, 0.1). Camera at (0, 0, -35) looking at the origin, fovx 60 deg."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n_shell = n // 20
+    n_cl = n - n_shell
+    centres = np.stack([rng.uniform(-20, 20, 200), rng.uniform(-5, 5, 200),
+                        rng.uniform(-20, 20, 200)]).astype(np.float32)
+    which = rng.integers(0, 200, n_cl)
+    means = np.empty((3, n), dtype=np.float32)
+    means[:, :n_cl] = centres[:, which] + rng.standard_normal((3, n_cl), dtype=np.float32) * 0.5
+    d = rng.standard_normal((3, n_shell))
+    d /= np.linalg.norm(d, axis=0, keepdims=True)
+    means[:, n_cl:] = (d * 100.0).astype(np.float32)
+    ls = np.empty((3, n), dtype=np.float32)
+    ls[:, :n_cl] = np.clip(-4.0 + rng.standard_t(3, (3, n_cl)), -9.0, 0.0)
+    ls[:, n_cl:] = rng.standard_normal((3, n_shell)) * 0.5 + 1.0
+    q = _quats(rng, n)
+    op = (rng.standard_normal(n, dtype=np.float32) * 2.0).astype(np.float32)
+    sh = _sh(rng, n, sh_degree, 0.5, 0.1)
+    cam = look_camera((0, 0, -35), (0, 0, 1), (0, -1, 0), width, height)
+    return Scene(means, ls, q, op, sh, sh_degree), cam
+
+
+def _city_points(rng, n, n_buildings):
+    """City layout on a 1000 x 1000 m ground plane (z up).
+
+    30% of the Gaussians lie on the ground (x, y ~ U[-500, 500], z ~ N(0, 0.2)).
+    70% lie on the surfaces (four walls and the roof) of ``n_buildings`` box
+    buildings with footprint sides ~ U[10, 40] m and heights lognormal with mean
+    20 m and log-sigma 0.6; each building receives Gaussians in proportion to its
+    surface area, and each face in proportion to its area."""
+    n_ground = int(round(0.3 * n))
+    n_b = n - n_ground
+    means = np.empty((3, n), dtype=np.float32)
+    means[0, :n_ground] = rng.uniform(-500, 500, n_ground)
+    means[1, :n_ground] = rng.uniform(-500, 500, n_ground)
+    means[2, :n_ground] = rng.standard_normal(n_ground) * 0.2
+    bx = rng.uniform(-500, 500, n_buildings)
+    by = rng.uniform(-500, 500, n_buildings)
+    sx = rng.uniform(10, 40, n_buildings)
+    sy = rng.uniform(10, 40, n_buildings)
+    mu = math.log(20.0) - 0.5 * 0.6 ** 2
+    h = np.exp(rng.standard_normal(n_buildings) * 0.6 + mu)
+    # face areas: 0,1 walls normal to x (sy*h); 2,3 walls normal to y (sx*h); 4 roof (sx*sy)
+    areas = np.stack([sy * h, sy * h, sx * h, sx * h, sx * sy], axis=1)
+    tot = areas.sum(axis=1)
+    b = rng.choice(n_buildings, size=n_b, p=tot / tot.sum())
+    cum = np.cumsum(areas[b] / tot[b, None], axis=1)
+    face = (rng.uniform(0, 1, n_b)[:, None] > cum).sum(axis=1)
+    face = np.minimum(face, 4)
+    u = rng.uniform(-0.5, 0.5, n_b)
+    v = rng.uniform(0.0, 1.0, n_b)
+    x = np.empty(n_b)
+    y = np.empty(n_b)
+    z = np.empty(n_b)
+    hx, hy, hb = sx[b] / 2, sy[b] / 2, h[b]
+    m = face == 0; x[m] = -hx[m]; y[m] = u[m] * sy[b][m]; z[m] = v[m] * hb[m]
+    m = face == 1; x[m] = hx[m];  y[m] = u[m] * sy[b][m]; z[m] = v[m] * hb[m]
+    m = face == 2; x[m] = u[m] * sx[b][m]; y[m] = -hy[m]; z[m] = v[m] * hb[m]
+    m = face == 3; x[m] = u[m] * sx[b][m]; y[m] = hy[m];  z[m] = v[m] * hb[m]
+    m = face == 4; x[m] = u[m] * sx[b][m]; y[m] = (v[m] - 0.5) * sy[b][m]; z[m] = hb[m]
+    means[0, n_ground:] = bx[b] + x
+    means[1, n_ground:] = by[b] + y
+    means[2, n_ground:] = z
+    return means
+
+
+def _aerial_camera(eye, yaw, width, height, pitch_deg=30.0):
+    p = math.radians(pitch_deg)
+    f = (math.cos(yaw) * math.cos(p), math.sin(yaw) * math.cos(p), -math.sin(p))
+    return look_camera(eye, f, (0, 0, 1), width, height)
+
+
+def city_scene(n=6_000_000, seed=0, sh_degree=3, n_buildings=3000, width=4608, height=3456):
+    """City-scale scene: ground plane plus box buildings, log-scales ~ N(-1, 1.2),
+    opacity logits ~ N(0, 2), SH degree 3 (DC ~ N(0, 0.5), bands ~ N(0, 0.1)).
+    Oblique aerial camera at (0, -600, 150) looking along +y, pitched 30 deg down,
+    fovx 60 deg, 4608x3456 (the Mill-19 resolution of Table I)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    means = _city_points(rng, n, n_buildings)
+    ls = (rng.standard_normal((3, n), dtype=np.float32) * 1.2 - 1.0).astype(np.float32)
+    q = _quats(rng, n)
+    op = (rng.standard_normal(n, dtype=np.float32) * 2.0).astype(np.float32)
+    sh = _sh(rng, n, sh_degree, 0.5, 0.1)
+    cam = _aerial_camera((0.0, -600.0, 150.0), math.pi / 2, width, height)
+    return Scene(means, ls, q, op, sh, sh_degree), cam
+
+
+def diff_workload(n=1_000_000, seed=0, target_seed=7):
+    """Differentiable-render workload: the mid-scene generator at N=1M viewed at
+    1280x720, with a seeded random target image U[0,1)^(3xHxW)."""
+    scene, cam = mid_scene(n=n, seed=seed, sh_degree=3, width=1280, height=720)
+    return scene, cam, target_image(cam["width"], cam["height"], target_seed)
+
+
+def target_image(width, height, seed=7):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(0, 1, (3, height, width)).astype(np.float32)
+
+
+BATCH_RESOLUTIONS = ((640, 480), (1920, 1080), (3840, 2160), (3660, 3200))
+
+
+def batched_workload(n=2_000_000, seed=0, n_views=64, orbit_seed=1234, n_buildings=1000):
+    """Batched multi-view workload: a city-style scene of ``n`` Gaussians and
+    ``n_views`` cameras at 150 m altitude on a radius-600 m orbit, azimuth
+    2 pi k / n_views + U(-pi/n_views, pi/n_views), pitched 30 deg down toward the
+    centre; view k has resolution ``BATCH_RESOLUTIONS[k % 4]``."""
+    scene, _ = city_scene(n=n, seed=seed, n_buildings=n_buildings)
+    rng = np.random.Generator(np.random.PCG64(orbit_seed))
+    cams = []
+    for k in range(n_views):
+        az = 2 * math.pi * k / n_views + rng.uniform(-math.pi / n_views, math.pi / n_views)
+        eye = (600 * math.cos(az), 600 * math.sin(az), 150.0)
+        w, h = BATCH_RESOLUTIONS[k % 4]
+        cams.append(_aerial_camera(eye, az + math.pi, w, h))
+    return scene, cams
+
+
+WORKLOADS = {
+    "tiny": "2,000 Gaussians, 128x128, SH degree 0",
+    "mid": "500K clustered Gaussians, 1920x1080, SH degree 3",
+    "city": "6M-Gaussian synthetic city, 4608x3456, SH degree 3",
+    "diff": "1M mid-style Gaussians, 1280x720, SH degree 3, L1 to a random target",
+    "batched": "2M-Gaussian city, 64 views of mixed resolution",
+}
+
+
+def workload(name, **kw):
+    if name == "tiny":
+        return tiny_scene(**kw)
+    if name == "mid":
+        return mid_scene(**kw)
+    if name == "city":
+        return city_scene(**kw)
+    if name == "diff":
+        return diff_workload(**kw)
+    if name == "batched":
+        return batched_workload(**kw)
+    raise KeyError(name)

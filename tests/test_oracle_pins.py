@@ -1,0 +1,440 @@
+"""Pins of the FP64 oracle against things other than itself: values printed in
+the paper, closed forms, library routines, quadrature and brute force.
+
+None of these tests touches the GPU."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2604_18980_amd import scenes
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")
+
+
+# --------------------------------------------------------------------------- constants
+def test_constants_match_paper(O):
+    """tau = 1/255 and the 1e-4 early exit (Sec. 2.1), 20 LUT bins over
+    [0, 100] (Sec. 3.4) and the 2 pi of eq. (9)-(10), as printed."""
+    gold = json.load(open(GOLDEN))
+    c = O.constants()
+    assert c["tau"] == gold["tau"]["value"] == 1.0 / 255.0
+    assert c["t_stop"] == gold["early_exit_T"]["value"]
+    assert c["lut_bins"] == gold["t_upper_bins"]["value"]
+    assert c["two_pi"] == gold["eq9_factor"]["value"] == 2 * math.pi
+    assert O.Mode().lut_depth_max == gold["t_upper_depth_range"]["value"][1]
+    assert c["tile"] == 16
+
+
+# --------------------------------------------------------------------------- SH colour basis
+def test_sh_basis_matches_scipy(O):
+    """Real SH with the Condon-Shortley phase: Y_l^{+m} = sqrt2 Re Y_l^m,
+    Y_l^{-m} = sqrt2 Im Y_l^m of scipy's complex harmonics."""
+    import scipy.special as sp
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        Y = O.sh_basis(3, d)
+        th, ph = np.arccos(d[2]), np.arctan2(d[1], d[0])
+        for l in range(4):
+            for m in range(-l, l + 1):
+                c = sp.sph_harm_y(l, abs(m), th, ph)
+                ref = c.real if m == 0 else np.sqrt(2) * (c.real if m > 0 else c.imag)
+                assert abs(Y[l * l + l + m] - ref) < 1e-12
+
+
+def test_sh_basis_orthonormal(O):
+    """Gram matrix over the sphere is the identity (Gauss-Legendre in cos(theta)
+    x uniform phi: exact for these polynomial degrees)."""
+    x, w = np.polynomial.legendre.leggauss(12)
+    nphi = 16
+    G = np.zeros((16, 16))
+    for z, wz in zip(x, w):
+        for k in range(nphi):
+            ph = 2 * np.pi * k / nphi
+            s = np.sqrt(1 - z * z)
+            Y = O.sh_basis(3, np.array([s * np.cos(ph), s * np.sin(ph), z]))
+            G += np.outer(Y, Y) * wz * (2 * np.pi / nphi)
+    assert np.abs(G - np.eye(16)).max() < 1e-12
+
+
+def test_sh_gradient_tangential_fd(O):
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        Y, dY = O.sh_basis(3, d, with_grad=True)
+        t = rng.normal(size=3)
+        t -= d * (t @ d)
+        t /= np.linalg.norm(t)
+        h = 1e-6
+        yp = O.sh_basis(3, (d + h * t) / np.linalg.norm(d + h * t))
+        ym = O.sh_basis(3, (d - h * t) / np.linalg.norm(d - h * t))
+        assert np.abs((yp - ym) / (2 * h) - dY @ t).max() < 1e-8
+
+
+# --------------------------------------------------------------------------- projection
+def _single(mu, log_scale, quat, logit=3.0, sh_dc=(0.0, 0.0, 0.0)):
+    sc = scenes.Scene(np.array(mu, np.float32).reshape(3, 1),
+                      np.array(log_scale, np.float32).reshape(3, 1),
+                      np.array(quat, np.float32).reshape(4, 1),
+                      np.array([logit], np.float32),
+                      np.array(sh_dc, np.float32).reshape(1, 3, 1), 0)
+    return sc
+
+
+def test_isotropic_on_axis_closed_form(O):
+    """A sphere of radius s at depth z on the optical axis projects to
+    (fx s / z)^2 I + 0.3 I, centred on the principal point."""
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 256, 256)
+    for z, ls in [(5.0, -2.0), (3.0, -3.5), (10.0, 0.0)]:
+        pre = O.preprocess(_single([0, 0, z], [ls] * 3, [1, 0, 0, 0]), cam)
+        s = math.exp(np.float32(ls))
+        fx = float(cam["fx"])
+        var = (fx * s / z) ** 2 + 0.3
+        assert pre.flags[0] >= 1
+        np.testing.assert_allclose(pre.cov2d[0], [var, 0, var], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(pre.conic[0], [1 / var, 0, 1 / var], rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(pre.mean2d[0], [float(cam["cx"]), float(cam["cy"])], atol=1e-12)
+        assert pre.depth[0] == pytest.approx(z, rel=1e-15)
+        assert pre.extent[0] == pytest.approx(3 * math.sqrt(var + math.sqrt(0.1)), rel=1e-12)
+
+
+def test_ewa_matches_monte_carlo_projection(O):
+    """Sample the 3D Gaussian built from scipy's rotation convention, push the
+    samples through the pinhole camera, and compare the sample covariance of
+    the image points with the oracle's 2D covariance (minus the 0.3 dilation).
+    Small s/z makes the first-order (EWA) projection accurate."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(3)
+    cam = scenes.look_camera((0.3, -0.2, -6.0), (0.05, 0.02, 1.0), (0, -1, 0), 320, 240)
+    vm = np.asarray(cam["viewmat"], np.float64).reshape(3, 4)
+    Rc, tc = vm[:, :3], vm[:, 3]
+    fx, fy, cx, cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
+    for trial in range(3):
+        mu = rng.uniform(-0.5, 0.5, 3)
+        ls = rng.uniform(-4.5, -3.0, 3)
+        q = rng.normal(size=4)
+        q /= np.linalg.norm(q)
+        sc = _single(mu, ls, q)
+        pre = O.preprocess(sc, cam)
+        mu64 = sc.means[:, 0].astype(np.float64)
+        s64 = np.exp(sc.log_scales[:, 0].astype(np.float64))
+        q64 = sc.quats[:, 0].astype(np.float64)
+        R = Rotation.from_quat([q64[1], q64[2], q64[3], q64[0]]).as_matrix()
+        S3 = R @ np.diag(s64 ** 2) @ R.T
+        pts = rng.multivariate_normal(mu64, S3, size=400_000)
+        pc = pts @ Rc.T + tc
+        uv = np.stack([fx * pc[:, 0] / pc[:, 2] + cx, fy * pc[:, 1] / pc[:, 2] + cy])
+        emp = np.cov(uv)
+        ora = np.array([[pre.cov2d[0, 0] - 0.3, pre.cov2d[0, 1]],
+                        [pre.cov2d[0, 1], pre.cov2d[0, 2] - 0.3]])
+        scale = np.sqrt(np.diag(ora)).max() ** 2
+        assert np.abs(emp - ora).max() / scale < 0.02
+        pc0 = Rc @ mu64 + tc
+        np.testing.assert_allclose(pre.mean2d[0], [fx * pc0[0] / pc0[2] + cx, fy * pc0[1] / pc0[2] + cy],
+                                   rtol=1e-12)
+
+
+def test_near_cull_and_degenerate_quaternion(O):
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 64, 64)
+    assert O.preprocess(_single([0, 0, 0.1999], [-2] * 3, [1, 0, 0, 0]), cam).flags[0] == 0
+    assert O.preprocess(_single([0, 0, 0.2001], [-2] * 3, [1, 0, 0, 0]), cam).flags[0] >= 1
+    a = O.preprocess(_single([0.1, 0.2, 4], [-2, -3, -2.5], [0, 0, 0, 0]), cam)
+    b = O.preprocess(_single([0.1, 0.2, 4], [-2, -3, -2.5], [1, 0, 0, 0]), cam)
+    np.testing.assert_array_equal(a.cov2d, b.cov2d)
+    nan = O.preprocess(_single([np.nan, 0, 4], [-2] * 3, [1, 0, 0, 0]), cam)
+    assert nan.flags[0] == 0
+
+
+# --------------------------------------------------------------------------- eq. (9)-(10)
+def _annulus_integral(a, b, c, sigma, x, h_frac=0.004):
+    """Quadrature of alpha over {tau <= alpha < x} on a fine pixel-free grid
+    (the integral of eq. (8), evaluated numerically)."""
+    cov = np.array([[a, b], [b, c]])
+    inv = np.linalg.inv(cov)
+    lam = np.linalg.eigvalsh(cov)
+    R = math.sqrt(2 * math.log(sigma / O_TAU)) * math.sqrt(lam.max()) * 1.02
+    h = h_frac * math.sqrt(lam.min())
+    g = np.arange(-R, R + h, h)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    q = inv[0, 0] * X * X + 2 * inv[0, 1] * X * Y + inv[1, 1] * Y * Y
+    al = sigma * np.exp(-0.5 * q)
+    m = (al >= O_TAU) & (al < x)
+    return float(al[m].sum() * h * h)
+
+
+O_TAU = 1.0 / 255.0
+
+
+@pytest.mark.parametrize("a,b,c,sigma,K,Tu", [
+    (4.3, 0.0, 1.3, 0.5, 0.1, 1.0),
+    (9.3, 2.0, 4.3, 0.8, 1.0, 1.0),
+    (0.9, 0.1, 0.7, 0.3, 0.1, 1.0),
+    (25.3, -6.0, 16.3, 0.9, 3.0, 0.4),
+])
+def test_threshold_solves_eq5_with_quadrature(O, a, b, c, sigma, K, Tu):
+    """Th of eq. (10) is the largest x with T_up * integral_{tau <= alpha < x} alpha <= K
+    (eq. (5) with the integral of eq. (8)); found here by bisection on a
+    numerically integrated score."""
+    det = a * c - b * b
+    lut = np.full(20, Tu, np.float32)
+    keep, th, s = O.adagscale(det, sigma, 5.0, K, lut)
+    assert keep
+    lo, hi = O_TAU, sigma
+    for _ in range(40):
+        mid = 0.5 * (lo + hi)
+        if np.float32(Tu) * _annulus_integral(a, b, c, sigma, mid) <= K:
+            lo = mid
+        else:
+            hi = mid
+    assert th == pytest.approx(lo, rel=2e-3)
+    # closed-form annulus integral of eq. (9) against the quadrature, at a few x
+    for x in (0.02, 0.5 * sigma, sigma):
+        quad = _annulus_integral(a, b, c, sigma, x)
+        assert quad == pytest.approx(2 * math.pi * math.sqrt(det) * (x - O_TAU), rel=2e-3)
+
+
+def test_scale_factor_is_contour_ratio(O):
+    """s shrinks the alpha = tau contour onto the alpha = Th contour: along any
+    direction the radius where alpha drops to Th, over the radius where it
+    drops to tau, equals s (bisection on alpha along the ray)."""
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        L = rng.normal(size=(2, 2))
+        cov = L @ L.T + np.eye(2) * 0.5
+        a, b, c = cov[0, 0], cov[0, 1], cov[1, 1]
+        sigma = rng.uniform(0.05, 0.99)
+        K = rng.uniform(0.01, 2.0)
+        keep, th, s = O.adagscale(a * c - b * b, sigma, 3.0, K)
+        if not keep:
+            assert th >= sigma
+            continue
+        u = rng.normal(size=2)
+        u /= np.linalg.norm(u)
+        inv = np.linalg.inv(cov)
+
+        def radius(t):
+            lo, hi = 0.0, 1e3
+            for _ in range(200):
+                m = 0.5 * (lo + hi)
+                if sigma * math.exp(-0.5 * m * m * (u @ inv @ u)) >= t:
+                    lo = m
+                else:
+                    hi = m
+            return lo
+        assert radius(th) / radius(O_TAU) == pytest.approx(s, rel=1e-9)
+
+
+def test_threshold_special_cases(O):
+    """Th >= tau always; K = 0 gives Th = tau and s = 1 exactly; Th >= opacity
+    drops the Gaussian (Sec. 3.3); an empty LUT bin (T_up = 0) drops it too."""
+    keep, th, s = O.adagscale(4.0, 0.5, 3.0, 0.0)
+    assert keep and th == O_TAU and s == 1.0
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        det = rng.uniform(0.1, 1e4)
+        sigma = rng.uniform(0.0, 1.0)
+        K = rng.uniform(0, 10)
+        keep, th, s = O.adagscale(det, sigma, 3.0, K)
+        assert th >= O_TAU
+        assert keep == (th < sigma)
+        if keep:
+            assert 0.0 < s <= 1.0
+    assert not O.adagscale(4.0, 0.5, 3.0, 0.1, np.zeros(20, np.float32))[0]
+
+
+def test_lut_bin_lookup(O):
+    """T_up is piecewise constant over 20 uniform depth bins of [0, D_max]
+    (Sec. 3.4); depths beyond D_max use the last bin."""
+    lut = np.arange(1, 21, dtype=np.float32) / 20
+    det, sigma, K = 9.0, 0.9, 0.05
+    for depth, b in [(0.3, 0), (4.99, 0), (5.0, 1), (52.0, 10), (99.9, 19), (150.0, 19)]:
+        _, th, _ = O.adagscale(det, sigma, depth, K, lut, 100.0)
+        expect_tu = float(lut[b])
+        assert th == pytest.approx(K / (expect_tu * 2 * math.pi * 3.0) + O_TAU, rel=1e-14)
+    _, th, _ = O.adagscale(det, sigma, 52.0, K, lut, 1000.0)
+    assert th == pytest.approx(K / (float(lut[1]) * 2 * math.pi * 3.0) + O_TAU, rel=1e-14)
+
+
+# --------------------------------------------------------------------------- blend closed forms
+def _pipeline_single(O, gaussians, cam, bg=(0, 0, 0)):
+    """Build a Frame from explicit 2D records (mean, conic, opacity, rgb)."""
+    n = len(gaussians)
+    rec = np.zeros((n, 9))
+    for i, g in enumerate(gaussians):
+        rec[i] = g
+    rec = rec.astype(np.float32).astype(np.float64)
+    ntiles = O.num_tiles(cam)
+    sv = np.arange(n, dtype=np.uint32)
+    rg = np.zeros((ntiles, 2), np.int64)
+    rg[:, 1] = n
+    fr = O.Frame(None, None, None, None, sv, rg)
+    return O.blend(fr, cam, bg, rec=rec)
+
+
+def test_blend_single_gaussian_at_centre(O):
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 16, 16)
+    for sigma in (0.2, 0.7, 0.995):
+        img, T, nc, *_ = _pipeline_single(O, [(5, 7, 0.5, 0.1, 0.3, sigma, 0.2, 0.5, 0.9)], cam)
+        a = min(0.99, float(np.float32(sigma)))
+        np.testing.assert_allclose(img[:, 7, 5], a * np.float32([0.2, 0.5, 0.9]).astype(np.float64),
+                                   rtol=1e-14)
+        assert T[7, 5] == pytest.approx(1 - a, rel=1e-14)
+        assert nc[7, 5] == 1
+
+
+def test_blend_two_gaussians_closed_form(O):
+    """C = a1 c1 + a2 (1 - a1) c2 + (1 - a1)(1 - a2) bg with a_i = s_i exp(power_i)."""
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 16, 16)
+    g1 = (3.0, 4.0, 0.2, 0.05, 0.1, 0.6, 1.0, 0.0, 0.2)
+    g2 = (6.0, 2.0, 0.1, -0.02, 0.3, 0.8, 0.0, 1.0, 0.4)
+    bg = (0.1, 0.2, 0.3)
+    img, T, nc, *_ = _pipeline_single(O, [g1, g2], cam, bg)
+    for py, px in [(4, 3), (2, 6), (5, 5), (0, 0)]:
+        col = np.zeros(3)
+        Tt = 1.0
+        for g in (g1, g2):
+            g = np.float32(g).astype(np.float64)
+            dx, dy = g[0] - px, g[1] - py
+            a = min(0.99, g[5] * math.exp(-0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy))
+            if a < O_TAU:
+                continue
+            col += a * Tt * g[6:9]
+            Tt *= 1 - a
+        np.testing.assert_allclose(img[:, py, px], col + Tt * np.array(bg), rtol=1e-13, atol=1e-15)
+
+
+def test_blend_early_exit_and_clamp(O):
+    """Stacked opaque Gaussians: alpha clamps to 0.99, T goes 1 -> 0.01 -> 1e-4;
+    the third would push T below 1e-4, so the pixel stops with two blended."""
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 16, 16)
+    g = (8.0, 8.0, 0.5, 0.0, 0.5, 0.999, 1.0, 1.0, 1.0)
+    img, T, nc, *_ = _pipeline_single(O, [g, g, g, g], cam)
+    assert nc[8, 8] == 2
+    assert T[8, 8] == pytest.approx(1e-4, rel=1e-10)
+    assert T[8, 8] >= 1e-4
+    assert img[0, 8, 8] == pytest.approx(0.99 + 0.99 * 0.01, rel=1e-12)
+
+
+def test_blend_skips_below_tau(O):
+    """A Gaussian whose alpha stays below 1/255 everywhere contributes nothing."""
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 16, 16)
+    img, T, nc, *_ = _pipeline_single(O, [(8, 8, 0.5, 0, 0.5, 1.0 / 256, 1, 1, 1)], cam)
+    assert np.all(img == 0) and np.all(T == 1) and np.all(nc == 0)
+
+
+# --------------------------------------------------------------------------- pipeline vs brute force
+@pytest.mark.parametrize("adagscale,K", [(False, 0.0), (True, 0.1), (True, 1.0)])
+def test_tile_pipeline_equals_bruteforce(O, adagscale, K):
+    """Emit + sort + ranges + blend equals blending, per pixel, every Gaussian
+    whose tile rectangle holds the pixel's tile, ordered by (depth, index)."""
+    sc, cam = scenes.tiny_scene(n=400, seed=11)
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 64, 48)
+    fr = O.render(sc, cam, O.Mode(adagscale=adagscale, K=K), bg=(0.1, 0.0, 0.3))
+    img, T, nc = O.blend_bruteforce(fr.pre, cam, 1, bg=(0.1, 0.0, 0.3))
+    np.testing.assert_array_equal(fr.image, img)
+    np.testing.assert_array_equal(fr.final_T, T)
+    np.testing.assert_array_equal(fr.n_contrib, nc)
+
+
+def test_emit_sort_ranges_against_numpy(O):
+    sc, cam = scenes.tiny_scene(seed=3)
+    pre = O.preprocess(sc, cam, O.Mode(adagscale=True, K=0.3))
+    keys, vals = O.emit(pre, cam)
+    assert keys.size == pre.tiles_touched.sum()
+    # emitted multiset: every tile of every rectangle exactly once
+    TX = (cam["width"] + 15) // 16
+    exp = []
+    for g in np.nonzero(pre.tiles_touched)[0]:
+        x0, y0, x1, y1 = pre.rect[g]
+        d = np.float32(pre.depth[g]).view(np.uint32)
+        for ty in range(y0, y1):
+            for tx in range(x0, x1):
+                exp.append(((ty * TX + tx) << 32) | int(d))
+    np.testing.assert_array_equal(keys, np.array(exp, np.uint64))
+    sk, sv = O.sort(keys, vals)
+    order = np.lexsort((vals, keys))
+    np.testing.assert_array_equal(sk, keys[order])
+    np.testing.assert_array_equal(sv, vals[order])
+    rg = O.ranges(sk, O.num_tiles(cam))
+    tiles = (sk >> np.uint64(32)).astype(np.int64)
+    for t in range(O.num_tiles(cam)):
+        assert rg[t, 0] == np.searchsorted(tiles, t, "left") or rg[t, 0] == rg[t, 1] == 0
+        assert rg[t, 1] - rg[t, 0] == np.count_nonzero(tiles == t)
+
+
+def test_blend_invariants_tiny(O):
+    sc, cam = scenes.tiny_scene()
+    fr = O.render(sc, cam)
+    assert np.all(fr.final_T >= 1e-4) and np.all(fr.final_T <= 1)
+    lens = fr.ranges[:, 1] - fr.ranges[:, 0]
+    TX = 8
+    for py in range(0, 128, 7):
+        for px in range(0, 128, 5):
+            t = (py // 16) * TX + px // 16
+            assert fr.n_contrib[py, px] <= lens[t]
+            assert fr.evals[py, px] <= lens[t]
+    assert np.all(fr.image >= 0)
+
+
+def test_unrestricted_blend_is_close(O):
+    """Diagnostic: blending every Gaussian (no tile rectangles) differs from the
+    tile pipeline only by the alpha mass outside the 3-sigma extent."""
+    sc, cam = scenes.tiny_scene(n=300, seed=2)
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 48, 48)
+    fr = O.render(sc, cam)
+    img2, _, _ = O.blend_bruteforce(fr.pre, cam, 2)
+    assert np.abs(img2 - fr.image).max() < 0.05
+
+
+# --------------------------------------------------------------------------- metrics
+def test_psnr_ssim_definitions(O):
+    rng = np.random.default_rng(6)
+    a = rng.uniform(0, 1, (3, 40, 40))
+    b = np.clip(a + 0.01, 0, 1)
+    assert O.psnr(a, b) == pytest.approx(10 * np.log10(1 / np.mean((a - b) ** 2)))
+    assert O.ssim(a, a) == pytest.approx(1.0, abs=1e-12)
+    c1, c2 = np.full((3, 20, 20), 0.3), np.full((3, 20, 20), 0.6)
+    C1 = 0.01 ** 2
+    assert O.ssim(c1, c2) == pytest.approx((2 * 0.18 + C1) / (0.09 + 0.36 + C1), rel=1e-9)
+
+
+def test_conic_inverts_covariance(O):
+    sc, cam = scenes.tiny_scene(seed=9)
+    pre = O.preprocess(sc, cam)
+    m = pre.flags >= 1
+    A, B, Cc = pre.conic[m].T
+    a, b, c = pre.cov2d[m].T
+    np.testing.assert_allclose(A * a + B * b, 1, atol=1e-12)
+    np.testing.assert_allclose(A * b + B * c, 0, atol=1e-12)
+    np.testing.assert_allclose(B * b + Cc * c, 1, atol=1e-12)
+
+
+@pytest.mark.parametrize("adagscale", [False, True])
+def test_rect_covers_extent_disc(O, adagscale):
+    """Every pixel within the (scaled) extent of the centre, less one pixel (the
+    rectangle rule rounds the centre's far edge to whole pixels), lies in a tile
+    of the Gaussian's rectangle, and no rectangle tile lies farther than one
+    tile beyond the extent (brute force over pixels)."""
+    sc, _ = scenes.tiny_scene(n=150, seed=4)
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 100, 70)
+    pre = O.preprocess(sc, cam, O.Mode(adagscale=adagscale, K=0.5))
+    py, px = np.mgrid[0:70, 0:100]
+    for g in np.nonzero(pre.flags == 2)[0]:
+        u, v = pre.mean2d[g]
+        r = pre.radius[g]
+        assert r == math.ceil(pre.extent[g] * pre.scale[g])
+        x0, y0, x1, y1 = pre.rect[g]
+        e = pre.extent[g] * pre.scale[g] - 1.0
+        inside = (np.abs(px - u) <= e) & (np.abs(py - v) <= e)
+        tx, ty = px[inside] // 16, py[inside] // 16
+        assert np.all((tx >= x0) & (tx < x1) & (ty >= y0) & (ty < y1))
+        for t_y in range(y0, y1):
+            for t_x in range(x0, x1):
+                nx = min(max(u, 16 * t_x), 16 * t_x + 15)
+                ny = min(max(v, 16 * t_y), 16 * t_y + 15)
+                assert max(abs(nx - u), abs(ny - v)) <= r + 16
