@@ -1,0 +1,308 @@
+"""Benchmark: frames per second of the 3D-GS tile-rendering hot path with
+AdaGScale beside plain 3D-GS, on the synthetic 6M-Gaussian city scene at
+4608x3456 (the Mill-19 resolution of the paper's Table I).
+
+A step is one frame of the whole forward path -- preprocess, pair emission,
+sort, tile ranges, rasterization -- enqueued through the C-ABI with the scene
+and every buffer already resident in HBM (pair buffers sized beforehand, so
+no host round trip inside the timed region).  K is binary-searched on the
+measured view so that PSNR(AdaGScale vs plain) sits at the quality point
+that corresponds to the paper's 0.5 dB drop.
+
+Prints ONE JSON line.  Single GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FPS @4608x3456 6M-Gaussian scene, AdaGScale vs plain 3D-GS; pairs; PSNR"
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+# Per evaluation of eq. (1)-(2) for one (pixel, Gaussian): dx, dy (2), the
+# sum-of-squares exponent (u = dx + beta dy: 2; A u^2 + gamma dy^2: 5;
+# times -1/2: 1), exp (1), times opacity (1), clamp (1), tau test (1),
+# 1 - alpha (1), T (1 - alpha) (1), stop test (1), alpha T (1), three colour
+# FMAs (6): 25 floating-point operations.
+FLOP_PER_EVAL = 25
+PSNR_TARGET_DB = 29.8
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--n", type=int, default=6_000_000)
+    p.add_argument("--width", type=int, default=4608)
+    p.add_argument("--height", type=int, default=3456)
+    p.add_argument("--K", type=float, default=None, help="fixed K (skip the search)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample-tiles", type=int, default=24)
+    return p.parse_args()
+
+
+class StageTimer:
+    """HIP events around each stage call, on the stream the kernels run on."""
+
+    def __init__(self, torch, stream, names):
+        self.t, self.s, self.names = torch, stream, names
+        self.ev = []
+
+    def frame(self):
+        evs = [self.t.cuda.Event(enable_timing=True) for _ in range(len(self.names) + 1)]
+        self.ev.append(evs)
+        return evs
+
+    def summary(self):
+        out = {n: [] for n in self.names}
+        for evs in self.ev:
+            for i, n in enumerate(self.names):
+                out[n].append(evs[i].elapsed_time(evs[i + 1]))
+        return {n: float(np.mean(v)) for n, v in out.items()}
+
+
+def timed_frames(torch, R, scene, cam_s, mode_s, fb, steps, warmup, stream):
+    names = ["preprocess", "emit", "sort", "raster"]
+    for _ in range(warmup):
+        R.enqueue_frame(scene, cam_s, mode_s, fb, stream=stream)
+    torch.cuda.synchronize()
+    timer = StageTimer(torch, stream, names)
+    frame_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            evs = timer.frame()
+            evs[0].record(stream)
+            R.run_preprocess(scene, cam_s, mode_s, fb, stream)
+            evs[1].record(stream)
+            R.run_emit(fb, cam_s, stream)
+            evs[2].record(stream)
+            R.run_sort(fb, cam_s, stream)
+            evs[3].record(stream)
+            R.run_raster(fb, cam_s, (0.0, 0.0, 0.0), stream)
+            evs[4].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1000.0
+    for evs in timer.ev:
+        frame_ms.append(evs[0].elapsed_time(evs[-1]))
+    return wall / steps, np.array(frame_ms), timer.summary()
+
+
+def count_evaluations(torch, R, fb, cam_s):
+    """Algorithmic evaluations of eq. (1): per pixel, the list entries up to and
+    including the one that stopped it (the whole list if none did), as the
+    rasterizer reports them."""
+    ne = torch.empty((fb.height, fb.width), dtype=torch.int32, device=fb.image.device)
+    R.run_raster(fb, cam_s, (0.0, 0.0, 0.0), n_evaluated=ne)
+    torch.cuda.synchronize()
+    return int(ne.to(torch.int64).sum().item())
+
+
+def psnr_t(torch, a, b):
+    mse = torch.mean((a.clamp(0, 1) - b.clamp(0, 1)) ** 2).item()
+    return float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)
+
+
+def ssim_t(torch, a, b):
+    import torch.nn.functional as F
+    x = torch.arange(11, dtype=torch.float32, device=a.device) - 5
+    g = torch.exp(-x ** 2 / (2 * 1.5 ** 2))
+    g = g / g.sum()
+    w = (g[:, None] * g[None, :])[None, None].repeat(3, 1, 1, 1)
+    a = a.clamp(0, 1)[None]
+    b = b.clamp(0, 1)[None]
+    f = lambda z: F.conv2d(z, w, groups=3)
+    ma, mb = f(a), f(b)
+    saa = f(a * a) - ma * ma
+    sbb = f(b * b) - mb * mb
+    sab = f(a * b) - ma * mb
+    c1, c2 = 0.01 ** 2, 0.03 ** 2
+    m = ((2 * ma * mb + c1) * (2 * sab + c2)) / ((ma * ma + mb * mb + c1) * (saa + sbb + c2))
+    return float(m.mean().item())
+
+
+def search_K(torch, R, gsr, scene, cam, cam_s, fb_plain, fb, stream):
+    """Binary search (in log K) for the largest K with PSNR(ada vs plain) >=
+    the target; PSNR falls as K grows (Sec. 3.4)."""
+    ref = fb_plain.image.clone()
+    lo, hi = 1e-3, 1e3
+    best = lo
+    for _ in range(14):
+        mid = math.sqrt(lo * hi)
+        R.render(scene, cam, adagscale=True, K=mid, fb=fb, slack=1.2)
+        p = psnr_t(torch, fb.image, ref)
+        if p >= PSNR_TARGET_DB:
+            best, lo = mid, mid
+        else:
+            hi = mid
+    return float(np.float32(best))
+
+
+def cpu_baseline(args, scene_h, cam, K, n_tiles_sample):
+    """The oracle (single-threaded FP64 C) on a bounded sample of the same
+    frame, scaled to one whole frame."""
+    from oracle import oracle as O
+    mode = O.Mode(adagscale=True, K=K)
+    t0 = time.perf_counter()
+    pre = O.preprocess(scene_h, cam, mode)
+    t_pre = time.perf_counter() - t0
+    vis = np.nonzero(pre.tiles_touched > 0)[0]
+    rng = np.random.default_rng(0)
+    frac = 1.0 / 64.0
+    sub = np.sort(rng.choice(vis, size=max(1, int(len(vis) * frac)), replace=False))
+    sub_pre = O.Preproc(**{k: (getattr(pre, k)[sub] if getattr(pre, k).shape[0] == scene_h.n else getattr(pre, k))
+                           for k in pre.__dataclass_fields__})
+    t0 = time.perf_counter()
+    keys, vals = O.emit(sub_pre, cam)
+    sk, sv = O.sort(keys, vals)
+    t_es = (time.perf_counter() - t0) / frac
+    # blend a sample of tiles with their full lists (B1 lists for those tiles)
+    W, H = cam["width"], cam["height"]
+    TX, TY = (W + 15) // 16, (H + 15) // 16
+    tiles = np.sort(rng.choice(TX * TY, size=n_tiles_sample, replace=False)).astype(np.int32)
+    rect = pre.rect
+    d32 = pre.depth.astype(np.float32)
+    lists, ranges = [], np.zeros((TX * TY, 2), np.int64)
+    off = 0
+    for t in tiles:
+        ty, tx = divmod(int(t), TX)
+        m = (pre.tiles_touched > 0) & (rect[:, 0] <= tx) & (tx < rect[:, 2]) & (rect[:, 1] <= ty) & (ty < rect[:, 3])
+        ids = np.nonzero(m)[0]
+        ids = ids[np.lexsort((ids, d32[ids]))]
+        lists.append(ids.astype(np.uint32))
+        ranges[t] = (off, off + ids.size)
+        off += ids.size
+    sv_s = np.concatenate(lists) if lists else np.zeros(0, np.uint32)
+    fr = O.Frame(pre, None, None, None, sv_s, ranges)
+    rec = pre.record()
+    t0 = time.perf_counter()
+    O.blend(fr, cam, tiles=tiles, rec=rec)
+    t_bl = (time.perf_counter() - t0) * (TX * TY) / len(tiles)
+    t_frame = t_pre + t_es + t_bl
+    return {"value": 1.0 / t_frame, "unit": "FPS", "cores": 1, "kind": "oracle",
+            "sample": (f"AdaGScale K={K:g}: full preprocess of {scene_h.n} Gaussians ({t_pre:.1f} s), "
+                       f"emit+sort of a 1/64 sample of visible Gaussians scaled x64 ({t_es:.1f} s), "
+                       f"blend of {len(tiles)} random tiles scaled to {TX * TY} tiles ({t_bl:.1f} s); "
+                       f"single-threaded FP64 C, -O2")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "single-GPU build: bench.py runs on one GPU only "
+                                   f"(asked for --gpus {args.gpus})"}))
+        sys.exit(2)
+    import torch
+    from paper_2604_18980_amd import gsr, render as R, scenes
+
+    gsr.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    scene_h, cam = scenes.city_scene(n=args.n, width=args.width, height=args.height)
+    log(f"scene generated in {time.perf_counter() - t0:.1f} s")
+    scene = R.DeviceScene.from_host(scene_h, dev)
+    cam_s = gsr.camera_struct(cam)
+    stream = torch.cuda.current_stream()
+
+    # plain frame, to size buffers and as the PSNR reference
+    fb_p = R.render(scene, cam, fb=None, slack=1.05)
+    torch.cuda.synchronize()
+    P_plain = int(fb_p.num_pairs.item())
+    log(f"plain pairs {P_plain}")
+    fb_a = R.FrameBuffers(scene.n, cam["width"], cam["height"], int(P_plain * 1.05) + 1024, dev)
+    K = args.K if args.K is not None else search_K(torch, R, gsr, scene, cam, cam_s, fb_p, fb_a, stream)
+    R.render(scene, cam, adagscale=True, K=K, fb=fb_a)
+    torch.cuda.synchronize()
+    P_ada = int(fb_a.num_pairs.item())
+    psnr = psnr_t(torch, fb_a.image, fb_p.image)
+    ssim = ssim_t(torch, fb_a.image, fb_p.image)
+    log(f"K={K} pairs {P_ada} psnr {psnr:.2f} ssim {ssim:.4f}")
+    E_plain = count_evaluations(torch, R, fb_p, cam_s)
+    E_ada = count_evaluations(torch, R, fb_a, cam_s)
+
+    mode_p = gsr.mode_struct()
+    mode_a = gsr.mode_struct(adagscale=True, K=K)
+    wall_a, fms_a, st_a = timed_frames(torch, R, scene, cam_s, mode_a, fb_a, args.steps, args.warmup, stream)
+    wall_p, fms_p, st_p = timed_frames(torch, R, scene, cam_s, mode_p, fb_p, args.steps, args.warmup, stream)
+    assert int(fb_a.num_pairs.item()) == P_ada and int(fb_p.num_pairs.item()) == P_plain
+
+    ms_a = float(np.median(fms_a))
+    ms_p = float(np.median(fms_p))
+    # dominant kernel: the rasterizer (one kernel per frame, timed by its events)
+    raster_ms = st_a["raster"]
+    flops = E_ada * FLOP_PER_EVAL
+    achieved = flops / (raster_ms * 1e-3) / 1e12
+    # HBM-bound stages: algorithmic bytes of this design
+    n = scene.n
+    vis = int((fb_a.tiles_touched > 0).sum().item())
+    vm = np.asarray(cam["viewmat"], np.float64).reshape(3, 4)
+    front = int(((vm[2, :3] @ scene_h.means.astype(np.float64)) + vm[2, 3] > 0.2).sum())
+    nsh = 3 * 16
+    ntiles = int(fb_a.ranges.shape[0])
+    passes = max(1, (int(math.ceil(math.log2(max(ntiles, 2)))) + 7) // 8)
+    pre_bytes = 12 * n + 32 * front + 4 * nsh * vis + 12 * n + 48 * vis
+    emit_bytes = 8 * n + vis * (4 + 8 + 4 * 20 + 12 + 12) + 8 * P_ada
+    sort_bytes = passes * 20 * P_ada - 4 * P_ada + 4 * P_ada + 8 * ntiles
+    stage_bw = {
+        "preprocess": pre_bytes / (st_a["preprocess"] * 1e-3) / 1e9,
+        "emit": emit_bytes / (st_a["emit"] * 1e-3) / 1e9,
+        "sort": sort_bytes / (st_a["sort"] * 1e-3) / 1e9,
+    }
+    out = {
+        "metric": METRIC,
+        "value": 1000.0 / ms_a,
+        "unit": "FPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_a,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "synthetic city, 6M Gaussians, 4608x3456, SH degree 3",
+                   "n_gaussians": n, "width": cam["width"], "height": cam["height"],
+                   "sh_degree": 3, "mode": "adagscale", "K": K,
+                   "psnr_target_db": PSNR_TARGET_DB},
+        "adagscale": {"fps": 1000.0 / ms_a, "ms_p50": ms_a, "ms_p99": float(np.percentile(fms_a, 99)),
+                      "pairs": P_ada, "pairs_per_s": P_ada / (ms_a * 1e-3), "K": K,
+                      "stages_ms": st_a, "evaluations": E_ada},
+        "plain": {"fps": 1000.0 / ms_p, "ms_p50": ms_p, "ms_p99": float(np.percentile(fms_p, 99)),
+                  "pairs": P_plain, "pairs_per_s": P_plain / (ms_p * 1e-3), "stages_ms": st_p,
+                  "evaluations": E_plain},
+        "speedup_vs_plain": ms_p / ms_a,
+        "pair_ratio": P_ada / max(P_plain, 1),
+        "psnr_db_vs_plain": psnr,
+        "ssim_vs_plain": ssim,
+        "wall_ms_per_step": wall_a,
+        "stage_hbm": {k: {"achieved_GBs": v, "frac": v / PEAK_HBM_GBS} for k, v in stage_bw.items()},
+        "roofline": {"kernel": "k_raster", "bound": "alu", "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": None,
+                     "basis": f"{FLOP_PER_EVAL} FLOP per eq.(1)-(2) evaluation x {E_ada} list-bounded evaluations"},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline(args, scene_h, cam, K, args.cpu_sample_tiles)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * gsr.h -- C-ABI of the MI355X (gfx950) 3D Gaussian Splatting tile renderer
+ * with AdaGScale viewpoint-adaptive scaling.
+ *
+ * The paper (Jo et al., AdaGScale, arXiv 2604.18980) splits a frame into four
+ * stages (Sec. 2.1, Fig. 1): preprocessing, Gaussian-tile pair generation,
+ * sorting and rasterization.  AdaGScale changes only the first two: the
+ * preprocess computes a per-Gaussian alpha threshold Th (eq. 10), drops
+ * Gaussians whose Th exceeds their opacity (Sec. 3.3), and the pair test uses
+ * the smaller extent that Th implies; the rasterizer keeps the original
+ * covariance and tau = 1/255 ("dual size", Sec. 3.3).
+ *
+ * General rules for every entry point
+ * -----------------------------------
+ * - Every pointer argument is DEVICE memory unless marked "host".  Buffers are
+ *   owned by the caller; the library never allocates, frees or retains them.
+ * - All work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *   default stream).  No entry point synchronises the host.
+ * - Arguments are validated on the host before anything is enqueued.  On
+ *   failure the call returns a non-zero gs_status, enqueues nothing, and
+ *   gs_last_error() returns a message (thread-local).
+ * - Pair counts live in device memory so that a frame can be enqueued (and
+ *   captured in a HIP graph) without a host round trip; see gs_emit_pairs.
+ *
+ * Layouts
+ * -------
+ * scene  : structure of arrays, float32, [C][n] contiguous:
+ *          means [3][n], log_scales [3][n], quats [4][n] (w, x, y, z; need not
+ *          be normalised), opacity_logits [n], sh [(d+1)^2][3][n] (SH
+ *          coefficient k of colour channel c of Gaussian i at (k*3+c)*n+i).
+ * splat  : array of structures, float32 [n][12], one 48-byte record per
+ *          Gaussian, written by gs_preprocess:
+ *            [0] mean x (pixels)   [1] mean y     [2] A         [3] beta
+ *            [4] gamma             [5] opacity    [6] depth     [7] Th
+ *            [8] red   [9] green   [10] blue      [11] extent scale s
+ *          A, beta, gamma hold the inverse 2D covariance of eq. (1) as a sum
+ *          of squares: with dx = mean x - px, dy = mean y - py,
+ *            d^T Sigma2^-1 d = A (dx + beta dy)^2 + gamma dy^2,
+ *          A = c/det, beta = -b/c, gamma = 1/c for Sigma2 = [[a, b], [b, c]]
+ *          (no cancellation for thin Gaussians far from their centre); the
+ *          alpha exponent is minus half of it.  Fields of Gaussians with
+ *          tiles_touched == 0 are unspecified.
+ * rect   : uint64 per Gaussian: x0 | y0 << 16 | x1 << 32 | y1 << 48, the
+ *          half-open rectangle of 16x16 tiles the Gaussian is paired with.
+ * pairs  : two parallel uint32 arrays, tile id (ty * TX + tx) and Gaussian id.
+ * ranges : uint32 [num_tiles][2] = [first, one-past-last) into the sorted pairs.
+ * image  : float32 [3][H][W]; final_T float32 [H][W]; n_contrib uint32 [H][W].
+ * Tiles are 16x16 pixels; TX = ceil(W/16), TY = ceil(H/16).
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GS_OK = 0,
+    GS_ERR_INVALID_ARGUMENT = 1, /* a pointer, size or option is out of range */
+    GS_ERR_CAPACITY = 2,         /* a caller buffer is too small */
+    GS_ERR_HIP = 3,              /* a HIP runtime call failed (message has the HIP text) */
+    GS_ERR_UNSUPPORTED = 4       /* valid request this build does not implement */
+} gs_status;
+
+#define GS_TILE 16
+#define GS_LUT_BINS 20
+#define GS_MAX_SH_DEGREE 3
+#define GS_MAX_IMAGE_SIDE 32768 /* tile coordinates are stored in 16 bits */
+
+/* Scene parameters (device, SoA float32, see layouts above). */
+typedef struct {
+    const float *means;
+    const float *log_scales;
+    const float *quats;
+    const float *opacity_logits;
+    const float *sh;
+    int64_t n;     /* number of Gaussians, 0 <= n < 2^31 */
+    int sh_degree; /* 0..3 */
+} gs_scene;
+
+/* Pinhole camera (host struct).  viewmat is the row-major 3x4 [R | t] mapping
+ * world to camera coordinates (x right, y down, z forward).  Pixel (px, py)
+ * is sampled at its integer coordinates. */
+typedef struct {
+    float viewmat[12];
+    float fx, fy, cx, cy;
+    int width, height; /* 1 .. GS_MAX_IMAGE_SIDE */
+} gs_camera;
+
+/* Per-call method switch (host struct).
+ * adagscale = 0: plain 3D-GS extent (3 standard deviations, tau = 1/255).
+ * adagscale = 1: AdaGScale (Sec. 3.2-3.3).  Th = K / (T_up(depth) 2 pi
+ *   sqrt(det Sigma2)) + tau (eq. 10) with T_up looked up in t_upper over 20
+ *   uniform bins of [0, lut_depth_max] (Sec. 3.4; depths beyond use the last
+ *   bin).  A Gaussian with Th >= opacity, or whose bin holds T_up <= 0, gets no
+ *   pairs; otherwise its extent is scaled by s = sqrt(ln(opacity/Th) /
+ *   ln(opacity/tau)), the factor that maps the alpha = tau contour onto the
+ *   alpha = Th contour.  force_unit_scale = 1 keeps s = 1 (testing aid). */
+typedef struct {
+    int adagscale;
+    float K;                       /* peripheral-loss budget, >= 0 (eq. 5) */
+    float t_upper[GS_LUT_BINS];    /* T_up per depth bin, in [0, 1]; all 1 = uncalibrated */
+    float lut_depth_max;           /* > 0; the paper's range is 100 */
+    int force_unit_scale;
+} gs_mode;
+
+/* Raster launch geometry.  Tiles stay 16x16 so pair sets are comparable.
+ * threads_per_tile in {64, 128, 256}; pixels_per_thread = 256/threads_per_tile;
+ * lds_batch in {32, 64, 128, 256} Gaussians staged per round.  A zeroed
+ * struct (or NULL) selects the default. */
+typedef struct {
+    int threads_per_tile;
+    int pixels_per_thread;
+    int lds_batch;
+} gs_raster_cfg;
+
+/* Gradients of the scene parameters (device, SoA float32, same layouts as
+ * gs_scene; each pointer receives [C][n] values, overwritten). */
+typedef struct {
+    float *d_means;
+    float *d_log_scales;
+    float *d_quats;
+    float *d_opacity_logits;
+    float *d_sh;
+} gs_scene_grads;
+
+/* Bytes of scratch ("workspace") that gs_emit_pairs and gs_sort need for n
+ * Gaussians, pair_capacity pairs and a width x height image.  The same
+ * workspace may be reused by consecutive calls on one stream. */
+size_t gs_workspace_size(int64_t n, int64_t pair_capacity, int width, int height);
+
+/* Stage 1 (Sec. 2.1 preprocessing; Sec. 3.3 AdaGScale preprocessing).
+ * One thread per Gaussian: near-plane cull (z <= 0.2), EWA projection of the
+ * 3D covariance R S S^T R^T to Sigma2 = J W Sigma3 W^T J^T + 0.3 I, conic =
+ * Sigma2^-1, pixel mean, depth = camera z, opacity = sigmoid(logit), colour =
+ * max(0, SH(view direction) + 0.5), plain extent 3 sqrt(lambda_max) or the
+ * AdaGScale-scaled extent, and the tile rectangle.  Geometry that decides
+ * discrete outputs is evaluated in double precision.
+ * Out: splats [n][12], rects [n], tiles_touched [n] (0 = no pairs). */
+gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_mode *mode,
+                        float *splats, uint64_t *rects, uint32_t *tiles_touched, void *stream);
+
+/* Stage 2 (Sec. 2.1 Gaussian-tile pair generation; Sec. 3.3: the rectangle
+ * already reflects AdaGScale's extent).  Emits one (tile, Gaussian) pair per
+ * tile of each rectangle.  Pairs are emitted Gaussian by Gaussian in
+ * ascending (float32 depth, Gaussian id) order, tile rows outer, columns
+ * inner; a stable sort by tile of this list is therefore the paper's per-tile
+ * depth order.
+ * num_pairs (device int64) receives the number of pairs REQUIRED; at most
+ * pair_capacity pairs are written.  When *num_pairs > pair_capacity the
+ * caller must grow the buffers and run the frame again (stages 3-4 then see a
+ * truncated list and their output is meaningless).
+ * ws: workspace of at least gs_workspace_size(n, pair_capacity, W, H) bytes. */
+gs_status gs_emit_pairs(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
+                        int64_t n, const gs_camera *cam, uint32_t *pair_tiles, uint32_t *pair_gids,
+                        int64_t pair_capacity, int64_t *num_pairs, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/* Stage 3 (Sec. 2.1 sorting).  Stable LSD radix sort (8-bit digits, LDS
+ * histograms) of the pairs by tile id, so each tile's run keeps the depth
+ * order of emission.  Reads min(*num_pairs, pair_capacity) pairs from
+ * (pair_tiles, pair_gids), which are left unchanged; writes the sorted tile
+ * ids to sorted_tiles and the Gaussian ids to sorted_gids (both distinct from
+ * the inputs, pair_capacity entries each), and ranges [num_tiles][2]. */
+gs_status gs_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids, const int64_t *num_pairs,
+                  int64_t pair_capacity, const gs_camera *cam, uint32_t *sorted_tiles,
+                  uint32_t *sorted_gids, uint32_t *ranges, void *ws, size_t ws_bytes,
+                  void *stream);
+
+/* Stage 4 (Sec. 2.1 rasterization, eq. 1-2; dual size, Sec. 3.3).  Per 16x16
+ * tile, front to back over its sorted list: alpha = min(0.99, opacity *
+ * exp(power)), skipped when power > 0 or alpha < 1/255; a pixel stops before
+ * a Gaussian that would bring T below 1e-4; colour += alpha T rgb.  Writes
+ * image = colour + T * bg (bg: host float[3]), final_T and n_contrib (1 + list
+ * position of the last blended Gaussian, 0 if none).  n_evaluated (nullable,
+ * uint32 [H][W]) receives the number of list entries the pixel evaluated: up
+ * to and including the one that stopped it, else the whole list. */
+gs_status gs_rasterize(const float *splats, int64_t n, const uint32_t *sorted_gids,
+                       const uint32_t *ranges, const gs_camera *cam, const float *bg,
+                       const gs_raster_cfg *cfg, float *image, float *final_T,
+                       uint32_t *n_contrib, uint32_t *n_evaluated, void *stream);
+
+/* Adjoint of stage 4 with the pair set and every blend decision of the
+ * forward pass frozen.  Walks each pixel's list back to front from n_contrib,
+ * recovering T_i = T_{i+1} / (1 - alpha_i) from final_T instead of storing
+ * per-pixel lists.  dL_dimage [3][H][W]; grad_splats [n][12] receives, at the
+ * splat record's offsets, d mean x, d mean y, d A, d beta, d gamma,
+ * d opacity, d red, d green, d blue (other slots 0).  grad_splats is
+ * overwritten. */
+gs_status gs_rasterize_backward(const float *splats, int64_t n, const uint32_t *sorted_gids,
+                                const uint32_t *ranges, const gs_camera *cam, const float *bg,
+                                const float *final_T, const uint32_t *n_contrib,
+                                const float *dL_dimage, float *grad_splats, void *stream);
+
+/* Adjoint of stage 1 for Gaussians with tiles_touched > 0 (others get zero
+ * gradients): chains grad_splats through the projection, the covariance, the
+ * quaternion normalisation, the scale exponential, the opacity sigmoid and
+ * the SH colour (clamped channels pass no gradient).  The tile extent (and
+ * with it Th and s) passes no gradient. */
+gs_status gs_preprocess_backward(const gs_scene *scene, const gs_camera *cam,
+                                 const uint32_t *tiles_touched, const float *grad_splats,
+                                 const gs_scene_grads *out, void *stream);
+
+const char *gs_status_string(gs_status s);
+const char *gs_last_error(void);
+/* Library version string, e.g. "gsr 0.1 gfx950". */
+const char *gs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -169,9 +169,11 @@ static int is_finite(double x) { return x == x && fabs(x) <= 1.79769313486231570
 /* Inputs are float32 structure-of-arrays, [C][N]; cam[0..11] is the          */
 /* row-major [R|t] world-to-camera matrix, cam[12..15] = fx, fy, cx, cy.      */
 /* Outputs (double, [N][k]): mean2d[2], conic[3] (inverse 2D covariance      */
-/* entries A, B, C with power = -A dx^2/2 - C dy^2/2 - B dx dy), opacity,     */
-/* rgb[3], depth, cov2d[3] (dilated a, b, c), extent (plain v), th, scale,    */
-/* rect[4] (x0, y0, x1, y1 half-open, tiles), tiles_touched, radius (int).    */
+/* entries A, B, C: d^T Sigma2^-1 d = A dx^2 + 2 B dx dy + C dy^2), quad[3]   */
+/* (the same form as a sum of squares, A (dx + beta dy)^2 + gamma dy^2, with  */
+/* A = c/det, beta = -b/c, gamma = 1/c), opacity, rgb[3], depth, cov2d[3]     */
+/* (dilated a, b, c), extent (plain v), th, scale, rect[4] (x0, y0, x1, y1    */
+/* half-open, tiles), tiles_touched, radius (int).                           */
 /* flags: 0 culled, 1 projected (finite, in front), 2 projected with tiles.   */
 /* ------------------------------------------------------------------------ */
 void orc_preprocess(int64_t n, const float *means, const float *log_scales, const float *quats,
@@ -179,7 +181,8 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
                     const float *cam, int width, int height,
                     int adagscale, double K, const float *t_upper, double lut_depth_max,
                     int force_unit_scale,
-                    double *mean2d, double *conic, double *opacity, double *rgb, double *depth,
+                    double *mean2d, double *conic, double *quad, double *opacity, double *rgb,
+                    double *depth,
                     double *cov2d, double *extent, double *th, double *scale,
                     int32_t *rect, int64_t *tiles_touched, int32_t *radius, int32_t *flags) {
     double W[3][3], t[3];
@@ -276,6 +279,9 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
         conic[3 * g] = c / det;
         conic[3 * g + 1] = -b / det;
         conic[3 * g + 2] = a / det;
+        quad[3 * g] = c / det;
+        quad[3 * g + 1] = -b / c;
+        quad[3 * g + 2] = 1.0 / c;
         cov2d[3 * g] = a; cov2d[3 * g + 1] = b; cov2d[3 * g + 2] = c;
         opacity[g] = sigma;
         depth[g] = p[2];
@@ -385,9 +391,11 @@ void orc_ranges(int64_t np, const uint64_t *keys, int num_tiles, int64_t *ranges
 /* ------------------------------------------------------------------------ */
 /* Blending of one pixel, eq. (1)-(2), front to back.                        */
 /*                                                                           */
-/* rec[g*9 .. g*9+8] = mean x, mean y, conic A, B, C, opacity, r, g, b (the   */
-/* float32 record values, here in double).  For each listed Gaussian:         */
-/*   power = -(A dx^2 + C dy^2)/2 - B dx dy; skipped if power > 0;           */
+/* rec[g*9 .. g*9+8] = mean x, mean y, A, beta, gamma, opacity, r, g, b (the  */
+/* float32 record values, here in double).  For each listed Gaussian, with   */
+/* dx = mean x - px, dy = mean y - py:                                       */
+/*   power = -(A (dx + beta dy)^2 + gamma dy^2)/2 = -d^T Sigma2^-1 d / 2;     */
+/*   skipped if power > 0 (never, as both terms are squares);                */
 /*   alpha = min(0.99, opacity * exp(power)); skipped if alpha < tau;        */
 /*   if T (1 - alpha) < 1e-4 the pixel stops before adding this Gaussian;    */
 /*   otherwise colour += alpha T rgb and T *= 1 - alpha.                     */
@@ -414,12 +422,8 @@ static void blend_pixel(double px, double py, const uint32_t *list, int64_t len,
         const double *g = rec + 9 * (int64_t)list[j];
         ++ev;
         double dx = g[0] - px, dy = g[1] - py;
-        double power = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
-        double scale = 0.5 * (fabs(g[2] * dx * dx) + fabs(g[4] * dy * dy)) + fabs(g[3] * dx * dy);
-        if (scale > 0.0) {
-            double mp = fabs(power) / scale;
-            if (mp < margin) margin = mp;
-        }
+        double uu = dx + g[3] * dy;
+        double power = -0.5 * (g[2] * uu * uu + g[4] * dy * dy);
         if (power > 0.0) continue;
         double alpha = g[5] * exp(power);
         if (alpha > ALPHA_MAX) alpha = ALPHA_MAX;
@@ -527,7 +531,7 @@ void orc_blend_bruteforce(int mode, int64_t n, int width, int height, const int3
 /*   dC/dalpha_i = T_i c_i - (sum_{j>i} alpha_j T_j c_j + T_{n+1} bg)/(1-alpha_i) */
 /* alpha = min(0.99, sigma e^power): a clamped alpha has zero derivative;     */
 /* otherwise dalpha/dsigma = e^power and dalpha/dpower = alpha.              */
-/* Outputs accumulate into g2d[g*9 + (mx, my, A, B, C, sigma, r, g, b)].      */
+/* Outputs accumulate into g2d[g*9 + (mx, my, A, beta, gamma, sigma, r, g, b)]. */
 /* ------------------------------------------------------------------------ */
 void orc_blend_backward(int width, int height, const int64_t *ranges, const uint32_t *sorted_vals,
                         const double *rec, const double *bg, const double *dL_dimage, double *g2d) {
@@ -555,7 +559,8 @@ void orc_blend_backward(int width, int height, const int64_t *ranges, const uint
                 for (int64_t j = 0; j < len; ++j) {
                     const double *g = rec + 9 * (int64_t)list[j];
                     double dx = g[0] - px, dy = g[1] - py;
-                    double power = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
+                    double uu = dx + g[3] * dy;
+                    double power = -0.5 * (g[2] * uu * uu + g[4] * dy * dy);
                     if (power > 0.0) continue;
                     double e = exp(power);
                     double alpha = g[5] * e;
@@ -585,14 +590,15 @@ void orc_blend_backward(int width, int height, const int64_t *ranges, const uint
                     }
                     for (int ch = 0; ch < 3; ++ch) behind[ch] += a * Ti * g[6 + ch];
                     if (cl[k]) continue;
-                    double dx = g[0] - px, dy = g[1] - py;
+                    double dx = g[0] - px, dy = g[1] - py, uu = dx + g[3] * dy;
                     o[5] += dLda * ex[k];
                     double dLdp = dLda * a;
-                    o[2] += dLdp * (-0.5 * dx * dx);
+                    /* power = -(A u^2 + gamma dy^2)/2, u = dx + beta dy */
+                    o[2] += dLdp * (-0.5 * uu * uu);
+                    o[3] += dLdp * (-g[2] * uu * dy);
                     o[4] += dLdp * (-0.5 * dy * dy);
-                    o[3] += dLdp * (-dx * dy);
-                    o[0] += dLdp * (-(g[2] * dx + g[3] * dy));
-                    o[1] += dLdp * (-(g[4] * dy + g[3] * dx));
+                    o[0] += dLdp * (-g[2] * uu);
+                    o[1] += dLdp * (-(g[2] * uu * g[3] + g[4] * dy));
                 }
             }
     }
@@ -697,11 +703,11 @@ void orc_preprocess_backward(int64_t n, const float *means, const float *log_sca
         dp[1] += G[1] * fy / p[2];
         dp[2] += -G[0] * fx * p[0] / (p[2] * p[2]) - G[1] * fy * p[1] / (p[2] * p[2]);
 
-        /* conic (A, B, C) = (c, -b, a)/det  ->  dL/d(a, b, c) */
-        double gA = G[2], gB = G[3], gC = G[4];
-        double ga = gA * (-c * c / d2) + gB * (b * c / d2) + gC * (-b * b / d2);
-        double gb = gA * (2.0 * b * c / d2) + gB * (-(a * c + b * b) / d2) + gC * (2.0 * a * b / d2);
-        double gc = gA * (-b * b / d2) + gB * (a * b / d2) + gC * (-a * a / d2);
+        /* A = c/det, beta = -b/c, gamma = 1/c  ->  dL/d(a, b, c) */
+        double gA = G[2], gbeta = G[3], ggam = G[4];
+        double ga = gA * (-c * c / d2);
+        double gb = gA * (2.0 * b * c / d2) + gbeta * (-1.0 / c);
+        double gc = gA * (-b * b / d2) + gbeta * (b / (c * c)) + ggam * (-1.0 / (c * c));
         /* symmetric matrix gradient of Sigma2 (b occupies both off-diagonals) */
         double G2[2][2] = {{ga, 0.5 * gb}, {0.5 * gb, gc}};
         /* dL/dSigma3 = T^T G2 T ; dL/dT = 2 G2 T Sigma3 */

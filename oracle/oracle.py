@@ -56,7 +56,7 @@ def lib():
                                     C.c_int, P, P]
         L.orc_adagscale.restype = C.c_int
         L.orc_preprocess.argtypes = ([C.c_int64, P, P, P, P, P, C.c_int, P, C.c_int, C.c_int,
-                                      C.c_int, C.c_double, P, C.c_double, C.c_int] + [P] * 13)
+                                      C.c_int, C.c_double, P, C.c_double, C.c_int] + [P] * 14)
         L.orc_emit.argtypes = [C.c_int64, P, P, P, C.c_int, P, P]
         L.orc_emit.restype = C.c_int64
         L.orc_sort.argtypes = [C.c_int64, P, P]
@@ -93,7 +93,8 @@ def default_lut():
 class Mode:
     """Per-call method switch: plain 3D-GS (``adagscale=False``) or AdaGScale
     with peripheral-loss budget ``K`` and depth LUT ``t_upper`` over
-    [0, ``lut_depth_max``] (Sec. 3.4)."""
+    [0, ``lut_depth_max``] (Sec. 3.4).  K and lut_depth_max are single
+    precision at the library interface, so the oracle rounds them the same way."""
     adagscale: bool = False
     K: float = 0.0
     t_upper: np.ndarray = None
@@ -108,6 +109,7 @@ class Mode:
 class Preproc:
     mean2d: np.ndarray
     conic: np.ndarray
+    quad: np.ndarray
     opacity: np.ndarray
     rgb: np.ndarray
     depth: np.ndarray
@@ -121,11 +123,11 @@ class Preproc:
     flags: np.ndarray
 
     def record(self, round_to_f32: bool = True) -> np.ndarray:
-        """Per-Gaussian record used by the blend: mean x, mean y, conic A, B, C,
-        opacity, r, g, b.  The renderer stores it in float32, so by default the
+        """Per-Gaussian record used by the blend: mean x, mean y, A, beta, gamma
+        (the inverse covariance as A (dx + beta dy)^2 + gamma dy^2), opacity, r, g, b.  The renderer stores it in float32, so by default the
         values are rounded to float32 (and widened back to double); gradient
         checks keep the unrounded double values."""
-        rec = np.concatenate([self.mean2d, self.conic, self.opacity[:, None], self.rgb], axis=1)
+        rec = np.concatenate([self.mean2d, self.quad, self.opacity[:, None], self.rgb], axis=1)
         if round_to_f32:
             rec = rec.astype(np.float32)
         return np.ascontiguousarray(rec.astype(np.float64))
@@ -138,7 +140,8 @@ class Preproc:
 def preprocess(scene, cam, mode: Mode = Mode()) -> Preproc:
     L = lib()
     n = scene.n
-    out = Preproc(mean2d=np.zeros((n, 2)), conic=np.zeros((n, 3)), opacity=np.zeros(n),
+    out = Preproc(mean2d=np.zeros((n, 2)), conic=np.zeros((n, 3)), quad=np.zeros((n, 3)),
+                  opacity=np.zeros(n),
                   rgb=np.zeros((n, 3)), depth=np.zeros(n), cov2d=np.zeros((n, 3)),
                   extent=np.zeros(n), th=np.zeros(n), scale=np.zeros(n),
                   rect=np.zeros((n, 4), np.int32), tiles_touched=np.zeros(n, np.int64),
@@ -148,9 +151,10 @@ def preprocess(scene, cam, mode: Mode = Mode()) -> Preproc:
     ca = cam_array(cam)
     lut = mode.lut()
     L.orc_preprocess(n, *[_p(a) for a in arrs], scene.sh_degree, _p(ca), cam["width"],
-                     cam["height"], int(mode.adagscale), float(mode.K), _p(lut),
-                     float(mode.lut_depth_max), int(mode.force_unit_scale),
-                     _p(out.mean2d), _p(out.conic), _p(out.opacity), _p(out.rgb), _p(out.depth),
+                     cam["height"], int(mode.adagscale), float(np.float32(mode.K)), _p(lut),
+                     float(np.float32(mode.lut_depth_max)), int(mode.force_unit_scale),
+                     _p(out.mean2d), _p(out.conic), _p(out.quad), _p(out.opacity), _p(out.rgb),
+                     _p(out.depth),
                      _p(out.cov2d), _p(out.extent), _p(out.th), _p(out.scale), _p(out.rect),
                      _p(out.tiles_touched), _p(out.radius), _p(out.flags))
     return out
@@ -253,8 +257,8 @@ def blend_bruteforce(pre: Preproc, cam, mode_id=1, bg=(0.0, 0.0, 0.0)):
 
 
 def blend_backward(frame: Frame, cam, dL_dimage, bg=(0.0, 0.0, 0.0), rec=None):
-    """Per-Gaussian gradients of the blend: [N][9] = d(mean x, mean y, A, B, C,
-    opacity, r, g, b)."""
+    """Per-Gaussian gradients of the blend: [N][9] = d(mean x, mean y, A, beta,
+    gamma, opacity, r, g, b)."""
     n = frame.pre.rect.shape[0]
     if rec is None:
         rec = frame.pre.record()

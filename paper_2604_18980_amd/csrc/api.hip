@@ -1,0 +1,366 @@
+// C-ABI of libgsr: argument validation, workspace layout and launches.
+// Every entry point validates on the host, then enqueues on the caller's
+// stream; nothing here synchronises or allocates.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "gsr_internal.hpp"
+
+namespace {
+thread_local std::string g_last_error;
+
+gs_status fail(gs_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+gs_status hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return GS_OK;
+    return fail(GS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_f(float x) { return isfinite(x) != 0; }
+
+gs_status check_camera(const gs_camera *cam) {
+    if (!cam) return fail(GS_ERR_INVALID_ARGUMENT, "camera is NULL");
+    if (cam->width < 1 || cam->height < 1 || cam->width > GS_MAX_IMAGE_SIDE ||
+        cam->height > GS_MAX_IMAGE_SIDE)
+        return fail(GS_ERR_INVALID_ARGUMENT, "image size %dx%d outside 1..%d", cam->width,
+                    cam->height, GS_MAX_IMAGE_SIDE);
+    for (int i = 0; i < 12; ++i)
+        if (!finite_f(cam->viewmat[i])) return fail(GS_ERR_INVALID_ARGUMENT, "viewmat[%d] not finite", i);
+    if (!(cam->fx > 0.0f) || !(cam->fy > 0.0f) || !finite_f(cam->fx) || !finite_f(cam->fy))
+        return fail(GS_ERR_INVALID_ARGUMENT, "focal lengths must be finite and positive");
+    if (!finite_f(cam->cx) || !finite_f(cam->cy))
+        return fail(GS_ERR_INVALID_ARGUMENT, "principal point not finite");
+    return GS_OK;
+}
+
+int tiles_x(const gs_camera *c) { return (c->width + GS_TILE - 1) / GS_TILE; }
+int tiles_y(const gs_camera *c) { return (c->height + GS_TILE - 1) / GS_TILE; }
+
+int bits_for(int64_t count) {
+    int b = 0;
+    while (b < 63 && ((int64_t)1 << b) < count) ++b;
+    return b;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Real-SH normalisation constants (Condon-Shortley phase) for the polynomial
+// forms used by the device code:
+//   c0 = sqrt(1/4pi), c1 = sqrt(3/4pi), c2 = sqrt(15/4pi), c3 = sqrt(5/16pi),
+//   c4 = sqrt(15/16pi), c5 = sqrt(35/32pi), c6 = sqrt(105/4pi), c7 = sqrt(21/32pi),
+//   c8 = sqrt(7/16pi), c9 = sqrt(105/16pi).
+void sh_constants(double *c) {
+    const double pi = 3.14159265358979323846;
+    c[0] = sqrt(1.0 / (4.0 * pi));
+    c[1] = sqrt(3.0 / (4.0 * pi));
+    c[2] = sqrt(15.0 / (4.0 * pi));
+    c[3] = sqrt(5.0 / (16.0 * pi));
+    c[4] = sqrt(15.0 / (16.0 * pi));
+    c[5] = sqrt(35.0 / (32.0 * pi));
+    c[6] = sqrt(105.0 / (4.0 * pi));
+    c[7] = sqrt(21.0 / (32.0 * pi));
+    c[8] = sqrt(7.0 / (16.0 * pi));
+    c[9] = sqrt(105.0 / (16.0 * pi));
+    for (int i = 10; i < 16; ++i) c[i] = 0.0;
+}
+
+void camera_to_double(const gs_camera *cam, double R[9], double t[3], double campos[3]) {
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) R[3 * i + j] = cam->viewmat[4 * i + j];
+        t[i] = cam->viewmat[4 * i + 3];
+    }
+    for (int j = 0; j < 3; ++j) campos[j] = -(R[j] * t[0] + R[3 + j] * t[1] + R[6 + j] * t[2]);
+}
+
+gs_status check_scene(const gs_scene *sc) {
+    if (!sc) return fail(GS_ERR_INVALID_ARGUMENT, "scene is NULL");
+    if (sc->n < 0 || sc->n >= ((int64_t)1 << 31))
+        return fail(GS_ERR_INVALID_ARGUMENT, "n = %lld outside [0, 2^31)", (long long)sc->n);
+    if (sc->sh_degree < 0 || sc->sh_degree > GS_MAX_SH_DEGREE)
+        return fail(GS_ERR_INVALID_ARGUMENT, "sh_degree %d outside 0..%d", sc->sh_degree, GS_MAX_SH_DEGREE);
+    if (sc->n > 0 && (!sc->means || !sc->log_scales || !sc->quats || !sc->opacity_logits || !sc->sh))
+        return fail(GS_ERR_INVALID_ARGUMENT, "scene has a NULL parameter array");
+    return GS_OK;
+}
+}  // namespace
+
+namespace gsr {
+// Sort region (depends on the pair capacity only) first, then the emit region.
+bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws) {
+    if (n < 0 || cap < 0) return false;
+    size_t off = 0;
+    char *b = static_cast<char *>(base);
+    auto take = [&](size_t bytes) -> char * {
+        off = align256(off);
+        char *p = b ? b + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    ws->nb_psort = cap > 0 ? (cap + kSortChunk - 1) / kSortChunk : 1;
+    ws->nb_gauss = n > 0 ? (n + 255) / 256 : 1;
+    ws->nb_dsort = n > 0 ? (n + kSortChunk - 1) / kSortChunk : 1;
+    const int64_t parts_sort = (256 * ws->nb_psort + kScanChunk - 1) / kScanChunk + 1;
+    const int64_t parts_emit = (256 * ws->nb_dsort + kScanChunk - 1) / kScanChunk +
+                               (ws->nb_gauss + kScanChunk - 1) / kScanChunk + 1;
+    ws->max_parts = parts_sort > parts_emit ? parts_sort : parts_emit;
+    // sort region
+    ws->ptile_tmp = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
+    ws->pgid_tmp = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
+    ws->phist = (uint32_t *)take(sizeof(uint32_t) * 256 * (size_t)ws->nb_psort);
+    ws->scan_part = (uint64_t *)take(sizeof(uint64_t) * (size_t)ws->max_parts);
+    ws->counters = (int64_t *)take(sizeof(int64_t) * 4);
+    const size_t sort_bytes = align256(off);
+    // emit region
+    ws->vis_count = (uint32_t *)take(sizeof(uint32_t) * (size_t)ws->nb_gauss);
+    ws->vis_off = (uint32_t *)take(sizeof(uint32_t) * (size_t)ws->nb_gauss);
+    ws->pair_cnt = (uint64_t *)take(sizeof(uint64_t) * (size_t)ws->nb_gauss);
+    ws->pair_off = (uint64_t *)take(sizeof(uint64_t) * (size_t)ws->nb_gauss);
+    for (int i = 0; i < 3; ++i) {
+        ws->dkey[i] = (uint32_t *)take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+        ws->dval[i] = (uint32_t *)take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    }
+    ws->dhist = (uint32_t *)take(sizeof(uint32_t) * 256 * (size_t)ws->nb_dsort);
+    ws->bytes = n > 0 ? align256(off) : sort_bytes;
+    return true;
+}
+}  // namespace gsr
+
+using namespace gsr;
+
+extern "C" {
+
+const char *gs_status_string(gs_status s) {
+    switch (s) {
+        case GS_OK: return "ok";
+        case GS_ERR_INVALID_ARGUMENT: return "invalid argument";
+        case GS_ERR_CAPACITY: return "capacity exceeded";
+        case GS_ERR_HIP: return "HIP error";
+        case GS_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *gs_last_error(void) { return g_last_error.c_str(); }
+
+const char *gs_version(void) { return "gsr 0.1 gfx950"; }
+
+size_t gs_workspace_size(int64_t n, int64_t pair_capacity, int width, int height) {
+    (void)width;
+    (void)height;
+    Workspace ws;
+    if (!workspace_layout(n, pair_capacity, nullptr, &ws)) return 0;
+    return ws.bytes;
+}
+
+gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_mode *mode,
+                        float *splats, uint64_t *rects, uint32_t *tiles_touched, void *stream) {
+    gs_status st;
+    if ((st = check_scene(scene)) != GS_OK) return st;
+    if ((st = check_camera(cam)) != GS_OK) return st;
+    if (!mode) return fail(GS_ERR_INVALID_ARGUMENT, "mode is NULL");
+    if (mode->adagscale != 0 && mode->adagscale != 1)
+        return fail(GS_ERR_INVALID_ARGUMENT, "mode.adagscale must be 0 or 1");
+    if (mode->adagscale) {
+        if (!(mode->K >= 0.0f) || !finite_f(mode->K))
+            return fail(GS_ERR_INVALID_ARGUMENT, "mode.K must be finite and >= 0");
+        if (!(mode->lut_depth_max > 0.0f) || !finite_f(mode->lut_depth_max))
+            return fail(GS_ERR_INVALID_ARGUMENT, "mode.lut_depth_max must be finite and > 0");
+        for (int i = 0; i < GS_LUT_BINS; ++i)
+            if (!(mode->t_upper[i] >= 0.0f && mode->t_upper[i] <= 1.0f))
+                return fail(GS_ERR_INVALID_ARGUMENT, "mode.t_upper[%d] outside [0, 1]", i);
+    }
+    if (scene->n > 0 && (!splats || !rects || !tiles_touched))
+        return fail(GS_ERR_INVALID_ARGUMENT, "output array is NULL");
+    PreprocessArgs a;
+    memset(&a, 0, sizeof a);
+    a.means = scene->means;
+    a.log_scales = scene->log_scales;
+    a.quats = scene->quats;
+    a.opacity_logits = scene->opacity_logits;
+    a.sh = scene->sh;
+    a.n = (int)scene->n;
+    a.sh_degree = scene->sh_degree;
+    camera_to_double(cam, a.R, a.t, a.campos);
+    a.fx = cam->fx;
+    a.fy = cam->fy;
+    a.cx = cam->cx;
+    a.cy = cam->cy;
+    a.limx = 1.3 * ((0.5 * cam->width) / a.fx);
+    a.limy = 1.3 * ((0.5 * cam->height) / a.fy);
+    a.width = cam->width;
+    a.height = cam->height;
+    a.tiles_x = tiles_x(cam);
+    a.tiles_y = tiles_y(cam);
+    a.adagscale = mode->adagscale;
+    a.force_unit_scale = mode->force_unit_scale ? 1 : 0;
+    a.K = mode->K;
+    a.lut_depth_max = mode->lut_depth_max;
+    for (int i = 0; i < GS_LUT_BINS; ++i) a.lut[i] = mode->t_upper[i];
+    sh_constants(a.shc);
+    a.splats = splats;
+    a.rects = rects;
+    a.tiles_touched = tiles_touched;
+    return hip_check(launch_preprocess(a, (hipStream_t)stream), "gs_preprocess");
+}
+
+gs_status gs_emit_pairs(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
+                        int64_t n, const gs_camera *cam, uint32_t *pair_tiles, uint32_t *pair_gids,
+                        int64_t pair_capacity, int64_t *num_pairs, void *ws, size_t ws_bytes,
+                        void *stream) {
+    gs_status st;
+    if ((st = check_camera(cam)) != GS_OK) return st;
+    if (n < 0 || n >= ((int64_t)1 << 31))
+        return fail(GS_ERR_INVALID_ARGUMENT, "n = %lld outside [0, 2^31)", (long long)n);
+    if (pair_capacity < 0 || pair_capacity > (int64_t)0xffffffffLL)
+        return fail(GS_ERR_INVALID_ARGUMENT, "pair_capacity outside [0, 2^32)");
+    if (!num_pairs) return fail(GS_ERR_INVALID_ARGUMENT, "num_pairs is NULL");
+    if (n > 0 && (!splats || !rects || !tiles_touched))
+        return fail(GS_ERR_INVALID_ARGUMENT, "input array is NULL");
+    if (pair_capacity > 0 && (!pair_tiles || !pair_gids))
+        return fail(GS_ERR_INVALID_ARGUMENT, "pair arrays are NULL");
+    Workspace w;
+    workspace_layout(n, pair_capacity, ws, &w);
+    if (!ws || ws_bytes < w.bytes)
+        return fail(GS_ERR_CAPACITY, "workspace of %zu bytes, %zu needed", ws_bytes, w.bytes);
+    return hip_check(launch_emit(splats, rects, tiles_touched, (int)n, tiles_x(cam), pair_tiles,
+                                 pair_gids, pair_capacity, num_pairs, w, (hipStream_t)stream),
+                     "gs_emit_pairs");
+}
+
+gs_status gs_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids, const int64_t *num_pairs,
+                  int64_t pair_capacity, const gs_camera *cam, uint32_t *sorted_tiles,
+                  uint32_t *sorted_gids, uint32_t *ranges, void *ws, size_t ws_bytes,
+                  void *stream) {
+    gs_status st;
+    if ((st = check_camera(cam)) != GS_OK) return st;
+    if (pair_capacity < 0 || pair_capacity > (int64_t)0xffffffffLL)
+        return fail(GS_ERR_INVALID_ARGUMENT, "pair_capacity outside [0, 2^32)");
+    if (!num_pairs || !ranges) return fail(GS_ERR_INVALID_ARGUMENT, "num_pairs or ranges is NULL");
+    if (pair_capacity > 0 && (!pair_tiles || !pair_gids || !sorted_tiles || !sorted_gids))
+        return fail(GS_ERR_INVALID_ARGUMENT, "pair arrays are NULL");
+    if (pair_capacity > 0 && (sorted_tiles == pair_tiles || sorted_gids == pair_gids))
+        return fail(GS_ERR_INVALID_ARGUMENT, "sorted arrays must not alias the inputs");
+    Workspace w;
+    workspace_layout(0, pair_capacity, ws, &w);
+    if (!ws || ws_bytes < w.bytes)
+        return fail(GS_ERR_CAPACITY, "workspace of %zu bytes, %zu needed", ws_bytes, w.bytes);
+    const int ntiles = tiles_x(cam) * tiles_y(cam);
+    hipStream_t s = (hipStream_t)stream;
+    if (pair_capacity > 0) {
+        hipError_t e = radix_sort_u32(pair_tiles, pair_gids, sorted_tiles, sorted_gids, w.ptile_tmp,
+                                      w.pgid_tmp, num_pairs, pair_capacity, bits_for(ntiles), w.phist,
+                                      w.nb_psort, w.scan_part, s);
+        if ((st = hip_check(e, "gs_sort")) != GS_OK) return st;
+    }
+    return hip_check(launch_tile_ranges(sorted_tiles, num_pairs, pair_capacity, ranges, ntiles, s),
+                     "gs_sort ranges");
+}
+
+gs_status gs_rasterize(const float *splats, int64_t n, const uint32_t *sorted_gids,
+                       const uint32_t *ranges, const gs_camera *cam, const float *bg,
+                       const gs_raster_cfg *cfg, float *image, float *final_T,
+                       uint32_t *n_contrib, uint32_t *n_evaluated, void *stream) {
+    gs_status st;
+    if ((st = check_camera(cam)) != GS_OK) return st;
+    if (n < 0) return fail(GS_ERR_INVALID_ARGUMENT, "n < 0");
+    if (!ranges || !image || !final_T || !n_contrib || !bg)
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (n > 0 && (!splats || !sorted_gids)) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    gs_raster_cfg c = {256, 1, 256};
+    if (cfg && (cfg->threads_per_tile || cfg->pixels_per_thread || cfg->lds_batch)) {
+        c = *cfg;
+        if (c.threads_per_tile != 256 || c.pixels_per_thread != 1 || c.lds_batch != 256)
+            return fail(GS_ERR_UNSUPPORTED, "raster geometry %d/%d/%d not built", c.threads_per_tile,
+                        c.pixels_per_thread, c.lds_batch);
+    }
+    RasterArgs a;
+    a.splats = splats;
+    a.gids = sorted_gids;
+    a.ranges = ranges;
+    a.width = cam->width;
+    a.height = cam->height;
+    a.tiles_x = tiles_x(cam);
+    a.tiles_y = tiles_y(cam);
+    for (int i = 0; i < 3; ++i) a.bg[i] = bg[i];
+    a.image = image;
+    a.final_T = final_T;
+    a.n_contrib = n_contrib;
+    a.n_evaluated = n_evaluated;
+    return hip_check(launch_raster(a, c, (hipStream_t)stream), "gs_rasterize");
+}
+
+gs_status gs_rasterize_backward(const float *splats, int64_t n, const uint32_t *sorted_gids,
+                                const uint32_t *ranges, const gs_camera *cam, const float *bg,
+                                const float *final_T, const uint32_t *n_contrib,
+                                const float *dL_dimage, float *grad_splats, void *stream) {
+    gs_status st;
+    if ((st = check_camera(cam)) != GS_OK) return st;
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GS_ERR_INVALID_ARGUMENT, "n outside [0, 2^31)");
+    if (!ranges || !final_T || !n_contrib || !dL_dimage || !bg)
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (n > 0 && (!splats || !sorted_gids || !grad_splats))
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    RasterBwdArgs a;
+    a.splats = splats;
+    a.gids = sorted_gids;
+    a.ranges = ranges;
+    a.width = cam->width;
+    a.height = cam->height;
+    a.tiles_x = tiles_x(cam);
+    a.tiles_y = tiles_y(cam);
+    for (int i = 0; i < 3; ++i) a.bg[i] = bg[i];
+    a.final_T = final_T;
+    a.n_contrib = n_contrib;
+    a.dL_dimage = dL_dimage;
+    a.grad_splats = grad_splats;
+    return hip_check(launch_raster_backward(a, n, (hipStream_t)stream), "gs_rasterize_backward");
+}
+
+gs_status gs_preprocess_backward(const gs_scene *scene, const gs_camera *cam,
+                                 const uint32_t *tiles_touched, const float *grad_splats,
+                                 const gs_scene_grads *out, void *stream) {
+    gs_status st;
+    if ((st = check_scene(scene)) != GS_OK) return st;
+    if ((st = check_camera(cam)) != GS_OK) return st;
+    if (!out) return fail(GS_ERR_INVALID_ARGUMENT, "gradient struct is NULL");
+    if (scene->n > 0 && (!tiles_touched || !grad_splats || !out->d_means || !out->d_log_scales ||
+                         !out->d_quats || !out->d_opacity_logits || !out->d_sh))
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    PreprocessBwdArgs a;
+    memset(&a, 0, sizeof a);
+    a.means = scene->means;
+    a.log_scales = scene->log_scales;
+    a.quats = scene->quats;
+    a.opacity_logits = scene->opacity_logits;
+    a.sh = scene->sh;
+    a.n = (int)scene->n;
+    a.sh_degree = scene->sh_degree;
+    camera_to_double(cam, a.R, a.t, a.campos);
+    a.fx = cam->fx;
+    a.fy = cam->fy;
+    a.limx = 1.3 * ((0.5 * cam->width) / a.fx);
+    a.limy = 1.3 * ((0.5 * cam->height) / a.fy);
+    sh_constants(a.shc);
+    a.tiles_touched = tiles_touched;
+    a.grad_splats = grad_splats;
+    a.d_means = out->d_means;
+    a.d_log_scales = out->d_log_scales;
+    a.d_quats = out->d_quats;
+    a.d_opacity_logits = out->d_opacity_logits;
+    a.d_sh = out->d_sh;
+    return hip_check(launch_preprocess_backward(a, (hipStream_t)stream), "gs_preprocess_backward");
+}
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+// Internal declarations shared by the HIP translation units of libgsr.
+// Device helpers are written for 64-wide wavefronts (CDNA4).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gsr.h"
+
+namespace gsr {
+
+constexpr int kTile = GS_TILE;
+constexpr int kWave = 64;
+constexpr int kLutBins = GS_LUT_BINS;
+
+// ---------------------------------------------------------------- launch args
+struct PreprocessArgs {
+    const float *means, *log_scales, *quats, *opacity_logits, *sh;
+    int n, sh_degree;
+    double R[9], t[3], campos[3];
+    double fx, fy, cx, cy, limx, limy;
+    int width, height, tiles_x, tiles_y;
+    int adagscale, force_unit_scale;
+    double K, lut_depth_max;
+    float lut[kLutBins];
+    double shc[16];  // real-SH normalisation constants, see preprocess.hip
+    float *splats;
+    uint64_t *rects;
+    uint32_t *tiles_touched;
+};
+
+// Workspace layout, computed identically by the size query and every stage.
+struct Workspace {
+    // emit
+    uint32_t *vis_count;   // [nb_gauss]
+    uint32_t *vis_off;     // [nb_gauss]
+    uint64_t *pair_cnt;    // [nb_gauss] pairs per block of depth-sorted Gaussians
+    uint64_t *pair_off;    // [nb_gauss]
+    uint32_t *dkey[3];     // [n] depth keys: input, sorted output, pass scratch
+    uint32_t *dval[3];     // [n] Gaussian ids, same roles
+    uint32_t *dhist;       // [256][nb_dsort]
+    // sort
+    uint32_t *ptile_tmp;   // [cap]
+    uint32_t *pgid_tmp;    // [cap]
+    uint32_t *phist;       // [256][nb_psort]
+    // device-wide scan partials (large enough for any scan above)
+    uint64_t *scan_part;   // [max_parts]
+    int64_t *counters;     // [0] visible Gaussians, [1] scratch
+    int64_t nb_gauss, nb_dsort, nb_psort, max_parts;
+    size_t bytes;
+};
+bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws);
+
+// ------------------------------------------------------------ sort constants
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;                            // per thread
+constexpr int kSortChunk = kSortThreads * kSortItems;     // 4096 items per block
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanChunk = kScanThreads * kScanItems;     // 4096 elements per block
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_preprocess(const PreprocessArgs &a, hipStream_t s);
+
+// device-wide exclusive scan of m elements (m known on the host); if total is
+// non-null the grand total is stored there (as int64).
+hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t m, uint64_t *parts,
+                              int64_t *total, hipStream_t s);
+hipError_t scan_exclusive_u64(const uint64_t *in, uint64_t *out, int64_t m, uint64_t *parts,
+                              int64_t *total, hipStream_t s);
+
+// stable LSD radix sort of (key, val) pairs, count in device memory (clamped
+// to cap); bits = number of significant key bits.  Reads (kin, vin), leaves
+// them unchanged, and puts the result in (kout, vout); (ktmp, vtmp) is pass
+// scratch distinct from both.  kout may be null when only values are needed
+// and the sort has one pass.
+hipError_t radix_sort_u32(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+                          uint32_t *ktmp, uint32_t *vtmp, const int64_t *count, int64_t cap,
+                          int bits, uint32_t *hist, int64_t nblocks, uint64_t *parts,
+                          hipStream_t s);
+
+hipError_t launch_emit(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
+                       int n, int tiles_x, uint32_t *pair_tiles, uint32_t *pair_gids, int64_t cap,
+                       int64_t *num_pairs, const Workspace &ws, hipStream_t s);
+
+hipError_t launch_tile_ranges(const uint32_t *sorted_tiles, const int64_t *num_pairs, int64_t cap,
+                              uint32_t *ranges, int num_tiles, hipStream_t s);
+
+struct RasterArgs {
+    const float *splats;
+    const uint32_t *gids;
+    const uint32_t *ranges;
+    int width, height, tiles_x, tiles_y;
+    float bg[3];
+    float *image, *final_T;
+    uint32_t *n_contrib;
+    uint32_t *n_evaluated;  // nullable
+};
+hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStream_t s);
+
+struct RasterBwdArgs {
+    const float *splats;
+    const uint32_t *gids;
+    const uint32_t *ranges;
+    int width, height, tiles_x, tiles_y;
+    float bg[3];
+    const float *final_T;
+    const uint32_t *n_contrib;
+    const float *dL_dimage;
+    float *grad_splats;
+};
+hipError_t launch_raster_backward(const RasterBwdArgs &a, int64_t n, hipStream_t s);
+
+struct PreprocessBwdArgs {
+    const float *means, *log_scales, *quats, *opacity_logits, *sh;
+    int n, sh_degree;
+    double R[9], t[3], campos[3];
+    double fx, fy, limx, limy;
+    double shc[16];
+    const uint32_t *tiles_touched;
+    const float *grad_splats;
+    float *d_means, *d_log_scales, *d_quats, *d_opacity_logits, *d_sh;
+};
+hipError_t launch_preprocess_backward(const PreprocessBwdArgs &a, hipStream_t s);
+
+// ------------------------------------------------------------ device helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// Exclusive scan across one block (BLOCK threads, multiple of 64) of a
+// per-thread value; `wave_tot` is LDS scratch of BLOCK/64 entries.  Returns the
+// exclusive prefix and writes the block total to *total.  Contains barriers.
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *wave_tot, T *total) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    T x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        T y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) wave_tot[wid] = x;
+    __syncthreads();
+    T pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / kWave; ++w) {
+        T t = wave_tot[w];
+        if (w < wid) pre += t;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + x - v;
+}
+
+}  // namespace gsr

@@ -1,0 +1,217 @@
+// Stage 1: per-Gaussian preprocess (paper Sec. 2.1; AdaGScale Sec. 3.2-3.3).
+//
+// One thread per Gaussian, structure-of-arrays float32 loads (each wave reads
+// 64 consecutive floats per parameter plane).  Everything that decides a
+// discrete output -- the cull, the tile rectangle, the AdaGScale threshold and
+// scale -- is computed in double precision with a fixed operation order, so
+// the rectangles are reproducible on any IEEE machine; gfx950 runs FP64 FMA,
+// add and multiply at the FP32 rate, so this costs no throughput on an
+// HBM-bound kernel.  SH colour is only fetched for Gaussians that get tiles.
+//
+// The inverse covariance is stored as the sum of squares
+//     d^T Sigma2^-1 d = A (dx + beta dy)^2 + gamma dy^2,
+//     A = c / det, beta = -b / c, gamma = 1 / c      (Sigma2 = [[a, b], [b, c]]),
+// which is exact algebra (block LDL^T of Sigma2^-1) and has no cancellation:
+// the expanded A dx^2 + 2B dx dy + C dy^2 of a thin Gaussian evaluated far
+// from its centre loses most of its float32 digits.
+#include <math.h>
+
+#include "gsr_internal.hpp"
+
+namespace gsr {
+
+namespace {
+constexpr double kTau = 1.0 / 255.0;            // alpha threshold
+constexpr double kTwoPi = 6.283185307179586;    // 2 pi (eq. 9-10)
+constexpr double kNearZ = 0.2;
+constexpr double kDilation = 0.3;
+constexpr double kLambdaFloor = 0.1;
+constexpr double kMaxRadius = 1073741824.0;     // 2^30 px
+
+__device__ __forceinline__ void store_splat(float *dst, float4 a, float4 b, float4 c) {
+    float4 *p = reinterpret_cast<float4 *>(dst);
+    p[0] = a;
+    p[1] = b;
+    p[2] = c;
+}
+
+// Real spherical harmonics (Condon-Shortley phase, coefficient k = l^2+l+m)
+// at the unit direction (x, y, z), as polynomials; c[] holds the
+// normalisation constants computed on the host (see sh_constants()).
+__device__ __forceinline__ void sh_eval(int degree, double x, double y, double z, const double *c,
+                                        double *Y) {
+    Y[0] = c[0];
+    if (degree < 1) return;
+    Y[1] = -c[1] * y;
+    Y[2] = c[1] * z;
+    Y[3] = -c[1] * x;
+    if (degree < 2) return;
+    const double xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = c[2] * (x * y);
+    Y[5] = -c[2] * (y * z);
+    Y[6] = c[3] * (3.0 * zz - 1.0);
+    Y[7] = -c[2] * (x * z);
+    Y[8] = c[4] * (xx - yy);
+    if (degree < 3) return;
+    Y[9] = -c[5] * (y * (3.0 * xx - yy));
+    Y[10] = c[6] * (x * y * z);
+    Y[11] = -c[7] * (y * (5.0 * zz - 1.0));
+    Y[12] = c[8] * (z * (5.0 * zz - 3.0));
+    Y[13] = -c[7] * (x * (5.0 * zz - 1.0));
+    Y[14] = c[9] * (z * (xx - yy));
+    Y[15] = -c[5] * (x * (xx - 3.0 * yy));
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.n) return;
+    const int n = a.n;
+    uint32_t tiles = 0;
+    uint64_t rect = 0;
+
+    // view transform: p = R mu + t
+    const double mx = a.means[g], my = a.means[n + g], mz = a.means[2 * n + g];
+    const double px = a.R[0] * mx + a.R[1] * my + a.R[2] * mz + a.t[0];
+    const double py = a.R[3] * mx + a.R[4] * my + a.R[5] * mz + a.t[1];
+    const double pz = a.R[6] * mx + a.R[7] * my + a.R[8] * mz + a.t[2];
+
+    if (pz > kNearZ) {
+        // scales and normalised rotation
+        const double sx = exp((double)a.log_scales[g]);
+        const double sy = exp((double)a.log_scales[n + g]);
+        const double sz = exp((double)a.log_scales[2 * n + g]);
+        double qw = a.quats[g], qx = a.quats[n + g], qy = a.quats[2 * n + g], qz = a.quats[3 * n + g];
+        const double qn = qw * qw + qx * qx + qy * qy + qz * qz;
+        if (qn > 0.0) {
+            const double r = sqrt(qn);
+            qw = qw / r; qx = qx / r; qy = qy / r; qz = qz / r;
+        } else {
+            qw = 1.0; qx = 0.0; qy = 0.0; qz = 0.0;
+        }
+        const double r00 = 1.0 - 2.0 * (qy * qy + qz * qz), r01 = 2.0 * (qx * qy - qw * qz),
+                     r02 = 2.0 * (qx * qz + qw * qy);
+        const double r10 = 2.0 * (qx * qy + qw * qz), r11 = 1.0 - 2.0 * (qx * qx + qz * qz),
+                     r12 = 2.0 * (qy * qz - qw * qx);
+        const double r20 = 2.0 * (qx * qz - qw * qy), r21 = 2.0 * (qy * qz + qw * qx),
+                     r22 = 1.0 - 2.0 * (qx * qx + qy * qy);
+        // M = R diag(s); Sigma3 = M M^T
+        const double m00 = r00 * sx, m01 = r01 * sy, m02 = r02 * sz;
+        const double m10 = r10 * sx, m11 = r11 * sy, m12 = r12 * sz;
+        const double m20 = r20 * sx, m21 = r21 * sy, m22 = r22 * sz;
+        const double s00 = m00 * m00 + m01 * m01 + m02 * m02;
+        const double s01 = m00 * m10 + m01 * m11 + m02 * m12;
+        const double s02 = m00 * m20 + m01 * m21 + m02 * m22;
+        const double s11 = m10 * m10 + m11 * m11 + m12 * m12;
+        const double s12 = m10 * m20 + m11 * m21 + m12 * m22;
+        const double s22 = m20 * m20 + m21 * m21 + m22 * m22;
+
+        // EWA: Jacobian of the perspective map at the clamped point, T = J W
+        double txz = px / pz, tyz = py / pz;
+        txz = txz < -a.limx ? -a.limx : (txz > a.limx ? a.limx : txz);
+        tyz = tyz < -a.limy ? -a.limy : (tyz > a.limy ? a.limy : tyz);
+        const double xc = txz * pz, yc = tyz * pz;
+        const double j00 = a.fx / pz, j02 = -(a.fx * xc) / (pz * pz);
+        const double j11 = a.fy / pz, j12 = -(a.fy * yc) / (pz * pz);
+        const double t00 = j00 * a.R[0] + j02 * a.R[6];
+        const double t01 = j00 * a.R[1] + j02 * a.R[7];
+        const double t02 = j00 * a.R[2] + j02 * a.R[8];
+        const double t10 = j11 * a.R[3] + j12 * a.R[6];
+        const double t11 = j11 * a.R[4] + j12 * a.R[7];
+        const double t12 = j11 * a.R[5] + j12 * a.R[8];
+        // U = T Sigma3, Sigma2 = U T^T
+        const double u00 = t00 * s00 + t01 * s01 + t02 * s02;
+        const double u01 = t00 * s01 + t01 * s11 + t02 * s12;
+        const double u02 = t00 * s02 + t01 * s12 + t02 * s22;
+        const double u10 = t10 * s00 + t11 * s01 + t12 * s02;
+        const double u11 = t10 * s01 + t11 * s11 + t12 * s12;
+        const double u12 = t10 * s02 + t11 * s12 + t12 * s22;
+        const double ca = (u00 * t00 + u01 * t01 + u02 * t02) + kDilation;
+        const double cb = u00 * t10 + u01 * t11 + u02 * t12;
+        const double cc = (u10 * t10 + u11 * t11 + u12 * t12) + kDilation;
+
+        const double det = ca * cc - cb * cb;
+        const double u = a.fx * (px / pz) + a.cx;
+        const double v = a.fy * (py / pz) + a.cy;
+        const bool finite = isfinite(u) && isfinite(v) && isfinite(ca) && isfinite(cb) && isfinite(cc);
+        if (finite && det > 0.0) {
+            const double sigma = 1.0 / (1.0 + exp(-(double)a.opacity_logits[g]));
+            // plain extent: 3 sqrt(lambda_max), discriminant floored
+            const double mid = 0.5 * (ca + cc);
+            double disc = mid * mid - det;
+            if (disc < kLambdaFloor) disc = kLambdaFloor;
+            double ext = 3.0 * sqrt(mid + sqrt(disc));
+            double th = kTau, sc = 1.0;
+            bool keep = true;
+            if (a.adagscale) {
+                // eq. (10): Th = K / (T_up(depth) 2 pi sqrt(det)) + tau
+                const double f = (pz * kLutBins) / a.lut_depth_max;
+                const int bin = f >= (double)(kLutBins - 1) ? kLutBins - 1 : (int)floor(f);
+                const double tu = (double)a.lut[bin];
+                if (!(tu > 0.0)) {
+                    keep = false;
+                } else {
+                    const double denom = (tu * kTwoPi) * sqrt(det);
+                    th = a.K / denom + kTau;
+                    if (th >= sigma) {
+                        keep = false;  // Sec. 3.3: negligible for this view
+                    } else {
+                        sc = a.force_unit_scale ? 1.0 : sqrt(log(sigma / th) / log(sigma / kTau));
+                        ext = ext * sc;
+                    }
+                }
+            }
+            double rd = ceil(ext);
+            if (rd > kMaxRadius) rd = kMaxRadius;
+            const int r = keep ? (int)rd : 0;
+            if (r > 0) {
+                double fx0 = floor((u - r) / kTile), fx1 = floor(((u + r) + (kTile - 1)) / kTile);
+                double fy0 = floor((v - r) / kTile), fy1 = floor(((v + r) + (kTile - 1)) / kTile);
+                const double TX = a.tiles_x, TY = a.tiles_y;
+                fx0 = fx0 < 0.0 ? 0.0 : (fx0 > TX ? TX : fx0);
+                fx1 = fx1 < 0.0 ? 0.0 : (fx1 > TX ? TX : fx1);
+                fy0 = fy0 < 0.0 ? 0.0 : (fy0 > TY ? TY : fy0);
+                fy1 = fy1 < 0.0 ? 0.0 : (fy1 > TY ? TY : fy1);
+                const uint32_t x0 = (uint32_t)fx0, x1 = (uint32_t)fx1, y0 = (uint32_t)fy0,
+                               y1 = (uint32_t)fy1;
+                tiles = (x1 - x0) * (y1 - y0);
+                if (tiles > 0) {
+                    rect = (uint64_t)x0 | ((uint64_t)y0 << 16) | ((uint64_t)x1 << 32) |
+                           ((uint64_t)y1 << 48);
+                    // colour: SH along the unit view direction, +0.5, clamped at 0
+                    double dx = mx - a.campos[0], dy = my - a.campos[1], dz = mz - a.campos[2];
+                    const double len = sqrt(dx * dx + dy * dy + dz * dz);
+                    dx = dx / len; dy = dy / len; dz = dz / len;
+                    double Y[16];
+                    sh_eval(a.sh_degree, dx, dy, dz, a.shc, Y);
+                    const int nsh = (a.sh_degree + 1) * (a.sh_degree + 1);
+                    double rgb[3];
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) {
+                        double acc = 0.0;
+                        for (int k = 0; k < nsh; ++k)
+                            acc += (double)a.sh[((size_t)k * 3 + ch) * n + g] * Y[k];
+                        acc += 0.5;
+                        rgb[ch] = acc < 0.0 ? 0.0 : acc;
+                    }
+                    store_splat(a.splats + (size_t)g * 12,
+                                make_float4((float)u, (float)v, (float)(cc / det), (float)(-cb / cc)),
+                                make_float4((float)(1.0 / cc), (float)sigma, (float)pz, (float)th),
+                                make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], (float)sc));
+                }
+            }
+        }
+    }
+    a.rects[g] = rect;
+    a.tiles_touched[g] = tiles;
+}
+
+hipError_t launch_preprocess(const PreprocessArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    const int threads = 256;
+    const int blocks = (a.n + threads - 1) / threads;
+    k_preprocess<<<blocks, threads, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace gsr

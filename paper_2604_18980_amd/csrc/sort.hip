@@ -1,0 +1,230 @@
+// Device-wide scans and the stable LSD radix sort used by stages 2 and 3.
+//
+// The radix sort is a reduce-then-scan LSD sort with 8-bit digits:
+//   k_radix_hist     per-block digit histogram in LDS (one 256-bin histogram per
+//                    wave, merged), written digit-major so that
+//   scan             one flat exclusive scan turns it into per-(digit, block)
+//                    output offsets, and
+//   k_radix_scatter  re-reads the block's keys and ranks them stably: each wave
+//                    walks its quarter of the chunk 64 items at a time, finds
+//                    the lanes holding the same digit with 8 ballots, and keeps
+//                    a running per-digit count in LDS; wave prefixes then order
+//                    the four waves.
+// Counts live in device memory (read by every kernel and clamped to the
+// capacity the grid was sized for), so no stage needs a host round trip.
+#include "gsr_internal.hpp"
+
+namespace gsr {
+
+// ------------------------------------------------------------------- scans
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T *in, int64_t m, uint64_t *parts) {
+    __shared__ T wt[kScanThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    T acc = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = base + (int64_t)i * kScanThreads + threadIdx.x;
+        if (idx < m) acc += in[idx];
+    }
+    T tot;
+    block_exclusive_scan<kScanThreads, T>(acc, wt, &tot);
+    if (threadIdx.x == 0) parts[blockIdx.x] = (uint64_t)tot;
+}
+
+// single block: exclusive scan of the partials in place; total -> *total
+__global__ __launch_bounds__(1024) void k_scan_top(uint64_t *parts, int64_t nparts, int64_t *total) {
+    __shared__ uint64_t wt[1024 / kWave];
+    uint64_t carry = 0;
+    for (int64_t b = 0; b < nparts; b += 1024) {
+        const int64_t i = b + threadIdx.x;
+        const uint64_t v = i < nparts ? parts[i] : 0;
+        uint64_t tot;
+        const uint64_t ex = block_exclusive_scan<1024, uint64_t>(v, wt, &tot);
+        if (i < nparts) parts[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = (int64_t)carry;
+}
+
+// Each block rescans its chunk: thread t owns kScanItems consecutive elements.
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const T *in, T *out, int64_t m,
+                                                            const uint64_t *parts) {
+    __shared__ T wt[kScanThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    T v[kScanItems];
+    T acc = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = base + i;
+        v[i] = idx < m ? in[idx] : 0;
+        acc += v[i];
+    }
+    T tot;
+    T run = block_exclusive_scan<kScanThreads, T>(acc, wt, &tot) + (T)parts[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = base + i;
+        if (idx < m) out[idx] = run;
+        run += v[i];
+    }
+}
+
+template <typename T>
+static hipError_t scan_exclusive(const T *in, T *out, int64_t m, uint64_t *parts, int64_t *total,
+                                 hipStream_t s) {
+    const int64_t nparts = (m + kScanChunk - 1) / kScanChunk;
+    if (nparts > 0) k_scan_reduce<T><<<(unsigned)nparts, kScanThreads, 0, s>>>(in, m, parts);
+    k_scan_top<<<1, 1024, 0, s>>>(parts, nparts, total);
+    if (nparts > 0) k_scan_down<T><<<(unsigned)nparts, kScanThreads, 0, s>>>(in, out, m, parts);
+    return hipGetLastError();
+}
+
+hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t m, uint64_t *parts,
+                              int64_t *total, hipStream_t s) {
+    return scan_exclusive<uint32_t>(in, out, m, parts, total, s);
+}
+hipError_t scan_exclusive_u64(const uint64_t *in, uint64_t *out, int64_t m, uint64_t *parts,
+                              int64_t *total, hipStream_t s) {
+    return scan_exclusive<uint64_t>(in, out, m, parts, total, s);
+}
+
+// ------------------------------------------------------------------ radix sort
+__device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t cap) {
+    const int64_t c = *count;
+    return c < cap ? (c < 0 ? 0 : c) : cap;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *keys, const int64_t *count,
+                                                             int64_t cap, int shift, uint32_t *hist,
+                                                             int64_t nblocks) {
+    __shared__ uint32_t h[kSortThreads / kWave][256];
+    const int wid = threadIdx.x / kWave;
+    for (int i = threadIdx.x; i < (kSortThreads / kWave) * 256; i += kSortThreads) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t n = clamp_count(count, cap);
+    const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+#pragma unroll 4
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&h[wid][(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    const int d = threadIdx.x;  // kSortThreads == 256 digits
+    uint32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < kSortThreads / kWave; ++w) tot += h[w][d];
+    hist[(int64_t)d * nblocks + blockIdx.x] = tot;
+}
+
+// Items of the chunk are assigned wave-striped: wave w owns positions
+// [w*1024, (w+1)*1024) of the chunk, and in step i lane l holds position
+// w*1024 + i*64 + l; so lane order, then step order, then wave order is the
+// input order, which makes the ranking stable.
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const int64_t *count,
+    int64_t cap, int shift, const uint32_t *offs, int64_t nblocks) {
+    constexpr int kWaves = kSortThreads / kWave;
+    constexpr int kPerWave = kSortChunk / kWaves;
+    __shared__ uint32_t wcnt[kWaves][256];
+    __shared__ uint32_t gbase[256];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    for (int i = threadIdx.x; i < kWaves * 256; i += kSortThreads) (&wcnt[0][0])[i] = 0;
+    const int64_t n = clamp_count(count, cap);
+    const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+    if (base >= n) return;  // whole block idle (uniform across the block)
+    gbase[threadIdx.x] = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    __syncthreads();
+
+    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t idx = base + (int64_t)wid * kPerWave + (int64_t)i * kWave + lane;
+        const bool valid = idx < n;
+        key[i] = valid ? kin[idx] : 0u;
+        val[i] = valid ? vin[idx] : 0u;
+        const uint32_t d = (key[i] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t before = wcnt[wid][d];
+        rank[i] = before + (uint32_t)__popcll(peers & lt);
+        // the highest lane of each digit group advances the running count
+        if (valid && (peers >> lane) == 1ull) wcnt[wid][d] = before + (uint32_t)__popcll(peers);
+        if (!valid) rank[i] = 0xffffffffu;
+    }
+    __syncthreads();
+    {   // exclusive prefix over waves per digit; thread t owns digit t
+        const int d = threadIdx.x;
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t c = wcnt[w][d];
+            wcnt[w][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        if (rank[i] == 0xffffffffu) continue;
+        const uint32_t d = (key[i] >> shift) & 255u;
+        const int64_t dst = (int64_t)gbase[d] + wcnt[wid][d] + rank[i];
+        if (kout) kout[dst] = key[i];
+        vout[dst] = val[i];
+    }
+}
+
+hipError_t radix_sort_u32(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+                          uint32_t *ktmp, uint32_t *vtmp, const int64_t *count, int64_t cap,
+                          int bits, uint32_t *hist, int64_t nblocks, uint64_t *parts,
+                          hipStream_t s) {
+    const int passes = bits <= 0 ? 1 : (bits + 7) / 8;
+    // choose buffers so the last pass lands in (kout, vout)
+    const uint32_t *srck = kin, *srcv = vin;
+    for (int p = 0; p < passes; ++p) {
+        const bool to_out = ((passes - 1 - p) % 2) == 0;
+        uint32_t *dk = to_out ? kout : ktmp, *dv = to_out ? vout : vtmp;
+        k_radix_hist<<<(unsigned)nblocks, kSortThreads, 0, s>>>(srck, count, cap, 8 * p, hist, nblocks);
+        hipError_t e = scan_exclusive_u32(hist, hist, 256 * nblocks, parts, nullptr, s);
+        if (e != hipSuccess) return e;
+        k_radix_scatter<<<(unsigned)nblocks, kSortThreads, 0, s>>>(srck, srcv, dk, dv, count, cap,
+                                                                    8 * p, hist, nblocks);
+        srck = dk;
+        srcv = dv;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- tile ranges
+__global__ void k_fill_u32(uint32_t *p, int64_t m, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *tiles, const int64_t *count,
+                                                     int64_t cap, uint32_t *ranges) {
+    const int64_t n = clamp_count(count, cap);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t t = tiles[i];
+    if (i == 0 || tiles[i - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)i;
+    if (i == n - 1 || tiles[i + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
+}
+
+hipError_t launch_tile_ranges(const uint32_t *sorted_tiles, const int64_t *num_pairs, int64_t cap,
+                              uint32_t *ranges, int num_tiles, hipStream_t s) {
+    const int64_t m = 2 * (int64_t)num_tiles;
+    k_fill_u32<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(ranges, m, 0u);
+    if (cap > 0)
+        k_tile_ranges<<<(unsigned)((cap + 255) / 256), 256, 0, s>>>(sorted_tiles, num_pairs, cap, ranges);
+    return hipGetLastError();
+}
+
+}  // namespace gsr

@@ -25,6 +25,8 @@ build targets (tiny 2K / mid 500K / city 6M at 4608x3456 / differentiable 1M /
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
@@ -33,6 +35,77 @@ __all__ = [
     "Scene", "make_camera", "look_camera", "tiny_scene", "mid_scene", "city_scene",
     "diff_workload", "batched_workload", "workload", "target_image", "WORKLOADS",
 ]
+
+
+_CHUNK = 1 << 20
+_POOL = ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1))
+
+
+class Rand:
+    """Seeded random arrays, filled in parallel.
+
+    Every call takes the next child of a SeedSequence and splits the array into
+    fixed 2^20-element chunks, each with its own PCG64 stream; the result
+    depends only on the seed and the order of calls, not on the thread count."""
+
+    def __init__(self, seed):
+        self.ss = np.random.SeedSequence(seed)
+
+    def _fill(self, shape, fn, out=None):
+        if out is None:
+            out = np.empty(shape, dtype=np.float32)
+        flat = out.reshape(-1)
+        nch = max(1, -(-flat.size // _CHUNK))
+        seeds = self.ss.spawn(1)[0].spawn(nch)
+
+        def work(i):
+            g = np.random.Generator(np.random.PCG64(seeds[i]))
+            seg = flat[i * _CHUNK:(i + 1) * _CHUNK]
+            if seg.size:
+                fn(g, seg)
+        list(_POOL.map(work, range(nch)))
+        return out
+
+    def normal(self, shape, mean=0.0, std=1.0, out=None):
+        """N(mean, std^2); ``out`` (contiguous float32) is filled in place."""
+        m, sd = np.float32(mean), np.float32(std)
+
+        def fn(g, seg):
+            g.standard_normal(out=seg, dtype=np.float32)
+            if sd != 1:
+                seg *= sd
+            if m != 0:
+                seg += m
+        return self._fill(shape, fn, out)
+
+    def uniform(self, shape, lo=0.0, hi=1.0, out=None):
+        w, l0 = np.float32(hi - lo), np.float32(lo)
+
+        def fn(g, seg):
+            g.random(out=seg, dtype=np.float32)
+            seg *= w
+            seg += l0
+        return self._fill(shape, fn, out)
+
+    def uniform64(self, size, lo=0.0, hi=1.0):
+        """Small double-precision draws (building layouts, cluster centres)."""
+        g = np.random.Generator(np.random.PCG64(self.ss.spawn(1)[0]))
+        return g.uniform(lo, hi, size)
+
+    def integers(self, size, hi):
+        return np.minimum((self.uniform(size) * hi).astype(np.int64), hi - 1)
+
+    def choice(self, size, p):
+        cdf = np.cumsum(p)
+        cdf = (cdf / cdf[-1]).astype(np.float32)
+        return np.minimum(np.searchsorted(cdf, self.uniform(size), side="right"), len(p) - 1)
+
+    def student_t(self, shape, dof):
+        z = self.normal(shape)
+        chi2 = np.zeros(shape, np.float32)
+        for _ in range(dof):
+            chi2 += self.normal(shape) ** 2
+        return z / np.sqrt(chi2 / np.float32(dof))
 
 
 @dataclass
@@ -88,7 +161,7 @@ def look_camera(eye, forward, up, width, height, fovx_deg=60.0):
 
 
 def _quats(rng, n):
-    q = rng.standard_normal((4, n), dtype=np.float32)
+    q = rng.normal((4, n))
     q /= np.linalg.norm(q, axis=0, keepdims=True)
     return q
 
@@ -96,9 +169,9 @@ def _quats(rng, n):
 def _sh(rng, n, degree, dc_std, rest_std):
     k = (degree + 1) ** 2
     sh = np.empty((k, 3, n), dtype=np.float32)
-    sh[0] = rng.standard_normal((3, n), dtype=np.float32) * np.float32(dc_std)
+    rng.normal(None, std=dc_std, out=sh[:1])
     if k > 1:
-        sh[1:] = rng.standard_normal((k - 1, 3, n), dtype=np.float32) * np.float32(rest_std)
+        rng.normal(None, std=rest_std, out=sh[1:])
     return sh
 
 
@@ -108,14 +181,14 @@ def tiny_scene(n=2000, seed=0, sh_degree=0):
     means: x, y ~ U[-2, 2], z ~ U[3, 7]; log-scales ~ N(-3.5, 0.5) per axis;
     quaternions normalised N(0, I); opacity logits ~ N(0, 1.5); SH DC ~ N(0, 0.5)
     (higher bands, if asked for, ~ N(0, 0.1)). Camera: 128x128, fov 60 deg."""
-    rng = np.random.Generator(np.random.PCG64(seed))
+    rng = Rand(seed)
     means = np.empty((3, n), dtype=np.float32)
-    means[0] = rng.uniform(-2, 2, n)
-    means[1] = rng.uniform(-2, 2, n)
-    means[2] = rng.uniform(3, 7, n)
-    ls = (rng.standard_normal((3, n), dtype=np.float32) * 0.5 - 3.5).astype(np.float32)
+    means[0] = rng.uniform(n, -2, 2)
+    means[1] = rng.uniform(n, -2, 2)
+    means[2] = rng.uniform(n, 3, 7)
+    ls = rng.normal((3, n), -3.5, 0.5)
     q = _quats(rng, n)
-    op = (rng.standard_normal(n, dtype=np.float32) * 1.5).astype(np.float32)
+    op = rng.normal(n, 0.0, 1.5)
     sh = _sh(rng, n, sh_degree, 0.5, 0.1)
     cam = make_camera(np.eye(3), np.zeros(3), 128, 128)
     return Scene(means, ls, q, op, sh, sh_degree), cam
@@ -130,22 +203,22 @@ def mid_scene(n=500_000, seed=0, sh_degree=3, width=1920, height=1080):
     Gaussians on a far shell of radius 100 with log-scales ~ N(1, 0.5).
     Opacity logits ~ N(0, 2); SH degree 3 with DC ~ N(0, 0.5) and higher bands
     ~ N(0, 0.1). Camera at (0, 0, -35) looking at the origin, fovx 60 deg."""
-    rng = np.random.Generator(np.random.PCG64(seed))
+    rng = Rand(seed)
     n_shell = n // 20
     n_cl = n - n_shell
-    centres = np.stack([rng.uniform(-20, 20, 200), rng.uniform(-5, 5, 200),
-                        rng.uniform(-20, 20, 200)]).astype(np.float32)
-    which = rng.integers(0, 200, n_cl)
+    centres = np.stack([rng.uniform64(200, -20, 20), rng.uniform64(200, -5, 5),
+                        rng.uniform64(200, -20, 20)]).astype(np.float32)
+    which = rng.integers(n_cl, 200)
     means = np.empty((3, n), dtype=np.float32)
-    means[:, :n_cl] = centres[:, which] + rng.standard_normal((3, n_cl), dtype=np.float32) * 0.5
-    d = rng.standard_normal((3, n_shell))
+    means[:, :n_cl] = centres[:, which] + rng.normal((3, n_cl), std=0.5)
+    d = rng.normal((3, n_shell)).astype(np.float64)
     d /= np.linalg.norm(d, axis=0, keepdims=True)
     means[:, n_cl:] = (d * 100.0).astype(np.float32)
     ls = np.empty((3, n), dtype=np.float32)
-    ls[:, :n_cl] = np.clip(-4.0 + rng.standard_t(3, (3, n_cl)), -9.0, 0.0)
-    ls[:, n_cl:] = rng.standard_normal((3, n_shell)) * 0.5 + 1.0
+    ls[:, :n_cl] = np.clip(np.float32(-4.0) + rng.student_t((3, n_cl), 3), -9.0, 0.0)
+    ls[:, n_cl:] = rng.normal((3, n_shell), 1.0, 0.5)
     q = _quats(rng, n)
-    op = (rng.standard_normal(n, dtype=np.float32) * 2.0).astype(np.float32)
+    op = rng.normal(n, 0.0, 2.0)
     sh = _sh(rng, n, sh_degree, 0.5, 0.1)
     cam = look_camera((0, 0, -35), (0, 0, 1), (0, -1, 0), width, height)
     return Scene(means, ls, q, op, sh, sh_degree), cam
@@ -162,33 +235,34 @@ def _city_points(rng, n, n_buildings):
     n_ground = int(round(0.3 * n))
     n_b = n - n_ground
     means = np.empty((3, n), dtype=np.float32)
-    means[0, :n_ground] = rng.uniform(-500, 500, n_ground)
-    means[1, :n_ground] = rng.uniform(-500, 500, n_ground)
-    means[2, :n_ground] = rng.standard_normal(n_ground) * 0.2
-    bx = rng.uniform(-500, 500, n_buildings)
-    by = rng.uniform(-500, 500, n_buildings)
-    sx = rng.uniform(10, 40, n_buildings)
-    sy = rng.uniform(10, 40, n_buildings)
+    means[0, :n_ground] = rng.uniform(n_ground, -500, 500)
+    means[1, :n_ground] = rng.uniform(n_ground, -500, 500)
+    means[2, :n_ground] = rng.normal(n_ground, std=0.2)
+    bx = rng.uniform64(n_buildings, -500, 500)
+    by = rng.uniform64(n_buildings, -500, 500)
+    sx = rng.uniform64(n_buildings, 10, 40)
+    sy = rng.uniform64(n_buildings, 10, 40)
     mu = math.log(20.0) - 0.5 * 0.6 ** 2
-    h = np.exp(rng.standard_normal(n_buildings) * 0.6 + mu)
+    h = np.exp(np.random.Generator(np.random.PCG64(rng.ss.spawn(1)[0])).standard_normal(n_buildings) * 0.6 + mu)
     # face areas: 0,1 walls normal to x (sy*h); 2,3 walls normal to y (sx*h); 4 roof (sx*sy)
     areas = np.stack([sy * h, sy * h, sx * h, sx * h, sx * sy], axis=1)
     tot = areas.sum(axis=1)
-    b = rng.choice(n_buildings, size=n_b, p=tot / tot.sum())
-    cum = np.cumsum(areas[b] / tot[b, None], axis=1)
-    face = (rng.uniform(0, 1, n_b)[:, None] > cum).sum(axis=1)
-    face = np.minimum(face, 4)
-    u = rng.uniform(-0.5, 0.5, n_b)
-    v = rng.uniform(0.0, 1.0, n_b)
-    x = np.empty(n_b)
-    y = np.empty(n_b)
-    z = np.empty(n_b)
-    hx, hy, hb = sx[b] / 2, sy[b] / 2, h[b]
-    m = face == 0; x[m] = -hx[m]; y[m] = u[m] * sy[b][m]; z[m] = v[m] * hb[m]
-    m = face == 1; x[m] = hx[m];  y[m] = u[m] * sy[b][m]; z[m] = v[m] * hb[m]
-    m = face == 2; x[m] = u[m] * sx[b][m]; y[m] = -hy[m]; z[m] = v[m] * hb[m]
-    m = face == 3; x[m] = u[m] * sx[b][m]; y[m] = hy[m];  z[m] = v[m] * hb[m]
-    m = face == 4; x[m] = u[m] * sx[b][m]; y[m] = (v[m] - 0.5) * sy[b][m]; z[m] = hb[m]
+    b = rng.choice(n_b, tot / tot.sum())
+    # face within the building, in proportion to its area
+    cum = (np.cumsum(areas, axis=1) / tot[:, None]).astype(np.float32)
+    r = rng.uniform(n_b)
+    face = np.zeros(n_b, np.int8)
+    for f in range(4):
+        face += (r > cum[b, f]).astype(np.int8)
+    u = rng.uniform(n_b, -0.5, 0.5).astype(np.float64)
+    v = rng.uniform(n_b, 0.0, 1.0).astype(np.float64)
+    sxb, syb, hb = sx[b], sy[b], h[b]
+    wall_x = face <= 1
+    wall_y = (face == 2) | (face == 3)
+    sign = np.where((face == 0) | (face == 2), -0.5, 0.5)
+    x = np.where(wall_x, sign * sxb, u * sxb)
+    y = np.where(wall_y, sign * syb, np.where(wall_x, u * syb, (v - 0.5) * syb))
+    z = np.where(face == 4, hb, v * hb)
     means[0, n_ground:] = bx[b] + x
     means[1, n_ground:] = by[b] + y
     means[2, n_ground:] = z
@@ -206,11 +280,11 @@ def city_scene(n=6_000_000, seed=0, sh_degree=3, n_buildings=3000, width=4608, h
     opacity logits ~ N(0, 2), SH degree 3 (DC ~ N(0, 0.5), bands ~ N(0, 0.1)).
     Oblique aerial camera at (0, -600, 150) looking along +y, pitched 30 deg down,
     fovx 60 deg, 4608x3456 (the Mill-19 resolution of Table I)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
+    rng = Rand(seed)
     means = _city_points(rng, n, n_buildings)
-    ls = (rng.standard_normal((3, n), dtype=np.float32) * 1.2 - 1.0).astype(np.float32)
+    ls = rng.normal((3, n), -1.0, 1.2)
     q = _quats(rng, n)
-    op = (rng.standard_normal(n, dtype=np.float32) * 2.0).astype(np.float32)
+    op = rng.normal(n, 0.0, 2.0)
     sh = _sh(rng, n, sh_degree, 0.5, 0.1)
     cam = _aerial_camera((0.0, -600.0, 150.0), math.pi / 2, width, height)
     return Scene(means, ls, q, op, sh, sh_degree), cam
@@ -224,8 +298,7 @@ def diff_workload(n=1_000_000, seed=0, target_seed=7):
 
 
 def target_image(width, height, seed=7):
-    rng = np.random.Generator(np.random.PCG64(seed))
-    return rng.uniform(0, 1, (3, height, width)).astype(np.float32)
+    return Rand(seed).uniform((3, height, width))
 
 
 BATCH_RESOLUTIONS = ((640, 480), (1920, 1080), (3840, 2160), (3660, 3200))
@@ -237,7 +310,7 @@ def batched_workload(n=2_000_000, seed=0, n_views=64, orbit_seed=1234, n_buildin
     2 pi k / n_views + U(-pi/n_views, pi/n_views), pitched 30 deg down toward the
     centre; view k has resolution ``BATCH_RESOLUTIONS[k % 4]``."""
     scene, _ = city_scene(n=n, seed=seed, n_buildings=n_buildings)
-    rng = np.random.Generator(np.random.PCG64(orbit_seed))
+    rng = np.random.Generator(np.random.PCG64(orbit_seed))  # 64 draws: sequential is fine
     cams = []
     for k in range(n_views):
         az = 2 * math.pi * k / n_views + rng.uniform(-math.pi / n_views, math.pi / n_views)

@@ -262,7 +262,9 @@ def test_lut_bin_lookup(O):
 
 # --------------------------------------------------------------------------- blend closed forms
 def _pipeline_single(O, gaussians, cam, bg=(0, 0, 0)):
-    """Build a Frame from explicit 2D records (mean, conic, opacity, rgb)."""
+    """Build a Frame from explicit 2D records (mean x, mean y, A, beta, gamma,
+    opacity, r, g, b), where the inverse covariance is
+    [[A, A beta], [A beta, A beta^2 + gamma]]."""
     n = len(gaussians)
     rec = np.zeros((n, 9))
     for i, g in enumerate(gaussians):
@@ -288,7 +290,8 @@ def test_blend_single_gaussian_at_centre(O):
 
 
 def test_blend_two_gaussians_closed_form(O):
-    """C = a1 c1 + a2 (1 - a1) c2 + (1 - a1)(1 - a2) bg with a_i = s_i exp(power_i)."""
+    """C = a1 c1 + a2 (1 - a1) c2 + (1 - a1)(1 - a2) bg with a_i = s_i exp(power_i),
+    power_i = -d^T M_i d / 2 evaluated as a plain matrix product."""
     cam = scenes.make_camera(np.eye(3), np.zeros(3), 16, 16)
     g1 = (3.0, 4.0, 0.2, 0.05, 0.1, 0.6, 1.0, 0.0, 0.2)
     g2 = (6.0, 2.0, 0.1, -0.02, 0.3, 0.8, 0.0, 1.0, 0.4)
@@ -299,8 +302,9 @@ def test_blend_two_gaussians_closed_form(O):
         Tt = 1.0
         for g in (g1, g2):
             g = np.float32(g).astype(np.float64)
-            dx, dy = g[0] - px, g[1] - py
-            a = min(0.99, g[5] * math.exp(-0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy))
+            d = np.array([g[0] - px, g[1] - py])
+            M = np.array([[g[2], g[2] * g[3]], [g[2] * g[3], g[2] * g[3] ** 2 + g[4]]])
+            a = min(0.99, g[5] * math.exp(-0.5 * d @ M @ d))
             if a < O_TAU:
                 continue
             col += a * Tt * g[6:9]
@@ -404,6 +408,8 @@ def test_psnr_ssim_definitions(O):
 
 
 def test_conic_inverts_covariance(O):
+    """conic is Sigma2^-1, and the sum-of-squares record (A, beta, gamma) gives
+    the same quadratic form d^T Sigma2^-1 d (numpy's matrix inverse)."""
     sc, cam = scenes.tiny_scene(seed=9)
     pre = O.preprocess(sc, cam)
     m = pre.flags >= 1
@@ -412,6 +418,14 @@ def test_conic_inverts_covariance(O):
     np.testing.assert_allclose(A * a + B * b, 1, atol=1e-12)
     np.testing.assert_allclose(A * b + B * c, 0, atol=1e-12)
     np.testing.assert_allclose(B * b + Cc * c, 1, atol=1e-12)
+    rng = np.random.default_rng(0)
+    for i in np.nonzero(m)[0][:200]:
+        inv = np.linalg.inv(np.array([[pre.cov2d[i, 0], pre.cov2d[i, 1]],
+                                      [pre.cov2d[i, 1], pre.cov2d[i, 2]]]))
+        d = rng.normal(size=2) * 10
+        qa, qb, qg = pre.quad[i]
+        q = qa * (d[0] + qb * d[1]) ** 2 + qg * d[1] ** 2
+        assert q == pytest.approx(d @ inv @ d, rel=1e-10)
 
 
 @pytest.mark.parametrize("adagscale", [False, True])
