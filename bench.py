@@ -214,7 +214,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
-    scene_h, cam = scenes.city_scene(n=args.n, width=args.width, height=args.height)
+    scene_h, cam = scenes.city_scene(n=args.n, width=args.width, height=args.height, progress=log)
     log(f"scene generated in {time.perf_counter() - t0:.1f} s")
     scene = R.DeviceScene.from_host(scene_h, dev)
     cam_s = gsr.camera_struct(cam)

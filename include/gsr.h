@@ -204,6 +204,48 @@ gs_status gs_preprocess_backward(const gs_scene *scene, const gs_camera *cam,
                                  const uint32_t *tiles_touched, const float *grad_splats,
                                  const gs_scene_grads *out, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Many views in one launch.  The per-view stages (gs_preprocess, gs_emit_pairs,
+ * gs_sort) run per view; the rasterization of all views then runs as ONE
+ * persistent launch over a queue of (view, tile) work items ordered longest
+ * tile list first, so the tail of the frame is short whatever the mix of
+ * resolutions.  Every call is graph-capturable (no host synchronisation, no
+ * allocation, no memset nodes).
+ * ------------------------------------------------------------------------- */
+#define GS_MAX_VIEWS 64
+
+/* One view's inputs (outputs of its own gs_preprocess / gs_sort) and outputs;
+ * all pointers are device memory, layouts as for gs_rasterize. */
+typedef struct {
+    const float *splats;
+    const uint32_t *sorted_gids;
+    const uint32_t *ranges;
+    float *image;
+    float *final_T;
+    uint32_t *n_contrib;
+    int width, height;
+} gs_view_target;
+
+/* Workspace bytes for gs_rasterize_views over total_tiles (view, tile) items. */
+size_t gs_views_workspace_size(int n_views, int64_t total_tiles);
+
+/* Rasterize n_views views (1..GS_MAX_VIEWS) in one persistent launch.
+ * views: HOST array (validated, and used to size the work queue); d_views: the
+ * same array in DEVICE memory (read by the kernels; caller-owned, must stay
+ * unchanged until the work completes).  bg: host float[3] shared by all views.
+ * cfg: raster geometry as for gs_rasterize.  clock (nullable, device uint64
+ * [1 + n_views]): [0] receives the device wall clock at the start of the
+ * launch, [1 + v] the clock when view v's last tile finished (the clock runs
+ * at hipDeviceAttributeWallClockRate kHz).  Results are identical to calling
+ * gs_rasterize once per view. */
+gs_status gs_rasterize_views(const gs_view_target *views, const gs_view_target *d_views,
+                             int n_views, const float *bg, const gs_raster_cfg *cfg,
+                             uint64_t *clock, void *ws, size_t ws_bytes, void *stream);
+
+/* Frequency of the device wall clock stamped by gs_rasterize_views, in kHz
+ * (0 if the query fails). */
+int gs_wall_clock_khz(int device);
+
 const char *gs_status_string(gs_status s);
 const char *gs_last_error(void);
 /* Library version string, e.g. "gsr 0.1 gfx950". */

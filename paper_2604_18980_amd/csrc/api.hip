@@ -96,6 +96,8 @@ gs_status check_scene(const gs_scene *sc) {
 }
 }  // namespace
 
+__global__ void k_set_count(int64_t *p, int64_t v) { *p = v; }
+
 namespace gsr {
 // Sort region (depends on the pair capacity only) first, then the emit region.
 bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws) {
@@ -278,10 +280,12 @@ gs_status gs_rasterize(const float *splats, int64_t n, const uint32_t *sorted_gi
     if (!ranges || !image || !final_T || !n_contrib || !bg)
         return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
     if (n > 0 && (!splats || !sorted_gids)) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
-    gs_raster_cfg c = {256, 1, 256};
+    gs_raster_cfg c = {64, 4, 64};
     if (cfg && (cfg->threads_per_tile || cfg->pixels_per_thread || cfg->lds_batch)) {
         c = *cfg;
-        if (c.threads_per_tile != 256 || c.pixels_per_thread != 1 || c.lds_batch != 256)
+        const bool block = c.threads_per_tile == 256 && c.pixels_per_thread == 1 && c.lds_batch == 256;
+        const bool wave = c.threads_per_tile == 64 && c.pixels_per_thread == 4 && c.lds_batch == 64;
+        if (!block && !wave)
             return fail(GS_ERR_UNSUPPORTED, "raster geometry %d/%d/%d not built", c.threads_per_tile,
                         c.pixels_per_thread, c.lds_batch);
     }
@@ -361,6 +365,109 @@ gs_status gs_preprocess_backward(const gs_scene *scene, const gs_camera *cam,
     a.d_opacity_logits = out->d_opacity_logits;
     a.d_sh = out->d_sh;
     return hip_check(launch_preprocess_backward(a, (hipStream_t)stream), "gs_preprocess_backward");
+}
+
+namespace {
+struct ViewsWs {
+    uint32_t *key[3], *val[3], *hist, *next, *view_left;
+    uint64_t *parts;
+    int64_t nblocks;
+    size_t bytes;
+};
+void views_layout(int n_views, int64_t total, void *base, ViewsWs *w) {
+    size_t off = 0;
+    char *b = static_cast<char *>(base);
+    auto take = [&](size_t bytes) -> char * {
+        off = align256(off);
+        char *p = b ? b + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const size_t m = (size_t)(total > 0 ? total : 1);
+    for (int i = 0; i < 3; ++i) {
+        w->key[i] = (uint32_t *)take(4 * m);
+        w->val[i] = (uint32_t *)take(4 * m);
+    }
+    w->nblocks = (int64_t)((m + kSortChunk - 1) / kSortChunk);
+    w->hist = (uint32_t *)take(4 * 256 * (size_t)w->nblocks);
+    w->parts = (uint64_t *)take(8 * (size_t)((256 * w->nblocks + kScanChunk - 1) / kScanChunk + 1));
+    w->next = (uint32_t *)take(4);
+    w->view_left = (uint32_t *)take(4 * (size_t)(n_views > 0 ? n_views : 1));
+    w->bytes = align256(off) + 256;  // + room for the item count
+}
+}  // namespace
+
+int gs_wall_clock_khz(int device) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, device) != hipSuccess) return 0;
+    return v;
+}
+
+size_t gs_views_workspace_size(int n_views, int64_t total_tiles) {
+    if (n_views < 0 || total_tiles < 0) return 0;
+    ViewsWs w;
+    views_layout(n_views, total_tiles, nullptr, &w);
+    return w.bytes;
+}
+
+gs_status gs_rasterize_views(const gs_view_target *views, const gs_view_target *d_views,
+                             int n_views, const float *bg, const gs_raster_cfg *cfg,
+                             uint64_t *clock, void *ws, size_t ws_bytes, void *stream) {
+    if (!views || !d_views || !bg) return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (n_views < 1 || n_views > GS_MAX_VIEWS)
+        return fail(GS_ERR_INVALID_ARGUMENT, "n_views %d outside 1..%d", n_views, GS_MAX_VIEWS);
+    ViewsPlan p;
+    memset(&p, 0, sizeof p);
+    p.n_views = n_views;
+    int64_t total = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const gs_view_target &t = views[v];
+        if (t.width < 1 || t.height < 1 || t.width > GS_MAX_IMAGE_SIDE || t.height > GS_MAX_IMAGE_SIDE)
+            return fail(GS_ERR_INVALID_ARGUMENT, "view %d: image size %dx%d", v, t.width, t.height);
+        if (!t.ranges || !t.image || !t.final_T || !t.n_contrib)
+            return fail(GS_ERR_INVALID_ARGUMENT, "view %d: NULL array", v);
+        p.tile_off[v] = (uint32_t)total;
+        p.tiles_x[v] = (uint32_t)((t.width + GS_TILE - 1) / GS_TILE);
+        total += (int64_t)p.tiles_x[v] * ((t.height + GS_TILE - 1) / GS_TILE);
+    }
+    if (total >= ((int64_t)1 << 26)) return fail(GS_ERR_INVALID_ARGUMENT, "more than 2^26 tiles");
+    p.tile_off[n_views] = (uint32_t)total;
+    gs_raster_cfg c = {64, 4, 64};
+    if (cfg && (cfg->threads_per_tile || cfg->pixels_per_thread || cfg->lds_batch)) {
+        c = *cfg;
+        const bool block = c.threads_per_tile == 256 && c.pixels_per_thread == 1 &&
+                           (c.lds_batch == 64 || c.lds_batch == 128 || c.lds_batch == 256);
+        const bool wave = c.threads_per_tile == 64 && c.pixels_per_thread == 4 && c.lds_batch == 64;
+        if (!block && !wave)
+            return fail(GS_ERR_UNSUPPORTED, "raster geometry %d/%d/%d not built", c.threads_per_tile,
+                        c.pixels_per_thread, c.lds_batch);
+    }
+    ViewsWs w;
+    views_layout(n_views, total, ws, &w);
+    if (!ws || ws_bytes < w.bytes)
+        return fail(GS_ERR_CAPACITY, "workspace of %zu bytes, %zu needed", ws_bytes, w.bytes);
+    hipStream_t s = (hipStream_t)stream;
+    int64_t *count = (int64_t *)((char *)ws + w.bytes - 256);
+    hipError_t e = launch_views_plan(p, d_views, w.key[0], w.val[0], w.next, w.view_left, clock, s);
+    if (e == hipSuccess) {
+        // the item count is a host-known constant; the sort reads it from device memory
+        k_set_count<<<1, 1, 0, s>>>(count, total);
+        e = radix_sort_u32(w.key[0], w.val[0], w.key[1], w.val[1], w.key[2], w.val[2], count, total,
+                           24, w.hist, w.nblocks, w.parts, s);
+    }
+    if (e != hipSuccess) return hip_check(e, "gs_rasterize_views plan");
+    ViewsArgs q;
+    q.views = d_views;
+    for (int i = 0; i < 3; ++i) q.bg[i] = bg[i];
+    q.items = w.val[1];
+    q.n_items = total;
+    q.next = w.next;
+    q.view_left = w.view_left;
+    q.clock = clock;
+    static thread_local int grid_cache[4] = {0, 0, 0, 0};
+    const int gi = c.threads_per_tile == 256 ? (c.lds_batch == 64 ? 1 : c.lds_batch == 128 ? 2 : 3) : 0;
+    if (!grid_cache[gi]) grid_cache[gi] = raster_views_grid(c);
+    return hip_check(launch_raster_views(q, c, grid_cache[gi], s), "gs_rasterize_views");
 }
 
 }  // extern "C"

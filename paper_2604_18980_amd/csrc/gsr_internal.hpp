@@ -97,6 +97,27 @@ struct RasterArgs {
 };
 hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStream_t s);
 
+struct ViewsArgs {
+    const gs_view_target *views;  // device
+    float bg[3];
+    const uint32_t *items;        // (view << 26 | tile), longest list first
+    int64_t n_items;
+    uint32_t *next;               // work ticket
+    uint32_t *view_left;          // [n_views] tiles not yet finished
+    uint64_t *clock;              // nullable, [1 + n_views]
+};
+hipError_t launch_raster_views(const ViewsArgs &q, const gs_raster_cfg &cfg, int grid, hipStream_t s);
+int raster_views_grid(const gs_raster_cfg &cfg);
+
+struct ViewsPlan {
+    int n_views;
+    uint32_t tile_off[GS_MAX_VIEWS + 1];  // prefix of tiles per view
+    uint32_t tiles_x[GS_MAX_VIEWS];
+};
+hipError_t launch_views_plan(const ViewsPlan &p, const gs_view_target *d_views, uint32_t *keys,
+                             uint32_t *vals, uint32_t *next, uint32_t *view_left, uint64_t *clock,
+                             hipStream_t s);
+
 struct RasterBwdArgs {
     const float *splats;
     const uint32_t *gids;

@@ -1,12 +1,24 @@
 // Stage 4: tile rasterization, front-to-back alpha blending (paper Sec. 2.1,
 // eq. 1-2), with the original covariance and tau in both modes (dual size,
-// Sec. 3.3).
+// Sec. 3.3).  Two tile programs, each usable by a one-view grid and by the
+// persistent multi-view work queue:
 //
-// One workgroup per 16x16 tile, one pixel per thread.  The tile's sorted list
-// is walked in batches: each thread gathers one 48-byte splat record (three
-// 16-byte loads) into LDS, then every pixel scans the batch with wave-uniform
-// LDS broadcasts.  A block-wide vote ends the walk once every pixel has hit
-// the 1e-4 transmittance stop.
+// tile_block<BATCH>  one 256-thread workgroup per tile, one pixel per thread.
+//   The tile's list is walked in batches of BATCH records gathered into LDS
+//   (three 16-byte loads per record); a block vote ends the walk once every
+//   pixel has reached the 1e-4 transmittance stop.
+//
+// tile_wave          one wave per tile, four pixels per lane.  Lane l owns
+//   column l % 16 and rows l / 16 + 4k (k = 0..3), so each wave instruction
+//   evaluates one 16x4 strip.  The list is walked 64 records at a time: every
+//   lane gathers one record and decides, for its Gaussian, which strips can
+//   reach alpha >= tau (the exponent's minimum over each strip row, taken over
+//   the continuous column interval, against 2 ln(opacity/tau) plus a margin
+//   that covers float32 rounding); four ballots turn that into 64-bit masks.
+//   The wave walks the set bits in list order, broadcasts each record into
+//   scalar registers with v_readlane and evaluates only the hit strips.  A
+//   skipped strip has alpha < tau at every pixel, so results are unchanged.
+//   No LDS and no barriers: waves run and retire independently.
 #include "gsr_internal.hpp"
 
 namespace gsr {
@@ -15,14 +27,30 @@ namespace {
 constexpr float kTauF = 1.0f / 255.0f;
 constexpr float kStopF = 1e-4f;
 constexpr float kAlphaMaxF = 0.99f;
-constexpr int kBatch = 256;
+constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
+constexpr float kLnTau = -5.5412635451584258f;            // ln(1/255)
+
+__device__ __forceinline__ float bcast(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+__device__ __forceinline__ void store_pixel(const RasterArgs &a, int px, int py, float cr, float cg,
+                                            float cb, float T, uint32_t last, uint32_t ev) {
+    const size_t npix = (size_t)a.width * a.height, pix = (size_t)py * a.width + px;
+    a.image[pix] = cr + T * a.bg[0];
+    a.image[npix + pix] = cg + T * a.bg[1];
+    a.image[2 * npix + pix] = cb + T * a.bg[2];
+    a.final_T[pix] = T;
+    a.n_contrib[pix] = last;
+    if (a.n_evaluated) a.n_evaluated[pix] = ev;
+}
 }  // namespace
 
-__global__ __launch_bounds__(256) void k_raster(const RasterArgs a) {
-    __shared__ float4 s_geo[kBatch];  // mean x, mean y, A, beta
-    __shared__ float4 s_att[kBatch];  // gamma, opacity, red, green
-    __shared__ float s_blue[kBatch];
-    const int tile = blockIdx.x;
+template <int BATCH>
+__device__ __forceinline__ void tile_block(const RasterArgs &a, int tile) {
+    __shared__ float4 s_geo[BATCH];  // mean x, mean y, A, beta
+    __shared__ float4 s_att[BATCH];  // gamma, opacity, red, green
+    __shared__ float s_blue[BATCH];
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int px = tx * kTile + (threadIdx.x & (kTile - 1));
     const int py = ty * kTile + (threadIdx.x / kTile);
@@ -34,10 +62,10 @@ __global__ __launch_bounds__(256) void k_raster(const RasterArgs a) {
     float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
     uint32_t last = 0, evaluated = end - start;
     bool done = !inside;
-    for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
+    for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
         if (__syncthreads_count(done) == (int)blockDim.x) break;
         const uint32_t j = b0 + threadIdx.x;
-        if (j < end) {
+        if (threadIdx.x < BATCH && j < end) {
             const size_t g = a.gids[j];
             const float4 g0 = spl[3 * g], g1 = spl[3 * g + 1], g2 = spl[3 * g + 2];
             s_geo[threadIdx.x] = g0;
@@ -45,7 +73,7 @@ __global__ __launch_bounds__(256) void k_raster(const RasterArgs a) {
             s_blue[threadIdx.x] = g2.z;
         }
         __syncthreads();
-        const int cnt = (int)min((uint32_t)kBatch, end - b0);
+        const int cnt = (int)min((uint32_t)BATCH, end - b0);
         if (!done) {
             for (int k = 0; k < cnt; ++k) {
                 const float4 g = s_geo[k];
@@ -63,30 +91,279 @@ __global__ __launch_bounds__(256) void k_raster(const RasterArgs a) {
                     break;
                 }
                 const float w = alpha * T;
-                cr += w * c.z;
-                cg += w * c.w;
-                cb += w * s_blue[k];
+                cr = fmaf(w, c.z, cr);
+                cg = fmaf(w, c.w, cg);
+                cb = fmaf(w, s_blue[k], cb);
                 T = Tn;
                 last = (b0 - start) + (uint32_t)k + 1u;
             }
         }
     }
-    if (inside) {
-        const size_t npix = (size_t)a.width * a.height, pix = (size_t)py * a.width + px;
-        a.image[pix] = cr + T * a.bg[0];
-        a.image[npix + pix] = cg + T * a.bg[1];
-        a.image[2 * npix + pix] = cb + T * a.bg[2];
-        a.final_T[pix] = T;
-        a.n_contrib[pix] = last;
-        if (a.n_evaluated) a.n_evaluated[pix] = evaluated;
+    if (inside) store_pixel(a, px, py, cr, cg, cb, T, last, evaluated);
+}
+
+__device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int col = lane & 15, row0 = lane >> 4;
+    const int px = tx * kTile + col;
+    const float fpx = (float)px;
+    const float x_lo = (float)(tx * kTile), x_hi = (float)(tx * kTile + kTile - 1);
+    float fpy[4], T[4], cr[4], cg[4], cb[4];
+    uint32_t last[4], ev[4];
+    bool done[4];
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int py = ty * kTile + row0 + 4 * k;
+        fpy[k] = (float)py;
+        T[k] = 1.0f;
+        cr[k] = cg[k] = cb[k] = 0.0f;
+        last[k] = 0;
+        ev[k] = end - start;
+        done[k] = !(px < a.width && py < a.height);
+    }
+    const float4 *spl = reinterpret_cast<const float4 *>(a.splats);
+
+    for (uint32_t base = start; base < end; base += kWave) {
+        uint32_t alive = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (__ballot(!done[k]) != 0ull) alive |= 1u << k;
+        if (!alive) break;
+        const uint32_t j = base + (uint32_t)lane;
+        float mx = 0.f, my = 0.f, A2 = 0.f, beta = 0.f, G2 = 0.f, sig = 0.f, r = 0.f, g = 0.f, bl = 0.f;
+        uint32_t hit = 0;
+        if (j < end) {
+            const size_t gid = a.gids[j];
+            const float4 g0 = spl[3 * gid], g1 = spl[3 * gid + 1], g2 = spl[3 * gid + 2];
+            mx = g0.x; my = g0.y; beta = g0.w; sig = g1.y; r = g2.x; g = g2.y; bl = g2.z;
+            const float A = g0.z, gam = g1.x;
+            A2 = A * kNegHalfLog2e;
+            G2 = gam * kNegHalfLog2e;
+            // alpha >= tau  <=>  q <= 2 ln(opacity / tau).  The cut gets a margin
+            // above the float32 rounding of both this test and the per-pixel
+            // evaluation: relative 1e-3, plus a term growing with the distance of
+            // the centre (dx and dy lose digits there).
+            const float qlim = 2.0f * (__logf(sig) - kLnTau);
+            if (qlim > -1e-3f) {
+                const float ql = fmaxf(qlim, 0.0f);
+                const float far = fabsf(mx - (x_lo + 7.5f)) + fabsf(my - (float)(ty * kTile) - 7.5f);
+                const float qcut = ql + 1e-3f * (1.0f + ql) +
+                                   1e-5f * far * (1.0f + sqrtf((A + gam) * ql));
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    float qmin = 3.0e38f;
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const float dy = my - (float)(ty * kTile + 4 * k + rr);
+                        const float lo = (mx - x_hi) + beta * dy, hi = (mx - x_lo) + beta * dy;
+                        const float um = lo > 0.0f ? lo : (hi < 0.0f ? -hi : 0.0f);
+                        qmin = fminf(qmin, A * um * um + gam * dy * dy);
+                    }
+                    if (qmin <= qcut) hit |= 1u << k;
+                }
+            }
+        }
+        uint64_t m[4], any = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            m[k] = ((alive >> k) & 1u) ? __ballot((hit >> k) & 1u) : 0ull;
+            any |= m[k];
+        }
+        while (any) {
+            const int jj = __ffsll((long long)any) - 1;
+            any &= any - 1ull;
+            const float smx = bcast(mx, jj), smy = bcast(my, jj), sA2 = bcast(A2, jj);
+            const float sbeta = bcast(beta, jj), sG2 = bcast(G2, jj), ssig = bcast(sig, jj);
+            const float sr = bcast(r, jj), sg = bcast(g, jj), sb = bcast(bl, jj);
+            const float dx = smx - fpx;
+            const uint32_t pos = (base - start) + (uint32_t)jj + 1u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!((m[k] >> jj) & 1ull)) continue;
+                if (done[k]) continue;
+                const float dy = smy - fpy[k];
+                const float u = fmaf(sbeta, dy, dx);
+                const float e2 = fmaf(sA2 * u, u, sG2 * (dy * dy));
+                const float alpha = fminf(kAlphaMaxF, ssig * __builtin_amdgcn_exp2f(e2));
+                if (alpha < kTauF) continue;
+                const float Tn = T[k] * (1.0f - alpha);
+                if (Tn < kStopF) {
+                    done[k] = true;
+                    ev[k] = pos;
+                    continue;
+                }
+                const float w = alpha * T[k];
+                cr[k] = fmaf(w, sr, cr[k]);
+                cg[k] = fmaf(w, sg, cg[k]);
+                cb[k] = fmaf(w, sb, cb[k]);
+                T[k] = Tn;
+                last[k] = pos;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int py = ty * kTile + row0 + 4 * k;
+        if (px < a.width && py < a.height) store_pixel(a, px, py, cr[k], cg[k], cb[k], T[k], last[k], ev[k]);
     }
 }
 
+// ------------------------------------------------------------- one view
+template <int BATCH>
+__global__ __launch_bounds__(256) void k_raster_block(const RasterArgs a) {
+    tile_block<BATCH>(a, (int)blockIdx.x);
+}
+
+// XCD-aware block order: workgroups are dealt round-robin to the 8 XCDs, so
+// give each XCD a contiguous run of tiles (neighbouring tiles share Gaussians,
+// and each XCD has its own L2).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int full = (nb / 8) * 8;
+    return b < full ? (b % 8) * (nb / 8) + b / 8 : b;
+}
+
+__global__ __launch_bounds__(256) void k_raster_wave(const RasterArgs a) {
+    const int tile = xcd_block((int)blockIdx.x, (int)gridDim.x) * 4 + (int)(threadIdx.x / kWave);
+    if (tile >= a.tiles_x * a.tiles_y) return;
+    tile_wave(a, tile);
+}
+
 hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStream_t s) {
-    (void)cfg;
     const unsigned tiles = (unsigned)a.tiles_x * (unsigned)a.tiles_y;
-    k_raster<<<tiles, 256, 0, s>>>(a);
+    if (cfg.threads_per_tile == 256) {
+        switch (cfg.lds_batch) {
+            case 64: k_raster_block<64><<<tiles, 256, 0, s>>>(a); break;
+            case 128: k_raster_block<128><<<tiles, 256, 0, s>>>(a); break;
+            default: k_raster_block<256><<<tiles, 256, 0, s>>>(a); break;
+        }
+    } else {
+        k_raster_wave<<<(tiles + 3) / 4, 256, 0, s>>>(a);
+    }
     return hipGetLastError();
+}
+
+// ------------------------------------------------------- many views at once
+// Work items are (view, tile) packed as view << 26 | tile, ordered longest
+// tile list first.  Waves (or workgroups) take the next item from a global
+// ticket until the queue is empty; the last item of each view stamps the
+// device clock so per-view latency can be read back.
+
+__device__ __forceinline__ void finish_item(const ViewsArgs &q, int view) {
+    if (atomicSub(&q.view_left[view], 1u) == 1u && q.clock) q.clock[1 + view] = wall_clock64();
+}
+
+__device__ __forceinline__ RasterArgs view_args(const ViewsArgs &q, int view) {
+    const gs_view_target v = q.views[view];
+    RasterArgs a;
+    a.splats = v.splats;
+    a.gids = v.sorted_gids;
+    a.ranges = v.ranges;
+    a.width = v.width;
+    a.height = v.height;
+    a.tiles_x = (v.width + kTile - 1) / kTile;
+    a.tiles_y = (v.height + kTile - 1) / kTile;
+    a.bg[0] = q.bg[0];
+    a.bg[1] = q.bg[1];
+    a.bg[2] = q.bg[2];
+    a.image = v.image;
+    a.final_T = v.final_T;
+    a.n_contrib = v.n_contrib;
+    a.n_evaluated = nullptr;
+    return a;
+}
+
+// Plan: one item per (view, tile); key = complemented list length (24 bits)
+// so an ascending stable sort puts the longest lists first.
+__global__ __launch_bounds__(256) void k_views_plan(const ViewsPlan p, const gs_view_target *views,
+                                                    uint32_t *keys, uint32_t *vals) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= p.tile_off[p.n_views]) return;
+    int v = 0;
+    while (v + 1 < p.n_views && p.tile_off[v + 1] <= i) ++v;
+    const uint32_t t = i - p.tile_off[v];
+    const uint32_t *r = views[v].ranges;
+    const uint32_t len = r[2 * t + 1] - r[2 * t];
+    keys[i] = 0xFFFFFFu - (len < 0xFFFFFFu ? len : 0xFFFFFFu);
+    vals[i] = ((uint32_t)v << 26) | t;
+}
+
+__global__ void k_views_init(const ViewsPlan p, uint32_t *next, uint32_t *view_left, uint64_t *clock) {
+    const int v = threadIdx.x;
+    if (v == 0) {
+        *next = 0u;
+        if (clock) clock[0] = wall_clock64();
+    }
+    if (v < p.n_views) view_left[v] = p.tile_off[v + 1] - p.tile_off[v];
+}
+
+hipError_t launch_views_plan(const ViewsPlan &p, const gs_view_target *d_views, uint32_t *keys,
+                             uint32_t *vals, uint32_t *next, uint32_t *view_left, uint64_t *clock,
+                             hipStream_t s) {
+    const uint32_t total = p.tile_off[p.n_views];
+    if (total > 0) k_views_plan<<<(total + 255) / 256, 256, 0, s>>>(p, d_views, keys, vals);
+    k_views_init<<<1, 64, 0, s>>>(p, next, view_left, clock);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_raster_views_wave(const ViewsArgs q) {
+    const int lane = threadIdx.x & (kWave - 1);
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0) item = atomicAdd(q.next, 1u);
+        item = (uint32_t)__builtin_amdgcn_readfirstlane((int)item);
+        if ((int64_t)item >= q.n_items) break;
+        const uint32_t code = q.items[item];
+        const int view = (int)(code >> 26), tile = (int)(code & ((1u << 26) - 1));
+        tile_wave(view_args(q, view), tile);
+        if (lane == 0) finish_item(q, view);
+    }
+}
+
+template <int BATCH>
+__global__ __launch_bounds__(256) void k_raster_views_block(const ViewsArgs q) {
+    __shared__ uint32_t s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(q.next, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        if ((int64_t)item >= q.n_items) break;
+        const uint32_t code = q.items[item];
+        const int view = (int)(code >> 26), tile = (int)(code & ((1u << 26) - 1));
+        tile_block<BATCH>(view_args(q, view), tile);
+        if (threadIdx.x == 0) finish_item(q, view);
+    }
+}
+
+hipError_t launch_raster_views(const ViewsArgs &q, const gs_raster_cfg &cfg, int grid, hipStream_t s) {
+    if (cfg.threads_per_tile == 256) {
+        switch (cfg.lds_batch) {
+            case 64: k_raster_views_block<64><<<grid, 256, 0, s>>>(q); break;
+            case 128: k_raster_views_block<128><<<grid, 256, 0, s>>>(q); break;
+            default: k_raster_views_block<256><<<grid, 256, 0, s>>>(q); break;
+        }
+    } else {
+        k_raster_views_wave<<<grid, 256, 0, s>>>(q);
+    }
+    return hipGetLastError();
+}
+
+int raster_views_grid(const gs_raster_cfg &cfg) {
+    int dev = 0, cus = 256, per = 1;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const void *fn;
+    if (cfg.threads_per_tile == 256) {
+        fn = cfg.lds_batch == 64    ? (const void *)k_raster_views_block<64>
+             : cfg.lds_batch == 128 ? (const void *)k_raster_views_block<128>
+                                    : (const void *)k_raster_views_block<256>;
+    } else {
+        fn = (const void *)k_raster_views_wave;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) != hipSuccess || per < 1) per = 1;
+    return cus * per;
 }
 
 }  // namespace gsr

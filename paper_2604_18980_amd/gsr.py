@@ -20,7 +20,8 @@ LUT_BINS = 20
 TILE = 16
 
 EXPORTS = ("gs_workspace_size", "gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_rasterize",
-           "gs_rasterize_backward", "gs_preprocess_backward", "gs_status_string", "gs_last_error",
+           "gs_rasterize_backward", "gs_preprocess_backward", "gs_views_workspace_size",
+           "gs_rasterize_views", "gs_wall_clock_khz", "gs_status_string", "gs_last_error",
            "gs_version")
 
 
@@ -192,3 +193,36 @@ def gs_preprocess_backward(scene: GsScene, cam: GsCamera, tiles_touched, grad_sp
                            grads: GsSceneGrads, stream=None):
     _check(load().gs_preprocess_backward(C.byref(scene), C.byref(cam), _ptr(tiles_touched),
                                          _ptr(grad_splats), C.byref(grads), _stream(stream)))
+
+
+class GsViewTarget(C.Structure):
+    _fields_ = [("splats", C.c_void_p), ("sorted_gids", C.c_void_p), ("ranges", C.c_void_p),
+                ("image", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p),
+                ("width", C.c_int), ("height", C.c_int)]
+
+
+def gs_views_workspace_size(n_views, total_tiles) -> int:
+    L = load()
+    L.gs_views_workspace_size.argtypes = [C.c_int, C.c_int64]
+    L.gs_views_workspace_size.restype = C.c_size_t
+    return int(L.gs_views_workspace_size(int(n_views), int(total_tiles)))
+
+
+def gs_rasterize_views(views_host, d_views, n_views, bg, cfg, clock, ws, stream=None):
+    """views_host: ctypes array of GsViewTarget; d_views: a device tensor holding
+    the same bytes."""
+    L = load()
+    L.gs_rasterize_views.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+    L.gs_rasterize_views.restype = C.c_int
+    bgv = (C.c_float * 3)(*[float(x) for x in bg])
+    _check(L.gs_rasterize_views(C.cast(views_host, C.c_void_p), _ptr(d_views), int(n_views), bgv,
+                                C.byref(cfg) if cfg is not None else None, _ptr(clock), _ptr(ws),
+                                int(ws.numel() * ws.element_size()), _stream(stream)))
+
+
+def gs_wall_clock_khz(device=0) -> int:
+    L = load()
+    L.gs_wall_clock_khz.argtypes = [C.c_int]
+    L.gs_wall_clock_khz.restype = C.c_int
+    return int(L.gs_wall_clock_khz(int(device)))

@@ -275,17 +275,22 @@ def _aerial_camera(eye, yaw, width, height, pitch_deg=30.0):
     return look_camera(eye, f, (0, 0, 1), width, height)
 
 
-def city_scene(n=6_000_000, seed=0, sh_degree=3, n_buildings=3000, width=4608, height=3456):
+def city_scene(n=6_000_000, seed=0, sh_degree=3, n_buildings=3000, width=4608, height=3456,
+               progress=None):
     """City-scale scene: ground plane plus box buildings, log-scales ~ N(-1, 1.2),
     opacity logits ~ N(0, 2), SH degree 3 (DC ~ N(0, 0.5), bands ~ N(0, 0.1)).
     Oblique aerial camera at (0, -600, 150) looking along +y, pitched 30 deg down,
     fovx 60 deg, 4608x3456 (the Mill-19 resolution of Table I)."""
+    say = progress or (lambda *_: None)
     rng = Rand(seed)
     means = _city_points(rng, n, n_buildings)
+    say("city scene: positions drawn")
     ls = rng.normal((3, n), -1.0, 1.2)
     q = _quats(rng, n)
     op = rng.normal(n, 0.0, 2.0)
+    say("city scene: shapes drawn")
     sh = _sh(rng, n, sh_degree, 0.5, 0.1)
+    say("city scene: colours drawn")
     cam = _aerial_camera((0.0, -600.0, 150.0), math.pi / 2, width, height)
     return Scene(means, ls, q, op, sh, sh_degree), cam
 
