@@ -52,6 +52,13 @@ def parse():
     p.add_argument("--K", type=float, default=None, help="fixed K (skip the search)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-tiles", type=int, default=24)
+    p.add_argument("--workload", choices=("city", "diff", "batched"), default="city",
+                   help="city: the headline FPS line; diff: forward+backward on the 1M "
+                        "differentiable workload; batched: 64 views in one graph")
+    p.add_argument("--views", type=int, default=64)
+    p.add_argument("--copy-probe-mib", type=int, default=0,
+                   help="also run one device copy of this many MiB (a known-size kernel "
+                        "for calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     return p.parse_args()
 
 
@@ -201,6 +208,120 @@ def cpu_baseline(args, scene_h, cam, K, n_tiles_sample):
                        f"single-threaded FP64 C, -O2")}
 
 
+def bench_diff(args):
+    """Forward + adjoint on the differentiable workload (1M mid-style Gaussians,
+    1280x720, L1 loss to a seeded random target, AdaGScale pair set)."""
+    import torch
+    from paper_2604_18980_amd import gsr, render as R, scenes
+    dev = torch.device("cuda:0")
+    scene_h, cam, target = scenes.diff_workload()
+    log("diff scene generated")
+    scene = R.DeviceScene.from_host(scene_h, dev)
+    tgt = torch.from_numpy(target).to(dev)
+    cam_s = gsr.camera_struct(cam)
+    mode = dict(adagscale=True, K=0.1)
+    fb = R.render(scene, cam, slack=1.05, **mode)
+    mode_s = gsr.mode_struct(**mode)
+    grad_img = torch.empty_like(fb.image)
+    grad_splats = torch.empty_like(fb.splats)
+    outs = [torch.empty_like(t) for t in (scene.means, scene.log_scales, scene.quats,
+                                          scene.opacity_logits, scene.sh)]
+    grads = gsr.GsSceneGrads(*[t.data_ptr() for t in outs])
+    n = fb.n
+
+    def step(ev=None):
+        if ev: ev[0].record()
+        R.enqueue_frame(scene, cam_s, mode_s, fb)
+        if ev: ev[1].record()
+        torch.sub(fb.image, tgt, out=grad_img)
+        grad_img.sign_().mul_(1.0 / grad_img.numel())
+        if ev: ev[2].record()
+        gsr.gs_rasterize_backward(fb.splats, n, fb.sorted_gids, fb.ranges, cam_s, (0, 0, 0),
+                                  fb.final_T, fb.n_contrib, grad_img, grad_splats)
+        if ev: ev[3].record()
+        gsr.gs_preprocess_backward(scene.struct(), cam_s, fb.tiles_touched, grad_splats, grads)
+        if ev: ev[4].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    for e in evs:
+        step(e)
+    torch.cuda.synchronize()
+    t = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs])
+    fwd, loss, rbwd, pbwd = t.mean(0)
+    total = float(np.median(t.sum(1)))
+    P = int(fb.num_pairs.item())
+    return {"metric": "forward+backward ms, differentiable 1M-Gaussian workload, AdaGScale pairs",
+            "value": total, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": total, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "differentiable: 1M mid-style Gaussians, 1280x720, SH degree 3, "
+                                   "L1 to a random target", "K": 0.1},
+            "stages_ms": {"forward": fwd, "loss_grad": loss, "raster_backward": rbwd,
+                          "preprocess_backward": pbwd},
+            "pairs": P}
+
+
+def bench_batched(args):
+    """64 views of a 2M-Gaussian city on an orbit, mixed resolutions, all in one
+    HIP graph (per-view preprocess/emit/sort + one persistent raster launch)."""
+    import torch
+    from paper_2604_18980_amd import autotune, gsr, render as R, scenes
+    from paper_2604_18980_amd.views import MultiView
+    dev = torch.device("cuda:0")
+    scene_h, cams = scenes.batched_workload(n_views=args.views)
+    log("batched scene generated")
+    scene = R.DeviceScene.from_host(scene_h, dev)
+    out = {}
+    for name, mode in (("plain", {}), ("adagscale", dict(adagscale=True, K=args.K or 3.0))):
+        mv = MultiView(scene, cams, mode=mode)
+        mv.enqueue()
+        torch.cuda.synchronize()
+        assert not mv.overflowed()
+        cfg, times = autotune.tune_views(mv)
+        log(f"{name}: geometry {cfg.threads_per_tile}x{cfg.pixels_per_thread}b{cfg.lds_batch} {times}")
+        mv.capture()
+        for _ in range(args.warmup):
+            mv.replay()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.steps):
+            mv.replay()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.steps
+        lat = mv.view_latency_ms()
+        pairs = sum(int(fb.num_pairs.item()) for fb in mv.fbs)
+        out[name] = {"frame_ms": ms, "views_per_s": len(cams) * 1000.0 / ms,
+                     "raster_latency_ms_p50": float(np.percentile(lat, 50)),
+                     "raster_latency_ms_p99": float(np.percentile(lat, 99)),
+                     "pairs": pairs, "geometry": [cfg.threads_per_tile, cfg.pixels_per_thread,
+                                                  cfg.lds_batch], "autotune_ms": times}
+        del mv
+        torch.cuda.empty_cache()
+    return {"metric": "views/s, 64 views of a 2M-Gaussian city (mixed resolutions), one HIP graph",
+            "value": out["adagscale"]["views_per_s"], "unit": "views/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": out["adagscale"]["frame_ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"batched: 2M-Gaussian city, {len(cams)} views, "
+                                   "640x480/1920x1080/3840x2160/3660x3200"},
+            **out}
+
+
+def copy_probe(mib):
+    import torch
+    x = torch.empty(mib * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    log(f"copy probe: {mib} MiB read + {mib} MiB written")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -209,6 +330,15 @@ def main():
         sys.exit(2)
     import torch
     from paper_2604_18980_amd import gsr, render as R, scenes
+
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
+    if args.workload == "diff":
+        print(json.dumps(bench_diff(args)))
+        return
+    if args.workload == "batched":
+        print(json.dumps(bench_batched(args)))
+        return
 
     gsr.load()
     dev = torch.device("cuda:0")

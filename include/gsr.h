@@ -108,8 +108,8 @@ typedef struct {
 } gs_mode;
 
 /* Raster launch geometry.  Tiles stay 16x16 so pair sets are comparable.
- * threads_per_tile in {64, 128, 256}; pixels_per_thread = 256/threads_per_tile;
- * lds_batch in {32, 64, 128, 256} Gaussians staged per round.  A zeroed
+ * Built: (64, 4, 64) one wave per tile, 4 pixels per lane; (256, 1, B) one
+ * 256-thread workgroup per tile staging B in {64, 128, 256} records.  A zeroed
  * struct (or NULL) selects the default. */
 typedef struct {
     int threads_per_tile;

@@ -56,6 +56,15 @@ int bits_for(int64_t count) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Raster geometries with a compiled kernel: one wave per tile with 4 pixels
+// per lane, or one 256-thread workgroup per tile staging 64/128/256 records.
+bool geometry_built(const gs_raster_cfg &c) {
+    const bool block = c.threads_per_tile == 256 && c.pixels_per_thread == 1 &&
+                       (c.lds_batch == 64 || c.lds_batch == 128 || c.lds_batch == 256);
+    const bool wave = c.threads_per_tile == 64 && c.pixels_per_thread == 4 && c.lds_batch == 64;
+    return block || wave;
+}
+
 // Real-SH normalisation constants (Condon-Shortley phase) for the polynomial
 // forms used by the device code:
 //   c0 = sqrt(1/4pi), c1 = sqrt(3/4pi), c2 = sqrt(15/4pi), c3 = sqrt(5/16pi),
@@ -283,9 +292,7 @@ gs_status gs_rasterize(const float *splats, int64_t n, const uint32_t *sorted_gi
     gs_raster_cfg c = {64, 4, 64};
     if (cfg && (cfg->threads_per_tile || cfg->pixels_per_thread || cfg->lds_batch)) {
         c = *cfg;
-        const bool block = c.threads_per_tile == 256 && c.pixels_per_thread == 1 && c.lds_batch == 256;
-        const bool wave = c.threads_per_tile == 64 && c.pixels_per_thread == 4 && c.lds_batch == 64;
-        if (!block && !wave)
+        if (!geometry_built(c))
             return fail(GS_ERR_UNSUPPORTED, "raster geometry %d/%d/%d not built", c.threads_per_tile,
                         c.pixels_per_thread, c.lds_batch);
     }
@@ -435,10 +442,7 @@ gs_status gs_rasterize_views(const gs_view_target *views, const gs_view_target *
     gs_raster_cfg c = {64, 4, 64};
     if (cfg && (cfg->threads_per_tile || cfg->pixels_per_thread || cfg->lds_batch)) {
         c = *cfg;
-        const bool block = c.threads_per_tile == 256 && c.pixels_per_thread == 1 &&
-                           (c.lds_batch == 64 || c.lds_batch == 128 || c.lds_batch == 256);
-        const bool wave = c.threads_per_tile == 64 && c.pixels_per_thread == 4 && c.lds_batch == 64;
-        if (!block && !wave)
+        if (!geometry_built(c))
             return fail(GS_ERR_UNSUPPORTED, "raster geometry %d/%d/%d not built", c.threads_per_tile,
                         c.pixels_per_thread, c.lds_batch);
     }

@@ -250,10 +250,6 @@ hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStrea
 // ticket until the queue is empty; the last item of each view stamps the
 // device clock so per-view latency can be read back.
 
-__device__ __forceinline__ void finish_item(const ViewsArgs &q, int view) {
-    if (atomicSub(&q.view_left[view], 1u) == 1u && q.clock) q.clock[1 + view] = wall_clock64();
-}
-
 __device__ __forceinline__ RasterArgs view_args(const ViewsArgs &q, int view) {
     const gs_view_target v = q.views[view];
     RasterArgs a;
@@ -307,17 +303,23 @@ hipError_t launch_views_plan(const ViewsPlan &p, const gs_view_target *d_views, 
     return hipGetLastError();
 }
 
+// The ticket loop holds no lane-divergent branch: every lane takes part in the
+// atomics (lane 0 adds 1, the others 0) and lane 0's result is read with an
+// explicit readlane.  A "lane 0 fetches, then broadcast" form lets the compiler
+// split the loop so that the other lanes re-read a stale ticket without lane 0.
 __global__ __launch_bounds__(256) void k_raster_views_wave(const ViewsArgs q) {
     const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t one = lane == 0 ? 1u : 0u;
     for (;;) {
-        uint32_t item = 0;
-        if (lane == 0) item = atomicAdd(q.next, 1u);
-        item = (uint32_t)__builtin_amdgcn_readfirstlane((int)item);
+        const uint32_t t = atomicAdd(q.next, one);
+        const uint32_t item = (uint32_t)__builtin_amdgcn_readlane((int)t, 0);
         if ((int64_t)item >= q.n_items) break;
         const uint32_t code = q.items[item];
         const int view = (int)(code >> 26), tile = (int)(code & ((1u << 26) - 1));
         tile_wave(view_args(q, view), tile);
-        if (lane == 0) finish_item(q, view);
+        const uint32_t left = atomicSub(&q.view_left[view], one);
+        if (__builtin_amdgcn_readlane((int)left, 0) == 1 && q.clock)
+            q.clock[1 + view] = wall_clock64();  // same value from every lane
     }
 }
 
@@ -333,7 +335,8 @@ __global__ __launch_bounds__(256) void k_raster_views_block(const ViewsArgs q) {
         const uint32_t code = q.items[item];
         const int view = (int)(code >> 26), tile = (int)(code & ((1u << 26) - 1));
         tile_block<BATCH>(view_args(q, view), tile);
-        if (threadIdx.x == 0) finish_item(q, view);
+        if (threadIdx.x == 0 && atomicSub(&q.view_left[view], 1u) == 1u && q.clock)
+            q.clock[1 + view] = wall_clock64();
     }
 }
 
