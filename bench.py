@@ -35,6 +35,10 @@ PEAK_FP32_TFLOPS = 157.3
 # FMAs (6): 25 floating-point operations.
 FLOP_PER_EVAL = 25
 PSNR_TARGET_DB = 29.8
+# HBM bytes of one AdaGScale-frame raster launch (K = 459.18) from rocprofv3 FETCH_SIZE x 2.0
+# + WRITE_SIZE x 1.0 (copy-calibrated; profiles/city_6M_4608x3456_hbm_counters.md), valid
+# only for the rasterizer source they were taken with.
+RASTER_TRAFFIC = {"source_sha256_16": "e35611054c83f04d", "bytes": (123.4 + 334.3) * 1e6}
 
 
 def log(*a):
@@ -110,6 +114,42 @@ def timed_frames(torch, R, scene, cam_s, mode_s, fb, steps, warmup, stream):
     return wall / steps, np.array(frame_ms), timer.summary()
 
 
+def raster_traffic():
+    """Counter-measured HBM bytes per raster launch, or None if the rasterizer
+    source changed since the counters were taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2604_18980_amd", "csrc", "raster.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return RASTER_TRAFFIC["bytes"] if h == RASTER_TRAFFIC["source_sha256_16"] else None
+
+
+def graph_frames(torch, R, scene, cam_s, mode_s, fb, steps, warmup):
+    """Capture one whole frame (all four stages) in a HIP graph and time
+    `steps` replays, each between HIP events; returns (median ms, all ms)."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        R.enqueue_frame(scene, cam_s, mode_s, fb, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        R.enqueue_frame(scene, cam_s, mode_s, fb, stream=torch.cuda.current_stream())
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for a, b in evs:
+        a.record()
+        g.replay()
+        b.record()
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in evs])
+    del g
+    return float(np.median(ms)), ms
+
+
 def count_evaluations(torch, R, fb, cam_s):
     """Algorithmic evaluations of eq. (1): per pixel, the list entries up to and
     including the one that stopped it (the whole list if none did), as the
@@ -126,18 +166,23 @@ def psnr_t(torch, a, b):
 
 
 def ssim_t(torch, a, b):
-    import torch.nn.functional as F
-    x = torch.arange(11, dtype=torch.float32, device=a.device) - 5
+    """SSIM (Wang et al. 2004: 11x11 Gaussian window, sigma 1.5, valid region,
+    mean over channels), with the separable window applied as shifted sums."""
+    x = torch.arange(11, dtype=torch.float64) - 5
     g = torch.exp(-x ** 2 / (2 * 1.5 ** 2))
-    g = g / g.sum()
-    w = (g[:, None] * g[None, :])[None, None].repeat(3, 1, 1, 1)
-    a = a.clamp(0, 1)[None]
-    b = b.clamp(0, 1)[None]
-    f = lambda z: F.conv2d(z, w, groups=3)
-    ma, mb = f(a), f(b)
-    saa = f(a * a) - ma * ma
-    sbb = f(b * b) - mb * mb
-    sab = f(a * b) - ma * mb
+    g = (g / g.sum()).tolist()
+
+    def blur(z):
+        W, H = z.shape[-1], z.shape[-2]
+        y = sum(g[i] * z[..., :, i:W - 10 + i] for i in range(11))
+        return sum(g[i] * y[..., i:H - 10 + i, :] for i in range(11))
+
+    a = a.clamp(0, 1)
+    b = b.clamp(0, 1)
+    ma, mb = blur(a), blur(b)
+    saa = blur(a * a) - ma * ma
+    sbb = blur(b * b) - mb * mb
+    sab = blur(a * b) - ma * mb
     c1, c2 = 0.01 ** 2, 0.03 ** 2
     m = ((2 * ma * mb + c1) * (2 * sab + c2)) / ((ma * ma + mb * mb + c1) * (saa + sbb + c2))
     return float(m.mean().item())
@@ -368,12 +413,18 @@ def main():
 
     mode_p = gsr.mode_struct()
     mode_a = gsr.mode_struct(adagscale=True, K=K)
+    # each mode's pair buffers sized from its own count (+5%), as a renderer
+    # sizes them from the previous frame
+    fb_a.set_capacity(int(P_ada * 1.05) + 1024)
+    fb_p.set_capacity(int(P_plain * 1.05) + 1024)
+    # per-stage HIP events (eager launches) ...
     wall_a, fms_a, st_a = timed_frames(torch, R, scene, cam_s, mode_a, fb_a, args.steps, args.warmup, stream)
     wall_p, fms_p, st_p = timed_frames(torch, R, scene, cam_s, mode_p, fb_p, args.steps, args.warmup, stream)
+    # ... and whole frames replayed from a HIP graph (no host work per frame)
+    ms_a, fms_ga = graph_frames(torch, R, scene, cam_s, mode_a, fb_a, args.steps, args.warmup)
+    ms_p, fms_gp = graph_frames(torch, R, scene, cam_s, mode_p, fb_p, args.steps, args.warmup)
     assert int(fb_a.num_pairs.item()) == P_ada and int(fb_p.num_pairs.item()) == P_plain
-
-    ms_a = float(np.median(fms_a))
-    ms_p = float(np.median(fms_p))
+    eager_a, eager_p = float(np.median(fms_a)), float(np.median(fms_p))
     # dominant kernel: the rasterizer (one kernel per frame, timed by its events)
     raster_ms = st_a["raster"]
     flops = E_ada * FLOP_PER_EVAL
@@ -411,21 +462,23 @@ def main():
                    "n_gaussians": n, "width": cam["width"], "height": cam["height"],
                    "sh_degree": 3, "mode": "adagscale", "K": K,
                    "psnr_target_db": PSNR_TARGET_DB},
-        "adagscale": {"fps": 1000.0 / ms_a, "ms_p50": ms_a, "ms_p99": float(np.percentile(fms_a, 99)),
+        "adagscale": {"fps": 1000.0 / ms_a, "ms_p50": ms_a, "ms_p99": float(np.percentile(fms_ga, 99)),
                       "pairs": P_ada, "pairs_per_s": P_ada / (ms_a * 1e-3), "K": K,
-                      "stages_ms": st_a, "evaluations": E_ada},
-        "plain": {"fps": 1000.0 / ms_p, "ms_p50": ms_p, "ms_p99": float(np.percentile(fms_p, 99)),
-                  "pairs": P_plain, "pairs_per_s": P_plain / (ms_p * 1e-3), "stages_ms": st_p,
-                  "evaluations": E_plain},
+                      "eager_ms_p50": eager_a, "stages_ms": st_a, "evaluations": E_ada},
+        "plain": {"fps": 1000.0 / ms_p, "ms_p50": ms_p, "ms_p99": float(np.percentile(fms_gp, 99)),
+                  "pairs": P_plain, "pairs_per_s": P_plain / (ms_p * 1e-3), "eager_ms_p50": eager_p,
+                  "stages_ms": st_p, "evaluations": E_plain},
         "speedup_vs_plain": ms_p / ms_a,
         "pair_ratio": P_ada / max(P_plain, 1),
         "psnr_db_vs_plain": psnr,
         "ssim_vs_plain": ssim,
-        "wall_ms_per_step": wall_a,
+        "timing": "frames replayed from a HIP graph (value, ms_p50); stages_ms from eager launches "
+                  "with HIP events between stages",
+        "wall_ms_per_step_eager": wall_a,
         "stage_hbm": {k: {"achieved_GBs": v, "frac": v / PEAK_HBM_GBS} for k, v in stage_bw.items()},
-        "roofline": {"kernel": "k_raster", "bound": "alu", "achieved": achieved,
+        "roofline": {"kernel": "k_raster_wave", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": None,
+                     "traffic": raster_traffic(),
                      "basis": f"{FLOP_PER_EVAL} FLOP per eq.(1)-(2) evaluation x {E_ada} list-bounded evaluations"},
     }
     if not args.no_cpu_baseline:

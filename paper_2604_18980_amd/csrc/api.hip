@@ -124,7 +124,7 @@ bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws) {
     ws->nb_dsort = n > 0 ? (n + kSortChunk - 1) / kSortChunk : 1;
     const int64_t parts_sort = (256 * ws->nb_psort + kScanChunk - 1) / kScanChunk + 1;
     const int64_t parts_emit = (256 * ws->nb_dsort + kScanChunk - 1) / kScanChunk +
-                               (ws->nb_gauss + kScanChunk - 1) / kScanChunk + 1;
+                               (n + kScanChunk - 1) / kScanChunk + 1;
     ws->max_parts = parts_sort > parts_emit ? parts_sort : parts_emit;
     // sort region
     ws->ptile_tmp = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
@@ -136,8 +136,9 @@ bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws) {
     // emit region
     ws->vis_count = (uint32_t *)take(sizeof(uint32_t) * (size_t)ws->nb_gauss);
     ws->vis_off = (uint32_t *)take(sizeof(uint32_t) * (size_t)ws->nb_gauss);
-    ws->pair_cnt = (uint64_t *)take(sizeof(uint64_t) * (size_t)ws->nb_gauss);
-    ws->pair_off = (uint64_t *)take(sizeof(uint64_t) * (size_t)ws->nb_gauss);
+    ws->pair_cnt = (uint64_t *)take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    ws->pair_off = (uint64_t *)take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    ws->slice_start = (uint32_t *)take(sizeof(uint32_t) * (size_t)(cap / emit_chunk() + 2));
     for (int i = 0; i < 3; ++i) {
         ws->dkey[i] = (uint32_t *)take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
         ws->dval[i] = (uint32_t *)take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));

@@ -33,8 +33,9 @@ struct Workspace {
     // emit
     uint32_t *vis_count;   // [nb_gauss]
     uint32_t *vis_off;     // [nb_gauss]
-    uint64_t *pair_cnt;    // [nb_gauss] pairs per block of depth-sorted Gaussians
-    uint64_t *pair_off;    // [nb_gauss]
+    uint64_t *pair_cnt;    // [n] pairs of each depth-sorted visible Gaussian
+    uint64_t *pair_off;    // [n] their exclusive prefix
+    uint32_t *slice_start; // [cap / emit chunk + 1] first Gaussian of each emission slice
     uint32_t *dkey[3];     // [n] depth keys: input, sorted output, pass scratch
     uint32_t *dval[3];     // [n] Gaussian ids, same roles
     uint32_t *dhist;       // [256][nb_dsort]
@@ -49,6 +50,7 @@ struct Workspace {
     size_t bytes;
 };
 bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws);
+int emit_chunk();
 
 // ------------------------------------------------------------ sort constants
 constexpr int kSortThreads = 256;

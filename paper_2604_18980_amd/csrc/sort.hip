@@ -105,10 +105,22 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *key
     __syncthreads();
     const int64_t n = clamp_count(count, cap);
     const int64_t base = (int64_t)blockIdx.x * kSortChunk;
-#pragma unroll 4
-    for (int i = 0; i < kSortItems; ++i) {
-        const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
-        if (idx < n) atomicAdd(&h[wid][(keys[idx] >> shift) & 255u], 1u);
+    if (base + kSortChunk <= n) {
+        // full chunk: 16-byte loads, four keys each
+        const uint4 *k4 = reinterpret_cast<const uint4 *>(keys + base);
+#pragma unroll
+        for (int i = 0; i < kSortItems / 4; ++i) {
+            const uint4 q = k4[i * kSortThreads + threadIdx.x];
+            atomicAdd(&h[wid][(q.x >> shift) & 255u], 1u);
+            atomicAdd(&h[wid][(q.y >> shift) & 255u], 1u);
+            atomicAdd(&h[wid][(q.z >> shift) & 255u], 1u);
+            atomicAdd(&h[wid][(q.w >> shift) & 255u], 1u);
+        }
+    } else {
+        for (int i = 0; i < kSortItems; ++i) {
+            const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
+            if (idx < n) atomicAdd(&h[wid][(keys[idx] >> shift) & 255u], 1u);
+        }
     }
     __syncthreads();
     const int d = threadIdx.x;  // kSortThreads == 256 digits
@@ -118,10 +130,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *key
     hist[(int64_t)d * nblocks + blockIdx.x] = tot;
 }
 
-// Items of the chunk are assigned wave-striped: wave w owns positions
-// [w*1024, (w+1)*1024) of the chunk, and in step i lane l holds position
-// w*1024 + i*64 + l; so lane order, then step order, then wave order is the
-// input order, which makes the ranking stable.
+// Ranking: items of the chunk are assigned wave-striped -- wave w owns
+// positions [w*1024, (w+1)*1024) of the chunk and in step i lane l holds
+// position w*1024 + i*64 + l -- so lane order, then step order, then wave
+// order is the input order, which makes the ranking stable.  The ranked chunk
+// is staged in LDS in (digit, input) order and written out by consecutive
+// threads, so each digit's run leaves the block as contiguous stores.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const int64_t *count,
     int64_t cap, int shift, const uint32_t *offs, int64_t nblocks) {
@@ -129,6 +143,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     constexpr int kPerWave = kSortChunk / kWaves;
     __shared__ uint32_t wcnt[kWaves][256];
     __shared__ uint32_t gbase[256];
+    __shared__ uint32_t dstart[256];
+    __shared__ uint32_t wt[kWaves];
+    __shared__ uint32_t skey[kSortChunk];
+    __shared__ uint32_t sval[kSortChunk];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     for (int i = threadIdx.x; i < kWaves * 256; i += kSortThreads) (&wcnt[0][0])[i] = 0;
     const int64_t n = clamp_count(count, cap);
@@ -160,24 +178,35 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         if (!valid) rank[i] = 0xffffffffu;
     }
     __syncthreads();
+    uint32_t tot_d = 0;
     {   // exclusive prefix over waves per digit; thread t owns digit t
         const int d = threadIdx.x;
-        uint32_t run = 0;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
             const uint32_t c = wcnt[w][d];
-            wcnt[w][d] = run;
-            run += c;
+            wcnt[w][d] = tot_d;
+            tot_d += c;
         }
     }
+    uint32_t all;
+    dstart[threadIdx.x] = block_exclusive_scan<kSortThreads, uint32_t>(tot_d, wt, &all);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         if (rank[i] == 0xffffffffu) continue;
         const uint32_t d = (key[i] >> shift) & 255u;
-        const int64_t dst = (int64_t)gbase[d] + wcnt[wid][d] + rank[i];
-        if (kout) kout[dst] = key[i];
-        vout[dst] = val[i];
+        const uint32_t p = dstart[d] + wcnt[wid][d] + rank[i];
+        skey[p] = key[i];
+        sval[p] = val[i];
+    }
+    __syncthreads();
+    const int cnt = (int)(n - base < kSortChunk ? n - base : kSortChunk);
+    for (int p = threadIdx.x; p < cnt; p += kSortThreads) {
+        const uint32_t k = skey[p];
+        const uint32_t d = (k >> shift) & 255u;
+        const int64_t dst = (int64_t)gbase[d] + (p - (int)dstart[d]);
+        if (kout) kout[dst] = k;
+        vout[dst] = sval[p];
     }
 }
 
@@ -208,14 +237,31 @@ __global__ void k_fill_u32(uint32_t *p, int64_t m, uint32_t v) {
     if (i < m) p[i] = v;
 }
 
+// Thread i tests the boundary between items i-1 and i, for four consecutive i
+// per thread (one 16-byte load plus the item before).
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *tiles, const int64_t *count,
                                                      int64_t cap, uint32_t *ranges) {
     const int64_t n = clamp_count(count, cap);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t t = tiles[i];
-    if (i == 0 || tiles[i - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)i;
-    if (i == n - 1 || tiles[i + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i0 >= n) return;
+    uint32_t t[5];
+    t[0] = i0 > 0 ? tiles[i0 - 1] : 0xffffffffu;
+    if (i0 + 4 <= n) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(tiles + i0);
+        t[1] = q.x; t[2] = q.y; t[3] = q.z; t[4] = q.w;
+    } else {
+        for (int k = 0; k < 4; ++k) t[1 + k] = i0 + k < n ? tiles[i0 + k] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = i0 + k;
+        if (i >= n) break;
+        if (t[k + 1] != t[k]) {
+            ranges[2 * (int64_t)t[k + 1]] = (uint32_t)i;
+            if (i > 0) ranges[2 * (int64_t)t[k] + 1] = (uint32_t)i;
+        }
+    }
+    if (i0 + 4 >= n && i0 < n) ranges[2 * (int64_t)tiles[n - 1] + 1] = (uint32_t)n;
 }
 
 hipError_t launch_tile_ranges(const uint32_t *sorted_tiles, const int64_t *num_pairs, int64_t cap,
@@ -223,7 +269,7 @@ hipError_t launch_tile_ranges(const uint32_t *sorted_tiles, const int64_t *num_p
     const int64_t m = 2 * (int64_t)num_tiles;
     k_fill_u32<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(ranges, m, 0u);
     if (cap > 0)
-        k_tile_ranges<<<(unsigned)((cap + 255) / 256), 256, 0, s>>>(sorted_tiles, num_pairs, cap, ranges);
+        k_tile_ranges<<<(unsigned)((cap + 1023) / 1024), 256, 0, s>>>(sorted_tiles, num_pairs, cap, ranges);
     return hipGetLastError();
 }
 
