@@ -532,9 +532,12 @@ void orc_blend_bruteforce(int mode, int64_t n, int width, int height, const int3
 /* alpha = min(0.99, sigma e^power): a clamped alpha has zero derivative;     */
 /* otherwise dalpha/dsigma = e^power and dalpha/dpower = alpha.              */
 /* Outputs accumulate into g2d[g*9 + (mx, my, A, beta, gamma, sigma, r, g, b)]. */
+/* tiles (n_sel >= 0): only those tiles' pixels are differentiated (the others  */
+/* are taken to have zero dL/dimage).                                          */
 /* ------------------------------------------------------------------------ */
 void orc_blend_backward(int width, int height, const int64_t *ranges, const uint32_t *sorted_vals,
-                        const double *rec, const double *bg, const double *dL_dimage, double *g2d) {
+                        const double *rec, const double *bg, const double *dL_dimage, double *g2d,
+                        const int32_t *tiles, int64_t n_sel) {
     int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
     int64_t npix = (int64_t)width * height;
     int64_t cap = 0;
@@ -542,12 +545,14 @@ void orc_blend_backward(int width, int height, const int64_t *ranges, const uint
         int64_t len = ranges[2 * t + 1] - ranges[2 * t];
         if (len > cap) cap = len;
     }
+    int64_t count = n_sel >= 0 ? n_sel : (int64_t)TX * TY;
     int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cap + 1));
     double *al = (double *)malloc(sizeof(double) * (size_t)(cap + 1));
     double *ex = (double *)malloc(sizeof(double) * (size_t)(cap + 1));
     int *cl = (int *)malloc(sizeof(int) * (size_t)(cap + 1));
     double *Ts = (double *)malloc(sizeof(double) * (size_t)(cap + 2));
-    for (int t = 0; t < TX * TY; ++t) {
+    for (int64_t sidx = 0; sidx < count; ++sidx) {
+        int t = n_sel >= 0 ? tiles[sidx] : (int)sidx;
         int tx = t % TX, ty = t / TX;
         const uint32_t *list = sorted_vals + ranges[2 * t];
         int64_t len = ranges[2 * t + 1] - ranges[2 * t];

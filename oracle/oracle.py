@@ -64,7 +64,7 @@ def lib():
         L.orc_blend.argtypes = [C.c_int, C.c_int, P, P, P, P, P, C.c_int64, P, P, P, P, P, P]
         L.orc_blend_bruteforce.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_int, P, P, P, P, P, P,
                                            P, P]
-        L.orc_blend_backward.argtypes = [C.c_int, C.c_int, P, P, P, P, P, P]
+        L.orc_blend_backward.argtypes = [C.c_int, C.c_int, P, P, P, P, P, P, P, C.c_int64]
         L.orc_constants.argtypes = [P]
         L.orc_preprocess_backward.argtypes = [C.c_int64, P, P, P, P, P, C.c_int, P, C.c_int,
                                               C.c_int, P, P, P, P, P, P, P]
@@ -256,18 +256,20 @@ def blend_bruteforce(pre: Preproc, cam, mode_id=1, bg=(0.0, 0.0, 0.0)):
     return img, T, nc
 
 
-def blend_backward(frame: Frame, cam, dL_dimage, bg=(0.0, 0.0, 0.0), rec=None):
+def blend_backward(frame: Frame, cam, dL_dimage, bg=(0.0, 0.0, 0.0), rec=None, tiles=None):
     """Per-Gaussian gradients of the blend: [N][9] = d(mean x, mean y, A, beta,
-    gamma, opacity, r, g, b)."""
+    gamma, opacity, r, g, b).  With ``tiles``, only those tiles' pixels are
+    differentiated (dL/dimage is taken as zero elsewhere)."""
     n = frame.pre.rect.shape[0]
     if rec is None:
         rec = frame.pre.record()
     g2d = np.zeros((n, 9))
     bgv = np.asarray(bg, np.float64)
     dL = np.ascontiguousarray(dL_dimage, np.float64)
+    sel = None if tiles is None else np.ascontiguousarray(tiles, np.int32)
     lib().orc_blend_backward(cam["width"], cam["height"], _p(np.ascontiguousarray(frame.ranges)),
                              _p(np.ascontiguousarray(frame.sorted_vals, np.uint32)), _p(rec),
-                             _p(bgv), _p(dL), _p(g2d))
+                             _p(bgv), _p(dL), _p(g2d), _p(sel), -1 if sel is None else sel.size)
     return g2d
 
 
