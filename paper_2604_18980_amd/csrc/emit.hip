@@ -53,8 +53,8 @@ __device__ __forceinline__ uint32_t rect_tiles(uint64_t r) {
 __global__ __launch_bounds__(256) void k_pair_counts(const uint32_t *sorted_ids, const int64_t *num_vis,
                                                      const uint64_t *rects, uint64_t *cnt, int64_t n) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    cnt[j] = j < *num_vis ? (uint64_t)rect_tiles(rects[sorted_ids[j]]) : 0ull;
+    if (j >= n || j >= *num_vis) return;
+    cnt[j] = (uint64_t)rect_tiles(rects[sorted_ids[j]]);
 }
 
 // Emission is split into fixed slices of kEmitChunk pairs, one per workgroup,
@@ -147,7 +147,9 @@ hipError_t launch_emit(const float *splats, const uint64_t *rects, const uint32_
                        num_vis, n, 32, ws.dhist, ws.nb_dsort, ws.scan_part, s);
     if (e != hipSuccess) return e;
     k_pair_counts<<<(unsigned)nb, 256, 0, s>>>(ws.dval[1], num_vis, rects, ws.pair_cnt, n);
-    e = scan_exclusive_u64(ws.pair_cnt, ws.pair_off, n, ws.scan_part, num_pairs, s);
+    // only the num_vis leading entries are live
+    e = scan_exclusive_u64(ws.pair_cnt, ws.pair_off, n, ws.scan_part, num_pairs, s,
+                           DevExtent{num_vis, n, 1, 1});
     if (e != hipSuccess) return e;
     if (cap > 0) {
         k_slice_starts<<<(unsigned)nb, 256, 0, s>>>(ws.pair_off, ws.pair_cnt, num_vis, ws.slice_start, n, cap);

@@ -54,7 +54,10 @@ int emit_chunk();
 
 // ------------------------------------------------------------ sort constants
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;                            // per thread
+#ifndef GSR_SORT_ITEMS
+#define GSR_SORT_ITEMS 16
+#endif
+constexpr int kSortItems = GSR_SORT_ITEMS;                // per thread
 constexpr int kSortChunk = kSortThreads * kSortItems;     // 4096 items per block
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
@@ -63,12 +66,27 @@ constexpr int kScanChunk = kScanThreads * kScanItems;     // 4096 elements per b
 // ------------------------------------------------------------------ launchers
 hipError_t launch_preprocess(const PreprocessArgs &a, hipStream_t s);
 
-// device-wide exclusive scan of m elements (m known on the host); if total is
-// non-null the grand total is stored there (as int64).
+// Number of live elements of a device-wide pass whose launch was sized on the
+// host for the capacity m: with `count` set, mul * ceil(min(*count, cap) / chunk)
+// (at most m), read on the device so no host round trip is needed.
+struct DevExtent {
+    const int64_t *count = nullptr;
+    int64_t cap = 0, chunk = 1, mul = 1;
+    __device__ __forceinline__ int64_t resolve(int64_t m) const {
+        if (!count) return m;
+        int64_t c = *count;
+        c = c < 0 ? 0 : (c > cap ? cap : c);
+        const int64_t e = ((c + chunk - 1) / chunk) * mul;
+        return e < m ? e : m;
+    }
+};
+
+// device-wide exclusive scan of m elements (m known on the host, or fewer as
+// given by ext); if total is non-null the grand total is stored there (as int64).
 hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t m, uint64_t *parts,
-                              int64_t *total, hipStream_t s);
+                              int64_t *total, hipStream_t s, DevExtent ext = DevExtent{});
 hipError_t scan_exclusive_u64(const uint64_t *in, uint64_t *out, int64_t m, uint64_t *parts,
-                              int64_t *total, hipStream_t s);
+                              int64_t *total, hipStream_t s, DevExtent ext = DevExtent{});
 
 // stable LSD radix sort of (key, val) pairs, count in device memory (clamped
 // to cap); bits = number of significant key bits.  Reads (kin, vin), leaves

@@ -35,6 +35,10 @@ __device__ __forceinline__ void store_splat(float *dst, float4 a, float4 b, floa
     p[2] = c;
 }
 
+// An empty asm that claims to modify x: the value must exist in a register at
+// this point of the program.
+__device__ __forceinline__ void pin_vgpr(float &x) { __asm__ volatile("" : "+v"(x)); }
+
 // Real spherical harmonics (Condon-Shortley phase, coefficient k = l^2+l+m)
 // at the unit direction (x, y, z), as polynomials; c[] holds the
 // normalisation constants computed on the host (see sh_constants()).
@@ -63,6 +67,9 @@ __device__ __forceinline__ void sh_eval(int degree, double x, double y, double z
 }
 }  // namespace
 
+// DEG is the SH degree (0..3), a template parameter so the colour loads of all
+// (DEG+1)^2 x 3 coefficients are issued together rather than one per loop trip.
+template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.n) return;
@@ -70,18 +77,30 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
     uint32_t tiles = 0;
     uint64_t rect = 0;
 
+    // Every per-Gaussian parameter is loaded at once (one memory round trip);
+    // the near cull below discards few Gaussians of a real view, so this
+    // fetches almost nothing the cull would have saved.
+    const float fmx = a.means[g], fmy = a.means[n + g], fmz = a.means[2 * n + g];
+    float fl0 = a.log_scales[g], fl1 = a.log_scales[n + g], fl2 = a.log_scales[2 * n + g];
+    float fqw = a.quats[g], fqx = a.quats[n + g], fqy = a.quats[2 * n + g], fqz = a.quats[3 * n + g];
+    float fop = a.opacity_logits[g];
+    // Pin the loads here: left alone, the compiler sinks them below the near
+    // cull, which costs a second dependent trip to memory.
+    pin_vgpr(fl0); pin_vgpr(fl1); pin_vgpr(fl2);
+    pin_vgpr(fqw); pin_vgpr(fqx); pin_vgpr(fqy); pin_vgpr(fqz); pin_vgpr(fop);
+
     // view transform: p = R mu + t
-    const double mx = a.means[g], my = a.means[n + g], mz = a.means[2 * n + g];
+    const double mx = fmx, my = fmy, mz = fmz;
     const double px = a.R[0] * mx + a.R[1] * my + a.R[2] * mz + a.t[0];
     const double py = a.R[3] * mx + a.R[4] * my + a.R[5] * mz + a.t[1];
     const double pz = a.R[6] * mx + a.R[7] * my + a.R[8] * mz + a.t[2];
 
     if (pz > kNearZ) {
         // scales and normalised rotation
-        const double sx = exp((double)a.log_scales[g]);
-        const double sy = exp((double)a.log_scales[n + g]);
-        const double sz = exp((double)a.log_scales[2 * n + g]);
-        double qw = a.quats[g], qx = a.quats[n + g], qy = a.quats[2 * n + g], qz = a.quats[3 * n + g];
+        const double sx = exp((double)fl0);
+        const double sy = exp((double)fl1);
+        const double sz = exp((double)fl2);
+        double qw = fqw, qx = fqx, qy = fqy, qz = fqz;
         const double qn = qw * qw + qx * qx + qy * qy + qz * qz;
         if (qn > 0.0) {
             const double r = sqrt(qn);
@@ -135,7 +154,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
         const double v = a.fy * (py / pz) + a.cy;
         const bool finite = isfinite(u) && isfinite(v) && isfinite(ca) && isfinite(cb) && isfinite(cc);
         if (finite && det > 0.0) {
-            const double sigma = 1.0 / (1.0 + exp(-(double)a.opacity_logits[g]));
+            const double sigma = 1.0 / (1.0 + exp(-(double)fop));
             // plain extent: 3 sqrt(lambda_max), discriminant floored
             const double mid = 0.5 * (ca + cc);
             double disc = mid * mid - det;
@@ -182,15 +201,18 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
                     double dx = mx - a.campos[0], dy = my - a.campos[1], dz = mz - a.campos[2];
                     const double len = sqrt(dx * dx + dy * dy + dz * dz);
                     dx = dx / len; dy = dy / len; dz = dz / len;
+                    constexpr int nsh = (DEG + 1) * (DEG + 1);
+                    float f[nsh * 3];
+#pragma unroll
+                    for (int k = 0; k < nsh * 3; ++k) f[k] = a.sh[(size_t)k * n + g];
                     double Y[16];
-                    sh_eval(a.sh_degree, dx, dy, dz, a.shc, Y);
-                    const int nsh = (a.sh_degree + 1) * (a.sh_degree + 1);
+                    sh_eval(DEG, dx, dy, dz, a.shc, Y);
                     double rgb[3];
 #pragma unroll
                     for (int ch = 0; ch < 3; ++ch) {
                         double acc = 0.0;
-                        for (int k = 0; k < nsh; ++k)
-                            acc += (double)a.sh[((size_t)k * 3 + ch) * n + g] * Y[k];
+#pragma unroll
+                        for (int k = 0; k < nsh; ++k) acc += (double)f[k * 3 + ch] * Y[k];
                         acc += 0.5;
                         rgb[ch] = acc < 0.0 ? 0.0 : acc;
                     }
@@ -210,7 +232,12 @@ hipError_t launch_preprocess(const PreprocessArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     const int threads = 256;
     const int blocks = (a.n + threads - 1) / threads;
-    k_preprocess<<<blocks, threads, 0, s>>>(a);
+    switch (a.sh_degree) {
+        case 0: k_preprocess<0><<<blocks, threads, 0, s>>>(a); break;
+        case 1: k_preprocess<1><<<blocks, threads, 0, s>>>(a); break;
+        case 2: k_preprocess<2><<<blocks, threads, 0, s>>>(a); break;
+        default: k_preprocess<3><<<blocks, threads, 0, s>>>(a); break;
+    }
     return hipGetLastError();
 }
 

@@ -18,9 +18,15 @@ namespace gsr {
 
 // ------------------------------------------------------------------- scans
 template <typename T>
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T *in, int64_t m, uint64_t *parts) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T *in, int64_t m, uint64_t *parts,
+                                                              DevExtent ext) {
     __shared__ T wt[kScanThreads / kWave];
+    m = ext.resolve(m);
     const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    if (base >= m) {  // past the live elements: contributes nothing
+        if (threadIdx.x == 0) parts[blockIdx.x] = 0;
+        return;
+    }
     T acc = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
@@ -50,8 +56,10 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint64_t *parts, int64_t npar
 // Each block rescans its chunk: thread t owns kScanItems consecutive elements.
 template <typename T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const T *in, T *out, int64_t m,
-                                                            const uint64_t *parts) {
+                                                            const uint64_t *parts, DevExtent ext) {
     __shared__ T wt[kScanThreads / kWave];
+    m = ext.resolve(m);
+    if ((int64_t)blockIdx.x * kScanChunk >= m) return;
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
     T v[kScanItems];
     T acc = 0;
@@ -73,21 +81,21 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const T *in, T *out,
 
 template <typename T>
 static hipError_t scan_exclusive(const T *in, T *out, int64_t m, uint64_t *parts, int64_t *total,
-                                 hipStream_t s) {
+                                 DevExtent ext, hipStream_t s) {
     const int64_t nparts = (m + kScanChunk - 1) / kScanChunk;
-    if (nparts > 0) k_scan_reduce<T><<<(unsigned)nparts, kScanThreads, 0, s>>>(in, m, parts);
+    if (nparts > 0) k_scan_reduce<T><<<(unsigned)nparts, kScanThreads, 0, s>>>(in, m, parts, ext);
     k_scan_top<<<1, 1024, 0, s>>>(parts, nparts, total);
-    if (nparts > 0) k_scan_down<T><<<(unsigned)nparts, kScanThreads, 0, s>>>(in, out, m, parts);
+    if (nparts > 0) k_scan_down<T><<<(unsigned)nparts, kScanThreads, 0, s>>>(in, out, m, parts, ext);
     return hipGetLastError();
 }
 
 hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t m, uint64_t *parts,
-                              int64_t *total, hipStream_t s) {
-    return scan_exclusive<uint32_t>(in, out, m, parts, total, s);
+                              int64_t *total, hipStream_t s, DevExtent ext) {
+    return scan_exclusive<uint32_t>(in, out, m, parts, total, ext, s);
 }
 hipError_t scan_exclusive_u64(const uint64_t *in, uint64_t *out, int64_t m, uint64_t *parts,
-                              int64_t *total, hipStream_t s) {
-    return scan_exclusive<uint64_t>(in, out, m, parts, total, s);
+                              int64_t *total, hipStream_t s, DevExtent ext) {
+    return scan_exclusive<uint64_t>(in, out, m, parts, total, ext, s);
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -105,6 +113,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *key
     __syncthreads();
     const int64_t n = clamp_count(count, cap);
     const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+    if (base >= n) return;  // idle block (uniform): holds no items, owns no histogram column
+    const int64_t nb_live = (n + kSortChunk - 1) / kSortChunk;
     if (base + kSortChunk <= n) {
         // full chunk: 16-byte loads, four keys each
         const uint4 *k4 = reinterpret_cast<const uint4 *>(keys + base);
@@ -127,7 +137,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *key
     uint32_t tot = 0;
 #pragma unroll
     for (int w = 0; w < kSortThreads / kWave; ++w) tot += h[w][d];
-    hist[(int64_t)d * nblocks + blockIdx.x] = tot;
+    hist[(int64_t)d * nb_live + blockIdx.x] = tot;
 }
 
 // Ranking: items of the chunk are assigned wave-striped -- wave w owns
@@ -152,7 +162,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const int64_t n = clamp_count(count, cap);
     const int64_t base = (int64_t)blockIdx.x * kSortChunk;
     if (base >= n) return;  // whole block idle (uniform across the block)
-    gbase[threadIdx.x] = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    const int64_t nb_live = (n + kSortChunk - 1) / kSortChunk;
+    gbase[threadIdx.x] = offs[(int64_t)threadIdx.x * nb_live + blockIdx.x];
     __syncthreads();
 
     uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
@@ -221,7 +232,9 @@ hipError_t radix_sort_u32(const uint32_t *kin, const uint32_t *vin, uint32_t *ko
         const bool to_out = ((passes - 1 - p) % 2) == 0;
         uint32_t *dk = to_out ? kout : ktmp, *dv = to_out ? vout : vtmp;
         k_radix_hist<<<(unsigned)nblocks, kSortThreads, 0, s>>>(srck, count, cap, 8 * p, hist, nblocks);
-        hipError_t e = scan_exclusive_u32(hist, hist, 256 * nblocks, parts, nullptr, s);
+        // histogram columns exist for live blocks only: 256 x ceil(count / chunk)
+        hipError_t e = scan_exclusive_u32(hist, hist, 256 * nblocks, parts, nullptr, s,
+                                          DevExtent{count, cap, kSortChunk, 256});
         if (e != hipSuccess) return e;
         k_radix_scatter<<<(unsigned)nblocks, kSortThreads, 0, s>>>(srck, srcv, dk, dv, count, cap,
                                                                     8 * p, hist, nblocks);
