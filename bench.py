@@ -86,10 +86,13 @@ class StageTimer:
         return {n: float(np.mean(v)) for n, v in out.items()}
 
 
-def timed_frames(torch, R, scene, cam_s, mode_s, fb, steps, warmup, stream):
-    names = ["preprocess", "emit", "sort", "raster"]
+def timed_frames(torch, R, scene, cam_s, mode_s, fb, steps, warmup, stream, staged=False):
+    """Eager frames with HIP events between stages.  Default stages:
+    preprocess, bin (gs_bin_pairs: emission + sort + ranges), raster; with
+    staged, the separate emission and sort entry points instead of bin."""
+    names = ["preprocess", "emit", "sort", "raster"] if staged else ["preprocess", "bin", "raster"]
     for _ in range(warmup):
-        R.enqueue_frame(scene, cam_s, mode_s, fb, stream=stream)
+        R.enqueue_frame(scene, cam_s, mode_s, fb, stream=stream, staged=staged)
     torch.cuda.synchronize()
     timer = StageTimer(torch, stream, names)
     frame_ms = []
@@ -101,12 +104,15 @@ def timed_frames(torch, R, scene, cam_s, mode_s, fb, steps, warmup, stream):
             evs[0].record(stream)
             R.run_preprocess(scene, cam_s, mode_s, fb, stream)
             evs[1].record(stream)
-            R.run_emit(fb, cam_s, stream)
-            evs[2].record(stream)
-            R.run_sort(fb, cam_s, stream)
-            evs[3].record(stream)
+            if staged:
+                R.run_emit(fb, cam_s, stream)
+                evs[2].record(stream)
+                R.run_sort(fb, cam_s, stream)
+            else:
+                R.run_bin(fb, cam_s, stream)
+            evs[-2].record(stream)
             R.run_raster(fb, cam_s, (0.0, 0.0, 0.0), stream)
-            evs[4].record(stream)
+            evs[-1].record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1000.0
     for evs in timer.ev:
@@ -420,6 +426,9 @@ def main():
     # per-stage HIP events (eager launches) ...
     wall_a, fms_a, st_a = timed_frames(torch, R, scene, cam_s, mode_a, fb_a, args.steps, args.warmup, stream)
     wall_p, fms_p, st_p = timed_frames(torch, R, scene, cam_s, mode_p, fb_p, args.steps, args.warmup, stream)
+    # the same frame through the separate emission and sort entry points, for reference
+    _, fms_sa, st_sa = timed_frames(torch, R, scene, cam_s, mode_a, fb_a, args.steps, args.warmup,
+                                    stream, staged=True)
     # ... and whole frames replayed from a HIP graph (no host work per frame)
     ms_a, fms_ga = graph_frames(torch, R, scene, cam_s, mode_a, fb_a, args.steps, args.warmup)
     ms_p, fms_gp = graph_frames(torch, R, scene, cam_s, mode_p, fb_p, args.steps, args.warmup)
@@ -438,12 +447,19 @@ def main():
     ntiles = int(fb_a.ranges.shape[0])
     passes = max(1, (int(math.ceil(math.log2(max(ntiles, 2)))) + 7) // 8)
     pre_bytes = 12 * n + 32 * front + 4 * nsh * vis + 12 * n + 48 * vis
+    # binning: visibility (8 B per Gaussian), per visible Gaussian the depth
+    # sort (4 passes x 20 B), pair counts and their scan (36 B), slice owners
+    # (12 B), the owner loads of both pass-1 kernels (2 x 20 B) and the
+    # rectangle corners (12 B); per pair one 4-byte word written, read twice
+    # and one id written (16 B); per tile count, start and range (16 B)
+    bin_bytes = 8 * n + vis * (8 + 80 + 36 + 12 + 40 + 12) + 16 * P_ada + 16 * ntiles
     emit_bytes = 8 * n + vis * (4 + 8 + 4 * 20 + 12 + 12) + 8 * P_ada
     sort_bytes = passes * 20 * P_ada - 4 * P_ada + 4 * P_ada + 8 * ntiles
     stage_bw = {
         "preprocess": pre_bytes / (st_a["preprocess"] * 1e-3) / 1e9,
-        "emit": emit_bytes / (st_a["emit"] * 1e-3) / 1e9,
-        "sort": sort_bytes / (st_a["sort"] * 1e-3) / 1e9,
+        "bin": bin_bytes / (st_a["bin"] * 1e-3) / 1e9,
+        "staged_emit": emit_bytes / (st_sa["emit"] * 1e-3) / 1e9,
+        "staged_sort": sort_bytes / (st_sa["sort"] * 1e-3) / 1e9,
     }
     out = {
         "metric": METRIC,
@@ -464,7 +480,8 @@ def main():
                    "psnr_target_db": PSNR_TARGET_DB},
         "adagscale": {"fps": 1000.0 / ms_a, "ms_p50": ms_a, "ms_p99": float(np.percentile(fms_ga, 99)),
                       "pairs": P_ada, "pairs_per_s": P_ada / (ms_a * 1e-3), "K": K,
-                      "eager_ms_p50": eager_a, "stages_ms": st_a, "evaluations": E_ada},
+                      "eager_ms_p50": eager_a, "stages_ms": st_a, "evaluations": E_ada,
+                      "staged_eager_ms_p50": float(np.median(fms_sa)), "staged_stages_ms": st_sa},
         "plain": {"fps": 1000.0 / ms_p, "ms_p50": ms_p, "ms_p99": float(np.percentile(fms_gp, 99)),
                   "pairs": P_plain, "pairs_per_s": P_plain / (ms_p * 1e-3), "eager_ms_p50": eager_p,
                   "stages_ms": st_p, "evaluations": E_plain},
@@ -473,7 +490,8 @@ def main():
         "psnr_db_vs_plain": psnr,
         "ssim_vs_plain": ssim,
         "timing": "frames replayed from a HIP graph (value, ms_p50); stages_ms from eager launches "
-                  "with HIP events between stages",
+                  "with HIP events between stages; staged_* = the same frame through the separate "
+                  "emission and sort entry points",
         "wall_ms_per_step_eager": wall_a,
         "stage_hbm": {k: {"achieved_GBs": v, "frac": v / PEAK_HBM_GBS} for k, v in stage_bw.items()},
         "roofline": {"kernel": "k_raster_wave", "bound": "alu", "achieved": achieved,

@@ -127,9 +127,9 @@ typedef struct {
     float *d_sh;
 } gs_scene_grads;
 
-/* Bytes of scratch ("workspace") that gs_emit_pairs and gs_sort need for n
- * Gaussians, pair_capacity pairs and a width x height image.  The same
- * workspace may be reused by consecutive calls on one stream. */
+/* Bytes of scratch ("workspace") that gs_emit_pairs, gs_sort and gs_bin_pairs
+ * need for n Gaussians, pair_capacity pairs and a width x height image.  The
+ * same workspace may be reused by consecutive calls on one stream. */
 size_t gs_workspace_size(int64_t n, int64_t pair_capacity, int width, int height);
 
 /* Stage 1 (Sec. 2.1 preprocessing; Sec. 3.3 AdaGScale preprocessing).
@@ -164,11 +164,34 @@ gs_status gs_emit_pairs(const float *splats, const uint64_t *rects, const uint32
  * order of emission.  Reads min(*num_pairs, pair_capacity) pairs from
  * (pair_tiles, pair_gids), which are left unchanged; writes the sorted tile
  * ids to sorted_tiles and the Gaussian ids to sorted_gids (both distinct from
- * the inputs, pair_capacity entries each), and ranges [num_tiles][2]. */
+ * the inputs, pair_capacity entries each), and ranges [num_tiles][2] as
+ * (start, end), (0, 0) for a tile with no pairs. */
 gs_status gs_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids, const int64_t *num_pairs,
                   int64_t pair_capacity, const gs_camera *cam, uint32_t *sorted_tiles,
                   uint32_t *sorted_gids, uint32_t *ranges, void *ws, size_t ws_bytes,
                   void *stream);
+
+/* Stages 2 and 3 fused (Sec. 2.1 pair generation, sorting and tile ranges;
+ * Sec. 3.3: the rectangles already carry AdaGScale's extent).  Produces the
+ * same per-tile lists as gs_emit_pairs followed by gs_sort -- every tile's
+ * Gaussians in ascending (float32 depth, Gaussian id) order -- without writing
+ * the emission-order pair arrays: the pairs are generated on the fly from the
+ * depth-ordered rectangles and sorted by tile with two 8-bit passes of one
+ * 32-bit word per pair (one pass when the image has at most 256 tiles; with
+ * more than 65536 tiles or n >= 2^24 it emits and sorts pairs internally).
+ * The ranges come from per-tile counts of the rectangles.
+ * Out: sorted_gids [pair_capacity]; sorted_tiles [pair_capacity] or NULL when
+ * not wanted; ranges [num_tiles][2] as (start, end), (0, 0) for a tile with no
+ * pairs, as gs_sort writes them; num_pairs (device int64)
+ * receives the number of pairs REQUIRED.  When *num_pairs > pair_capacity
+ * nothing is binned: every range is empty and the caller must grow the
+ * buffers and run the frame again.
+ * ws: workspace of at least gs_workspace_size(n, pair_capacity, W, H) bytes for
+ * this camera's W x H. */
+gs_status gs_bin_pairs(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
+                       int64_t n, const gs_camera *cam, uint32_t *sorted_gids,
+                       uint32_t *sorted_tiles, uint32_t *ranges, int64_t pair_capacity,
+                       int64_t *num_pairs, void *ws, size_t ws_bytes, void *stream);
 
 /* Stage 4 (Sec. 2.1 rasterization, eq. 1-2; dual size, Sec. 3.3).  Per 16x16
  * tile, front to back over its sorted list: alpha = min(0.99, opacity *

@@ -109,8 +109,9 @@ __global__ void k_set_count(int64_t *p, int64_t v) { *p = v; }
 
 namespace gsr {
 // Sort region (depends on the pair capacity only) first, then the emit region.
-bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws) {
-    if (n < 0 || cap < 0) return false;
+bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws, int tx, int ty) {
+    if (n < 0 || cap < 0 || tx < 0 || ty < 0) return false;
+    memset(ws, 0, sizeof *ws);
     size_t off = 0;
     char *b = static_cast<char *>(base);
     auto take = [&](size_t bytes) -> char * {
@@ -119,13 +120,19 @@ bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws) {
         off += bytes;
         return p;
     };
+    const bool bin = tx > 0 && ty > 0;
+    const int64_t ntiles = (int64_t)tx * ty;
+    ws->tiles_x = tx;
+    ws->tiles_y = ty;
     ws->nb_psort = cap > 0 ? (cap + kSortChunk - 1) / kSortChunk : 1;
     ws->nb_gauss = n > 0 ? (n + 255) / 256 : 1;
     ws->nb_dsort = n > 0 ? (n + kSortChunk - 1) / kSortChunk : 1;
     const int64_t parts_sort = (256 * ws->nb_psort + kScanChunk - 1) / kScanChunk + 1;
     const int64_t parts_emit = (256 * ws->nb_dsort + kScanChunk - 1) / kScanChunk +
                                (n + kScanChunk - 1) / kScanChunk + 1;
+    const int64_t parts_bin = (ntiles + kScanChunk - 1) / kScanChunk + 1;
     ws->max_parts = parts_sort > parts_emit ? parts_sort : parts_emit;
+    if (parts_bin > ws->max_parts) ws->max_parts = parts_bin;
     // sort region
     ws->ptile_tmp = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
     ws->pgid_tmp = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
@@ -138,13 +145,28 @@ bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws) {
     ws->vis_off = (uint32_t *)take(sizeof(uint32_t) * (size_t)ws->nb_gauss);
     ws->pair_cnt = (uint64_t *)take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     ws->pair_off = (uint64_t *)take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
-    ws->slice_start = (uint32_t *)take(sizeof(uint32_t) * (size_t)(cap / emit_chunk() + 2));
+    ws->slice_start = (uint32_t *)take(sizeof(uint32_t) * (size_t)(cap / kEmitChunk + 2));
     for (int i = 0; i < 3; ++i) {
         ws->dkey[i] = (uint32_t *)take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
         ws->dval[i] = (uint32_t *)take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
     }
     ws->dhist = (uint32_t *)take(sizeof(uint32_t) * 256 * (size_t)ws->nb_dsort);
-    ws->bytes = n > 0 ? align256(off) : sort_bytes;
+    const size_t emit_bytes = align256(off);
+    if (!bin) {
+        ws->bytes = n > 0 ? emit_bytes : sort_bytes;
+        return true;
+    }
+    // binning region
+    ws->bpacked = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
+    ws->bhist = (uint32_t *)take(sizeof(uint32_t) * 256 * (size_t)ws->nb_psort);
+    ws->tdiff = (int32_t *)take(sizeof(int32_t) * (size_t)(tx + 1) * (size_t)(ty + 1));
+    ws->tcount = (uint32_t *)take(sizeof(uint32_t) * (size_t)ntiles);
+    ws->toff = (uint32_t *)take(sizeof(uint32_t) * (size_t)ntiles);
+    if (!bin_packed(n, tx, ty)) {
+        ws->bkey = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
+        ws->bval = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
+    }
+    ws->bytes = align256(off);
     return true;
 }
 }  // namespace gsr
@@ -169,10 +191,12 @@ const char *gs_last_error(void) { return g_last_error.c_str(); }
 const char *gs_version(void) { return "gsr 0.1 gfx950"; }
 
 size_t gs_workspace_size(int64_t n, int64_t pair_capacity, int width, int height) {
-    (void)width;
-    (void)height;
     Workspace ws;
-    if (!workspace_layout(n, pair_capacity, nullptr, &ws)) return 0;
+    const bool img = width >= 1 && height >= 1 && width <= GS_MAX_IMAGE_SIDE &&
+                     height <= GS_MAX_IMAGE_SIDE;
+    const int tx = img ? (width + GS_TILE - 1) / GS_TILE : 0;
+    const int ty = img ? (height + GS_TILE - 1) / GS_TILE : 0;
+    if (!workspace_layout(n, pair_capacity, nullptr, &ws, tx, ty)) return 0;
     return ws.bytes;
 }
 
@@ -249,6 +273,31 @@ gs_status gs_emit_pairs(const float *splats, const uint64_t *rects, const uint32
     return hip_check(launch_emit(splats, rects, tiles_touched, (int)n, tiles_x(cam), pair_tiles,
                                  pair_gids, pair_capacity, num_pairs, w, (hipStream_t)stream),
                      "gs_emit_pairs");
+}
+
+gs_status gs_bin_pairs(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
+                       int64_t n, const gs_camera *cam, uint32_t *sorted_gids,
+                       uint32_t *sorted_tiles, uint32_t *ranges, int64_t pair_capacity,
+                       int64_t *num_pairs, void *ws, size_t ws_bytes, void *stream) {
+    gs_status st;
+    if ((st = check_camera(cam)) != GS_OK) return st;
+    if (n < 0 || n >= ((int64_t)1 << 31))
+        return fail(GS_ERR_INVALID_ARGUMENT, "n = %lld outside [0, 2^31)", (long long)n);
+    if (pair_capacity < 0 || pair_capacity > (int64_t)0xffffffffLL)
+        return fail(GS_ERR_INVALID_ARGUMENT, "pair_capacity outside [0, 2^32)");
+    if (!num_pairs || !ranges) return fail(GS_ERR_INVALID_ARGUMENT, "num_pairs or ranges is NULL");
+    if (n > 0 && (!splats || !rects || !tiles_touched))
+        return fail(GS_ERR_INVALID_ARGUMENT, "input array is NULL");
+    if (pair_capacity > 0 && !sorted_gids)
+        return fail(GS_ERR_INVALID_ARGUMENT, "sorted_gids is NULL");
+    Workspace w;
+    workspace_layout(n, pair_capacity, ws, &w, tiles_x(cam), tiles_y(cam));
+    if (!ws || ws_bytes < w.bytes)
+        return fail(GS_ERR_CAPACITY, "workspace of %zu bytes, %zu needed", ws_bytes, w.bytes);
+    return hip_check(launch_bin(splats, rects, tiles_touched, (int)n, tiles_x(cam), tiles_y(cam),
+                                sorted_gids, sorted_tiles, ranges, pair_capacity, num_pairs, w,
+                                (hipStream_t)stream),
+                     "gs_bin_pairs");
 }
 
 gs_status gs_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids, const int64_t *num_pairs,

@@ -61,7 +61,6 @@ __global__ __launch_bounds__(256) void k_pair_counts(const uint32_t *sorted_ids,
 // so a few huge Gaussians cannot serialise one block.  bstart[b] = the sorted
 // Gaussian that owns pair b * kEmitChunk (each Gaussian marks the slices that
 // begin inside its pair range).
-constexpr int kEmitChunk = 4096;
 
 __global__ __launch_bounds__(256) void k_slice_starts(const uint64_t *off, const uint64_t *cnt,
                                                       const int64_t *num_vis, uint32_t *bstart,
@@ -129,13 +128,14 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *sorted_ids, const 
     }
 }
 
-hipError_t launch_emit(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
-                       int n, int tiles_x, uint32_t *pair_tiles, uint32_t *pair_gids, int64_t cap,
-                       int64_t *num_pairs, const Workspace &ws, hipStream_t s) {
+hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
+                               const uint32_t *tiles_touched, int n, int64_t cap, int64_t *num_pairs,
+                               const Workspace &ws, hipStream_t s) {
     const int64_t nb = ws.nb_gauss;
     int64_t *num_vis = ws.counters;
     if (n == 0) {
         k_set_i64<<<1, 1, 0, s>>>(num_pairs, 0);
+        k_set_i64<<<1, 1, 0, s>>>(num_vis, 0);
         return hipGetLastError();
     }
     k_vis_count<<<(unsigned)nb, 256, 0, s>>>(tiles_touched, n, ws.vis_count);
@@ -151,13 +151,28 @@ hipError_t launch_emit(const float *splats, const uint64_t *rects, const uint32_
     e = scan_exclusive_u64(ws.pair_cnt, ws.pair_off, n, ws.scan_part, num_pairs, s,
                            DevExtent{num_vis, n, 1, 1});
     if (e != hipSuccess) return e;
-    if (cap > 0) {
-        k_slice_starts<<<(unsigned)nb, 256, 0, s>>>(ws.pair_off, ws.pair_cnt, num_vis, ws.slice_start, n, cap);
-        k_emit<<<(unsigned)((cap + kEmitChunk - 1) / kEmitChunk), 256, 0, s>>>(
-            ws.dval[1], num_vis, rects, ws.pair_off, ws.slice_start, num_pairs, tiles_x, pair_tiles,
-            pair_gids, cap);
-    }
+    if (cap > 0)
+        k_slice_starts<<<(unsigned)nb, 256, 0, s>>>(ws.pair_off, ws.pair_cnt, num_vis, ws.slice_start,
+                                                   n, cap);
     return hipGetLastError();
+}
+
+hipError_t launch_emit_pairs(const uint64_t *rects, int tiles_x, uint32_t *pair_tiles,
+                             uint32_t *pair_gids, int64_t cap, const int64_t *num_pairs,
+                             const Workspace &ws, hipStream_t s) {
+    if (cap > 0)
+        k_emit<<<(unsigned)((cap + kEmitChunk - 1) / kEmitChunk), 256, 0, s>>>(
+            ws.dval[1], ws.counters, rects, ws.pair_off, ws.slice_start, num_pairs, tiles_x,
+            pair_tiles, pair_gids, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
+                       int n, int tiles_x, uint32_t *pair_tiles, uint32_t *pair_gids, int64_t cap,
+                       int64_t *num_pairs, const Workspace &ws, hipStream_t s) {
+    hipError_t e = launch_emit_prepare(splats, rects, tiles_touched, n, cap, num_pairs, ws, s);
+    if (e != hipSuccess || n == 0) return e;
+    return launch_emit_pairs(rects, tiles_x, pair_tiles, pair_gids, cap, num_pairs, ws, s);
 }
 
 int emit_chunk() { return kEmitChunk; }

@@ -43,13 +43,25 @@ struct Workspace {
     uint32_t *ptile_tmp;   // [cap]
     uint32_t *pgid_tmp;    // [cap]
     uint32_t *phist;       // [256][nb_psort]
+    // fused binning (bin.hip)
+    uint32_t *bpacked;     // [cap] pass-1 output: tile >> 8 in bits 24..31, depth rank below
+    uint32_t *bhist;       // [256][nb_psort] pass-1 histogram / offsets
+    int32_t *tdiff;        // [(tiles_y + 1) * (tiles_x + 1)] rectangle corner differences
+    uint32_t *tcount;      // [tiles] pairs per tile
+    uint32_t *toff;        // [tiles] their exclusive prefix
+    uint32_t *bkey, *bval; // [cap] each, only when the packed path does not apply
     // device-wide scan partials (large enough for any scan above)
     uint64_t *scan_part;   // [max_parts]
     int64_t *counters;     // [0] visible Gaussians, [1] scratch
     int64_t nb_gauss, nb_dsort, nb_psort, max_parts;
+    int tiles_x, tiles_y;
     size_t bytes;
 };
-bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws);
+// tiles_x = tiles_y = 0 leaves out the binning buffers (emit and sort alone).
+bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws, int tiles_x = 0,
+                      int tiles_y = 0);
+// whether launch_bin takes the packed two-pass route for this problem
+bool bin_packed(int64_t n, int tiles_x, int tiles_y);
 int emit_chunk();
 
 // ------------------------------------------------------------ sort constants
@@ -59,6 +71,9 @@ constexpr int kSortThreads = 256;
 #endif
 constexpr int kSortItems = GSR_SORT_ITEMS;                // per thread
 constexpr int kSortChunk = kSortThreads * kSortItems;     // 4096 items per block
+// pairs per emission slice (one workgroup each); slice_start[b] is the
+// depth-sorted Gaussian that owns pair b * kEmitChunk
+constexpr int kEmitChunk = 4096;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanChunk = kScanThreads * kScanItems;     // 4096 elements per block
@@ -69,13 +84,22 @@ hipError_t launch_preprocess(const PreprocessArgs &a, hipStream_t s);
 // Number of live elements of a device-wide pass whose launch was sized on the
 // host for the capacity m: with `count` set, mul * ceil(min(*count, cap) / chunk)
 // (at most m), read on the device so no host round trip is needed.
+// A count read on the device, clamped to the capacity cap that launches were
+// sized for; with empty_if_over, a count above cap counts as zero (a pass that
+// must not run on a partial set).
+__device__ __forceinline__ int64_t live_count(const int64_t *count, int64_t cap, int empty_if_over) {
+    const int64_t c = *count;
+    if (c > cap) return empty_if_over ? 0 : cap;
+    return c < 0 ? 0 : c;
+}
+
 struct DevExtent {
     const int64_t *count = nullptr;
     int64_t cap = 0, chunk = 1, mul = 1;
+    bool empty_if_over = false;
     __device__ __forceinline__ int64_t resolve(int64_t m) const {
         if (!count) return m;
-        int64_t c = *count;
-        c = c < 0 ? 0 : (c > cap ? cap : c);
+        const int64_t c = live_count(count, cap, empty_if_over);
         const int64_t e = ((c + chunk - 1) / chunk) * mul;
         return e < m ? e : m;
     }
@@ -88,19 +112,43 @@ hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t m, uint
 hipError_t scan_exclusive_u64(const uint64_t *in, uint64_t *out, int64_t m, uint64_t *parts,
                               int64_t *total, hipStream_t s, DevExtent ext = DevExtent{});
 
-// stable LSD radix sort of (key, val) pairs, count in device memory (clamped
-// to cap); bits = number of significant key bits.  Reads (kin, vin), leaves
-// them unchanged, and puts the result in (kout, vout); (ktmp, vtmp) is pass
-// scratch distinct from both.  kout may be null when only values are needed
-// and the sort has one pass.
+// stable LSD radix sort of (key, val) pairs by key bits [first_bit, bits),
+// count in device memory (clamped to cap, or taken as zero when above cap with
+// empty_if_over).  Reads (kin, vin), leaves them unchanged, and puts the result
+// in (kout, vout); (ktmp, vtmp) is pass scratch distinct from both.  kout may
+// be null when only values are needed and the sort has one pass.
 hipError_t radix_sort_u32(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
                           uint32_t *ktmp, uint32_t *vtmp, const int64_t *count, int64_t cap,
                           int bits, uint32_t *hist, int64_t nblocks, uint64_t *parts,
-                          hipStream_t s);
+                          hipStream_t s, int first_bit = 0, int empty_if_over = 0);
+// One pass of it: digit (key >> shift) & 255; and its histogram + scan alone
+// (hist then holds each (digit, live block) output offset, digit-major).
+void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+                const int64_t *count, int64_t cap, int shift, uint32_t *hist, int64_t nblocks,
+                uint64_t *parts, hipStream_t s, int empty_if_over);
+void radix_hist(const uint32_t *keys, const int64_t *count, int64_t cap, int shift, uint32_t *hist,
+                int64_t nblocks, uint64_t *parts, hipStream_t s, int empty_if_over);
 
 hipError_t launch_emit(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
                        int n, int tiles_x, uint32_t *pair_tiles, uint32_t *pair_gids, int64_t cap,
                        int64_t *num_pairs, const Workspace &ws, hipStream_t s);
+// Everything of launch_emit before the pairs are written: visible Gaussians in
+// depth order (ws.dval[1], count in ws.counters[0]), their pair counts and
+// offsets (ws.pair_cnt, ws.pair_off), the pair total, and the emission slice
+// owners (ws.slice_start, when cap > 0).
+hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
+                               const uint32_t *tiles_touched, int n, int64_t cap, int64_t *num_pairs,
+                               const Workspace &ws, hipStream_t s);
+// The pair-writing part of launch_emit, after launch_emit_prepare.
+hipError_t launch_emit_pairs(const uint64_t *rects, int tiles_x, uint32_t *pair_tiles,
+                             uint32_t *pair_gids, int64_t cap, const int64_t *num_pairs,
+                             const Workspace &ws, hipStream_t s);
+// Emission and tile sort fused (bin.hip): the sorted ids, optionally the sorted
+// tile ids, and the ranges, without the emission-order pair arrays.
+hipError_t launch_bin(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
+                      int n, int tiles_x, int tiles_y, uint32_t *sorted_gids, uint32_t *sorted_tiles,
+                      uint32_t *ranges, int64_t cap, int64_t *num_pairs, const Workspace &ws,
+                      hipStream_t s);
 
 hipError_t launch_tile_ranges(const uint32_t *sorted_tiles, const int64_t *num_pairs, int64_t cap,
                               uint32_t *ranges, int num_tiles, hipStream_t s);

@@ -1,0 +1,99 @@
+// Stable block-level ranking by one 8-bit digit, shared by the radix sort's
+// scatter and by the fused binning passes.
+//
+// A block of kSortThreads threads holds kSortChunk items in registers,
+// assigned wave-striped -- wave w owns chunk positions [w*kPerWave,
+// (w+1)*kPerWave) and in step i lane l holds position w*kPerWave + i*64 + l --
+// so lane order, then step order, then wave order is the input order.  Each
+// wave ranks its items with eight ballots per step (the lanes sharing the
+// digit) and a running per-digit count in LDS; per-digit wave prefixes and a
+// block scan then order the waves.  The ranked chunk is staged in LDS in
+// (digit, input) order and handed to the caller's writer by consecutive
+// threads, so each digit's run leaves the block as contiguous stores.
+#pragma once
+#include "gsr_internal.hpp"
+
+namespace gsr {
+
+constexpr int kRankWaves = kSortThreads / kWave;
+constexpr int kRankPerWave = kSortChunk / kRankWaves;
+
+struct RankSmem {
+    uint32_t wcnt[kRankWaves][256];  // per-wave running digit counts, then wave prefixes
+    uint32_t gbase[256];             // global output start of each digit for this block
+    uint32_t dstart[256];            // block-local start of each digit
+    uint32_t wt[kRankWaves];
+};
+
+// Zero the per-wave counts; the caller then fills gbase and issues a barrier.
+__device__ __forceinline__ void rank_init(RankSmem &sm) {
+    for (int i = threadIdx.x; i < kRankWaves * 256; i += kSortThreads) (&sm.wcnt[0][0])[i] = 0;
+}
+
+// Chunk position of item i of this thread.
+__device__ __forceinline__ int rank_pos(int i) {
+    return (threadIdx.x / kWave) * kRankPerWave + i * kWave + (threadIdx.x & (kWave - 1));
+}
+
+// Ranks the block's items by digit (key >> shift) & 255 and calls
+// write(dst, key, val) once per valid item, where dst = gbase[digit] + the
+// item's stable rank within its digit.  Items at positions >= cnt are invalid.
+// skey / sval: kSortChunk-entry LDS staging arrays, which may alias memory the
+// caller no longer reads (item generation must be complete).  Contains barriers;
+// the caller must have run rank_init, set gbase and issued a barrier.
+template <class Write>
+__device__ __forceinline__ void rank_stage_write(const uint32_t (&key)[kSortItems],
+                                                 const uint32_t (&val)[kSortItems], int cnt,
+                                                 int shift, RankSmem &sm, uint32_t *skey,
+                                                 uint32_t *sval, Write write) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    uint32_t rank[kSortItems];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const bool valid = rank_pos(i) < cnt;
+        const uint32_t d = (key[i] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t before = sm.wcnt[wid][d];
+        rank[i] = before + (uint32_t)__popcll(peers & lt);
+        // the highest lane of each digit group advances the running count
+        if (valid && (peers >> lane) == 1ull) sm.wcnt[wid][d] = before + (uint32_t)__popcll(peers);
+        if (!valid) rank[i] = 0xffffffffu;
+    }
+    __syncthreads();
+    uint32_t tot_d = 0;
+    {   // exclusive prefix over waves per digit; thread t owns digit t
+        const int d = threadIdx.x;
+#pragma unroll
+        for (int w = 0; w < kRankWaves; ++w) {
+            const uint32_t c = sm.wcnt[w][d];
+            sm.wcnt[w][d] = tot_d;
+            tot_d += c;
+        }
+    }
+    uint32_t all;
+    sm.dstart[threadIdx.x] = block_exclusive_scan<kSortThreads, uint32_t>(tot_d, sm.wt, &all);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        if (rank[i] == 0xffffffffu) continue;
+        const uint32_t d = (key[i] >> shift) & 255u;
+        const uint32_t p = sm.dstart[d] + sm.wcnt[wid][d] + rank[i];
+        skey[p] = key[i];
+        sval[p] = val[i];
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < cnt; p += kSortThreads) {
+        const uint32_t k = skey[p];
+        const uint32_t d = (k >> shift) & 255u;
+        write((int64_t)sm.gbase[d] + (p - (int)sm.dstart[d]), k, sval[p]);
+    }
+}
+
+}  // namespace gsr

@@ -13,6 +13,7 @@
 // Counts live in device memory (read by every kernel and clamped to the
 // capacity the grid was sized for), so no stage needs a host round trip.
 #include "gsr_internal.hpp"
+#include "radix_rank.hpp"
 
 namespace gsr {
 
@@ -99,19 +100,16 @@ hipError_t scan_exclusive_u64(const uint64_t *in, uint64_t *out, int64_t m, uint
 }
 
 // ------------------------------------------------------------------ radix sort
-__device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t cap) {
-    const int64_t c = *count;
-    return c < cap ? (c < 0 ? 0 : c) : cap;
-}
+
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *keys, const int64_t *count,
                                                              int64_t cap, int shift, uint32_t *hist,
-                                                             int64_t nblocks) {
+                                                             int64_t nblocks, int empty_if_over) {
     __shared__ uint32_t h[kSortThreads / kWave][256];
     const int wid = threadIdx.x / kWave;
     for (int i = threadIdx.x; i < (kSortThreads / kWave) * 256; i += kSortThreads) (&h[0][0])[i] = 0;
     __syncthreads();
-    const int64_t n = clamp_count(count, cap);
+    const int64_t n = live_count(count, cap, empty_if_over);
     const int64_t base = (int64_t)blockIdx.x * kSortChunk;
     if (base >= n) return;  // idle block (uniform): holds no items, owns no histogram column
     const int64_t nb_live = (n + kSortChunk - 1) / kSortChunk;
@@ -140,108 +138,68 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *key
     hist[(int64_t)d * nb_live + blockIdx.x] = tot;
 }
 
-// Ranking: items of the chunk are assigned wave-striped -- wave w owns
-// positions [w*1024, (w+1)*1024) of the chunk and in step i lane l holds
-// position w*1024 + i*64 + l -- so lane order, then step order, then wave
-// order is the input order, which makes the ranking stable.  The ranked chunk
-// is staged in LDS in (digit, input) order and written out by consecutive
-// threads, so each digit's run leaves the block as contiguous stores.
+// Scatter: re-reads the block's keys, ranks them stably by the digit and
+// writes each digit's run contiguously (radix_rank.hpp).
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const int64_t *count,
-    int64_t cap, int shift, const uint32_t *offs, int64_t nblocks) {
-    constexpr int kWaves = kSortThreads / kWave;
-    constexpr int kPerWave = kSortChunk / kWaves;
-    __shared__ uint32_t wcnt[kWaves][256];
-    __shared__ uint32_t gbase[256];
-    __shared__ uint32_t dstart[256];
-    __shared__ uint32_t wt[kWaves];
+    int64_t cap, int shift, const uint32_t *offs, int64_t nblocks, int empty_if_over) {
+    __shared__ RankSmem sm;
     __shared__ uint32_t skey[kSortChunk];
     __shared__ uint32_t sval[kSortChunk];
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    for (int i = threadIdx.x; i < kWaves * 256; i += kSortThreads) (&wcnt[0][0])[i] = 0;
-    const int64_t n = clamp_count(count, cap);
+    rank_init(sm);
+    const int64_t n = live_count(count, cap, empty_if_over);
     const int64_t base = (int64_t)blockIdx.x * kSortChunk;
     if (base >= n) return;  // whole block idle (uniform across the block)
     const int64_t nb_live = (n + kSortChunk - 1) / kSortChunk;
-    gbase[threadIdx.x] = offs[(int64_t)threadIdx.x * nb_live + blockIdx.x];
-    __syncthreads();
-
-    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
-    const uint64_t lt = lanemask_lt();
-#pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-        const int64_t idx = base + (int64_t)wid * kPerWave + (int64_t)i * kWave + lane;
-        const bool valid = idx < n;
-        key[i] = valid ? kin[idx] : 0u;
-        val[i] = valid ? vin[idx] : 0u;
-        const uint32_t d = (key[i] >> shift) & 255u;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        const uint32_t before = wcnt[wid][d];
-        rank[i] = before + (uint32_t)__popcll(peers & lt);
-        // the highest lane of each digit group advances the running count
-        if (valid && (peers >> lane) == 1ull) wcnt[wid][d] = before + (uint32_t)__popcll(peers);
-        if (!valid) rank[i] = 0xffffffffu;
-    }
-    __syncthreads();
-    uint32_t tot_d = 0;
-    {   // exclusive prefix over waves per digit; thread t owns digit t
-        const int d = threadIdx.x;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-            const uint32_t c = wcnt[w][d];
-            wcnt[w][d] = tot_d;
-            tot_d += c;
-        }
-    }
-    uint32_t all;
-    dstart[threadIdx.x] = block_exclusive_scan<kSortThreads, uint32_t>(tot_d, wt, &all);
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-        if (rank[i] == 0xffffffffu) continue;
-        const uint32_t d = (key[i] >> shift) & 255u;
-        const uint32_t p = dstart[d] + wcnt[wid][d] + rank[i];
-        skey[p] = key[i];
-        sval[p] = val[i];
-    }
+    sm.gbase[threadIdx.x] = offs[(int64_t)threadIdx.x * nb_live + blockIdx.x];
     __syncthreads();
     const int cnt = (int)(n - base < kSortChunk ? n - base : kSortChunk);
-    for (int p = threadIdx.x; p < cnt; p += kSortThreads) {
-        const uint32_t k = skey[p];
-        const uint32_t d = (k >> shift) & 255u;
-        const int64_t dst = (int64_t)gbase[d] + (p - (int)dstart[d]);
-        if (kout) kout[dst] = k;
-        vout[dst] = sval[p];
+    uint32_t key[kSortItems], val[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int p = rank_pos(i);
+        key[i] = p < cnt ? kin[base + p] : 0u;
+        val[i] = p < cnt ? vin[base + p] : 0u;
     }
+    rank_stage_write(key, val, cnt, shift, sm, skey, sval, [&](int64_t dst, uint32_t k, uint32_t v) {
+        if (kout) kout[dst] = k;
+        vout[dst] = v;
+    });
 }
 
 hipError_t radix_sort_u32(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
                           uint32_t *ktmp, uint32_t *vtmp, const int64_t *count, int64_t cap,
                           int bits, uint32_t *hist, int64_t nblocks, uint64_t *parts,
-                          hipStream_t s) {
-    const int passes = bits <= 0 ? 1 : (bits + 7) / 8;
+                          hipStream_t s, int first_bit, int empty_if_over) {
+    const int passes = bits <= first_bit ? 1 : (bits - first_bit + 7) / 8;
     // choose buffers so the last pass lands in (kout, vout)
     const uint32_t *srck = kin, *srcv = vin;
     for (int p = 0; p < passes; ++p) {
         const bool to_out = ((passes - 1 - p) % 2) == 0;
         uint32_t *dk = to_out ? kout : ktmp, *dv = to_out ? vout : vtmp;
-        k_radix_hist<<<(unsigned)nblocks, kSortThreads, 0, s>>>(srck, count, cap, 8 * p, hist, nblocks);
-        // histogram columns exist for live blocks only: 256 x ceil(count / chunk)
-        hipError_t e = scan_exclusive_u32(hist, hist, 256 * nblocks, parts, nullptr, s,
-                                          DevExtent{count, cap, kSortChunk, 256});
-        if (e != hipSuccess) return e;
-        k_radix_scatter<<<(unsigned)nblocks, kSortThreads, 0, s>>>(srck, srcv, dk, dv, count, cap,
-                                                                    8 * p, hist, nblocks);
+        const int shift = first_bit + 8 * p;
+        radix_pass(srck, srcv, dk, dv, count, cap, shift, hist, nblocks, parts, s, empty_if_over);
         srck = dk;
         srcv = dv;
     }
     return hipGetLastError();
+}
+
+void radix_hist(const uint32_t *keys, const int64_t *count, int64_t cap, int shift, uint32_t *hist,
+                int64_t nblocks, uint64_t *parts, hipStream_t s, int empty_if_over) {
+    k_radix_hist<<<(unsigned)nblocks, kSortThreads, 0, s>>>(keys, count, cap, shift, hist, nblocks,
+                                                            empty_if_over);
+    // histogram columns exist for live blocks only: 256 x ceil(count / chunk)
+    scan_exclusive_u32(hist, hist, 256 * nblocks, parts, nullptr, s,
+                       DevExtent{count, cap, kSortChunk, 256, empty_if_over != 0});
+}
+
+void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+                const int64_t *count, int64_t cap, int shift, uint32_t *hist, int64_t nblocks,
+                uint64_t *parts, hipStream_t s, int empty_if_over) {
+    radix_hist(kin, count, cap, shift, hist, nblocks, parts, s, empty_if_over);
+    k_radix_scatter<<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, count, cap,
+                                                                shift, hist, nblocks, empty_if_over);
 }
 
 // ------------------------------------------------------------- tile ranges
@@ -254,7 +212,7 @@ __global__ void k_fill_u32(uint32_t *p, int64_t m, uint32_t v) {
 // per thread (one 16-byte load plus the item before).
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *tiles, const int64_t *count,
                                                      int64_t cap, uint32_t *ranges) {
-    const int64_t n = clamp_count(count, cap);
+    const int64_t n = live_count(count, cap, 0);
     const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
     if (i0 >= n) return;
     uint32_t t[5];

@@ -19,7 +19,8 @@ GS_OK, GS_ERR_INVALID_ARGUMENT, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED 
 LUT_BINS = 20
 TILE = 16
 
-EXPORTS = ("gs_workspace_size", "gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_rasterize",
+EXPORTS = ("gs_workspace_size", "gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_bin_pairs",
+           "gs_rasterize",
            "gs_rasterize_backward", "gs_preprocess_backward", "gs_views_workspace_size",
            "gs_rasterize_views", "gs_wall_clock_khz", "gs_status_string", "gs_last_error",
            "gs_version")
@@ -74,11 +75,12 @@ def load():
     L.gs_preprocess.argtypes = [P, P, P, P, P, P, P]
     L.gs_emit_pairs.argtypes = [P, P, P, I64, P, P, P, I64, P, P, C.c_size_t, P]
     L.gs_sort.argtypes = [P, P, P, I64, P, P, P, P, P, C.c_size_t, P]
+    L.gs_bin_pairs.argtypes = [P, P, P, I64, P, P, P, P, I64, P, P, C.c_size_t, P]
     L.gs_rasterize.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P]
     L.gs_rasterize_backward.argtypes = [P, I64, P, P, P, P, P, P, P, P, P]
     L.gs_preprocess_backward.argtypes = [P, P, P, P, P, P]
-    for f in ("gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_rasterize", "gs_rasterize_backward",
-              "gs_preprocess_backward"):
+    for f in ("gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_bin_pairs", "gs_rasterize",
+              "gs_rasterize_backward", "gs_preprocess_backward"):
         getattr(L, f).restype = C.c_int
     L.gs_status_string.argtypes = [I]
     L.gs_status_string.restype = C.c_char_p
@@ -170,6 +172,16 @@ def gs_sort(pair_tiles, pair_gids, num_pairs, pair_capacity, cam: GsCamera, sort
                           C.byref(cam), _ptr(sorted_tiles), _ptr(sorted_gids), _ptr(ranges),
                           _ptr(ws), int(ws.numel() * ws.element_size()) if ws is not None else 0,
                           _stream(stream)))
+
+
+def gs_bin_pairs(splats, rects, tiles_touched, n, cam: GsCamera, sorted_gids, sorted_tiles, ranges,
+                 pair_capacity, num_pairs, ws, stream=None):
+    """sorted_tiles may be None (not written)."""
+    _check(load().gs_bin_pairs(_ptr(splats), _ptr(rects), _ptr(tiles_touched), int(n),
+                               C.byref(cam), _ptr(sorted_gids), _ptr(sorted_tiles), _ptr(ranges),
+                               int(pair_capacity), _ptr(num_pairs), _ptr(ws),
+                               int(ws.numel() * ws.element_size()) if ws is not None else 0,
+                               _stream(stream)))
 
 
 def gs_rasterize(splats, n, sorted_gids, ranges, cam: GsCamera, bg, cfg, image, final_T,

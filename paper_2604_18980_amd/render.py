@@ -90,34 +90,58 @@ def run_sort(fb: FrameBuffers, cam_s, stream=None):
                 fb.sorted_gids, fb.ranges, fb.ws, stream)
 
 
+def run_bin(fb: FrameBuffers, cam_s, stream=None, with_tiles=False):
+    """Emission + sort + ranges in one call (gs_bin_pairs); pair_tiles and
+    pair_gids are not written, sorted_tiles only with with_tiles."""
+    gsr.gs_bin_pairs(fb.splats, fb.rects, fb.tiles_touched, fb.n, cam_s, fb.sorted_gids,
+                     fb.sorted_tiles if with_tiles else None, fb.ranges, fb.capacity,
+                     fb.num_pairs, fb.ws, stream)
+
+
 def run_raster(fb: FrameBuffers, cam_s, bg, stream=None, cfg=None, n_evaluated=None):
     gsr.gs_rasterize(fb.splats, fb.n, fb.sorted_gids, fb.ranges, cam_s, bg, cfg, fb.image,
                      fb.final_T, fb.n_contrib, n_evaluated, stream)
 
 
 def enqueue_frame(scene: DeviceScene, cam_s, mode_s, fb: FrameBuffers, bg=(0.0, 0.0, 0.0),
-                  stream=None, cfg=None):
-    """Enqueue one whole frame on the stream; no host synchronisation."""
+                  stream=None, cfg=None, staged=False):
+    """Enqueue one whole frame on the stream; no host synchronisation.  The
+    default path bins the pairs with gs_bin_pairs; staged=True runs the
+    separate emission and sort entry points instead (same lists)."""
     run_preprocess(scene, cam_s, mode_s, fb, stream)
-    run_emit(fb, cam_s, stream)
-    run_sort(fb, cam_s, stream)
+    if staged:
+        run_emit(fb, cam_s, stream)
+        run_sort(fb, cam_s, stream)
+    else:
+        run_bin(fb, cam_s, stream)
     run_raster(fb, cam_s, bg, stream, cfg)
 
 
 def render(scene: DeviceScene, cam, adagscale=False, K=0.0, t_upper=None, lut_depth_max=100.0,
-           force_unit_scale=False, bg=(0.0, 0.0, 0.0), fb: FrameBuffers = None, slack=1.0):
+           force_unit_scale=False, bg=(0.0, 0.0, 0.0), fb: FrameBuffers = None, slack=1.0,
+           staged=False, with_tiles=False):
     """Render one frame.  Sizes the pair buffers from a counting pass (one host
-    read of the pair count) unless ``fb`` already has enough capacity."""
+    read of the pair count) unless ``fb`` already has enough capacity.
+    staged=True uses gs_emit_pairs + gs_sort (emission-order pairs kept in
+    fb.pair_tiles / fb.pair_gids); otherwise gs_bin_pairs, which also writes
+    fb.sorted_tiles when with_tiles."""
     cam_s = gsr.camera_struct(cam)
     mode_s = gsr.mode_struct(adagscale, K, t_upper, lut_depth_max, force_unit_scale)
     if fb is None:
         fb = FrameBuffers(scene.n, cam["width"], cam["height"], 0, scene.means.device)
     run_preprocess(scene, cam_s, mode_s, fb)
-    run_emit(fb, cam_s)
-    need = int(fb.num_pairs.item())
-    if need > fb.capacity:
-        fb.set_capacity(int(need * slack))
+    if staged:
         run_emit(fb, cam_s)
-    run_sort(fb, cam_s)
+        need = int(fb.num_pairs.item())
+        if need > fb.capacity:
+            fb.set_capacity(int(need * slack))
+            run_emit(fb, cam_s)
+        run_sort(fb, cam_s)
+    else:
+        run_bin(fb, cam_s, with_tiles=with_tiles)
+        need = int(fb.num_pairs.item())
+        if need > fb.capacity:
+            fb.set_capacity(int(need * slack))
+            run_bin(fb, cam_s, with_tiles=with_tiles)
     run_raster(fb, cam_s, bg)
     return fb

@@ -1,4 +1,4 @@
-"""Many views of one scene per frame: per-view preprocess, emission and sort,
+"""Many views of one scene per frame: per-view preprocess and binning,
 then every view's tiles rasterized by one persistent launch over a
 longest-first (view, tile) queue (gs_rasterize_views).  After one eager frame
 sizes the pair buffers, the whole frame can be captured in a HIP graph and
@@ -26,7 +26,7 @@ class MultiView:
         # size every view's pair buffers from one counting pass
         for fb, cs in zip(self.fbs, self.cam_s):
             R.run_preprocess(scene, cs, self.mode, fb)
-            R.run_emit(fb, cs)
+            R.run_bin(fb, cs)
         torch.cuda.synchronize()
         for fb in self.fbs:
             fb.set_capacity(int(int(fb.num_pairs.item()) * slack) + 256)
@@ -48,8 +48,7 @@ class MultiView:
     def enqueue(self, stream=None):
         for fb, cs in zip(self.fbs, self.cam_s):
             R.run_preprocess(self.scene, cs, self.mode, fb, stream)
-            R.run_emit(fb, cs, stream)
-            R.run_sort(fb, cs, stream)
+            R.run_bin(fb, cs, stream)
         gsr.gs_rasterize_views(self.views, self.d_views, self.n_views, self.bg, self.cfg,
                                self.clock, self.ws, stream)
 

@@ -19,14 +19,17 @@ def decode_rects(r):
     return np.stack([(r >> np.uint64(s)) & np.uint64(0xFFFF) for s in (0, 16, 32, 48)], 1).astype(np.int64)
 
 
-def gpu_frame(scene, cam, mode=None, bg=(0.0, 0.0, 0.0), capacity=None):
-    """Full frame through the C-ABI.  Returns a dict of numpy outputs."""
+def gpu_frame(scene, cam, mode=None, bg=(0.0, 0.0, 0.0), capacity=None, staged=True):
+    """Full frame through the C-ABI.  Returns a dict of numpy outputs.  The
+    staged path (gs_emit_pairs + gs_sort) also yields the emission-order pairs;
+    otherwise gs_bin_pairs runs, with sorted tiles requested, and the
+    emission-order arrays are absent."""
     mode = mode or {}
     ds = R.DeviceScene.from_host(scene)
     fb = None
     if capacity is not None:
         fb = R.FrameBuffers(ds.n, cam["width"], cam["height"], capacity)
-    fb = R.render(ds, cam, bg=bg, fb=fb, **mode)
+    fb = R.render(ds, cam, bg=bg, fb=fb, staged=staged, with_tiles=not staged, **mode)
     torch.cuda.synchronize()
     P = int(fb.num_pairs.item())
     m = min(P, fb.capacity)
@@ -35,8 +38,8 @@ def gpu_frame(scene, cam, mode=None, bg=(0.0, 0.0, 0.0), capacity=None):
         splats=to_np(fb.splats)[: ds.n],
         rects=decode_rects(to_np(fb.rects)[: ds.n]),
         tiles=to_np(fb.tiles_touched)[: ds.n].astype(np.uint32).astype(np.int64),
-        pair_tiles=to_np(fb.pair_tiles)[:m].astype(np.uint32).astype(np.int64),
-        pair_gids=to_np(fb.pair_gids)[:m].astype(np.uint32).astype(np.int64),
+        pair_tiles=to_np(fb.pair_tiles)[:m].astype(np.uint32).astype(np.int64) if staged else None,
+        pair_gids=to_np(fb.pair_gids)[:m].astype(np.uint32).astype(np.int64) if staged else None,
         sorted_tiles=to_np(fb.sorted_tiles)[:m].astype(np.uint32).astype(np.int64),
         sorted_gids=to_np(fb.sorted_gids)[:m].astype(np.uint32).astype(np.int64),
         ranges=to_np(fb.ranges).astype(np.uint32).astype(np.int64),

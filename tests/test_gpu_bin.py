@@ -1,0 +1,103 @@
+"""gs_bin_pairs (emission, tile sort and ranges fused) on every route it
+takes -- one ranking pass (at most 256 tiles), two passes of packed words, and
+the emit-then-sort fallback (more than 65536 tiles) -- against the separate
+gs_emit_pairs + gs_sort entry points (bit for bit) and against the oracle's
+sorted keys and ranges; plus ragged images, empty and culled scenes and the
+overflow contract."""
+import numpy as np
+import pytest
+
+from paper_2604_18980_amd import scenes
+
+from gpu_util import gpu_frame, oracle_mode
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    if name == "tiny128":            # 8 x 8 tiles: one pass
+        sc, cam = scenes.tiny_scene(n=2000, seed=21)
+        return sc, cam, {}
+    if name == "tiny128_ada":
+        sc, cam = scenes.tiny_scene(n=2000, seed=22)
+        return sc, cam, dict(adagscale=True, K=0.1)
+    if name == "ragged_257x129":     # 17 x 9 = 153 tiles: one pass, ragged edges
+        sc, cam = scenes.tiny_scene(n=3000, seed=23)
+        return sc, dict(cam, width=257, height=129, cx=128.0, cy=64.0), {}
+    if name == "ragged_300x301":     # 19 x 19 = 361 tiles: two passes
+        sc, cam = scenes.tiny_scene(n=3000, seed=24)
+        return sc, dict(cam, width=300, height=301, cx=149.5, cy=150.0), {}
+    if name == "mid_1920x1080":      # 8160 tiles: two passes, many owners per slice
+        sc, cam = scenes.mid_scene(n=40_000, seed=3)
+        return sc, cam, dict(adagscale=True, K=0.5)
+    if name == "wide_4112x4112":     # 257 x 257 = 66049 tiles: fallback route
+        sc, cam = scenes.mid_scene(n=20_000, seed=4, width=4112, height=4112)
+        return sc, cam, {}
+    raise KeyError(name)
+
+
+CASES = ["tiny128", "tiny128_ada", "ragged_257x129", "ragged_300x301", "mid_1920x1080",
+         "wide_4112x4112"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_bin_equals_staged_and_oracle(O, name):
+    sc, cam, mode = _case(name)
+    print(f"bin case {name}: n={sc.n} {cam['width']}x{cam['height']}", flush=True)
+    st = gpu_frame(sc, cam, mode, staged=True)
+    bn = gpu_frame(sc, cam, mode, staged=False)
+    P = st["num_pairs"]
+    assert bn["num_pairs"] == P
+    np.testing.assert_array_equal(bn["ranges"], st["ranges"])
+    np.testing.assert_array_equal(bn["sorted_gids"][:P], st["sorted_gids"][:P])
+    np.testing.assert_array_equal(bn["sorted_tiles"][:P], st["sorted_tiles"][:P])
+    for k in ("image", "final_T", "n_contrib"):
+        np.testing.assert_array_equal(bn[k], st[k])
+    # against the oracle's sort (O13) and ranges (O14)
+    fr = O.render(sc, cam, oracle_mode(O, mode), tiles=np.zeros(0, np.int32))
+    assert fr.sorted_keys.size == P
+    np.testing.assert_array_equal(bn["sorted_tiles"][:P], (fr.sorted_keys >> np.uint64(32)).astype(np.int64))
+    np.testing.assert_array_equal(bn["sorted_gids"][:P], fr.sorted_vals.astype(np.int64))
+    np.testing.assert_array_equal(bn["ranges"], fr.ranges)
+    print(f"  pairs {P}", flush=True)
+
+
+def test_bin_empty_and_culled(O):
+    sc, cam = scenes.tiny_scene(n=500, seed=25)
+    behind = dict(cam)
+    vm = np.asarray(cam["viewmat"], np.float32).reshape(3, 4).copy()
+    vm[2, 3] = -100.0  # every Gaussian behind the near plane
+    behind["viewmat"] = vm.reshape(-1)
+    g = gpu_frame(sc, behind, staged=False)
+    assert g["num_pairs"] == 0 and not g["ranges"].any()
+    empty = sc.subset(np.zeros(0, np.int64))
+    g = gpu_frame(empty, cam, staged=False)
+    assert g["num_pairs"] == 0 and not g["ranges"].any()
+    assert np.all(g["final_T"] == 1.0) and not g["image"].any()
+
+
+@pytest.mark.parametrize("name", ["tiny128", "ragged_300x301", "wide_4112x4112"])
+def test_bin_overflow_bins_nothing(O, name):
+    """Capacity below the pair count: the required count is reported, no list
+    is produced (every range empty, image = background), and a regrown buffer
+    gives the full result."""
+    import torch
+    from paper_2604_18980_amd import gsr, render as R
+    sc, cam, mode = _case(name)
+    full = gpu_frame(sc, cam, mode, staged=True)
+    ds = R.DeviceScene.from_host(sc)
+    cam_s, mode_s = gsr.camera_struct(cam), gsr.mode_struct(**mode)
+    fb = R.FrameBuffers(ds.n, cam["width"], cam["height"], full["num_pairs"] // 3)
+    R.enqueue_frame(ds, cam_s, mode_s, fb, bg=(0.25, 0.5, 0.75))
+    torch.cuda.synchronize()
+    assert int(fb.num_pairs.item()) == full["num_pairs"]
+    assert not fb.ranges.cpu().numpy().any()
+    img = fb.image.cpu().numpy()
+    for c, v in enumerate((0.25, 0.5, 0.75)):
+        assert np.all(img[c] == np.float32(v))
+    fb.set_capacity(full["num_pairs"])
+    R.enqueue_frame(ds, cam_s, mode_s, fb)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(fb.image.cpu().numpy(), full["image"])
+    np.testing.assert_array_equal(fb.ranges.cpu().numpy().astype(np.uint32).astype(np.int64),
+                                  full["ranges"])
