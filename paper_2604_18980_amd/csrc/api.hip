@@ -130,7 +130,7 @@ bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws, int tx,
     const int64_t parts_sort = (256 * ws->nb_psort + kScanChunk - 1) / kScanChunk + 1;
     const int64_t parts_emit = (256 * ws->nb_dsort + kScanChunk - 1) / kScanChunk +
                                (n + kScanChunk - 1) / kScanChunk + 1;
-    const int64_t parts_bin = (ntiles + kScanChunk - 1) / kScanChunk + 1;
+    const int64_t parts_bin = (256 * (ws->nb_psort + 256) + kScanChunk - 1) / kScanChunk + 1;
     ws->max_parts = parts_sort > parts_emit ? parts_sort : parts_emit;
     if (parts_bin > ws->max_parts) ws->max_parts = parts_bin;
     // sort region
@@ -159,9 +159,8 @@ bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws, int tx,
     // binning region
     ws->bpacked = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
     ws->bhist = (uint32_t *)take(sizeof(uint32_t) * 256 * (size_t)ws->nb_psort);
-    ws->tdiff = (int32_t *)take(sizeof(int32_t) * (size_t)(tx + 1) * (size_t)(ty + 1));
-    ws->tcount = (uint32_t *)take(sizeof(uint32_t) * (size_t)ntiles);
-    ws->toff = (uint32_t *)take(sizeof(uint32_t) * (size_t)ntiles);
+    ws->bhist2 = (uint32_t *)take(sizeof(uint32_t) * 256 * (size_t)(ws->nb_psort + 256));
+    ws->bplan = (uint32_t *)take(sizeof(uint32_t) * 2 * 257);
     if (!bin_packed(n, tx, ty)) {
         ws->bkey = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
         ws->bval = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);

@@ -18,11 +18,12 @@
 //                    (and, optionally, the tile id: high byte from the word, low
 //                    byte from the pass-1 bucket that held it)
 //
-// The ranges come from per-tile counts: each rectangle adds its four corners
-// to a (tiles_y+1) x (tiles_x+1) difference array, whose 2D prefix sum is the
-// list length of every tile; the exclusive scan of those is the list starts.
-// With at most 256 tiles, pass 1 writes the final lists directly.  Beyond the
-// packed limits the path falls back to emitting the pairs and sorting them.
+// Pass 2 runs bucket-aligned: each of its blocks holds items of a single
+// pass-1 bucket (one low byte l), so the digit-major exclusive offsets of its
+// histogram give the lists for free -- tile (h, l) occupies
+// [offs(h, first block of l), offs(h, first block of l + 1)).  With at most 256
+// tiles, pass 1 writes the final lists directly and its bucket starts are the
+// ranges.  Beyond the packed limits the path emits pairs and sorts them.
 //
 // If the pair count exceeds the capacity, nothing is binned: every range is
 // empty and num_pairs holds the required count.
@@ -199,170 +200,193 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_scatter1(const SliceArgs a
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) rkey[i] = FINAL ? key[i] : val[i];
     if (FINAL) {
-        rank_stage_write(rkey, val, cnt, 0, sm, u.stage[0], u.stage[1],
-                         [&](int64_t dst, uint32_t tile, uint32_t j) {
-                             sorted_gids[dst] = a.sorted_ids[j];
-                             if (sorted_tiles) sorted_tiles[dst] = tile;
-                         });
+        rank_stage_write(
+            rkey, val, cnt, 0, sm, u.stage[0], u.stage[1],
+            [&](uint32_t, uint32_t j) { return a.sorted_ids[j]; },
+            [&](int64_t dst, uint32_t tile, uint32_t gid) {
+                sorted_gids[dst] = gid;
+                if (sorted_tiles) sorted_tiles[dst] = tile;
+            });
     } else {
-        rank_stage_write(rkey, key, cnt, 0, sm, u.stage[0], u.stage[1],
-                         [&](int64_t dst, uint32_t, uint32_t word) { packed[dst] = word; });
+        rank_stage_write(
+            rkey, key, cnt, 0, sm, u.stage[0], u.stage[1], [](uint32_t, uint32_t word) { return word; },
+            [&](int64_t dst, uint32_t, uint32_t word) { packed[dst] = word; });
     }
 }
 
-// Pass 2: rank the packed words by their high byte (the tile's high byte),
-// write the Gaussian id of the word's depth rank, and optionally the tile id,
-// whose low byte is the pass-1 bucket the word was read from (bucket starts:
-// the pass-1 offsets of slice 0, lo_offs[d * nb1]).
+// Pass-2 plan (one block): bucket starts B[l] (the pass-1 offsets of slice
+// 0; B[256] = P) and the first pass-2 block of each bucket, bfirst[l]
+// (bfirst[256] = number of pass-2 blocks, also stored in *nb2).
+__global__ __launch_bounds__(256) void k_bin_plan2(const uint32_t *hist1, const int64_t *num_pairs,
+                                                   int64_t cap, uint32_t *plan, int64_t *nb2) {
+    __shared__ uint32_t wt[256 / kWave];
+    const int64_t P = live_count(num_pairs, cap, 1);
+    const int64_t nb1 = (P + kSortChunk - 1) / kSortChunk;
+    const int l = threadIdx.x;
+    const uint32_t b0 = P > 0 ? hist1[(int64_t)l * nb1] : 0u;
+    const uint32_t b1 = P > 0 ? (l < 255 ? hist1[(int64_t)(l + 1) * nb1] : (uint32_t)P) : 0u;
+    const uint32_t blocks = (b1 - b0 + kSortChunk - 1) / kSortChunk;
+    uint32_t tot;
+    const uint32_t first = block_exclusive_scan<256, uint32_t>(blocks, wt, &tot);
+    plan[l] = b0;
+    plan[257 + l] = first;
+    if (l == 0) {
+        plan[256] = (uint32_t)P;
+        plan[257 + 256] = tot;
+        *nb2 = tot;
+    }
+}
+
+struct Pass2Block {
+    int l;             // the bucket (tile low byte)
+    int64_t base;      // first item
+    int cnt;           // items
+    int64_t nb2;
+};
+
+// Which bucket and items pass-2 block b holds (false for an idle block, the
+// same for the whole block).  s_bfirst: LDS copy of bfirst[0..256].
+// Contains a barrier.
+__device__ __forceinline__ bool pass2_block(const uint32_t *plan, const int64_t *nb2_p,
+                                            uint32_t *s_bfirst, Pass2Block &pb) {
+    const int64_t nb2 = *nb2_p;
+    const uint32_t b = blockIdx.x;
+    if ((int64_t)b >= nb2) return false;
+    s_bfirst[threadIdx.x] = plan[257 + threadIdx.x];
+    if (threadIdx.x == 0) s_bfirst[256] = plan[257 + 256];
+    __syncthreads();
+    int lo = 0, hi = 255;  // last bucket whose first block is <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_bfirst[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    const int64_t start = (int64_t)plan[lo] + (int64_t)(b - s_bfirst[lo]) * kSortChunk;
+    const int64_t end = plan[lo + 1];
+    pb.l = lo;
+    pb.base = start;
+    pb.cnt = (int)(end - start < kSortChunk ? end - start : kSortChunk);
+    pb.nb2 = nb2;
+    return true;
+}
+
+// Pass-2 histogram of the high byte, digit-major [256][nb2].
+__global__ __launch_bounds__(kSortThreads) void k_bin_hist2(const uint32_t *packed, const uint32_t *plan,
+                                                            const int64_t *nb2_p, uint32_t *hist) {
+    __shared__ uint32_t h[kSortThreads / kWave][256];
+    __shared__ uint32_t s_bfirst[257];
+    Pass2Block pb;
+    if (!pass2_block(plan, nb2_p, s_bfirst, pb)) return;
+    for (int i = threadIdx.x; i < (kSortThreads / kWave) * 256; i += kSortThreads) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int wid = threadIdx.x / kWave;
+    for (int k = threadIdx.x; k < pb.cnt; k += kSortThreads)
+        atomicAdd(&h[wid][packed[pb.base + k] >> kRankBits], 1u);
+    __syncthreads();
+    const int d = threadIdx.x;
+    uint32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < kSortThreads / kWave; ++w) tot += h[w][d];
+    hist[(int64_t)d * pb.nb2 + blockIdx.x] = tot;
+}
+
+// Pass 2: rank the packed words by their high byte and write the Gaussian id
+// of each word's depth rank (and optionally the tile id, high byte << 8 | the
+// block's bucket).
 template <bool TILES>
-__global__ __launch_bounds__(kSortThreads) void k_bin_scatter2(
-    const uint32_t *packed, const int64_t *num_pairs, int64_t cap, const uint32_t *offs,
-    const uint32_t *sorted_ids, uint32_t *sorted_gids, uint32_t *sorted_tiles,
-    const uint32_t *lo_offs) {
+__global__ __launch_bounds__(kSortThreads) void k_bin_scatter2(const uint32_t *packed, const uint32_t *plan,
+                                                               const int64_t *nb2_p, const uint32_t *offs,
+                                                               const uint32_t *sorted_ids,
+                                                               uint32_t *sorted_gids,
+                                                               uint32_t *sorted_tiles) {
     __shared__ RankSmem sm;
     __shared__ uint32_t skey[kSortChunk];
     __shared__ uint32_t sval[kSortChunk];
-    __shared__ uint32_t lo_start[256];
+    __shared__ uint32_t s_bfirst[257];
+    Pass2Block pb;
+    if (!pass2_block(plan, nb2_p, s_bfirst, pb)) return;
     rank_init(sm);
-    const int64_t n = live_count(num_pairs, cap, 1);
-    const int64_t base = (int64_t)blockIdx.x * kSortChunk;
-    if (base >= n) return;
-    const int64_t nb_live = (n + kSortChunk - 1) / kSortChunk;
-    sm.gbase[threadIdx.x] = offs[(int64_t)threadIdx.x * nb_live + blockIdx.x];
-    if (TILES) lo_start[threadIdx.x] = lo_offs[(int64_t)threadIdx.x * nb_live];
+    sm.gbase[threadIdx.x] = offs[(int64_t)threadIdx.x * pb.nb2 + blockIdx.x];
     __syncthreads();
-    const int cnt = (int)(n - base < kSortChunk ? n - base : kSortChunk);
     uint32_t key[kSortItems], val[kSortItems];
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const int p = rank_pos(i);
-        key[i] = p < cnt ? packed[base + p] : 0u;
-        val[i] = (uint32_t)p;
+        key[i] = p < pb.cnt ? packed[pb.base + p] : 0u;
+        val[i] = 0u;
     }
-    rank_stage_write(key, val, cnt, kRankBits, sm, skey, sval,
-                     [&](int64_t dst, uint32_t word, uint32_t p) {
-                         sorted_gids[dst] = sorted_ids[word & kRankMask];
-                         if (TILES) {
-                             // last bucket whose start is <= the word's input position
-                             const uint32_t pos = (uint32_t)(base + p);
-                             int lo = 0, hi = 255;
-                             while (lo < hi) {
-                                 const int mid = (lo + hi + 1) >> 1;
-                                 if (lo_start[mid] <= pos) lo = mid; else hi = mid - 1;
-                             }
-                             sorted_tiles[dst] = ((word >> kRankBits) << 8) | (uint32_t)lo;
-                         }
-                     });
+    const uint32_t l = (uint32_t)pb.l;
+    rank_stage_write(
+        key, val, pb.cnt, kRankBits, sm, skey, sval,
+        [&](uint32_t word, uint32_t) { return sorted_ids[word & kRankMask]; },
+        [&](int64_t dst, uint32_t word, uint32_t gid) {
+            sorted_gids[dst] = gid;
+            if (TILES) sorted_tiles[dst] = ((word >> kRankBits) << 8) | l;
+        });
 }
 
-// ---------------------------------------------------------------- tile counts
-__global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int64_t m) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < m) p[i] = 0;
-}
-
-// Each visible rectangle [x0, x1) x [y0, y1) adds +1 at (y0, x0) and (y1, x1)
-// and -1 at (y0, x1) and (y1, x0) of the difference array.
-__global__ __launch_bounds__(256) void k_rect_corners(const uint32_t *sorted_ids, const int64_t *num_vis,
-                                                      const uint64_t *rects, int tiles_x, int32_t *diff,
-                                                      int64_t n) {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= n || j >= *num_vis) return;
-    const uint64_t r = rects[sorted_ids[j]];
-    const uint32_t x0 = r & 0xffff, y0 = (r >> 16) & 0xffff, x1 = (r >> 32) & 0xffff, y1 = r >> 48;
-    const int64_t W = tiles_x + 1;
-    atomicAdd(&diff[y0 * W + x0], 1);
-    atomicAdd(&diff[y0 * W + x1], -1);
-    atomicAdd(&diff[y1 * W + x0], -1);
-    atomicAdd(&diff[y1 * W + x1], 1);
-}
-
-// Inclusive prefix along x of rows 0 .. tiles_y - 1 (one block per row).
-__global__ __launch_bounds__(256) void k_prefix_rows(int32_t *diff, int tiles_x) {
-    __shared__ int32_t wt[256 / kWave];
-    int32_t *row = diff + (int64_t)blockIdx.x * (tiles_x + 1);
-    int32_t carry = 0;
-    for (int c0 = 0; c0 < tiles_x; c0 += 256 * 8) {
-        int32_t v[8], s = 0;
-        const int c = c0 + threadIdx.x * 8;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            v[i] = c + i < tiles_x ? row[c + i] : 0;
-            s += v[i];
-        }
-        int32_t tot;
-        int32_t run = carry + block_exclusive_scan<256, int32_t>(s, wt, &tot);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            run += v[i];
-            if (c + i < tiles_x) row[c + i] = run;
-        }
-        carry += tot;
-    }
-}
-
-// Inclusive prefix along y (one thread per column): the list length of every
-// tile, written densely; zero for all tiles when the pairs overflowed.
-__global__ __launch_bounds__(256) void k_prefix_cols(const int32_t *diff, int tiles_x, int tiles_y,
-                                                     const int64_t *num_pairs, int64_t cap,
-                                                     uint32_t *count) {
-    const int x = blockIdx.x * 256 + threadIdx.x;
-    if (x >= tiles_x) return;
-    const bool over = *num_pairs > cap;
-    int32_t acc = 0;
-    for (int y = 0; y < tiles_y; ++y) {
-        acc += diff[(int64_t)y * (tiles_x + 1) + x];
-        count[(int64_t)y * tiles_x + x] = over ? 0u : (uint32_t)acc;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_ranges_from_counts(const uint32_t *count, const uint32_t *off,
-                                                            int64_t ntiles, uint32_t *ranges) {
+// ranges[t] for t = (h, l): [offs(h, bfirst[l]), offs(h, bfirst[l + 1])), the
+// flat digit-major index h * nb2 + bfirst[256] being the next digit's start
+// (or P past the last).  (0, 0) for an empty tile, and for every tile when the
+// pairs overflowed.
+__global__ __launch_bounds__(256) void k_bin_ranges2(const uint32_t *offs, const uint32_t *plan,
+                                                     const int64_t *nb2_p, const int64_t *num_pairs,
+                                                     int64_t cap, int64_t ntiles, uint32_t *ranges) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= ntiles) return;
-    const uint32_t c = count[t], s = c ? off[t] : 0u;  // an empty tile's range is (0, 0)
-    reinterpret_cast<uint2 *>(ranges)[t] = make_uint2(s, s + c);
+    const int64_t P = live_count(num_pairs, cap, 1);
+    const int64_t nb2 = *nb2_p;
+    uint32_t s = 0, e = 0;
+    if (P > 0 && nb2 > 0) {
+        const int64_t h = t >> 8, l = t & 255;
+        const uint32_t *bfirst = plan + 257;
+        if (bfirst[l] < bfirst[l + 1]) {
+            const int64_t i0 = h * nb2 + bfirst[l], i1 = h * nb2 + bfirst[l + 1];
+            s = offs[i0];
+            e = i1 < 256 * nb2 ? offs[i1] : (uint32_t)P;
+        }
+        if (s == e) s = e = 0;
+    }
+    reinterpret_cast<uint2 *>(ranges)[t] = make_uint2(s, e);
 }
 
-// Counts -> starts -> ranges.  Needs launch_emit_prepare's outputs.
-static hipError_t bin_ranges(const uint64_t *rects, int n, int tiles_x, int tiles_y, int64_t cap,
-                             const int64_t *num_pairs, uint32_t *ranges, const Workspace &ws,
-                             hipStream_t s) {
-    const int64_t ntiles = (int64_t)tiles_x * tiles_y;
-    const int64_t md = (int64_t)(tiles_x + 1) * (tiles_y + 1);
-    k_fill_i32<<<(unsigned)((md + 255) / 256), 256, 0, s>>>(ws.tdiff, md);
-    if (n > 0)
-        k_rect_corners<<<(unsigned)ws.nb_gauss, 256, 0, s>>>(ws.dval[1], ws.counters, rects, tiles_x,
-                                                             ws.tdiff, n);
-    k_prefix_rows<<<(unsigned)tiles_y, 256, 0, s>>>(ws.tdiff, tiles_x);
-    k_prefix_cols<<<(unsigned)((tiles_x + 255) / 256), 256, 0, s>>>(ws.tdiff, tiles_x, tiles_y,
-                                                                    num_pairs, cap, ws.tcount);
-    hipError_t e = scan_exclusive_u32(ws.tcount, ws.toff, ntiles, ws.scan_part, nullptr, s);
-    if (e != hipSuccess) return e;
-    k_ranges_from_counts<<<(unsigned)((ntiles + 255) / 256), 256, 0, s>>>(ws.tcount, ws.toff, ntiles,
-                                                                         ranges);
-    return hipGetLastError();
+// One-pass route (at most 256 tiles): tile t is bucket t, [B[t], B[t + 1]).
+__global__ __launch_bounds__(256) void k_bin_ranges1(const uint32_t *plan, int64_t ntiles,
+                                                     uint32_t *ranges) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= ntiles) return;
+    uint32_t s = plan[t], e = plan[t + 1];
+    if (s == e) s = e = 0;
+    reinterpret_cast<uint2 *>(ranges)[t] = make_uint2(s, e);
+}
+
+__global__ __launch_bounds__(256) void k_zero_ranges(uint32_t *ranges, int64_t m) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < m) ranges[i] = 0u;
 }
 
 hipError_t launch_bin(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
                       int n, int tiles_x, int tiles_y, uint32_t *sorted_gids, uint32_t *sorted_tiles,
                       uint32_t *ranges, int64_t cap, int64_t *num_pairs, const Workspace &ws,
                       hipStream_t s) {
+    const int64_t ntiles = (int64_t)tiles_x * tiles_y;
     hipError_t e = launch_emit_prepare(splats, rects, tiles_touched, n, cap, num_pairs, ws, s);
     if (e != hipSuccess) return e;
-    e = bin_ranges(rects, n, tiles_x, tiles_y, cap, num_pairs, ranges, ws, s);
-    if (e != hipSuccess || n == 0 || cap == 0) return e;
+    if (n == 0 || cap == 0) {  // no pairs can be binned: every range empty
+        k_zero_ranges<<<(unsigned)((2 * ntiles + 255) / 256), 256, 0, s>>>(ranges, 2 * ntiles);
+        return hipGetLastError();
+    }
     const int64_t nb = ws.nb_psort;  // slices = sort blocks = ceil(cap / 4096)
-    const int64_t ntiles = (int64_t)tiles_x * tiles_y;
     if (!bin_packed(n, tiles_x, tiles_y)) {
-        // generic route: emit the pairs, then sort them by tile (empty if over)
+        // generic route: emit the pairs, sort them by tile (nothing if over), ranges
         e = launch_emit_pairs(rects, tiles_x, ws.bkey, ws.bval, cap, num_pairs, ws, s);
         if (e != hipSuccess) return e;
         uint32_t *kout = sorted_tiles ? sorted_tiles : ws.bpacked;
         int bits = 0;
         while (bits < 63 && ((int64_t)1 << bits) < ntiles) ++bits;
-        return radix_sort_u32(ws.bkey, ws.bval, kout, sorted_gids, ws.ptile_tmp, ws.pgid_tmp,
-                              num_pairs, cap, bits, ws.phist, nb, ws.scan_part, s, 0, 1);
+        e = radix_sort_u32(ws.bkey, ws.bval, kout, sorted_gids, ws.ptile_tmp, ws.pgid_tmp,
+                           num_pairs, cap, bits, ws.phist, nb, ws.scan_part, s, 0, 1);
+        if (e != hipSuccess) return e;
+        return launch_tile_ranges(kout, num_pairs, cap, ranges, (int)ntiles, s, 1);
     }
     SliceArgs a;
     a.sorted_ids = ws.dval[1];
@@ -377,20 +401,29 @@ hipError_t launch_bin(const float *splats, const uint64_t *rects, const uint32_t
     e = scan_exclusive_u32(ws.bhist, ws.bhist, 256 * nb, ws.scan_part, nullptr, s,
                            DevExtent{num_pairs, cap, kSortChunk, 256, true});
     if (e != hipSuccess) return e;
+    int64_t *nb2 = ws.counters + 2;
+    k_bin_plan2<<<1, 256, 0, s>>>(ws.bhist, num_pairs, cap, ws.bplan, nb2);
+    const unsigned ranges_grid = (unsigned)((ntiles + 255) / 256);
     if (ntiles <= 256) {
         k_bin_scatter1<true><<<(unsigned)nb, kSortThreads, 0, s>>>(a, ws.bhist, nullptr, sorted_gids,
                                                                   sorted_tiles);
+        k_bin_ranges1<<<ranges_grid, 256, 0, s>>>(ws.bplan, ntiles, ranges);
         return hipGetLastError();
     }
     k_bin_scatter1<false><<<(unsigned)nb, kSortThreads, 0, s>>>(a, ws.bhist, ws.bpacked, nullptr,
                                                                nullptr);
-    radix_hist(ws.bpacked, num_pairs, cap, kRankBits, ws.phist, nb, ws.scan_part, s, 1);
+    const int64_t nb2max = nb + 256;  // bucket alignment adds at most one partial block per bucket
+    k_bin_hist2<<<(unsigned)nb2max, kSortThreads, 0, s>>>(ws.bpacked, ws.bplan, nb2, ws.bhist2);
+    e = scan_exclusive_u32(ws.bhist2, ws.bhist2, 256 * nb2max, ws.scan_part, nullptr, s,
+                           DevExtent{nb2, nb2max, 1, 256});
+    if (e != hipSuccess) return e;
     if (sorted_tiles)
-        k_bin_scatter2<true><<<(unsigned)nb, kSortThreads, 0, s>>>(
-            ws.bpacked, num_pairs, cap, ws.phist, ws.dval[1], sorted_gids, sorted_tiles, ws.bhist);
+        k_bin_scatter2<true><<<(unsigned)nb2max, kSortThreads, 0, s>>>(
+            ws.bpacked, ws.bplan, nb2, ws.bhist2, ws.dval[1], sorted_gids, sorted_tiles);
     else
-        k_bin_scatter2<false><<<(unsigned)nb, kSortThreads, 0, s>>>(
-            ws.bpacked, num_pairs, cap, ws.phist, ws.dval[1], sorted_gids, nullptr, ws.bhist);
+        k_bin_scatter2<false><<<(unsigned)nb2max, kSortThreads, 0, s>>>(
+            ws.bpacked, ws.bplan, nb2, ws.bhist2, ws.dval[1], sorted_gids, nullptr);
+    k_bin_ranges2<<<ranges_grid, 256, 0, s>>>(ws.bhist2, ws.bplan, nb2, num_pairs, cap, ntiles, ranges);
     return hipGetLastError();
 }
 

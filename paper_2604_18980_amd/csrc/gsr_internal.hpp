@@ -46,13 +46,12 @@ struct Workspace {
     // fused binning (bin.hip)
     uint32_t *bpacked;     // [cap] pass-1 output: tile >> 8 in bits 24..31, depth rank below
     uint32_t *bhist;       // [256][nb_psort] pass-1 histogram / offsets
-    int32_t *tdiff;        // [(tiles_y + 1) * (tiles_x + 1)] rectangle corner differences
-    uint32_t *tcount;      // [tiles] pairs per tile
-    uint32_t *toff;        // [tiles] their exclusive prefix
+    uint32_t *bhist2;      // [256][nb_psort + 256] pass-2 histogram / offsets
+    uint32_t *bplan;       // [2][257] pass-1 bucket starts, first pass-2 block per bucket
     uint32_t *bkey, *bval; // [cap] each, only when the packed path does not apply
     // device-wide scan partials (large enough for any scan above)
     uint64_t *scan_part;   // [max_parts]
-    int64_t *counters;     // [0] visible Gaussians, [1] scratch
+    int64_t *counters;     // [0] visible Gaussians, [1] scratch, [2] pass-2 blocks
     int64_t nb_gauss, nb_dsort, nb_psort, max_parts;
     int tiles_x, tiles_y;
     size_t bytes;
@@ -151,7 +150,7 @@ hipError_t launch_bin(const float *splats, const uint64_t *rects, const uint32_t
                       hipStream_t s);
 
 hipError_t launch_tile_ranges(const uint32_t *sorted_tiles, const int64_t *num_pairs, int64_t cap,
-                              uint32_t *ranges, int num_tiles, hipStream_t s);
+                              uint32_t *ranges, int num_tiles, hipStream_t s, int empty_if_over = 0);
 
 struct RasterArgs {
     const float *splats;

@@ -35,17 +35,19 @@ __device__ __forceinline__ int rank_pos(int i) {
     return (threadIdx.x / kWave) * kRankPerWave + i * kWave + (threadIdx.x & (kWave - 1));
 }
 
-// Ranks the block's items by digit (key >> shift) & 255 and calls
-// write(dst, key, val) once per valid item, where dst = gbase[digit] + the
-// item's stable rank within its digit.  Items at positions >= cnt are invalid.
-// skey / sval: kSortChunk-entry LDS staging arrays, which may alias memory the
-// caller no longer reads (item generation must be complete).  Contains barriers;
-// the caller must have run rank_init, set gbase and issued a barrier.
-template <class Write>
+// Ranks the block's items by digit (key >> shift) & 255 and, for each valid
+// item, computes payload = fetch(key, val) and calls store(dst, key, payload),
+// where dst = gbase[digit] + the item's stable rank within its digit.  Every
+// thread runs all its fetches (loads may be in flight together) before its
+// stores.  Items at positions >= cnt are invalid.  skey / sval: kSortChunk-entry
+// LDS staging arrays, which may alias memory the caller no longer reads (item
+// generation must be complete).  Contains barriers; the caller must have run
+// rank_init, set gbase and issued a barrier.
+template <class Fetch, class Store>
 __device__ __forceinline__ void rank_stage_write(const uint32_t (&key)[kSortItems],
                                                  const uint32_t (&val)[kSortItems], int cnt,
                                                  int shift, RankSmem &sm, uint32_t *skey,
-                                                 uint32_t *sval, Write write) {
+                                                 uint32_t *sval, Fetch fetch, Store store) {
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     uint32_t rank[kSortItems];
     const uint64_t lt = lanemask_lt();
@@ -89,11 +91,23 @@ __device__ __forceinline__ void rank_stage_write(const uint32_t (&key)[kSortItem
         sval[p] = val[i];
     }
     __syncthreads();
-    for (int p = threadIdx.x; p < cnt; p += kSortThreads) {
-        const uint32_t k = skey[p];
-        const uint32_t d = (k >> shift) & 255u;
-        write((int64_t)sm.gbase[d] + (p - (int)sm.dstart[d]), k, sval[p]);
+    // position p = threadIdx.x + i * kSortThreads: consecutive threads take
+    // consecutive staged items, so each digit's run is stored contiguously
+    uint32_t k[kSortItems], pay[kSortItems];
+    int64_t dst[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int p = threadIdx.x + i * kSortThreads;
+        if (p < cnt) {
+            k[i] = skey[p];
+            const uint32_t d = (k[i] >> shift) & 255u;
+            dst[i] = (int64_t)sm.gbase[d] + (p - (int)sm.dstart[d]);
+            pay[i] = fetch(k[i], sval[p]);
+        }
     }
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i)
+        if (threadIdx.x + i * kSortThreads < cnt) store(dst[i], k[i], pay[i]);
 }
 
 }  // namespace gsr

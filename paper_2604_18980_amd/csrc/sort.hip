@@ -161,10 +161,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         key[i] = p < cnt ? kin[base + p] : 0u;
         val[i] = p < cnt ? vin[base + p] : 0u;
     }
-    rank_stage_write(key, val, cnt, shift, sm, skey, sval, [&](int64_t dst, uint32_t k, uint32_t v) {
-        if (kout) kout[dst] = k;
-        vout[dst] = v;
-    });
+    rank_stage_write(
+        key, val, cnt, shift, sm, skey, sval, [](uint32_t, uint32_t v) { return v; },
+        [&](int64_t dst, uint32_t k, uint32_t v) {
+            if (kout) kout[dst] = k;
+            vout[dst] = v;
+        });
 }
 
 hipError_t radix_sort_u32(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
@@ -211,8 +213,8 @@ __global__ void k_fill_u32(uint32_t *p, int64_t m, uint32_t v) {
 // Thread i tests the boundary between items i-1 and i, for four consecutive i
 // per thread (one 16-byte load plus the item before).
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *tiles, const int64_t *count,
-                                                     int64_t cap, uint32_t *ranges) {
-    const int64_t n = live_count(count, cap, 0);
+                                                     int64_t cap, uint32_t *ranges, int empty_if_over) {
+    const int64_t n = live_count(count, cap, empty_if_over);
     const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
     if (i0 >= n) return;
     uint32_t t[5];
@@ -236,11 +238,12 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *tiles, cons
 }
 
 hipError_t launch_tile_ranges(const uint32_t *sorted_tiles, const int64_t *num_pairs, int64_t cap,
-                              uint32_t *ranges, int num_tiles, hipStream_t s) {
+                              uint32_t *ranges, int num_tiles, hipStream_t s, int empty_if_over) {
     const int64_t m = 2 * (int64_t)num_tiles;
     k_fill_u32<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(ranges, m, 0u);
     if (cap > 0)
-        k_tile_ranges<<<(unsigned)((cap + 1023) / 1024), 256, 0, s>>>(sorted_tiles, num_pairs, cap, ranges);
+        k_tile_ranges<<<(unsigned)((cap + 1023) / 1024), 256, 0, s>>>(sorted_tiles, num_pairs, cap, ranges,
+                                                                      empty_if_over);
     return hipGetLastError();
 }
 
