@@ -109,9 +109,12 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
     const int px = tx * kTile + col;
     const float fpx = (float)px;
     const float x_lo = (float)(tx * kTile), x_hi = (float)(tx * kTile + kTile - 1);
-    float fpy[4], T[4], cr[4], cg[4], cb[4];
+    // Per pixel k: thr[k] is the alpha a Gaussian must reach to be blended --
+    // tau while the pixel is live, 2 (above any clamped alpha) once it has
+    // stopped or lies outside the image -- so "live and alpha >= tau" is one
+    // compare and the per-pixel state needs no boolean merges.
+    float fpy[4], T[4], cr[4], cg[4], cb[4], thr[4];
     uint32_t last[4], ev[4];
-    bool done[4];
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -121,7 +124,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
         cr[k] = cg[k] = cb[k] = 0.0f;
         last[k] = 0;
         ev[k] = end - start;
-        done[k] = !(px < a.width && py < a.height);
+        thr[k] = (px < a.width && py < a.height) ? kTauF : 2.0f;
     }
     const float4 *spl = reinterpret_cast<const float4 *>(a.splats);
 
@@ -129,7 +132,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
         uint32_t alive = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (__ballot(!done[k]) != 0ull) alive |= 1u << k;
+            if (__ballot(thr[k] < 1.0f) != 0ull) alive |= 1u << k;
         if (!alive) break;
         const uint32_t j = base + (uint32_t)lane;
         float mx = 0.f, my = 0.f, A2 = 0.f, beta = 0.f, G2 = 0.f, sig = 0.f, r = 0.f, g = 0.f, bl = 0.f;
@@ -181,25 +184,23 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
             const uint32_t pos = (base - start) + (uint32_t)jj + 1u;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (!((m[k] >> jj) & 1ull)) continue;
-                if (done[k]) continue;
+                if (!((m[k] >> jj) & 1ull)) continue;  // uniform: strip k missed
                 const float dy = smy - fpy[k];
                 const float u = fmaf(sbeta, dy, dx);
                 const float e2 = fmaf(sA2 * u, u, sG2 * (dy * dy));
                 const float alpha = fminf(kAlphaMaxF, ssig * __builtin_amdgcn_exp2f(e2));
-                if (alpha < kTauF) continue;
-                const float Tn = T[k] * (1.0f - alpha);
-                if (Tn < kStopF) {
-                    done[k] = true;
-                    ev[k] = pos;
-                    continue;
+                if (alpha >= thr[k]) {  // live pixel, alpha >= tau
+                    const float Tn = T[k] * (1.0f - alpha);
+                    const bool stop = Tn < kStopF;  // this Gaussian is not blended
+                    const float w = stop ? 0.0f : alpha * T[k];
+                    cr[k] = fmaf(w, sr, cr[k]);
+                    cg[k] = fmaf(w, sg, cg[k]);
+                    cb[k] = fmaf(w, sb, cb[k]);
+                    T[k] = stop ? T[k] : Tn;
+                    last[k] = stop ? last[k] : pos;
+                    ev[k] = stop ? pos : ev[k];
+                    thr[k] = stop ? 2.0f : thr[k];
                 }
-                const float w = alpha * T[k];
-                cr[k] = fmaf(w, sr, cr[k]);
-                cg[k] = fmaf(w, sg, cg[k]);
-                cb[k] = fmaf(w, sb, cb[k]);
-                T[k] = Tn;
-                last[k] = pos;
             }
         }
     }
