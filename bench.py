@@ -3,9 +3,10 @@ AdaGScale beside plain 3D-GS, on the synthetic 6M-Gaussian city scene at
 4608x3456 (the Mill-19 resolution of the paper's Table I).
 
 A step is one frame of the whole forward path -- preprocess, pair emission,
-sort, tile ranges, rasterization -- enqueued through the C-ABI with the scene
-and every buffer already resident in HBM (pair buffers sized beforehand, so
-no host round trip inside the timed region).  K is binary-searched on the
+sort and tile ranges (fused in one binning call), rasterization -- enqueued
+through the C-ABI with the scene and every buffer already resident in HBM
+(pair buffers sized beforehand, so no host round trip inside the timed
+region).  K is binary-searched on the
 measured view so that PSNR(AdaGScale vs plain) sits at the quality point
 that corresponds to the paper's 0.5 dB drop.
 

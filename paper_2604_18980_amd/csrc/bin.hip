@@ -123,8 +123,9 @@ __device__ __forceinline__ void slice_pair(const Owners &ow, int k, int tiles_x,
     const int o = (int)ow.mark_prefix[wi] + __popc(upto) - 1;
     const uint32_t m = o == 0 ? ow.m0 + (uint32_t)k : (uint32_t)k - ow.rel[o];
     const uint32_t w = ow.w[o];
-    // m / w by a float reciprocal, corrected by one step (m < 2^22 here)
-    int q = (int)((float)m * (1.0f / (float)w));
+    // m / w by the hardware reciprocal (within an ulp), corrected by one step:
+    // m < 2^22 here, so the truncated estimate is off by at most one
+    int q = (int)((float)m * __builtin_amdgcn_rcpf((float)w));
     int r = (int)m - q * (int)w;
     if (r < 0) { --q; r += (int)w; } else if (r >= (int)w) { ++q; r -= (int)w; }
     tile = ((uint32_t)ow.y0[o] + (uint32_t)q) * (uint32_t)tiles_x + ow.x0[o] + (uint32_t)r;

@@ -211,6 +211,10 @@ struct PreprocessBwdArgs {
 hipError_t launch_preprocess_backward(const PreprocessBwdArgs &a, hipStream_t s);
 
 // ------------------------------------------------------------ device helpers
+// An empty asm that claims to modify x: the value must exist in a register at
+// this point, so the compiler neither sinks its computation nor recomputes it.
+__device__ __forceinline__ void pin_vgpr(float &x) { __asm__ volatile("" : "+v"(x)); }
+
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 

@@ -35,9 +35,6 @@ __device__ __forceinline__ void store_splat(float *dst, float4 a, float4 b, floa
     p[2] = c;
 }
 
-// An empty asm that claims to modify x: the value must exist in a register at
-// this point of the program.
-__device__ __forceinline__ void pin_vgpr(float &x) { __asm__ volatile("" : "+v"(x)); }
 
 // Real spherical harmonics (Condon-Shortley phase, coefficient k = l^2+l+m)
 // at the unit direction (x, y, z), as polynomials; c[] holds the

@@ -55,13 +55,18 @@ __device__ __forceinline__ void rank_stage_write(const uint32_t (&key)[kSortItem
     for (int i = 0; i < kSortItems; ++i) {
         const bool valid = rank_pos(i) < cnt;
         const uint32_t d = (key[i] >> shift) & 255u;
-        uint64_t peers = __ballot(valid);
+        // lanes whose digit differs from this lane's in some bit: per bit the
+        // ballot XOR this lane's bit spread over 32 bits, OR-accumulated in the
+        // two 32-lane halves (cheaper than selecting ballot or ~ballot per lane)
+        uint32_t dlo = 0u, dhi = 0u;
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
+            const uint32_t spread = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);  // 0 or ~0
+            const uint64_t m = __ballot((int32_t)spread < 0);
+            dlo |= (uint32_t)m ^ spread;
+            dhi |= (uint32_t)(m >> 32) ^ spread;
         }
+        const uint64_t peers = __ballot(valid) & ~(((uint64_t)dhi << 32) | dlo);
         const uint32_t before = sm.wcnt[wid][d];
         rank[i] = before + (uint32_t)__popcll(peers & lt);
         // the highest lane of each digit group advances the running count

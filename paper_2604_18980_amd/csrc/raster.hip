@@ -30,6 +30,7 @@ constexpr float kAlphaMaxF = 0.99f;
 constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
 constexpr float kLnTau = -5.5412635451584258f;            // ln(1/255)
 
+
 __device__ __forceinline__ float bcast(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
@@ -102,6 +103,8 @@ __device__ __forceinline__ void tile_block(const RasterArgs &a, int tile) {
     if (inside) store_pixel(a, px, py, cr, cg, cb, T, last, evaluated);
 }
 
+// EV: also count, per pixel, the list entries evaluated (n_evaluated output).
+template <bool EV>
 __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
     const int lane = threadIdx.x & (kWave - 1);
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
@@ -109,22 +112,23 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
     const int px = tx * kTile + col;
     const float fpx = (float)px;
     const float x_lo = (float)(tx * kTile), x_hi = (float)(tx * kTile + kTile - 1);
-    // Per pixel k: thr[k] is the alpha a Gaussian must reach to be blended --
-    // tau while the pixel is live, 2 (above any clamped alpha) once it has
-    // stopped or lies outside the image -- so "live and alpha >= tau" is one
+    // Per pixel k: off[k] is 0 while the pixel is live and -inf once it has
+    // stopped (or lies outside the image); it is added to the exponent before
+    // the alpha >= tau test, so "live and alpha >= tau" is one add and one
     // compare and the per-pixel state needs no boolean merges.
-    float fpy[4], T[4], cr[4], cg[4], cb[4], thr[4];
+    float fpy[4], T[4], cr[4], cg[4], cb[4], off[4];
     uint32_t last[4], ev[4];
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int py = ty * kTile + row0 + 4 * k;
         fpy[k] = (float)py;
+        pin_vgpr(fpy[k]);  // keep the float; recomputing it costs a convert per evaluation
         T[k] = 1.0f;
         cr[k] = cg[k] = cb[k] = 0.0f;
         last[k] = 0;
         ev[k] = end - start;
-        thr[k] = (px < a.width && py < a.height) ? kTauF : 2.0f;
+        off[k] = (px < a.width && py < a.height) ? 0.0f : -INFINITY;
     }
     const float4 *spl = reinterpret_cast<const float4 *>(a.splats);
 
@@ -132,10 +136,11 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
         uint32_t alive = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (__ballot(thr[k] < 1.0f) != 0ull) alive |= 1u << k;
+            if (__ballot(off[k] == 0.0f) != 0ull) alive |= 1u << k;
         if (!alive) break;
         const uint32_t j = base + (uint32_t)lane;
         float mx = 0.f, my = 0.f, A2 = 0.f, beta = 0.f, G2 = 0.f, sig = 0.f, r = 0.f, g = 0.f, bl = 0.f;
+        float elim = 0.f;  // alpha >= tau  <=>  exponent (base 2) >= elim
         uint32_t hit = 0;
         if (j < end) {
             const size_t gid = a.gids[j];
@@ -149,6 +154,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
             // evaluation: relative 1e-3, plus a term growing with the distance of
             // the centre (dx and dy lose digits there).
             const float qlim = 2.0f * (__logf(sig) - kLnTau);
+            elim = kNegHalfLog2e * qlim;
             if (qlim > -1e-3f) {
                 const float ql = fmaxf(qlim, 0.0f);
                 const float far = fabsf(mx - (x_lo + 7.5f)) + fabsf(my - (float)(ty * kTile) - 7.5f);
@@ -180,6 +186,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
             const float smx = bcast(mx, jj), smy = bcast(my, jj), sA2 = bcast(A2, jj);
             const float sbeta = bcast(beta, jj), sG2 = bcast(G2, jj), ssig = bcast(sig, jj);
             const float sr = bcast(r, jj), sg = bcast(g, jj), sb = bcast(bl, jj);
+            const float selim = bcast(elim, jj);
             const float dx = smx - fpx;
             const uint32_t pos = (base - start) + (uint32_t)jj + 1u;
 #pragma unroll
@@ -188,18 +195,21 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
                 const float dy = smy - fpy[k];
                 const float u = fmaf(sbeta, dy, dx);
                 const float e2 = fmaf(sA2 * u, u, sG2 * (dy * dy));
-                const float alpha = fminf(kAlphaMaxF, ssig * __builtin_amdgcn_exp2f(e2));
-                if (alpha >= thr[k]) {  // live pixel, alpha >= tau
-                    const float Tn = T[k] * (1.0f - alpha);
-                    const bool stop = Tn < kStopF;  // this Gaussian is not blended
-                    const float w = stop ? 0.0f : alpha * T[k];
+                // live pixel and opacity * 2^e2 >= tau, decided on the exponent
+                // so the exponential is only taken where it is used
+                if (e2 + off[k] >= selim) {
+                    const float alpha = fminf(kAlphaMaxF, ssig * __builtin_amdgcn_exp2f(e2));
+                    const float wa = alpha * T[k];
+                    const float Tn = T[k] - wa;     // T (1 - alpha)
+                    const bool stop = Tn < kStopF;  // not blended; the pixel is done
+                    const float w = stop ? 0.0f : wa;
                     cr[k] = fmaf(w, sr, cr[k]);
                     cg[k] = fmaf(w, sg, cg[k]);
                     cb[k] = fmaf(w, sb, cb[k]);
                     T[k] = stop ? T[k] : Tn;
                     last[k] = stop ? last[k] : pos;
-                    ev[k] = stop ? pos : ev[k];
-                    thr[k] = stop ? 2.0f : thr[k];
+                    if (EV) ev[k] = stop ? pos : ev[k];
+                    off[k] = stop ? -INFINITY : off[k];
                 }
             }
         }
@@ -225,10 +235,11 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return b < full ? (b % 8) * (nb / 8) + b / 8 : b;
 }
 
+template <bool EV>
 __global__ __launch_bounds__(256) void k_raster_wave(const RasterArgs a) {
     const int tile = xcd_block((int)blockIdx.x, (int)gridDim.x) * 4 + (int)(threadIdx.x / kWave);
     if (tile >= a.tiles_x * a.tiles_y) return;
-    tile_wave(a, tile);
+    tile_wave<EV>(a, tile);
 }
 
 hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStream_t s) {
@@ -240,7 +251,10 @@ hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStrea
             default: k_raster_block<256><<<tiles, 256, 0, s>>>(a); break;
         }
     } else {
-        k_raster_wave<<<(tiles + 3) / 4, 256, 0, s>>>(a);
+        if (a.n_evaluated)
+            k_raster_wave<true><<<(tiles + 3) / 4, 256, 0, s>>>(a);
+        else
+            k_raster_wave<false><<<(tiles + 3) / 4, 256, 0, s>>>(a);
     }
     return hipGetLastError();
 }
@@ -317,7 +331,7 @@ __global__ __launch_bounds__(256) void k_raster_views_wave(const ViewsArgs q) {
         if ((int64_t)item >= q.n_items) break;
         const uint32_t code = q.items[item];
         const int view = (int)(code >> 26), tile = (int)(code & ((1u << 26) - 1));
-        tile_wave(view_args(q, view), tile);
+        tile_wave<false>(view_args(q, view), tile);
         const uint32_t left = atomicSub(&q.view_left[view], one);
         if (__builtin_amdgcn_readlane((int)left, 0) == 1 && q.clock)
             q.clock[1 + view] = wall_clock64();  // same value from every lane
