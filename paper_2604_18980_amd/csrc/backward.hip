@@ -1,13 +1,17 @@
 // Adjoints of stage 4 (blend, eq. 1-2) and stage 1 (preprocess).
 //
-// Raster backward: one workgroup per 16x16 tile, one pixel per thread, the
-// tile's list walked back to front in LDS batches from the largest n_contrib
-// of the tile.  Each pixel recovers the transmittance before Gaussian i as
-// T_i = T_{i+1} / (1 - alpha_i) starting from its final T, so no per-pixel
-// list is stored.  alpha is recomputed with exactly the forward's float32
-// operations, so the skip decisions (alpha < tau) and the clamp are the
-// forward's.  Per Gaussian, the 9 gradients of a wave are summed with a
-// butterfly reduction and added to global memory by one lane.
+// Raster backward: one wave per 16x16 tile with the forward's pixel layout
+// (lane l owns column l % 16 of rows l / 16 + 4k, k = 0..3: four 16x4 strips).
+// The tile's list is walked back to front, 64 records at a time, from the
+// largest n_contrib of the tile; every lane gathers one record and decides,
+// per strip, whether the Gaussian can reach alpha >= tau there (the forward's
+// cull), and the wave visits the hits in reverse list order.  Each pixel
+// recovers the transmittance in front of Gaussian i as T_i = T_{i+1} /
+// (1 - alpha_i) starting from its final T, so no per-pixel list is stored;
+// alpha and the blend decision are recomputed with exactly the forward's
+// float32 operations, so a pixel differentiates precisely the Gaussians it
+// blended.  Per Gaussian, each lane sums its four pixels' contributions, the
+// wave sums the lanes, and one lane adds the 9 gradients to global memory.
 //
 // Preprocess backward: one thread per Gaussian, double precision, chaining the
 // 2D record gradients (mean, A, beta, gamma, opacity, colour) back to the scene
@@ -20,14 +24,27 @@
 namespace gsr {
 
 namespace {
-constexpr float kTauF = 1.0f / 255.0f;
 constexpr float kAlphaMaxF = 0.99f;
-constexpr int kBatch = 256;
+constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
+constexpr float kLnTau = -5.5412635451584258f;            // ln(1/255)
 
+// v moved across lanes by the DPP pattern CTRL into the rows in ROW_MASK (0 elsewhere).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+// Sum over the 64 lanes with DPP adds (no LDS traffic): pairs and quads by
+// quad permutes, 8 and 16 lanes by the half-row and row mirrors, then the
+// row-15 and row-31 broadcasts carry the row sums up to lane 63.
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    v += dpp<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += dpp<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += dpp<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp<0x140, 0xF>(v);  // row_mirror
+    v += dpp<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 }  // namespace
 
@@ -36,99 +53,150 @@ __global__ void k_zero_f32(float *p, int64_t m) {
     if (i < m) p[i] = 0.0f;
 }
 
+__device__ __forceinline__ float bcast(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
 __global__ __launch_bounds__(256) void k_raster_backward(const RasterBwdArgs a) {
-    __shared__ float4 s_geo[kBatch];  // mean x, mean y, A, beta
-    __shared__ float4 s_att[kBatch];  // gamma, opacity, red, green
-    __shared__ float s_blue[kBatch];
-    __shared__ uint32_t s_gid[kBatch];
-    __shared__ uint32_t s_max_last;
-    const int tile = blockIdx.x;
+    const int tile = (int)blockIdx.x * 4 + (int)(threadIdx.x / kWave);
+    if (tile >= a.tiles_x * a.tiles_y) return;
+    const int lane = threadIdx.x & (kWave - 1);
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const int px = tx * kTile + (threadIdx.x & (kTile - 1));
-    const int py = ty * kTile + (threadIdx.x / kTile);
-    const bool inside = px < a.width && py < a.height;
-    const float fpx = (float)px, fpy = (float)py;
+    const int col = lane & 15, row0 = lane >> 4;
+    const int px = tx * kTile + col;
+    const float fpx = (float)px;
+    const float x_lo = (float)(tx * kTile), x_hi = (float)(tx * kTile + kTile - 1);
+    const size_t npix = (size_t)a.width * a.height;
+    float fpy[4], T[4], G0[4], G1[4], G2[4], b0[4], b1[4], b2[4];
+    uint32_t last[4];
+    uint32_t max_last = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int py = ty * kTile + row0 + 4 * k;
+        fpy[k] = (float)py;
+        pin_vgpr(fpy[k]);
+        last[k] = 0;
+        T[k] = G0[k] = G1[k] = G2[k] = 0.0f;
+        if (px < a.width && py < a.height) {
+            const size_t pix = (size_t)py * a.width + px;
+            last[k] = a.n_contrib[pix];
+            T[k] = a.final_T[pix];
+            G0[k] = a.dL_dimage[pix];
+            G1[k] = a.dL_dimage[npix + pix];
+            G2[k] = a.dL_dimage[2 * npix + pix];
+        }
+        // colour of everything behind the current Gaussian: starts with the background
+        b0[k] = T[k] * a.bg[0];
+        b1[k] = T[k] * a.bg[1];
+        b2[k] = T[k] * a.bg[2];
+        max_last = max_last > last[k] ? max_last : last[k];
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const uint32_t other = (uint32_t)__shfl_xor((int)max_last, o, kWave);
+        max_last = max_last > other ? max_last : other;
+    }
     const uint32_t start = a.ranges[2 * tile];
     const float4 *spl = reinterpret_cast<const float4 *>(a.splats);
-    const size_t npix = (size_t)a.width * a.height, pix = (size_t)py * a.width + px;
 
-    uint32_t last = 0;
-    float T = 0.0f, G0 = 0.0f, G1 = 0.0f, G2 = 0.0f;
-    if (inside) {
-        last = a.n_contrib[pix];
-        T = a.final_T[pix];
-        G0 = a.dL_dimage[pix];
-        G1 = a.dL_dimage[npix + pix];
-        G2 = a.dL_dimage[2 * npix + pix];
-    }
-    // colour of everything behind the current Gaussian: starts with the background
-    float b0 = T * a.bg[0], b1 = T * a.bg[1], b2 = T * a.bg[2];
-    if (threadIdx.x == 0) s_max_last = 0;
-    __syncthreads();
-    atomicMax(&s_max_last, last);
-    __syncthreads();
-    const int max_last = (int)s_max_last;
-
-    for (int hi = max_last; hi > 0; hi -= kBatch) {
-        const int lo = hi > kBatch ? hi - kBatch : 0;
-        __syncthreads();
-        const int j = lo + (int)threadIdx.x;
+    for (int hi = (int)max_last; hi > 0; hi -= kWave) {
+        const int lo = hi > kWave ? hi - kWave : 0;
+        // a strip takes part while one of its pixels has blended list position >= lo
+        uint32_t alive = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (__ballot(last[k] > (uint32_t)lo) != 0ull) alive |= 1u << k;
+        const int j = lo + lane;
+        float mx = 0.f, my = 0.f, A = 0.f, beta = 0.f, gam = 0.f, sig = 0.f, r = 0.f, g = 0.f, bl = 0.f;
+        float elim = 0.f;
+        uint32_t gid = 0, hit = 0;
         if (j < hi) {
-            const size_t g = a.gids[start + j];
-            const float4 g0 = spl[3 * g], g1 = spl[3 * g + 1], g2 = spl[3 * g + 2];
-            s_geo[threadIdx.x] = g0;
-            s_att[threadIdx.x] = make_float4(g1.x, g1.y, g2.x, g2.y);
-            s_blue[threadIdx.x] = g2.z;
-            s_gid[threadIdx.x] = (uint32_t)g;
+            gid = a.gids[start + j];
+            const float4 g0 = spl[3 * (size_t)gid], g1 = spl[3 * (size_t)gid + 1], g2 = spl[3 * (size_t)gid + 2];
+            mx = g0.x; my = g0.y; A = g0.z; beta = g0.w; gam = g1.x; sig = g1.y; r = g2.x; g = g2.y; bl = g2.z;
+            // the forward's cull and blend threshold, computed identically
+            const float qlim = 2.0f * (__logf(sig) - kLnTau);
+            elim = kNegHalfLog2e * qlim;
+            if (qlim > -1e-3f) {
+                const float ql = fmaxf(qlim, 0.0f);
+                const float far = fabsf(mx - (x_lo + 7.5f)) + fabsf(my - (float)(ty * kTile) - 7.5f);
+                const float qcut = ql + 1e-3f * (1.0f + ql) +
+                                   1e-5f * far * (1.0f + sqrtf((A + gam) * ql));
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    float qmin = 3.0e38f;
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const float dy = my - (float)(ty * kTile + 4 * k + rr);
+                        const float lo_ = (mx - x_hi) + beta * dy, hi_ = (mx - x_lo) + beta * dy;
+                        const float um = lo_ > 0.0f ? lo_ : (hi_ < 0.0f ? -hi_ : 0.0f);
+                        qmin = fminf(qmin, A * um * um + gam * dy * dy);
+                    }
+                    if (qmin <= qcut) hit |= 1u << k;
+                }
+            }
         }
-        __syncthreads();
-        for (int k = hi - lo - 1; k >= 0; --k) {
+        const float A2 = A * kNegHalfLog2e, G2s = gam * kNegHalfLog2e;
+        uint64_t m[4], any = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            m[k] = ((alive >> k) & 1u) ? __ballot((hit >> k) & 1u) : 0ull;
+            any |= m[k];
+        }
+        while (any) {  // back to front: highest list position first
+            const int jj = 63 - __clzll((long long)any);
+            any &= ~(1ull << jj);
+            const float smx = bcast(mx, jj), smy = bcast(my, jj), sA = bcast(A, jj);
+            const float sbeta = bcast(beta, jj), sgam = bcast(gam, jj), ssig = bcast(sig, jj);
+            const float sA2 = bcast(A2, jj), sG2 = bcast(G2s, jj), selim = bcast(elim, jj);
+            const float sr = bcast(r, jj), sg = bcast(g, jj), sb = bcast(bl, jj);
+            const uint32_t pos = (uint32_t)(lo + jj);
+            const float dx = smx - fpx;
             float d[9];
 #pragma unroll
             for (int q = 0; q < 9; ++q) d[q] = 0.0f;
             bool contrib = false;
-            if ((uint32_t)(lo + k) < last) {
-                const float4 g = s_geo[k];
-                const float4 c = s_att[k];
-                const float dx = g.x - fpx, dy = g.y - fpy;
-                const float u = fmaf(g.w, dy, dx);
-                const float power = -0.5f * fmaf(g.z * u, u, c.x * (dy * dy));
-                if (!(power > 0.0f)) {
-                    const float e = __expf(power);
-                    const float raw = c.y * e;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!((m[k] >> jj) & 1ull)) continue;  // uniform: strip k missed
+                const float dy = smy - fpy[k];
+                const float u = fmaf(sbeta, dy, dx);
+                const float e2 = fmaf(sA2 * u, u, sG2 * (dy * dy));
+                if (pos < last[k] && e2 >= selim) {  // the forward blended it here
+                    contrib = true;
+                    const float e = __builtin_amdgcn_exp2f(e2);
+                    const float raw = ssig * e;
                     const float alpha = fminf(kAlphaMaxF, raw);
-                    if (!(alpha < kTauF)) {
-                        contrib = true;
-                        const float om = 1.0f - alpha;
-                        T = T / om;  // transmittance in front of this Gaussian
-                        const float w = alpha * T;
-                        const float cb = s_blue[k];
-                        d[6] = w * G0;
-                        d[7] = w * G1;
-                        d[8] = w * G2;
-                        const float dLda = G0 * (T * c.z - b0 / om) + G1 * (T * c.w - b1 / om) +
-                                           G2 * (T * cb - b2 / om);
-                        b0 = fmaf(w, c.z, b0);
-                        b1 = fmaf(w, c.w, b1);
-                        b2 = fmaf(w, cb, b2);
-                        if (!(raw > kAlphaMaxF)) {
-                            d[5] = dLda * e;  // d opacity
-                            const float dLdp = dLda * alpha;
-                            const float Au = g.z * u;
-                            d[2] = dLdp * (-0.5f * u * u);        // d A
-                            d[3] = dLdp * (-Au * dy);             // d beta
-                            d[4] = dLdp * (-0.5f * dy * dy);      // d gamma
-                            d[0] = dLdp * (-Au);                  // d mean x
-                            d[1] = dLdp * (-(Au * g.w + c.x * dy)); // d mean y
-                        }
+                    const float om = 1.0f - alpha;
+                    const float Tb = T[k] / om;  // transmittance in front of this Gaussian
+                    const float w = alpha * Tb;
+                    d[6] = fmaf(w, G0[k], d[6]);
+                    d[7] = fmaf(w, G1[k], d[7]);
+                    d[8] = fmaf(w, G2[k], d[8]);
+                    const float dLda = G0[k] * (Tb * sr - b0[k] / om) + G1[k] * (Tb * sg - b1[k] / om) +
+                                       G2[k] * (Tb * sb - b2[k] / om);
+                    b0[k] = fmaf(w, sr, b0[k]);
+                    b1[k] = fmaf(w, sg, b1[k]);
+                    b2[k] = fmaf(w, sb, b2[k]);
+                    T[k] = Tb;
+                    if (!(raw > kAlphaMaxF)) {  // a clamped alpha does not depend on the Gaussian
+                        d[5] = fmaf(dLda, e, d[5]);  // opacity
+                        const float dLdp = dLda * alpha;  // d/d(power), power = -q/2
+                        const float Au = sA * u;
+                        d[2] = fmaf(dLdp, -0.5f * u * u, d[2]);           // A
+                        d[3] = fmaf(dLdp, -Au * dy, d[3]);                // beta
+                        d[4] = fmaf(dLdp, -0.5f * dy * dy, d[4]);         // gamma
+                        d[0] = fmaf(dLdp, -Au, d[0]);                     // mean x
+                        d[1] = fmaf(dLdp, -(Au * sbeta + sgam * dy), d[1]);  // mean y
                     }
                 }
             }
             if (__ballot(contrib) != 0ull) {
 #pragma unroll
                 for (int q = 0; q < 9; ++q) d[q] = wave_sum(d[q]);
-                if ((threadIdx.x & (kWave - 1)) == 0) {
-                    float *dst = a.grad_splats + (size_t)s_gid[k] * 12;
+                if (lane == 0) {
+                    const uint32_t sgid = (uint32_t)__builtin_amdgcn_readlane((int)gid, jj);
+                    float *dst = a.grad_splats + (size_t)sgid * 12;
                     atomicAdd(dst + 0, d[0]);
                     atomicAdd(dst + 1, d[1]);
                     atomicAdd(dst + 2, d[2]);
@@ -148,7 +216,7 @@ hipError_t launch_raster_backward(const RasterBwdArgs &a, int64_t n, hipStream_t
     const int64_t m = 12 * (n > 0 ? n : 0);
     if (m > 0) k_zero_f32<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(a.grad_splats, m);
     const unsigned tiles = (unsigned)a.tiles_x * (unsigned)a.tiles_y;
-    k_raster_backward<<<tiles, 256, 0, s>>>(a);
+    k_raster_backward<<<(tiles + 3) / 4, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -144,54 +144,26 @@ __device__ __forceinline__ bool slice_bounds(const SliceArgs &a, int64_t &P, int
 }  // namespace
 
 // Low-byte histogram of the tiles of one slice, digit-major [256][live slices].
-// An owner's pairs in the slice cover whole or partial rows of its rectangle;
-// each row segment is a run of consecutive tile ids, i.e. a circular interval
-// of low bytes, added to a difference array (plus whole turns of 256 to every
-// digit), so the cost is per row segment rather than per pair.
 __global__ __launch_bounds__(kSortThreads) void k_bin_hist(const SliceArgs a, uint32_t *hist) {
     __shared__ Owners ow;
-    __shared__ int32_t diff[257];
-    __shared__ uint32_t turns;
+    __shared__ uint32_t h[kSortThreads / kWave][256];
     int64_t P, p0, p1, nb_live;
     if (!slice_bounds(a, P, p0, p1, nb_live)) return;
-    for (int i = threadIdx.x; i < 257; i += kSortThreads) diff[i] = 0;
-    if (threadIdx.x == 0) turns = 0u;
+    for (int i = threadIdx.x; i < (kSortThreads / kWave) * 256; i += kSortThreads) (&h[0][0])[i] = 0;
     load_owners(a, blockIdx.x, p0, p1, P, ow);
+    const int wid = threadIdx.x / kWave;
     const int cnt = (int)(p1 - p0);
-    // owners present in the table: the marks' population (== no unless a guard fired)
-    const int no = (int)(ow.mark_prefix[kEmitChunk / 32 - 1] +
-                         (uint32_t)__popc(ow.marks[kEmitChunk / 32 - 1]));
-    uint32_t my_turns = 0;
-    for (int o = threadIdx.x; o < no; o += kSortThreads) {
-        const uint32_t k0 = ow.rel[o], k1 = o + 1 < no ? ow.rel[o + 1] : (uint32_t)cnt;
-        const uint32_t w = ow.w[o];
-        if (w == 0u || k1 <= k0) continue;  // not an owner row (cannot happen with consistent offsets)
-        const uint32_t ma = o == 0 ? ow.m0 : 0u, mb = ma + (k1 - k0);  // rectangle indices [ma, mb)
-        for (uint32_t q = ma / w; q * w < mb; ++q) {
-            const uint32_t xa = ma > q * w ? ma - q * w : 0u;
-            const uint32_t xb = mb - q * w < w ? mb - q * w : w;
-            const uint32_t t0 = ((uint32_t)ow.y0[o] + q) * (uint32_t)a.tiles_x + ow.x0[o] + xa;
-            const uint32_t len = xb - xa;
-            my_turns += len >> 8;
-            const uint32_t r = len & 255u, d0 = t0 & 255u, d1 = d0 + r;
-            if (r) {
-                atomicAdd(&diff[d0], 1);
-                if (d1 <= 256u) {
-                    atomicAdd(&diff[d1], -1);
-                } else {
-                    atomicAdd(&diff[0], 1);
-                    atomicAdd(&diff[d1 - 256u], -1);
-                }
-            }
-        }
+    for (int k = threadIdx.x; k < cnt; k += kSortThreads) {
+        uint32_t tile, j;
+        slice_pair(ow, k, a.tiles_x, tile, j);
+        atomicAdd(&h[wid][tile & 255u], 1u);
     }
-    if (my_turns) atomicAdd(&turns, my_turns);
     __syncthreads();
-    // inclusive prefix of the difference array = count per digit
-    const int32_t v = diff[threadIdx.x];
-    int32_t tot;
-    const int32_t ex = block_exclusive_scan<kSortThreads, int32_t>(v, (int32_t *)ow.wt, &tot);
-    hist[(int64_t)threadIdx.x * nb_live + blockIdx.x] = (uint32_t)(ex + v) + turns;
+    const int d = threadIdx.x;
+    uint32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < kSortThreads / kWave; ++w) tot += h[w][d];
+    hist[(int64_t)d * nb_live + blockIdx.x] = tot;
 }
 
 // Pass 1: regenerate the slice, rank by the tile's low byte, write.  FINAL

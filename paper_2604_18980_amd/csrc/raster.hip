@@ -15,10 +15,12 @@
 //   reach alpha >= tau (the exponent's minimum over each strip row, taken over
 //   the continuous column interval, against 2 ln(opacity/tau) plus a margin
 //   that covers float32 rounding); four ballots turn that into 64-bit masks.
-//   The wave walks the set bits in list order, broadcasts each record into
-//   scalar registers with v_readlane and evaluates only the hit strips.  A
-//   skipped strip has alpha < tau at every pixel, so results are unchanged.
-//   No LDS and no barriers: waves run and retire independently.
+//   The lanes park their records in the wave's own LDS slots, and the wave
+//   walks the set bits in list order, reading each hit record with one
+//   uniform-address (broadcast) LDS read per 16 bytes -- the next record's
+//   read overlapping the current evaluation -- and evaluates only the hit
+//   strips.  A skipped strip has alpha < tau at every pixel, so results are
+//   unchanged.  No barriers: waves run and retire independently.
 #include "gsr_internal.hpp"
 
 namespace gsr {
@@ -30,10 +32,6 @@ constexpr float kAlphaMaxF = 0.99f;
 constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
 constexpr float kLnTau = -5.5412635451584258f;            // ln(1/255)
 
-
-__device__ __forceinline__ float bcast(float v, int lane) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
 
 __device__ __forceinline__ void store_pixel(const RasterArgs &a, int px, int py, float cr, float cg,
                                             float cb, float T, uint32_t last, uint32_t ev) {
@@ -106,6 +104,9 @@ __device__ __forceinline__ void tile_block(const RasterArgs &a, int tile) {
 // EV: also count, per pixel, the list entries evaluated (n_evaluated output).
 template <bool EV>
 __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
+    __shared__ float4 s0[4][64], s1[4][64];
+    __shared__ float2 s2[4][64];
+    const int wid = threadIdx.x / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int col = lane & 15, row0 = lane >> 4;
@@ -180,18 +181,17 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
             m[k] = ((alive >> k) & 1u) ? __ballot((hit >> k) & 1u) : 0ull;
             any |= m[k];
         }
-        while (any) {
-            const int jj = __ffsll((long long)any) - 1;
-            any &= any - 1ull;
-            const float smx = bcast(mx, jj), smy = bcast(my, jj), sA2 = bcast(A2, jj);
-            const float sbeta = bcast(beta, jj), sG2 = bcast(G2, jj), ssig = bcast(sig, jj);
-            const float sr = bcast(r, jj), sg = bcast(g, jj), sb = bcast(bl, jj);
-            const float selim = bcast(elim, jj);
+        s0[wid][lane] = make_float4(mx, my, A2, beta);
+        s1[wid][lane] = make_float4(G2, sig, elim, r);
+        s2[wid][lane] = make_float2(g, bl);
+        auto eval = [&](const float4 r0, const float4 r1, const float2 r2, const int cur) {
+            const float smx = r0.x, smy = r0.y, sA2 = r0.z, sbeta = r0.w;
+            const float sG2 = r1.x, ssig = r1.y, selim = r1.z, sr = r1.w, sg = r2.x, sb = r2.y;
             const float dx = smx - fpx;
-            const uint32_t pos = (base - start) + (uint32_t)jj + 1u;
+            const uint32_t pos = (base - start) + (uint32_t)cur + 1u;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (!((m[k] >> jj) & 1ull)) continue;  // uniform: strip k missed
+                if (!((m[k] >> cur) & 1ull)) continue;  // uniform: strip k missed
                 const float dy = smy - fpy[k];
                 const float u = fmaf(sbeta, dy, dx);
                 const float e2 = fmaf(sA2 * u, u, sG2 * (dy * dy));
@@ -212,6 +212,30 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
                     off[k] = stop ? -INFINITY : off[k];
                 }
             }
+        };
+        if (any) {
+            // two record sets in flight: while one hit Gaussian is evaluated the
+            // next one's record is being read (unconditionally, from slot 0 when
+            // there is none) so no register copies are needed
+            int ja = __ffsll((long long)any) - 1;
+            any &= any - 1ull;
+            float4 a0 = s0[wid][ja], a1 = s1[wid][ja];
+            float2 a2 = s2[wid][ja];
+            for (;;) {
+                const bool hb = any != 0ull;
+                const int jb = hb ? __ffsll((long long)any) - 1 : 0;
+                any &= any - 1ull;
+                const float4 b0 = s0[wid][jb], b1 = s1[wid][jb];
+                const float2 b2 = s2[wid][jb];
+                eval(a0, a1, a2, ja);
+                if (!hb) break;
+                const bool ha = any != 0ull;
+                ja = ha ? __ffsll((long long)any) - 1 : 0;
+                any &= any - 1ull;
+                a0 = s0[wid][ja]; a1 = s1[wid][ja]; a2 = s2[wid][ja];
+                eval(b0, b1, b2, jb);
+                if (!ha) break;
+            }
         }
     }
 #pragma unroll
@@ -220,6 +244,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
         if (px < a.width && py < a.height) store_pixel(a, px, py, cr[k], cg[k], cb[k], T[k], last[k], ev[k]);
     }
 }
+
 
 // ------------------------------------------------------------- one view
 template <int BATCH>

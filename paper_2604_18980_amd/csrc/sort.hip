@@ -20,10 +20,12 @@ namespace gsr {
 // ------------------------------------------------------------------- scans
 template <typename T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T *in, int64_t m, uint64_t *parts,
-                                                              DevExtent ext) {
+                                                              DevExtent ext, int64_t *total) {
     __shared__ T wt[kScanThreads / kWave];
     m = ext.resolve(m);
     const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    // the total of an empty input; k_scan_down's last live block overwrites it
+    if (total && blockIdx.x == 0 && threadIdx.x == 0) *total = 0;
     if (base >= m) {  // past the live elements: contributes nothing
         if (threadIdx.x == 0) parts[blockIdx.x] = 0;
         return;
@@ -39,28 +41,22 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T *in, int64
     if (threadIdx.x == 0) parts[blockIdx.x] = (uint64_t)tot;
 }
 
-// single block: exclusive scan of the partials in place; total -> *total
-__global__ __launch_bounds__(1024) void k_scan_top(uint64_t *parts, int64_t nparts, int64_t *total) {
-    __shared__ uint64_t wt[1024 / kWave];
-    uint64_t carry = 0;
-    for (int64_t b = 0; b < nparts; b += 1024) {
-        const int64_t i = b + threadIdx.x;
-        const uint64_t v = i < nparts ? parts[i] : 0;
-        uint64_t tot;
-        const uint64_t ex = block_exclusive_scan<1024, uint64_t>(v, wt, &tot);
-        if (i < nparts) parts[i] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0 && total) *total = (int64_t)carry;
-}
-
 // Each block rescans its chunk: thread t owns kScanItems consecutive elements.
+// The block's offset, the sum of the partials of the blocks before it, is
+// reduced here (the partial count is small), so no separate pass scans them;
+// the last live block stores the grand total.
 template <typename T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const T *in, T *out, int64_t m,
-                                                            const uint64_t *parts, DevExtent ext) {
+                                                            const uint64_t *parts, DevExtent ext,
+                                                            int64_t *total) {
     __shared__ T wt[kScanThreads / kWave];
+    __shared__ uint64_t wt64[kScanThreads / kWave];
     m = ext.resolve(m);
     if ((int64_t)blockIdx.x * kScanChunk >= m) return;
+    uint64_t before = 0;
+    for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanThreads) before += parts[i];
+    uint64_t btot;
+    block_exclusive_scan<kScanThreads, uint64_t>(before, wt64, &btot);
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
     T v[kScanItems];
     T acc = 0;
@@ -71,22 +67,29 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const T *in, T *out,
         acc += v[i];
     }
     T tot;
-    T run = block_exclusive_scan<kScanThreads, T>(acc, wt, &tot) + (T)parts[blockIdx.x];
+    T run = block_exclusive_scan<kScanThreads, T>(acc, wt, &tot) + (T)btot;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t idx = base + i;
         if (idx < m) out[idx] = run;
         run += v[i];
     }
+    if (total && threadIdx.x == 0 && ((int64_t)blockIdx.x + 1) * kScanChunk >= m)
+        *total = (int64_t)(btot + (uint64_t)tot);
 }
+
+__global__ void k_set_total(int64_t *total) { *total = 0; }
 
 template <typename T>
 static hipError_t scan_exclusive(const T *in, T *out, int64_t m, uint64_t *parts, int64_t *total,
                                  DevExtent ext, hipStream_t s) {
     const int64_t nparts = (m + kScanChunk - 1) / kScanChunk;
-    if (nparts > 0) k_scan_reduce<T><<<(unsigned)nparts, kScanThreads, 0, s>>>(in, m, parts, ext);
-    k_scan_top<<<1, 1024, 0, s>>>(parts, nparts, total);
-    if (nparts > 0) k_scan_down<T><<<(unsigned)nparts, kScanThreads, 0, s>>>(in, out, m, parts, ext);
+    if (nparts == 0) {
+        if (total) k_set_total<<<1, 1, 0, s>>>(total);
+        return hipGetLastError();
+    }
+    k_scan_reduce<T><<<(unsigned)nparts, kScanThreads, 0, s>>>(in, m, parts, ext, total);
+    k_scan_down<T><<<(unsigned)nparts, kScanThreads, 0, s>>>(in, out, m, parts, ext, total);
     return hipGetLastError();
 }
 
