@@ -301,7 +301,6 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_scatter2(const uint32_t *p
                                                                uint32_t *sorted_tiles) {
     __shared__ RankSmem sm;
     __shared__ uint32_t skey[kSortChunk];
-    __shared__ uint32_t sval[kSortChunk];
     __shared__ uint32_t s_bfirst[257];
     Pass2Block pb;
     if (!pass2_block(plan, nb2_p, s_bfirst, pb)) return;
@@ -317,7 +316,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_scatter2(const uint32_t *p
     }
     const uint32_t l = (uint32_t)pb.l;
     rank_stage_write(
-        key, val, pb.cnt, kRankBits, sm, skey, sval,
+        key, val, pb.cnt, kRankBits, sm, skey, nullptr,
         [&](uint32_t word, uint32_t) { return sorted_ids[word & kRankMask]; },
         [&](int64_t dst, uint32_t word, uint32_t gid) {
             sorted_gids[dst] = gid;

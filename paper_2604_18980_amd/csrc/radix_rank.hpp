@@ -43,6 +43,8 @@ __device__ __forceinline__ int rank_pos(int i) {
 // LDS staging arrays, which may alias memory the caller no longer reads (item
 // generation must be complete).  Contains barriers; the caller must have run
 // rank_init, set gbase and issued a barrier.
+// sval may be null when the values are not needed (fetch then gets 0).
+// Output positions are below 2^32 (capacities are 32-bit).
 template <class Fetch, class Store>
 __device__ __forceinline__ void rank_stage_write(const uint32_t (&key)[kSortItems],
                                                  const uint32_t (&val)[kSortItems], int cnt,
@@ -93,26 +95,25 @@ __device__ __forceinline__ void rank_stage_write(const uint32_t (&key)[kSortItem
         const uint32_t d = (key[i] >> shift) & 255u;
         const uint32_t p = sm.dstart[d] + sm.wcnt[wid][d] + rank[i];
         skey[p] = key[i];
-        sval[p] = val[i];
+        if (sval) sval[p] = val[i];
     }
     __syncthreads();
     // position p = threadIdx.x + i * kSortThreads: consecutive threads take
     // consecutive staged items, so each digit's run is stored contiguously
-    uint32_t k[kSortItems], pay[kSortItems];
-    int64_t dst[kSortItems];
+    uint32_t k[kSortItems], pay[kSortItems], dst[kSortItems];
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const int p = threadIdx.x + i * kSortThreads;
         if (p < cnt) {
             k[i] = skey[p];
             const uint32_t d = (k[i] >> shift) & 255u;
-            dst[i] = (int64_t)sm.gbase[d] + (p - (int)sm.dstart[d]);
-            pay[i] = fetch(k[i], sval[p]);
+            dst[i] = sm.gbase[d] + ((uint32_t)p - sm.dstart[d]);
+            pay[i] = fetch(k[i], sval ? sval[p] : 0u);
         }
     }
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i)
-        if (threadIdx.x + i * kSortThreads < cnt) store(dst[i], k[i], pay[i]);
+        if (threadIdx.x + i * kSortThreads < cnt) store((int64_t)dst[i], k[i], pay[i]);
 }
 
 }  // namespace gsr
