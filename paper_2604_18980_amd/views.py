@@ -15,9 +15,14 @@ from . import render as R
 
 
 class MultiView:
+    """lanes: number of streams the per-view preprocess and binning chains are
+    spread over (views are independent until the shared raster launch, so
+    their many small kernels overlap); 1 keeps everything on one stream."""
+
     def __init__(self, scene: R.DeviceScene, cams, mode=None, bg=(0.0, 0.0, 0.0), cfg=None,
-                 slack=1.02):
+                 slack=1.02, lanes=4):
         self.scene, self.cams, self.bg = scene, list(cams), tuple(bg)
+        self.lanes = max(1, int(lanes))
         self.mode = gsr.mode_struct(**(mode or {}))
         self.cam_s = [gsr.camera_struct(c) for c in self.cams]
         self.cfg = cfg
@@ -43,14 +48,28 @@ class MultiView:
         self.ws = torch.empty(gsr.gs_views_workspace_size(self.n_views, self.total_tiles),
                               dtype=torch.uint8, device=dev)
         self.clock = torch.zeros(1 + self.n_views, dtype=torch.int64, device=dev)
+        self.side = [torch.cuda.Stream(device=dev) for _ in range(self.lanes)] if self.lanes > 1 else []
         self.graph = None
 
     def enqueue(self, stream=None):
-        for fb, cs in zip(self.fbs, self.cam_s):
-            R.run_preprocess(self.scene, cs, self.mode, fb, stream)
-            R.run_bin(fb, cs, stream)
+        main = stream if stream is not None else torch.cuda.current_stream()
+        if not self.side:
+            for fb, cs in zip(self.fbs, self.cam_s):
+                R.run_preprocess(self.scene, cs, self.mode, fb, main)
+                R.run_bin(fb, cs, main)
+        else:
+            # fork: every lane starts after the work already on the main stream;
+            # view v runs on lane v % lanes; join before the shared raster launch
+            for s in self.side:
+                s.wait_stream(main)
+            for v, (fb, cs) in enumerate(zip(self.fbs, self.cam_s)):
+                s = self.side[v % len(self.side)]
+                R.run_preprocess(self.scene, cs, self.mode, fb, s)
+                R.run_bin(fb, cs, s)
+            for s in self.side:
+                main.wait_stream(s)
         gsr.gs_rasterize_views(self.views, self.d_views, self.n_views, self.bg, self.cfg,
-                               self.clock, self.ws, stream)
+                               self.clock, self.ws, main)
 
     def overflowed(self):
         return any(int(fb.num_pairs.item()) > fb.capacity for fb in self.fbs)
