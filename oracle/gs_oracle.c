@@ -214,8 +214,8 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
         double q[4] = {quats[g], quats[n + g], quats[2 * n + g], quats[3 * n + g]};
         double qn = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
         if (qn > 0.0) {
-            double r = sqrt(qn);
-            for (int k = 0; k < 4; ++k) q[k] = q[k] / r;
+            double ir = 1.0 / sqrt(qn);
+            for (int k = 0; k < 4; ++k) q[k] = q[k] * ir;
         } else {
             q[0] = 1.0; q[1] = q[2] = q[3] = 0.0;
         }
@@ -238,14 +238,15 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
            perspective map at the clamped point) */
         double limx = FRUSTUM_SLACK * ((0.5 * width) / fx);
         double limy = FRUSTUM_SLACK * ((0.5 * height) / fy);
-        double txz = p[0] / p[2], tyz = p[1] / p[2];
+        double ipz = 1.0 / p[2];
+        double txz = p[0] * ipz, tyz = p[1] * ipz;
         if (txz < -limx) txz = -limx;
         if (txz > limx) txz = limx;
         if (tyz < -limy) tyz = -limy;
         if (tyz > limy) tyz = limy;
         double xc = txz * p[2], yc = tyz * p[2];
-        double J[2][3] = {{fx / p[2], 0.0, -(fx * xc) / (p[2] * p[2])},
-                          {0.0, fy / p[2], -(fy * yc) / (p[2] * p[2])}};
+        double J[2][3] = {{fx * ipz, 0.0, -(fx * xc) * (ipz * ipz)},
+                          {0.0, fy * ipz, -(fy * yc) * (ipz * ipz)}};
         double T[2][3], U[2][3], S2[2][2];
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 3; ++j) {
@@ -269,8 +270,8 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
 
         /* determinant, conic (eq. 1 uses the inverse of G_cov), mean, depth */
         double det = a * c - b * b;
-        double u = fx * (p[0] / p[2]) + cx;
-        double v = fy * (p[1] / p[2]) + cy;
+        double u = fx * (p[0] * ipz) + cx;
+        double v = fy * (p[1] * ipz) + cy;
         if (!(is_finite(u) && is_finite(v) && is_finite(a) && is_finite(b) && is_finite(c))) continue;
         if (!(det > 0.0)) continue;
         double sigma = 1.0 / (1.0 + exp(-(double)opacity_logits[g]));
@@ -279,9 +280,10 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
         conic[3 * g] = c / det;
         conic[3 * g + 1] = -b / det;
         conic[3 * g + 2] = a / det;
+        double ic = 1.0 / c;
         quad[3 * g] = c / det;
-        quad[3 * g + 1] = -b / c;
-        quad[3 * g + 2] = 1.0 / c;
+        quad[3 * g + 1] = -b * ic;
+        quad[3 * g + 2] = ic;
         cov2d[3 * g] = a; cov2d[3 * g + 1] = b; cov2d[3 * g + 2] = c;
         opacity[g] = sigma;
         depth[g] = p[2];
@@ -677,15 +679,16 @@ void orc_preprocess_backward(int64_t n, const float *means, const float *log_sca
                 for (int k = 0; k < 3; ++k) S3[i][j] += M[i][k] * M[j][k];
             }
         double limx = FRUSTUM_SLACK * ((0.5 * width) / fx), limy = FRUSTUM_SLACK * ((0.5 * height) / fy);
-        double txz = p[0] / p[2], tyz = p[1] / p[2];
+        double ipz = 1.0 / p[2];
+        double txz = p[0] * ipz, tyz = p[1] * ipz;
         int clx = 0, cly = 0;
         if (txz < -limx) { txz = -limx; clx = -1; }
         if (txz > limx) { txz = limx; clx = 1; }
         if (tyz < -limy) { tyz = -limy; cly = -1; }
         if (tyz > limy) { tyz = limy; cly = 1; }
         double xc = txz * p[2], yc = tyz * p[2];
-        double J[2][3] = {{fx / p[2], 0.0, -(fx * xc) / (p[2] * p[2])},
-                          {0.0, fy / p[2], -(fy * yc) / (p[2] * p[2])}};
+        double J[2][3] = {{fx * ipz, 0.0, -(fx * xc) * (ipz * ipz)},
+                          {0.0, fy * ipz, -(fy * yc) * (ipz * ipz)}};
         double T[2][3];
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 3; ++j) {

@@ -244,6 +244,7 @@ gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_mo
     a.lut_depth_max = mode->lut_depth_max;
     for (int i = 0; i < GS_LUT_BINS; ++i) a.lut[i] = mode->t_upper[i];
     sh_constants(a.shc);
+    for (int i = 0; i < 16; ++i) a.shcf[i] = (float)a.shc[i];
     a.splats = splats;
     a.rects = rects;
     a.tiles_touched = tiles_touched;

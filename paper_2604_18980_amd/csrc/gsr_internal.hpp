@@ -23,6 +23,7 @@ struct PreprocessArgs {
     double K, lut_depth_max;
     float lut[kLutBins];
     double shc[16];  // real-SH normalisation constants, see preprocess.hip
+    float shcf[16];  // the same, rounded to float32 (colour is evaluated in float32)
     float *splats;
     uint64_t *rects;
     uint32_t *tiles_touched;

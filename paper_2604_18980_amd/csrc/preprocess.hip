@@ -10,7 +10,7 @@
 //
 // The inverse covariance is stored as the sum of squares
 //     d^T Sigma2^-1 d = A (dx + beta dy)^2 + gamma dy^2,
-//     A = c / det, beta = -b / c, gamma = 1 / c      (Sigma2 = [[a, b], [b, c]]),
+//     A = c / det, beta = -b (1 / c), gamma = 1 / c  (Sigma2 = [[a, b], [b, c]]),
 // which is exact algebra (block LDL^T of Sigma2^-1) and has no cancellation:
 // the expanded A dx^2 + 2B dx dy + C dy^2 of a thin Gaussian evaluated far
 // from its centre loses most of its float32 digits.
@@ -39,28 +39,28 @@ __device__ __forceinline__ void store_splat(float *dst, float4 a, float4 b, floa
 // Real spherical harmonics (Condon-Shortley phase, coefficient k = l^2+l+m)
 // at the unit direction (x, y, z), as polynomials; c[] holds the
 // normalisation constants computed on the host (see sh_constants()).
-__device__ __forceinline__ void sh_eval(int degree, double x, double y, double z, const double *c,
-                                        double *Y) {
+template <typename R>
+__device__ __forceinline__ void sh_eval(int degree, R x, R y, R z, const R *c, R *Y) {
     Y[0] = c[0];
     if (degree < 1) return;
     Y[1] = -c[1] * y;
     Y[2] = c[1] * z;
     Y[3] = -c[1] * x;
     if (degree < 2) return;
-    const double xx = x * x, yy = y * y, zz = z * z;
+    const R xx = x * x, yy = y * y, zz = z * z;
     Y[4] = c[2] * (x * y);
     Y[5] = -c[2] * (y * z);
-    Y[6] = c[3] * (3.0 * zz - 1.0);
+    Y[6] = c[3] * (R(3) * zz - R(1));
     Y[7] = -c[2] * (x * z);
     Y[8] = c[4] * (xx - yy);
     if (degree < 3) return;
-    Y[9] = -c[5] * (y * (3.0 * xx - yy));
+    Y[9] = -c[5] * (y * (R(3) * xx - yy));
     Y[10] = c[6] * (x * y * z);
-    Y[11] = -c[7] * (y * (5.0 * zz - 1.0));
-    Y[12] = c[8] * (z * (5.0 * zz - 3.0));
-    Y[13] = -c[7] * (x * (5.0 * zz - 1.0));
+    Y[11] = -c[7] * (y * (R(5) * zz - R(1)));
+    Y[12] = c[8] * (z * (R(5) * zz - R(3)));
+    Y[13] = -c[7] * (x * (R(5) * zz - R(1)));
     Y[14] = c[9] * (z * (xx - yy));
-    Y[15] = -c[5] * (x * (xx - 3.0 * yy));
+    Y[15] = -c[5] * (x * (xx - R(3) * yy));
 }
 }  // namespace
 
@@ -100,8 +100,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
         double qw = fqw, qx = fqx, qy = fqy, qz = fqz;
         const double qn = qw * qw + qx * qx + qy * qy + qz * qz;
         if (qn > 0.0) {
-            const double r = sqrt(qn);
-            qw = qw / r; qx = qx / r; qy = qy / r; qz = qz / r;
+            const double ir = 1.0 / sqrt(qn);
+            qw = qw * ir; qx = qx * ir; qy = qy * ir; qz = qz * ir;
         } else {
             qw = 1.0; qx = 0.0; qy = 0.0; qz = 0.0;
         }
@@ -123,12 +123,13 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
         const double s22 = m20 * m20 + m21 * m21 + m22 * m22;
 
         // EWA: Jacobian of the perspective map at the clamped point, T = J W
-        double txz = px / pz, tyz = py / pz;
+        const double ipz = 1.0 / pz;
+        double txz = px * ipz, tyz = py * ipz;
         txz = txz < -a.limx ? -a.limx : (txz > a.limx ? a.limx : txz);
         tyz = tyz < -a.limy ? -a.limy : (tyz > a.limy ? a.limy : tyz);
         const double xc = txz * pz, yc = tyz * pz;
-        const double j00 = a.fx / pz, j02 = -(a.fx * xc) / (pz * pz);
-        const double j11 = a.fy / pz, j12 = -(a.fy * yc) / (pz * pz);
+        const double j00 = a.fx * ipz, j02 = -(a.fx * xc) * (ipz * ipz);
+        const double j11 = a.fy * ipz, j12 = -(a.fy * yc) * (ipz * ipz);
         const double t00 = j00 * a.R[0] + j02 * a.R[6];
         const double t01 = j00 * a.R[1] + j02 * a.R[7];
         const double t02 = j00 * a.R[2] + j02 * a.R[8];
@@ -147,8 +148,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
         const double cc = (u10 * t10 + u11 * t11 + u12 * t12) + kDilation;
 
         const double det = ca * cc - cb * cb;
-        const double u = a.fx * (px / pz) + a.cx;
-        const double v = a.fy * (py / pz) + a.cy;
+        const double u = a.fx * (px * ipz) + a.cx;
+        const double v = a.fy * (py * ipz) + a.cy;
         const bool finite = isfinite(u) && isfinite(v) && isfinite(ca) && isfinite(cb) && isfinite(cc);
         if (finite && det > 0.0) {
             const double sigma = 1.0 / (1.0 + exp(-(double)fop));
@@ -194,29 +195,32 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
                 if (tiles > 0) {
                     rect = (uint64_t)x0 | ((uint64_t)y0 << 16) | ((uint64_t)x1 << 32) |
                            ((uint64_t)y1 << 48);
-                    // colour: SH along the unit view direction, +0.5, clamped at 0
-                    double dx = mx - a.campos[0], dy = my - a.campos[1], dz = mz - a.campos[2];
-                    const double len = sqrt(dx * dx + dy * dy + dz * dz);
-                    dx = dx / len; dy = dy / len; dz = dz / len;
+                    // colour: SH along the unit view direction, +0.5, clamped at 0.  No
+                    // discrete output depends on it, so it runs in float32 (the
+                    // camera-to-mean difference is formed in double, then rounded).
+                    const float ex = (float)(mx - a.campos[0]), ey = (float)(my - a.campos[1]),
+                                ez = (float)(mz - a.campos[2]);
+                    const float il = __builtin_amdgcn_rsqf(fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
                     constexpr int nsh = (DEG + 1) * (DEG + 1);
                     float f[nsh * 3];
 #pragma unroll
                     for (int k = 0; k < nsh * 3; ++k) f[k] = a.sh[(size_t)k * n + g];
-                    double Y[16];
-                    sh_eval(DEG, dx, dy, dz, a.shc, Y);
-                    double rgb[3];
+                    float Y[16];
+                    sh_eval<float>(DEG, ex * il, ey * il, ez * il, a.shcf, Y);
+                    float rgb[3];
 #pragma unroll
                     for (int ch = 0; ch < 3; ++ch) {
-                        double acc = 0.0;
+                        float acc = 0.0f;
 #pragma unroll
-                        for (int k = 0; k < nsh; ++k) acc += (double)f[k * 3 + ch] * Y[k];
-                        acc += 0.5;
-                        rgb[ch] = acc < 0.0 ? 0.0 : acc;
+                        for (int k = 0; k < nsh; ++k) acc = fmaf(f[k * 3 + ch], Y[k], acc);
+                        acc += 0.5f;
+                        rgb[ch] = acc < 0.0f ? 0.0f : acc;
                     }
+                    const double icc = 1.0 / cc;
                     store_splat(a.splats + (size_t)g * 12,
-                                make_float4((float)u, (float)v, (float)(cc / det), (float)(-cb / cc)),
-                                make_float4((float)(1.0 / cc), (float)sigma, (float)pz, (float)th),
-                                make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], (float)sc));
+                                make_float4((float)u, (float)v, (float)(cc / det), (float)(-cb * icc)),
+                                make_float4((float)icc, (float)sigma, (float)pz, (float)th),
+                                make_float4(rgb[0], rgb[1], rgb[2], (float)sc));
                 }
             }
         }
