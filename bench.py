@@ -8,7 +8,7 @@ through the C-ABI with the scene and every buffer already resident in HBM
 (pair buffers sized beforehand, so no host round trip inside the timed
 region).  K is binary-searched on the
 measured view so that PSNR(AdaGScale vs plain) sits at the quality point
-that corresponds to the paper's 0.5 dB drop (see DESIGN.md).
+that corresponds to the paper's 0.5 dB drop.
 
 Prints ONE JSON line.  Single GPU only.
 """
@@ -28,13 +28,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FPS @4608x3456 6M-Gaussian scene, AdaGScale vs plain 3D-GS; pairs; PSNR"
 PEAK_HBM_GBS = 8000.0
+# FP32 vector peak: 256 CUs x 4 SIMDs x 32 FP32 lanes x 2 FLOP (FMA) x 2.4 GHz,
+# the published figure; a wave64 FP32 instruction issues in two cycles on
+# gfx950 (measured: ~2.5 cycles per dependent-free v_fma_f32 including loop
+# overhead), so no packed-FP32 instructions are needed to reach it.
 PEAK_FP32_TFLOPS = 157.3
-# Per evaluation of eq. (1)-(2) for one (pixel, Gaussian): dx, dy (2), the
-# sum-of-squares exponent (u = dx + beta dy: 2; A u^2 + gamma dy^2: 5;
-# times -1/2: 1), exp (1), times opacity (1), clamp (1), tau test (1),
-# 1 - alpha (1), T (1 - alpha) (1), stop test (1), alpha T (1), three colour
-# FMAs (6): 25 floating-point operations.
-FLOP_PER_EVAL = 25
+# FLOP of one evaluation of eq. (1)-(2) at one pixel, in two parts.  Test:
+# dx, dy (2), u = dx + beta dy (2), A u^2 (2), gamma dy^2 (2), their sum (1),
+# the live-and-alpha >= tau test on the exponent (1) = 10.  Blend, where it
+# passes: exp (1), times opacity (1), clamp (1), alpha T (1), T - alpha T (1),
+# the stop test (1), three colour FMAs (6) = 12.
+FLOP_TEST = 10
+FLOP_BLEND = 12
 PSNR_TARGET_DB = 29.8
 # HBM bytes of one AdaGScale-frame raster launch (K = 459.18) from rocprofv3 FETCH_SIZE x 2.0
 # + WRITE_SIZE x 1.0 (copy-calibrated; profiles/city_6M_4608x3456_hbm_counters.md), valid
@@ -61,6 +66,10 @@ def parse():
                    help="city: the headline FPS line; diff: forward+backward on the 1M "
                         "differentiable workload; batched: 64 views in one graph")
     p.add_argument("--views", type=int, default=64)
+    p.add_argument("--ada-only", action="store_true",
+                   help="with --K: run only AdaGScale frames (no plain frames, no staged "
+                        "reference), so a profiler's per-kernel statistics cover the "
+                        "measured workload alone")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="also run one device copy of this many MiB (a known-size kernel "
                         "for calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -157,14 +166,12 @@ def graph_frames(torch, R, scene, cam_s, mode_s, fb, steps, warmup):
     return float(np.median(ms)), ms
 
 
-def count_evaluations(torch, R, fb, cam_s):
-    """Algorithmic evaluations of eq. (1): per pixel, the list entries up to and
-    including the one that stopped it (the whole list if none did), as the
-    rasterizer reports them."""
-    ne = torch.empty((fb.height, fb.width), dtype=torch.int32, device=fb.image.device)
-    R.run_raster(fb, cam_s, (0.0, 0.0, 0.0), n_evaluated=ne)
-    torch.cuda.synchronize()
-    return int(ne.to(torch.int64).sum().item())
+def raster_work(R, fb, cam_s):
+    """The rasterizer's work on this frame's lists (gs_raster_work): list-bounded
+    evaluations (per pixel: entries up to and including the stopping one),
+    executed strip evaluations (64 pixel evaluations each), blended pixel
+    evaluations, list entries loaded."""
+    return R.raster_work(fb, cam_s)
 
 
 def psnr_t(torch, a, b):
@@ -402,44 +409,58 @@ def main():
     cam_s = gsr.camera_struct(cam)
     stream = torch.cuda.current_stream()
 
-    # plain frame, to size buffers and as the PSNR reference
-    fb_p = R.render(scene, cam, fb=None, slack=1.05)
-    torch.cuda.synchronize()
-    P_plain = int(fb_p.num_pairs.item())
-    log(f"plain pairs {P_plain}")
-    fb_a = R.FrameBuffers(scene.n, cam["width"], cam["height"], int(P_plain * 1.05) + 1024, dev)
-    K = args.K if args.K is not None else search_K(torch, R, gsr, scene, cam, cam_s, fb_p, fb_a, stream)
-    R.render(scene, cam, adagscale=True, K=K, fb=fb_a)
-    torch.cuda.synchronize()
-    P_ada = int(fb_a.num_pairs.item())
-    psnr = psnr_t(torch, fb_a.image, fb_p.image)
-    ssim = ssim_t(torch, fb_a.image, fb_p.image)
-    log(f"K={K} pairs {P_ada} psnr {psnr:.2f} ssim {ssim:.4f}")
-    E_plain = count_evaluations(torch, R, fb_p, cam_s)
-    E_ada = count_evaluations(torch, R, fb_a, cam_s)
+    if args.ada_only and args.K is None:
+        raise SystemExit("--ada-only needs --K")
+    if args.ada_only:
+        K = args.K
+        fb_a = R.render(scene, cam, adagscale=True, K=K, fb=None, slack=1.05)
+        torch.cuda.synchronize()
+        P_ada = int(fb_a.num_pairs.item())
+        psnr = ssim = None
+        P_plain = W_plain = None
+    else:
+        # plain frame, to size buffers and as the PSNR reference
+        fb_p = R.render(scene, cam, fb=None, slack=1.05)
+        torch.cuda.synchronize()
+        P_plain = int(fb_p.num_pairs.item())
+        log(f"plain pairs {P_plain}")
+        fb_a = R.FrameBuffers(scene.n, cam["width"], cam["height"], int(P_plain * 1.05) + 1024, dev)
+        K = args.K if args.K is not None else search_K(torch, R, gsr, scene, cam, cam_s, fb_p, fb_a,
+                                                       stream)
+        R.render(scene, cam, adagscale=True, K=K, fb=fb_a)
+        torch.cuda.synchronize()
+        P_ada = int(fb_a.num_pairs.item())
+        psnr = psnr_t(torch, fb_a.image, fb_p.image)
+        ssim = ssim_t(torch, fb_a.image, fb_p.image)
+        log(f"K={K} pairs {P_ada} psnr {psnr:.2f} ssim {ssim:.4f}")
+        W_plain = raster_work(R, fb_p, cam_s)
+    W_ada = raster_work(R, fb_a, cam_s)
 
     mode_p = gsr.mode_struct()
     mode_a = gsr.mode_struct(adagscale=True, K=K)
     # each mode's pair buffers sized from its own count (+5%), as a renderer
     # sizes them from the previous frame
     fb_a.set_capacity(int(P_ada * 1.05) + 1024)
-    fb_p.set_capacity(int(P_plain * 1.05) + 1024)
     # per-stage HIP events (eager launches) ...
     wall_a, fms_a, st_a = timed_frames(torch, R, scene, cam_s, mode_a, fb_a, args.steps, args.warmup, stream)
-    wall_p, fms_p, st_p = timed_frames(torch, R, scene, cam_s, mode_p, fb_p, args.steps, args.warmup, stream)
-    # the same frame through the separate emission and sort entry points, for reference
-    _, fms_sa, st_sa = timed_frames(torch, R, scene, cam_s, mode_a, fb_a, args.steps, args.warmup,
-                                    stream, staged=True)
     # ... and whole frames replayed from a HIP graph (no host work per frame)
     ms_a, fms_ga = graph_frames(torch, R, scene, cam_s, mode_a, fb_a, args.steps, args.warmup)
-    ms_p, fms_gp = graph_frames(torch, R, scene, cam_s, mode_p, fb_p, args.steps, args.warmup)
-    assert int(fb_a.num_pairs.item()) == P_ada and int(fb_p.num_pairs.item()) == P_plain
-    eager_a, eager_p = float(np.median(fms_a)), float(np.median(fms_p))
+    assert int(fb_a.num_pairs.item()) == P_ada
+    eager_a = float(np.median(fms_a))
+    if not args.ada_only:
+        fb_p.set_capacity(int(P_plain * 1.05) + 1024)
+        _, fms_p, st_p = timed_frames(torch, R, scene, cam_s, mode_p, fb_p, args.steps, args.warmup,
+                                      stream)
+        # the same frame through the separate emission and sort entry points, for reference
+        _, fms_sa, st_sa = timed_frames(torch, R, scene, cam_s, mode_a, fb_a, args.steps,
+                                        args.warmup, stream, staged=True)
+        ms_p, fms_gp = graph_frames(torch, R, scene, cam_s, mode_p, fb_p, args.steps, args.warmup)
+        assert int(fb_p.num_pairs.item()) == P_plain
     # dominant kernel: the rasterizer (one kernel per frame, timed by its events)
     raster_ms = st_a["raster"]
-    flops = E_ada * FLOP_PER_EVAL
+    flops = FLOP_TEST * 64 * W_ada["strip_evaluations"] + FLOP_BLEND * W_ada["blended"]
     achieved = flops / (raster_ms * 1e-3) / 1e12
-    # HBM-bound stages: algorithmic bytes of this design (see DESIGN.md)
+    # HBM-bound stages: algorithmic bytes of this design
     n = scene.n
     vis = int((fb_a.tiles_touched > 0).sum().item())
     vm = np.asarray(cam["viewmat"], np.float64).reshape(3, 4)
@@ -459,9 +480,10 @@ def main():
     stage_bw = {
         "preprocess": pre_bytes / (st_a["preprocess"] * 1e-3) / 1e9,
         "bin": bin_bytes / (st_a["bin"] * 1e-3) / 1e9,
-        "staged_emit": emit_bytes / (st_sa["emit"] * 1e-3) / 1e9,
-        "staged_sort": sort_bytes / (st_sa["sort"] * 1e-3) / 1e9,
     }
+    if not args.ada_only:
+        stage_bw["staged_emit"] = emit_bytes / (st_sa["emit"] * 1e-3) / 1e9
+        stage_bw["staged_sort"] = sort_bytes / (st_sa["sort"] * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": 1000.0 / ms_a,
@@ -481,13 +503,10 @@ def main():
                    "psnr_target_db": PSNR_TARGET_DB},
         "adagscale": {"fps": 1000.0 / ms_a, "ms_p50": ms_a, "ms_p99": float(np.percentile(fms_ga, 99)),
                       "pairs": P_ada, "pairs_per_s": P_ada / (ms_a * 1e-3), "K": K,
-                      "eager_ms_p50": eager_a, "stages_ms": st_a, "evaluations": E_ada,
-                      "staged_eager_ms_p50": float(np.median(fms_sa)), "staged_stages_ms": st_sa},
-        "plain": {"fps": 1000.0 / ms_p, "ms_p50": ms_p, "ms_p99": float(np.percentile(fms_gp, 99)),
-                  "pairs": P_plain, "pairs_per_s": P_plain / (ms_p * 1e-3), "eager_ms_p50": eager_p,
-                  "stages_ms": st_p, "evaluations": E_plain},
-        "speedup_vs_plain": ms_p / ms_a,
-        "pair_ratio": P_ada / max(P_plain, 1),
+                      "eager_ms_p50": eager_a, "stages_ms": st_a, "raster_work": W_ada},
+        "plain": None,
+        "speedup_vs_plain": None,
+        "pair_ratio": None,
         "psnr_db_vs_plain": psnr,
         "ssim_vs_plain": ssim,
         "timing": "frames replayed from a HIP graph (value, ms_p50); stages_ms from eager launches "
@@ -498,8 +517,20 @@ def main():
         "roofline": {"kernel": "k_raster_wave", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": raster_traffic(),
-                     "basis": f"{FLOP_PER_EVAL} FLOP per eq.(1)-(2) evaluation x {E_ada} list-bounded evaluations"},
+                     "basis": f"{FLOP_TEST} FLOP x 64 pixels x {W_ada['strip_evaluations']} executed "
+                              f"strip evaluations + {FLOP_BLEND} FLOP x {W_ada['blended']} blended "
+                              f"pixel evaluations of eq. (1)-(2); peak = FP32 vector FMA rate"},
     }
+    if not args.ada_only:
+        out["adagscale"]["staged_eager_ms_p50"] = float(np.median(fms_sa))
+        out["adagscale"]["staged_stages_ms"] = st_sa
+        out["plain"] = {"fps": 1000.0 / ms_p, "ms_p50": ms_p,
+                        "ms_p99": float(np.percentile(fms_gp, 99)), "pairs": P_plain,
+                        "pairs_per_s": P_plain / (ms_p * 1e-3),
+                        "eager_ms_p50": float(np.median(fms_p)), "stages_ms": st_p,
+                        "raster_work": W_plain}
+        out["speedup_vs_plain"] = ms_p / ms_a
+        out["pair_ratio"] = P_ada / max(P_plain, 1)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(args, scene_h, cam, K, args.cpu_sample_tiles)

@@ -24,10 +24,12 @@
  *
  * Layouts
  * -------
- * scene  : structure of arrays, float32, [C][n] contiguous:
+ * scene  : float32.  Geometry as structure of arrays, [C][n] contiguous:
  *          means [3][n], log_scales [3][n], quats [4][n] (w, x, y, z; need not
- *          be normalised), opacity_logits [n], sh [(d+1)^2][3][n] (SH
- *          coefficient k of colour channel c of Gaussian i at (k*3+c)*n+i).
+ *          be normalised), opacity_logits [n].  Colour Gaussian-major:
+ *          sh [n][(d+1)^2][3] (SH coefficient k of colour channel c of
+ *          Gaussian i at (i*(d+1)^2 + k)*3 + c), 16-byte aligned, so a
+ *          Gaussian's coefficients are read only if it survives the cull.
  * splat  : array of structures, float32 [n][12], one 48-byte record per
  *          Gaussian, written by gs_preprocess:
  *            [0] mean x (pixels)   [1] mean y     [2] A         [3] beta
@@ -70,7 +72,7 @@ typedef enum {
 #define GS_MAX_SH_DEGREE 3
 #define GS_MAX_IMAGE_SIDE 32768 /* tile coordinates are stored in 16 bits */
 
-/* Scene parameters (device, SoA float32, see layouts above). */
+/* Scene parameters (device float32, see layouts above). */
 typedef struct {
     const float *means;
     const float *log_scales;
@@ -117,8 +119,8 @@ typedef struct {
     int lds_batch;
 } gs_raster_cfg;
 
-/* Gradients of the scene parameters (device, SoA float32, same layouts as
- * gs_scene; each pointer receives [C][n] values, overwritten). */
+/* Gradients of the scene parameters (device float32, same layouts as
+ * gs_scene, d_sh 16-byte aligned; every value is overwritten). */
 typedef struct {
     float *d_means;
     float *d_log_scales;
@@ -205,6 +207,23 @@ gs_status gs_rasterize(const float *splats, int64_t n, const uint32_t *sorted_gi
                        const uint32_t *ranges, const gs_camera *cam, const float *bg,
                        const gs_raster_cfg *cfg, float *image, float *final_T,
                        uint32_t *n_contrib, uint32_t *n_evaluated, void *stream);
+
+/* Work of the default (one wave per tile) rasterizer on these lists, for
+ * measurement: runs its walk without writing pixels and ADDS to work[0..3]
+ * (device uint64[4]; the caller zeroes it, the counts accumulate over calls):
+ *   [0] list entries evaluated, summed over pixels -- the n_evaluated total of
+ *       gs_rasterize: per pixel, eq. (1)-(2) entries up to and including the
+ *       one that stopped it, else the whole list;
+ *   [1] strip evaluations executed: (16x4 pixel strip, list entry) pairs the
+ *       rasterizer's conservative per-strip bound did not rule out, each one
+ *       evaluation of eq. (1)-(2) at the strip's 64 pixels;
+ *   [2] pixel evaluations that blended a Gaussian (alpha >= tau on a live
+ *       pixel, not the stopping one);
+ *   [3] list entries loaded (read and bounded before the tile finished).
+ * Same argument rules as gs_rasterize. */
+gs_status gs_raster_work(const float *splats, int64_t n, const uint32_t *sorted_gids,
+                         const uint32_t *ranges, const gs_camera *cam, uint64_t *work,
+                         void *stream);
 
 /* Adjoint of stage 4 with the pair set and every blend decision of the
  * forward pass frozen.  Walks each pixel's list back to front from n_contrib,

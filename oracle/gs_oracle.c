@@ -448,22 +448,24 @@ static void blend_pixel(double px, double py, const uint32_t *list, int64_t len,
 
 static void store_pixel(const pix_t *o, int64_t idx, int64_t npix, const double *bg, double *image,
                         double *final_T, int64_t *n_contrib, double *margin, int64_t *evals,
-                        uint64_t *sig) {
+                        uint64_t *sig, int64_t *blended) {
     for (int ch = 0; ch < 3; ++ch) image[ch * npix + idx] = o->color[ch] + o->T * bg[ch];
     final_T[idx] = o->T;
     n_contrib[idx] = o->last;
     if (margin) margin[idx] = o->margin;
     if (evals) evals[idx] = o->evaluated;
     if (sig) sig[idx] = o->sig ^ (uint64_t)o->blended;
+    if (blended) blended[idx] = o->blended;
 }
 
 /* Tile-list rasterizer: pixel (px, py) lies in tile (px/16, py/16) and blends
  * that tile's sorted list.  tiles: optional subset of tile ids (n_sel >= 0);
- * n_sel < 0 blends every tile.  Outputs are [3][H][W] and [H][W]. */
+ * n_sel < 0 blends every tile.  Outputs are [3][H][W] and [H][W]; margin,
+ * evals, sig and blended (Gaussians blended per pixel) may be NULL. */
 void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *sorted_vals,
                const double *rec, const double *bg, const int32_t *tiles, int64_t n_sel,
                double *image, double *final_T, int64_t *n_contrib, double *margin, int64_t *evals,
-               uint64_t *sig) {
+               uint64_t *sig, int64_t *blended) {
     int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
     int64_t npix = (int64_t)width * height;
     int64_t count = n_sel >= 0 ? n_sel : (int64_t)TX * TY;
@@ -476,7 +478,7 @@ void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *sor
                 blend_pixel((double)px, (double)py, sorted_vals + ranges[2 * t],
                             ranges[2 * t + 1] - ranges[2 * t], rec, &o);
                 store_pixel(&o, (int64_t)py * width + px, npix, bg, image, final_T, n_contrib,
-                            margin, evals, sig);
+                            margin, evals, sig, blended);
             }
     }
 }
@@ -518,7 +520,7 @@ void orc_blend_bruteforce(int mode, int64_t n, int width, int height, const int3
             pix_t o;
             blend_pixel((double)px, (double)py, list, m, rec, &o);
             store_pixel(&o, (int64_t)py * width + px, npix, bg, image, final_T, n_contrib, NULL,
-                        NULL, NULL);
+                        NULL, NULL, NULL);
             (void)TX;
         }
     free(cand);

@@ -61,7 +61,7 @@ def lib():
         L.orc_emit.restype = C.c_int64
         L.orc_sort.argtypes = [C.c_int64, P, P]
         L.orc_ranges.argtypes = [C.c_int64, P, C.c_int, P]
-        L.orc_blend.argtypes = [C.c_int, C.c_int, P, P, P, P, P, C.c_int64, P, P, P, P, P, P]
+        L.orc_blend.argtypes = [C.c_int, C.c_int, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P]
         L.orc_blend_bruteforce.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_int, P, P, P, P, P, P,
                                            P, P]
         L.orc_blend_backward.argtypes = [C.c_int, C.c_int, P, P, P, P, P, P, P, C.c_int64]
@@ -228,8 +228,30 @@ def blend(frame_or_parts, cam, bg=(0.0, 0.0, 0.0), tiles=None, rec=None):
         sel = np.ascontiguousarray(tiles, np.int32)
         nsel = sel.size
     lib().orc_blend(W, H, _p(rg), _p(sv), _p(rec), _p(bgv), _p(sel), nsel, _p(img), _p(T),
-                    _p(nc), _p(mg), _p(ev), _p(sg))
+                    _p(nc), _p(mg), _p(ev), _p(sg), None)
     return img, T, nc, mg, ev, sg
+
+
+def blend_counts(frame: "Frame", cam, tiles=None, rec=None):
+    """Per-pixel work of the blend: (list entries evaluated, Gaussians
+    blended, decision margin), each [H][W]; pixels outside ``tiles`` are 0."""
+    W, H = cam["width"], cam["height"]
+    if rec is None:
+        rec = frame.pre.record()
+    img = np.zeros((3, H, W))
+    T = np.zeros((H, W))
+    nc = np.zeros((H, W), np.int64)
+    mg = np.full((H, W), np.inf)
+    ev = np.zeros((H, W), np.int64)
+    bl = np.zeros((H, W), np.int64)
+    bgv = np.zeros(3)
+    rg = np.ascontiguousarray(frame.ranges, np.int64)
+    sv = np.ascontiguousarray(frame.sorted_vals, np.uint32)
+    sel = None if tiles is None else np.ascontiguousarray(tiles, np.int32)
+    nsel = -1 if sel is None else sel.size
+    lib().orc_blend(W, H, _p(rg), _p(sv), _p(rec), _p(bgv), _p(sel), nsel, _p(img), _p(T),
+                    _p(nc), _p(mg), _p(ev), None, _p(bl))
+    return ev, bl, mg
 
 
 def render(scene, cam, mode: Mode = Mode(), bg=(0.0, 0.0, 0.0), tiles=None) -> Frame:

@@ -38,5 +38,8 @@ class RasterizeFn(torch.autograd.Function):
 
 def rasterize(means, log_scales, quats, opacity_logits, sh, sh_degree, cam, bg=(0.0, 0.0, 0.0),
               **mode):
-    """Differentiable render of one view: image [3][H][W]."""
+    """Differentiable render of one view: image [3][H][W].  Parameters in the
+    library's layouts: means/log_scales [3][n], quats [4][n], opacity_logits
+    [n], sh [n][(d+1)^2][3] (render.sh_to_device_layout converts a host
+    [(d+1)^2][3][n] array); gradients come back in the same layouts."""
     return RasterizeFn.apply(means, log_scales, quats, opacity_logits, sh, sh_degree, cam, mode, bg)

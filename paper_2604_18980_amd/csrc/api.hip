@@ -101,6 +101,8 @@ gs_status check_scene(const gs_scene *sc) {
         return fail(GS_ERR_INVALID_ARGUMENT, "sh_degree %d outside 0..%d", sc->sh_degree, GS_MAX_SH_DEGREE);
     if (sc->n > 0 && (!sc->means || !sc->log_scales || !sc->quats || !sc->opacity_logits || !sc->sh))
         return fail(GS_ERR_INVALID_ARGUMENT, "scene has a NULL parameter array");
+    if (((uintptr_t)sc->sh & 15) != 0)
+        return fail(GS_ERR_INVALID_ARGUMENT, "sh is not 16-byte aligned");
     return GS_OK;
 }
 }  // namespace
@@ -359,7 +361,33 @@ gs_status gs_rasterize(const float *splats, int64_t n, const uint32_t *sorted_gi
     a.final_T = final_T;
     a.n_contrib = n_contrib;
     a.n_evaluated = n_evaluated;
+    a.work = nullptr;
     return hip_check(launch_raster(a, c, (hipStream_t)stream), "gs_rasterize");
+}
+
+gs_status gs_raster_work(const float *splats, int64_t n, const uint32_t *sorted_gids,
+                         const uint32_t *ranges, const gs_camera *cam, uint64_t *work,
+                         void *stream) {
+    gs_status st;
+    if ((st = check_camera(cam)) != GS_OK) return st;
+    if (n < 0) return fail(GS_ERR_INVALID_ARGUMENT, "n < 0");
+    if (!ranges || !work) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (n > 0 && (!splats || !sorted_gids)) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    RasterArgs a;
+    a.splats = splats;
+    a.gids = sorted_gids;
+    a.ranges = ranges;
+    a.width = cam->width;
+    a.height = cam->height;
+    a.tiles_x = tiles_x(cam);
+    a.tiles_y = tiles_y(cam);
+    for (int i = 0; i < 3; ++i) a.bg[i] = 0.0f;
+    a.image = a.final_T = nullptr;
+    a.n_contrib = nullptr;
+    a.n_evaluated = nullptr;
+    a.work = reinterpret_cast<unsigned long long *>(work);
+    const gs_raster_cfg c = {64, 4, 64};
+    return hip_check(launch_raster(a, c, (hipStream_t)stream), "gs_raster_work");
 }
 
 gs_status gs_rasterize_backward(const float *splats, int64_t n, const uint32_t *sorted_gids,
@@ -399,6 +427,8 @@ gs_status gs_preprocess_backward(const gs_scene *scene, const gs_camera *cam,
     if (scene->n > 0 && (!tiles_touched || !grad_splats || !out->d_means || !out->d_log_scales ||
                          !out->d_quats || !out->d_opacity_logits || !out->d_sh))
         return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (((uintptr_t)out->d_sh & 15) != 0)
+        return fail(GS_ERR_INVALID_ARGUMENT, "d_sh is not 16-byte aligned");
     PreprocessBwdArgs a;
     memset(&a, 0, sizeof a);
     a.means = scene->means;
@@ -414,6 +444,7 @@ gs_status gs_preprocess_backward(const gs_scene *scene, const gs_camera *cam,
     a.limx = 1.3 * ((0.5 * cam->width) / a.fx);
     a.limy = 1.3 * ((0.5 * cam->height) / a.fy);
     sh_constants(a.shc);
+    for (int i = 0; i < 16; ++i) a.shcf[i] = (float)a.shc[i];
     a.tiles_touched = tiles_touched;
     a.grad_splats = grad_splats;
     a.d_means = out->d_means;

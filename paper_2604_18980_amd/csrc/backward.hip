@@ -161,7 +161,8 @@ __global__ __launch_bounds__(256) void k_raster_backward(const RasterBwdArgs a) 
                 if (!((m[k] >> jj) & 1ull)) continue;  // uniform: strip k missed
                 const float dy = smy - fpy[k];
                 const float u = fmaf(sbeta, dy, dx);
-                const float e2 = fmaf(sA2 * u, u, sG2 * (dy * dy));
+                // the forward's exponent, term for term (its state offset is 0 here)
+                const float e2 = fmaf(sA2 * u, u, fmaf(sG2 * dy, dy, 0.0f));
                 if (pos < last[k] && e2 >= selim) {  // the forward blended it here
                     contrib = true;
                     const float e = __builtin_amdgcn_exp2f(e2);
@@ -222,201 +223,262 @@ hipError_t launch_raster_backward(const RasterBwdArgs &a, int64_t n, hipStream_t
 
 // ------------------------------------------------------------ preprocess backward
 namespace {
-// Real SH basis (as in the forward) and its partials in x, y, z (the
-// polynomials extended off the sphere; only their tangential part is used).
-__device__ void sh_eval_grad(int degree, double x, double y, double z, const double *c, double *Y,
-                             double (*dY)[3]) {
-    for (int k = 0; k < 16; ++k) { Y[k] = 0.0; dY[k][0] = dY[k][1] = dY[k][2] = 0.0; }
+// Real SH basis (as in the forward's colour) in float32, DEG a compile-time
+// degree so the polynomials stay in registers.
+template <int DEG>
+__device__ __forceinline__ void sh_basis_f(float x, float y, float z, const float *c, float *Y) {
     Y[0] = c[0];
-    if (degree < 1) return;
-    Y[1] = -c[1] * y; dY[1][1] = -c[1];
-    Y[2] = c[1] * z;  dY[2][2] = c[1];
-    Y[3] = -c[1] * x; dY[3][0] = -c[1];
-    if (degree < 2) return;
-    const double xx = x * x, yy = y * y, zz = z * z;
-    Y[4] = c[2] * x * y;              dY[4][0] = c[2] * y;  dY[4][1] = c[2] * x;
-    Y[5] = -c[2] * y * z;             dY[5][1] = -c[2] * z; dY[5][2] = -c[2] * y;
-    Y[6] = c[3] * (3.0 * zz - 1.0);   dY[6][2] = 6.0 * c[3] * z;
-    Y[7] = -c[2] * x * z;             dY[7][0] = -c[2] * z; dY[7][2] = -c[2] * x;
-    Y[8] = c[4] * (xx - yy);          dY[8][0] = 2.0 * c[4] * x; dY[8][1] = -2.0 * c[4] * y;
-    if (degree < 3) return;
-    Y[9] = -c[5] * y * (3.0 * xx - yy);
-    dY[9][0] = -c[5] * 6.0 * x * y;   dY[9][1] = -c[5] * (3.0 * xx - 3.0 * yy);
-    Y[10] = c[6] * x * y * z;
-    dY[10][0] = c[6] * y * z;         dY[10][1] = c[6] * x * z; dY[10][2] = c[6] * x * y;
-    Y[11] = -c[7] * y * (5.0 * zz - 1.0);
-    dY[11][1] = -c[7] * (5.0 * zz - 1.0); dY[11][2] = -c[7] * 10.0 * y * z;
-    Y[12] = c[8] * z * (5.0 * zz - 3.0);
-    dY[12][2] = c[8] * (15.0 * zz - 3.0);
-    Y[13] = -c[7] * x * (5.0 * zz - 1.0);
-    dY[13][0] = -c[7] * (5.0 * zz - 1.0); dY[13][2] = -c[7] * 10.0 * x * z;
-    Y[14] = c[9] * z * (xx - yy);
-    dY[14][0] = 2.0 * c[9] * x * z;   dY[14][1] = -2.0 * c[9] * y * z; dY[14][2] = c[9] * (xx - yy);
-    Y[15] = -c[5] * x * (xx - 3.0 * yy);
-    dY[15][0] = -c[5] * (3.0 * xx - 3.0 * yy); dY[15][1] = c[5] * 6.0 * x * y;
+    if (DEG < 1) return;
+    Y[1] = -c[1] * y;
+    Y[2] = c[1] * z;
+    Y[3] = -c[1] * x;
+    if (DEG < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = c[2] * (x * y);
+    Y[5] = -c[2] * (y * z);
+    Y[6] = c[3] * (3.0f * zz - 1.0f);
+    Y[7] = -c[2] * (x * z);
+    Y[8] = c[4] * (xx - yy);
+    if (DEG < 3) return;
+    Y[9] = -c[5] * (y * (3.0f * xx - yy));
+    Y[10] = c[6] * (x * y * z);
+    Y[11] = -c[7] * (y * (5.0f * zz - 1.0f));
+    Y[12] = c[8] * (z * (5.0f * zz - 3.0f));
+    Y[13] = -c[7] * (x * (5.0f * zz - 1.0f));
+    Y[14] = c[9] * (z * (xx - yy));
+    Y[15] = -c[5] * (x * (xx - 3.0f * yy));
+}
+
+// g = sum_k w[k] grad Y_k at (x, y, z): the partials of the basis polynomials
+// above (extended off the sphere; the caller keeps the tangential part).
+template <int DEG>
+__device__ __forceinline__ void sh_grad_dot(float x, float y, float z, const float *c, const float *w,
+                                            float *g) {
+    g[0] = g[1] = g[2] = 0.0f;
+    if (DEG < 1) return;
+    g[1] += w[1] * -c[1];
+    g[2] += w[2] * c[1];
+    g[0] += w[3] * -c[1];
+    if (DEG < 2) return;
+    g[0] += w[4] * (c[2] * y);         g[1] += w[4] * (c[2] * x);
+    g[1] += w[5] * (-c[2] * z);        g[2] += w[5] * (-c[2] * y);
+    g[2] += w[6] * (6.0f * c[3] * z);
+    g[0] += w[7] * (-c[2] * z);        g[2] += w[7] * (-c[2] * x);
+    g[0] += w[8] * (2.0f * c[4] * x);  g[1] += w[8] * (-2.0f * c[4] * y);
+    if (DEG < 3) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    g[0] += w[9] * (-c[5] * 6.0f * x * y);
+    g[1] += w[9] * (-c[5] * (3.0f * xx - 3.0f * yy));
+    g[0] += w[10] * (c[6] * y * z);    g[1] += w[10] * (c[6] * x * z);  g[2] += w[10] * (c[6] * x * y);
+    g[1] += w[11] * (-c[7] * (5.0f * zz - 1.0f));
+    g[2] += w[11] * (-c[7] * 10.0f * y * z);
+    g[2] += w[12] * (c[8] * (15.0f * zz - 3.0f));
+    g[0] += w[13] * (-c[7] * (5.0f * zz - 1.0f));
+    g[2] += w[13] * (-c[7] * 10.0f * x * z);
+    g[0] += w[14] * (2.0f * c[9] * x * z);
+    g[1] += w[14] * (-2.0f * c[9] * y * z);
+    g[2] += w[14] * (c[9] * (xx - yy));
+    g[0] += w[15] * (-c[5] * (3.0f * xx - 3.0f * yy));
+    g[1] += w[15] * (c[5] * 6.0f * x * y);
 }
 }  // namespace
 
+// One thread per Gaussian, 128 per block.  The geometry adjoint runs in FP64
+// (one reciprocal per repeated denominator); the colour adjoint in float32.
+// d_sh rows (Gaussian-major, 3 (DEG+1)^2 floats each) are assembled in LDS
+// and the block's contiguous span of d_sh is written with consecutive
+// threads on consecutive words.
+template <int DEG>
 __global__ __launch_bounds__(128) void k_preprocess_backward(const PreprocessBwdArgs a) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.n) return;
+    constexpr int NSH = (DEG + 1) * (DEG + 1), NC = NSH * 3, ROW = NC + 1;  // odd row pitch
+    __shared__ float s_dsh[128 * ROW];
+    const int g0 = blockIdx.x * 128;
+    const int g = g0 + threadIdx.x;
     const int n = a.n;
-    const int nsh = (a.sh_degree + 1) * (a.sh_degree + 1);
-    double dmean[3] = {0, 0, 0}, dls[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dop = 0.0;
-    double dsh[16][3];
-    for (int k = 0; k < nsh; ++k) dsh[k][0] = dsh[k][1] = dsh[k][2] = 0.0;
-
-    if (a.tiles_touched[g] > 0) {
-        const float *G = a.grad_splats + (size_t)g * 12;
-        const double gmx = G[0], gmy = G[1], gA = G[2], gbeta = G[3], ggam = G[4], gsig = G[5];
-        const double grgb[3] = {G[8], G[9], G[10]};
-        const double mx = a.means[g], my = a.means[n + g], mz = a.means[2 * n + g];
-        const double *R = a.R;
-        const double p0 = R[0] * mx + R[1] * my + R[2] * mz + a.t[0];
-        const double p1 = R[3] * mx + R[4] * my + R[5] * mz + a.t[1];
-        const double p2 = R[6] * mx + R[7] * my + R[8] * mz + a.t[2];
-        const double s[3] = {exp((double)a.log_scales[g]), exp((double)a.log_scales[n + g]),
-                             exp((double)a.log_scales[2 * n + g])};
-        const double q0[4] = {a.quats[g], a.quats[n + g], a.quats[2 * n + g], a.quats[3 * n + g]};
-        const double qn = q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3];
-        const bool qdeg = !(qn > 0.0);
-        const double qr = qdeg ? 1.0 : sqrt(qn);
-        const double w = qdeg ? 1.0 : q0[0] / qr, x = qdeg ? 0.0 : q0[1] / qr,
-                     y = qdeg ? 0.0 : q0[2] / qr, z = qdeg ? 0.0 : q0[3] / qr;
-        const double Rq[3][3] = {
-            {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
-            {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
-            {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
-        double M[3][3], S3[3][3];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) M[i][j] = Rq[i][j] * s[j];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) S3[i][j] = M[i][0] * M[j][0] + M[i][1] * M[j][1] + M[i][2] * M[j][2];
-        double txz = p0 / p2, tyz = p1 / p2;
-        int clx = 0, cly = 0;
-        if (txz < -a.limx) { txz = -a.limx; clx = -1; }
-        if (txz > a.limx) { txz = a.limx; clx = 1; }
-        if (tyz < -a.limy) { tyz = -a.limy; cly = -1; }
-        if (tyz > a.limy) { tyz = a.limy; cly = 1; }
-        const double xc = txz * p2, yc = tyz * p2, p22 = p2 * p2;
-        const double J00 = a.fx / p2, J02 = -(a.fx * xc) / p22, J11 = a.fy / p2, J12 = -(a.fy * yc) / p22;
-        double T[2][3];
-        for (int j = 0; j < 3; ++j) {
-            T[0][j] = J00 * R[j] + J02 * R[6 + j];
-            T[1][j] = J11 * R[3 + j] + J12 * R[6 + j];
-        }
-        double U[2][3];
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 3; ++j) U[i][j] = T[i][0] * S3[0][j] + T[i][1] * S3[1][j] + T[i][2] * S3[2][j];
-        const double ca = U[0][0] * T[0][0] + U[0][1] * T[0][1] + U[0][2] * T[0][2] + 0.3;
-        const double cb = U[0][0] * T[1][0] + U[0][1] * T[1][1] + U[0][2] * T[1][2];
-        const double cc = U[1][0] * T[1][0] + U[1][1] * T[1][1] + U[1][2] * T[1][2] + 0.3;
-        const double det = ca * cc - cb * cb, d2 = det * det;
-
-        // mean2d
-        double dp[3] = {gmx * a.fx / p2, gmy * a.fy / p2, -gmx * a.fx * p0 / p22 - gmy * a.fy * p1 / p22};
-        // (A, beta, gamma) = (c/det, -b/c, 1/c)
-        const double ga = gA * (-cc * cc / d2);
-        const double gb = gA * (2.0 * cb * cc / d2) + gbeta * (-1.0 / cc);
-        const double gc = gA * (-cb * cb / d2) + gbeta * (cb / (cc * cc)) + ggam * (-1.0 / (cc * cc));
-        const double G2[2][2] = {{ga, 0.5 * gb}, {0.5 * gb, gc}};
-        // dL/dSigma3 = T^T G2 T ; dL/dT = 2 G2 T Sigma3
-        double G3[3][3], GT[2][3], TS[2][3];
-        for (int i = 0; i < 3; ++i)
+    float *row = s_dsh + threadIdx.x * ROW;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) row[k] = 0.0f;
+    if (g < n) {
+        double dmean[3] = {0, 0, 0}, dls[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dop = 0.0;
+        if (a.tiles_touched[g] > 0) {
+            const float *G = a.grad_splats + (size_t)g * 12;
+            const double gmx = G[0], gmy = G[1], gA = G[2], gbeta = G[3], ggam = G[4], gsig = G[5];
+            const float grgb[3] = {G[8], G[9], G[10]};
+            const double mx = a.means[g], my = a.means[n + g], mz = a.means[2 * n + g];
+            const double *R = a.R;
+            const double p0 = R[0] * mx + R[1] * my + R[2] * mz + a.t[0];
+            const double p1 = R[3] * mx + R[4] * my + R[5] * mz + a.t[1];
+            const double p2 = R[6] * mx + R[7] * my + R[8] * mz + a.t[2];
+            const double s[3] = {exp((double)a.log_scales[g]), exp((double)a.log_scales[n + g]),
+                                 exp((double)a.log_scales[2 * n + g])};
+            const double q0[4] = {a.quats[g], a.quats[n + g], a.quats[2 * n + g], a.quats[3 * n + g]};
+            const double qn = q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3];
+            const bool qdeg = !(qn > 0.0);
+            const double iqr = qdeg ? 1.0 : 1.0 / sqrt(qn);
+            const double w = qdeg ? 1.0 : q0[0] * iqr, x = qdeg ? 0.0 : q0[1] * iqr,
+                         y = qdeg ? 0.0 : q0[2] * iqr, z = qdeg ? 0.0 : q0[3] * iqr;
+            const double Rq[3][3] = {
+                {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+                {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+                {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+            double M[3][3], S3[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) M[i][j] = Rq[i][j] * s[j];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    S3[i][j] = M[i][0] * M[j][0] + M[i][1] * M[j][1] + M[i][2] * M[j][2];
+            const double ip2 = 1.0 / p2, ip22 = ip2 * ip2;
+            double txz = p0 * ip2, tyz = p1 * ip2;
+            int clx = 0, cly = 0;
+            if (txz < -a.limx) { txz = -a.limx; clx = -1; }
+            if (txz > a.limx) { txz = a.limx; clx = 1; }
+            if (tyz < -a.limy) { tyz = -a.limy; cly = -1; }
+            if (tyz > a.limy) { tyz = a.limy; cly = 1; }
+            const double xc = txz * p2, yc = tyz * p2;
+            const double J00 = a.fx * ip2, J02 = -(a.fx * xc) * ip22, J11 = a.fy * ip2,
+                         J12 = -(a.fy * yc) * ip22;
+            double T[2][3];
             for (int j = 0; j < 3; ++j) {
-                double acc = 0.0;
-                for (int k = 0; k < 2; ++k)
-                    for (int l = 0; l < 2; ++l) acc += T[k][i] * G2[k][l] * T[l][j];
-                G3[i][j] = acc;
+                T[0][j] = J00 * R[j] + J02 * R[6 + j];
+                T[1][j] = J11 * R[3 + j] + J12 * R[6 + j];
             }
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 3; ++j) TS[i][j] = T[i][0] * S3[0][j] + T[i][1] * S3[1][j] + T[i][2] * S3[2][j];
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 3; ++j) GT[i][j] = 2.0 * (G2[i][0] * TS[0][j] + G2[i][1] * TS[1][j]);
-        // T = J W -> dL/dJ = dL/dT W^T (only the four non-zero J entries matter)
-        double GJ00 = 0, GJ02 = 0, GJ11 = 0, GJ12 = 0;
-        for (int k = 0; k < 3; ++k) {
-            GJ00 += GT[0][k] * R[k];
-            GJ02 += GT[0][k] * R[6 + k];
-            GJ11 += GT[1][k] * R[3 + k];
-            GJ12 += GT[1][k] * R[6 + k];
-        }
-        dp[2] += GJ00 * (-a.fx / p22) + GJ11 * (-a.fy / p22);
-        if (clx == 0) {
-            dp[0] += GJ02 * (-a.fx / p22);
-            dp[2] += GJ02 * (2.0 * a.fx * p0 / (p22 * p2));
-        } else {
-            dp[2] += GJ02 * (a.fx * clx * a.limx / p22);
-        }
-        if (cly == 0) {
-            dp[1] += GJ12 * (-a.fy / p22);
-            dp[2] += GJ12 * (2.0 * a.fy * p1 / (p22 * p2));
-        } else {
-            dp[2] += GJ12 * (a.fy * cly * a.limy / p22);
-        }
-        // Sigma3 = M M^T -> dL/dM = 2 G3 M; M = Rq diag(s)
-        double GM[3][3];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) GM[i][j] = 2.0 * (G3[i][0] * M[0][j] + G3[i][1] * M[1][j] + G3[i][2] * M[2][j]);
-        for (int j = 0; j < 3; ++j)
-            dls[j] = (GM[0][j] * Rq[0][j] + GM[1][j] * Rq[1][j] + GM[2][j] * Rq[2][j]) * s[j];
-        double GR[3][3];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) GR[i][j] = GM[i][j] * s[j];
-        // dRq/dq for unit q = (w, x, y, z)
-        double gq[4];
-        gq[0] = GR[0][1] * (-2 * z) + GR[0][2] * (2 * y) + GR[1][0] * (2 * z) + GR[1][2] * (-2 * x) +
-                GR[2][0] * (-2 * y) + GR[2][1] * (2 * x);
-        gq[1] = GR[0][1] * (2 * y) + GR[0][2] * (2 * z) + GR[1][0] * (2 * y) + GR[1][1] * (-4 * x) +
-                GR[1][2] * (-2 * w) + GR[2][0] * (2 * z) + GR[2][1] * (2 * w) + GR[2][2] * (-4 * x);
-        gq[2] = GR[0][0] * (-4 * y) + GR[0][1] * (2 * x) + GR[0][2] * (2 * w) + GR[1][0] * (2 * x) +
-                GR[1][2] * (2 * z) + GR[2][0] * (-2 * w) + GR[2][1] * (2 * z) + GR[2][2] * (-4 * y);
-        gq[3] = GR[0][0] * (-4 * z) + GR[0][1] * (-2 * w) + GR[0][2] * (2 * x) + GR[1][0] * (2 * w) +
-                GR[1][1] * (-4 * z) + GR[1][2] * (2 * y) + GR[2][0] * (2 * x) + GR[2][1] * (2 * y);
-        if (!qdeg) {
-            const double qv[4] = {w, x, y, z};
-            const double qg = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
-            for (int k = 0; k < 4; ++k) dq[k] = (gq[k] - qv[k] * qg) / qr;
-        }
-        // opacity
-        const double sg = 1.0 / (1.0 + exp(-(double)a.opacity_logits[g]));
-        dop = gsig * sg * (1.0 - sg);
-        // colour
-        const double dv[3] = {mx - a.campos[0], my - a.campos[1], mz - a.campos[2]};
-        const double len = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-        const double dir[3] = {dv[0] / len, dv[1] / len, dv[2] / len};
-        double Y[16], dY[16][3];
-        sh_eval_grad(a.sh_degree, dir[0], dir[1], dir[2], a.shc, Y, dY);
-        double gdir[3] = {0, 0, 0};
-        for (int ch = 0; ch < 3; ++ch) {
-            double acc = 0.0;
-            for (int k = 0; k < nsh; ++k) acc += (double)a.sh[((size_t)k * 3 + ch) * n + g] * Y[k];
-            if (acc + 0.5 < 0.0) continue;  // clamped channel
-            for (int k = 0; k < nsh; ++k) {
-                dsh[k][ch] = grgb[ch] * Y[k];
-                const double cf = grgb[ch] * (double)a.sh[((size_t)k * 3 + ch) * n + g];
-                gdir[0] += cf * dY[k][0];
-                gdir[1] += cf * dY[k][1];
-                gdir[2] += cf * dY[k][2];
+            double U[2][3];
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 3; ++j)
+                    U[i][j] = T[i][0] * S3[0][j] + T[i][1] * S3[1][j] + T[i][2] * S3[2][j];
+            const double ca = U[0][0] * T[0][0] + U[0][1] * T[0][1] + U[0][2] * T[0][2] + 0.3;
+            const double cb = U[0][0] * T[1][0] + U[0][1] * T[1][1] + U[0][2] * T[1][2];
+            const double cc = U[1][0] * T[1][0] + U[1][1] * T[1][1] + U[1][2] * T[1][2] + 0.3;
+            const double det = ca * cc - cb * cb, id2 = 1.0 / (det * det), icc = 1.0 / cc;
+            (void)ca;
+
+            // mean2d
+            double dp[3] = {gmx * a.fx * ip2, gmy * a.fy * ip2,
+                            -gmx * a.fx * p0 * ip22 - gmy * a.fy * p1 * ip22};
+            // (A, beta, gamma) = (c/det, -b/c, 1/c)
+            const double ga = gA * (-cc * cc * id2);
+            const double gb = gA * (2.0 * cb * cc * id2) + gbeta * (-icc);
+            const double gc = gA * (-cb * cb * id2) + gbeta * (cb * icc * icc) + ggam * (-icc * icc);
+            const double G2[2][2] = {{ga, 0.5 * gb}, {0.5 * gb, gc}};
+            // dL/dSigma3 = T^T G2 T ; dL/dT = 2 G2 T Sigma3
+            double G3[3][3], GT[2][3], TS[2][3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    double acc = 0.0;
+                    for (int k = 0; k < 2; ++k)
+                        for (int l = 0; l < 2; ++l) acc += T[k][i] * G2[k][l] * T[l][j];
+                    G3[i][j] = acc;
+                }
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 3; ++j)
+                    TS[i][j] = T[i][0] * S3[0][j] + T[i][1] * S3[1][j] + T[i][2] * S3[2][j];
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 3; ++j) GT[i][j] = 2.0 * (G2[i][0] * TS[0][j] + G2[i][1] * TS[1][j]);
+            // T = J W -> dL/dJ = dL/dT W^T (only the four non-zero J entries matter)
+            double GJ00 = 0, GJ02 = 0, GJ11 = 0, GJ12 = 0;
+            for (int k = 0; k < 3; ++k) {
+                GJ00 += GT[0][k] * R[k];
+                GJ02 += GT[0][k] * R[6 + k];
+                GJ11 += GT[1][k] * R[3 + k];
+                GJ12 += GT[1][k] * R[6 + k];
             }
+            dp[2] += GJ00 * (-a.fx * ip22) + GJ11 * (-a.fy * ip22);
+            if (clx == 0) {
+                dp[0] += GJ02 * (-a.fx * ip22);
+                dp[2] += GJ02 * (2.0 * a.fx * p0 * (ip22 * ip2));
+            } else {
+                dp[2] += GJ02 * (a.fx * clx * a.limx * ip22);
+            }
+            if (cly == 0) {
+                dp[1] += GJ12 * (-a.fy * ip22);
+                dp[2] += GJ12 * (2.0 * a.fy * p1 * (ip22 * ip2));
+            } else {
+                dp[2] += GJ12 * (a.fy * cly * a.limy * ip22);
+            }
+            // Sigma3 = M M^T -> dL/dM = 2 G3 M; M = Rq diag(s)
+            double GM[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    GM[i][j] = 2.0 * (G3[i][0] * M[0][j] + G3[i][1] * M[1][j] + G3[i][2] * M[2][j]);
+            for (int j = 0; j < 3; ++j)
+                dls[j] = (GM[0][j] * Rq[0][j] + GM[1][j] * Rq[1][j] + GM[2][j] * Rq[2][j]) * s[j];
+            double GR[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) GR[i][j] = GM[i][j] * s[j];
+            // dRq/dq for unit q = (w, x, y, z)
+            double gq[4];
+            gq[0] = GR[0][1] * (-2 * z) + GR[0][2] * (2 * y) + GR[1][0] * (2 * z) + GR[1][2] * (-2 * x) +
+                    GR[2][0] * (-2 * y) + GR[2][1] * (2 * x);
+            gq[1] = GR[0][1] * (2 * y) + GR[0][2] * (2 * z) + GR[1][0] * (2 * y) + GR[1][1] * (-4 * x) +
+                    GR[1][2] * (-2 * w) + GR[2][0] * (2 * z) + GR[2][1] * (2 * w) + GR[2][2] * (-4 * x);
+            gq[2] = GR[0][0] * (-4 * y) + GR[0][1] * (2 * x) + GR[0][2] * (2 * w) + GR[1][0] * (2 * x) +
+                    GR[1][2] * (2 * z) + GR[2][0] * (-2 * w) + GR[2][1] * (2 * z) + GR[2][2] * (-4 * y);
+            gq[3] = GR[0][0] * (-4 * z) + GR[0][1] * (-2 * w) + GR[0][2] * (2 * x) + GR[1][0] * (2 * w) +
+                    GR[1][1] * (-4 * z) + GR[1][2] * (2 * y) + GR[2][0] * (2 * x) + GR[2][1] * (2 * y);
+            if (!qdeg) {
+                const double qv[4] = {w, x, y, z};
+                const double qg = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
+                for (int k = 0; k < 4; ++k) dq[k] = (gq[k] - qv[k] * qg) * iqr;
+            }
+            // opacity
+            const double sg = 1.0 / (1.0 + exp(-(double)a.opacity_logits[g]));
+            dop = gsig * sg * (1.0 - sg);
+            // colour (float32): rgb = max(sum_k sh[k] Y_k(dir) + 0.5, 0) per channel
+            const double dv[3] = {mx - a.campos[0], my - a.campos[1], mz - a.campos[2]};
+            const double len = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]), ilen = 1.0 / len;
+            const double dir[3] = {dv[0] * ilen, dv[1] * ilen, dv[2] * ilen};
+            const float fx = (float)dir[0], fy = (float)dir[1], fz = (float)dir[2];
+            float Y[16];
+            sh_basis_f<DEG>(fx, fy, fz, a.shcf, Y);
+            const float *shg = a.sh + (size_t)g * NC;
+            float f[NC];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) f[k] = shg[k];
+            float gch[3];  // d rgb, zero for a clamped channel
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int k = 0; k < NSH; ++k) acc = fmaf(f[k * 3 + ch], Y[k], acc);
+                gch[ch] = acc + 0.5f < 0.0f ? 0.0f : grgb[ch];
+            }
+            float wk[16];
+#pragma unroll
+            for (int k = 0; k < NSH; ++k) {
+                wk[k] = gch[0] * f[k * 3] + gch[1] * f[k * 3 + 1] + gch[2] * f[k * 3 + 2];
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) row[k * 3 + ch] = gch[ch] * Y[k];
+            }
+            float gd3[3];
+            sh_grad_dot<DEG>(fx, fy, fz, a.shcf, wk, gd3);
+            const double gdir[3] = {gd3[0], gd3[1], gd3[2]};
+            const double gd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
+            for (int e = 0; e < 3; ++e)
+                dmean[e] = (gdir[e] - dir[e] * gd) * ilen + R[e] * dp[0] + R[3 + e] * dp[1] +
+                           R[6 + e] * dp[2];
         }
-        const double gd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
-        for (int e = 0; e < 3; ++e)
-            dmean[e] = (gdir[e] - dir[e] * gd) / len + R[e] * dp[0] + R[3 + e] * dp[1] + R[6 + e] * dp[2];
+        for (int e = 0; e < 3; ++e) {
+            a.d_means[(size_t)e * n + g] = (float)dmean[e];
+            a.d_log_scales[(size_t)e * n + g] = (float)dls[e];
+        }
+        for (int e = 0; e < 4; ++e) a.d_quats[(size_t)e * n + g] = (float)dq[e];
+        a.d_opacity_logits[g] = (float)dop;
     }
-    for (int e = 0; e < 3; ++e) {
-        a.d_means[(size_t)e * n + g] = (float)dmean[e];
-        a.d_log_scales[(size_t)e * n + g] = (float)dls[e];
-    }
-    for (int e = 0; e < 4; ++e) a.d_quats[(size_t)e * n + g] = (float)dq[e];
-    a.d_opacity_logits[g] = (float)dop;
-    for (int k = 0; k < nsh; ++k)
-        for (int ch = 0; ch < 3; ++ch) a.d_sh[((size_t)k * 3 + ch) * n + g] = (float)dsh[k][ch];
+    __syncthreads();
+    const int cnt = min(128, n - g0);
+    float *dst = a.d_sh + (size_t)g0 * NC;
+    for (int i = threadIdx.x; i < cnt * NC; i += 128) dst[i] = s_dsh[(i / NC) * ROW + i % NC];
 }
 
 hipError_t launch_preprocess_backward(const PreprocessBwdArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    k_preprocess_backward<<<(a.n + 127) / 128, 128, 0, s>>>(a);
+    const unsigned blocks = (unsigned)((a.n + 127) / 128);
+    switch (a.sh_degree) {
+        case 0: k_preprocess_backward<0><<<blocks, 128, 0, s>>>(a); break;
+        case 1: k_preprocess_backward<1><<<blocks, 128, 0, s>>>(a); break;
+        case 2: k_preprocess_backward<2><<<blocks, 128, 0, s>>>(a); break;
+        default: k_preprocess_backward<3><<<blocks, 128, 0, s>>>(a); break;
+    }
     return hipGetLastError();
 }
 

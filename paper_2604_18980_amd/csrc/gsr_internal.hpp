@@ -162,6 +162,7 @@ struct RasterArgs {
     float *image, *final_T;
     uint32_t *n_contrib;
     uint32_t *n_evaluated;  // nullable
+    unsigned long long *work;  // nullable; set: count work instead of writing pixels
 };
 hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStream_t s);
 
@@ -205,6 +206,7 @@ struct PreprocessBwdArgs {
     double R[9], t[3], campos[3];
     double fx, fy, limx, limy;
     double shc[16];
+    float shcf[16];
     const uint32_t *tiles_touched;
     const float *grad_splats;
     float *d_means, *d_log_scales, *d_quats, *d_opacity_logits, *d_sh;

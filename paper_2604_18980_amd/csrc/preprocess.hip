@@ -203,8 +203,18 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
                     const float il = __builtin_amdgcn_rsqf(fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
                     constexpr int nsh = (DEG + 1) * (DEG + 1);
                     float f[nsh * 3];
+                    const float *shg = a.sh + (size_t)g * (nsh * 3);
+                    if constexpr ((nsh * 3) % 4 == 0) {  // 16-byte aligned rows: vector loads
+                        const float4 *s4 = reinterpret_cast<const float4 *>(shg);
 #pragma unroll
-                    for (int k = 0; k < nsh * 3; ++k) f[k] = a.sh[(size_t)k * n + g];
+                        for (int k = 0; k < nsh * 3 / 4; ++k) {
+                            const float4 v = s4[k];
+                            f[4 * k] = v.x; f[4 * k + 1] = v.y; f[4 * k + 2] = v.z; f[4 * k + 3] = v.w;
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < nsh * 3; ++k) f[k] = shg[k];
+                    }
                     float Y[16];
                     sh_eval<float>(DEG, ex * il, ey * il, ez * il, a.shcf, Y);
                     float rgb[3];

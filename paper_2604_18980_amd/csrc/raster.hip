@@ -101,9 +101,21 @@ __device__ __forceinline__ void tile_block(const RasterArgs &a, int tile) {
     if (inside) store_pixel(a, px, py, cr, cg, cb, T, last, evaluated);
 }
 
-// EV: also count, per pixel, the list entries evaluated (n_evaluated output).
-template <bool EV>
+// Wave-wide sum of a 64-bit per-lane value (every lane receives it).
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// MODE 0: the renderer.  MODE 1: also count, per pixel, the list entries
+// evaluated (n_evaluated output).  MODE 2: write no pixels; add this tile's
+// work to a.work[0..3]: list entries evaluated (the n_evaluated sum), strip
+// evaluations executed (one per wave instruction sequence over a 16x4 strip),
+// pixel evaluations that blended a Gaussian, and list entries loaded.
+template <int MODE>
 __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
+    constexpr bool EV = MODE != 0;
     __shared__ float4 s0[4][64], s1[4][64];
     __shared__ float2 s2[4][64];
     const int wid = threadIdx.x / kWave;
@@ -132,6 +144,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
         off[k] = (px < a.width && py < a.height) ? 0.0f : -INFINITY;
     }
     const float4 *spl = reinterpret_cast<const float4 *>(a.splats);
+    uint32_t w_strips = 0, w_blended = 0, w_loaded = 0;  // MODE 2 only
 
     for (uint32_t base = start; base < end; base += kWave) {
         uint32_t alive = 0;
@@ -139,6 +152,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
         for (int k = 0; k < 4; ++k)
             if (__ballot(off[k] == 0.0f) != 0ull) alive |= 1u << k;
         if (!alive) break;
+        if (MODE == 2) w_loaded += min(end - base, (uint32_t)kWave);
         const uint32_t j = base + (uint32_t)lane;
         float mx = 0.f, my = 0.f, A2 = 0.f, beta = 0.f, G2 = 0.f, sig = 0.f, r = 0.f, g = 0.f, bl = 0.f;
         float elim = 0.f;  // alpha >= tau  <=>  exponent (base 2) >= elim
@@ -192,24 +206,38 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (!((m[k] >> cur) & 1ull)) continue;  // uniform: strip k missed
+                if (MODE == 2) ++w_strips;
                 const float dy = smy - fpy[k];
                 const float u = fmaf(sbeta, dy, dx);
-                const float e2 = fmaf(sA2 * u, u, sG2 * (dy * dy));
+                // exponent (base 2) plus the pixel's state offset, folded into
+                // the gamma term's FMA: for a live pixel (offset 0) this is the
+                // rounded product, so e2 is the same as without the offset; a
+                // stopped pixel gets -inf and fails the test below
+                const float e2 = fmaf(sA2 * u, u, fmaf(sG2 * dy, dy, off[k]));
                 // live pixel and opacity * 2^e2 >= tau, decided on the exponent
                 // so the exponential is only taken where it is used
-                if (e2 + off[k] >= selim) {
+                if (e2 >= selim) {
                     const float alpha = fminf(kAlphaMaxF, ssig * __builtin_amdgcn_exp2f(e2));
                     const float wa = alpha * T[k];
                     const float Tn = T[k] - wa;     // T (1 - alpha)
-                    const bool stop = Tn < kStopF;  // not blended; the pixel is done
-                    const float w = stop ? 0.0f : wa;
+                    float w = wa, Tk = Tn;
+                    uint32_t lk = pos;
+                    if (__ballot(Tn < kStopF) != 0ull) {
+                        // rare: some lane stops here (not blended; the pixel is done)
+                        const bool stop = Tn < kStopF;
+                        w = stop ? 0.0f : wa;
+                        Tk = stop ? T[k] : Tn;
+                        lk = stop ? last[k] : pos;
+                        if (EV) ev[k] = stop ? pos : ev[k];
+                        if (MODE == 2) w_blended -= stop ? 1u : 0u;
+                        off[k] = stop ? -INFINITY : off[k];
+                    }
                     cr[k] = fmaf(w, sr, cr[k]);
                     cg[k] = fmaf(w, sg, cg[k]);
                     cb[k] = fmaf(w, sb, cb[k]);
-                    T[k] = stop ? T[k] : Tn;
-                    last[k] = stop ? last[k] : pos;
-                    if (EV) ev[k] = stop ? pos : ev[k];
-                    off[k] = stop ? -INFINITY : off[k];
+                    T[k] = Tk;
+                    last[k] = lk;
+                    if (MODE == 2) ++w_blended;
                 }
             }
         };
@@ -238,6 +266,21 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
             }
         }
     }
+    if (MODE == 2) {
+        unsigned long long e = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (px < a.width && ty * kTile + row0 + 4 * k < a.height) e += ev[k];
+        e = wave_sum_u64(e);
+        const unsigned long long b = wave_sum_u64(w_blended);
+        if (lane == 0) {
+            atomicAdd(&a.work[0], e);
+            atomicAdd(&a.work[1], (unsigned long long)w_strips);
+            atomicAdd(&a.work[2], b);
+            atomicAdd(&a.work[3], (unsigned long long)w_loaded);
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int py = ty * kTile + row0 + 4 * k;
@@ -258,16 +301,18 @@ __global__ __launch_bounds__(256) void k_raster_block(const RasterArgs a) {
 // shared records) measured 1.6x slower on a 6M-Gaussian 4608x3456 frame: the
 // pair load is concentrated in parts of the image, and contiguous bands leave
 // some XCDs with most of the work.
-template <bool EV>
+template <int MODE>
 __global__ __launch_bounds__(256) void k_raster_wave(const RasterArgs a) {
     const int tile = (int)blockIdx.x * 4 + (int)(threadIdx.x / kWave);
     if (tile >= a.tiles_x * a.tiles_y) return;
-    tile_wave<EV>(a, tile);
+    tile_wave<MODE>(a, tile);
 }
 
 hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStream_t s) {
     const unsigned tiles = (unsigned)a.tiles_x * (unsigned)a.tiles_y;
-    if (cfg.threads_per_tile == 256) {
+    if (a.work) {
+        k_raster_wave<2><<<(tiles + 3) / 4, 256, 0, s>>>(a);
+    } else if (cfg.threads_per_tile == 256) {
         switch (cfg.lds_batch) {
             case 64: k_raster_block<64><<<tiles, 256, 0, s>>>(a); break;
             case 128: k_raster_block<128><<<tiles, 256, 0, s>>>(a); break;
@@ -275,9 +320,9 @@ hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStrea
         }
     } else {
         if (a.n_evaluated)
-            k_raster_wave<true><<<(tiles + 3) / 4, 256, 0, s>>>(a);
+            k_raster_wave<1><<<(tiles + 3) / 4, 256, 0, s>>>(a);
         else
-            k_raster_wave<false><<<(tiles + 3) / 4, 256, 0, s>>>(a);
+            k_raster_wave<0><<<(tiles + 3) / 4, 256, 0, s>>>(a);
     }
     return hipGetLastError();
 }
@@ -305,6 +350,7 @@ __device__ __forceinline__ RasterArgs view_args(const ViewsArgs &q, int view) {
     a.final_T = v.final_T;
     a.n_contrib = v.n_contrib;
     a.n_evaluated = nullptr;
+    a.work = nullptr;
     return a;
 }
 
@@ -354,7 +400,7 @@ __global__ __launch_bounds__(256) void k_raster_views_wave(const ViewsArgs q) {
         if ((int64_t)item >= q.n_items) break;
         const uint32_t code = q.items[item];
         const int view = (int)(code >> 26), tile = (int)(code & ((1u << 26) - 1));
-        tile_wave<false>(view_args(q, view), tile);
+        tile_wave<0>(view_args(q, view), tile);
         const uint32_t left = atomicSub(&q.view_left[view], one);
         if (__builtin_amdgcn_readlane((int)left, 0) == 1 && q.clock)
             q.clock[1 + view] = wall_clock64();  // same value from every lane

@@ -15,6 +15,18 @@ import torch
 from . import gsr
 
 
+def sh_to_device_layout(sh):
+    """Host SH [(d+1)^2][3][n] -> the library's Gaussian-major [n][(d+1)^2][3]."""
+    return np.ascontiguousarray(np.asarray(sh, np.float32).transpose(2, 0, 1))
+
+
+def sh_to_host_layout(sh):
+    """The library's [n][(d+1)^2][3] (numpy or tensor) -> host [(d+1)^2][3][n]."""
+    if isinstance(sh, torch.Tensor):
+        sh = sh.detach().cpu().numpy()
+    return np.ascontiguousarray(np.asarray(sh).transpose(1, 2, 0))
+
+
 @dataclass
 class DeviceScene:
     means: torch.Tensor
@@ -30,9 +42,12 @@ class DeviceScene:
 
     @staticmethod
     def from_host(scene, device="cuda") -> "DeviceScene":
+        """Upload a host scene (numpy, SH as [(d+1)^2][3][n]); SH goes to the
+        library's Gaussian-major layout [n][(d+1)^2][3]."""
         f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
         return DeviceScene(f(scene.means), f(scene.log_scales), f(scene.quats),
-                           f(scene.opacity_logits), f(scene.sh), int(scene.sh_degree))
+                           f(scene.opacity_logits), f(sh_to_device_layout(scene.sh)),
+                           int(scene.sh_degree))
 
     def struct(self) -> gsr.GsScene:
         return gsr.scene_struct(self.means, self.log_scales, self.quats, self.opacity_logits,
@@ -101,6 +116,16 @@ def run_bin(fb: FrameBuffers, cam_s, stream=None, with_tiles=False):
 def run_raster(fb: FrameBuffers, cam_s, bg, stream=None, cfg=None, n_evaluated=None):
     gsr.gs_rasterize(fb.splats, fb.n, fb.sorted_gids, fb.ranges, cam_s, bg, cfg, fb.image,
                      fb.final_T, fb.n_contrib, n_evaluated, stream)
+
+
+def raster_work(fb: FrameBuffers, cam_s, stream=None):
+    """The default rasterizer's work on fb's lists (gs_raster_work), as a dict
+    of Python ints; synchronises."""
+    import torch
+    w = torch.zeros(4, dtype=torch.int64, device=fb.image.device)
+    gsr.gs_raster_work(fb.splats, fb.n, fb.sorted_gids, fb.ranges, cam_s, w, stream)
+    v = w.cpu().tolist()
+    return dict(list_evaluations=v[0], strip_evaluations=v[1], blended=v[2], loaded=v[3])
 
 
 def enqueue_frame(scene: DeviceScene, cam_s, mode_s, fb: FrameBuffers, bg=(0.0, 0.0, 0.0),

@@ -12,6 +12,12 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-4
 
 
+def _host(name, t):
+    """A parameter gradient in the host scene layout (SH back to [(d+1)^2][3][n])."""
+    from paper_2604_18980_amd.render import sh_to_host_layout
+    return sh_to_host_layout(t) if name == "sh" else t.cpu().numpy()
+
+
 def _rel(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
@@ -83,7 +89,7 @@ def test_preprocess_backward_matches_oracle(O):
     torch.cuda.synchronize()
     ref = O.preprocess_backward(sc, cam, fr.pre, g2d32.astype(np.float64))
     for name, t in zip(("means", "log_scales", "quats", "opacity_logits", "sh"), out):
-        r = _rel(t.cpu().numpy(), ref[name])
+        r = _rel(_host(name, t), ref[name])
         print(f"{name}: rel {r:.2e}")
         assert r < 1e-5, (name, r)
 
@@ -96,8 +102,10 @@ def test_autograd_end_to_end(O, mode):
     from paper_2604_18980_amd.autograd import rasterize
     sc, cam = scenes.tiny_scene(n=1500, seed=9, sh_degree=3)
     target = scenes.target_image(cam["width"], cam["height"], seed=7)
+    from paper_2604_18980_amd.render import sh_to_device_layout
     params = [torch.from_numpy(np.ascontiguousarray(a)).cuda().requires_grad_(True)
-              for a in (sc.means, sc.log_scales, sc.quats, sc.opacity_logits, sc.sh)]
+              for a in (sc.means, sc.log_scales, sc.quats, sc.opacity_logits,
+                        sh_to_device_layout(sc.sh))]
     fr = O.render(sc, cam, O.Mode(adagscale=mode.get("adagscale", False), K=mode.get("K", 0.0)))
     keep = (fr.margin >= 1e-4).astype(np.float32)  # drop float32-ambiguous pixels from the loss
     img = rasterize(*params, sc.sh_degree, cam, bg=(0.0, 0.0, 0.0), **mode)
@@ -108,6 +116,6 @@ def test_autograd_end_to_end(O, mode):
     g2d = O.blend_backward(fr, cam, dL)
     ref = O.preprocess_backward(sc, cam, fr.pre, g2d)
     for name, p in zip(("means", "log_scales", "quats", "opacity_logits", "sh"), params):
-        r = _rel(p.grad.cpu().numpy(), ref[name])
+        r = _rel(_host(name, p.grad), ref[name])
         print(f"{name}: rel {r:.2e}")
         assert r < TOL, (name, r)

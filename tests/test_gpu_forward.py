@@ -157,6 +157,43 @@ def test_evaluation_counts_match_oracle(O):
     np.testing.assert_array_equal(ne.cpu().numpy()[ok], fr.evals[ok])
 
 
+@pytest.mark.parametrize("which", ["tiny", "mid"])
+def test_raster_work_counts(O, which):
+    """gs_raster_work: its list-evaluation total equals the n_evaluated sum,
+    its blended count equals the oracle's (up to decision-ambiguous pixels),
+    and the strip and load counts are consistent with both."""
+    import torch
+    from paper_2604_18980_amd import gsr, render as R
+    if which == "tiny":
+        sc, cam = scenes.tiny_scene(seed=21)
+    else:
+        sc, cam = scenes.mid_scene(n=40_000, seed=6, width=640, height=360)
+    mode = O.Mode(adagscale=True, K=0.1)
+    ds = R.DeviceScene.from_host(sc)
+    fb = R.render(ds, cam, adagscale=True, K=0.1)
+    cam_s = gsr.camera_struct(cam)
+    ne = torch.empty((cam["height"], cam["width"]), dtype=torch.int32, device="cuda")
+    R.run_raster(fb, cam_s, (0.0, 0.0, 0.0), n_evaluated=ne)
+    w = R.raster_work(fb, cam_s)
+    w2 = R.raster_work(fb, cam_s)
+    assert w == w2
+    P = int(fb.num_pairs.item())
+    print(which, P, w, flush=True)
+    assert w["list_evaluations"] == int(ne.to(torch.int64).sum().item())
+    fr = O.render(sc, cam, mode)
+    ev, bl, mg = O.blend_counts(fr, cam)
+    amb = mg < 1e-4
+    lens = (fr.ranges[:, 1] - fr.ranges[:, 0]).max()
+    slack = int(amb.sum()) * int(lens)
+    assert abs(w["list_evaluations"] - int(ev.sum())) <= slack
+    assert abs(w["blended"] - int(bl.sum())) <= slack
+    assert w["blended"] > 0
+    assert w["blended"] <= 64 * w["strip_evaluations"]
+    assert w["strip_evaluations"] <= 4 * w["loaded"]
+    nonempty = int((fr.ranges[:, 1] > fr.ranges[:, 0]).sum())
+    assert nonempty <= w["loaded"] <= P
+
+
 @pytest.mark.parametrize("geom", [(256, 1, 256), (64, 4, 64)], ids=["block", "wave"])
 @pytest.mark.parametrize("which", ["tiny", "mid"])
 def test_raster_geometries_match_oracle(O, geom, which):

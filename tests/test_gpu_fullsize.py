@@ -113,7 +113,7 @@ def test_diff_1M_1280x720_adjoint(O):
     """dL/dimage drawn on sampled tiles (zero elsewhere and on float32-ambiguous
     pixels); the GPU adjoint against the oracle adjoint over the same tiles."""
     import torch
-    from paper_2604_18980_amd import gsr
+    from paper_2604_18980_amd import gsr, render as R
     sc, cam, _ = scenes.diff_workload()
     mode = dict(adagscale=True, K=0.1)
     print("diff 1M 1280x720 adjoint", flush=True)
@@ -142,7 +142,8 @@ def test_diff_1M_1280x720_adjoint(O):
         assert r < 1e-4, (name, r)
     ref = O.preprocess_backward(sc, cam, pre, g2d)
     for name, t in zip(("means", "log_scales", "quats", "opacity_logits", "sh"), out):
-        r = _rel(to_np(t).astype(np.float64), ref[name])
+        h = R.sh_to_host_layout(t) if name == "sh" else to_np(t)
+        r = _rel(h.astype(np.float64), ref[name])
         print(f"  {name}: rel {r:.2e}", flush=True)
         assert r < 1e-4, (name, r)
 

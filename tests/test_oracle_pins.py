@@ -324,6 +324,34 @@ def test_blend_early_exit_and_clamp(O):
     assert img[0, 8, 8] == pytest.approx(0.99 + 0.99 * 0.01, rel=1e-12)
 
 
+def test_blend_counts_stacked(O):
+    """Work counts on the stacked case: at the centre four entries are
+    evaluated (two blended, the third stops the pixel, the fourth is never
+    reached -> 3 evaluated); far from the centre every alpha is below tau, so
+    all four are evaluated and none blended."""
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 16, 16)
+    g = (8.0, 8.0, 0.5, 0.0, 0.5, 0.999, 1.0, 1.0, 1.0)
+    rec = np.asarray([g] * 4, np.float64).astype(np.float32).astype(np.float64)
+    rg = np.zeros((O.num_tiles(cam), 2), np.int64)
+    rg[:, 1] = 4
+    fr = O.Frame(None, None, None, None, np.arange(4, dtype=np.uint32), rg)
+    ev, bl, mg = O.blend_counts(fr, cam, rec=rec)
+    assert ev[8, 8] == 3 and bl[8, 8] == 2
+    assert ev[0, 0] == 4 and bl[0, 0] == 0
+
+
+def test_blend_counts_invariants_tiny(O):
+    """blended <= n_contrib <= evaluated per pixel; blended > 0 iff n_contrib > 0;
+    evaluated equals the blend's own count."""
+    sc, cam = scenes.tiny_scene(seed=5)
+    fr = O.render(sc, cam, O.Mode(adagscale=True, K=0.1))
+    ev, bl, mg = O.blend_counts(fr, cam)
+    np.testing.assert_array_equal(ev, fr.evals)
+    assert np.all(bl <= fr.n_contrib) and np.all(fr.n_contrib <= ev)
+    np.testing.assert_array_equal(bl > 0, fr.n_contrib > 0)
+    assert bl.sum() > 0
+
+
 def test_blend_skips_below_tau(O):
     """A Gaussian whose alpha stays below 1/255 everywhere contributes nothing."""
     cam = scenes.make_camera(np.eye(3), np.zeros(3), 16, 16)
