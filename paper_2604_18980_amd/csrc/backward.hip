@@ -20,13 +20,12 @@
 #include <math.h>
 
 #include "gsr_internal.hpp"
+#include "raster_cull.hpp"
 
 namespace gsr {
 
 namespace {
 constexpr float kAlphaMaxF = 0.99f;
-constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
-constexpr float kLnTau = -5.5412635451584258f;            // ln(1/255)
 
 // v moved across lanes by the DPP pattern CTRL into the rows in ROW_MASK (0 elsewhere).
 template <int CTRL, int ROW_MASK>
@@ -114,27 +113,9 @@ __global__ __launch_bounds__(256) void k_raster_backward(const RasterBwdArgs a) 
             gid = a.gids[start + j];
             const float4 g0 = spl[3 * (size_t)gid], g1 = spl[3 * (size_t)gid + 1], g2 = spl[3 * (size_t)gid + 2];
             mx = g0.x; my = g0.y; A = g0.z; beta = g0.w; gam = g1.x; sig = g1.y; r = g2.x; g = g2.y; bl = g2.z;
-            // the forward's cull and blend threshold, computed identically
-            const float qlim = 2.0f * (__logf(sig) - kLnTau);
-            elim = kNegHalfLog2e * qlim;
-            if (qlim > -1e-3f) {
-                const float ql = fmaxf(qlim, 0.0f);
-                const float far = fabsf(mx - (x_lo + 7.5f)) + fabsf(my - (float)(ty * kTile) - 7.5f);
-                const float qcut = ql + 1e-3f * (1.0f + ql) +
-                                   1e-5f * far * (1.0f + sqrtf((A + gam) * ql));
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    float qmin = 3.0e38f;
-#pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) {
-                        const float dy = my - (float)(ty * kTile + 4 * k + rr);
-                        const float lo_ = (mx - x_hi) + beta * dy, hi_ = (mx - x_lo) + beta * dy;
-                        const float um = lo_ > 0.0f ? lo_ : (hi_ < 0.0f ? -hi_ : 0.0f);
-                        qmin = fminf(qmin, A * um * um + gam * dy * dy);
-                    }
-                    if (qmin <= qcut) hit |= 1u << k;
-                }
-            }
+            // the forward's blend threshold and strip bound, computed identically
+            elim = alpha_tau_elim(sig);
+            hit = strip_hits(mx, my, A, beta, gam, elim, x_lo, x_hi, (float)(ty * kTile));
         }
         const float A2 = A * kNegHalfLog2e, G2s = gam * kNegHalfLog2e;
         uint64_t m[4], any = 0;

@@ -22,6 +22,7 @@
 //   strips.  A skipped strip has alpha < tau at every pixel, so results are
 //   unchanged.  No barriers: waves run and retire independently.
 #include "gsr_internal.hpp"
+#include "raster_cull.hpp"
 
 namespace gsr {
 
@@ -29,8 +30,6 @@ namespace {
 constexpr float kTauF = 1.0f / 255.0f;
 constexpr float kStopF = 1e-4f;
 constexpr float kAlphaMaxF = 0.99f;
-constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
-constexpr float kLnTau = -5.5412635451584258f;            // ln(1/255)
 
 
 __device__ __forceinline__ void store_pixel(const RasterArgs &a, int px, int py, float cr, float cg,
@@ -126,9 +125,9 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
     const float fpx = (float)px;
     const float x_lo = (float)(tx * kTile), x_hi = (float)(tx * kTile + kTile - 1);
     // Per pixel k: off[k] is 0 while the pixel is live and -inf once it has
-    // stopped (or lies outside the image); it is added to the exponent before
-    // the alpha >= tau test, so "live and alpha >= tau" is one add and one
-    // compare and the per-pixel state needs no boolean merges.
+    // stopped (or lies outside the image); it enters the exponent through the
+    // gamma term's FMA, so "live and alpha >= tau" is one compare and the
+    // per-pixel state needs no boolean merges.
     float fpy[4], T[4], cr[4], cg[4], cb[4], off[4];
     uint32_t last[4], ev[4];
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
@@ -164,30 +163,8 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
             const float A = g0.z, gam = g1.x;
             A2 = A * kNegHalfLog2e;
             G2 = gam * kNegHalfLog2e;
-            // alpha >= tau  <=>  q <= 2 ln(opacity / tau).  The cut gets a margin
-            // above the float32 rounding of both this test and the per-pixel
-            // evaluation: relative 1e-3, plus a term growing with the distance of
-            // the centre (dx and dy lose digits there).
-            const float qlim = 2.0f * (__logf(sig) - kLnTau);
-            elim = kNegHalfLog2e * qlim;
-            if (qlim > -1e-3f) {
-                const float ql = fmaxf(qlim, 0.0f);
-                const float far = fabsf(mx - (x_lo + 7.5f)) + fabsf(my - (float)(ty * kTile) - 7.5f);
-                const float qcut = ql + 1e-3f * (1.0f + ql) +
-                                   1e-5f * far * (1.0f + sqrtf((A + gam) * ql));
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    float qmin = 3.0e38f;
-#pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) {
-                        const float dy = my - (float)(ty * kTile + 4 * k + rr);
-                        const float lo = (mx - x_hi) + beta * dy, hi = (mx - x_lo) + beta * dy;
-                        const float um = lo > 0.0f ? lo : (hi < 0.0f ? -hi : 0.0f);
-                        qmin = fminf(qmin, A * um * um + gam * dy * dy);
-                    }
-                    if (qmin <= qcut) hit |= 1u << k;
-                }
-            }
+            elim = alpha_tau_elim(sig);
+            hit = strip_hits(mx, my, A, beta, gam, elim, x_lo, x_hi, (float)(ty * kTile));
         }
         uint64_t m[4], any = 0;
 #pragma unroll

@@ -101,3 +101,35 @@ def test_bin_overflow_bins_nothing(O, name):
     np.testing.assert_array_equal(fb.image.cpu().numpy(), full["image"])
     np.testing.assert_array_equal(fb.ranges.cpu().numpy().astype(np.uint32).astype(np.int64),
                                   full["ranges"])
+
+
+def test_bin_reused_workspace_matches_fresh(O):
+    """One set of buffers (and so one workspace, whose single-pass look-back
+    state is reset per call) serves frames with many, few and no visible
+    Gaussians in turn; each frame equals a render into fresh buffers."""
+    import torch
+    from paper_2604_18980_amd import render as R
+    sc, cam = scenes.mid_scene(n=40_000, seed=7, width=640, height=360)
+    far = dict(cam)
+    vm = np.asarray(cam["viewmat"], np.float32).reshape(3, 4).copy()
+    vm[2, 3] += 60.0  # step back: fewer Gaussians get tiles
+    far["viewmat"] = vm.reshape(-1)
+    behind = dict(cam)
+    vb = vm.copy()
+    vb[2, 3] = -100.0  # nothing in front
+    behind["viewmat"] = vb.reshape(-1)
+    ds = R.DeviceScene.from_host(sc)
+    fresh = {}
+    for name, c in (("near", cam), ("far", far), ("behind", behind)):
+        fb = R.render(ds, c, adagscale=True, K=0.3, slack=1.2)
+        torch.cuda.synchronize()
+        fresh[name] = (fb.image.clone(), fb.ranges.clone(), int(fb.num_pairs.item()))
+    shared = R.FrameBuffers(ds.n, cam["width"], cam["height"], max(v[2] for v in fresh.values()) + 64)
+    for name, c in (("near", cam), ("far", far), ("behind", behind), ("near", cam), ("far", far)):
+        R.render(ds, c, adagscale=True, K=0.3, fb=shared)
+        torch.cuda.synchronize()
+        img, rg, P = fresh[name]
+        print(f"  {name}: pairs {P}", flush=True)
+        assert int(shared.num_pairs.item()) == P
+        assert torch.equal(shared.ranges, rg)
+        assert torch.equal(shared.image, img)
