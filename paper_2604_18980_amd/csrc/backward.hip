@@ -10,8 +10,8 @@
 // (1 - alpha_i) starting from its final T, so no per-pixel list is stored;
 // alpha and the blend decision are recomputed with exactly the forward's
 // float32 operations, so a pixel differentiates precisely the Gaussians it
-// blended.  Per Gaussian, each lane sums its four pixels' contributions, the
-// wave sums the lanes, and one lane adds the 9 gradients to global memory.
+// blended.  Per Gaussian, each lane sums its four pixels' contributions and
+// the wave's lanes are summed through LDS, a few Gaussians at a time (below).
 //
 // Preprocess backward: one thread per Gaussian, double precision, chaining the
 // 2D record gradients (mean, A, beta, gamma, opacity, colour) back to the scene
@@ -33,18 +33,6 @@ __device__ __forceinline__ float dpp(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
 }
 
-// Sum over the 64 lanes with DPP adds (no LDS traffic): pairs and quads by
-// quad permutes, 8 and 16 lanes by the half-row and row mirrors, then the
-// row-15 and row-31 broadcasts carry the row sums up to lane 63.
-__device__ __forceinline__ float wave_sum(float v) {
-    v += dpp<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-    v += dpp<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-    v += dpp<0x141, 0xF>(v);  // row_half_mirror
-    v += dpp<0x140, 0xF>(v);  // row_mirror
-    v += dpp<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-    v += dpp<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-}
 }  // namespace
 
 __global__ void k_zero_f32(float *p, int64_t m) {
@@ -56,10 +44,45 @@ __device__ __forceinline__ float bcast(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+// Per-Gaussian gradient sums go through LDS: for each contributing Gaussian
+// the lanes add neighbour pairs with one DPP step and park the 32 pair sums
+// of each of the 9 values in a row; every kRedG Gaussians, lane L < 9 kRedG
+// sums row L and adds it to global memory, so one atomic instruction covers
+// them all (in place of 9 wave-wide sums and 9 single-lane atomics each).
+constexpr int kRedG = 5;
+constexpr int kRedRows = 9 * kRedG;
+constexpr int kRedPitch = 36;  // floats per row: 32 pair sums, 16-byte aligned rows
+
 __global__ __launch_bounds__(256) void k_raster_backward(const RasterBwdArgs a) {
+    __shared__ __align__(16) float s_red[4][kRedRows][kRedPitch];
+    __shared__ uint32_t s_rgid[4][kRedG];
     const int tile = (int)blockIdx.x * 4 + (int)(threadIdx.x / kWave);
     if (tile >= a.tiles_x * a.tiles_y) return;
     const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    int nred = 0;  // Gaussians parked (wave-uniform)
+    // offsets of the 9 gradients in a 12-float splat record
+    auto red_off = [](int q) { return q < 6 ? q : q + 2; };
+    auto flush = [&]() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < 9 * nred) {
+            const float4 *row = reinterpret_cast<const float4 *>(&s_red[wid][lane][0]);
+            float sum = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float4 v = row[i];
+                sum += (v.x + v.y) + (v.z + v.w);
+            }
+            const int slot = lane / 9, q = lane - 9 * slot;
+            atomicAdd(a.grad_splats + (size_t)s_rgid[wid][slot] * 12 + red_off(q), sum);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        nred = 0;
+    };
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int col = lane & 15, row0 = lane >> 4;
     const int px = tx * kTile + col;
@@ -149,14 +172,14 @@ __global__ __launch_bounds__(256) void k_raster_backward(const RasterBwdArgs a) 
                     const float e = __builtin_amdgcn_exp2f(e2);
                     const float raw = ssig * e;
                     const float alpha = fminf(kAlphaMaxF, raw);
-                    const float om = 1.0f - alpha;
-                    const float Tb = T[k] / om;  // transmittance in front of this Gaussian
+                    const float iom = 1.0f / (1.0f - alpha);  // one division, four products
+                    const float Tb = T[k] * iom;  // transmittance in front of this Gaussian
                     const float w = alpha * Tb;
                     d[6] = fmaf(w, G0[k], d[6]);
                     d[7] = fmaf(w, G1[k], d[7]);
                     d[8] = fmaf(w, G2[k], d[8]);
-                    const float dLda = G0[k] * (Tb * sr - b0[k] / om) + G1[k] * (Tb * sg - b1[k] / om) +
-                                       G2[k] * (Tb * sb - b2[k] / om);
+                    const float dLda = G0[k] * (Tb * sr - b0[k] * iom) + G1[k] * (Tb * sg - b1[k] * iom) +
+                                       G2[k] * (Tb * sb - b2[k] * iom);
                     b0[k] = fmaf(w, sr, b0[k]);
                     b1[k] = fmaf(w, sg, b1[k]);
                     b2[k] = fmaf(w, sb, b2[k]);
@@ -175,23 +198,16 @@ __global__ __launch_bounds__(256) void k_raster_backward(const RasterBwdArgs a) 
             }
             if (__ballot(contrib) != 0ull) {
 #pragma unroll
-                for (int q = 0; q < 9; ++q) d[q] = wave_sum(d[q]);
-                if (lane == 0) {
-                    const uint32_t sgid = (uint32_t)__builtin_amdgcn_readlane((int)gid, jj);
-                    float *dst = a.grad_splats + (size_t)sgid * 12;
-                    atomicAdd(dst + 0, d[0]);
-                    atomicAdd(dst + 1, d[1]);
-                    atomicAdd(dst + 2, d[2]);
-                    atomicAdd(dst + 3, d[3]);
-                    atomicAdd(dst + 4, d[4]);
-                    atomicAdd(dst + 5, d[5]);
-                    atomicAdd(dst + 8, d[6]);
-                    atomicAdd(dst + 9, d[7]);
-                    atomicAdd(dst + 10, d[8]);
+                for (int q = 0; q < 9; ++q) {
+                    const float pr = d[q] + dpp<0xB1, 0xF>(d[q]);  // lanes 2i, 2i+1: their sum
+                    if ((lane & 1) == 0) s_red[wid][9 * nred + q][lane >> 1] = pr;
                 }
+                if (lane == 0) s_rgid[wid][nred] = (uint32_t)__builtin_amdgcn_readlane((int)gid, jj);
+                if (++nred == kRedG) flush();
             }
         }
     }
+    if (nred > 0) flush();
 }
 
 hipError_t launch_raster_backward(const RasterBwdArgs &a, int64_t n, hipStream_t s) {
