@@ -143,8 +143,12 @@ bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws, int tx,
     ws->counters = (int64_t *)take(sizeof(int64_t) * 4);
     const size_t sort_bytes = align256(off);
     // emit region
-    ws->vis_count = (uint32_t *)take(sizeof(uint32_t) * (size_t)ws->nb_gauss);
-    ws->vis_off = (uint32_t *)take(sizeof(uint32_t) * (size_t)ws->nb_gauss);
+    ws->nb_dgroups = (ws->nb_dsort + kDepthGroup - 1) / kDepthGroup;
+    ws->vis_count = (uint32_t *)take(sizeof(uint32_t) * (size_t)ws->nb_dsort);
+    ws->pair_tot = (uint64_t *)take(sizeof(uint64_t) * (size_t)ws->nb_dsort);
+    // group sums then totals, one region (cleared together)
+    ws->dgsum = (uint32_t *)take(sizeof(uint32_t) * 4 * 256 * (size_t)(ws->nb_dgroups + 1));
+    ws->dtot = ws->dgsum ? ws->dgsum + 4 * 256 * ws->nb_dgroups : nullptr;
     ws->pair_cnt = (uint64_t *)take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     ws->pair_off = (uint64_t *)take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     ws->slice_start = (uint32_t *)take(sizeof(uint32_t) * (size_t)(cap / kEmitChunk + 2));

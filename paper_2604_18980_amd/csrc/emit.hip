@@ -7,9 +7,10 @@
 // sort by tile id (16 bits at 4608x3456) instead of a 48-bit (tile | depth)
 // sort of every pair; the sorted result is the same sequence.
 //
-//   k_vis_count / scan / k_vis_compact   visible Gaussians -> (depth bits, id)
-//   radix_sort_u32                      by depth bits (stable: ties keep id order)
-//   k_pair_block_counts / scan          pairs per block of 256 sorted Gaussians
+//   k_vis_count / k_vis_compact         visible Gaussians -> (depth bits, id)
+//   depth_sort                          by depth bits (stable: ties keep id order)
+//   k_pair_counts / k_pair_offsets      pairs per sorted Gaussian, their prefix,
+//                                       the owner of each emission slice
 //   k_emit                              each block writes its pairs contiguously,
 //                                       one pair per thread per step, after an LDS
 //                                       scan of its Gaussians' tile counts
@@ -19,59 +20,153 @@ namespace gsr {
 
 __global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
 
-__global__ __launch_bounds__(256) void k_vis_count(const uint32_t *tiles_touched, int n,
-                                                   uint32_t *vis_count) {
-    __shared__ uint32_t wt[4];
-    const int g = blockIdx.x * 256 + threadIdx.x;
-    const uint32_t v = (g < n && tiles_touched[g] > 0) ? 1u : 0u;
-    uint32_t tot;
-    block_exclusive_scan<256, uint32_t>(v, wt, &tot);
-    if (threadIdx.x == 0) vis_count[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(256) void k_vis_compact(const uint32_t *tiles_touched, const float *splats,
-                                                     int n, const uint32_t *vis_off, uint32_t *dkey,
-                                                     uint32_t *dval) {
-    __shared__ uint32_t wt[4];
-    const int g = blockIdx.x * 256 + threadIdx.x;
-    const bool vis = g < n && tiles_touched[g] > 0;
-    uint32_t tot;
-    const uint32_t pos = vis_off[blockIdx.x] +
-                         block_exclusive_scan<256, uint32_t>(vis ? 1u : 0u, wt, &tot);
-    if (vis) {
-        dkey[pos] = __float_as_uint(splats[(size_t)g * 12 + 6]);  // depth > 0.2: bits order = value order
-        dval[pos] = (uint32_t)g;
-    }
-}
-
 __device__ __forceinline__ uint32_t rect_tiles(uint64_t r) {
     const uint32_t x0 = r & 0xffff, y0 = (r >> 16) & 0xffff, x1 = (r >> 32) & 0xffff, y1 = r >> 48;
     return (x1 - x0) * (y1 - y0);
 }
 
-// Pairs of each depth-sorted visible Gaussian.
+// Sum over the blocks before this one of a per-block total (a short array:
+// the offset of this block's chunk).  Contains barriers.
+template <typename T>
+__device__ __forceinline__ T sum_before(const T *tot, int64_t b, T *wt) {
+    T acc = 0;
+    for (int64_t i0 = threadIdx.x; i0 < b; i0 += 4 * 256) {  // four loads in flight
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc += i0 + 256 * k < b ? tot[i0 + 256 * k] : (T)0;
+    }
+    T all;
+    block_exclusive_scan<256, T>(acc, wt, &all);
+    return all;
+}
+
+// Visible Gaussians per chunk of 4096 ids; also clears the depth passes'
+// digit totals and group sums (accumulated by k_dhist) and the pair totals
+// per chunk (accumulated by k_pair_counts).
+__global__ __launch_bounds__(256) void k_vis_count(const uint32_t *tiles_touched, int n,
+                                                   uint32_t *vis_count, uint32_t *clear,
+                                                   int64_t nclear, uint64_t *clear64,
+                                                   int64_t nclear64) {
+    __shared__ uint32_t wt[4];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nclear; i += (int64_t)gridDim.x * 256)
+        clear[i] = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nclear64; i += (int64_t)gridDim.x * 256)
+        clear64[i] = 0ull;
+    const int64_t base = (int64_t)blockIdx.x * kSortChunk + threadIdx.x;
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t g = base + (int64_t)i * 256;
+        c += (g < n && tiles_touched[g] > 0u) ? 1u : 0u;
+    }
+    uint32_t tot;
+    block_exclusive_scan<256, uint32_t>(c, wt, &tot);
+    if (threadIdx.x == 0) vis_count[blockIdx.x] = tot;
+}
+
+// Visible Gaussians in id order as (depth bits, id).  Block b owns ids
+// [4096 b, 4096 b + 4096): wave w the 1024 from 4096 b + 1024 w, lane l item
+// i at ... + 64 i + l, so ballots order each wave's items; the block's output
+// offset is the sum of the earlier blocks' counts.  The last block stores the
+// visible count.
+__global__ __launch_bounds__(256) void k_vis_compact(const uint32_t *tiles_touched, const float *splats,
+                                                     int n, const uint32_t *vis_count, uint32_t *dkey,
+                                                     uint32_t *dval, int64_t *num_vis) {
+    __shared__ uint32_t wt[4], s_wcnt[4];
+    const int64_t b = blockIdx.x;
+    const uint32_t before = sum_before<uint32_t>(vis_count, b, wt);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int64_t wbase = b * kSortChunk + (int64_t)wid * 1024 + lane;
+    const uint64_t lt = lanemask_lt();
+    uint64_t m[kSortItems];
+    uint32_t pos[kSortItems], wc = 0;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t g = wbase + 64 * i;
+        m[i] = __ballot(g < n && tiles_touched[g] > 0u);
+        pos[i] = wc + (uint32_t)__popcll(m[i] & lt);
+        wc += (uint32_t)__popcll(m[i]);
+    }
+    if (lane == 0) s_wcnt[wid] = wc;
+    __syncthreads();
+    uint32_t woff = before, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        woff += w < wid ? s_wcnt[w] : 0u;
+        tot += s_wcnt[w];
+    }
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        if ((m[i] >> lane) & 1ull) {
+            const int64_t g = wbase + 64 * i;
+            dkey[woff + pos[i]] = __float_as_uint(splats[(size_t)g * 12 + 6]);  // depth > 0.2: bits order = value order
+            dval[woff + pos[i]] = (uint32_t)g;
+        }
+    }
+    if (threadIdx.x == 0 && b == (int64_t)gridDim.x - 1) *num_vis = (int64_t)(before + tot);
+}
+
+// Pairs of each depth-sorted visible Gaussian (one per thread), added to the
+// total of its chunk of 4096 (cleared by k_vis_count).
 __global__ __launch_bounds__(256) void k_pair_counts(const uint32_t *sorted_ids, const int64_t *num_vis,
-                                                     const uint64_t *rects, uint64_t *cnt, int64_t n) {
+                                                     const uint64_t *rects, uint64_t *cnt,
+                                                     uint64_t *chunk_tot) {
+    __shared__ uint64_t wt[4];
+    const int64_t V = *num_vis;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= n || j >= *num_vis) return;
-    cnt[j] = (uint64_t)rect_tiles(rects[sorted_ids[j]]);
+    if ((int64_t)blockIdx.x * 256 >= V) return;  // uniform
+    uint64_t c = 0;
+    if (j < V) {
+        c = rect_tiles(rects[sorted_ids[j]]);
+        cnt[j] = c;
+    }
+    uint64_t tot;
+    block_exclusive_scan<256, uint64_t>(c, wt, &tot);
+    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&chunk_tot[(int64_t)blockIdx.x * 256 / kSortChunk],
+                                           (unsigned long long)tot);
+}
+
+// Exclusive prefix of the pair counts (the chunk's offset is the sum of the
+// earlier chunks' totals), the first Gaussian of each emission slice that
+// starts below the capacity, and the total (stored by the last live chunk).
+__global__ __launch_bounds__(256) void k_pair_offsets(const uint64_t *cnt, const uint64_t *chunk_tot,
+                                                      const int64_t *num_vis, uint64_t *off,
+                                                      uint32_t *bstart, int64_t *num_pairs, int64_t cap) {
+    __shared__ uint64_t wt[4];
+    const int64_t V = *num_vis;
+    const int64_t b = blockIdx.x;
+    if (V == 0) {
+        if (b == 0 && threadIdx.x == 0) *num_pairs = 0;
+        return;
+    }
+    if (b * kSortChunk >= V) return;  // uniform
+    const uint64_t before = sum_before<uint64_t>(chunk_tot, b, wt);
+    const int64_t j0 = b * kSortChunk + (int64_t)threadIdx.x * kSortItems;  // 16 consecutive
+    uint64_t c[kSortItems], acc = 0;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        c[i] = j0 + i < V ? cnt[j0 + i] : 0ull;
+        acc += c[i];
+    }
+    uint64_t tot;
+    uint64_t run = before + block_exclusive_scan<256, uint64_t>(acc, wt, &tot);
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        if (j0 + i < V) {
+            off[j0 + i] = run;
+            const uint64_t p1 = run + c[i];
+            for (uint64_t s = (run + kEmitChunk - 1) / kEmitChunk;
+                 s * kEmitChunk < p1 && (int64_t)(s * kEmitChunk) < cap; ++s)
+                bstart[s] = (uint32_t)(j0 + i);
+        }
+        run += c[i];
+    }
+    if (threadIdx.x == 0 && (b + 1) * kSortChunk >= V) *num_pairs = (int64_t)(before + tot);
 }
 
 // Emission is split into fixed slices of kEmitChunk pairs, one per workgroup,
 // so a few huge Gaussians cannot serialise one block.  bstart[b] = the sorted
-// Gaussian that owns pair b * kEmitChunk (each Gaussian marks the slices that
-// begin inside its pair range).
-
-__global__ __launch_bounds__(256) void k_slice_starts(const uint64_t *off, const uint64_t *cnt,
-                                                      const int64_t *num_vis, uint32_t *bstart,
-                                                      int64_t n, int64_t cap) {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= n || j >= *num_vis) return;
-    const uint64_t p0 = off[j], p1 = p0 + cnt[j];
-    // only slices that start below the capacity are ever emitted
-    for (uint64_t b = (p0 + kEmitChunk - 1) / kEmitChunk; b * kEmitChunk < p1 && (int64_t)(b * kEmitChunk) < cap; ++b)
-        bstart[b] = (uint32_t)j;
-}
+// Gaussian that owns pair b * kEmitChunk (k_pair_offsets marks the slices
+// that begin inside each Gaussian's pair range).
 
 __global__ __launch_bounds__(256) void k_emit(const uint32_t *sorted_ids, const int64_t *num_vis,
                                               const uint64_t *rects, const uint64_t *off,
@@ -131,29 +226,24 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *sorted_ids, const 
 hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
                                const uint32_t *tiles_touched, int n, int64_t cap, int64_t *num_pairs,
                                const Workspace &ws, hipStream_t s) {
-    const int64_t nb = ws.nb_gauss;
     int64_t *num_vis = ws.counters;
     if (n == 0) {
         k_set_i64<<<1, 1, 0, s>>>(num_pairs, 0);
         k_set_i64<<<1, 1, 0, s>>>(num_vis, 0);
         return hipGetLastError();
     }
-    k_vis_count<<<(unsigned)nb, 256, 0, s>>>(tiles_touched, n, ws.vis_count);
-    hipError_t e = scan_exclusive_u32(ws.vis_count, ws.vis_off, nb, ws.scan_part, num_vis, s);
+    const unsigned nb = (unsigned)ws.nb_dsort;  // chunks of 4096 (ids, then visible Gaussians)
+    // the depth passes' digit group sums and totals are contiguous: clear both
+    k_vis_count<<<nb, 256, 0, s>>>(tiles_touched, n, ws.vis_count, ws.dgsum,
+                                   4 * 256 * (ws.nb_dgroups + 1), ws.pair_tot, ws.nb_dsort);
+    k_vis_compact<<<nb, 256, 0, s>>>(tiles_touched, splats, n, ws.vis_count, ws.dkey[0], ws.dval[0],
+                                     num_vis);
+    hipError_t e = depth_sort(ws, num_vis, s);  // dkey/dval[0] -> [1]
     if (e != hipSuccess) return e;
-    k_vis_compact<<<(unsigned)nb, 256, 0, s>>>(tiles_touched, splats, n, ws.vis_off, ws.dkey[0],
-                                              ws.dval[0]);
-    e = radix_sort_u32(ws.dkey[0], ws.dval[0], ws.dkey[1], ws.dval[1], ws.dkey[2], ws.dval[2],
-                       num_vis, n, 32, ws.dhist, ws.nb_dsort, ws.scan_part, s);
-    if (e != hipSuccess) return e;
-    k_pair_counts<<<(unsigned)nb, 256, 0, s>>>(ws.dval[1], num_vis, rects, ws.pair_cnt, n);
-    // only the num_vis leading entries are live
-    e = scan_exclusive_u64(ws.pair_cnt, ws.pair_off, n, ws.scan_part, num_pairs, s,
-                           DevExtent{num_vis, n, 1, 1});
-    if (e != hipSuccess) return e;
-    if (cap > 0)
-        k_slice_starts<<<(unsigned)nb, 256, 0, s>>>(ws.pair_off, ws.pair_cnt, num_vis, ws.slice_start,
-                                                   n, cap);
+    k_pair_counts<<<(unsigned)ws.nb_gauss, 256, 0, s>>>(ws.dval[1], num_vis, rects, ws.pair_cnt,
+                                                       ws.pair_tot);
+    k_pair_offsets<<<nb, 256, 0, s>>>(ws.pair_cnt, ws.pair_tot, num_vis, ws.pair_off, ws.slice_start,
+                                      num_pairs, cap);
     return hipGetLastError();
 }
 

@@ -32,8 +32,11 @@ struct PreprocessArgs {
 // Workspace layout, computed identically by the size query and every stage.
 struct Workspace {
     // emit
-    uint32_t *vis_count;   // [nb_gauss]
-    uint32_t *vis_off;     // [nb_gauss]
+    uint32_t *vis_count;   // [nb_dsort] visible Gaussians per chunk of 4096 ids
+    uint64_t *pair_tot;    // [nb_dsort] pairs per chunk of 4096 depth-sorted visible Gaussians
+    uint32_t *dgsum;       // [4][256][groups of 32 blocks] depth-pass digit sums per block group
+    uint32_t *dtot;        // [4][256] depth-pass digit totals
+    int64_t nb_dgroups;
     uint64_t *pair_cnt;    // [n] pairs of each depth-sorted visible Gaussian
     uint64_t *pair_off;    // [n] their exclusive prefix
     uint32_t *slice_start; // [cap / emit chunk + 1] first Gaussian of each emission slice
@@ -74,6 +77,8 @@ constexpr int kSortChunk = kSortThreads * kSortItems;     // 4096 items per bloc
 // pairs per emission slice (one workgroup each); slice_start[b] is the
 // depth-sorted Gaussian that owns pair b * kEmitChunk
 constexpr int kEmitChunk = 4096;
+// depth presort: blocks per group of the two-level digit offsets
+constexpr int kDepthGroup = 32;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanChunk = kScanThreads * kScanItems;     // 4096 elements per block
@@ -136,6 +141,10 @@ hipError_t launch_emit(const float *splats, const uint64_t *rects, const uint32_
 // depth order (ws.dval[1], count in ws.counters[0]), their pair counts and
 // offsets (ws.pair_cnt, ws.pair_off), the pair total, and the emission slice
 // owners (ws.slice_start, when cap > 0).
+// Stable sort of the visible Gaussians' depth keys dkey/dval[0] (count in
+// device memory) into dkey/dval[1]: four 8-bit LSD passes of two kernels
+// each (digit offsets from block-group sums, no device-wide scan kernels).
+hipError_t depth_sort(const Workspace &ws, const int64_t *count, hipStream_t s);
 hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
                                const uint32_t *tiles_touched, int n, int64_t cap, int64_t *num_pairs,
                                const Workspace &ws, hipStream_t s);

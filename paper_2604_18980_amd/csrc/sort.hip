@@ -53,19 +53,25 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const T *in, T *out,
     __shared__ uint64_t wt64[kScanThreads / kWave];
     m = ext.resolve(m);
     if ((int64_t)blockIdx.x * kScanChunk >= m) return;
-    uint64_t before = 0;
-    for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanThreads) before += parts[i];
-    uint64_t btot;
-    block_exclusive_scan<kScanThreads, uint64_t>(before, wt64, &btot);
+    // the chunk and the partials before it are requested together
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
     T v[kScanItems];
-    T acc = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t idx = base + i;
         v[i] = idx < m ? in[idx] : 0;
-        acc += v[i];
     }
+    uint64_t before = 0;
+    for (int64_t i0 = threadIdx.x; i0 < (int64_t)blockIdx.x; i0 += 4 * kScanThreads) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            before += i0 + k * kScanThreads < (int64_t)blockIdx.x ? parts[i0 + k * kScanThreads] : 0ull;
+    }
+    uint64_t btot;
+    block_exclusive_scan<kScanThreads, uint64_t>(before, wt64, &btot);
+    T acc = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) acc += v[i];
     T tot;
     T run = block_exclusive_scan<kScanThreads, T>(acc, wt, &tot) + (T)btot;
 #pragma unroll
@@ -205,6 +211,106 @@ void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32
     radix_hist(kin, count, cap, shift, hist, nblocks, parts, s, empty_if_over);
     k_radix_scatter<<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, count, cap,
                                                                 shift, hist, nblocks, empty_if_over);
+}
+
+// ---------------------------------------------------------- depth presort
+// The same LSD passes without the device-wide scan kernels: the histogram
+// kernel also adds each block's digit counts to per-digit totals and to sums
+// over groups of kDepthGroup blocks, and each scatter block forms its digit
+// offsets itself -- the exclusive scan of the totals over digits, plus the
+// sums of the earlier groups, plus the counts of the earlier blocks of its
+// own group (at most nb / kDepthGroup + kDepthGroup - 1 reads per digit).
+__global__ __launch_bounds__(kSortThreads) void k_dhist(const uint32_t *keys, const int64_t *count,
+                                                        int shift, uint32_t *hist, int64_t nb,
+                                                        uint32_t *gsum, int64_t ngroups,
+                                                        uint32_t *tot) {
+    __shared__ uint32_t h[kSortThreads / kWave][256];
+    const int wid = threadIdx.x / kWave;
+    for (int i = threadIdx.x; i < (kSortThreads / kWave) * 256; i += kSortThreads) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t n = *count;
+    const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+    if (base >= n) return;  // uniform
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&h[wid][(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    const int d = threadIdx.x;
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kSortThreads / kWave; ++w) c += h[w][d];
+    hist[(int64_t)d * nb + blockIdx.x] = c;
+    if (c) {
+        atomicAdd(gsum + (int64_t)d * ngroups + blockIdx.x / kDepthGroup, c);
+        atomicAdd(tot + d, c);
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_dscatter(const uint32_t *kin, const uint32_t *vin,
+                                                           uint32_t *kout, uint32_t *vout,
+                                                           const int64_t *count, int shift,
+                                                           const uint32_t *hist, int64_t nb,
+                                                           const uint32_t *gsum, int64_t ngroups,
+                                                           const uint32_t *tot) {
+    __shared__ RankSmem sm;
+    __shared__ uint32_t skey[kSortChunk];
+    __shared__ uint32_t sval[kSortChunk];
+    __shared__ uint32_t s_wt[kSortThreads / kWave];
+    rank_init(sm);
+    const int64_t n = *count;
+    const int64_t b = blockIdx.x;
+    const int64_t base = b * kSortChunk;
+    if (base >= n) return;  // uniform
+    // the chunk's keys, the digit totals and this block's earlier counts are
+    // all requested before any of them is used (one round trip, mostly to
+    // other XCDs' writes)
+    const int cnt = (int)(n - base < kSortChunk ? n - base : kSortChunk);
+    uint32_t key[kSortItems], val[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int p = rank_pos(i);
+        key[i] = p < cnt ? kin[base + p] : 0u;
+        val[i] = p < cnt ? vin[base + p] : 0u;
+    }
+    const int d = threadIdx.x;
+    const int64_t g = b / kDepthGroup;
+    const uint32_t t = tot[d];
+    uint32_t pre = 0;
+    const uint32_t *hrow = hist + (int64_t)d * nb + g * kDepthGroup;
+    const int in_group = (int)(b - g * kDepthGroup);
+#pragma unroll
+    for (int i = 0; i < kDepthGroup - 1; ++i) pre += i < in_group ? hrow[i] : 0u;
+    const uint32_t *grow = gsum + (int64_t)d * ngroups;
+    for (int64_t i0 = 0; i0 < g; i0 += 8) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) pre += i0 + i < g ? grow[i0 + i] : 0u;
+    }
+    uint32_t all;
+    sm.gbase[d] = block_exclusive_scan<kSortThreads, uint32_t>(t, s_wt, &all) + pre;
+    __syncthreads();
+    rank_stage_write(
+        key, val, cnt, shift, sm, skey, sval, [](uint32_t, uint32_t v) { return v; },
+        [&](int64_t dst, uint32_t k, uint32_t v) {
+            kout[dst] = k;
+            vout[dst] = v;
+        });
+}
+
+hipError_t depth_sort(const Workspace &ws, const int64_t *count, hipStream_t s) {
+    // 0 -> 2 -> 1 -> 2 -> 1: the fourth pass lands in buffer 1
+    const int src[4] = {0, 2, 1, 2}, dst[4] = {2, 1, 2, 1};
+    const unsigned nb = (unsigned)ws.nb_dsort;
+    for (int p = 0; p < 4; ++p) {
+        uint32_t *gsum = ws.dgsum + (int64_t)p * 256 * ws.nb_dgroups, *tot = ws.dtot + 256 * p;
+        k_dhist<<<nb, kSortThreads, 0, s>>>(ws.dkey[src[p]], count, 8 * p, ws.dhist, ws.nb_dsort, gsum,
+                                           ws.nb_dgroups, tot);
+        k_dscatter<<<nb, kSortThreads, 0, s>>>(ws.dkey[src[p]], ws.dval[src[p]], ws.dkey[dst[p]],
+                                              ws.dval[dst[p]], count, 8 * p, ws.dhist, ws.nb_dsort,
+                                              gsum, ws.nb_dgroups, tot);
+    }
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------- tile ranges
