@@ -44,7 +44,7 @@ PSNR_TARGET_DB = 29.8
 # HBM bytes of one AdaGScale-frame raster launch (K = 459.18) from rocprofv3 FETCH_SIZE x 2.0
 # + WRITE_SIZE x 1.0 (copy-calibrated; profiles/city_6M_4608x3456_hbm_counters.md), valid
 # only for the rasterizer source they were taken with.
-RASTER_TRAFFIC = {"source_sha256_16": "efb343192bb4a21c", "bytes": (153.0 + 332.6) * 1e6}
+RASTER_TRAFFIC = {"source_sha256_16": "20cf0fbf11887123", "bytes": (153.9 + 337.9) * 1e6}
 
 
 def log(*a):
@@ -61,7 +61,7 @@ def parse():
     p.add_argument("--height", type=int, default=3456)
     p.add_argument("--K", type=float, default=None, help="fixed K (skip the search)")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample-tiles", type=int, default=6)
+    p.add_argument("--cpu-sample-tiles", type=int, default=1024)
     p.add_argument("--workload", choices=("city", "diff", "batched"), default="city",
                    help="city: the headline FPS line; diff: forward+backward on the 1M "
                         "differentiable workload; batched: 64 views in one graph")
