@@ -415,8 +415,10 @@ typedef struct {
     uint64_t sig;      /* hash of the blended positions */
 } pix_t;
 
+/* max_t (nullable, [n]): per Gaussian, the largest transmittance in front of
+ * it at a pixel where it is blended (the max(T^i) of Sec. 3.2). */
 static void blend_pixel(double px, double py, const uint32_t *list, int64_t len, const double *rec,
-                        pix_t *o) {
+                        pix_t *o, double *max_t) {
     double T = 1.0, C[3] = {0.0, 0.0, 0.0}, margin = INFINITY;
     int64_t last = 0, blended = 0, ev = 0;
     uint64_t sig = 1469598103934665603ull;
@@ -437,6 +439,7 @@ static void blend_pixel(double px, double py, const uint32_t *list, int64_t len,
         if (mt < margin) margin = mt;
         if (Tn < T_STOP) break;
         for (int ch = 0; ch < 3; ++ch) C[ch] += alpha * T * g[6 + ch];
+        if (max_t && T > max_t[list[j]]) max_t[list[j]] = T;
         T = Tn;
         last = j + 1;
         ++blended;
@@ -461,11 +464,13 @@ static void store_pixel(const pix_t *o, int64_t idx, int64_t npix, const double 
 /* Tile-list rasterizer: pixel (px, py) lies in tile (px/16, py/16) and blends
  * that tile's sorted list.  tiles: optional subset of tile ids (n_sel >= 0);
  * n_sel < 0 blends every tile.  Outputs are [3][H][W] and [H][W]; margin,
- * evals, sig and blended (Gaussians blended per pixel) may be NULL. */
+ * evals, sig, blended (Gaussians blended per pixel) and max_t (per Gaussian,
+ * raised to the transmittance in front of it where it blends; caller
+ * initialises) may be NULL. */
 void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *sorted_vals,
                const double *rec, const double *bg, const int32_t *tiles, int64_t n_sel,
                double *image, double *final_T, int64_t *n_contrib, double *margin, int64_t *evals,
-               uint64_t *sig, int64_t *blended) {
+               uint64_t *sig, int64_t *blended, double *max_t) {
     int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
     int64_t npix = (int64_t)width * height;
     int64_t count = n_sel >= 0 ? n_sel : (int64_t)TX * TY;
@@ -476,7 +481,7 @@ void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *sor
             for (int px = tx * TILE; px < (tx + 1) * TILE && px < width; ++px) {
                 pix_t o;
                 blend_pixel((double)px, (double)py, sorted_vals + ranges[2 * t],
-                            ranges[2 * t + 1] - ranges[2 * t], rec, &o);
+                            ranges[2 * t + 1] - ranges[2 * t], rec, &o, max_t);
                 store_pixel(&o, (int64_t)py * width + px, npix, bg, image, final_T, n_contrib,
                             margin, evals, sig, blended);
             }
@@ -518,7 +523,7 @@ void orc_blend_bruteforce(int mode, int64_t n, int width, int height, const int3
             qsort(cand, (size_t)m, sizeof(di_t), di_cmp);
             for (int64_t k = 0; k < m; ++k) list[k] = cand[k].i;
             pix_t o;
-            blend_pixel((double)px, (double)py, list, m, rec, &o);
+            blend_pixel((double)px, (double)py, list, m, rec, &o, NULL);
             store_pixel(&o, (int64_t)py * width + px, npix, bg, image, final_T, n_contrib, NULL,
                         NULL, NULL, NULL);
             (void)TX;
@@ -819,6 +824,22 @@ void orc_preprocess_backward(int64_t n, const float *means, const float *log_sca
 /* The oracle's constants, for comparison with the values printed in the paper:
  * tau, early-exit T, LUT bins, 2 pi, alpha clamp, near plane, dilation,
  * frustum slack, discriminant floor, tile size. */
+/* T_upper look-up table (Sec. 3.4): LUT_BINS uniform depth bins over
+ * [0, lut_depth_max); bin = min(floor(LUT_BINS depth / lut_depth_max),
+ * LUT_BINS - 1) of the float32 depth; each bin takes the largest max_t of the
+ * Gaussians in it that were blended somewhere (max_t > 0), raising lut[]
+ * (the caller initialises it, 0 for a first view).  Several views accumulate
+ * by calling once per view. */
+void orc_t_upper_accumulate(int64_t n, const float *depth, const double *max_t, double lut_depth_max,
+                            double *lut) {
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(max_t[i] > 0.0)) continue;
+        const double f = ((double)depth[i] * LUT_BINS) / lut_depth_max;
+        const int bin = f >= LUT_BINS - 1 ? LUT_BINS - 1 : (int)floor(f);
+        if (max_t[i] > lut[bin]) lut[bin] = max_t[i];
+    }
+}
+
 void orc_constants(double *out) {
     out[0] = TAU; out[1] = T_STOP; out[2] = LUT_BINS; out[3] = TWO_PI; out[4] = ALPHA_MAX;
     out[5] = NEAR_Z; out[6] = DILATION; out[7] = FRUSTUM_SLACK; out[8] = LAMBDA_FLOOR; out[9] = TILE;

@@ -61,7 +61,8 @@ def lib():
         L.orc_emit.restype = C.c_int64
         L.orc_sort.argtypes = [C.c_int64, P, P]
         L.orc_ranges.argtypes = [C.c_int64, P, C.c_int, P]
-        L.orc_blend.argtypes = [C.c_int, C.c_int, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P]
+        L.orc_blend.argtypes = [C.c_int, C.c_int, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P]
+        L.orc_t_upper_accumulate.argtypes = [C.c_int64, P, P, C.c_double, P]
         L.orc_blend_bruteforce.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_int, P, P, P, P, P, P,
                                            P, P]
         L.orc_blend_backward.argtypes = [C.c_int, C.c_int, P, P, P, P, P, P, P, C.c_int64]
@@ -228,7 +229,7 @@ def blend(frame_or_parts, cam, bg=(0.0, 0.0, 0.0), tiles=None, rec=None):
         sel = np.ascontiguousarray(tiles, np.int32)
         nsel = sel.size
     lib().orc_blend(W, H, _p(rg), _p(sv), _p(rec), _p(bgv), _p(sel), nsel, _p(img), _p(T),
-                    _p(nc), _p(mg), _p(ev), _p(sg), None)
+                    _p(nc), _p(mg), _p(ev), _p(sg), None, None)
     return img, T, nc, mg, ev, sg
 
 
@@ -250,8 +251,45 @@ def blend_counts(frame: "Frame", cam, tiles=None, rec=None):
     sel = None if tiles is None else np.ascontiguousarray(tiles, np.int32)
     nsel = -1 if sel is None else sel.size
     lib().orc_blend(W, H, _p(rg), _p(sv), _p(rec), _p(bgv), _p(sel), nsel, _p(img), _p(T),
-                    _p(nc), _p(mg), _p(ev), None, _p(bl))
+                    _p(nc), _p(mg), _p(ev), None, _p(bl), None)
     return ev, bl, mg
+
+
+def max_transmittance(frame: "Frame", cam, rec=None):
+    """Per Gaussian, the largest transmittance in front of it over the pixels
+    where it is blended (max(T^i), Sec. 3.2); 0 where it is never blended.
+    Also returns the per-pixel decision margin."""
+    W, H = cam["width"], cam["height"]
+    if rec is None:
+        rec = frame.pre.record()
+    n = rec.shape[0]
+    img = np.zeros((3, H, W))
+    T = np.zeros((H, W))
+    nc = np.zeros((H, W), np.int64)
+    mg = np.full((H, W), np.inf)
+    mt = np.zeros(max(n, 1))
+    rg = np.ascontiguousarray(frame.ranges, np.int64)
+    sv = np.ascontiguousarray(frame.sorted_vals, np.uint32)
+    lib().orc_blend(W, H, _p(rg), _p(sv), _p(np.ascontiguousarray(rec, np.float64)), _p(np.zeros(3)),
+                    None, -1, _p(img), _p(T), _p(nc), _p(mg), None, None, None, _p(mt))
+    return mt[:n], mg
+
+
+def t_upper_accumulate(depth_f32, max_t, lut_depth_max, lut=None):
+    """Raise the 20-bin T_upper table (Sec. 3.4) with one view's per-Gaussian
+    max transmittance, binned by the float32 depth; returns the table."""
+    lut = np.zeros(20) if lut is None else np.ascontiguousarray(lut, np.float64)
+    d = np.ascontiguousarray(depth_f32, np.float32)
+    m = np.ascontiguousarray(max_t, np.float64)
+    lib().orc_t_upper_accumulate(d.size, _p(d), _p(m), float(lut_depth_max), _p(lut))
+    return lut
+
+
+def t_upper_finish(lut):
+    """Bins no calibration Gaussian fell in get 1 (the trivial bound)."""
+    lut = np.asarray(lut, np.float64).copy()
+    lut[~(lut > 0)] = 1.0
+    return lut
 
 
 def render(scene, cam, mode: Mode = Mode(), bg=(0.0, 0.0, 0.0), tiles=None) -> Frame:

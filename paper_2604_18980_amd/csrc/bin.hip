@@ -280,8 +280,15 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_hist2(const uint32_t *pack
     for (int i = threadIdx.x; i < (kSortThreads / kWave) * 256; i += kSortThreads) (&h[0][0])[i] = 0;
     __syncthreads();
     const int wid = threadIdx.x / kWave;
-    for (int k = threadIdx.x; k < pb.cnt; k += kSortThreads)
-        atomicAdd(&h[wid][packed[pb.base + k] >> kRankBits], 1u);
+    uint32_t w[kSortItems];  // all loads in flight before the first count
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int k = threadIdx.x + i * kSortThreads;
+        w[i] = k < pb.cnt ? packed[pb.base + k] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i)
+        if (threadIdx.x + i * kSortThreads < pb.cnt) atomicAdd(&h[wid][w[i] >> kRankBits], 1u);
     __syncthreads();
     const int d = threadIdx.x;
     uint32_t tot = 0;

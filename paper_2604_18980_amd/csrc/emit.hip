@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_vis_compact(const uint32_t *tiles_touch
     const int64_t b = blockIdx.x;
     const uint32_t before = sum_before<uint32_t>(vis_count, b, wt);
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    const int64_t wbase = b * kSortChunk + (int64_t)wid * 1024 + lane;
+    const int64_t wbase = b * kSortChunk + (int64_t)wid * (kSortItems * kWave) + lane;
     const uint64_t lt = lanemask_lt();
     uint64_t m[kSortItems];
     uint32_t pos[kSortItems], wc = 0;

@@ -76,7 +76,7 @@ constexpr int kSortItems = GSR_SORT_ITEMS;                // per thread
 constexpr int kSortChunk = kSortThreads * kSortItems;     // 4096 items per block
 // pairs per emission slice (one workgroup each); slice_start[b] is the
 // depth-sorted Gaussian that owns pair b * kEmitChunk
-constexpr int kEmitChunk = 4096;
+constexpr int kEmitChunk = kSortChunk;
 // depth presort: blocks per group of the two-level digit offsets
 constexpr int kDepthGroup = 32;
 constexpr int kScanThreads = 256;
