@@ -225,6 +225,23 @@ gs_status gs_raster_work(const float *splats, int64_t n, const uint32_t *sorted_
                          const uint32_t *ranges, const gs_camera *cam, uint64_t *work,
                          void *stream);
 
+/* T_upper calibration (Sec. 3.2, transmittance approximation; Sec. 3.4):
+ * runs the default rasterizer's walk over these lists (plain-mode lists of a
+ * calibration view) without writing pixels, and for every Gaussian it blends
+ * takes the largest transmittance in front of it over the pixels where it is
+ * blended, max(T^i).  That value, as float bits, raises
+ *   t_upper_bits[bin]   (device uint32[GS_LUT_BINS]; required) with bin =
+ *                       min(floor(GS_LUT_BINS * depth / lut_depth_max),
+ *                       GS_LUT_BINS - 1) of the record's float32 depth,
+ *                       evaluated in double;
+ *   max_t_bits[i]       (device uint32[n]; nullable) per Gaussian.
+ * Both are raised with atomic max and never cleared: the caller zeroes them
+ * once and calls once per calibration view.  A bin left at 0 saw no blended
+ * Gaussian (take 1.0, the trivial bound, for it).  lut_depth_max > 0. */
+gs_status gs_calibrate_t_upper(const float *splats, int64_t n, const uint32_t *sorted_gids,
+                               const uint32_t *ranges, const gs_camera *cam, float lut_depth_max,
+                               uint32_t *t_upper_bits, uint32_t *max_t_bits, void *stream);
+
 /* Adjoint of stage 4 with the pair set and every blend decision of the
  * forward pass frozen.  Walks each pixel's list back to front from n_contrib,
  * recovering T_i = T_{i+1} / (1 - alpha_i) from final_T instead of storing

@@ -366,6 +366,8 @@ gs_status gs_rasterize(const float *splats, int64_t n, const uint32_t *sorted_gi
     a.n_contrib = n_contrib;
     a.n_evaluated = n_evaluated;
     a.work = nullptr;
+    a.lut_bits = a.max_t_bits = nullptr;
+    a.lut_depth_max = 0.0;
     return hip_check(launch_raster(a, c, (hipStream_t)stream), "gs_rasterize");
 }
 
@@ -390,8 +392,40 @@ gs_status gs_raster_work(const float *splats, int64_t n, const uint32_t *sorted_
     a.n_contrib = nullptr;
     a.n_evaluated = nullptr;
     a.work = reinterpret_cast<unsigned long long *>(work);
+    a.lut_bits = a.max_t_bits = nullptr;
+    a.lut_depth_max = 0.0;
     const gs_raster_cfg c = {64, 4, 64};
     return hip_check(launch_raster(a, c, (hipStream_t)stream), "gs_raster_work");
+}
+
+gs_status gs_calibrate_t_upper(const float *splats, int64_t n, const uint32_t *sorted_gids,
+                               const uint32_t *ranges, const gs_camera *cam, float lut_depth_max,
+                               uint32_t *t_upper_bits, uint32_t *max_t_bits, void *stream) {
+    gs_status st;
+    if ((st = check_camera(cam)) != GS_OK) return st;
+    if (n < 0) return fail(GS_ERR_INVALID_ARGUMENT, "n < 0");
+    if (!ranges || !t_upper_bits) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (n > 0 && (!splats || !sorted_gids)) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (!(lut_depth_max > 0.0f) || !finite_f(lut_depth_max))
+        return fail(GS_ERR_INVALID_ARGUMENT, "lut_depth_max must be finite and > 0");
+    RasterArgs a;
+    a.splats = splats;
+    a.gids = sorted_gids;
+    a.ranges = ranges;
+    a.width = cam->width;
+    a.height = cam->height;
+    a.tiles_x = tiles_x(cam);
+    a.tiles_y = tiles_y(cam);
+    for (int i = 0; i < 3; ++i) a.bg[i] = 0.0f;
+    a.image = a.final_T = nullptr;
+    a.n_contrib = nullptr;
+    a.n_evaluated = nullptr;
+    a.work = nullptr;
+    a.lut_bits = t_upper_bits;
+    a.max_t_bits = max_t_bits;
+    a.lut_depth_max = (double)lut_depth_max;
+    const gs_raster_cfg c = {64, 4, 64};
+    return hip_check(launch_raster(a, c, (hipStream_t)stream), "gs_calibrate_t_upper");
 }
 
 gs_status gs_rasterize_backward(const float *splats, int64_t n, const uint32_t *sorted_gids,

@@ -172,6 +172,13 @@ struct RasterArgs {
     uint32_t *n_contrib;
     uint32_t *n_evaluated;  // nullable
     unsigned long long *work;  // nullable; set: count work instead of writing pixels
+    // T_upper calibration (set lut_bits: no pixels written): per depth bin
+    // (kLutBins over [0, lut_depth_max)) and optionally per Gaussian, the
+    // largest transmittance in front of a Gaussian where it blends, as float
+    // bits raised with atomicMax
+    uint32_t *lut_bits;
+    uint32_t *max_t_bits;
+    double lut_depth_max;
 };
 hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStream_t s);
 

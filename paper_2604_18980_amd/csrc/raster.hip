@@ -107,16 +107,29 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
 // MODE 0: the renderer.  MODE 1: also count, per pixel, the list entries
 // evaluated (n_evaluated output).  MODE 2: write no pixels; add this tile's
 // work to a.work[0..3]: list entries evaluated (the n_evaluated sum), strip
 // evaluations executed (one per wave instruction sequence over a 16x4 strip),
 // pixel evaluations that blended a Gaussian, and list entries loaded.
+// MODE 3: write no pixels; T_upper calibration -- for each Gaussian the wave
+// blends, the largest transmittance in front of it over the tile's pixels,
+// raised into its depth bin (per-wave maxima in LDS, flushed at the end of
+// the tile) and, if requested, into the Gaussian's own entry.
 template <int MODE>
 __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
-    constexpr bool EV = MODE != 0;
+    constexpr bool EV = MODE == 1 || MODE == 2;
     __shared__ float4 s0[4][64], s1[4][64];
     __shared__ float2 s2[4][64];
+    __shared__ uint32_t s_cal[MODE == 3 ? 4 : 1][64];   // MODE 3: depth bin of each slot
+    __shared__ uint32_t s_cgid[MODE == 3 ? 4 : 1][64];  // MODE 3: Gaussian id of each slot
+    __shared__ uint32_t s_lut[MODE == 3 ? 4 : 1][kLutBins];
     const int wid = threadIdx.x / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
@@ -144,6 +157,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
     }
     const float4 *spl = reinterpret_cast<const float4 *>(a.splats);
     uint32_t w_strips = 0, w_blended = 0, w_loaded = 0;  // MODE 2 only
+    if (MODE == 3 && lane < kLutBins) s_lut[wid][lane] = 0u;
 
     for (uint32_t base = start; base < end; base += kWave) {
         uint32_t alive = 0;
@@ -165,6 +179,12 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
             G2 = gam * kNegHalfLog2e;
             elim = alpha_tau_elim(sig);
             hit = strip_hits(mx, my, A, beta, gam, elim, x_lo, x_hi, (float)(ty * kTile));
+            if (MODE == 3) {
+                // the record's float32 depth, binned in double as the oracle does
+                const double f = ((double)g1.z * kLutBins) / a.lut_depth_max;
+                s_cal[wid][lane] = f >= (double)(kLutBins - 1) ? (uint32_t)(kLutBins - 1) : (uint32_t)floor(f);
+                s_cgid[wid][lane] = (uint32_t)gid;
+            }
         }
         uint64_t m[4], any = 0;
 #pragma unroll
@@ -180,6 +200,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
             const float sG2 = r1.x, ssig = r1.y, selim = r1.z, sr = r1.w, sg = r2.x, sb = r2.y;
             const float dx = smx - fpx;
             const uint32_t pos = (base - start) + (uint32_t)cur + 1u;
+            float tmax = 0.0f;  // MODE 3: largest T in front of it where it blends
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (!((m[k] >> cur) & 1ull)) continue;  // uniform: strip k missed
@@ -197,6 +218,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
                     const float alpha = fminf(kAlphaMaxF, ssig * __builtin_amdgcn_exp2f(e2));
                     const float wa = alpha * T[k];
                     const float Tn = T[k] - wa;     // T (1 - alpha)
+                    if (MODE == 3 && !(Tn < kStopF)) tmax = fmaxf(tmax, T[k]);
                     float w = wa, Tk = Tn;
                     uint32_t lk = pos;
                     if (__ballot(Tn < kStopF) != 0ull) {
@@ -215,6 +237,14 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
                     T[k] = Tk;
                     last[k] = lk;
                     if (MODE == 2) ++w_blended;
+                }
+            }
+            if (MODE == 3) {
+                const float t = wave_max(tmax);
+                if (lane == 0 && t > 0.0f) {
+                    const uint32_t bits = __float_as_uint(t), bin = s_cal[wid][cur];
+                    if (bits > s_lut[wid][bin]) s_lut[wid][bin] = bits;
+                    if (a.max_t_bits) atomicMax(a.max_t_bits + s_cgid[wid][cur], bits);
                 }
             }
         };
@@ -242,6 +272,10 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
                 if (!ha) break;
             }
         }
+    }
+    if (MODE == 3) {
+        if (lane < kLutBins && s_lut[wid][lane] != 0u) atomicMax(a.lut_bits + lane, s_lut[wid][lane]);
+        return;
     }
     if (MODE == 2) {
         unsigned long long e = 0;
@@ -287,7 +321,9 @@ __global__ __launch_bounds__(256) void k_raster_wave(const RasterArgs a) {
 
 hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStream_t s) {
     const unsigned tiles = (unsigned)a.tiles_x * (unsigned)a.tiles_y;
-    if (a.work) {
+    if (a.lut_bits) {
+        k_raster_wave<3><<<(tiles + 3) / 4, 256, 0, s>>>(a);
+    } else if (a.work) {
         k_raster_wave<2><<<(tiles + 3) / 4, 256, 0, s>>>(a);
     } else if (cfg.threads_per_tile == 256) {
         switch (cfg.lds_batch) {
@@ -328,6 +364,8 @@ __device__ __forceinline__ RasterArgs view_args(const ViewsArgs &q, int view) {
     a.n_contrib = v.n_contrib;
     a.n_evaluated = nullptr;
     a.work = nullptr;
+    a.lut_bits = a.max_t_bits = nullptr;
+    a.lut_depth_max = 0.0;
     return a;
 }
 

@@ -20,7 +20,7 @@ LUT_BINS = 20
 TILE = 16
 
 EXPORTS = ("gs_workspace_size", "gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_bin_pairs",
-           "gs_rasterize", "gs_raster_work",
+           "gs_rasterize", "gs_raster_work", "gs_calibrate_t_upper",
            "gs_rasterize_backward", "gs_preprocess_backward", "gs_views_workspace_size",
            "gs_rasterize_views", "gs_wall_clock_khz", "gs_status_string", "gs_last_error",
            "gs_version")
@@ -78,10 +78,11 @@ def load():
     L.gs_bin_pairs.argtypes = [P, P, P, I64, P, P, P, P, I64, P, P, C.c_size_t, P]
     L.gs_rasterize.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P]
     L.gs_raster_work.argtypes = [P, I64, P, P, P, P, P]
+    L.gs_calibrate_t_upper.argtypes = [P, I64, P, P, P, C.c_float, P, P, P]
     L.gs_rasterize_backward.argtypes = [P, I64, P, P, P, P, P, P, P, P, P]
     L.gs_preprocess_backward.argtypes = [P, P, P, P, P, P]
     for f in ("gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_bin_pairs", "gs_rasterize",
-              "gs_raster_work",
+              "gs_raster_work", "gs_calibrate_t_upper",
               "gs_rasterize_backward", "gs_preprocess_backward"):
         getattr(L, f).restype = C.c_int
     L.gs_status_string.argtypes = [I]
@@ -198,6 +199,13 @@ def gs_rasterize(splats, n, sorted_gids, ranges, cam: GsCamera, bg, cfg, image, 
 def gs_raster_work(splats, n, sorted_gids, ranges, cam: GsCamera, work, stream=None):
     _check(load().gs_raster_work(_ptr(splats), int(n), _ptr(sorted_gids), _ptr(ranges),
                                  C.byref(cam), _ptr(work), _stream(stream)))
+
+
+def gs_calibrate_t_upper(splats, n, sorted_gids, ranges, cam: GsCamera, lut_depth_max, t_upper_bits,
+                         max_t_bits=None, stream=None):
+    _check(load().gs_calibrate_t_upper(_ptr(splats), int(n), _ptr(sorted_gids), _ptr(ranges),
+                                       C.byref(cam), float(lut_depth_max), _ptr(t_upper_bits),
+                                       _ptr(max_t_bits), _stream(stream)))
 
 
 def gs_rasterize_backward(splats, n, sorted_gids, ranges, cam: GsCamera, bg, final_T, n_contrib,

@@ -295,6 +295,20 @@ def city_scene(n=6_000_000, seed=0, sh_degree=3, n_buildings=3000, width=4608, h
     return Scene(means, ls, q, op, sh, sh_degree), cam
 
 
+def city_calibration_cameras(n_views=16, seed=99, width=4608, height=3456):
+    """Calibration viewpoints for the city scene (the paper's 16 sampled
+    training views, Sec. 3.4): aerial cameras around the measured one --
+    eye (U(-150, 150), -600 + U(-150, 150), 150 + U(-30, 30)) m, yaw
+    pi/2 + U(-0.3, 0.3), pitch 30 + U(-5, 5) deg -- none equal to it."""
+    rng = np.random.Generator(np.random.PCG64(seed))  # 16 x 5 draws: sequential is fine
+    cams = []
+    for _ in range(n_views):
+        eye = (rng.uniform(-150, 150), -600.0 + rng.uniform(-150, 150), 150.0 + rng.uniform(-30, 30))
+        yaw = math.pi / 2 + rng.uniform(-0.3, 0.3)
+        cams.append(_aerial_camera(eye, yaw, width, height, pitch_deg=30.0 + rng.uniform(-5, 5)))
+    return cams
+
+
 def diff_workload(n=1_000_000, seed=0, target_seed=7):
     """Differentiable-render workload: the mid-scene generator at N=1M viewed at
     1280x720, with a seeded random target image U[0,1)^(3xHxW)."""
