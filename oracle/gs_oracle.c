@@ -164,6 +164,90 @@ int orc_adagscale(double det, double sigma, double depth, double K, const float 
 static int is_finite(double x) { return x == x && fabs(x) <= 1.79769313486231570815e308; }
 
 /* ------------------------------------------------------------------------ */
+/* Ellipse tile test (extent rule 1): the ellipse boundary of the prior work */
+/* the paper builds on (Sec. 2.3, Fig. 3(c); Sec. 4.1), with the alpha       */
+/* threshold t = Th of Sec. 3.3 under AdaGScale and t = tau otherwise.       */
+/*                                                                           */
+/* Pixel (px, py) can reach alpha >= t only inside the ellipse               */
+/*     q(X, Y) = A (X + beta Y)^2 + gamma Y^2 <= c,  c = 2 ln(sigma / t),     */
+/* with (X, Y) = (px - u, py - v).  A tile (tx, ty) is kept when its pixel   */
+/* box [16 tx, 16 tx + 15] x [16 ty, 16 ty + 15] meets the ellipse.  For the  */
+/* row band Y in [Y0, Y1] the ellipse's slice at Y spans                      */
+/*     X in [-beta Y - S(Y), -beta Y + S(Y)],  S(Y) = sqrt((c - gamma Y^2)/A), */
+/* for |Y| <= R = sqrt(c / gamma).  The left end is convex in Y and the right */
+/* end concave, so over the band they reach their extremes at the clamp of    */
+/* the unconstrained extremes Y = w (leftmost point of the ellipse) and       */
+/* Y = -w (rightmost), w = beta sqrt(A c / (gamma (gamma + A beta^2))).       */
+/* The band's pixel x-range [xl, xr] then meets tile column tx exactly when   */
+/* ceil((xl - 15) / 16) <= tx <= floor(xr / 16).                             */
+/*                                                                           */
+/* Every value is the float32 record value widened to double (the renderer   */
+/* evaluates the same record), so emission can recompute the spans.  The     */
+/* test runs inside the plain tile rectangle and only removes tiles from it. */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double u, v, A, beta, gamma, c, R, w;
+    int ok;
+} ellipse_t;
+
+static double f32r(double x) { return (double)(float)x; }
+
+/* ok = 0 (no tiles) unless every value is finite, A, gamma > 0 and c > 0. */
+static void ellipse_setup(double u, double v, double A, double beta, double gamma, double sigma,
+                          double t, ellipse_t *e) {
+    e->ok = 0;
+    if (!(is_finite(u) && is_finite(v) && is_finite(A) && is_finite(beta) && is_finite(gamma)))
+        return;
+    if (!(A > 0.0 && gamma > 0.0)) return;
+    double c = 2.0 * log(sigma / t);
+    if (!(c > 0.0 && is_finite(c))) return;
+    double R = sqrt(c / gamma);
+    double w = beta * sqrt((A * c) / (gamma * (gamma + A * (beta * beta))));
+    if (!(is_finite(R) && is_finite(w))) return;
+    e->u = u; e->v = v; e->A = A; e->beta = beta; e->gamma = gamma; e->c = c; e->R = R; e->w = w;
+    e->ok = 1;
+}
+
+static double ellipse_half_width(const ellipse_t *e, double Y) {
+    double r = e->c - e->gamma * (Y * Y);
+    if (!(r > 0.0)) r = 0.0;
+    return sqrt(r / e->A);
+}
+
+/* Tile columns [*a, *b] of row ty that meet the ellipse, clipped to
+ * [cx0, cx1]; empty when *b < *a.  A NaN bound clips to the column range. */
+static void ellipse_row_span(const ellipse_t *e, int ty, int cx0, int cx1, int *a, int *b) {
+    double y0 = (double)(TILE * ty) - e->v, y1 = y0 + (double)(TILE - 1);
+    *a = 1; *b = 0;
+    if (y1 < -e->R || y0 > e->R) return;
+    double lo = y0 < -e->R ? -e->R : y0, hi = y1 > e->R ? e->R : y1;
+    double wl = e->w < lo ? lo : (e->w > hi ? hi : e->w);
+    double wr = -e->w < lo ? lo : (-e->w > hi ? hi : -e->w);
+    double xl = (e->u - e->beta * wl) - ellipse_half_width(e, wl);
+    double xr = (e->u - e->beta * wr) + ellipse_half_width(e, wr);
+    double fa = ceil((xl - (double)(TILE - 1)) / (double)TILE);
+    double fb = floor(xr / (double)TILE);
+    fa = fa >= (double)cx0 ? fa : (double)cx0;
+    fb = fb <= (double)cx1 ? fb : (double)cx1;
+    if (fa > (double)cx1 || fb < (double)cx0 || fb < fa) return;
+    *a = (int)fa; *b = (int)fb;
+}
+
+/* Python-facing form of the row test for the pins: spans[2 * (ty - ty0)]. */
+int orc_ellipse_spans(double u, double v, double A, double beta, double gamma, double sigma,
+                      double t, int ty0, int ty1, int cx0, int cx1, int32_t *spans) {
+    ellipse_t e;
+    ellipse_setup(u, v, A, beta, gamma, sigma, t, &e);
+    for (int ty = ty0; ty < ty1; ++ty) {
+        int a = 1, b = 0;
+        if (e.ok) ellipse_row_span(&e, ty, cx0, cx1, &a, &b);
+        spans[2 * (ty - ty0)] = a;
+        spans[2 * (ty - ty0) + 1] = b;
+    }
+    return e.ok;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Preprocess (Sec. 2.1; AdaGScale additions Sec. 3.3).                      */
 /*                                                                           */
 /* Inputs are float32 structure-of-arrays, [C][N]; cam[0..11] is the          */
@@ -175,12 +259,16 @@ static int is_finite(double x) { return x == x && fabs(x) <= 1.79769313486231570
 /* (dilated a, b, c), extent (plain v), th, scale, rect[4] (x0, y0, x1, y1    */
 /* half-open, tiles), tiles_touched, radius (int).                           */
 /* flags: 0 culled, 1 projected (finite, in front), 2 projected with tiles.   */
+/* extent_rule 0: the rectangle of radius ceil(v s) (s = 1 when plain) and   */
+/* tiles_touched = its area.  extent_rule 1: the tiles of the plain radius-  */
+/* ceil(v) rectangle that meet the alpha >= th ellipse, tiles_touched = their */
+/* count and rect = their bounding box.                                       */
 /* ------------------------------------------------------------------------ */
 void orc_preprocess(int64_t n, const float *means, const float *log_scales, const float *quats,
                     const float *opacity_logits, const float *sh, int sh_degree,
                     const float *cam, int width, int height,
                     int adagscale, double K, const float *t_upper, double lut_depth_max,
-                    int force_unit_scale,
+                    int force_unit_scale, int extent_rule,
                     double *mean2d, double *conic, double *quad, double *opacity, double *rgb,
                     double *depth,
                     double *cov2d, double *extent, double *th, double *scale,
@@ -301,7 +389,7 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
             th[g] = thv;
             scale[g] = sv;
             if (!keep) continue;
-            ext = ext * sv;
+            if (extent_rule == 0) ext = ext * sv;  /* rule 1 tests the alpha = Th ellipse below */
         }
         double rd = ceil(ext);
         if (rd > 1073741824.0) rd = 1073741824.0; /* 2^30 px: covers any image */
@@ -319,6 +407,28 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
         int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
         int64_t tiles = (int64_t)(x1 - x0) * (int64_t)(y1 - y0);
         if (tiles <= 0) continue;
+        if (extent_rule == 1) {
+            /* the tiles of the plain rectangle that meet the alpha >= th ellipse;
+               the rectangle shrinks to their bounding box */
+            ellipse_t e;
+            ellipse_setup(f32r(u), f32r(v), f32r(c / det), f32r(-b * ic), f32r(ic), f32r(sigma),
+                          f32r(th[g]), &e);
+            if (!e.ok) continue;
+            int nx0 = x1, nx1 = x0, ny0 = -1, ny1 = -1;
+            tiles = 0;
+            for (int ty = y0; ty < y1; ++ty) {
+                int sa, sb;
+                ellipse_row_span(&e, ty, x0, x1 - 1, &sa, &sb);
+                if (sb < sa) continue;
+                tiles += sb - sa + 1;
+                if (sa < nx0) nx0 = sa;
+                if (sb + 1 > nx1) nx1 = sb + 1;
+                if (ny0 < 0) ny0 = ty;
+                ny1 = ty + 1;
+            }
+            if (tiles == 0) continue;
+            x0 = nx0; x1 = nx1; y0 = ny0; y1 = ny1;
+        }
         rect[4 * g] = x0; rect[4 * g + 1] = y0; rect[4 * g + 2] = x1; rect[4 * g + 3] = y1;
         tiles_touched[g] = tiles;
         flags[g] = 2;
@@ -342,23 +452,36 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
 /* ------------------------------------------------------------------------ */
 /* Pair emission (Sec. 2.1): Gaussians in index order, tile rows outer,       */
 /* columns inner.  key = tile << 32 | bits(float32 depth), value = index.    */
+/* Rule 0 emits the whole rectangle; rule 1 each row's ellipse span, from    */
+/* the same record values the preprocess tested.                             */
 /* ------------------------------------------------------------------------ */
 int64_t orc_emit(int64_t n, const int32_t *rect, const int64_t *tiles_touched, const float *depth_f32,
-                 int width, uint64_t *keys, uint32_t *vals) {
+                 int width, int extent_rule, const double *mean2d, const double *quad,
+                 const double *opacity, const double *th, uint64_t *keys, uint32_t *vals) {
     int TX = (width + TILE - 1) / TILE;
     int64_t p = 0;
     for (int64_t g = 0; g < n; ++g) {
         if (tiles_touched[g] <= 0) continue;
         uint32_t dbits;
         memcpy(&dbits, &depth_f32[g], 4);
-        for (int ty = rect[4 * g + 1]; ty < rect[4 * g + 3]; ++ty)
-            for (int tx = rect[4 * g]; tx < rect[4 * g + 2]; ++tx) {
+        ellipse_t e;
+        if (extent_rule == 1) {
+            ellipse_setup(f32r(mean2d[2 * g]), f32r(mean2d[2 * g + 1]), f32r(quad[3 * g]),
+                          f32r(quad[3 * g + 1]), f32r(quad[3 * g + 2]), f32r(opacity[g]),
+                          f32r(th[g]), &e);
+            if (!e.ok) continue;
+        }
+        for (int ty = rect[4 * g + 1]; ty < rect[4 * g + 3]; ++ty) {
+            int a = rect[4 * g], b = rect[4 * g + 2] - 1;
+            if (extent_rule == 1) ellipse_row_span(&e, ty, a, b, &a, &b);
+            for (int tx = a; tx <= b; ++tx) {
                 if (keys) {
                     keys[p] = ((uint64_t)(uint32_t)(ty * TX + tx) << 32) | dbits;
                     vals[p] = (uint32_t)g;
                 }
                 ++p;
             }
+        }
     }
     return p;
 }

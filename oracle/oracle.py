@@ -56,8 +56,11 @@ def lib():
                                     C.c_int, P, P]
         L.orc_adagscale.restype = C.c_int
         L.orc_preprocess.argtypes = ([C.c_int64, P, P, P, P, P, C.c_int, P, C.c_int, C.c_int,
-                                      C.c_int, C.c_double, P, C.c_double, C.c_int] + [P] * 14)
-        L.orc_emit.argtypes = [C.c_int64, P, P, P, C.c_int, P, P]
+                                      C.c_int, C.c_double, P, C.c_double, C.c_int, C.c_int]
+                                     + [P] * 14)
+        L.orc_emit.argtypes = [C.c_int64, P, P, P, C.c_int, C.c_int, P, P, P, P, P, P]
+        L.orc_ellipse_spans.argtypes = [C.c_double] * 7 + [C.c_int] * 4 + [P]
+        L.orc_ellipse_spans.restype = C.c_int
         L.orc_emit.restype = C.c_int64
         L.orc_sort.argtypes = [C.c_int64, P, P]
         L.orc_ranges.argtypes = [C.c_int64, P, C.c_int, P]
@@ -101,6 +104,7 @@ class Mode:
     t_upper: np.ndarray = None
     lut_depth_max: float = 100.0
     force_unit_scale: bool = False
+    extent_rule: int = 0   # 0: tile rectangle; 1: tiles meeting the alpha >= Th ellipse
 
     def lut(self):
         return _f32(self.t_upper if self.t_upper is not None else default_lut())
@@ -122,6 +126,7 @@ class Preproc:
     tiles_touched: np.ndarray
     radius: np.ndarray
     flags: np.ndarray
+    extent_rule: int = 0
 
     def record(self, round_to_f32: bool = True) -> np.ndarray:
         """Per-Gaussian record used by the blend: mean x, mean y, A, beta, gamma
@@ -146,7 +151,8 @@ def preprocess(scene, cam, mode: Mode = Mode()) -> Preproc:
                   rgb=np.zeros((n, 3)), depth=np.zeros(n), cov2d=np.zeros((n, 3)),
                   extent=np.zeros(n), th=np.zeros(n), scale=np.zeros(n),
                   rect=np.zeros((n, 4), np.int32), tiles_touched=np.zeros(n, np.int64),
-                  radius=np.zeros(n, np.int32), flags=np.zeros(n, np.int32))
+                  radius=np.zeros(n, np.int32), flags=np.zeros(n, np.int32),
+                  extent_rule=int(mode.extent_rule))
     arrs = [_f32(scene.means), _f32(scene.log_scales), _f32(scene.quats),
             _f32(scene.opacity_logits), _f32(scene.sh)]
     ca = cam_array(cam)
@@ -154,7 +160,7 @@ def preprocess(scene, cam, mode: Mode = Mode()) -> Preproc:
     L.orc_preprocess(n, *[_p(a) for a in arrs], scene.sh_degree, _p(ca), cam["width"],
                      cam["height"], int(mode.adagscale), float(np.float32(mode.K)), _p(lut),
                      float(np.float32(mode.lut_depth_max)), int(mode.force_unit_scale),
-                     _p(out.mean2d), _p(out.conic), _p(out.quad), _p(out.opacity), _p(out.rgb),
+                     int(mode.extent_rule), _p(out.mean2d), _p(out.conic), _p(out.quad), _p(out.opacity), _p(out.rgb),
                      _p(out.depth),
                      _p(out.cov2d), _p(out.extent), _p(out.th), _p(out.scale), _p(out.rect),
                      _p(out.tiles_touched), _p(out.radius), _p(out.flags))
@@ -169,11 +175,26 @@ def emit(pre: Preproc, cam):
     L = lib()
     n = pre.rect.shape[0]
     d32 = _f32(pre.depth_f32)
-    np_ = L.orc_emit(n, _p(pre.rect), _p(pre.tiles_touched), _p(d32), cam["width"], None, None)
+    geo = [_p(np.ascontiguousarray(a, np.float64)) for a in (pre.mean2d, pre.quad, pre.opacity, pre.th)]
+    args = (n, _p(pre.rect), _p(pre.tiles_touched), _p(d32), cam["width"], pre.extent_rule, *geo)
+    np_ = L.orc_emit(*args, None, None)
     keys = np.zeros(max(np_, 1), np.uint64)
     vals = np.zeros(max(np_, 1), np.uint32)
-    L.orc_emit(n, _p(pre.rect), _p(pre.tiles_touched), _p(d32), cam["width"], _p(keys), _p(vals))
+    L.orc_emit(*args, _p(keys), _p(vals))
     return keys[:np_], vals[:np_]
+
+
+def ellipse_spans(u, v, A, beta, gamma, sigma, t, ty0, ty1, cx0, cx1):
+    """Rule-1 row test on explicit values: for tile rows ty0 .. ty1-1, the
+    inclusive tile-column span [a, b] (empty when b < a) that meets the ellipse
+    A (X + beta Y)^2 + gamma Y^2 <= 2 ln(sigma / t), clipped to [cx0, cx1].
+    Returns (ok, spans[rows][2]); the values are used as given (no float32
+    rounding)."""
+    spans = np.zeros((max(ty1 - ty0, 0), 2), np.int32)
+    ok = lib().orc_ellipse_spans(float(u), float(v), float(A), float(beta), float(gamma),
+                                 float(sigma), float(t), int(ty0), int(ty1), int(cx0), int(cx1),
+                                 _p(spans))
+    return bool(ok), spans
 
 
 def sort(keys, vals):

@@ -556,3 +556,182 @@ def test_max_transmittance_invariants_tiny(O):
     b = np.minimum(np.floor(f), 19).astype(int)
     ok = mt > 0
     assert np.all(mt[ok] <= lut[b[ok]])
+
+
+# --------------------------------------------------------------------------- ellipse tile test (rule 1)
+def _box_min_q(A, beta, gamma, X0, X1, Y0, Y1):
+    """Minimum of q(X, Y) = A (X + beta Y)^2 + gamma Y^2 over the box
+    [X0, X1] x [Y0, Y1]: 0 if the box holds the centre, else the smallest of
+    the four edge minima (each a 1-D quadratic, minimised in closed form and
+    clamped into the edge)."""
+    q = lambda X, Y: A * (X + beta * Y) ** 2 + gamma * Y * Y
+    if X0 <= 0.0 <= X1 and Y0 <= 0.0 <= Y1:
+        return 0.0
+    best = math.inf
+    for X in (X0, X1):  # vertical edges: dq/dY = 0 at Y = -A beta X / (A beta^2 + gamma)
+        Y = min(max(-A * beta * X / (A * beta * beta + gamma), Y0), Y1)
+        best = min(best, q(X, Y))
+    for Y in (Y0, Y1):  # horizontal edges: minimum at X = -beta Y
+        X = min(max(-beta * Y, X0), X1)
+        best = min(best, q(X, Y))
+    return best
+
+
+def test_ellipse_spans_match_box_minimum(O):
+    """The row spans are exactly the tiles whose pixel box [16 tx, 16 tx + 15]
+    x [16 ty, 16 ty + 15] holds a point with q <= 2 ln(sigma / t) (a convex
+    minimum over the box, computed edge by edge), on random ellipses of every
+    orientation and size; tiles within 1e-9 of tangency are not judged."""
+    rng = np.random.default_rng(21)
+    checked = 0
+    for it in range(300):
+        sx, sy = np.exp(rng.uniform(-0.5, 3.5, 2))
+        th = rng.uniform(0, np.pi)
+        cth, sth = np.cos(th), np.sin(th)
+        a = cth * cth * sx * sx + sth * sth * sy * sy
+        b = cth * sth * (sx * sx - sy * sy)
+        c = sth * sth * sx * sx + cth * cth * sy * sy
+        det = a * c - b * b
+        A, beta, gamma = c / det, -b / c, 1.0 / c
+        u, v = rng.uniform(-40, 200, 2)
+        sigma = rng.uniform(0.01, 1.0)
+        t = rng.choice([1 / 255, rng.uniform(1 / 255, sigma)])
+        cc = 2 * math.log(sigma / t)
+        ok, spans = O.ellipse_spans(u, v, A, beta, gamma, sigma, t, 0, 12, 0, 11)
+        assert ok == (cc > 0)
+        for ty in range(12):
+            for tx in range(12):
+                m = _box_min_q(A, beta, gamma, 16 * tx - u, 16 * tx + 15 - u,
+                               16 * ty - v, 16 * ty + 15 - v)
+                if ok and abs(m - cc) <= 1e-9 * cc:
+                    continue
+                want = ok and m <= cc
+                got = spans[ty, 0] <= tx <= spans[ty, 1]
+                assert got == want, (it, ty, tx, m, cc, spans[ty])
+                checked += 1
+    assert checked > 40000
+
+
+def test_ellipse_spans_axis_aligned_closed_form(O):
+    """beta = 0: the ellipse X^2/rx^2 + Y^2/ry^2 <= 1, rx = sqrt(c/A), ry =
+    sqrt(c/gamma).  A row band meets it over |X| <= rx sqrt(1 - Y*^2/ry^2)
+    with Y* the band's point nearest the centre; the span is the tiles that
+    range touches.  Also: t >= sigma (c <= 0) has no tiles."""
+    A, gamma, sigma, t = 1 / 400.0, 1 / 100.0, 0.8, 1 / 255
+    cc = 2 * math.log(sigma / t)
+    rx, ry = math.sqrt(cc / A), math.sqrt(cc / gamma)
+    u, v = 100.5, 70.25
+    ok, spans = O.ellipse_spans(u, v, A, 0.0, gamma, sigma, t, 0, 10, 0, 14)
+    assert ok
+    for ty in range(10):
+        Y0, Y1 = 16 * ty - v, 16 * ty + 15 - v
+        if Y1 < -ry or Y0 > ry:
+            assert spans[ty, 1] < spans[ty, 0]
+            continue
+        Ys = min(max(0.0, Y0), Y1)
+        hw = rx * math.sqrt(max(0.0, 1 - (Ys / ry) ** 2))
+        lo, hi = u - hw, u + hw
+        want = [tx for tx in range(15) if 16 * tx <= hi and 16 * tx + 15 >= lo]
+        assert list(range(spans[ty, 0], spans[ty, 1] + 1)) == want
+    ok, spans = O.ellipse_spans(u, v, A, 0.0, gamma, 0.5, 0.5, 0, 10, 0, 14)
+    assert not ok and np.all(spans[:, 1] < spans[:, 0])
+
+
+def _pair_sets(keys, vals):
+    return set(zip((keys >> np.uint64(32)).tolist(), vals.tolist()))
+
+
+@pytest.mark.parametrize("adagscale,K", [(False, 0.0), (True, 0.3)])
+def test_rule1_tiles_are_the_ellipse_tiles(O, adagscale, K):
+    """Rule 1 on a tiny scene: each Gaussian's emitted tiles are the tiles of
+    its plain rectangle whose box meets the alpha >= th ellipse (box minimum,
+    from the float32 record values), tiles_touched counts them, rect is their
+    bounding box, and every pixel of the plain rectangle that the blend would
+    give alpha >= th lies in one of them."""
+    sc, _ = scenes.tiny_scene(n=300, seed=5)
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 100, 70)
+    m0 = O.Mode(adagscale=adagscale, K=K)
+    m1 = O.Mode(adagscale=adagscale, K=K, extent_rule=1)
+    p0, p1 = O.preprocess(sc, cam, m0), O.preprocess(sc, cam, m1)
+    k1, v1 = O.emit(p1, cam)
+    TX = (cam["width"] + 15) // 16
+    f32 = lambda x: float(np.float32(x))
+    py, px = np.mgrid[0:70, 0:100]
+    n_dropped = 0
+    for g in np.nonzero(p0.flags >= 1)[0]:
+        mine = k1[v1 == g] >> np.uint64(32)
+        tiles = sorted(int(t) for t in mine)
+        assert len(tiles) == p1.tiles_touched[g]
+        u, v = f32(p1.mean2d[g, 0]), f32(p1.mean2d[g, 1])
+        A, beta, gamma = (f32(x) for x in p1.quad[g])
+        sigma, t = f32(p1.opacity[g]), f32(p1.th[g])
+        cc = 2 * math.log(sigma / t) if sigma > t else -1.0
+        if p1.radius[g] > 0:
+            # the plain rectangle: radius ceil(v), not the scaled one
+            assert p1.radius[g] == math.ceil(p1.extent[g])
+        x0, y0, x1, y1 = O_plain_rect(p1, g, cam)
+        want = []
+        for ty in range(y0, y1):
+            for tx in range(x0, x1):
+                m = _box_min_q(A, beta, gamma, 16 * tx - u, 16 * tx + 15 - u,
+                               16 * ty - v, 16 * ty + 15 - v)
+                if cc > 0 and m <= cc:
+                    want.append(ty * TX + tx)
+        assert tiles == sorted(want)
+        if tiles:
+            tyx = [(t // TX, t % TX) for t in tiles]
+            r = p1.rect[g]
+            assert (r[0], r[1], r[2], r[3]) == (min(x for _, x in tyx), min(y for y, _ in tyx),
+                                                max(x for _, x in tyx) + 1,
+                                                max(y for y, _ in tyx) + 1)
+            # pixels reaching alpha >= t lie in the emitted tiles
+            X, Y = px - u, py - v
+            alpha = sigma * np.exp(-0.5 * (A * (X + beta * Y) ** 2 + gamma * Y * Y))
+            inrect = (px // 16 >= x0) & (px // 16 < x1) & (py // 16 >= y0) & (py // 16 < y1)
+            hit = (alpha >= t * (1 + 1e-9)) & inrect
+            assert set(((py[hit] // 16) * TX + px[hit] // 16).tolist()) <= set(tiles)
+        n_dropped += (x1 - x0) * (y1 - y0) - len(tiles)
+    assert n_dropped > 0
+
+
+def O_plain_rect(pre, g, cam):
+    """The plain rectangle of radius pre.radius[g] around the double mean, in
+    tiles (the rule both extent rules start from)."""
+    TX, TY = (cam["width"] + 15) // 16, (cam["height"] + 15) // 16
+    u, v = pre.mean2d[g]
+    r = int(pre.radius[g])
+    if r <= 0:
+        return 0, 0, 0, 0
+    cl = lambda x, hi: int(min(max(x, 0), hi))
+    return (cl(math.floor((u - r) / 16), TX), cl(math.floor((v - r) / 16), TY),
+            cl(math.floor((u + r + 15) / 16), TX), cl(math.floor((v + r + 15) / 16), TY))
+
+
+def test_rule1_plain_renders_the_same_image(O):
+    """Plain 3D-GS with the ellipse test drops only pairs whose every pixel has
+    alpha < tau, which the blend skips without effect: image, final T and the
+    per-pixel blended count equal the rectangle rule's, with fewer pairs."""
+    sc, _ = scenes.tiny_scene(n=400, seed=12)
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 96, 64)
+    f0 = O.render(sc, cam, O.Mode(), bg=(0.2, 0.1, 0.0))
+    f1 = O.render(sc, cam, O.Mode(extent_rule=1), bg=(0.2, 0.1, 0.0))
+    assert f1.keys.size < 0.9 * f0.keys.size
+    assert _pair_sets(f1.keys, f1.vals) <= _pair_sets(f0.keys, f0.vals)
+    np.testing.assert_array_equal(f1.image, f0.image)
+    np.testing.assert_array_equal(f1.final_T, f0.final_T)
+    ev1, bl1, _ = O.blend_counts(f1, cam)
+    ev0, bl0, _ = O.blend_counts(f0, cam)
+    np.testing.assert_array_equal(bl1, bl0)
+    assert ev1.sum() < ev0.sum()
+
+
+def test_rule1_adagscale_pairs_within_plain(O):
+    """Th >= tau shrinks the ellipse: AdaGScale's rule-1 pairs are a subset of
+    plain rule-1 pairs, and K = 0 (Th = tau) gives the same pairs."""
+    sc, cam = scenes.tiny_scene(n=1000, seed=8)
+    kp, vp = O.emit(O.preprocess(sc, cam, O.Mode(extent_rule=1)), cam)
+    ka, va = O.emit(O.preprocess(sc, cam, O.Mode(adagscale=True, K=0.5, extent_rule=1)), cam)
+    k0, v0 = O.emit(O.preprocess(sc, cam, O.Mode(adagscale=True, K=0.0, extent_rule=1)), cam)
+    assert ka.size < kp.size
+    assert _pair_sets(ka, va) <= _pair_sets(kp, vp)
+    assert _pair_sets(k0, v0) == _pair_sets(kp, vp)
