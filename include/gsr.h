@@ -100,13 +100,22 @@ typedef struct {
  *   bin).  A Gaussian with Th >= opacity, or whose bin holds T_up <= 0, gets no
  *   pairs; otherwise its extent is scaled by s = sqrt(ln(opacity/Th) /
  *   ln(opacity/tau)), the factor that maps the alpha = tau contour onto the
- *   alpha = Th contour.  force_unit_scale = 1 keeps s = 1 (testing aid). */
+ *   alpha = Th contour.  force_unit_scale = 1 keeps s = 1 (testing aid).
+ * extent_rule = 0: the tile rectangle of that (scaled) extent.
+ * extent_rule = 1: the ellipse test of the prior work the paper builds on
+ *   (Sec. 2.3 Fig. 3(c), Sec. 4.1): of the plain (unscaled) rectangle, only the
+ *   tiles whose pixel box [16 tx, 16 tx + 15] x [16 ty, 16 ty + 15] meets the
+ *   ellipse alpha >= t, t = Th under AdaGScale and tau otherwise, evaluated in
+ *   double from the float32 splat record; rects then holds their bounding
+ *   box and tiles_touched their count.  The same rule must be passed to
+ *   gs_emit_pairs / gs_bin_pairs. */
 typedef struct {
     int adagscale;
     float K;                       /* peripheral-loss budget, >= 0 (eq. 5) */
     float t_upper[GS_LUT_BINS];    /* T_up per depth bin, in [0, 1]; all 1 = uncalibrated */
     float lut_depth_max;           /* > 0; the paper's range is 100 */
     int force_unit_scale;
+    int extent_rule;               /* 0 rectangle, 1 ellipse; other values are rejected */
 } gs_mode;
 
 /* Raster launch geometry.  Tiles stay 16x16 so pair sets are comparable.
@@ -147,19 +156,22 @@ gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_mo
 
 /* Stage 2 (Sec. 2.1 Gaussian-tile pair generation; Sec. 3.3: the rectangle
  * already reflects AdaGScale's extent).  Emits one (tile, Gaussian) pair per
- * tile of each rectangle.  Pairs are emitted Gaussian by Gaussian in
- * ascending (float32 depth, Gaussian id) order, tile rows outer, columns
- * inner; a stable sort by tile of this list is therefore the paper's per-tile
- * depth order.
+ * tile of each rectangle (extent_rule 0), or per tile of each rectangle row's
+ * ellipse span (extent_rule 1, recomputed from the splat records exactly as
+ * gs_preprocess counted it; pass the rule gs_preprocess ran with).  Pairs
+ * are emitted Gaussian by Gaussian in ascending (float32 depth, Gaussian id)
+ * order, tile rows outer, columns inner; a stable sort by tile of this list is
+ * therefore the paper's per-tile depth order.  extent_rule other than 0 or 1
+ * is rejected (GS_ERR_INVALID_ARGUMENT).
  * num_pairs (device int64) receives the number of pairs REQUIRED; at most
  * pair_capacity pairs are written.  When *num_pairs > pair_capacity the
  * caller must grow the buffers and run the frame again (stages 3-4 then see a
  * truncated list and their output is meaningless).
  * ws: workspace of at least gs_workspace_size(n, pair_capacity, W, H) bytes. */
 gs_status gs_emit_pairs(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
-                        int64_t n, const gs_camera *cam, uint32_t *pair_tiles, uint32_t *pair_gids,
-                        int64_t pair_capacity, int64_t *num_pairs, void *ws, size_t ws_bytes,
-                        void *stream);
+                        int64_t n, const gs_camera *cam, int extent_rule, uint32_t *pair_tiles,
+                        uint32_t *pair_gids, int64_t pair_capacity, int64_t *num_pairs, void *ws,
+                        size_t ws_bytes, void *stream);
 
 /* Stage 3 (Sec. 2.1 sorting).  Stable LSD radix sort (8-bit digits, LDS
  * histograms) of the pairs by tile id, so each tile's run keeps the depth
@@ -175,12 +187,14 @@ gs_status gs_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids, const i
 
 /* Stages 2 and 3 fused (Sec. 2.1 pair generation, sorting and tile ranges;
  * Sec. 3.3: the rectangles already carry AdaGScale's extent).  Produces the
- * same per-tile lists as gs_emit_pairs followed by gs_sort -- every tile's
- * Gaussians in ascending (float32 depth, Gaussian id) order -- without writing
- * the emission-order pair arrays: the pairs are generated on the fly from the
- * depth-ordered rectangles and sorted by tile with two 8-bit passes of one
- * 32-bit word per pair (one pass when the image has at most 256 tiles; with
- * more than 65536 tiles or n >= 2^24 it emits and sorts pairs internally).
+ * same per-tile lists as gs_emit_pairs followed by gs_sort with the same
+ * extent_rule -- every tile's Gaussians in ascending (float32 depth, Gaussian
+ * id) order -- without writing the emission-order pair arrays.  Under rule 0
+ * the pairs are generated on the fly from the depth-ordered rectangles and
+ * sorted by tile with two 8-bit passes of one 32-bit word per pair (one pass
+ * when the image has at most 256 tiles; with more than 65536 tiles or
+ * n >= 2^24 it emits and sorts pairs internally); under rule 1 the pairs are
+ * emitted into the workspace and sorted by tile.
  * The ranges come from per-tile counts of the rectangles.
  * Out: sorted_gids [pair_capacity]; sorted_tiles [pair_capacity] or NULL when
  * not wanted; ranges [num_tiles][2] as (start, end), (0, 0) for a tile with no
@@ -191,7 +205,7 @@ gs_status gs_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids, const i
  * ws: workspace of at least gs_workspace_size(n, pair_capacity, W, H) bytes for
  * this camera's W x H. */
 gs_status gs_bin_pairs(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
-                       int64_t n, const gs_camera *cam, uint32_t *sorted_gids,
+                       int64_t n, const gs_camera *cam, int extent_rule, uint32_t *sorted_gids,
                        uint32_t *sorted_tiles, uint32_t *ranges, int64_t pair_capacity,
                        int64_t *num_pairs, void *ws, size_t ws_bytes, void *stream);
 

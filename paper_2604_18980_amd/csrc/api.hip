@@ -222,6 +222,8 @@ gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_mo
             if (!(mode->t_upper[i] >= 0.0f && mode->t_upper[i] <= 1.0f))
                 return fail(GS_ERR_INVALID_ARGUMENT, "mode.t_upper[%d] outside [0, 1]", i);
     }
+    if (mode->extent_rule != 0 && mode->extent_rule != 1)
+        return fail(GS_ERR_INVALID_ARGUMENT, "mode.extent_rule must be 0 or 1");
     if (scene->n > 0 && (!splats || !rects || !tiles_touched))
         return fail(GS_ERR_INVALID_ARGUMENT, "output array is NULL");
     PreprocessArgs a;
@@ -246,6 +248,7 @@ gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_mo
     a.tiles_y = tiles_y(cam);
     a.adagscale = mode->adagscale;
     a.force_unit_scale = mode->force_unit_scale ? 1 : 0;
+    a.extent_rule = mode->extent_rule;
     a.K = mode->K;
     a.lut_depth_max = mode->lut_depth_max;
     for (int i = 0; i < GS_LUT_BINS; ++i) a.lut[i] = mode->t_upper[i];
@@ -258,11 +261,13 @@ gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_mo
 }
 
 gs_status gs_emit_pairs(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
-                        int64_t n, const gs_camera *cam, uint32_t *pair_tiles, uint32_t *pair_gids,
-                        int64_t pair_capacity, int64_t *num_pairs, void *ws, size_t ws_bytes,
-                        void *stream) {
+                        int64_t n, const gs_camera *cam, int extent_rule, uint32_t *pair_tiles,
+                        uint32_t *pair_gids, int64_t pair_capacity, int64_t *num_pairs, void *ws,
+                        size_t ws_bytes, void *stream) {
     gs_status st;
     if ((st = check_camera(cam)) != GS_OK) return st;
+    if (extent_rule != 0 && extent_rule != 1)
+        return fail(GS_ERR_INVALID_ARGUMENT, "extent_rule must be 0 or 1");
     if (n < 0 || n >= ((int64_t)1 << 31))
         return fail(GS_ERR_INVALID_ARGUMENT, "n = %lld outside [0, 2^31)", (long long)n);
     if (pair_capacity < 0 || pair_capacity > (int64_t)0xffffffffLL)
@@ -276,17 +281,20 @@ gs_status gs_emit_pairs(const float *splats, const uint64_t *rects, const uint32
     workspace_layout(n, pair_capacity, ws, &w);
     if (!ws || ws_bytes < w.bytes)
         return fail(GS_ERR_CAPACITY, "workspace of %zu bytes, %zu needed", ws_bytes, w.bytes);
-    return hip_check(launch_emit(splats, rects, tiles_touched, (int)n, tiles_x(cam), pair_tiles,
-                                 pair_gids, pair_capacity, num_pairs, w, (hipStream_t)stream),
+    return hip_check(launch_emit(splats, rects, tiles_touched, (int)n, tiles_x(cam), extent_rule,
+                                 pair_tiles, pair_gids, pair_capacity, num_pairs, w,
+                                 (hipStream_t)stream),
                      "gs_emit_pairs");
 }
 
 gs_status gs_bin_pairs(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
-                       int64_t n, const gs_camera *cam, uint32_t *sorted_gids,
+                       int64_t n, const gs_camera *cam, int extent_rule, uint32_t *sorted_gids,
                        uint32_t *sorted_tiles, uint32_t *ranges, int64_t pair_capacity,
                        int64_t *num_pairs, void *ws, size_t ws_bytes, void *stream) {
     gs_status st;
     if ((st = check_camera(cam)) != GS_OK) return st;
+    if (extent_rule != 0 && extent_rule != 1)
+        return fail(GS_ERR_INVALID_ARGUMENT, "extent_rule must be 0 or 1");
     if (n < 0 || n >= ((int64_t)1 << 31))
         return fail(GS_ERR_INVALID_ARGUMENT, "n = %lld outside [0, 2^31)", (long long)n);
     if (pair_capacity < 0 || pair_capacity > (int64_t)0xffffffffLL)
@@ -301,8 +309,8 @@ gs_status gs_bin_pairs(const float *splats, const uint64_t *rects, const uint32_
     if (!ws || ws_bytes < w.bytes)
         return fail(GS_ERR_CAPACITY, "workspace of %zu bytes, %zu needed", ws_bytes, w.bytes);
     return hip_check(launch_bin(splats, rects, tiles_touched, (int)n, tiles_x(cam), tiles_y(cam),
-                                sorted_gids, sorted_tiles, ranges, pair_capacity, num_pairs, w,
-                                (hipStream_t)stream),
+                                extent_rule, sorted_gids, sorted_tiles, ranges, pair_capacity,
+                                num_pairs, w, (hipStream_t)stream),
                      "gs_bin_pairs");
 }
 

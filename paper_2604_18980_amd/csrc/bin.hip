@@ -23,7 +23,9 @@
 // histogram give the lists for free -- tile (h, l) occupies
 // [offs(h, first block of l), offs(h, first block of l + 1)).  With at most 256
 // tiles, pass 1 writes the final lists directly and its bucket starts are the
-// ranges.  Beyond the packed limits the path emits pairs and sorts them.
+// ranges.  Beyond the packed limits, and under the ellipse extent rule (whose
+// per-Gaussian pairs are row spans, not a rectangle), the path emits pairs
+// and sorts them.
 //
 // If the pair count exceeds the capacity, nothing is binned: every range is
 // empty and num_pairs holds the required count.
@@ -372,9 +374,9 @@ __global__ __launch_bounds__(256) void k_zero_ranges(uint32_t *ranges, int64_t m
 }
 
 hipError_t launch_bin(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
-                      int n, int tiles_x, int tiles_y, uint32_t *sorted_gids, uint32_t *sorted_tiles,
-                      uint32_t *ranges, int64_t cap, int64_t *num_pairs, const Workspace &ws,
-                      hipStream_t s) {
+                      int n, int tiles_x, int tiles_y, int extent_rule, uint32_t *sorted_gids,
+                      uint32_t *sorted_tiles, uint32_t *ranges, int64_t cap, int64_t *num_pairs,
+                      const Workspace &ws, hipStream_t s) {
     const int64_t ntiles = (int64_t)tiles_x * tiles_y;
     hipError_t e = launch_emit_prepare(splats, rects, tiles_touched, n, cap, num_pairs, ws, s);
     if (e != hipSuccess) return e;
@@ -383,15 +385,28 @@ hipError_t launch_bin(const float *splats, const uint64_t *rects, const uint32_t
         return hipGetLastError();
     }
     const int64_t nb = ws.nb_psort;  // slices = sort blocks = ceil(cap / 4096)
-    if (!bin_packed(n, tiles_x, tiles_y)) {
-        // generic route: emit the pairs, sort them by tile (nothing if over), ranges
-        e = launch_emit_pairs(rects, tiles_x, ws.bkey, ws.bval, cap, num_pairs, ws, s);
-        if (e != hipSuccess) return e;
+    const bool packed = bin_packed(n, tiles_x, tiles_y);
+    if (!packed || extent_rule == 1) {
+        // generic route (and the ellipse rule, whose pairs are not a rectangle
+        // enumeration): emit the pairs, sort them by tile (nothing if over), ranges
         uint32_t *kout = sorted_tiles ? sorted_tiles : ws.bpacked;
         int bits = 0;
         while (bits < 63 && ((int64_t)1 << bits) < ntiles) ++bits;
-        e = radix_sort_u32(ws.bkey, ws.bval, kout, sorted_gids, ws.ptile_tmp, ws.pgid_tmp,
-                           num_pairs, cap, bits, ws.phist, nb, ws.scan_part, s, 0, 1);
+        const int passes = bits <= 0 ? 1 : (bits + 7) / 8;
+        // Emit into the buffers the sort's first pass reads.  Beyond the packed
+        // limits the workspace has its own pair arrays; within them (at most
+        // two passes) an odd count reads the sort scratch, and an even count the
+        // outputs, which the first pass leaves for the scratch before the
+        // second pass writes them.
+        uint32_t *ek = ws.bkey, *ev = ws.bval;
+        if (packed) {
+            ek = passes % 2 ? ws.ptile_tmp : kout;
+            ev = passes % 2 ? ws.pgid_tmp : sorted_gids;
+        }
+        e = launch_emit_pairs(splats, rects, tiles_x, extent_rule, ek, ev, cap, num_pairs, ws, s);
+        if (e != hipSuccess) return e;
+        e = radix_sort_u32(ek, ev, kout, sorted_gids, ws.ptile_tmp, ws.pgid_tmp, num_pairs, cap,
+                           bits, ws.phist, nb, ws.scan_part, s, 0, 1);
         if (e != hipSuccess) return e;
         return launch_tile_ranges(kout, num_pairs, cap, ranges, (int)ntiles, s, 1);
     }

@@ -14,16 +14,14 @@
 //   k_emit                              each block writes its pairs contiguously,
 //                                       one pair per thread per step, after an LDS
 //                                       scan of its Gaussians' tile counts
+//   k_emit_spans                        extent rule 1: per Gaussian, its rows'
+//                                       ellipse spans (ellipse.hpp)
+#include "ellipse.hpp"
 #include "gsr_internal.hpp"
 
 namespace gsr {
 
 __global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
-
-__device__ __forceinline__ uint32_t rect_tiles(uint64_t r) {
-    const uint32_t x0 = r & 0xffff, y0 = (r >> 16) & 0xffff, x1 = (r >> 32) & 0xffff, y1 = r >> 48;
-    return (x1 - x0) * (y1 - y0);
-}
 
 // Sum over the blocks before this one of a per-block total (a short array:
 // the offset of this block's chunk).  Contains barriers.
@@ -105,10 +103,11 @@ __global__ __launch_bounds__(256) void k_vis_compact(const uint32_t *tiles_touch
     if (threadIdx.x == 0 && b == (int64_t)gridDim.x - 1) *num_vis = (int64_t)(before + tot);
 }
 
-// Pairs of each depth-sorted visible Gaussian (one per thread), added to the
-// total of its chunk of 4096 (cleared by k_vis_count).
+// Pairs of each depth-sorted visible Gaussian (one per thread; its
+// tiles_touched, which is the rectangle's area under extent rule 0), added to
+// the total of its chunk of 4096 (cleared by k_vis_count).
 __global__ __launch_bounds__(256) void k_pair_counts(const uint32_t *sorted_ids, const int64_t *num_vis,
-                                                     const uint64_t *rects, uint64_t *cnt,
+                                                     const uint32_t *tiles_touched, uint64_t *cnt,
                                                      uint64_t *chunk_tot) {
     __shared__ uint64_t wt[4];
     const int64_t V = *num_vis;
@@ -116,7 +115,7 @@ __global__ __launch_bounds__(256) void k_pair_counts(const uint32_t *sorted_ids,
     if ((int64_t)blockIdx.x * 256 >= V) return;  // uniform
     uint64_t c = 0;
     if (j < V) {
-        c = rect_tiles(rects[sorted_ids[j]]);
+        c = tiles_touched[sorted_ids[j]];
         cnt[j] = c;
     }
     uint64_t tot;
@@ -240,17 +239,55 @@ hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
                                      num_vis);
     hipError_t e = depth_sort(ws, num_vis, s);  // dkey/dval[0] -> [1]
     if (e != hipSuccess) return e;
-    k_pair_counts<<<(unsigned)ws.nb_gauss, 256, 0, s>>>(ws.dval[1], num_vis, rects, ws.pair_cnt,
-                                                       ws.pair_tot);
+    k_pair_counts<<<(unsigned)ws.nb_gauss, 256, 0, s>>>(ws.dval[1], num_vis, tiles_touched,
+                                                       ws.pair_cnt, ws.pair_tot);
     k_pair_offsets<<<nb, 256, 0, s>>>(ws.pair_cnt, ws.pair_tot, num_vis, ws.pair_off, ws.slice_start,
                                       num_pairs, cap);
     return hipGetLastError();
 }
 
-hipError_t launch_emit_pairs(const uint64_t *rects, int tiles_x, uint32_t *pair_tiles,
-                             uint32_t *pair_gids, int64_t cap, const int64_t *num_pairs,
-                             const Workspace &ws, hipStream_t s) {
-    if (cap > 0)
+// Extent rule 1: one thread per depth-sorted visible Gaussian writes its pairs
+// at its offset, row by row over its (bounding) rectangle, each row's ellipse
+// span recomputed from the splat record exactly as the preprocess counted it.
+// Pairs at or beyond the capacity are not written.
+__global__ __launch_bounds__(256) void k_emit_spans(const uint32_t *sorted_ids, const int64_t *num_vis,
+                                                    const float *splats, const uint64_t *rects,
+                                                    const uint64_t *off, int tiles_x,
+                                                    uint32_t *pair_tiles, uint32_t *pair_gids,
+                                                    int64_t cap) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= *num_vis) return;
+    uint64_t k = off[j];
+    if (k >= (uint64_t)cap) return;
+    const uint32_t g = sorted_ids[j];
+    const uint64_t r = rects[g];
+    const int x0 = (int)(r & 0xffff), y0 = (int)((r >> 16) & 0xffff), x1 = (int)((r >> 32) & 0xffff),
+              y1 = (int)(r >> 48);
+    const float *rec = splats + (size_t)g * 12;
+    Ellipse e;
+    if (!ellipse_setup(rec[0], rec[1], rec[2], rec[3], rec[4], rec[5], rec[7], e)) return;
+    for (int ty = y0; ty < y1; ++ty) {
+        int a, b;
+        if (!ellipse_row_span(e, ty, x0, x1 - 1, a, b)) continue;
+        const uint32_t row = (uint32_t)ty * (uint32_t)tiles_x;
+        for (int tx = a; tx <= b; ++tx, ++k) {
+            if (k >= (uint64_t)cap) return;
+            pair_tiles[k] = row + (uint32_t)tx;
+            pair_gids[k] = g;
+        }
+    }
+}
+
+hipError_t launch_emit_pairs(const float *splats, const uint64_t *rects, int tiles_x,
+                             int extent_rule, uint32_t *pair_tiles, uint32_t *pair_gids,
+                             int64_t cap, const int64_t *num_pairs, const Workspace &ws,
+                             hipStream_t s) {
+    if (cap <= 0) return hipGetLastError();
+    if (extent_rule == 1)
+        k_emit_spans<<<(unsigned)ws.nb_gauss, 256, 0, s>>>(ws.dval[1], ws.counters, splats, rects,
+                                                          ws.pair_off, tiles_x, pair_tiles,
+                                                          pair_gids, cap);
+    else
         k_emit<<<(unsigned)((cap + kEmitChunk - 1) / kEmitChunk), 256, 0, s>>>(
             ws.dval[1], ws.counters, rects, ws.pair_off, ws.slice_start, num_pairs, tiles_x,
             pair_tiles, pair_gids, cap);
@@ -258,11 +295,13 @@ hipError_t launch_emit_pairs(const uint64_t *rects, int tiles_x, uint32_t *pair_
 }
 
 hipError_t launch_emit(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
-                       int n, int tiles_x, uint32_t *pair_tiles, uint32_t *pair_gids, int64_t cap,
-                       int64_t *num_pairs, const Workspace &ws, hipStream_t s) {
+                       int n, int tiles_x, int extent_rule, uint32_t *pair_tiles,
+                       uint32_t *pair_gids, int64_t cap, int64_t *num_pairs, const Workspace &ws,
+                       hipStream_t s) {
     hipError_t e = launch_emit_prepare(splats, rects, tiles_touched, n, cap, num_pairs, ws, s);
     if (e != hipSuccess || n == 0) return e;
-    return launch_emit_pairs(rects, tiles_x, pair_tiles, pair_gids, cap, num_pairs, ws, s);
+    return launch_emit_pairs(splats, rects, tiles_x, extent_rule, pair_tiles, pair_gids, cap,
+                             num_pairs, ws, s);
 }
 
 int emit_chunk() { return kEmitChunk; }

@@ -20,6 +20,7 @@ struct PreprocessArgs {
     double fx, fy, cx, cy, limx, limy;
     int width, height, tiles_x, tiles_y;
     int adagscale, force_unit_scale;
+    int extent_rule;  // 0: tile rectangle; 1: rectangle tiles meeting the alpha >= th ellipse
     double K, lut_depth_max;
     float lut[kLutBins];
     double shc[16];  // real-SH normalisation constants, see preprocess.hip
@@ -135,8 +136,9 @@ void radix_hist(const uint32_t *keys, const int64_t *count, int64_t cap, int shi
                 int64_t nblocks, uint64_t *parts, hipStream_t s, int empty_if_over);
 
 hipError_t launch_emit(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
-                       int n, int tiles_x, uint32_t *pair_tiles, uint32_t *pair_gids, int64_t cap,
-                       int64_t *num_pairs, const Workspace &ws, hipStream_t s);
+                       int n, int tiles_x, int extent_rule, uint32_t *pair_tiles,
+                       uint32_t *pair_gids, int64_t cap, int64_t *num_pairs, const Workspace &ws,
+                       hipStream_t s);
 // Everything of launch_emit before the pairs are written: visible Gaussians in
 // depth order (ws.dval[1], count in ws.counters[0]), their pair counts and
 // offsets (ws.pair_cnt, ws.pair_off), the pair total, and the emission slice
@@ -148,16 +150,19 @@ hipError_t depth_sort(const Workspace &ws, const int64_t *count, hipStream_t s);
 hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
                                const uint32_t *tiles_touched, int n, int64_t cap, int64_t *num_pairs,
                                const Workspace &ws, hipStream_t s);
-// The pair-writing part of launch_emit, after launch_emit_prepare.
-hipError_t launch_emit_pairs(const uint64_t *rects, int tiles_x, uint32_t *pair_tiles,
-                             uint32_t *pair_gids, int64_t cap, const int64_t *num_pairs,
-                             const Workspace &ws, hipStream_t s);
+// The pair-writing part of launch_emit, after launch_emit_prepare: whole
+// rectangles (extent rule 0) or each rectangle row's ellipse span (rule 1,
+// recomputed from the splat records).
+hipError_t launch_emit_pairs(const float *splats, const uint64_t *rects, int tiles_x,
+                             int extent_rule, uint32_t *pair_tiles, uint32_t *pair_gids,
+                             int64_t cap, const int64_t *num_pairs, const Workspace &ws,
+                             hipStream_t s);
 // Emission and tile sort fused (bin.hip): the sorted ids, optionally the sorted
 // tile ids, and the ranges, without the emission-order pair arrays.
 hipError_t launch_bin(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
-                      int n, int tiles_x, int tiles_y, uint32_t *sorted_gids, uint32_t *sorted_tiles,
-                      uint32_t *ranges, int64_t cap, int64_t *num_pairs, const Workspace &ws,
-                      hipStream_t s);
+                      int n, int tiles_x, int tiles_y, int extent_rule, uint32_t *sorted_gids,
+                      uint32_t *sorted_tiles, uint32_t *ranges, int64_t cap, int64_t *num_pairs,
+                      const Workspace &ws, hipStream_t s);
 
 hipError_t launch_tile_ranges(const uint32_t *sorted_tiles, const int64_t *num_pairs, int64_t cap,
                               uint32_t *ranges, int num_tiles, hipStream_t s, int empty_if_over = 0);

@@ -45,7 +45,8 @@ class GsCamera(C.Structure):
 
 class GsMode(C.Structure):
     _fields_ = [("adagscale", C.c_int), ("K", C.c_float), ("t_upper", C.c_float * LUT_BINS),
-                ("lut_depth_max", C.c_float), ("force_unit_scale", C.c_int)]
+                ("lut_depth_max", C.c_float), ("force_unit_scale", C.c_int),
+                ("extent_rule", C.c_int)]
 
 
 class GsRasterCfg(C.Structure):
@@ -73,9 +74,9 @@ def load():
     L.gs_workspace_size.argtypes = [I64, I64, I, I]
     L.gs_workspace_size.restype = C.c_size_t
     L.gs_preprocess.argtypes = [P, P, P, P, P, P, P]
-    L.gs_emit_pairs.argtypes = [P, P, P, I64, P, P, P, I64, P, P, C.c_size_t, P]
+    L.gs_emit_pairs.argtypes = [P, P, P, I64, P, I, P, P, I64, P, P, C.c_size_t, P]
     L.gs_sort.argtypes = [P, P, P, I64, P, P, P, P, P, C.c_size_t, P]
-    L.gs_bin_pairs.argtypes = [P, P, P, I64, P, P, P, P, I64, P, P, C.c_size_t, P]
+    L.gs_bin_pairs.argtypes = [P, P, P, I64, P, I, P, P, P, I64, P, P, C.c_size_t, P]
     L.gs_rasterize.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P]
     L.gs_raster_work.argtypes = [P, I64, P, P, P, P, P]
     L.gs_calibrate_t_upper.argtypes = [P, I64, P, P, P, C.c_float, P, P, P]
@@ -124,7 +125,7 @@ def camera_struct(cam) -> GsCamera:
 
 
 def mode_struct(adagscale=False, K=0.0, t_upper=None, lut_depth_max=100.0,
-                force_unit_scale=False) -> GsMode:
+                force_unit_scale=False, extent_rule=0) -> GsMode:
     m = GsMode()
     m.adagscale = 1 if adagscale else 0
     m.K = float(K)
@@ -133,6 +134,7 @@ def mode_struct(adagscale=False, K=0.0, t_upper=None, lut_depth_max=100.0,
         m.t_upper[i] = float(lut[i])
     m.lut_depth_max = float(lut_depth_max)
     m.force_unit_scale = 1 if force_unit_scale else 0
+    m.extent_rule = int(extent_rule)
     return m
 
 
@@ -160,10 +162,10 @@ def gs_preprocess(scene: GsScene, cam: GsCamera, mode: GsMode, splats, rects, ti
                                 _ptr(rects), _ptr(tiles_touched), _stream(stream)))
 
 
-def gs_emit_pairs(splats, rects, tiles_touched, n, cam: GsCamera, pair_tiles, pair_gids,
-                  pair_capacity, num_pairs, ws, stream=None):
+def gs_emit_pairs(splats, rects, tiles_touched, n, cam: GsCamera, extent_rule, pair_tiles,
+                  pair_gids, pair_capacity, num_pairs, ws, stream=None):
     _check(load().gs_emit_pairs(_ptr(splats), _ptr(rects), _ptr(tiles_touched), int(n),
-                                C.byref(cam), _ptr(pair_tiles), _ptr(pair_gids),
+                                C.byref(cam), int(extent_rule), _ptr(pair_tiles), _ptr(pair_gids),
                                 int(pair_capacity), _ptr(num_pairs), _ptr(ws),
                                 int(ws.numel() * ws.element_size()) if ws is not None else 0,
                                 _stream(stream)))
@@ -177,11 +179,12 @@ def gs_sort(pair_tiles, pair_gids, num_pairs, pair_capacity, cam: GsCamera, sort
                           _stream(stream)))
 
 
-def gs_bin_pairs(splats, rects, tiles_touched, n, cam: GsCamera, sorted_gids, sorted_tiles, ranges,
-                 pair_capacity, num_pairs, ws, stream=None):
+def gs_bin_pairs(splats, rects, tiles_touched, n, cam: GsCamera, extent_rule, sorted_gids,
+                 sorted_tiles, ranges, pair_capacity, num_pairs, ws, stream=None):
     """sorted_tiles may be None (not written)."""
     _check(load().gs_bin_pairs(_ptr(splats), _ptr(rects), _ptr(tiles_touched), int(n),
-                               C.byref(cam), _ptr(sorted_gids), _ptr(sorted_tiles), _ptr(ranges),
+                               C.byref(cam), int(extent_rule), _ptr(sorted_gids),
+                               _ptr(sorted_tiles), _ptr(ranges),
                                int(pair_capacity), _ptr(num_pairs), _ptr(ws),
                                int(ws.numel() * ws.element_size()) if ws is not None else 0,
                                _stream(stream)))

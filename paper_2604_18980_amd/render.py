@@ -74,6 +74,7 @@ class FrameBuffers:
         self.n_contrib = torch.empty((self.height, self.width), dtype=torch.int32, device=device)
         assert npix == self.final_T.numel()
         self.capacity = -1
+        self.extent_rule = 0  # the rule of the last preprocess; emission must match it
         self.set_capacity(capacity)
 
     def set_capacity(self, capacity):
@@ -93,11 +94,12 @@ class FrameBuffers:
 
 def run_preprocess(scene: DeviceScene, cam_s, mode_s, fb: FrameBuffers, stream=None):
     gsr.gs_preprocess(scene.struct(), cam_s, mode_s, fb.splats, fb.rects, fb.tiles_touched, stream)
+    fb.extent_rule = int(mode_s.extent_rule)
 
 
 def run_emit(fb: FrameBuffers, cam_s, stream=None):
-    gsr.gs_emit_pairs(fb.splats, fb.rects, fb.tiles_touched, fb.n, cam_s, fb.pair_tiles,
-                      fb.pair_gids, fb.capacity, fb.num_pairs, fb.ws, stream)
+    gsr.gs_emit_pairs(fb.splats, fb.rects, fb.tiles_touched, fb.n, cam_s, fb.extent_rule,
+                      fb.pair_tiles, fb.pair_gids, fb.capacity, fb.num_pairs, fb.ws, stream)
 
 
 def run_sort(fb: FrameBuffers, cam_s, stream=None):
@@ -108,9 +110,9 @@ def run_sort(fb: FrameBuffers, cam_s, stream=None):
 def run_bin(fb: FrameBuffers, cam_s, stream=None, with_tiles=False):
     """Emission + sort + ranges in one call (gs_bin_pairs); pair_tiles and
     pair_gids are not written, sorted_tiles only with with_tiles."""
-    gsr.gs_bin_pairs(fb.splats, fb.rects, fb.tiles_touched, fb.n, cam_s, fb.sorted_gids,
-                     fb.sorted_tiles if with_tiles else None, fb.ranges, fb.capacity,
-                     fb.num_pairs, fb.ws, stream)
+    gsr.gs_bin_pairs(fb.splats, fb.rects, fb.tiles_touched, fb.n, cam_s, fb.extent_rule,
+                     fb.sorted_gids, fb.sorted_tiles if with_tiles else None, fb.ranges,
+                     fb.capacity, fb.num_pairs, fb.ws, stream)
 
 
 def run_raster(fb: FrameBuffers, cam_s, bg, stream=None, cfg=None, n_evaluated=None):
@@ -144,14 +146,14 @@ def enqueue_frame(scene: DeviceScene, cam_s, mode_s, fb: FrameBuffers, bg=(0.0, 
 
 def render(scene: DeviceScene, cam, adagscale=False, K=0.0, t_upper=None, lut_depth_max=100.0,
            force_unit_scale=False, bg=(0.0, 0.0, 0.0), fb: FrameBuffers = None, slack=1.0,
-           staged=False, with_tiles=False):
+           staged=False, with_tiles=False, extent_rule=0):
     """Render one frame.  Sizes the pair buffers from a counting pass (one host
     read of the pair count) unless ``fb`` already has enough capacity.
     staged=True uses gs_emit_pairs + gs_sort (emission-order pairs kept in
     fb.pair_tiles / fb.pair_gids); otherwise gs_bin_pairs, which also writes
     fb.sorted_tiles when with_tiles."""
     cam_s = gsr.camera_struct(cam)
-    mode_s = gsr.mode_struct(adagscale, K, t_upper, lut_depth_max, force_unit_scale)
+    mode_s = gsr.mode_struct(adagscale, K, t_upper, lut_depth_max, force_unit_scale, extent_rule)
     if fb is None:
         fb = FrameBuffers(scene.n, cam["width"], cam["height"], 0, scene.means.device)
     run_preprocess(scene, cam_s, mode_s, fb)

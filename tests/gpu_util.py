@@ -53,7 +53,8 @@ def oracle_mode(O, mode):
     mode = mode or {}
     return O.Mode(adagscale=mode.get("adagscale", False), K=mode.get("K", 0.0),
                   t_upper=mode.get("t_upper"), lut_depth_max=mode.get("lut_depth_max", 100.0),
-                  force_unit_scale=mode.get("force_unit_scale", False))
+                  force_unit_scale=mode.get("force_unit_scale", False),
+                  extent_rule=mode.get("extent_rule", 0))
 
 
 def check_preprocess(pre, g):

@@ -1,16 +1,20 @@
 """Per-tile views of the oracle's frame for checks at full size, where the
-oracle's whole emit/sort/blend would take too long: list lengths of every
-tile, and the sorted lists of a few sampled tiles, both derived from the
-oracle's rectangles and float32 depths alone."""
+oracle's whole sort/blend would take too long: list lengths of every tile,
+and the sorted lists of a few sampled tiles, derived from the oracle's
+rectangles and float32 depths (rectangle rule) or from the oracle's emitted
+pairs (ellipse rule, whose pairs are not whole rectangles)."""
 import numpy as np
 
 TILE = 16
 
 
-def tile_counts(pre, cam):
+def tile_counts(pre, cam, pairs=None):
     """Length of every tile's list: how many visible rectangles hold the tile
-    (2D difference array over the tile grid)."""
+    (2D difference array over the tile grid), or, given the oracle's emitted
+    (keys, vals), how many pairs name it."""
     TX, TY = (cam["width"] + TILE - 1) // TILE, (cam["height"] + TILE - 1) // TILE
+    if pairs is not None:
+        return np.bincount((pairs[0] >> np.uint64(32)).astype(np.int64), minlength=TX * TY)
     r = pre.rect[pre.tiles_touched > 0].astype(np.int64)
     W1 = TX + 1
     m = (TY + 1) * W1
@@ -19,10 +23,19 @@ def tile_counts(pre, cam):
     return D.reshape(TY + 1, W1).cumsum(0).cumsum(1)[:TY, :TX].reshape(-1)
 
 
-def tile_lists(pre, cam, tiles):
+def tile_lists(pre, cam, tiles, pairs=None):
     """Sorted list of each tile in `tiles`: the visible Gaussians whose
-    rectangle holds it, by float32 depth, ties by index."""
+    rectangle holds it (or, given the oracle's emitted (keys, vals), that are
+    paired with it), by float32 depth, ties by index."""
     TX = (cam["width"] + TILE - 1) // TILE
+    if pairs is not None:
+        t_of = (pairs[0] >> np.uint64(32)).astype(np.int64)
+        d32 = pre.depth.astype(np.float32)
+        out = []
+        for t in tiles:
+            ids = pairs[1][t_of == int(t)].astype(np.int64)
+            out.append(ids[np.lexsort((ids, d32[ids]))].astype(np.uint32))
+        return out
     vis = np.nonzero(pre.tiles_touched > 0)[0]
     r = pre.rect[vis]
     d32 = pre.depth[vis].astype(np.float32)
@@ -35,10 +48,10 @@ def tile_lists(pre, cam, tiles):
     return out
 
 
-def tile_frame(O, pre, cam, tiles):
+def tile_frame(O, pre, cam, tiles, pairs=None):
     """Oracle Frame whose ranges cover only `tiles` (the other tiles empty),
     for blending or differentiating those tiles alone."""
-    lists = tile_lists(pre, cam, tiles)
+    lists = tile_lists(pre, cam, tiles, pairs)
     ranges = np.zeros((O.num_tiles(cam), 2), np.int64)
     off = 0
     for t, lst in zip(tiles, lists):

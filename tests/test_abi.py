@@ -92,8 +92,18 @@ def test_invalid_arguments_rejected_on_host(G):
     assert b"K" in L.gs_last_error()
     m = G.mode_struct(adagscale=True, K=0.1, t_upper=[2.0] * 20)
     assert L.gs_preprocess(C.byref(sc), C.byref(cam), C.byref(m), P(1), P(1), P(1), None) == 1
+    m = G.mode_struct(extent_rule=2)
+    assert L.gs_preprocess(C.byref(sc), C.byref(cam), C.byref(m), P(1), P(1), P(1), None) == 1
+    assert b"extent_rule" in L.gs_last_error()
+    # unknown extent rule at emission and binning
+    assert L.gs_emit_pairs(P(1), P(1), P(1), 10, C.byref(cam), 3, P(1), P(1), 100, P(1), P(1),
+                           1 << 40, None) == 1
+    assert b"extent_rule" in L.gs_last_error()
+    assert L.gs_bin_pairs(P(1), P(1), P(1), 10, C.byref(cam), -1, P(1), None, P(1), 100, P(1),
+                          P(1), 1 << 40, None) == 1
+    assert b"extent_rule" in L.gs_last_error()
     # workspace too small
-    assert L.gs_emit_pairs(P(1), P(1), P(1), 10, C.byref(cam), P(1), P(1), 100, P(1), P(1), 8,
+    assert L.gs_emit_pairs(P(1), P(1), P(1), 10, C.byref(cam), 0, P(1), P(1), 100, P(1), P(1), 8,
                            None) == 2
     assert b"workspace" in L.gs_last_error()
     # capacity beyond 32-bit indices

@@ -40,10 +40,15 @@ CASES = ["tiny128", "tiny128_ada", "ragged_257x129", "ragged_300x301", "mid_1920
          "wide_4112x4112"]
 
 
+@pytest.mark.parametrize("rule", [0, 1], ids=["rect", "ellipse"])
 @pytest.mark.parametrize("name", CASES)
-def test_bin_equals_staged_and_oracle(O, name):
+def test_bin_equals_staged_and_oracle(O, name, rule):
+    """Under the ellipse rule every case takes the emit-then-sort route, with
+    the pairs emitted into the sort scratch (one pass), the outputs (two
+    passes) or the route's own arrays (beyond the packed limits)."""
     sc, cam, mode = _case(name)
-    print(f"bin case {name}: n={sc.n} {cam['width']}x{cam['height']}", flush=True)
+    mode = dict(mode, extent_rule=rule)
+    print(f"bin case {name} rule {rule}: n={sc.n} {cam['width']}x{cam['height']}", flush=True)
     st = gpu_frame(sc, cam, mode, staged=True)
     bn = gpu_frame(sc, cam, mode, staged=False)
     P = st["num_pairs"]
@@ -76,14 +81,16 @@ def test_bin_empty_and_culled(O):
     assert np.all(g["final_T"] == 1.0) and not g["image"].any()
 
 
+@pytest.mark.parametrize("rule", [0, 1], ids=["rect", "ellipse"])
 @pytest.mark.parametrize("name", ["tiny128", "ragged_300x301", "wide_4112x4112"])
-def test_bin_overflow_bins_nothing(O, name):
+def test_bin_overflow_bins_nothing(O, name, rule):
     """Capacity below the pair count: the required count is reported, no list
     is produced (every range empty, image = background), and a regrown buffer
     gives the full result."""
     import torch
     from paper_2604_18980_amd import gsr, render as R
     sc, cam, mode = _case(name)
+    mode = dict(mode, extent_rule=rule)
     full = gpu_frame(sc, cam, mode, staged=True)
     ds = R.DeviceScene.from_host(sc)
     cam_s, mode_s = gsr.camera_struct(cam), gsr.mode_struct(**mode)

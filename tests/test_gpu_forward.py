@@ -8,8 +8,8 @@ import pytest
 
 from paper_2604_18980_amd import scenes
 
-from gpu_util import (check_emission_order, check_image, check_pairs, check_preprocess,
-                      check_sorted, gpu_frame, oracle_mode)
+from gpu_util import (EXEMPT_MARGIN, check_emission_order, check_image, check_pairs,
+                      check_preprocess, check_sorted, gpu_frame, oracle_mode)
 
 pytestmark = pytest.mark.gpu
 
@@ -20,6 +20,12 @@ MODES = [
     ("ada_K1", dict(adagscale=True, K=1.0)),
     ("ada_unit", dict(adagscale=True, K=1.0, force_unit_scale=True)),
     ("ada_lut", dict(adagscale=True, K=0.3, t_upper=np.linspace(1.0, 0.05, 20), lut_depth_max=8.0)),
+    # the ellipse tile test (extent rule 1)
+    ("plain_ell", dict(extent_rule=1)),
+    ("ada_ell_K0.1", dict(adagscale=True, K=0.1, extent_rule=1)),
+    ("ada_ell_K1", dict(adagscale=True, K=1.0, extent_rule=1)),
+    ("ada_ell_lut", dict(adagscale=True, K=0.3, t_upper=np.linspace(1.0, 0.05, 20),
+                         lut_depth_max=8.0, extent_rule=1)),
 ]
 
 
@@ -53,13 +59,15 @@ def test_ragged_image_sizes(O, w, h):
     cam = scenes.make_camera(np.eye(3), np.zeros(3), w, h)
     _full_check(O, sc, cam, dict(adagscale=True, K=0.1))
     _full_check(O, sc, cam, {})
+    _full_check(O, sc, cam, dict(adagscale=True, K=0.1, extent_rule=1))
 
 
 def test_mid_scene_subsample(O):
     """Mid-scene generator (clustered, SH degree 3, far shell), 60K Gaussians at
     1920x1080: spans thousands of tiles, several sort blocks and ragged tails."""
     sc, cam = scenes.mid_scene(n=60_000, seed=1)
-    for mode in ({}, dict(adagscale=True, K=1.0)):
+    for mode in ({}, dict(adagscale=True, K=1.0), dict(extent_rule=1),
+                 dict(adagscale=True, K=1.0, extent_rule=1)):
         g = gpu_frame(sc, cam, mode)
         fr = O.render(sc, cam, oracle_mode(O, mode),
                       tiles=np.arange(0, O.num_tiles(cam), 37, dtype=np.int32))
@@ -95,28 +103,46 @@ def test_non_finite_and_degenerate_inputs(O):
     sc.log_scales[:, 25:30] = -30.0      # sub-pixel: dilation dominates
     sc.opacity_logits[30:40] = -30.0     # opacity ~ 0
     sc.opacity_logits[40:50] = 30.0      # opacity ~ 1, alpha clamps at 0.99
-    for mode in ({}, dict(adagscale=True, K=0.5)):
+    for mode in ({}, dict(adagscale=True, K=0.5), dict(extent_rule=1),
+                 dict(adagscale=True, K=0.5, extent_rule=1)):
         _full_check(O, sc, cam, mode)
 
 
-def test_capacity_overflow_reports_required_count(O):
+@pytest.mark.parametrize("staged", [False, True], ids=["bin", "staged"])
+@pytest.mark.parametrize("rule", [0, 1], ids=["rect", "ellipse"])
+def test_capacity_overflow_reports_required_count(O, rule, staged):
     """An undersized pair buffer: emit reports the required count, the stages
     after it stay in bounds, and a regrown buffer gives the full result."""
     import torch
     from paper_2604_18980_amd import gsr, render as R
     sc, cam = scenes.tiny_scene()
-    full = gpu_frame(sc, cam)
+    full = gpu_frame(sc, cam, dict(extent_rule=rule))
     ds = R.DeviceScene.from_host(sc)
-    cam_s, mode_s = gsr.camera_struct(cam), gsr.mode_struct()
+    cam_s, mode_s = gsr.camera_struct(cam), gsr.mode_struct(extent_rule=rule)
     fb = R.FrameBuffers(ds.n, cam["width"], cam["height"], full["num_pairs"] // 3)
-    R.enqueue_frame(ds, cam_s, mode_s, fb)
+    R.enqueue_frame(ds, cam_s, mode_s, fb, staged=staged)
     torch.cuda.synchronize()
     assert int(fb.num_pairs.item()) == full["num_pairs"]
     assert fb.capacity == full["num_pairs"] // 3
     fb.set_capacity(full["num_pairs"])
-    R.enqueue_frame(ds, cam_s, mode_s, fb)
+    R.enqueue_frame(ds, cam_s, mode_s, fb, staged=staged)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(fb.image.cpu().numpy(), full["image"])
+
+
+def test_ellipse_rule_on_gpu_drops_only_empty_pairs(O):
+    """Plain 3D-GS with the ellipse test: a subset of the rectangle rule's
+    pairs, markedly fewer, and the same image within the parity tolerance."""
+    sc, cam = scenes.tiny_scene(seed=14)
+    rect = gpu_frame(sc, cam, {})
+    ell = gpu_frame(sc, cam, dict(extent_rule=1))
+    assert ell["num_pairs"] < 0.9 * rect["num_pairs"]
+    pr = set(zip(rect["pair_tiles"].tolist(), rect["pair_gids"].tolist()))
+    pe = set(zip(ell["pair_tiles"].tolist(), ell["pair_gids"].tolist()))
+    assert pe <= pr
+    ok = O.render(sc, cam).margin >= EXEMPT_MARGIN  # no blend decision near a threshold
+    assert np.abs(ell["image"] - rect["image"])[:, ok].max() <= 2e-5
+    print(f"  pairs rect {rect['num_pairs']} ellipse {ell['num_pairs']}", flush=True)
 
 
 def test_deterministic(O):

@@ -40,10 +40,17 @@ def _gpu_frame(sc, cam, mode):
 
 
 def _omode(O, mode):
-    return O.Mode(adagscale=mode.get("adagscale", False), K=mode.get("K", 0.0))
+    return O.Mode(adagscale=mode.get("adagscale", False), K=mode.get("K", 0.0),
+                  extent_rule=mode.get("extent_rule", 0))
 
 
-def check_sampled(O, pre, cam, fb, tiles, n, check_records=True):
+def _pairs(O, pre, cam):
+    """The oracle's emitted pairs under the ellipse rule (None under the
+    rectangle rule, whose lists follow from the rectangles)."""
+    return O.emit(pre, cam) if pre.extent_rule == 1 else None
+
+
+def check_sampled(O, pre, cam, fb, tiles, n, check_records=True, pairs=None):
     """Everything of one view that the oracle can check at full size."""
     if check_records:
         tt = to_np(fb.tiles_touched)[:n].astype(np.uint32).astype(np.int64)
@@ -62,14 +69,14 @@ def check_sampled(O, pre, cam, fb, tiles, n, check_records=True):
         P = int(fb.num_pairs.item())
         assert P == int(pre.tiles_touched.sum()) and P <= fb.capacity
     rg = to_np(fb.ranges).astype(np.uint32).astype(np.int64)
-    counts = tile_counts(pre, cam)
+    counts = tile_counts(pre, cam, pairs)
     np.testing.assert_array_equal(rg[:, 1] - rg[:, 0], counts)
     nz = counts > 0
     if nz.any():
         st = np.sort(rg[nz, 0])
         en = np.sort(rg[nz, 1])
         assert st[0] == 0 and np.all(st[1:] == en[:-1]) and en[-1] == counts.sum()
-    fr, lists = tile_frame(O, pre, cam, tiles)
+    fr, lists = tile_frame(O, pre, cam, tiles, pairs)
     gids = to_np(fb.sorted_gids).astype(np.uint32)
     for t, lst in zip(tiles, lists):
         np.testing.assert_array_equal(gids[rg[t, 0]:rg[t, 1]], lst)
@@ -80,15 +87,18 @@ def check_sampled(O, pre, cam, fb, tiles, n, check_records=True):
     return int(counts.sum()), n_ex
 
 
-@pytest.mark.parametrize("mode", [{}, dict(adagscale=True, K=CITY_K)], ids=["plain", "ada"])
+@pytest.mark.parametrize("mode", [{}, dict(adagscale=True, K=CITY_K), dict(extent_rule=1),
+                                  dict(adagscale=True, K=CITY_K, extent_rule=1)],
+                         ids=["plain", "ada", "plain_ellipse", "ada_ellipse"])
 def test_city_6M_4608x3456(O, mode):
     import torch
     sc, cam = _city()
     print(f"city 6M 4608x3456 {mode}", flush=True)
     ds, fb = _gpu_frame(sc, cam, mode)
     pre = O.preprocess(sc, cam, _omode(O, mode))
-    tiles = pick_tiles(tile_counts(pre, cam), 40, 8, 0)
-    P, n_ex = check_sampled(O, pre, cam, fb, tiles, sc.n)
+    pairs = _pairs(O, pre, cam)
+    tiles = pick_tiles(tile_counts(pre, cam, pairs), 40, 8, 0)
+    P, n_ex = check_sampled(O, pre, cam, fb, tiles, sc.n, pairs=pairs)
     print(f"  pairs {P}, {tiles.size} tiles checked, {n_ex} exempt pixels", flush=True)
     del ds, fb
     torch.cuda.empty_cache()

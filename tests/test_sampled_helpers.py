@@ -8,9 +8,17 @@ from paper_2604_18980_amd import scenes
 from sampled import pick_tiles, tile_counts, tile_frame, tile_mask
 
 
-@pytest.mark.parametrize("case", ["tiny", "mid_subset", "ragged"])
+@pytest.mark.parametrize("case", ["tiny", "mid_subset", "ragged", "tiny_ellipse",
+                                  "mid_subset_ellipse"])
 def test_tile_shortcuts_match_full_pipeline(O, case):
-    if case == "tiny":
+    pairs = None
+    if case == "tiny_ellipse":
+        sc, cam = scenes.tiny_scene(n=2000, seed=3)
+        mode = O.Mode(extent_rule=1)
+    elif case == "mid_subset_ellipse":
+        sc, cam = scenes.mid_scene(n=20_000, seed=2, width=480, height=270)
+        mode = O.Mode(adagscale=True, K=1.0, extent_rule=1)
+    elif case == "tiny":
         sc, cam = scenes.tiny_scene(n=2000, seed=3)
         mode = O.Mode()
     elif case == "mid_subset":
@@ -21,10 +29,12 @@ def test_tile_shortcuts_match_full_pipeline(O, case):
         cam = dict(cam, width=100, height=37)
         mode = O.Mode()
     fr = O.render(sc, cam, mode)
-    counts = tile_counts(fr.pre, cam)
+    if mode.extent_rule == 1:
+        pairs = O.emit(fr.pre, cam)
+    counts = tile_counts(fr.pre, cam, pairs)
     np.testing.assert_array_equal(counts, fr.ranges[:, 1] - fr.ranges[:, 0])
     tiles = pick_tiles(counts, 12, 4, 0)
-    sub, lists = tile_frame(O, fr.pre, cam, tiles)
+    sub, lists = tile_frame(O, fr.pre, cam, tiles, pairs)
     for t, lst in zip(tiles, lists):
         np.testing.assert_array_equal(fr.sorted_vals[fr.ranges[t, 0]:fr.ranges[t, 1]], lst)
     img, T, nc, mg, ev, sg = O.blend(sub, cam, tiles=tiles)
