@@ -182,8 +182,8 @@ static int is_finite(double x) { return x == x && fabs(x) <= 1.79769313486231570
 /* ceil((xl - 15) / 16) <= tx <= floor(xr / 16).                             */
 /*                                                                           */
 /* Every value is the float32 record value widened to double (the renderer   */
-/* evaluates the same record), so emission can recompute the spans.  The     */
-/* test runs inside the plain tile rectangle and only removes tiles from it. */
+/* blends the same record).  The test runs inside the plain tile rectangle   */
+/* and only removes tiles from it.                                           */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     double u, v, A, beta, gamma, c, R, w;
@@ -260,9 +260,9 @@ int orc_ellipse_spans(double u, double v, double A, double beta, double gamma, d
 /* half-open, tiles), tiles_touched, radius (int).                           */
 /* flags: 0 culled, 1 projected (finite, in front), 2 projected with tiles.   */
 /* extent_rule 0: the rectangle of radius ceil(v s) (s = 1 when plain) and   */
-/* tiles_touched = its area.  extent_rule 1: the tiles of the plain radius-  */
-/* ceil(v) rectangle that meet the alpha >= th ellipse, tiles_touched = their */
-/* count and rect = their bounding box.                                       */
+/* tiles_touched = its area.  extent_rule 1: the plain radius-ceil(v)         */
+/* rectangle and its area, the candidates that pair generation then tests    */
+/* against the alpha >= th ellipse (Sec. 3.3 applies Th in that stage).      */
 /* ------------------------------------------------------------------------ */
 void orc_preprocess(int64_t n, const float *means, const float *log_scales, const float *quats,
                     const float *opacity_logits, const float *sh, int sh_degree,
@@ -389,7 +389,7 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
             th[g] = thv;
             scale[g] = sv;
             if (!keep) continue;
-            if (extent_rule == 0) ext = ext * sv;  /* rule 1 tests the alpha = Th ellipse below */
+            if (extent_rule == 0) ext = ext * sv;  /* rule 1: Th enters at pair generation */
         }
         double rd = ceil(ext);
         if (rd > 1073741824.0) rd = 1073741824.0; /* 2^30 px: covers any image */
@@ -407,28 +407,6 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
         int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
         int64_t tiles = (int64_t)(x1 - x0) * (int64_t)(y1 - y0);
         if (tiles <= 0) continue;
-        if (extent_rule == 1) {
-            /* the tiles of the plain rectangle that meet the alpha >= th ellipse;
-               the rectangle shrinks to their bounding box */
-            ellipse_t e;
-            ellipse_setup(f32r(u), f32r(v), f32r(c / det), f32r(-b * ic), f32r(ic), f32r(sigma),
-                          f32r(th[g]), &e);
-            if (!e.ok) continue;
-            int nx0 = x1, nx1 = x0, ny0 = -1, ny1 = -1;
-            tiles = 0;
-            for (int ty = y0; ty < y1; ++ty) {
-                int sa, sb;
-                ellipse_row_span(&e, ty, x0, x1 - 1, &sa, &sb);
-                if (sb < sa) continue;
-                tiles += sb - sa + 1;
-                if (sa < nx0) nx0 = sa;
-                if (sb + 1 > nx1) nx1 = sb + 1;
-                if (ny0 < 0) ny0 = ty;
-                ny1 = ty + 1;
-            }
-            if (tiles == 0) continue;
-            x0 = nx0; x1 = nx1; y0 = ny0; y1 = ny1;
-        }
         rect[4 * g] = x0; rect[4 * g + 1] = y0; rect[4 * g + 2] = x1; rect[4 * g + 3] = y1;
         tiles_touched[g] = tiles;
         flags[g] = 2;
@@ -453,7 +431,7 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
 /* Pair emission (Sec. 2.1): Gaussians in index order, tile rows outer,       */
 /* columns inner.  key = tile << 32 | bits(float32 depth), value = index.    */
 /* Rule 0 emits the whole rectangle; rule 1 each row's ellipse span, from    */
-/* the same record values the preprocess tested.                             */
+/* the float32 record values the renderer blends.                            */
 /* ------------------------------------------------------------------------ */
 int64_t orc_emit(int64_t n, const int32_t *rect, const int64_t *tiles_touched, const float *depth_f32,
                  int width, int extent_rule, const double *mean2d, const double *quad,
