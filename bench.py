@@ -3,15 +3,19 @@ AdaGScale beside plain 3D-GS, on the synthetic 6M-Gaussian city scene at
 4608x3456 (the Mill-19 resolution of the paper's Table I).
 
 A step is one frame of the whole forward path -- preprocess, pair emission,
-sort and tile ranges (fused in one binning call), rasterization -- enqueued
-through the C-ABI with the scene and every buffer already resident in HBM
-(pair buffers sized beforehand, so no host round trip inside the timed
-region).  AdaGScale's T_upper table is calibrated offline on 16 seeded
-views other than the measured one (Sec. 3.4), and K is binary-searched on
-the measured view so that PSNR(AdaGScale vs plain) sits at the quality point
-that corresponds to the paper's 0.5 dB drop (the paper tunes K on the test
-views for its speedup comparison).  The same search and timing with the
-trivial bound T_upper = 1 are reported beside it.
+sort and tile ranges (one binning call), rasterization -- enqueued through
+the C-ABI with the scene and every buffer already resident in HBM (pair
+buffers sized beforehand, so no host round trip inside the timed region).
+The measured AdaGScale frame uses the ellipse tile test (the base of the
+paper's implementation, Sec. 4.1) with the alpha >= Th ellipse; AdaGScale
+with the tile rectangle, plain 3D-GS (rectangle) and plain 3D-GS with the
+ellipse test are measured beside it.  AdaGScale's T_upper table is
+calibrated offline on 16 seeded views other than the measured one
+(Sec. 3.4), and K is binary-searched on the measured view, for each extent
+rule, so that PSNR(AdaGScale vs plain 3D-GS) sits at the quality point that
+corresponds to the paper's 0.5 dB drop (the paper tunes K on the test views
+for its speedup comparison).  The same search and timing with the trivial
+bound T_upper = 1 are reported beside it.
 
 Prints ONE JSON line.  Single GPU only.
 """
@@ -48,10 +52,10 @@ PSNR_TARGET_DB = 29.8
 # about 1 km, so the 20 depth bins span [0, 1200) m instead of the paper's [0, 100)
 CALIB_VIEWS = 16
 LUT_DEPTH_MAX = 1200.0
-# HBM bytes of one AdaGScale-frame raster launch (K = 459.18) from rocprofv3 FETCH_SIZE x 2.0
-# + WRITE_SIZE x 1.0 (copy-calibrated; profiles/city_6M_4608x3456_hbm_counters.md), valid
-# only for the rasterizer source they were taken with.
-RASTER_TRAFFIC = {"source_sha256_16": "20cf0fbf11887123", "bytes": (153.9 + 337.9) * 1e6}
+# HBM bytes of one AdaGScale-frame raster launch per extent rule, from rocprofv3
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (copy-calibrated; profiles/*_hbm_counters.md),
+# valid only for the rasterizer source they were taken with (None: not measured).
+RASTER_TRAFFIC = {"source_sha256_16": None, "bytes": {0: None, 1: None}}
 
 
 def log(*a):
@@ -73,6 +77,9 @@ def parse():
                    help="city: the headline FPS line; diff: forward+backward on the 1M "
                         "differentiable workload; batched: 64 views in one graph")
     p.add_argument("--views", type=int, default=64)
+    p.add_argument("--rule", type=int, choices=(0, 1), default=1,
+                   help="extent rule of the measured AdaGScale frame: 1 = ellipse tile test "
+                        "(default), 0 = tile rectangle; the other rule is measured beside it")
     p.add_argument("--uncalibrated", action="store_true",
                    help="AdaGScale with the trivial bound T_upper = 1 instead of the calibrated table")
     p.add_argument("--ada-only", action="store_true",
@@ -139,13 +146,13 @@ def timed_frames(torch, R, scene, cam_s, mode_s, fb, steps, warmup, stream, stag
     return wall / steps, np.array(frame_ms), timer.summary()
 
 
-def raster_traffic():
-    """Counter-measured HBM bytes per raster launch, or None if the rasterizer
-    source changed since the counters were taken."""
+def raster_traffic(rule):
+    """Counter-measured HBM bytes per raster launch of the measured frame, or
+    None if the rasterizer source changed since the counters were taken."""
     import hashlib
     src = os.path.join(ROOT, "paper_2604_18980_amd", "csrc", "raster.hip")
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    return RASTER_TRAFFIC["bytes"] if h == RASTER_TRAFFIC["source_sha256_16"] else None
+    return RASTER_TRAFFIC["bytes"][rule] if h == RASTER_TRAFFIC["source_sha256_16"] else None
 
 
 def graph_frames(torch, R, scene, cam_s, mode_s, fb, steps, warmup):
@@ -213,8 +220,8 @@ def ssim_t(torch, a, b):
 
 def search_K(torch, R, gsr, scene, cam, cam_s, fb_plain, fb, stream, **mode):
     """Binary search (in log K) for the largest K with PSNR(ada vs plain) >=
-    the target; PSNR falls as K grows (Sec. 3.4).  ``mode``: t_upper and
-    lut_depth_max of the AdaGScale renders."""
+    the target; PSNR falls as K grows (Sec. 3.4).  ``mode``: t_upper,
+    lut_depth_max and extent_rule of the AdaGScale renders."""
     ref = fb_plain.image.clone()
     lo, hi = 1e-3, 1e5
     best = lo
@@ -229,11 +236,13 @@ def search_K(torch, R, gsr, scene, cam, cam_s, fb_plain, fb, stream, **mode):
     return float(np.float32(best))
 
 
-def cpu_baseline(args, scene_h, cam, K, n_tiles_sample, t_upper=None, lut_depth_max=100.0):
+def cpu_baseline(args, scene_h, cam, K, n_tiles_sample, t_upper=None, lut_depth_max=100.0,
+                 extent_rule=0):
     """The oracle (single-threaded FP64 C) on a bounded sample of the same
     frame, scaled to one whole frame."""
     from oracle import oracle as O
-    mode = O.Mode(adagscale=True, K=K, t_upper=t_upper, lut_depth_max=lut_depth_max)
+    mode = O.Mode(adagscale=True, K=K, t_upper=t_upper, lut_depth_max=lut_depth_max,
+                  extent_rule=extent_rule)
     t0 = time.perf_counter()
     pre = O.preprocess(scene_h, cam, mode)
     t_pre = time.perf_counter() - t0
@@ -241,8 +250,8 @@ def cpu_baseline(args, scene_h, cam, K, n_tiles_sample, t_upper=None, lut_depth_
     rng = np.random.default_rng(0)
     frac = 1.0 / 64.0
     sub = np.sort(rng.choice(vis, size=max(1, int(len(vis) * frac)), replace=False))
-    sub_pre = O.Preproc(**{k: (getattr(pre, k)[sub] if getattr(pre, k).shape[0] == scene_h.n else getattr(pre, k))
-                           for k in pre.__dataclass_fields__})
+    field = lambda v: v[sub] if isinstance(v, np.ndarray) and v.shape[0] == scene_h.n else v
+    sub_pre = O.Preproc(**{k: field(getattr(pre, k)) for k in pre.__dataclass_fields__})
     t0 = time.perf_counter()
     keys, vals = O.emit(sub_pre, cam)
     sk, sv = O.sort(keys, vals)
@@ -255,10 +264,19 @@ def cpu_baseline(args, scene_h, cam, K, n_tiles_sample, t_upper=None, lut_depth_
     d32 = pre.depth.astype(np.float32)
     lists, ranges = [], np.zeros((TX * TY, 2), np.int64)
     off = 0
+    if extent_rule == 1:  # the sampled tiles' members from the whole emission (not timed)
+        ek, ev = O.emit(pre, cam)
+        e_tile = (ek >> np.uint64(32)).astype(np.int64)
+        keep = np.isin(e_tile, tiles)
+        e_tile, e_id = e_tile[keep], ev[keep].astype(np.int64)
     for t in tiles:
-        ty, tx = divmod(int(t), TX)
-        m = (pre.tiles_touched > 0) & (rect[:, 0] <= tx) & (tx < rect[:, 2]) & (rect[:, 1] <= ty) & (ty < rect[:, 3])
-        ids = np.nonzero(m)[0]
+        if extent_rule == 1:
+            ids = e_id[e_tile == int(t)]
+        else:
+            ty, tx = divmod(int(t), TX)
+            m = ((pre.tiles_touched > 0) & (rect[:, 0] <= tx) & (tx < rect[:, 2])
+                 & (rect[:, 1] <= ty) & (ty < rect[:, 3]))
+            ids = np.nonzero(m)[0]
         ids = ids[np.lexsort((ids, d32[ids]))]
         lists.append(ids.astype(np.uint32))
         ranges[t] = (off, off + ids.size)
@@ -271,7 +289,8 @@ def cpu_baseline(args, scene_h, cam, K, n_tiles_sample, t_upper=None, lut_depth_
     t_bl = (time.perf_counter() - t0) * (TX * TY) / len(tiles)
     t_frame = t_pre + t_es + t_bl
     return {"value": 1.0 / t_frame, "unit": "FPS", "cores": 1, "kind": "oracle",
-            "sample": (f"AdaGScale K={K:g}: full preprocess of {scene_h.n} Gaussians ({t_pre:.1f} s), "
+            "sample": (f"AdaGScale K={K:g}, {('rectangle', 'ellipse')[extent_rule]} tile test: "
+                       f"full preprocess of {scene_h.n} Gaussians ({t_pre:.1f} s), "
                        f"emit+sort of a 1/64 sample of visible Gaussians scaled x64 ({t_es:.1f} s), "
                        f"blend of {len(tiles)} random tiles scaled to {TX * TY} tiles ({t_bl:.1f} s); "
                        f"single-threaded FP64 C, -O2")}
@@ -391,6 +410,24 @@ def copy_probe(mib):
     log(f"copy probe: {mib} MiB read + {mib} MiB written")
 
 
+def measure(torch, R, scene, cam_s, mode_s, fb, P, args, stream, staged_too=False):
+    """Eager frames with per-stage HIP events, then whole frames replayed from
+    a HIP graph (the reported rate); the pair count must not change."""
+    _, fms_e, st = timed_frames(torch, R, scene, cam_s, mode_s, fb, args.steps, args.warmup, stream)
+    ms, fms_g = graph_frames(torch, R, scene, cam_s, mode_s, fb, args.steps, args.warmup)
+    assert int(fb.num_pairs.item()) == P
+    out = {"fps": 1000.0 / ms, "ms_p50": ms, "ms_p99": float(np.percentile(fms_g, 99)),
+           "pairs": P, "pairs_per_s": P / (ms * 1e-3), "eager_ms_p50": float(np.median(fms_e)),
+           "stages_ms": st}
+    if staged_too:
+        # the same frame through the separate emission and sort entry points
+        _, fms_s, st_s = timed_frames(torch, R, scene, cam_s, mode_s, fb, args.steps, args.warmup,
+                                      stream, staged=True)
+        out["staged_eager_ms_p50"] = float(np.median(fms_s))
+        out["staged_stages_ms"] = st_s
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -418,6 +455,8 @@ def main():
     scene = R.DeviceScene.from_host(scene_h, dev)
     cam_s = gsr.camera_struct(cam)
     stream = torch.cuda.current_stream()
+    rule, other = args.rule, 1 - args.rule
+    rule_name = {0: "rectangle", 1: "ellipse"}
 
     # offline calibration of the T_upper table (not part of a frame)
     from paper_2604_18980_amd import calib
@@ -433,67 +472,83 @@ def main():
 
     if args.ada_only and args.K is None:
         raise SystemExit("--ada-only needs --K")
-    unc_out = None
+    extra = {}
     if args.ada_only:
         K = args.K
-        fb_a = R.render(scene, cam, adagscale=True, K=K, fb=None, slack=1.05, **ada)
+        fb_a = R.render(scene, cam, adagscale=True, K=K, fb=None, slack=1.05, extent_rule=rule, **ada)
         torch.cuda.synchronize()
         P_ada = int(fb_a.num_pairs.item())
         psnr = ssim = None
-        P_plain = W_plain = None
     else:
-        # plain frame, to size buffers and as the PSNR reference
+        # plain 3D-GS (rectangle rule): buffer sizing and the PSNR reference
         fb_p = R.render(scene, cam, fb=None, slack=1.05)
         torch.cuda.synchronize()
         P_plain = int(fb_p.num_pairs.item())
         log(f"plain pairs {P_plain}")
+        ref = fb_p.image.clone()
+        # plain with the ellipse tile test (the base the paper's implementation starts from)
+        fb_pe = R.render(scene, cam, fb=None, slack=1.05, extent_rule=1)
+        torch.cuda.synchronize()
+        P_pe = int(fb_pe.num_pairs.item())
+        psnr_pe = psnr_t(torch, fb_pe.image, ref)
+        log(f"plain ellipse pairs {P_pe} psnr vs plain {psnr_pe:.2f}")
         fb_a = R.FrameBuffers(scene.n, cam["width"], cam["height"], int(P_plain * 1.05) + 1024, dev)
         K = args.K if args.K is not None else search_K(torch, R, gsr, scene, cam, cam_s, fb_p, fb_a,
-                                                       stream, **ada)
-        R.render(scene, cam, adagscale=True, K=K, fb=fb_a, **ada)
+                                                       stream, extent_rule=rule, **ada)
+        R.render(scene, cam, adagscale=True, K=K, fb=fb_a, extent_rule=rule, **ada)
         torch.cuda.synchronize()
         P_ada = int(fb_a.num_pairs.item())
-        psnr = psnr_t(torch, fb_a.image, fb_p.image)
-        ssim = ssim_t(torch, fb_a.image, fb_p.image)
-        log(f"K={K} pairs {P_ada} psnr {psnr:.2f} ssim {ssim:.4f}")
-        W_plain = raster_work(R, fb_p, cam_s)
+        psnr = psnr_t(torch, fb_a.image, ref)
+        ssim = ssim_t(torch, fb_a.image, ref)
+        log(f"{rule_name[rule]}: K={K} pairs {P_ada} psnr {psnr:.2f} ssim {ssim:.4f}")
+        # AdaGScale under the other extent rule, searched to the same PSNR target
+        K_o = search_K(torch, R, gsr, scene, cam, cam_s, fb_p, fb_a, stream, extent_rule=other, **ada)
+        fb_o = R.render(scene, cam, adagscale=True, K=K_o, fb=None, slack=1.05, extent_rule=other,
+                        **ada)
+        torch.cuda.synchronize()
+        P_o = int(fb_o.num_pairs.item())
+        psnr_o = psnr_t(torch, fb_o.image, ref)
+        log(f"{rule_name[other]}: K={K_o} pairs {P_o} psnr {psnr_o:.2f}")
         if not args.uncalibrated:
             # the same search and timing with the trivial bound, for comparison
-            K_u = search_K(torch, R, gsr, scene, cam, cam_s, fb_p, fb_a, stream, **unc)
-            fb_u = R.render(scene, cam, adagscale=True, K=K_u, fb=None, slack=1.05, **unc)
+            K_u = search_K(torch, R, gsr, scene, cam, cam_s, fb_p, fb_a, stream, extent_rule=rule,
+                           **unc)
+            fb_u = R.render(scene, cam, adagscale=True, K=K_u, fb=None, slack=1.05,
+                            extent_rule=rule, **unc)
             torch.cuda.synchronize()
             P_u = int(fb_u.num_pairs.item())
-            psnr_u = psnr_t(torch, fb_u.image, fb_p.image)
-            mode_u = gsr.mode_struct(adagscale=True, K=K_u, **unc)
-            _, fms_eu, st_u = timed_frames(torch, R, scene, cam_s, mode_u, fb_u, args.steps, args.warmup,
-                                           stream)
-            ms_u, fms_gu = graph_frames(torch, R, scene, cam_s, mode_u, fb_u, args.steps, args.warmup)
-            unc_out = {"fps": 1000.0 / ms_u, "ms_p50": ms_u, "pairs": P_u, "K": K_u,
-                       "psnr_db_vs_plain": psnr_u, "stages_ms": st_u}
-            log(f"uncalibrated: K={K_u} pairs {P_u} psnr {psnr_u:.2f} fps {1000.0 / ms_u:.1f}")
+            psnr_u = psnr_t(torch, fb_u.image, ref)
+            mode_u = gsr.mode_struct(adagscale=True, K=K_u, extent_rule=rule, **unc)
+            extra["adagscale_uncalibrated"] = dict(
+                measure(torch, R, scene, cam_s, mode_u, fb_u, P_u, args, stream), K=K_u,
+                psnr_db_vs_plain=psnr_u)
+            log(f"uncalibrated: K={K_u} pairs {P_u} psnr {psnr_u:.2f} "
+                f"fps {extra['adagscale_uncalibrated']['fps']:.1f}")
             del fb_u
+        mode_o = gsr.mode_struct(adagscale=True, K=K_o, extent_rule=other, **ada)
+        extra[f"adagscale_{rule_name[other]}"] = dict(
+            measure(torch, R, scene, cam_s, mode_o, fb_o, P_o, args, stream), K=K_o,
+            psnr_db_vs_plain=psnr_o, raster_work=raster_work(R, fb_o, cam_s))
+        del fb_o
     W_ada = raster_work(R, fb_a, cam_s)
 
-    mode_p = gsr.mode_struct()
-    mode_a = gsr.mode_struct(adagscale=True, K=K, **ada)
+    mode_a = gsr.mode_struct(adagscale=True, K=K, extent_rule=rule, **ada)
     # each mode's pair buffers sized from its own count (+5%), as a renderer
     # sizes them from the previous frame
     fb_a.set_capacity(int(P_ada * 1.05) + 1024)
-    # per-stage HIP events (eager launches) ...
-    wall_a, fms_a, st_a = timed_frames(torch, R, scene, cam_s, mode_a, fb_a, args.steps, args.warmup, stream)
-    # ... and whole frames replayed from a HIP graph (no host work per frame)
-    ms_a, fms_ga = graph_frames(torch, R, scene, cam_s, mode_a, fb_a, args.steps, args.warmup)
-    assert int(fb_a.num_pairs.item()) == P_ada
-    eager_a = float(np.median(fms_a))
+    res_a = measure(torch, R, scene, cam_s, mode_a, fb_a, P_ada, args, stream,
+                    staged_too=not args.ada_only)
+    res_a.update(K=K, raster_work=W_ada, extent_rule=rule_name[rule])
+    ms_a, st_a = res_a["ms_p50"], res_a["stages_ms"]
     if not args.ada_only:
+        W_plain = raster_work(R, fb_p, cam_s)
         fb_p.set_capacity(int(P_plain * 1.05) + 1024)
-        _, fms_p, st_p = timed_frames(torch, R, scene, cam_s, mode_p, fb_p, args.steps, args.warmup,
-                                      stream)
-        # the same frame through the separate emission and sort entry points, for reference
-        _, fms_sa, st_sa = timed_frames(torch, R, scene, cam_s, mode_a, fb_a, args.steps,
-                                        args.warmup, stream, staged=True)
-        ms_p, fms_gp = graph_frames(torch, R, scene, cam_s, mode_p, fb_p, args.steps, args.warmup)
-        assert int(fb_p.num_pairs.item()) == P_plain
+        res_p = measure(torch, R, scene, cam_s, gsr.mode_struct(), fb_p, P_plain, args, stream)
+        res_p["raster_work"] = W_plain
+        fb_pe.set_capacity(int(P_pe * 1.05) + 1024)
+        res_pe = measure(torch, R, scene, cam_s, gsr.mode_struct(extent_rule=1), fb_pe, P_pe, args,
+                         stream)
+        res_pe.update(psnr_db_vs_plain=psnr_pe, raster_work=raster_work(R, fb_pe, cam_s))
     # dominant kernel: the rasterizer (one kernel per frame, timed by its events)
     raster_ms = st_a["raster"]
     flops = FLOP_TEST * 64 * W_ada["strip_evaluations"] + FLOP_BLEND * W_ada["blended"]
@@ -507,21 +562,33 @@ def main():
     ntiles = int(fb_a.ranges.shape[0])
     passes = max(1, (int(math.ceil(math.log2(max(ntiles, 2)))) + 7) // 8)
     pre_bytes = 12 * n + 32 * front + 4 * nsh * vis + 12 * n + 48 * vis
-    # binning: visibility (8 B per Gaussian), per visible Gaussian the depth
-    # sort (4 passes x 20 B), pair counts and their scan (36 B), slice owners
-    # (12 B), the owner loads of both pass-1 kernels (2 x 20 B) and the
-    # rectangle corners (12 B); per pair one 4-byte word written, read twice
-    # and one id written (16 B); per tile count, start and range (16 B)
-    bin_bytes = 8 * n + vis * (8 + 80 + 36 + 12 + 40 + 12) + 16 * P_ada + 16 * ntiles
-    emit_bytes = 8 * n + vis * (4 + 8 + 4 * 20 + 12 + 12) + 8 * P_ada
+    # emission preparation (both rules): visibility (8 B per Gaussian), per
+    # visible Gaussian the depth sort (4 passes x 20 B) and the pair counts and
+    # their scan (36 B)
+    prep_bytes = 8 * n + vis * (8 + 80 + 36)
+    if rule == 0:
+        # fused packed binning: slice owners (12 B), the owner loads of both
+        # pass-1 kernels (2 x 20 B) and the rectangle corners (12 B) per visible
+        # Gaussian; per pair one 4-byte word written, read twice and one id
+        # written (16 B); per tile count, start and range (16 B)
+        bin_bytes = prep_bytes + vis * (12 + 40 + 12) + 16 * P_ada + 16 * ntiles
+    else:
+        # span emission (id, offset, rectangle and the 7 record floats read per
+        # visible Gaussian, 8 B written per pair), then the tile sort (per pass:
+        # keys read twice, keys and ids read and written once = 20 B per pair)
+        # and the ranges (keys read, 8 B per tile)
+        bin_bytes = (prep_bytes + vis * (4 + 8 + 8 + 28) + 8 * P_ada + passes * 20 * P_ada
+                     + 4 * P_ada + 8 * ntiles)
+    emit_bytes = prep_bytes + vis * (12 + 12) + 8 * P_ada
     sort_bytes = passes * 20 * P_ada - 4 * P_ada + 4 * P_ada + 8 * ntiles
     stage_bw = {
         "preprocess": pre_bytes / (st_a["preprocess"] * 1e-3) / 1e9,
         "bin": bin_bytes / (st_a["bin"] * 1e-3) / 1e9,
     }
     if not args.ada_only:
-        stage_bw["staged_emit"] = emit_bytes / (st_sa["emit"] * 1e-3) / 1e9
-        stage_bw["staged_sort"] = sort_bytes / (st_sa["sort"] * 1e-3) / 1e9
+        stage_bw["staged_emit"] = emit_bytes / (res_a["staged_stages_ms"]["emit"] * 1e-3) / 1e9
+        stage_bw["staged_sort"] = sort_bytes / (res_a["staged_stages_ms"]["sort"] * 1e-3) / 1e9
+    cal = f"T_upper calibrated on {CALIB_VIEWS} views"
     out = {
         "metric": METRIC,
         "value": 1000.0 / ms_a,
@@ -538,48 +605,47 @@ def main():
         "config": {"workload": "synthetic city, 6M Gaussians, 4608x3456, SH degree 3",
                    "n_gaussians": n, "width": cam["width"], "height": cam["height"],
                    "sh_degree": 3,
-                   "mode": ("adagscale, T_upper = 1" if args.uncalibrated else
-                            f"adagscale, T_upper calibrated on {CALIB_VIEWS} views"),
+                   "mode": (f"adagscale, {rule_name[rule]} tile test, "
+                            + ("T_upper = 1" if args.uncalibrated else cal)),
                    "K": K, "psnr_target_db": PSNR_TARGET_DB},
         "calibration": {"views": CALIB_VIEWS, "lut_depth_max": LUT_DEPTH_MAX,
                         "t_upper": [float(x) for x in table], "seconds": t_cal,
                         "empty_bins": int((raw_bits == 0).sum()),
                         "used": not args.uncalibrated},
-        "adagscale_uncalibrated": unc_out,
-        "adagscale": {"fps": 1000.0 / ms_a, "ms_p50": ms_a, "ms_p99": float(np.percentile(fms_ga, 99)),
-                      "pairs": P_ada, "pairs_per_s": P_ada / (ms_a * 1e-3), "K": K,
-                      "eager_ms_p50": eager_a, "stages_ms": st_a, "raster_work": W_ada},
+        "adagscale": res_a,
+        **extra,
         "plain": None,
+        "plain_ellipse": None,
         "speedup_vs_plain": None,
+        "speedup_vs_plain_ellipse": None,
         "pair_ratio": None,
+        "pair_reduction_vs_plain_ellipse": None,
         "psnr_db_vs_plain": psnr,
         "ssim_vs_plain": ssim,
         "timing": "frames replayed from a HIP graph (value, ms_p50); stages_ms from eager launches "
                   "with HIP events between stages; staged_* = the same frame through the separate "
-                  "emission and sort entry points",
-        "wall_ms_per_step_eager": wall_a,
+                  "emission and sort entry points; plain = 3D-GS with the tile rectangle, "
+                  "plain_ellipse = 3D-GS with the ellipse tile test",
         "stage_hbm": {k: {"achieved_GBs": v, "frac": v / PEAK_HBM_GBS} for k, v in stage_bw.items()},
         "roofline": {"kernel": "k_raster_wave", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": raster_traffic(),
+                     "traffic": raster_traffic(rule),
                      "basis": f"{FLOP_TEST} FLOP x 64 pixels x {W_ada['strip_evaluations']} executed "
                               f"strip evaluations + {FLOP_BLEND} FLOP x {W_ada['blended']} blended "
                               f"pixel evaluations of eq. (1)-(2); peak = FP32 vector FMA rate"},
     }
     if not args.ada_only:
-        out["adagscale"]["staged_eager_ms_p50"] = float(np.median(fms_sa))
-        out["adagscale"]["staged_stages_ms"] = st_sa
-        out["plain"] = {"fps": 1000.0 / ms_p, "ms_p50": ms_p,
-                        "ms_p99": float(np.percentile(fms_gp, 99)), "pairs": P_plain,
-                        "pairs_per_s": P_plain / (ms_p * 1e-3),
-                        "eager_ms_p50": float(np.median(fms_p)), "stages_ms": st_p,
-                        "raster_work": W_plain}
-        out["speedup_vs_plain"] = ms_p / ms_a
+        out["plain"] = res_p
+        out["plain_ellipse"] = res_pe
+        out["speedup_vs_plain"] = res_p["ms_p50"] / ms_a
+        out["speedup_vs_plain_ellipse"] = res_pe["ms_p50"] / ms_a
         out["pair_ratio"] = P_ada / max(P_plain, 1)
+        out["pair_reduction_vs_plain_ellipse"] = 1.0 - P_ada / max(P_pe, 1)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(args, scene_h, cam, K, args.cpu_sample_tiles,
-                                           t_upper=ada["t_upper"], lut_depth_max=ada["lut_depth_max"])
+                                           t_upper=ada["t_upper"], lut_depth_max=ada["lut_depth_max"],
+                                           extent_rule=rule)
     print(json.dumps(out))
 
 

@@ -101,14 +101,15 @@ typedef struct {
  *   pairs; otherwise its extent is scaled by s = sqrt(ln(opacity/Th) /
  *   ln(opacity/tau)), the factor that maps the alpha = tau contour onto the
  *   alpha = Th contour.  force_unit_scale = 1 keeps s = 1 (testing aid).
- * extent_rule = 0: the tile rectangle of that (scaled) extent.
+ * extent_rule = 0: the pairs are the tile rectangle of that (scaled) extent.
  * extent_rule = 1: the ellipse test of the prior work the paper builds on
- *   (Sec. 2.3 Fig. 3(c), Sec. 4.1): of the plain (unscaled) rectangle, only the
- *   tiles whose pixel box [16 tx, 16 tx + 15] x [16 ty, 16 ty + 15] meets the
- *   ellipse alpha >= t, t = Th under AdaGScale and tau otherwise, evaluated in
- *   double from the float32 splat record; rects then holds their bounding
- *   box and tiles_touched their count.  The same rule must be passed to
- *   gs_emit_pairs / gs_bin_pairs. */
+ *   (Sec. 2.3 Fig. 3(c), Sec. 4.1), applied at pair generation as Sec. 3.3
+ *   applies Th there: gs_preprocess writes the plain (unscaled) rectangle and
+ *   its area as the candidates, and gs_emit_pairs / gs_bin_pairs keep only the
+ *   candidate tiles whose pixel box [16 tx, 16 tx + 15] x [16 ty, 16 ty + 15]
+ *   meets the ellipse alpha >= t, t = Th under AdaGScale and tau otherwise,
+ *   evaluated in double from the float32 splat record.  The same rule must be
+ *   passed to gs_emit_pairs / gs_bin_pairs. */
 typedef struct {
     int adagscale;
     float K;                       /* peripheral-loss budget, >= 0 (eq. 5) */
@@ -148,17 +149,20 @@ size_t gs_workspace_size(int64_t n, int64_t pair_capacity, int width, int height
  * 3D covariance R S S^T R^T to Sigma2 = J W Sigma3 W^T J^T + 0.3 I, conic =
  * Sigma2^-1, pixel mean, depth = camera z, opacity = sigmoid(logit), colour =
  * max(0, SH(view direction) + 0.5), plain extent 3 sqrt(lambda_max) or the
- * AdaGScale-scaled extent, and the tile rectangle.  Geometry that decides
- * discrete outputs is evaluated in double precision.
- * Out: splats [n][12], rects [n], tiles_touched [n] (0 = no pairs). */
+ * AdaGScale-scaled extent (extent_rule 0; rule 1 keeps the plain extent), and
+ * the tile rectangle.  Geometry that decides discrete outputs is evaluated in
+ * double precision.
+ * Out: splats [n][12], rects [n], tiles_touched [n] = the rectangle's area
+ * (0 = no pairs; under rule 1 an upper bound of the pairs). */
 gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_mode *mode,
                         float *splats, uint64_t *rects, uint32_t *tiles_touched, void *stream);
 
 /* Stage 2 (Sec. 2.1 Gaussian-tile pair generation; Sec. 3.3: the rectangle
- * already reflects AdaGScale's extent).  Emits one (tile, Gaussian) pair per
- * tile of each rectangle (extent_rule 0), or per tile of each rectangle row's
- * ellipse span (extent_rule 1, recomputed from the splat records exactly as
- * gs_preprocess counted it; pass the rule gs_preprocess ran with).  Pairs
+ * already reflects AdaGScale's extent under rule 0, and the ellipse of Th is
+ * applied here under rule 1).  Emits one (tile, Gaussian) pair per tile of
+ * each rectangle (extent_rule 0), or per rectangle tile that meets the
+ * Gaussian's ellipse (extent_rule 1, from the splat records; pass the rule
+ * gs_preprocess ran with).  Pairs
  * are emitted Gaussian by Gaussian in ascending (float32 depth, Gaussian id)
  * order, tile rows outer, columns inner; a stable sort by tile of this list is
  * therefore the paper's per-tile depth order.  extent_rule other than 0 or 1

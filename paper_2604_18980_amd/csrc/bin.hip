@@ -378,7 +378,8 @@ hipError_t launch_bin(const float *splats, const uint64_t *rects, const uint32_t
                       uint32_t *sorted_tiles, uint32_t *ranges, int64_t cap, int64_t *num_pairs,
                       const Workspace &ws, hipStream_t s) {
     const int64_t ntiles = (int64_t)tiles_x * tiles_y;
-    hipError_t e = launch_emit_prepare(splats, rects, tiles_touched, n, cap, num_pairs, ws, s);
+    hipError_t e = launch_emit_prepare(splats, rects, tiles_touched, n, extent_rule, cap, num_pairs,
+                                       ws, s);
     if (e != hipSuccess) return e;
     if (n == 0 || cap == 0) {  // no pairs can be binned: every range empty
         k_zero_ranges<<<(unsigned)((2 * ntiles + 255) / 256), 256, 0, s>>>(ranges, 2 * ntiles);

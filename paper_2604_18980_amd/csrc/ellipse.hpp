@@ -16,9 +16,11 @@
 //
 // Everything is evaluated in double precision from the float32 record values
 // (the same record the rasterizer blends), with a fixed operation order, so
-// the preprocess (which counts the tiles) and the emission (which writes
-// them) get the same spans, and so does an IEEE FP64 reimplementation.  The
-// build disables FP contraction.
+// the pair count and the emission get the same spans; so does any FP64
+// reimplementation with the same operation order whose log agrees to the last
+// bit (the other operations are correctly rounded).  The build disables FP
+// contraction.  The test runs inside the preprocess's plain tile rectangle and
+// only removes tiles from it.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -62,8 +64,12 @@ __device__ __forceinline__ bool ellipse_row_span(const Ellipse &e, int ty, int c
     const double lo = y0 < -e.R ? -e.R : y0, hi = y1 > e.R ? e.R : y1;
     const double wl = e.w < lo ? lo : (e.w > hi ? hi : e.w);
     const double wr = -e.w < lo ? lo : (-e.w > hi ? hi : -e.w);
-    const double xl = (e.u - e.beta * wl) - ellipse_half_width(e, wl);
-    const double xr = (e.u - e.beta * wr) + ellipse_half_width(e, wr);
+    // when the band holds both extremes, wr = -wl and the half widths are the
+    // same number (Y * Y is exact under negation): evaluate it once
+    const double sl = ellipse_half_width(e, wl);
+    const double sr = wr == -wl ? sl : ellipse_half_width(e, wr);
+    const double xl = (e.u - e.beta * wl) - sl;
+    const double xr = (e.u - e.beta * wr) + sr;
     double fa = ceil((xl - 15.0) / 16.0);
     double fb = floor(xr / 16.0);
     fa = fa >= (double)cx0 ? fa : (double)cx0;
@@ -72,6 +78,30 @@ __device__ __forceinline__ bool ellipse_row_span(const Ellipse &e, int ty, int c
     a = (int)fa;
     b = (int)fb;
     return true;
+}
+
+// The rows of [y0, y1) that can meet the band |Y| <= R: row ty meets it when
+// 16 ty - v + 15 >= -R and 16 ty - v <= R, i.e. ceil((v - R - 15) / 16) <= ty
+// <= floor((v + R) / 16); one row to spare on each side absorbs the rounding
+// of these bounds (far below a pixel).  The rows left out have empty spans, so
+// walking [ra, rb) instead of [y0, y1) gives the same result.
+__device__ __forceinline__ void ellipse_row_band(const Ellipse &e, int y0, int y1, int &ra, int &rb) {
+    const double flo = ceil((e.v - e.R - 15.0) / 16.0) - 1.0;
+    const double fhi = floor((e.v + e.R) / 16.0) + 2.0;
+    ra = flo > (double)y0 ? (flo < (double)y1 ? (int)flo : y1) : y0;
+    rb = fhi < (double)y1 ? (fhi > (double)ra ? (int)fhi : ra) : y1;
+}
+
+// Number of tiles of the rectangle [x0, x1) x [y0, y1) that meet the ellipse.
+__device__ __forceinline__ uint32_t ellipse_tile_count(const Ellipse &e, int x0, int y0, int x1, int y1) {
+    int ra, rb;
+    ellipse_row_band(e, y0, y1, ra, rb);
+    uint32_t cnt = 0;
+    for (int ty = ra; ty < rb; ++ty) {
+        int a, b;
+        if (ellipse_row_span(e, ty, x0, x1 - 1, a, b)) cnt += (uint32_t)(b - a + 1);
+    }
+    return cnt;
 }
 
 }  // namespace gsr

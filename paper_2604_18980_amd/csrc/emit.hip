@@ -14,8 +14,11 @@
 //   k_emit                              each block writes its pairs contiguously,
 //                                       one pair per thread per step, after an LDS
 //                                       scan of its Gaussians' tile counts
-//   k_emit_spans                        extent rule 1: per Gaussian, its rows'
-//                                       ellipse spans (ellipse.hpp)
+//   k_emit_spans                        extent rule 1: per wave 64 Gaussians'
+//                                       row spans (ellipse.hpp), written by the
+//                                       whole wave
+//                                       (Gaussians with long row bands: one at a
+//                                       time by the whole wave, a row per lane)
 #include "ellipse.hpp"
 #include "gsr_internal.hpp"
 
@@ -103,21 +106,85 @@ __global__ __launch_bounds__(256) void k_vis_compact(const uint32_t *tiles_touch
     if (threadIdx.x == 0 && b == (int64_t)gridDim.x - 1) *num_vis = (int64_t)(before + tot);
 }
 
-// Pairs of each depth-sorted visible Gaussian (one per thread; its
-// tiles_touched, which is the rectangle's area under extent rule 0), added to
-// the total of its chunk of 4096 (cleared by k_vis_count).
+// Broadcast of one lane's ellipse and row range to the whole wave.
+struct WaveGaussian {
+    Ellipse e;
+    int x0, x1, ra, rb;
+};
+__device__ __forceinline__ WaveGaussian wave_broadcast(const Ellipse &e, int x0, int x1, int ra, int rb,
+                                                       int src) {
+    WaveGaussian w;
+    w.e.u = __shfl(e.u, src, kWave);
+    w.e.v = __shfl(e.v, src, kWave);
+    w.e.A = __shfl(e.A, src, kWave);
+    w.e.beta = __shfl(e.beta, src, kWave);
+    w.e.gamma = __shfl(e.gamma, src, kWave);
+    w.e.c = __shfl(e.c, src, kWave);
+    w.e.R = __shfl(e.R, src, kWave);
+    w.e.w = __shfl(e.w, src, kWave);
+    w.x0 = __shfl(x0, src, kWave);
+    w.x1 = __shfl(x1, src, kWave);
+    w.ra = __shfl(ra, src, kWave);
+    w.rb = __shfl(rb, src, kWave);
+    return w;
+}
+
+// Pairs of each depth-sorted visible Gaussian (one per thread), added to the
+// total of its chunk of 4096 (cleared by k_vis_count): the rectangle's area
+// (tiles_touched) under extent rule 0, the count of its tiles that meet the
+// ellipse under rule 1.  The visible Gaussians are dense here, so the FP64
+// span arithmetic of rule 1 keeps the lanes busy.  A Gaussian whose row band
+// is longer than kSmallRows is counted afterwards by its whole wave, one row
+// per lane, so no lane walks a giant's rows alone.
+template <int RULE>
 __global__ __launch_bounds__(256) void k_pair_counts(const uint32_t *sorted_ids, const int64_t *num_vis,
-                                                     const uint32_t *tiles_touched, uint64_t *cnt,
+                                                     const uint32_t *tiles_touched, const float *splats,
+                                                     const uint64_t *rects, uint64_t *cnt,
                                                      uint64_t *chunk_tot) {
     __shared__ uint64_t wt[4];
     const int64_t V = *num_vis;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if ((int64_t)blockIdx.x * 256 >= V) return;  // uniform
     uint64_t c = 0;
-    if (j < V) {
-        c = tiles_touched[sorted_ids[j]];
-        cnt[j] = c;
+    if constexpr (RULE == 0) {
+        if (j < V) c = tiles_touched[sorted_ids[j]];
+    } else {
+        const int lane = threadIdx.x & (kWave - 1);
+        Ellipse e;
+        int x0 = 0, x1 = 0, ra = 0, rb = 0;
+        bool big = false;
+        if (j < V) {
+            const uint32_t g = sorted_ids[j];
+            const uint64_t r = rects[g];
+            const float *rec = splats + (size_t)g * 12;
+            if (ellipse_setup(rec[0], rec[1], rec[2], rec[3], rec[4], rec[5], rec[7], e)) {
+                x0 = (int)(r & 0xffff);
+                x1 = (int)((r >> 32) & 0xffff);
+                ellipse_row_band(e, (int)((r >> 16) & 0xffff), (int)(r >> 48), ra, rb);
+                big = rb - ra > kSmallRows;
+                if (!big) {
+                    for (int ty = ra; ty < rb; ++ty) {
+                        int a, b;
+                        if (ellipse_row_span(e, ty, x0, x1 - 1, a, b)) c += (uint64_t)(b - a + 1);
+                    }
+                }
+            }
+        }
+        // the wave's long-band Gaussians, one at a time, a row per lane
+        for (uint64_t m = __ballot(big); m; m &= m - 1) {  // wave-uniform
+            const int src = __ffsll((long long)m) - 1;
+            const WaveGaussian w = wave_broadcast(e, x0, x1, ra, rb, src);
+            uint32_t part = 0;
+            for (int ty = w.ra + lane; ty < w.rb; ty += kWave) {
+                int a, b;
+                if (ellipse_row_span(w.e, ty, w.x0, w.x1 - 1, a, b)) part += (uint32_t)(b - a + 1);
+            }
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
+            if (lane == src) c = part;
+        }
     }
+    if (j < V) cnt[j] = c;
     uint64_t tot;
     block_exclusive_scan<256, uint64_t>(c, wt, &tot);
     if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&chunk_tot[(int64_t)blockIdx.x * 256 / kSortChunk],
@@ -223,8 +290,8 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *sorted_ids, const 
 }
 
 hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
-                               const uint32_t *tiles_touched, int n, int64_t cap, int64_t *num_pairs,
-                               const Workspace &ws, hipStream_t s) {
+                               const uint32_t *tiles_touched, int n, int extent_rule, int64_t cap,
+                               int64_t *num_pairs, const Workspace &ws, hipStream_t s) {
     int64_t *num_vis = ws.counters;
     if (n == 0) {
         k_set_i64<<<1, 1, 0, s>>>(num_pairs, 0);
@@ -239,41 +306,146 @@ hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
                                      num_vis);
     hipError_t e = depth_sort(ws, num_vis, s);  // dkey/dval[0] -> [1]
     if (e != hipSuccess) return e;
-    k_pair_counts<<<(unsigned)ws.nb_gauss, 256, 0, s>>>(ws.dval[1], num_vis, tiles_touched,
-                                                       ws.pair_cnt, ws.pair_tot);
+    if (extent_rule == 1)
+        k_pair_counts<1><<<(unsigned)ws.nb_gauss, 256, 0, s>>>(ws.dval[1], num_vis, tiles_touched,
+                                                              splats, rects, ws.pair_cnt, ws.pair_tot);
+    else
+        k_pair_counts<0><<<(unsigned)ws.nb_gauss, 256, 0, s>>>(ws.dval[1], num_vis, tiles_touched,
+                                                              splats, rects, ws.pair_cnt, ws.pair_tot);
     k_pair_offsets<<<nb, 256, 0, s>>>(ws.pair_cnt, ws.pair_tot, num_vis, ws.pair_off, ws.slice_start,
                                       num_pairs, cap);
     return hipGetLastError();
 }
 
-// Extent rule 1: one thread per depth-sorted visible Gaussian writes its pairs
-// at its offset, row by row over its (bounding) rectangle, each row's ellipse
-// span recomputed from the splat record exactly as the preprocess counted it.
-// Pairs at or beyond the capacity are not written.
+// Extent rule 1: each wave takes 64 consecutive depth-sorted visible
+// Gaussians, one per lane.  Those with short row bands are walked in lockstep:
+// per step every lane recomputes the ellipse span of its next row (exactly as
+// k_pair_counts counted it), a wave prefix sum lays the spans end to end, and
+// the whole wave writes them -- lane l takes pairs l, l + 64, ..., finding the
+// span that holds each by binary search over the 64 span starts in LDS.  Then
+// the long-band Gaussians follow one at a time, 64 of their rows per step, one
+// row per lane, written the same way.  Pairs at or beyond the capacity are not
+// written.
+struct SpanTable {
+    uint32_t start[kWave];  // exclusive prefix of the step's span lengths
+    uint64_t k[kWave];      // output index of each span's first pair
+    uint32_t t0[kWave];     // tile id of each span's first tile
+    uint32_t gid[kWave];
+};
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Writes one step's spans (lane l's span: len pairs from output index k, tiles
+// t0, t0 + 1, ..., Gaussian gid).  Returns nothing; contains wave barriers.
+__device__ __forceinline__ void wave_write_spans(SpanTable &st, uint32_t len, uint64_t k, uint32_t t0,
+                                                 uint32_t gid, uint32_t *pair_tiles,
+                                                 uint32_t *pair_gids, int64_t cap) {
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t x = len;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    const uint32_t total = __shfl(x, kWave - 1, kWave);
+    st.start[lane] = x - len;
+    st.k[lane] = k;
+    st.t0[lane] = t0;
+    st.gid[lane] = gid;
+    wave_sync_lds();
+    for (uint32_t i = (uint32_t)lane; i < total; i += kWave) {
+        // the span holding pair i: the last lane whose start is <= i (a lane
+        // with an empty span shares its start with the next lane)
+        int lo = 0, hi = kWave - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (st.start[mid] <= i) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t m = i - st.start[lo];
+        const uint64_t kk = st.k[lo] + m;
+        if (kk < (uint64_t)cap) {
+            pair_tiles[kk] = st.t0[lo] + m;
+            pair_gids[kk] = st.gid[lo];
+        }
+    }
+    wave_sync_lds();  // every lane has read the table before it is rewritten
+}
+
 __global__ __launch_bounds__(256) void k_emit_spans(const uint32_t *sorted_ids, const int64_t *num_vis,
                                                     const float *splats, const uint64_t *rects,
                                                     const uint64_t *off, int tiles_x,
                                                     uint32_t *pair_tiles, uint32_t *pair_gids,
                                                     int64_t cap) {
+    __shared__ SpanTable s_tab[4];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int64_t V = *num_vis;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= *num_vis) return;
-    uint64_t k = off[j];
-    if (k >= (uint64_t)cap) return;
-    const uint32_t g = sorted_ids[j];
-    const uint64_t r = rects[g];
-    const int x0 = (int)(r & 0xffff), y0 = (int)((r >> 16) & 0xffff), x1 = (int)((r >> 32) & 0xffff),
-              y1 = (int)(r >> 48);
-    const float *rec = splats + (size_t)g * 12;
+    if ((int64_t)blockIdx.x * 256 + wid * kWave >= V) return;  // wave-uniform
+    SpanTable &st = s_tab[wid];
+    bool live = false, big = false;
+    uint64_t k = 0;
+    uint32_t g = 0;
+    int ra = 0, rb = 0, x0 = 0, x1 = 0;
     Ellipse e;
-    if (!ellipse_setup(rec[0], rec[1], rec[2], rec[3], rec[4], rec[5], rec[7], e)) return;
-    for (int ty = y0; ty < y1; ++ty) {
-        int a, b;
-        if (!ellipse_row_span(e, ty, x0, x1 - 1, a, b)) continue;
-        const uint32_t row = (uint32_t)ty * (uint32_t)tiles_x;
-        for (int tx = a; tx <= b; ++tx, ++k) {
-            if (k >= (uint64_t)cap) return;
-            pair_tiles[k] = row + (uint32_t)tx;
-            pair_gids[k] = g;
+    if (j < V) {
+        k = off[j];
+        g = sorted_ids[j];
+        const uint64_t r = rects[g];
+        x0 = (int)(r & 0xffff);
+        x1 = (int)((r >> 32) & 0xffff);
+        const float *rec = splats + (size_t)g * 12;
+        if (k < (uint64_t)cap &&
+            ellipse_setup(rec[0], rec[1], rec[2], rec[3], rec[4], rec[5], rec[7], e)) {
+            ellipse_row_band(e, (int)((r >> 16) & 0xffff), (int)(r >> 48), ra, rb);
+            big = rb - ra > kSmallRows;
+            live = !big;
+        }
+    }
+    // short bands: every lane its own rows, in lockstep
+    uint64_t ks = k;
+    for (int ty = ra;;) {
+        const bool act = live && ty < rb;
+        if (!__ballot(act)) break;  // wave-uniform
+        uint32_t len = 0, t0 = 0;
+        if (act) {
+            int a, b;
+            if (ellipse_row_span(e, ty, x0, x1 - 1, a, b)) {
+                len = (uint32_t)(b - a + 1);
+                t0 = (uint32_t)ty * (uint32_t)tiles_x + (uint32_t)a;
+            }
+            ++ty;
+        }
+        wave_write_spans(st, len, ks, t0, g, pair_tiles, pair_gids, cap);
+        ks += len;
+    }
+    // long bands: one Gaussian at a time, a row per lane
+    for (uint64_t m = __ballot(big); m; m &= m - 1) {  // wave-uniform
+        const int src = __ffsll((long long)m) - 1;
+        const WaveGaussian w = wave_broadcast(e, x0, x1, ra, rb, src);
+        uint64_t kb = __shfl(k, src, kWave);
+        const uint32_t gb = __shfl(g, src, kWave);
+        for (int t = w.ra; t < w.rb; t += kWave) {  // wave-uniform
+            const int ty = t + lane;
+            uint32_t len = 0, t0 = 0;
+            int a, b;
+            if (ty < w.rb && ellipse_row_span(w.e, ty, w.x0, w.x1 - 1, a, b)) {
+                len = (uint32_t)(b - a + 1);
+                t0 = (uint32_t)ty * (uint32_t)tiles_x + (uint32_t)a;
+            }
+            // this lane's row starts after the rows of the lanes below it
+            uint32_t x = len;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o, kWave);
+                if (lane >= o) x += y;
+            }
+            const uint32_t total = __shfl(x, kWave - 1, kWave);
+            wave_write_spans(st, len, kb + (x - len), t0, gb, pair_tiles, pair_gids, cap);
+            kb += total;
         }
     }
 }
@@ -298,7 +470,8 @@ hipError_t launch_emit(const float *splats, const uint64_t *rects, const uint32_
                        int n, int tiles_x, int extent_rule, uint32_t *pair_tiles,
                        uint32_t *pair_gids, int64_t cap, int64_t *num_pairs, const Workspace &ws,
                        hipStream_t s) {
-    hipError_t e = launch_emit_prepare(splats, rects, tiles_touched, n, cap, num_pairs, ws, s);
+    hipError_t e = launch_emit_prepare(splats, rects, tiles_touched, n, extent_rule, cap, num_pairs,
+                                       ws, s);
     if (e != hipSuccess || n == 0) return e;
     return launch_emit_pairs(splats, rects, tiles_x, extent_rule, pair_tiles, pair_gids, cap,
                              num_pairs, ws, s);

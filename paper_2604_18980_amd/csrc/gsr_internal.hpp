@@ -20,7 +20,7 @@ struct PreprocessArgs {
     double fx, fy, cx, cy, limx, limy;
     int width, height, tiles_x, tiles_y;
     int adagscale, force_unit_scale;
-    int extent_rule;  // 0: tile rectangle; 1: rectangle tiles meeting the alpha >= th ellipse
+    int extent_rule;  // 0: scaled extent's rectangle; 1: plain rectangle (ellipse test at emission)
     double K, lut_depth_max;
     float lut[kLutBins];
     double shc[16];  // real-SH normalisation constants, see preprocess.hip
@@ -80,6 +80,9 @@ constexpr int kSortChunk = kSortThreads * kSortItems;     // 4096 items per bloc
 constexpr int kEmitChunk = kSortChunk;
 // depth presort: blocks per group of the two-level digit offsets
 constexpr int kDepthGroup = 32;
+// ellipse rule: a Gaussian whose row band spans more tile rows than this is
+// counted and emitted by its whole wave (one row per lane), not by its lane
+constexpr int kSmallRows = 16;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanChunk = kScanThreads * kScanItems;     // 4096 elements per block
@@ -148,8 +151,8 @@ hipError_t launch_emit(const float *splats, const uint64_t *rects, const uint32_
 // each (digit offsets from block-group sums, no device-wide scan kernels).
 hipError_t depth_sort(const Workspace &ws, const int64_t *count, hipStream_t s);
 hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
-                               const uint32_t *tiles_touched, int n, int64_t cap, int64_t *num_pairs,
-                               const Workspace &ws, hipStream_t s);
+                               const uint32_t *tiles_touched, int n, int extent_rule, int64_t cap,
+                               int64_t *num_pairs, const Workspace &ws, hipStream_t s);
 // The pair-writing part of launch_emit, after launch_emit_prepare: whole
 // rectangles (extent rule 0) or each rectangle row's ellipse span (rule 1,
 // recomputed from the splat records).

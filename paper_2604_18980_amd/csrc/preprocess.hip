@@ -16,7 +16,6 @@
 // from its centre loses most of its float32 digits.
 #include <math.h>
 
-#include "ellipse.hpp"
 #include "gsr_internal.hpp"
 
 namespace gsr {
@@ -175,7 +174,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
                         keep = false;  // Sec. 3.3: negligible for this view
                     } else {
                         sc = a.force_unit_scale ? 1.0 : sqrt(log(sigma / th) / log(sigma / kTau));
-                        if (a.extent_rule == 0) ext = ext * sc;  // rule 1: the alpha = Th ellipse below
+                        if (a.extent_rule == 0) ext = ext * sc;  // rule 1: Th enters at pair generation
                     }
                 }
             }
@@ -190,32 +189,9 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
                 fx1 = fx1 < 0.0 ? 0.0 : (fx1 > TX ? TX : fx1);
                 fy0 = fy0 < 0.0 ? 0.0 : (fy0 > TY ? TY : fy0);
                 fy1 = fy1 < 0.0 ? 0.0 : (fy1 > TY ? TY : fy1);
-                uint32_t x0 = (uint32_t)fx0, x1 = (uint32_t)fx1, y0 = (uint32_t)fy0,
-                         y1 = (uint32_t)fy1;
+                const uint32_t x0 = (uint32_t)fx0, x1 = (uint32_t)fx1, y0 = (uint32_t)fy0,
+                               y1 = (uint32_t)fy1;
                 tiles = (x1 - x0) * (y1 - y0);
-                // the record as stored (float32); the ellipse test reads these values
-                const double icc = 1.0 / cc;
-                const float rA = (float)(cc / det), rbeta = (float)(-cb * icc), rgamma = (float)icc;
-                const float ru = (float)u, rv = (float)v, rsig = (float)sigma, rth = (float)th;
-                if (tiles > 0 && a.extent_rule == 1) {
-                    // keep the rectangle's tiles that meet the alpha >= th ellipse; the
-                    // rectangle shrinks to their bounding box
-                    Ellipse e;
-                    uint32_t cnt = 0, nx0 = x1, nx1 = x0, ny0 = y1, ny1 = y0;
-                    if (ellipse_setup(ru, rv, rA, rbeta, rgamma, rsig, rth, e)) {
-                        for (uint32_t ty = y0; ty < y1; ++ty) {
-                            int sa, sb;
-                            if (!ellipse_row_span(e, (int)ty, (int)x0, (int)x1 - 1, sa, sb)) continue;
-                            cnt += (uint32_t)(sb - sa + 1);
-                            nx0 = (uint32_t)sa < nx0 ? (uint32_t)sa : nx0;
-                            nx1 = (uint32_t)sb + 1u > nx1 ? (uint32_t)sb + 1u : nx1;
-                            ny0 = ty < ny0 ? ty : ny0;
-                            ny1 = ty + 1u;
-                        }
-                    }
-                    tiles = cnt;
-                    x0 = nx0; x1 = nx1; y0 = ny0; y1 = ny1;
-                }
                 if (tiles > 0) {
                     rect = (uint64_t)x0 | ((uint64_t)y0 << 16) | ((uint64_t)x1 << 32) |
                            ((uint64_t)y1 << 48);
@@ -250,8 +226,10 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
                         acc += 0.5f;
                         rgb[ch] = acc < 0.0f ? 0.0f : acc;
                     }
-                    store_splat(a.splats + (size_t)g * 12, make_float4(ru, rv, rA, rbeta),
-                                make_float4(rgamma, rsig, (float)pz, rth),
+                    const double icc = 1.0 / cc;
+                    store_splat(a.splats + (size_t)g * 12,
+                                make_float4((float)u, (float)v, (float)(cc / det), (float)(-cb * icc)),
+                                make_float4((float)icc, (float)sigma, (float)pz, (float)th),
                                 make_float4(rgb[0], rgb[1], rgb[2], (float)sc));
                 }
             }

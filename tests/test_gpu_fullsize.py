@@ -67,7 +67,8 @@ def check_sampled(O, pre, cam, fb, tiles, n, check_records=True, pairs=None):
         np.testing.assert_array_equal(s[:, 11], f32(pre.scale[vis]))
         assert np.abs(s[:, 8:11] - pre.rgb[vis]).max(initial=0) < 1e-6
         P = int(fb.num_pairs.item())
-        assert P == int(pre.tiles_touched.sum()) and P <= fb.capacity
+        want = int(pre.tiles_touched.sum()) if pairs is None else int(pairs[0].size)
+        assert P == want and P <= fb.capacity
     rg = to_np(fb.ranges).astype(np.uint32).astype(np.int64)
     counts = tile_counts(pre, cam, pairs)
     np.testing.assert_array_equal(rg[:, 1] - rg[:, 0], counts)
