@@ -340,7 +340,11 @@ __device__ __forceinline__ void wave_sync_lds() {
 }
 
 // Writes one step's spans (lane l's span: len pairs from output index k, tiles
-// t0, t0 + 1, ..., Gaussian gid).  Returns nothing; contains wave barriers.
+// t0, t0 + 1, ..., Gaussian gid).  Long spans are written one after another by
+// the whole wave (the span's values read from its lane, consecutive lanes on
+// consecutive pairs); many short ones together, each lane finding the span of
+// its pair by binary search over the span starts in LDS.  Contains wave
+// barriers.
 __device__ __forceinline__ void wave_write_spans(SpanTable &st, uint32_t len, uint64_t k, uint32_t t0,
                                                  uint32_t gid, uint32_t *pair_tiles,
                                                  uint32_t *pair_gids, int64_t cap) {
@@ -352,6 +356,22 @@ __device__ __forceinline__ void wave_write_spans(SpanTable &st, uint32_t len, ui
         if (lane >= o) x += y;
     }
     const uint32_t total = __shfl(x, kWave - 1, kWave);
+    const uint64_t spans = __ballot(len > 0u);
+    if (total >= 16u * (uint32_t)__popcll(spans)) {  // long spans: one at a time
+        for (uint64_t m = spans; m; m &= m - 1) {  // wave-uniform
+            const int src = __ffsll((long long)m) - 1;
+            const uint32_t n = __shfl(len, src, kWave), tb = __shfl(t0, src, kWave),
+                           gb = __shfl(gid, src, kWave);
+            const uint64_t kb = __shfl(k, src, kWave);
+            for (uint32_t i = (uint32_t)lane; i < n; i += kWave) {
+                if (kb + i < (uint64_t)cap) {
+                    pair_tiles[kb + i] = tb + i;
+                    pair_gids[kb + i] = gb;
+                }
+            }
+        }
+        return;
+    }
     st.start[lane] = x - len;
     st.k[lane] = k;
     st.t0[lane] = t0;

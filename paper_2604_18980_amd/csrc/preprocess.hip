@@ -4,9 +4,10 @@
 // 64 consecutive floats per parameter plane).  Everything that decides a
 // discrete output -- the cull, the tile rectangle, the AdaGScale threshold and
 // scale -- is computed in double precision with a fixed operation order, so
-// the rectangles are reproducible on any IEEE machine; gfx950 runs FP64 FMA,
-// add and multiply at the FP32 rate, so this costs no throughput on an
-// HBM-bound kernel.  SH colour is only fetched for Gaussians that get tiles.
+// the rectangles are reproducible on any IEEE machine; gfx950 runs FP64 add,
+// multiply and FMA at half the FP32 rate (divisions and square roots are
+// multi-instruction sequences), affordable once per Gaussian.  SH colour is
+// only fetched for Gaussians that get tiles.
 //
 // The inverse covariance is stored as the sum of squares
 //     d^T Sigma2^-1 d = A (dx + beta dy)^2 + gamma dy^2,
