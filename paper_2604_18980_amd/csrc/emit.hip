@@ -106,6 +106,19 @@ __global__ __launch_bounds__(256) void k_vis_compact(const uint32_t *tiles_touch
     if (threadIdx.x == 0 && b == (int64_t)gridDim.x - 1) *num_vis = (int64_t)(before + tot);
 }
 
+// Reads lane `src` (wave-uniform) of a register: v_readlane, a scalar read,
+// instead of a cross-lane permute through the LDS crossbar.
+__device__ __forceinline__ uint32_t lane_u32(uint32_t x, int src) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, src);
+}
+__device__ __forceinline__ int lane_i32(int x, int src) { return __builtin_amdgcn_readlane(x, src); }
+__device__ __forceinline__ uint64_t lane_u64(uint64_t x, int src) {
+    return (uint64_t)lane_u32((uint32_t)x, src) | ((uint64_t)lane_u32((uint32_t)(x >> 32), src) << 32);
+}
+__device__ __forceinline__ double lane_f64(double x, int src) {
+    return __longlong_as_double((long long)lane_u64((uint64_t)__double_as_longlong(x), src));
+}
+
 // Broadcast of one lane's ellipse and row range to the whole wave.
 struct WaveGaussian {
     Ellipse e;
@@ -114,18 +127,18 @@ struct WaveGaussian {
 __device__ __forceinline__ WaveGaussian wave_broadcast(const Ellipse &e, int x0, int x1, int ra, int rb,
                                                        int src) {
     WaveGaussian w;
-    w.e.u = __shfl(e.u, src, kWave);
-    w.e.v = __shfl(e.v, src, kWave);
-    w.e.A = __shfl(e.A, src, kWave);
-    w.e.beta = __shfl(e.beta, src, kWave);
-    w.e.gamma = __shfl(e.gamma, src, kWave);
-    w.e.c = __shfl(e.c, src, kWave);
-    w.e.R = __shfl(e.R, src, kWave);
-    w.e.w = __shfl(e.w, src, kWave);
-    w.x0 = __shfl(x0, src, kWave);
-    w.x1 = __shfl(x1, src, kWave);
-    w.ra = __shfl(ra, src, kWave);
-    w.rb = __shfl(rb, src, kWave);
+    w.e.u = lane_f64(e.u, src);
+    w.e.v = lane_f64(e.v, src);
+    w.e.A = lane_f64(e.A, src);
+    w.e.beta = lane_f64(e.beta, src);
+    w.e.gamma = lane_f64(e.gamma, src);
+    w.e.c = lane_f64(e.c, src);
+    w.e.R = lane_f64(e.R, src);
+    w.e.w = lane_f64(e.w, src);
+    w.x0 = lane_i32(x0, src);
+    w.x1 = lane_i32(x1, src);
+    w.ra = lane_i32(ra, src);
+    w.rb = lane_i32(rb, src);
     return w;
 }
 
@@ -355,14 +368,13 @@ __device__ __forceinline__ void wave_write_spans(SpanTable &st, uint32_t len, ui
         const uint32_t y = __shfl_up(x, o, kWave);
         if (lane >= o) x += y;
     }
-    const uint32_t total = __shfl(x, kWave - 1, kWave);
+    const uint32_t total = lane_u32(x, kWave - 1);
     const uint64_t spans = __ballot(len > 0u);
     if (total >= 16u * (uint32_t)__popcll(spans)) {  // long spans: one at a time
         for (uint64_t m = spans; m; m &= m - 1) {  // wave-uniform
             const int src = __ffsll((long long)m) - 1;
-            const uint32_t n = __shfl(len, src, kWave), tb = __shfl(t0, src, kWave),
-                           gb = __shfl(gid, src, kWave);
-            const uint64_t kb = __shfl(k, src, kWave);
+            const uint32_t n = lane_u32(len, src), tb = lane_u32(t0, src), gb = lane_u32(gid, src);
+            const uint64_t kb = lane_u64(k, src);
             for (uint32_t i = (uint32_t)lane; i < n; i += kWave) {
                 if (kb + i < (uint64_t)cap) {
                     pair_tiles[kb + i] = tb + i;
@@ -446,8 +458,8 @@ __global__ __launch_bounds__(256) void k_emit_spans(const uint32_t *sorted_ids, 
     for (uint64_t m = __ballot(big); m; m &= m - 1) {  // wave-uniform
         const int src = __ffsll((long long)m) - 1;
         const WaveGaussian w = wave_broadcast(e, x0, x1, ra, rb, src);
-        uint64_t kb = __shfl(k, src, kWave);
-        const uint32_t gb = __shfl(g, src, kWave);
+        uint64_t kb = lane_u64(k, src);
+        const uint32_t gb = lane_u32(g, src);
         for (int t = w.ra; t < w.rb; t += kWave) {  // wave-uniform
             const int ty = t + lane;
             uint32_t len = 0, t0 = 0;
@@ -463,7 +475,7 @@ __global__ __launch_bounds__(256) void k_emit_spans(const uint32_t *sorted_ids, 
                 const uint32_t y = __shfl_up(x, o, kWave);
                 if (lane >= o) x += y;
             }
-            const uint32_t total = __shfl(x, kWave - 1, kWave);
+            const uint32_t total = lane_u32(x, kWave - 1);
             wave_write_spans(st, len, kb + (x - len), t0, gb, pair_tiles, pair_gids, cap);
             kb += total;
         }
