@@ -55,7 +55,7 @@ LUT_DEPTH_MAX = 1200.0
 # HBM bytes of one AdaGScale-frame raster launch per extent rule, from rocprofv3
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (copy-calibrated; profiles/*_hbm_counters.md),
 # valid only for the rasterizer source they were taken with (None: not measured).
-RASTER_TRAFFIC = {"source_sha256_16": None, "bytes": {0: None, 1: None}}
+RASTER_TRAFFIC = {"source_sha256_16": "cb1d352a19a0a61a", "bytes": {0: None, 1: (83.5 + 319.5) * 1e6}}
 
 
 def log(*a):
@@ -81,7 +81,8 @@ def parse():
                    help="extent rule of the measured AdaGScale frame: 1 = ellipse tile test "
                         "(default), 0 = tile rectangle; the other rule is measured beside it")
     p.add_argument("--uncalibrated", action="store_true",
-                   help="AdaGScale with the trivial bound T_upper = 1 instead of the calibrated table")
+                   help="AdaGScale with the trivial bound T_upper = 1 instead of the calibrated "
+                        "table (no calibration runs)")
     p.add_argument("--ada-only", action="store_true",
                    help="with --K: run only AdaGScale frames (no plain frames, no staged "
                         "reference), so a profiler's per-kernel statistics cover the "
@@ -458,14 +459,17 @@ def main():
     rule, other = args.rule, 1 - args.rule
     rule_name = {0: "rectangle", 1: "ellipse"}
 
-    # offline calibration of the T_upper table (not part of a frame)
+    # offline calibration of the T_upper table (not part of a frame; skipped
+    # with --uncalibrated, which uses the trivial bound instead)
     from paper_2604_18980_amd import calib
-    t0 = time.perf_counter()
-    cal_cams = scenes.city_calibration_cameras(CALIB_VIEWS, width=args.width, height=args.height)
-    table, raw_bits = calib.t_upper_table(scene, cal_cams, LUT_DEPTH_MAX)
-    torch.cuda.synchronize()
-    t_cal = time.perf_counter() - t0
-    log(f"T_upper calibrated on {CALIB_VIEWS} views in {t_cal:.1f} s: {np.round(table, 4).tolist()}")
+    table, raw_bits, t_cal = np.ones(20, np.float32), None, 0.0
+    if not args.uncalibrated:
+        t0 = time.perf_counter()
+        cal_cams = scenes.city_calibration_cameras(CALIB_VIEWS, width=args.width, height=args.height)
+        table, raw_bits = calib.t_upper_table(scene, cal_cams, LUT_DEPTH_MAX)
+        torch.cuda.synchronize()
+        t_cal = time.perf_counter() - t0
+        log(f"T_upper calibrated on {CALIB_VIEWS} views in {t_cal:.1f} s: {np.round(table, 4).tolist()}")
     ada = dict(t_upper=None, lut_depth_max=100.0) if args.uncalibrated else \
         dict(t_upper=table, lut_depth_max=LUT_DEPTH_MAX)
     unc = dict(t_upper=None, lut_depth_max=100.0)
@@ -608,10 +612,10 @@ def main():
                    "mode": (f"adagscale, {rule_name[rule]} tile test, "
                             + ("T_upper = 1" if args.uncalibrated else cal)),
                    "K": K, "psnr_target_db": PSNR_TARGET_DB},
-        "calibration": {"views": CALIB_VIEWS, "lut_depth_max": LUT_DEPTH_MAX,
-                        "t_upper": [float(x) for x in table], "seconds": t_cal,
-                        "empty_bins": int((raw_bits == 0).sum()),
-                        "used": not args.uncalibrated},
+        "calibration": None if args.uncalibrated else {
+            "views": CALIB_VIEWS, "lut_depth_max": LUT_DEPTH_MAX,
+            "t_upper": [float(x) for x in table], "seconds": t_cal,
+            "empty_bins": int((raw_bits == 0).sum())},
         "adagscale": res_a,
         **extra,
         "plain": None,
