@@ -15,7 +15,9 @@
  *   sort         Sec. 2.1: pairs ordered by depth inside each tile
  *   ranges       start/end of every tile's run in the sorted list
  *   blend        eq. (1) and eq. (2) with tau = 1/255 and the 1e-4 early exit,
- *                original covariance and tau in both modes (dual size, Sec. 3.3)
+ *                original covariance and tau in both modes (dual size, Sec. 3.3);
+ *                optionally skipping blends of low contribution (eq. 3 and its
+ *                max(T) and T_up(depth) approximations, Sec. 2.4, 3.2)
  *   backward     analytic adjoint of the above with every discrete decision
  *                frozen (pair set, skips, stop, clamps)
  *
@@ -516,10 +518,37 @@ typedef struct {
     uint64_t sig;      /* hash of the blended positions */
 } pix_t;
 
+/* Contribution-skip rule of the analysis experiments (Sec. 2.4, Sec. 3.2):
+ * a blend operation of Gaussian i at a pixel is skipped -- no colour, no
+ * transmittance update -- when its contribution is below theta.  The
+ * contribution is alpha T (eq. 3, kind 0, with the pixel's running T), alpha
+ * max(T^i) (kind 1, weight[i] = the Gaussian's largest T over the pixels where
+ * it blends, Sec. 3.2) or alpha T_up(depth_i) (kind 2, the depth-binned table
+ * of Sec. 3.2-3.4, bin = min(floor(20 depth / lut_depth_max), 19)). */
+typedef struct {
+    int kind;
+    double theta;
+    const double *weight;   /* kind 1: [n] */
+    const float *depth_f32; /* kind 2: [n] */
+    const double *lut;      /* kind 2: [20] */
+    double lut_depth_max;
+} skip_t;
+
+static double skip_weight(const skip_t *sk, uint32_t g, double T) {
+    if (sk->kind == 0) return T;
+    if (sk->kind == 1) return sk->weight[g];
+    double f = ((double)sk->depth_f32[g] * LUT_BINS) / sk->lut_depth_max;
+    int bin = (f >= LUT_BINS - 1) ? LUT_BINS - 1 : (int)floor(f);
+    return sk->lut[bin];
+}
+
 /* max_t (nullable, [n]): per Gaussian, the largest transmittance in front of
- * it at a pixel where it is blended (the max(T^i) of Sec. 3.2). */
-static void blend_pixel(double px, double py, const uint32_t *list, int64_t len, const double *rec,
-                        pix_t *o, double *max_t) {
+ * it at a pixel where it is blended (the max(T^i) of Sec. 3.2).  sk
+ * (nullable): the contribution-skip rule above; skipped blends count in
+ * *skipped (nullable). */
+static void blend_pixel_skip(double px, double py, const uint32_t *list, int64_t len,
+                             const double *rec, pix_t *o, double *max_t, const skip_t *sk,
+                             int64_t *skipped) {
     double T = 1.0, C[3] = {0.0, 0.0, 0.0}, margin = INFINITY;
     int64_t last = 0, blended = 0, ev = 0;
     uint64_t sig = 1469598103934665603ull;
@@ -535,6 +564,15 @@ static void blend_pixel(double px, double py, const uint32_t *list, int64_t len,
         double ma = fabs(alpha - TAU) / TAU;
         if (ma < margin) margin = ma;
         if (alpha < TAU) continue;
+        if (sk && sk->theta > 0.0) {
+            double c = alpha * skip_weight(sk, list[j], T);
+            double mc = fabs(c - sk->theta) / sk->theta;
+            if (mc < margin) margin = mc;
+            if (c < sk->theta) {
+                if (skipped) ++*skipped;
+                continue;
+            }
+        }
         double Tn = T * (1.0 - alpha);
         double mt = fabs(Tn - T_STOP) / T_STOP;
         if (mt < margin) margin = mt;
@@ -548,6 +586,11 @@ static void blend_pixel(double px, double py, const uint32_t *list, int64_t len,
     }
     for (int ch = 0; ch < 3; ++ch) o->color[ch] = C[ch];
     o->T = T; o->last = last; o->blended = blended; o->evaluated = ev; o->margin = margin; o->sig = sig;
+}
+
+static void blend_pixel(double px, double py, const uint32_t *list, int64_t len, const double *rec,
+                        pix_t *o, double *max_t) {
+    blend_pixel_skip(px, py, list, len, rec, o, max_t, NULL, NULL);
 }
 
 static void store_pixel(const pix_t *o, int64_t idx, int64_t npix, const double *bg, double *image,
@@ -585,6 +628,33 @@ void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *sor
                             ranges[2 * t + 1] - ranges[2 * t], rec, &o, max_t);
                 store_pixel(&o, (int64_t)py * width + px, npix, bg, image, final_T, n_contrib,
                             margin, evals, sig, blended);
+            }
+    }
+}
+
+/* orc_blend with the contribution-skip rule (kind, theta, weight / depth and
+ * table as in skip_t); skipped[0] receives the number of skipped blends and
+ * blended (nullable, [H][W]) the blends kept per pixel. */
+void orc_blend_skip(int width, int height, const int64_t *ranges, const uint32_t *sorted_vals,
+                    const double *rec, const double *bg, const int32_t *tiles, int64_t n_sel,
+                    int kind, double theta, const double *weight, const float *depth_f32,
+                    const double *lut, double lut_depth_max, double *image, double *final_T,
+                    int64_t *n_contrib, double *margin, int64_t *blended, int64_t *skipped) {
+    skip_t sk = {kind, theta, weight, depth_f32, lut, lut_depth_max};
+    int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
+    int64_t npix = (int64_t)width * height;
+    int64_t count = n_sel >= 0 ? n_sel : (int64_t)TX * TY;
+    skipped[0] = 0;
+    for (int64_t s = 0; s < count; ++s) {
+        int t = n_sel >= 0 ? tiles[s] : (int)s;
+        int tx = t % TX, ty = t / TX;
+        for (int py = ty * TILE; py < (ty + 1) * TILE && py < height; ++py)
+            for (int px = tx * TILE; px < (tx + 1) * TILE && px < width; ++px) {
+                pix_t o;
+                blend_pixel_skip((double)px, (double)py, sorted_vals + ranges[2 * t],
+                                 ranges[2 * t + 1] - ranges[2 * t], rec, &o, NULL, &sk, skipped);
+                store_pixel(&o, (int64_t)py * width + px, npix, bg, image, final_T, n_contrib,
+                            margin, NULL, NULL, blended);
             }
     }
 }

@@ -66,6 +66,8 @@ def lib():
         L.orc_ranges.argtypes = [C.c_int64, P, C.c_int, P]
         L.orc_blend.argtypes = [C.c_int, C.c_int, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P]
         L.orc_t_upper_accumulate.argtypes = [C.c_int64, P, P, C.c_double, P]
+        L.orc_blend_skip.argtypes = ([C.c_int, C.c_int, P, P, P, P, P, C.c_int64, C.c_int,
+                                      C.c_double, P, P, P, C.c_double] + [P] * 6)
         L.orc_blend_bruteforce.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_int, P, P, P, P, P, P,
                                            P, P]
         L.orc_blend_backward.argtypes = [C.c_int, C.c_int, P, P, P, P, P, P, P, C.c_int64]
@@ -274,6 +276,36 @@ def blend_counts(frame: "Frame", cam, tiles=None, rec=None):
     lib().orc_blend(W, H, _p(rg), _p(sv), _p(rec), _p(bgv), _p(sel), nsel, _p(img), _p(T),
                     _p(nc), _p(mg), _p(ev), None, _p(bl), None)
     return ev, bl, mg
+
+
+def blend_skip(frame: "Frame", cam, kind, theta, weight=None, lut=None, lut_depth_max=100.0,
+               bg=(0.0, 0.0, 0.0), tiles=None, rec=None):
+    """Blend with the contribution-skip rule (Sec. 2.4, 3.2): a blend whose
+    contribution is below theta is skipped (no colour, no T update).  kind 0:
+    alpha T (eq. 3); 1: alpha weight[i] (max(T^i)); 2: alpha T_up(depth_i) from
+    the 20-bin `lut` over [0, lut_depth_max].  Returns (image, final_T,
+    n_contrib, margin, blended per pixel, skipped blends in total)."""
+    W, H = cam["width"], cam["height"]
+    rec = np.ascontiguousarray(frame.pre.record() if rec is None else rec, np.float64)
+    n = rec.shape[0]
+    img = np.zeros((3, H, W))
+    T = np.zeros((H, W))
+    nc = np.zeros((H, W), np.int64)
+    mg = np.full((H, W), np.inf)
+    bl = np.zeros((H, W), np.int64)
+    sk = np.zeros(1, np.int64)
+    bgv = np.asarray(bg, np.float64)
+    w = np.ascontiguousarray(weight if weight is not None else np.zeros(max(n, 1)), np.float64)
+    d32 = _f32(frame.pre.depth_f32) if frame.pre is not None else np.zeros(max(n, 1), np.float32)
+    lt = np.ascontiguousarray(lut if lut is not None else np.ones(LUT_BINS), np.float64)
+    rg = np.ascontiguousarray(frame.ranges, np.int64)
+    sv = np.ascontiguousarray(frame.sorted_vals, np.uint32)
+    sel = None if tiles is None else np.ascontiguousarray(tiles, np.int32)
+    nsel = -1 if sel is None else sel.size
+    lib().orc_blend_skip(W, H, _p(rg), _p(sv), _p(rec), _p(bgv), _p(sel), nsel, int(kind),
+                         float(theta), _p(w), _p(d32), _p(lt), float(lut_depth_max), _p(img),
+                         _p(T), _p(nc), _p(mg), _p(bl), _p(sk))
+    return img, T, nc, mg, bl, int(sk[0])
 
 
 def max_transmittance(frame: "Frame", cam, rec=None):

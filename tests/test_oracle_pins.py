@@ -732,3 +732,115 @@ def test_rule1_adagscale_pairs_within_plain(O):
     assert ka.size < kp.size
     assert _pair_sets(ka, va) <= _pair_sets(kp, vp)
     assert _pair_sets(k0, v0) == _pair_sets(kp, vp)
+
+
+# --------------------------------------------------------------------------- contribution-skip blend (Sec. 2.4, 3.2)
+def test_skip_blend_theta_zero_is_the_blend(O):
+    """theta = 0 skips nothing: every kind equals the plain blend bit for bit."""
+    sc, cam = scenes.tiny_scene(n=500, seed=31)
+    fr = O.render(sc, cam, bg=(0.1, 0.2, 0.3))
+    mt, _ = O.max_transmittance(fr, cam)
+    for kind, kw in ((0, {}), (1, dict(weight=mt)), (2, dict(lut=np.linspace(1, 0.2, 20)))):
+        img, T, nc, _, _, skipped = O.blend_skip(fr, cam, kind, 0.0, bg=(0.1, 0.2, 0.3), **kw)
+        assert skipped == 0
+        np.testing.assert_array_equal(img, fr.image)
+        np.testing.assert_array_equal(T, fr.final_T)
+        np.testing.assert_array_equal(nc, fr.n_contrib)
+
+
+def test_skip_blend_stacked_closed_form(O):
+    """Two Gaussians on pixel (5, 5), front alpha 0.3 (red), back alpha 0.5
+    (green), black background.  Exact contributions 0.3 and 0.5 x 0.7 = 0.35.
+    theta = 0.2 keeps both: colour (0.3, 0.35, 0), T = 0.35.  theta = 0.32
+    drops the front one, after which the back one contributes 0.5 x 1 and is
+    kept: colour (0, 0.5, 0), T = 0.5.  theta = 0.4: exact (kind 0) still keeps
+    the back one (0.5), while with max(T) weights (1 and 0.7, kind 1) it
+    contributes 0.35 and is dropped too.  theta = 0.6 drops both."""
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 16, 16)
+    g1 = (5.0, 5.0, 20.0, 0.0, 20.0, 0.3, 1, 0, 0)
+    g2 = (5.0, 5.0, 20.0, 0.0, 20.0, 0.5, 0, 1, 0)
+    fr, rec = _frame_of(O, [g1, g2], cam)
+    a1, a2 = float(np.float32(0.3)), float(np.float32(0.5))  # records hold float32 values
+    img, T, nc, _, bl, sk = O.blend_skip(fr, cam, 0, 0.2, rec=rec)
+    np.testing.assert_allclose(img[:, 5, 5], [a1, a2 * (1 - a1), 0.0], rtol=1e-15, atol=0)
+    assert T[5, 5] == pytest.approx((1 - a1) * (1 - a2), rel=1e-15) and nc[5, 5] == 2
+    img, T, nc, _, bl, sk = O.blend_skip(fr, cam, 0, 0.32, rec=rec)
+    np.testing.assert_allclose(img[:, 5, 5], [0.0, a2, 0.0], rtol=1e-15, atol=0)
+    assert T[5, 5] == 1 - a2 and nc[5, 5] == 2 and bl[5, 5] == 1
+    img, T, nc, _, bl, sk = O.blend_skip(fr, cam, 0, 0.4, rec=rec)
+    assert T[5, 5] == 1 - a2 and bl[5, 5] == 1
+    w = np.array([1.0, 1 - a1])
+    img, T, nc, _, bl, sk = O.blend_skip(fr, cam, 1, 0.32, weight=w, rec=rec)
+    assert T[5, 5] == 1 - a2 and bl[5, 5] == 1
+    img, T, nc, _, bl, sk = O.blend_skip(fr, cam, 1, 0.4, weight=w, rec=rec)
+    assert T[5, 5] == 1.0 and nc[5, 5] == 0 and not img[:, 5, 5].any()
+    img, T, nc, _, bl, sk = O.blend_skip(fr, cam, 0, 0.6, rec=rec)
+    assert T[5, 5] == 1.0 and nc[5, 5] == 0 and not img[:, 5, 5].any()
+
+
+def _numpy_skip_blend(pre, fr, cam, thr_of):
+    """Per pixel, the tile's sorted list walked front to back in plain numpy:
+    alpha = min(0.99, opacity exp(-q/2)); skipped if alpha < tau or
+    thr_of(i, alpha) (a T-independent rule); stop before T(1 - alpha) < 1e-4."""
+    W, H = cam["width"], cam["height"]
+    rec = pre.record()
+    TX = (W + 15) // 16
+    img = np.zeros((3, H, W))
+    Tm = np.ones((H, W))
+    for py in range(H):
+        for px in range(W):
+            t = (py // 16) * TX + px // 16
+            T = 1.0
+            col = np.zeros(3)
+            for i in fr.sorted_vals[fr.ranges[t, 0]:fr.ranges[t, 1]]:
+                mx, my, A, beta, gam, op = rec[i, :6]
+                dx, dy = mx - px, my - py
+                q = A * (dx + beta * dy) ** 2 + gam * dy * dy
+                alpha = min(0.99, op * math.exp(-0.5 * q))
+                if alpha < 1 / 255 or thr_of(i, alpha):
+                    continue
+                if T * (1 - alpha) < 1e-4:
+                    break
+                col += alpha * T * rec[i, 6:9]
+                T *= 1 - alpha
+            img[:, py, px] = col
+            Tm[py, px] = T
+    return img, Tm
+
+
+def test_skip_blend_t_independent_kinds_against_numpy(O):
+    """Kinds 1 and 2 do not depend on the running T: their skip is a fixed
+    per-(Gaussian, alpha) test, so a plain numpy walk of the same lists with
+    that test reproduces them (max(T) weights from the oracle's own walk,
+    a decreasing depth table)."""
+    sc, _ = scenes.tiny_scene(n=150, seed=33)
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 40, 28)
+    fr = O.render(sc, cam)
+    pre = fr.pre
+    mt, _ = O.max_transmittance(fr, cam)
+    lut = np.linspace(1.0, 0.3, 20)
+    d32 = pre.depth.astype(np.float32).astype(np.float64)
+    binw = lambda i: lut[min(int(np.floor(d32[i] * 20 / 8.0)), 19)]
+    for kind, theta, kw, rule in (
+            (1, 0.05, dict(weight=mt), lambda i, a: a * mt[i] < 0.05),
+            (2, 0.08, dict(lut=lut, lut_depth_max=8.0), lambda i, a: a * binw(i) < 0.08)):
+        img, T, nc, mg, bl, sk = O.blend_skip(fr, cam, kind, theta, **kw)
+        want_img, want_T = _numpy_skip_blend(pre, fr, cam, rule)
+        assert sk > 0
+        ok = mg >= 1e-9
+        assert np.abs(img - want_img)[:, ok].max() < 1e-12
+        assert np.abs(T - want_T)[ok].max() < 1e-12
+
+
+def test_skip_blend_huge_theta_and_monotone(O):
+    """theta above any contribution skips every blend (background, T = 1);
+    for the T-independent kinds the skipped count grows with theta."""
+    sc, cam = scenes.tiny_scene(n=400, seed=34)
+    fr = O.render(sc, cam, bg=(0.2, 0.4, 0.6))
+    img, T, nc, _, bl, sk = O.blend_skip(fr, cam, 0, 2.0, bg=(0.2, 0.4, 0.6))
+    assert np.all(T == 1.0) and not nc.any() and not bl.any() and sk > 0
+    np.testing.assert_array_equal(img[1], np.full_like(img[1], 0.4))
+    mt, _ = O.max_transmittance(fr, cam)
+    for kind, kw in ((1, dict(weight=mt)), (2, dict(lut=np.linspace(1, 0.1, 20)))):
+        counts = [O.blend_skip(fr, cam, kind, th, **kw)[5] for th in (0.0, 0.01, 0.05, 0.2, 0.5)]
+        assert counts == sorted(counts) and counts[0] == 0 and counts[-1] > counts[1]
