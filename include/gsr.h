@@ -260,6 +260,27 @@ gs_status gs_calibrate_t_upper(const float *splats, int64_t n, const uint32_t *s
                                const uint32_t *ranges, const gs_camera *cam, float lut_depth_max,
                                uint32_t *t_upper_bits, uint32_t *max_t_bits, void *stream);
 
+/* Stage 4 with low-contribution blends skipped: the analysis of Sec. 2.4
+ * (Fig. 4(a)) and its approximations in Sec. 3.2 (Fig. 5).  As
+ * gs_rasterize with the default geometry, except that a blend of Gaussian i
+ * at a pixel (alpha >= 1/255) is skipped -- no colour, no transmittance
+ * update, not counted in n_contrib -- when its contribution is below theta:
+ *   kind 0: alpha T, T the pixel's running transmittance (eq. 3);
+ *   kind 1: alpha weight[i] (device float[n]; e.g. max(T^i) of this view, as
+ *           gs_calibrate_t_upper's max_t_bits give it);
+ *   kind 2: alpha t_upper[bin] (host float[GS_LUT_BINS]) of the record's
+ *           float32 depth, bin = min(floor(GS_LUT_BINS * depth /
+ *           lut_depth_max), GS_LUT_BINS - 1) evaluated in double.
+ * theta = 0 renders exactly as gs_rasterize.  counts (nullable, device
+ * uint64[2]) is added to: [0] skipped blends, [1] kept blends (the caller
+ * zeroes it).  theta must be finite and >= 0, kind 0..2 (else
+ * GS_ERR_INVALID_ARGUMENT). */
+gs_status gs_rasterize_skip(const float *splats, int64_t n, const uint32_t *sorted_gids,
+                            const uint32_t *ranges, const gs_camera *cam, const float *bg,
+                            int kind, float theta, const float *weight, const float *t_upper,
+                            float lut_depth_max, float *image, float *final_T, uint32_t *n_contrib,
+                            unsigned long long *counts, void *stream);
+
 /* Adjoint of stage 4 with the pair set and every blend decision of the
  * forward pass frozen.  Walks each pixel's list back to front from n_contrib,
  * recovering T_i = T_{i+1} / (1 - alpha_i) from final_T instead of storing

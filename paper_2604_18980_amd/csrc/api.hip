@@ -375,6 +375,7 @@ gs_status gs_rasterize(const float *splats, int64_t n, const uint32_t *sorted_gi
     a.n_evaluated = n_evaluated;
     a.work = nullptr;
     a.lut_bits = a.max_t_bits = nullptr;
+    a.skip_kind = -1;
     a.lut_depth_max = 0.0;
     return hip_check(launch_raster(a, c, (hipStream_t)stream), "gs_rasterize");
 }
@@ -401,6 +402,7 @@ gs_status gs_raster_work(const float *splats, int64_t n, const uint32_t *sorted_
     a.n_evaluated = nullptr;
     a.work = reinterpret_cast<unsigned long long *>(work);
     a.lut_bits = a.max_t_bits = nullptr;
+    a.skip_kind = -1;
     a.lut_depth_max = 0.0;
     const gs_raster_cfg c = {64, 4, 64};
     return hip_check(launch_raster(a, c, (hipStream_t)stream), "gs_raster_work");
@@ -432,8 +434,53 @@ gs_status gs_calibrate_t_upper(const float *splats, int64_t n, const uint32_t *s
     a.lut_bits = t_upper_bits;
     a.max_t_bits = max_t_bits;
     a.lut_depth_max = (double)lut_depth_max;
+    a.skip_kind = -1;
     const gs_raster_cfg c = {64, 4, 64};
     return hip_check(launch_raster(a, c, (hipStream_t)stream), "gs_calibrate_t_upper");
+}
+
+gs_status gs_rasterize_skip(const float *splats, int64_t n, const uint32_t *sorted_gids,
+                            const uint32_t *ranges, const gs_camera *cam, const float *bg,
+                            int kind, float theta, const float *weight, const float *t_upper,
+                            float lut_depth_max, float *image, float *final_T, uint32_t *n_contrib,
+                            unsigned long long *counts, void *stream) {
+    gs_status st;
+    if ((st = check_camera(cam)) != GS_OK) return st;
+    if (n < 0) return fail(GS_ERR_INVALID_ARGUMENT, "n < 0");
+    if (!ranges || !image || !final_T || !n_contrib || !bg)
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (n > 0 && (!splats || !sorted_gids)) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (kind < 0 || kind > 2) return fail(GS_ERR_INVALID_ARGUMENT, "kind must be 0, 1 or 2");
+    if (!(theta >= 0.0f) || !finite_f(theta))
+        return fail(GS_ERR_INVALID_ARGUMENT, "theta must be finite and >= 0");
+    if (kind == 1 && n > 0 && !weight) return fail(GS_ERR_INVALID_ARGUMENT, "kind 1 needs weight");
+    if (kind == 2) {
+        if (!t_upper) return fail(GS_ERR_INVALID_ARGUMENT, "kind 2 needs t_upper");
+        if (!(lut_depth_max > 0.0f) || !finite_f(lut_depth_max))
+            return fail(GS_ERR_INVALID_ARGUMENT, "lut_depth_max must be finite and > 0");
+    }
+    RasterArgs a;
+    a.splats = splats;
+    a.gids = sorted_gids;
+    a.ranges = ranges;
+    a.width = cam->width;
+    a.height = cam->height;
+    a.tiles_x = tiles_x(cam);
+    a.tiles_y = tiles_y(cam);
+    for (int i = 0; i < 3; ++i) a.bg[i] = bg[i];
+    a.image = image;
+    a.final_T = final_T;
+    a.n_contrib = n_contrib;
+    a.n_evaluated = nullptr;
+    a.work = counts;
+    a.lut_bits = a.max_t_bits = nullptr;
+    a.lut_depth_max = kind == 2 ? (double)lut_depth_max : 1.0;
+    a.skip_kind = kind;
+    a.skip_theta = theta;
+    a.skip_weight = weight;
+    for (int i = 0; i < GS_LUT_BINS; ++i) a.skip_lut[i] = kind == 2 ? t_upper[i] : 1.0f;
+    const gs_raster_cfg c = {64, 4, 64};
+    return hip_check(launch_raster(a, c, (hipStream_t)stream), "gs_rasterize_skip");
 }
 
 gs_status gs_rasterize_backward(const float *splats, int64_t n, const uint32_t *sorted_gids,

@@ -187,6 +187,14 @@ struct RasterArgs {
     uint32_t *lut_bits;
     uint32_t *max_t_bits;
     double lut_depth_max;
+    // contribution-skip rendering (skip_kind >= 0; pixels written): a blend
+    // whose contribution alpha x (T, skip_weight[i] or skip_lut[depth bin of i],
+    // for kinds 0, 1, 2) is below skip_theta is skipped; work, if set, then
+    // receives [0] the skipped and [1] the kept blends (added)
+    int skip_kind;  // -1: off
+    float skip_theta;
+    const float *skip_weight;
+    float skip_lut[kLutBins];
 };
 hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStream_t s);
 

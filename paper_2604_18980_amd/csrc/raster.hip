@@ -122,14 +122,21 @@ __device__ __forceinline__ float wave_max(float v) {
 // blends, the largest transmittance in front of it over the tile's pixels,
 // raised into its depth bin (per-wave maxima in LDS, flushed at the end of
 // the tile) and, if requested, into the Gaussian's own entry.
+// MODE 4: the renderer with the contribution-skip rule of the analysis
+// experiments (Sec. 2.4, 3.2): a blend whose contribution alpha x (T, the
+// Gaussian's weight, or T_up of its depth bin) is below a.skip_theta is
+// skipped (no colour, no T update, not a contributor); a.work, if set,
+// receives the skipped and kept blend counts.
 template <int MODE>
 __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
     constexpr bool EV = MODE == 1 || MODE == 2;
+    constexpr bool CNT = MODE == 2 || MODE == 4;  // counts kept blends
     __shared__ float4 s0[4][64], s1[4][64];
     __shared__ float2 s2[4][64];
     __shared__ uint32_t s_cal[MODE == 3 ? 4 : 1][64];   // MODE 3: depth bin of each slot
     __shared__ uint32_t s_cgid[MODE == 3 ? 4 : 1][64];  // MODE 3: Gaussian id of each slot
     __shared__ uint32_t s_lut[MODE == 3 ? 4 : 1][kLutBins];
+    __shared__ float s_w[MODE == 4 ? 4 : 1][64];          // MODE 4: weight of each slot
     const int wid = threadIdx.x / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
@@ -156,7 +163,8 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
         off[k] = (px < a.width && py < a.height) ? 0.0f : -INFINITY;
     }
     const float4 *spl = reinterpret_cast<const float4 *>(a.splats);
-    uint32_t w_strips = 0, w_blended = 0, w_loaded = 0;  // MODE 2 only
+    uint32_t w_strips = 0, w_blended = 0, w_loaded = 0;  // MODE 2 (w_blended also MODE 4)
+    uint32_t w_skipped = 0;                              // MODE 4
     if (MODE == 3 && lane < kLutBins) s_lut[wid][lane] = 0u;
 
     for (uint32_t base = start; base < end; base += kWave) {
@@ -185,6 +193,16 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
                 s_cal[wid][lane] = f >= (double)(kLutBins - 1) ? (uint32_t)(kLutBins - 1) : (uint32_t)floor(f);
                 s_cgid[wid][lane] = (uint32_t)gid;
             }
+            if (MODE == 4) {
+                float wv = 1.0f;
+                if (a.skip_kind == 1) {
+                    wv = a.skip_weight[gid];
+                } else if (a.skip_kind == 2) {
+                    const double f = ((double)g1.z * kLutBins) / a.lut_depth_max;
+                    wv = a.skip_lut[f >= (double)(kLutBins - 1) ? kLutBins - 1 : (int)floor(f)];
+                }
+                s_w[wid][lane] = wv;
+            }
         }
         uint64_t m[4], any = 0;
 #pragma unroll
@@ -201,6 +219,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
             const float dx = smx - fpx;
             const uint32_t pos = (base - start) + (uint32_t)cur + 1u;
             float tmax = 0.0f;  // MODE 3: largest T in front of it where it blends
+            const float swt = MODE == 4 ? s_w[wid][cur] : 0.0f;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (!((m[k] >> cur) & 1ull)) continue;  // uniform: strip k missed
@@ -215,20 +234,28 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
                 // live pixel and opacity * 2^e2 >= tau, decided on the exponent
                 // so the exponential is only taken where it is used
                 if (e2 >= selim) {
-                    const float alpha = fminf(kAlphaMaxF, ssig * __builtin_amdgcn_exp2f(e2));
+                    float alpha = fminf(kAlphaMaxF, ssig * __builtin_amdgcn_exp2f(e2));
+                    bool skip = false;
+                    if (MODE == 4) {
+                        // contribution below theta: blend nothing (alpha 0 leaves
+                        // T, the colour and the stop test untouched)
+                        skip = alpha * (a.skip_kind == 0 ? T[k] : swt) < a.skip_theta;
+                        alpha = skip ? 0.0f : alpha;
+                        w_skipped += skip ? 1u : 0u;
+                    }
                     const float wa = alpha * T[k];
                     const float Tn = T[k] - wa;     // T (1 - alpha)
                     if (MODE == 3 && !(Tn < kStopF)) tmax = fmaxf(tmax, T[k]);
                     float w = wa, Tk = Tn;
-                    uint32_t lk = pos;
+                    uint32_t lk = skip ? last[k] : pos;
                     if (__ballot(Tn < kStopF) != 0ull) {
                         // rare: some lane stops here (not blended; the pixel is done)
                         const bool stop = Tn < kStopF;
                         w = stop ? 0.0f : wa;
                         Tk = stop ? T[k] : Tn;
-                        lk = stop ? last[k] : pos;
+                        lk = stop ? last[k] : lk;
                         if (EV) ev[k] = stop ? pos : ev[k];
-                        if (MODE == 2) w_blended -= stop ? 1u : 0u;
+                        if (CNT) w_blended -= stop ? 1u : 0u;
                         off[k] = stop ? -INFINITY : off[k];
                     }
                     cr[k] = fmaf(w, sr, cr[k]);
@@ -236,7 +263,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
                     cb[k] = fmaf(w, sb, cb[k]);
                     T[k] = Tk;
                     last[k] = lk;
-                    if (MODE == 2) ++w_blended;
+                    if (CNT) w_blended += skip ? 0u : 1u;
                 }
             }
             if (MODE == 3) {
@@ -292,6 +319,13 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
         }
         return;
     }
+    if (MODE == 4 && a.work) {
+        const unsigned long long sk = wave_sum_u64(w_skipped), b = wave_sum_u64(w_blended);
+        if (lane == 0) {
+            atomicAdd(&a.work[0], sk);
+            atomicAdd(&a.work[1], b);
+        }
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int py = ty * kTile + row0 + 4 * k;
@@ -323,6 +357,8 @@ hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStrea
     const unsigned tiles = (unsigned)a.tiles_x * (unsigned)a.tiles_y;
     if (a.lut_bits) {
         k_raster_wave<3><<<(tiles + 3) / 4, 256, 0, s>>>(a);
+    } else if (a.skip_kind >= 0) {
+        k_raster_wave<4><<<(tiles + 3) / 4, 256, 0, s>>>(a);
     } else if (a.work) {
         k_raster_wave<2><<<(tiles + 3) / 4, 256, 0, s>>>(a);
     } else if (cfg.threads_per_tile == 256) {
@@ -365,6 +401,7 @@ __device__ __forceinline__ RasterArgs view_args(const ViewsArgs &q, int view) {
     a.n_evaluated = nullptr;
     a.work = nullptr;
     a.lut_bits = a.max_t_bits = nullptr;
+    a.skip_kind = -1;
     a.lut_depth_max = 0.0;
     return a;
 }

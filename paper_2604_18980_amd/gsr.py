@@ -20,7 +20,7 @@ LUT_BINS = 20
 TILE = 16
 
 EXPORTS = ("gs_workspace_size", "gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_bin_pairs",
-           "gs_rasterize", "gs_raster_work", "gs_calibrate_t_upper",
+           "gs_rasterize", "gs_raster_work", "gs_calibrate_t_upper", "gs_rasterize_skip",
            "gs_rasterize_backward", "gs_preprocess_backward", "gs_views_workspace_size",
            "gs_rasterize_views", "gs_wall_clock_khz", "gs_status_string", "gs_last_error",
            "gs_version")
@@ -80,10 +80,12 @@ def load():
     L.gs_rasterize.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P]
     L.gs_raster_work.argtypes = [P, I64, P, P, P, P, P]
     L.gs_calibrate_t_upper.argtypes = [P, I64, P, P, P, C.c_float, P, P, P]
+    L.gs_rasterize_skip.argtypes = [P, I64, P, P, P, P, I, C.c_float, P, P, C.c_float, P, P, P, P,
+                                    P]
     L.gs_rasterize_backward.argtypes = [P, I64, P, P, P, P, P, P, P, P, P]
     L.gs_preprocess_backward.argtypes = [P, P, P, P, P, P]
     for f in ("gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_bin_pairs", "gs_rasterize",
-              "gs_raster_work", "gs_calibrate_t_upper",
+              "gs_raster_work", "gs_calibrate_t_upper", "gs_rasterize_skip",
               "gs_rasterize_backward", "gs_preprocess_backward"):
         getattr(L, f).restype = C.c_int
     L.gs_status_string.argtypes = [I]
@@ -209,6 +211,17 @@ def gs_calibrate_t_upper(splats, n, sorted_gids, ranges, cam: GsCamera, lut_dept
     _check(load().gs_calibrate_t_upper(_ptr(splats), int(n), _ptr(sorted_gids), _ptr(ranges),
                                        C.byref(cam), float(lut_depth_max), _ptr(t_upper_bits),
                                        _ptr(max_t_bits), _stream(stream)))
+
+
+def gs_rasterize_skip(splats, n, sorted_gids, ranges, cam: GsCamera, bg, kind, theta, weight,
+                      t_upper, lut_depth_max, image, final_T, n_contrib, counts=None, stream=None):
+    """t_upper: host sequence of GS_LUT_BINS floats (kind 2) or None."""
+    bgv = (C.c_float * 3)(*[float(x) for x in bg])
+    lut = None if t_upper is None else (C.c_float * LUT_BINS)(*[float(x) for x in t_upper])
+    _check(load().gs_rasterize_skip(_ptr(splats), int(n), _ptr(sorted_gids), _ptr(ranges),
+                                    C.byref(cam), bgv, int(kind), float(theta), _ptr(weight), lut,
+                                    float(lut_depth_max), _ptr(image), _ptr(final_T),
+                                    _ptr(n_contrib), _ptr(counts), _stream(stream)))
 
 
 def gs_rasterize_backward(splats, n, sorted_gids, ranges, cam: GsCamera, bg, final_T, n_contrib,
