@@ -73,9 +73,10 @@ def parse():
     p.add_argument("--K", type=float, default=None, help="fixed K (skip the search)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-tiles", type=int, default=1024)
-    p.add_argument("--workload", choices=("city", "diff", "batched"), default="city",
+    p.add_argument("--workload", choices=("city", "diff", "batched", "contrib"), default="city",
                    help="city: the headline FPS line; diff: forward+backward on the 1M "
-                        "differentiable workload; batched: 64 views in one graph")
+                        "differentiable workload; batched: 64 views in one graph; contrib: "
+                        "PSNR versus skipped low-contribution blends (Sec. 2.4, 3.2)")
     p.add_argument("--views", type=int, default=64)
     p.add_argument("--rule", type=int, choices=(0, 1), default=1,
                    help="extent rule of the measured AdaGScale frame: 1 = ellipse tile test "
@@ -401,6 +402,97 @@ def bench_batched(args):
             **out}
 
 
+SKIP_FRACTIONS = (0.2, 0.4, 0.5, 0.6, 0.8)
+
+
+def bench_contrib(args):
+    """The contribution analysis of Sec. 2.4 (Fig. 4(a)) and Sec. 3.2 (Fig. 5)
+    on synthetic scenes: PSNR of a render that skips the lowest-contribution
+    blend operations, against the full render, versus the fraction skipped,
+    for the exact contribution alpha T (eq. 3) and its approximations alpha
+    max(T^i) (this view's per-Gaussian maximum) and alpha T_up(depth) (the
+    16-view calibrated table).  For each target fraction theta is bisected in
+    log space until the skipped fraction is within 0.005 of it (the exact
+    rule's fraction depends on theta through T, so each step is a render).
+    Plain 3D-GS pair lists; every render runs in gs_rasterize_skip."""
+    import torch
+    from paper_2604_18980_amd import calib, gsr, render as R, scenes
+    dev = torch.device("cuda:0")
+    out = {}
+    cases = (("mid 500K 1920x1080", scenes.mid_scene(), scenes.mid_calibration_cameras(CALIB_VIEWS), 150.0),
+             ("city 6M 4608x3456", scenes.city_scene(), scenes.city_calibration_cameras(CALIB_VIEWS),
+              LUT_DEPTH_MAX))
+    for name, (scene_h, cam), cal_cams, dmax in cases:
+        log(f"contrib: {name}")
+        scene = R.DeviceScene.from_host(scene_h, dev)
+        table, _ = calib.t_upper_table(scene, cal_cams, dmax)
+        fb = R.render(scene, cam, slack=1.02)
+        cam_s = gsr.camera_struct(cam)
+        ref = fb.image.clone()
+        mt_bits = torch.zeros(max(scene.n, 1), dtype=torch.int32, device=dev)
+        lut_bits = torch.zeros(gsr.LUT_BINS, dtype=torch.int32, device=dev)
+        gsr.gs_calibrate_t_upper(fb.splats, fb.n, fb.sorted_gids, fb.ranges, cam_s, dmax, lut_bits,
+                                 mt_bits)
+        max_t = mt_bits.view(torch.float32).clone()
+        img = torch.empty_like(fb.image)
+        T = torch.empty_like(fb.final_T)
+        nc = torch.empty_like(fb.n_contrib)
+        counts = torch.zeros(2, dtype=torch.int64, device=dev)
+
+        def run(kind, theta):
+            counts.zero_()
+            gsr.gs_rasterize_skip(fb.splats, fb.n, fb.sorted_gids, fb.ranges, cam_s, (0, 0, 0), kind,
+                                  theta, max_t if kind == 1 else None,
+                                  [float(x) for x in table] if kind == 2 else None, dmax, img, T, nc,
+                                  counts)
+            sk, kept = counts.tolist()
+            return sk / max(sk + kept, 1)
+
+        # timing: one skip render at a mid threshold, HIP events
+        run(0, 1e-3)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(5):
+            gsr.gs_rasterize_skip(fb.splats, fb.n, fb.sorted_gids, fb.ranges, cam_s, (0, 0, 0), 0,
+                                  1e-3, None, None, dmax, img, T, nc, counts)
+        ev[1].record()
+        torch.cuda.synchronize()
+        curves = {}
+        for kind, kname in ((0, "exact alpha T"), (1, "alpha max(T)"), (2, "alpha T_up(depth)")):
+            pts = []
+            for f in SKIP_FRACTIONS:
+                lo, hi = -30.0, 0.0  # log2 theta
+                best = None
+                for _ in range(30):
+                    mid = 0.5 * (lo + hi)
+                    frac = run(kind, 2.0 ** mid)
+                    if best is None or abs(frac - f) < abs(best[1] - f):
+                        best = (2.0 ** mid, frac)
+                    if abs(frac - f) < 0.005:
+                        break
+                    if frac < f:
+                        lo = mid
+                    else:
+                        hi = mid
+                run(kind, best[0])
+                pts.append({"target": f, "skipped": best[1], "theta": best[0],
+                            "psnr_db": psnr_t(torch, img, ref)})
+            curves[kname] = pts
+            log(f"  {kname}: " + ", ".join(f"{p['skipped']:.2f}->{p['psnr_db']:.1f} dB" for p in pts))
+        out[name] = {"pairs": int(fb.num_pairs.item()), "skip_render_ms": ev[0].elapsed_time(ev[1]) / 5,
+                     "t_upper": [float(x) for x in table], "lut_depth_max": dmax, "curves": curves}
+        del fb, scene
+        torch.cuda.empty_cache()
+    return {"metric": "PSNR (dB, against the full render) versus skipped fraction of blend operations, "
+                      "contribution alpha T and its max(T) and T_up(depth) approximations",
+            "value": None, "unit": "dB", "n_gpus": 1, "steps": None, "warmup": None,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "contribution analysis: mid 500K 1920x1080 and city 6M 4608x3456, "
+                                   "plain 3D-GS lists"},
+            **out}
+
+
 def copy_probe(mib):
     import torch
     x = torch.empty(mib * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
@@ -445,6 +537,9 @@ def main():
         return
     if args.workload == "batched":
         print(json.dumps(bench_batched(args)))
+        return
+    if args.workload == "contrib":
+        print(json.dumps(bench_contrib(args)))
         return
 
     gsr.load()

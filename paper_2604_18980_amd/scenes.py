@@ -309,6 +309,17 @@ def city_calibration_cameras(n_views=16, seed=99, width=4608, height=3456):
     return cams
 
 
+def mid_calibration_cameras(n_views=16, seed=98, width=1920, height=1080):
+    """Calibration viewpoints for the mid scene: eye (U(-8, 8), U(-4, 4),
+    -35 + U(-5, 5)) looking at the origin, none equal to the measured view."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cams = []
+    for _ in range(n_views):
+        eye = np.array([rng.uniform(-8, 8), rng.uniform(-4, 4), -35.0 + rng.uniform(-5, 5)])
+        cams.append(look_camera(tuple(eye), tuple(-eye / np.linalg.norm(eye)), (0, -1, 0), width, height))
+    return cams
+
+
 def diff_workload(n=1_000_000, seed=0, target_seed=7):
     """Differentiable-render workload: the mid-scene generator at N=1M viewed at
     1280x720, with a seeded random target image U[0,1)^(3xHxW)."""
