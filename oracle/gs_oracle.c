@@ -235,6 +235,116 @@ static void ellipse_row_span(const ellipse_t *e, int ty, int cx0, int cx1, int *
     *a = (int)fa; *b = (int)fb;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Oriented-box tile test (extent rule 2): the OBB test of the prior work    */
+/* (GSCore, Sec. 2.3 Fig. 3(b)).  The box is centred on the projected mean,  */
+/* along the eigenvectors of the 2D covariance, with half-lengths 3 sqrt of  */
+/* the eigenvalues times the AdaGScale scale s (1 plain): the same 3-sigma   */
+/* extent as the rectangle rule, oriented.  A tile is kept when its pixel    */
+/* box [16 tx, 16 tx + 15] x [16 ty, 16 ty + 15] meets the OBB: per tile row, */
+/* the x-range of the OBB inside the row's band is spanned by the vertices   */
+/* in the band and the edges' crossings of the band's two lines.  The        */
+/* covariance is recovered from the float32 record (A, beta, gamma):         */
+/* a = 1/A + beta^2/gamma, b = -beta/gamma, c = 1/gamma.  Candidates are the  */
+/* rectangle rule's tiles, so the test only removes tiles.                   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double vx[4], vy[4], k[4], ymin, ymax;
+    int ok;
+} obb_t;
+
+static void obb_setup(double u, double v, double A, double beta, double gamma, double s, obb_t *o) {
+    o->ok = 0;
+    if (!(is_finite(u) && is_finite(v) && is_finite(A) && is_finite(beta) && is_finite(gamma) &&
+          is_finite(s)))
+        return;
+    if (!(A > 0.0 && gamma > 0.0 && s > 0.0)) return;
+    double a = 1.0 / A + (beta * beta) / gamma, b = -(beta / gamma), c = 1.0 / gamma;
+    double mid = 0.5 * (a + c), det = a * c - b * b;
+    double disc = mid * mid - det;
+    if (!(disc > 0.0)) disc = 0.0;
+    double sq = sqrt(disc), l1 = mid + sq, l2 = mid - sq;
+    if (!(l2 > 0.0)) l2 = 0.0;
+    /* major eigenvector: (b, l1 - a) or (l1 - c, b), whichever is longer */
+    double px = b, py = l1 - a, qx = l1 - c, qy = b;
+    double np = px * px + py * py, nq = qx * qx + qy * qy;
+    double ex = np >= nq ? px : qx, ey = np >= nq ? py : qy, nn = np >= nq ? np : nq;
+    if (nn > 0.0) {
+        double r = sqrt(nn);
+        ex = ex / r;
+        ey = ey / r;
+    } else {
+        ex = 1.0;
+        ey = 0.0;
+    }
+    double h1 = (3.0 * sqrt(l1)) * s, h2 = (3.0 * sqrt(l2)) * s;
+    double ax = h1 * ex, ay = h1 * ey, bx = -(h2 * ey), by = h2 * ex;
+    /* vertices in order around the box: +a+b, +a-b, -a-b, -a+b */
+    o->vx[0] = (u + ax) + bx; o->vy[0] = (v + ay) + by;
+    o->vx[1] = (u + ax) - bx; o->vy[1] = (v + ay) - by;
+    o->vx[2] = (u - ax) - bx; o->vy[2] = (v - ay) - by;
+    o->vx[3] = (u - ax) + bx; o->vy[3] = (v - ay) + by;
+    o->ymin = o->vy[0]; o->ymax = o->vy[0];
+    for (int i = 0; i < 4; ++i) {
+        int j = (i + 1) & 3;
+        double dy = o->vy[j] - o->vy[i];
+        o->k[i] = dy != 0.0 ? (o->vx[j] - o->vx[i]) / dy : 0.0;
+        if (o->vy[i] < o->ymin) o->ymin = o->vy[i];
+        if (o->vy[i] > o->ymax) o->ymax = o->vy[i];
+    }
+    if (!(is_finite(o->ymin) && is_finite(o->ymax))) return;
+    for (int i = 0; i < 4; ++i)
+        if (!(is_finite(o->vx[i]) && is_finite(o->k[i]))) return;
+    o->ok = 1;
+}
+
+/* Tile columns [*a, *b] of row ty that meet the box, clipped to [cx0, cx1]. */
+static void obb_row_span(const obb_t *o, int ty, int cx0, int cx1, int *a, int *b) {
+    double y0 = (double)(TILE * ty), y1 = y0 + (double)(TILE - 1);
+    *a = 1; *b = 0;
+    if (y1 < o->ymin || y0 > o->ymax) return;
+    double xmin = INFINITY, xmax = -INFINITY;
+    for (int i = 0; i < 4; ++i) {
+        if (o->vy[i] >= y0 && o->vy[i] <= y1) {
+            if (o->vx[i] < xmin) xmin = o->vx[i];
+            if (o->vx[i] > xmax) xmax = o->vx[i];
+        }
+        int j = (i + 1) & 3;
+        double ya = o->vy[i], yb = o->vy[j];
+        if (ya == yb) continue;
+        for (int e = 0; e < 2; ++e) {
+            double yl = e ? y1 : y0;
+            if ((yl - ya) * (yl - yb) <= 0.0) {
+                double x = o->vx[i] + (yl - ya) * o->k[i];
+                if (x < xmin) xmin = x;
+                if (x > xmax) xmax = x;
+            }
+        }
+    }
+    if (!(xmin <= xmax)) return;
+    double fa = ceil((xmin - (double)(TILE - 1)) / (double)TILE);
+    double fb = floor(xmax / (double)TILE);
+    fa = fa >= (double)cx0 ? fa : (double)cx0;
+    fb = fb <= (double)cx1 ? fb : (double)cx1;
+    if (fa > (double)cx1 || fb < (double)cx0 || fb < fa) return;
+    *a = (int)fa; *b = (int)fb;
+}
+
+int orc_obb_spans(double u, double v, double A, double beta, double gamma, double s, int ty0,
+                  int ty1, int cx0, int cx1, int32_t *spans, double *verts) {
+    obb_t o;
+    obb_setup(u, v, A, beta, gamma, s, &o);
+    for (int ty = ty0; ty < ty1; ++ty) {
+        int a = 1, b = 0;
+        if (o.ok) obb_row_span(&o, ty, cx0, cx1, &a, &b);
+        spans[2 * (ty - ty0)] = a;
+        spans[2 * (ty - ty0) + 1] = b;
+    }
+    if (verts)
+        for (int i = 0; i < 4; ++i) { verts[2 * i] = o.vx[i]; verts[2 * i + 1] = o.vy[i]; }
+    return o.ok;
+}
+
 /* Python-facing form of the row test for the pins: spans[2 * (ty - ty0)]. */
 int orc_ellipse_spans(double u, double v, double A, double beta, double gamma, double sigma,
                       double t, int ty0, int ty1, int cx0, int cx1, int32_t *spans) {
@@ -261,7 +371,8 @@ int orc_ellipse_spans(double u, double v, double A, double beta, double gamma, d
 /* (dilated a, b, c), extent (plain v), th, scale, rect[4] (x0, y0, x1, y1    */
 /* half-open, tiles), tiles_touched, radius (int).                           */
 /* flags: 0 culled, 1 projected (finite, in front), 2 projected with tiles.   */
-/* extent_rule 0: the rectangle of radius ceil(v s) (s = 1 when plain) and   */
+/* extent_rule 0 (and 2, whose oriented box pair generation then tests):    */
+/* the rectangle of radius ceil(v s) (s = 1 when plain) and                  */
 /* tiles_touched = its area.  extent_rule 1: the plain radius-ceil(v)         */
 /* rectangle and its area, the candidates that pair generation then tests    */
 /* against the alpha >= th ellipse (Sec. 3.3 applies Th in that stage).      */
@@ -391,7 +502,7 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
             th[g] = thv;
             scale[g] = sv;
             if (!keep) continue;
-            if (extent_rule == 0) ext = ext * sv;  /* rule 1: Th enters at pair generation */
+            if (extent_rule != 1) ext = ext * sv;  /* rule 1: Th enters at pair generation */
         }
         double rd = ceil(ext);
         if (rd > 1073741824.0) rd = 1073741824.0; /* 2^30 px: covers any image */
@@ -432,12 +543,14 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
 /* ------------------------------------------------------------------------ */
 /* Pair emission (Sec. 2.1): Gaussians in index order, tile rows outer,       */
 /* columns inner.  key = tile << 32 | bits(float32 depth), value = index.    */
-/* Rule 0 emits the whole rectangle; rule 1 each row's ellipse span, from    */
-/* the float32 record values the renderer blends.                            */
+/* Rule 0 emits the whole rectangle; rule 1 each row's ellipse span and      */
+/* rule 2 each row's oriented-box span, from the float32 record values the   */
+/* renderer blends.                                                          */
 /* ------------------------------------------------------------------------ */
 int64_t orc_emit(int64_t n, const int32_t *rect, const int64_t *tiles_touched, const float *depth_f32,
                  int width, int extent_rule, const double *mean2d, const double *quad,
-                 const double *opacity, const double *th, uint64_t *keys, uint32_t *vals) {
+                 const double *opacity, const double *th, const double *scale, uint64_t *keys,
+                 uint32_t *vals) {
     int TX = (width + TILE - 1) / TILE;
     int64_t p = 0;
     for (int64_t g = 0; g < n; ++g) {
@@ -445,15 +558,21 @@ int64_t orc_emit(int64_t n, const int32_t *rect, const int64_t *tiles_touched, c
         uint32_t dbits;
         memcpy(&dbits, &depth_f32[g], 4);
         ellipse_t e;
+        obb_t ob;
         if (extent_rule == 1) {
             ellipse_setup(f32r(mean2d[2 * g]), f32r(mean2d[2 * g + 1]), f32r(quad[3 * g]),
                           f32r(quad[3 * g + 1]), f32r(quad[3 * g + 2]), f32r(opacity[g]),
                           f32r(th[g]), &e);
             if (!e.ok) continue;
+        } else if (extent_rule == 2) {
+            obb_setup(f32r(mean2d[2 * g]), f32r(mean2d[2 * g + 1]), f32r(quad[3 * g]),
+                      f32r(quad[3 * g + 1]), f32r(quad[3 * g + 2]), f32r(scale[g]), &ob);
+            if (!ob.ok) continue;
         }
         for (int ty = rect[4 * g + 1]; ty < rect[4 * g + 3]; ++ty) {
             int a = rect[4 * g], b = rect[4 * g + 2] - 1;
             if (extent_rule == 1) ellipse_row_span(&e, ty, a, b, &a, &b);
+            if (extent_rule == 2) obb_row_span(&ob, ty, a, b, &a, &b);
             for (int tx = a; tx <= b; ++tx) {
                 if (keys) {
                     keys[p] = ((uint64_t)(uint32_t)(ty * TX + tx) << 32) | dbits;

@@ -58,7 +58,9 @@ def lib():
         L.orc_preprocess.argtypes = ([C.c_int64, P, P, P, P, P, C.c_int, P, C.c_int, C.c_int,
                                       C.c_int, C.c_double, P, C.c_double, C.c_int, C.c_int]
                                      + [P] * 14)
-        L.orc_emit.argtypes = [C.c_int64, P, P, P, C.c_int, C.c_int, P, P, P, P, P, P]
+        L.orc_emit.argtypes = [C.c_int64, P, P, P, C.c_int, C.c_int, P, P, P, P, P, P, P]
+        L.orc_obb_spans.argtypes = [C.c_double] * 6 + [C.c_int] * 4 + [P, P]
+        L.orc_obb_spans.restype = C.c_int
         L.orc_ellipse_spans.argtypes = [C.c_double] * 7 + [C.c_int] * 4 + [P]
         L.orc_ellipse_spans.restype = C.c_int
         L.orc_emit.restype = C.c_int64
@@ -106,7 +108,7 @@ class Mode:
     t_upper: np.ndarray = None
     lut_depth_max: float = 100.0
     force_unit_scale: bool = False
-    extent_rule: int = 0   # 0: tile rectangle; 1: tiles meeting the alpha >= Th ellipse
+    extent_rule: int = 0   # 0: tile rectangle; 1: alpha >= Th ellipse; 2: oriented 3-sigma box
 
     def lut(self):
         return _f32(self.t_upper if self.t_upper is not None else default_lut())
@@ -177,13 +179,26 @@ def emit(pre: Preproc, cam):
     L = lib()
     n = pre.rect.shape[0]
     d32 = _f32(pre.depth_f32)
-    geo = [_p(np.ascontiguousarray(a, np.float64)) for a in (pre.mean2d, pre.quad, pre.opacity, pre.th)]
+    geo_arrays = [np.ascontiguousarray(a, np.float64)
+                  for a in (pre.mean2d, pre.quad, pre.opacity, pre.th, pre.scale)]
+    geo = [_p(a) for a in geo_arrays]
     args = (n, _p(pre.rect), _p(pre.tiles_touched), _p(d32), cam["width"], pre.extent_rule, *geo)
     np_ = L.orc_emit(*args, None, None)
     keys = np.zeros(max(np_, 1), np.uint64)
     vals = np.zeros(max(np_, 1), np.uint32)
     L.orc_emit(*args, _p(keys), _p(vals))
     return keys[:np_], vals[:np_]
+
+
+def obb_spans(u, v, A, beta, gamma, s, ty0, ty1, cx0, cx1):
+    """Rule-2 row test on explicit values: (ok, spans[rows][2], vertices[4][2])
+    of the oriented 3-sigma box (scaled by s) of the covariance recovered from
+    (A, beta, gamma)."""
+    spans = np.zeros((max(ty1 - ty0, 0), 2), np.int32)
+    verts = np.zeros((4, 2))
+    ok = lib().orc_obb_spans(float(u), float(v), float(A), float(beta), float(gamma), float(s),
+                             int(ty0), int(ty1), int(cx0), int(cx1), _p(spans), _p(verts))
+    return bool(ok), spans, verts
 
 
 def ellipse_spans(u, v, A, beta, gamma, sigma, t, ty0, ty1, cx0, cx1):

@@ -844,3 +844,107 @@ def test_skip_blend_huge_theta_and_monotone(O):
     for kind, kw in ((1, dict(weight=mt)), (2, dict(lut=np.linspace(1, 0.1, 20)))):
         counts = [O.blend_skip(fr, cam, kind, th, **kw)[5] for th in (0.0, 0.01, 0.05, 0.2, 0.5)]
         assert counts == sorted(counts) and counts[0] == 0 and counts[-1] > counts[1]
+
+
+# --------------------------------------------------------------------------- oriented-box tile test (rule 2)
+def _box_meets_polygon(verts, X0, X1, Y0, Y1, eps=0.0):
+    """Separating-axis test of an axis-aligned box against a convex polygon:
+    returns the largest separation gap over the candidate axes (<= 0: they
+    meet)."""
+    box = np.array([[X0, Y0], [X1, Y0], [X1, Y1], [X0, Y1]])
+    axes = [np.array([1.0, 0.0]), np.array([0.0, 1.0])]
+    for i in range(len(verts)):
+        e = verts[(i + 1) % len(verts)] - verts[i]
+        nrm = np.array([-e[1], e[0]])
+        if np.linalg.norm(nrm) > 0:
+            axes.append(nrm / np.linalg.norm(nrm))
+    gap = -np.inf
+    for ax in axes:
+        p, q = verts @ ax, box @ ax
+        gap = max(gap, max(q.min() - p.max(), p.min() - q.max()))
+    return gap
+
+
+def test_obb_vertices_are_the_scaled_eigenbox(O):
+    """The box's vertices are the mean +- 3 s sqrt(lambda_i) e_i of the
+    covariance recovered from (A, beta, gamma), against numpy's eigh."""
+    rng = np.random.default_rng(61)
+    for _ in range(100):
+        sx, sy = np.exp(rng.uniform(-0.5, 3.0, 2))
+        th = rng.uniform(0, np.pi)
+        c_, s_ = np.cos(th), np.sin(th)
+        S = np.array([[c_ * c_ * sx * sx + s_ * s_ * sy * sy, c_ * s_ * (sx * sx - sy * sy)],
+                      [c_ * s_ * (sx * sx - sy * sy), s_ * s_ * sx * sx + c_ * c_ * sy * sy]])
+        a, b, c = S[0, 0], S[0, 1], S[1, 1]
+        det = a * c - b * b
+        A, beta, gamma = c / det, -b / c, 1.0 / c
+        u, v, sc = rng.uniform(0, 100, 2).tolist() + [rng.uniform(0.2, 1.0)]
+        ok, _, verts = O.obb_spans(u, v, A, beta, gamma, sc, 0, 1, 0, 10)
+        assert ok
+        lam, vec = np.linalg.eigh(S)
+        h = 3 * np.sqrt(lam) * sc
+        want = [np.array([u, v]) + s1 * h[1] * vec[:, 1] + s2 * h[0] * vec[:, 0]
+                for s1 in (1, -1) for s2 in (1, -1)]
+        for w in want:  # every eigen-box corner is one of the vertices
+            assert np.min(np.linalg.norm(verts - w, axis=1)) < 1e-9 * (1 + h.max())
+
+
+def test_obb_spans_match_separating_axis_test(O):
+    """The row spans are exactly the tiles whose pixel box meets the oriented
+    box (separating-axis test), on random boxes; tiles within 1e-9 px of
+    touching are not judged."""
+    rng = np.random.default_rng(62)
+    checked = 0
+    for it in range(300):
+        sx, sy = np.exp(rng.uniform(-0.5, 3.5, 2))
+        th = rng.uniform(0, np.pi)
+        c_, s_ = np.cos(th), np.sin(th)
+        a = c_ * c_ * sx * sx + s_ * s_ * sy * sy
+        b = c_ * s_ * (sx * sx - sy * sy)
+        c = s_ * s_ * sx * sx + c_ * c_ * sy * sy
+        det = a * c - b * b
+        A, beta, gamma = c / det, -b / c, 1.0 / c
+        u, v = rng.uniform(-40, 200, 2)
+        sc = rng.choice([1.0, rng.uniform(0.1, 1.0)])
+        ok, spans, verts = O.obb_spans(u, v, A, beta, gamma, sc, 0, 12, 0, 11)
+        assert ok
+        for ty in range(12):
+            for tx in range(12):
+                gap = _box_meets_polygon(verts, 16 * tx, 16 * tx + 15, 16 * ty, 16 * ty + 15)
+                if abs(gap) <= 1e-9:
+                    continue
+                got = spans[ty, 0] <= tx <= spans[ty, 1]
+                assert got == (gap < 0), (it, ty, tx, gap, spans[ty])
+                checked += 1
+    assert checked > 40000
+
+
+@pytest.mark.parametrize("adagscale,K", [(False, 0.0), (True, 0.3)])
+def test_rule2_pairs_cover_the_extent_ellipse(O, adagscale, K):
+    """Rule 2 on a tiny scene: the rectangle and tile count are rule 0's (the
+    candidates), the pairs are a subset of rule 0's, and every pixel of the
+    rectangle within the 3 s sigma ellipse (Mahalanobis distance <= 3 s,
+    which the oriented box contains) lies in an emitted tile."""
+    sc, _ = scenes.tiny_scene(n=300, seed=63)
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 100, 70)
+    p0 = O.preprocess(sc, cam, O.Mode(adagscale=adagscale, K=K))
+    p2 = O.preprocess(sc, cam, O.Mode(adagscale=adagscale, K=K, extent_rule=2))
+    np.testing.assert_array_equal(p2.rect, p0.rect)
+    np.testing.assert_array_equal(p2.tiles_touched, p0.tiles_touched)
+    k0, v0 = O.emit(p0, cam)
+    k2, v2 = O.emit(p2, cam)
+    assert _pair_sets(k2, v2) <= _pair_sets(k0, v0) and k2.size < k0.size
+    TX = (cam["width"] + 15) // 16
+    py, px = np.mgrid[0:70, 0:100]
+    f32 = lambda x: float(np.float32(x))
+    for g in np.nonzero(p2.tiles_touched > 0)[0]:
+        tiles = set(int(t) for t in (k2[v2 == g] >> np.uint64(32)))
+        u, v = f32(p2.mean2d[g, 0]), f32(p2.mean2d[g, 1])
+        A, beta, gamma = (f32(x) for x in p2.quad[g])
+        s = f32(p2.scale[g])
+        X, Y = px - u, py - v
+        q = A * (X + beta * Y) ** 2 + gamma * Y * Y
+        x0, y0, x1, y1 = p2.rect[g]
+        inrect = (px // 16 >= x0) & (px // 16 < x1) & (py // 16 >= y0) & (py // 16 < y1)
+        inside = (q <= (3 * s) ** 2 * (1 - 1e-9)) & inrect
+        assert set(((py[inside] // 16) * TX + px[inside] // 16).tolist()) <= tiles
