@@ -78,9 +78,10 @@ def parse():
                         "differentiable workload; batched: 64 views in one graph; contrib: "
                         "PSNR versus skipped low-contribution blends (Sec. 2.4, 3.2)")
     p.add_argument("--views", type=int, default=64)
-    p.add_argument("--rule", type=int, choices=(0, 1), default=1,
+    p.add_argument("--rule", type=int, choices=(0, 1, 2), default=1,
                    help="extent rule of the measured AdaGScale frame: 1 = ellipse tile test "
-                        "(default), 0 = tile rectangle; the other rule is measured beside it")
+                        "(default), 0 = tile rectangle, 2 = oriented box; the other rules are "
+                        "measured beside it")
     p.add_argument("--uncalibrated", action="store_true",
                    help="AdaGScale with the trivial bound T_upper = 1 instead of the calibrated "
                         "table (no calibration runs)")
@@ -266,13 +267,13 @@ def cpu_baseline(args, scene_h, cam, K, n_tiles_sample, t_upper=None, lut_depth_
     d32 = pre.depth.astype(np.float32)
     lists, ranges = [], np.zeros((TX * TY, 2), np.int64)
     off = 0
-    if extent_rule == 1:  # the sampled tiles' members from the whole emission (not timed)
+    if extent_rule != 0:  # the sampled tiles' members from the whole emission (not timed)
         ek, ev = O.emit(pre, cam)
         e_tile = (ek >> np.uint64(32)).astype(np.int64)
         keep = np.isin(e_tile, tiles)
         e_tile, e_id = e_tile[keep], ev[keep].astype(np.int64)
     for t in tiles:
-        if extent_rule == 1:
+        if extent_rule != 0:
             ids = e_id[e_tile == int(t)]
         else:
             ty, tx = divmod(int(t), TX)
@@ -291,7 +292,7 @@ def cpu_baseline(args, scene_h, cam, K, n_tiles_sample, t_upper=None, lut_depth_
     t_bl = (time.perf_counter() - t0) * (TX * TY) / len(tiles)
     t_frame = t_pre + t_es + t_bl
     return {"value": 1.0 / t_frame, "unit": "FPS", "cores": 1, "kind": "oracle",
-            "sample": (f"AdaGScale K={K:g}, {('rectangle', 'ellipse')[extent_rule]} tile test: "
+            "sample": (f"AdaGScale K={K:g}, {('rectangle', 'ellipse', 'oriented-box')[extent_rule]} tile test: "
                        f"full preprocess of {scene_h.n} Gaussians ({t_pre:.1f} s), "
                        f"emit+sort of a 1/64 sample of visible Gaussians scaled x64 ({t_es:.1f} s), "
                        f"blend of {len(tiles)} random tiles scaled to {TX * TY} tiles ({t_bl:.1f} s); "
@@ -551,8 +552,9 @@ def main():
     scene = R.DeviceScene.from_host(scene_h, dev)
     cam_s = gsr.camera_struct(cam)
     stream = torch.cuda.current_stream()
-    rule, other = args.rule, 1 - args.rule
-    rule_name = {0: "rectangle", 1: "ellipse"}
+    rule = args.rule
+    others = [r for r in (0, 1, 2) if r != rule]
+    rule_name = {0: "rectangle", 1: "ellipse", 2: "oriented_box"}
 
     # offline calibration of the T_upper table (not part of a frame; skipped
     # with --uncalibrated, which uses the trivial bound instead)
@@ -600,14 +602,18 @@ def main():
         psnr = psnr_t(torch, fb_a.image, ref)
         ssim = ssim_t(torch, fb_a.image, ref)
         log(f"{rule_name[rule]}: K={K} pairs {P_ada} psnr {psnr:.2f} ssim {ssim:.4f}")
-        # AdaGScale under the other extent rule, searched to the same PSNR target
-        K_o = search_K(torch, R, gsr, scene, cam, cam_s, fb_p, fb_a, stream, extent_rule=other, **ada)
-        fb_o = R.render(scene, cam, adagscale=True, K=K_o, fb=None, slack=1.05, extent_rule=other,
-                        **ada)
-        torch.cuda.synchronize()
-        P_o = int(fb_o.num_pairs.item())
-        psnr_o = psnr_t(torch, fb_o.image, ref)
-        log(f"{rule_name[other]}: K={K_o} pairs {P_o} psnr {psnr_o:.2f}")
+        # AdaGScale under the other extent rules, each searched to the same PSNR target
+        other_runs = []
+        for other in others:
+            K_o = search_K(torch, R, gsr, scene, cam, cam_s, fb_p, fb_a, stream, extent_rule=other,
+                           **ada)
+            fb_o = R.render(scene, cam, adagscale=True, K=K_o, fb=None, slack=1.05,
+                            extent_rule=other, **ada)
+            torch.cuda.synchronize()
+            P_o = int(fb_o.num_pairs.item())
+            psnr_o = psnr_t(torch, fb_o.image, ref)
+            log(f"{rule_name[other]}: K={K_o} pairs {P_o} psnr {psnr_o:.2f}")
+            other_runs.append((other, K_o, fb_o, P_o, psnr_o))
         if not args.uncalibrated:
             # the same search and timing with the trivial bound, for comparison
             K_u = search_K(torch, R, gsr, scene, cam, cam_s, fb_p, fb_a, stream, extent_rule=rule,
@@ -624,11 +630,12 @@ def main():
             log(f"uncalibrated: K={K_u} pairs {P_u} psnr {psnr_u:.2f} "
                 f"fps {extra['adagscale_uncalibrated']['fps']:.1f}")
             del fb_u
-        mode_o = gsr.mode_struct(adagscale=True, K=K_o, extent_rule=other, **ada)
-        extra[f"adagscale_{rule_name[other]}"] = dict(
-            measure(torch, R, scene, cam_s, mode_o, fb_o, P_o, args, stream), K=K_o,
-            psnr_db_vs_plain=psnr_o, raster_work=raster_work(R, fb_o, cam_s))
-        del fb_o
+        for other, K_o, fb_o, P_o, psnr_o in other_runs:
+            mode_o = gsr.mode_struct(adagscale=True, K=K_o, extent_rule=other, **ada)
+            extra[f"adagscale_{rule_name[other]}"] = dict(
+                measure(torch, R, scene, cam_s, mode_o, fb_o, P_o, args, stream), K=K_o,
+                psnr_db_vs_plain=psnr_o, raster_work=raster_work(R, fb_o, cam_s))
+        del other_runs, fb_o
     W_ada = raster_work(R, fb_a, cam_s)
 
     mode_a = gsr.mode_struct(adagscale=True, K=K, extent_rule=rule, **ada)

@@ -108,15 +108,21 @@ typedef struct {
  *   its area as the candidates, and gs_emit_pairs / gs_bin_pairs keep only the
  *   candidate tiles whose pixel box [16 tx, 16 tx + 15] x [16 ty, 16 ty + 15]
  *   meets the ellipse alpha >= t, t = Th under AdaGScale and tau otherwise,
- *   evaluated in double from the float32 splat record.  The same rule must be
- *   passed to gs_emit_pairs / gs_bin_pairs. */
+ *   evaluated in double from the float32 splat record.
+ * extent_rule = 2: the oriented-box test of the prior work (GSCore, Sec. 2.3
+ *   Fig. 3(b)): gs_preprocess writes rule 0's rectangle and area as the
+ *   candidates, and pair generation keeps the candidate tiles whose pixel box
+ *   meets the box of half-lengths 3 s sqrt(lambda_i) along the eigenvectors of
+ *   the 2D covariance (recovered from the record), s the AdaGScale scale (1
+ *   plain).
+ * The same rule must be passed to gs_emit_pairs / gs_bin_pairs. */
 typedef struct {
     int adagscale;
     float K;                       /* peripheral-loss budget, >= 0 (eq. 5) */
     float t_upper[GS_LUT_BINS];    /* T_up per depth bin, in [0, 1]; all 1 = uncalibrated */
     float lut_depth_max;           /* > 0; the paper's range is 100 */
     int force_unit_scale;
-    int extent_rule;               /* 0 rectangle, 1 ellipse; other values are rejected */
+    int extent_rule;               /* 0 rectangle, 1 ellipse, 2 oriented box; others rejected */
 } gs_mode;
 
 /* Raster launch geometry.  Tiles stay 16x16 so pair sets are comparable.
@@ -161,12 +167,12 @@ gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_mo
  * already reflects AdaGScale's extent under rule 0, and the ellipse of Th is
  * applied here under rule 1).  Emits one (tile, Gaussian) pair per tile of
  * each rectangle (extent_rule 0), or per rectangle tile that meets the
- * Gaussian's ellipse (extent_rule 1, from the splat records; pass the rule
- * gs_preprocess ran with).  Pairs
+ * Gaussian's ellipse (extent_rule 1) or oriented box (extent_rule 2), from the
+ * splat records; pass the rule gs_preprocess ran with.  Pairs
  * are emitted Gaussian by Gaussian in ascending (float32 depth, Gaussian id)
  * order, tile rows outer, columns inner; a stable sort by tile of this list is
- * therefore the paper's per-tile depth order.  extent_rule other than 0 or 1
- * is rejected (GS_ERR_INVALID_ARGUMENT).
+ * therefore the paper's per-tile depth order.  extent_rule outside 0..2 is
+ * rejected (GS_ERR_INVALID_ARGUMENT).
  * num_pairs (device int64) receives the number of pairs REQUIRED; at most
  * pair_capacity pairs are written.  When *num_pairs > pair_capacity the
  * caller must grow the buffers and run the frame again (stages 3-4 then see a
@@ -197,8 +203,8 @@ gs_status gs_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids, const i
  * the pairs are generated on the fly from the depth-ordered rectangles and
  * sorted by tile with two 8-bit passes of one 32-bit word per pair (one pass
  * when the image has at most 256 tiles; with more than 65536 tiles or
- * n >= 2^24 it emits and sorts pairs internally); under rule 1 the pairs are
- * emitted into the workspace and sorted by tile.
+ * n >= 2^24 it emits and sorts pairs internally); under rules 1 and 2 the
+ * pairs are emitted into the workspace and sorted by tile.
  * The ranges come from per-tile counts of the rectangles.
  * Out: sorted_gids [pair_capacity]; sorted_tiles [pair_capacity] or NULL when
  * not wanted; ranges [num_tiles][2] as (start, end), (0, 0) for a tile with no

@@ -222,8 +222,8 @@ gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_mo
             if (!(mode->t_upper[i] >= 0.0f && mode->t_upper[i] <= 1.0f))
                 return fail(GS_ERR_INVALID_ARGUMENT, "mode.t_upper[%d] outside [0, 1]", i);
     }
-    if (mode->extent_rule != 0 && mode->extent_rule != 1)
-        return fail(GS_ERR_INVALID_ARGUMENT, "mode.extent_rule must be 0 or 1");
+    if (mode->extent_rule < 0 || mode->extent_rule > 2)
+        return fail(GS_ERR_INVALID_ARGUMENT, "mode.extent_rule must be 0, 1 or 2");
     if (scene->n > 0 && (!splats || !rects || !tiles_touched))
         return fail(GS_ERR_INVALID_ARGUMENT, "output array is NULL");
     PreprocessArgs a;
@@ -266,8 +266,8 @@ gs_status gs_emit_pairs(const float *splats, const uint64_t *rects, const uint32
                         size_t ws_bytes, void *stream) {
     gs_status st;
     if ((st = check_camera(cam)) != GS_OK) return st;
-    if (extent_rule != 0 && extent_rule != 1)
-        return fail(GS_ERR_INVALID_ARGUMENT, "extent_rule must be 0 or 1");
+    if (extent_rule < 0 || extent_rule > 2)
+        return fail(GS_ERR_INVALID_ARGUMENT, "extent_rule must be 0, 1 or 2");
     if (n < 0 || n >= ((int64_t)1 << 31))
         return fail(GS_ERR_INVALID_ARGUMENT, "n = %lld outside [0, 2^31)", (long long)n);
     if (pair_capacity < 0 || pair_capacity > (int64_t)0xffffffffLL)
@@ -293,8 +293,8 @@ gs_status gs_bin_pairs(const float *splats, const uint64_t *rects, const uint32_
                        int64_t *num_pairs, void *ws, size_t ws_bytes, void *stream) {
     gs_status st;
     if ((st = check_camera(cam)) != GS_OK) return st;
-    if (extent_rule != 0 && extent_rule != 1)
-        return fail(GS_ERR_INVALID_ARGUMENT, "extent_rule must be 0 or 1");
+    if (extent_rule < 0 || extent_rule > 2)
+        return fail(GS_ERR_INVALID_ARGUMENT, "extent_rule must be 0, 1 or 2");
     if (n < 0 || n >= ((int64_t)1 << 31))
         return fail(GS_ERR_INVALID_ARGUMENT, "n = %lld outside [0, 2^31)", (long long)n);
     if (pair_capacity < 0 || pair_capacity > (int64_t)0xffffffffLL)

@@ -23,9 +23,9 @@
 // histogram give the lists for free -- tile (h, l) occupies
 // [offs(h, first block of l), offs(h, first block of l + 1)).  With at most 256
 // tiles, pass 1 writes the final lists directly and its bucket starts are the
-// ranges.  Beyond the packed limits, and under the ellipse extent rule (whose
-// per-Gaussian pairs are row spans, not a rectangle), the path emits pairs
-// and sorts them.
+// ranges.  Beyond the packed limits, and under the ellipse and oriented-box
+// extent rules (whose per-Gaussian pairs are row spans, not a rectangle), the
+// path emits pairs and sorts them.
 //
 // If the pair count exceeds the capacity, nothing is binned: every range is
 // empty and num_pairs holds the required count.
@@ -387,9 +387,10 @@ hipError_t launch_bin(const float *splats, const uint64_t *rects, const uint32_t
     }
     const int64_t nb = ws.nb_psort;  // slices = sort blocks = ceil(cap / 4096)
     const bool packed = bin_packed(n, tiles_x, tiles_y);
-    if (!packed || extent_rule == 1) {
-        // generic route (and the ellipse rule, whose pairs are not a rectangle
-        // enumeration): emit the pairs, sort them by tile (nothing if over), ranges
+    if (!packed || extent_rule != 0) {
+        // generic route (and the ellipse and oriented-box rules, whose pairs are
+        // not a rectangle enumeration): emit the pairs, sort them by tile
+        // (nothing if over), ranges
         uint32_t *kout = sorted_tiles ? sorted_tiles : ws.bpacked;
         int bits = 0;
         while (bits < 63 && ((int64_t)1 << bits) < ntiles) ++bits;

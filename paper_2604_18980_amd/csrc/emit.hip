@@ -14,12 +14,12 @@
 //   k_emit                              each block writes its pairs contiguously,
 //                                       one pair per thread per step, after an LDS
 //                                       scan of its Gaussians' tile counts
-//   k_emit_spans                        extent rule 1: per wave 64 Gaussians'
-//                                       row spans (ellipse.hpp), written by the
-//                                       whole wave
+//   k_emit_spans                        extent rules 1 and 2: per wave 64
+//                                       Gaussians' row spans (tile_shapes.hpp),
+//                                       written by the whole wave
 //                                       (Gaussians with long row bands: one at a
 //                                       time by the whole wave, a row per lane)
-#include "ellipse.hpp"
+#include "tile_shapes.hpp"
 #include "gsr_internal.hpp"
 
 namespace gsr {
@@ -106,35 +106,18 @@ __global__ __launch_bounds__(256) void k_vis_compact(const uint32_t *tiles_touch
     if (threadIdx.x == 0 && b == (int64_t)gridDim.x - 1) *num_vis = (int64_t)(before + tot);
 }
 
-// Reads lane `src` (wave-uniform) of a register: v_readlane, a scalar read,
-// instead of a cross-lane permute through the LDS crossbar.
-__device__ __forceinline__ uint32_t lane_u32(uint32_t x, int src) {
-    return (uint32_t)__builtin_amdgcn_readlane((int)x, src);
-}
-__device__ __forceinline__ int lane_i32(int x, int src) { return __builtin_amdgcn_readlane(x, src); }
-__device__ __forceinline__ uint64_t lane_u64(uint64_t x, int src) {
-    return (uint64_t)lane_u32((uint32_t)x, src) | ((uint64_t)lane_u32((uint32_t)(x >> 32), src) << 32);
-}
-__device__ __forceinline__ double lane_f64(double x, int src) {
-    return __longlong_as_double((long long)lane_u64((uint64_t)__double_as_longlong(x), src));
-}
-
-// Broadcast of one lane's ellipse and row range to the whole wave.
-struct WaveGaussian {
-    Ellipse e;
+// Broadcast of one lane's shape and row range to the whole wave.
+template <class Shape>
+struct WaveShape {
+    Shape e;
     int x0, x1, ra, rb;
 };
-__device__ __forceinline__ WaveGaussian wave_broadcast(const Ellipse &e, int x0, int x1, int ra, int rb,
-                                                       int src) {
-    WaveGaussian w;
-    w.e.u = lane_f64(e.u, src);
-    w.e.v = lane_f64(e.v, src);
-    w.e.A = lane_f64(e.A, src);
-    w.e.beta = lane_f64(e.beta, src);
-    w.e.gamma = lane_f64(e.gamma, src);
-    w.e.c = lane_f64(e.c, src);
-    w.e.R = lane_f64(e.R, src);
-    w.e.w = lane_f64(e.w, src);
+template <class Shape>
+__device__ __forceinline__ WaveShape<Shape> wave_broadcast(const Shape &e, int x0, int x1, int ra, int rb,
+                                                           int src) {
+    WaveShape<Shape> w;
+    w.e = e;
+    w.e.broadcast(src);
     w.x0 = lane_i32(x0, src);
     w.x1 = lane_i32(x1, src);
     w.ra = lane_i32(ra, src);
@@ -149,6 +132,54 @@ __device__ __forceinline__ WaveGaussian wave_broadcast(const Ellipse &e, int x0,
 // span arithmetic of rule 1 keeps the lanes busy.  A Gaussian whose row band
 // is longer than kSmallRows is counted afterwards by its whole wave, one row
 // per lane, so no lane walks a giant's rows alone.
+// Pair count of one visible Gaussian under a shape rule: its tiles meeting the
+// shape, or the whole wave's long-band Gaussians afterwards (see below).
+template <class Shape>
+__device__ __forceinline__ uint64_t shape_pair_count(const float *splats, const uint64_t *rects,
+                                                     uint32_t g, bool valid) {
+    const int lane = threadIdx.x & (kWave - 1);
+    Shape e;
+    int x0 = 0, x1 = 0, ra = 0, rb = 0;
+    bool big = false;
+    uint64_t c = 0;
+    if (valid) {
+        const uint64_t r = rects[g];
+        if (e.setup(splats + (size_t)g * 12)) {
+            x0 = (int)(r & 0xffff);
+            x1 = (int)((r >> 32) & 0xffff);
+            e.row_band((int)((r >> 16) & 0xffff), (int)(r >> 48), ra, rb);
+            big = rb - ra > kSmallRows;
+            if (!big) {
+                for (int ty = ra; ty < rb; ++ty) {
+                    int a, b;
+                    if (e.row_span(ty, x0, x1 - 1, a, b)) c += (uint64_t)(b - a + 1);
+                }
+            }
+        }
+    }
+    // the wave's long-band Gaussians, one at a time, a row per lane
+    for (uint64_t m = __ballot(big); m; m &= m - 1) {  // wave-uniform
+        const int src = __ffsll((long long)m) - 1;
+        const WaveShape<Shape> w = wave_broadcast(e, x0, x1, ra, rb, src);
+        uint32_t part = 0;
+        for (int ty = w.ra + lane; ty < w.rb; ty += kWave) {
+            int a, b;
+            if (w.e.row_span(ty, w.x0, w.x1 - 1, a, b)) part += (uint32_t)(b - a + 1);
+        }
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
+        if (lane == src) c = part;
+    }
+    return c;
+}
+
+// Pairs of each depth-sorted visible Gaussian (one per thread), added to the
+// total of its chunk of 4096 (cleared by k_vis_count): the rectangle's area
+// (tiles_touched) under extent rule 0, the count of its tiles that meet the
+// ellipse (rule 1) or the oriented box (rule 2).  The visible Gaussians are
+// dense here, so the FP64 span arithmetic keeps the lanes busy.  A Gaussian
+// whose row band is longer than kSmallRows is counted afterwards by its whole
+// wave, one row per lane, so no lane walks a giant's rows alone.
 template <int RULE>
 __global__ __launch_bounds__(256) void k_pair_counts(const uint32_t *sorted_ids, const int64_t *num_vis,
                                                      const uint32_t *tiles_touched, const float *splats,
@@ -159,43 +190,13 @@ __global__ __launch_bounds__(256) void k_pair_counts(const uint32_t *sorted_ids,
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if ((int64_t)blockIdx.x * 256 >= V) return;  // uniform
     uint64_t c = 0;
+    const uint32_t g = j < V ? sorted_ids[j] : 0u;
     if constexpr (RULE == 0) {
-        if (j < V) c = tiles_touched[sorted_ids[j]];
+        if (j < V) c = tiles_touched[g];
+    } else if constexpr (RULE == 1) {
+        c = shape_pair_count<Ellipse>(splats, rects, g, j < V);
     } else {
-        const int lane = threadIdx.x & (kWave - 1);
-        Ellipse e;
-        int x0 = 0, x1 = 0, ra = 0, rb = 0;
-        bool big = false;
-        if (j < V) {
-            const uint32_t g = sorted_ids[j];
-            const uint64_t r = rects[g];
-            const float *rec = splats + (size_t)g * 12;
-            if (ellipse_setup(rec[0], rec[1], rec[2], rec[3], rec[4], rec[5], rec[7], e)) {
-                x0 = (int)(r & 0xffff);
-                x1 = (int)((r >> 32) & 0xffff);
-                ellipse_row_band(e, (int)((r >> 16) & 0xffff), (int)(r >> 48), ra, rb);
-                big = rb - ra > kSmallRows;
-                if (!big) {
-                    for (int ty = ra; ty < rb; ++ty) {
-                        int a, b;
-                        if (ellipse_row_span(e, ty, x0, x1 - 1, a, b)) c += (uint64_t)(b - a + 1);
-                    }
-                }
-            }
-        }
-        // the wave's long-band Gaussians, one at a time, a row per lane
-        for (uint64_t m = __ballot(big); m; m &= m - 1) {  // wave-uniform
-            const int src = __ffsll((long long)m) - 1;
-            const WaveGaussian w = wave_broadcast(e, x0, x1, ra, rb, src);
-            uint32_t part = 0;
-            for (int ty = w.ra + lane; ty < w.rb; ty += kWave) {
-                int a, b;
-                if (ellipse_row_span(w.e, ty, w.x0, w.x1 - 1, a, b)) part += (uint32_t)(b - a + 1);
-            }
-#pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
-            if (lane == src) c = part;
-        }
+        c = shape_pair_count<OrientedBox>(splats, rects, g, j < V);
     }
     if (j < V) cnt[j] = c;
     uint64_t tot;
@@ -322,6 +323,9 @@ hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
     if (extent_rule == 1)
         k_pair_counts<1><<<(unsigned)ws.nb_gauss, 256, 0, s>>>(ws.dval[1], num_vis, tiles_touched,
                                                               splats, rects, ws.pair_cnt, ws.pair_tot);
+    else if (extent_rule == 2)
+        k_pair_counts<2><<<(unsigned)ws.nb_gauss, 256, 0, s>>>(ws.dval[1], num_vis, tiles_touched,
+                                                              splats, rects, ws.pair_cnt, ws.pair_tot);
     else
         k_pair_counts<0><<<(unsigned)ws.nb_gauss, 256, 0, s>>>(ws.dval[1], num_vis, tiles_touched,
                                                               splats, rects, ws.pair_cnt, ws.pair_tot);
@@ -407,6 +411,7 @@ __device__ __forceinline__ void wave_write_spans(SpanTable &st, uint32_t len, ui
     wave_sync_lds();  // every lane has read the table before it is rewritten
 }
 
+template <class Shape>
 __global__ __launch_bounds__(256) void k_emit_spans(const uint32_t *sorted_ids, const int64_t *num_vis,
                                                     const float *splats, const uint64_t *rects,
                                                     const uint64_t *off, int tiles_x,
@@ -422,7 +427,7 @@ __global__ __launch_bounds__(256) void k_emit_spans(const uint32_t *sorted_ids, 
     uint64_t k = 0;
     uint32_t g = 0;
     int ra = 0, rb = 0, x0 = 0, x1 = 0;
-    Ellipse e;
+    Shape e;
     if (j < V) {
         k = off[j];
         g = sorted_ids[j];
@@ -430,9 +435,8 @@ __global__ __launch_bounds__(256) void k_emit_spans(const uint32_t *sorted_ids, 
         x0 = (int)(r & 0xffff);
         x1 = (int)((r >> 32) & 0xffff);
         const float *rec = splats + (size_t)g * 12;
-        if (k < (uint64_t)cap &&
-            ellipse_setup(rec[0], rec[1], rec[2], rec[3], rec[4], rec[5], rec[7], e)) {
-            ellipse_row_band(e, (int)((r >> 16) & 0xffff), (int)(r >> 48), ra, rb);
+        if (k < (uint64_t)cap && e.setup(rec)) {
+            e.row_band((int)((r >> 16) & 0xffff), (int)(r >> 48), ra, rb);
             big = rb - ra > kSmallRows;
             live = !big;
         }
@@ -445,7 +449,7 @@ __global__ __launch_bounds__(256) void k_emit_spans(const uint32_t *sorted_ids, 
         uint32_t len = 0, t0 = 0;
         if (act) {
             int a, b;
-            if (ellipse_row_span(e, ty, x0, x1 - 1, a, b)) {
+            if (e.row_span(ty, x0, x1 - 1, a, b)) {
                 len = (uint32_t)(b - a + 1);
                 t0 = (uint32_t)ty * (uint32_t)tiles_x + (uint32_t)a;
             }
@@ -457,14 +461,14 @@ __global__ __launch_bounds__(256) void k_emit_spans(const uint32_t *sorted_ids, 
     // long bands: one Gaussian at a time, a row per lane
     for (uint64_t m = __ballot(big); m; m &= m - 1) {  // wave-uniform
         const int src = __ffsll((long long)m) - 1;
-        const WaveGaussian w = wave_broadcast(e, x0, x1, ra, rb, src);
+        const WaveShape<Shape> w = wave_broadcast(e, x0, x1, ra, rb, src);
         uint64_t kb = lane_u64(k, src);
         const uint32_t gb = lane_u32(g, src);
         for (int t = w.ra; t < w.rb; t += kWave) {  // wave-uniform
             const int ty = t + lane;
             uint32_t len = 0, t0 = 0;
             int a, b;
-            if (ty < w.rb && ellipse_row_span(w.e, ty, w.x0, w.x1 - 1, a, b)) {
+            if (ty < w.rb && w.e.row_span(ty, w.x0, w.x1 - 1, a, b)) {
                 len = (uint32_t)(b - a + 1);
                 t0 = (uint32_t)ty * (uint32_t)tiles_x + (uint32_t)a;
             }
@@ -488,9 +492,11 @@ hipError_t launch_emit_pairs(const float *splats, const uint64_t *rects, int til
                              hipStream_t s) {
     if (cap <= 0) return hipGetLastError();
     if (extent_rule == 1)
-        k_emit_spans<<<(unsigned)ws.nb_gauss, 256, 0, s>>>(ws.dval[1], ws.counters, splats, rects,
-                                                          ws.pair_off, tiles_x, pair_tiles,
-                                                          pair_gids, cap);
+        k_emit_spans<Ellipse><<<(unsigned)ws.nb_gauss, 256, 0, s>>>(
+            ws.dval[1], ws.counters, splats, rects, ws.pair_off, tiles_x, pair_tiles, pair_gids, cap);
+    else if (extent_rule == 2)
+        k_emit_spans<OrientedBox><<<(unsigned)ws.nb_gauss, 256, 0, s>>>(
+            ws.dval[1], ws.counters, splats, rects, ws.pair_off, tiles_x, pair_tiles, pair_gids, cap);
     else
         k_emit<<<(unsigned)((cap + kEmitChunk - 1) / kEmitChunk), 256, 0, s>>>(
             ws.dval[1], ws.counters, rects, ws.pair_off, ws.slice_start, num_pairs, tiles_x,

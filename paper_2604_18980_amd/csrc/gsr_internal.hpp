@@ -20,7 +20,8 @@ struct PreprocessArgs {
     double fx, fy, cx, cy, limx, limy;
     int width, height, tiles_x, tiles_y;
     int adagscale, force_unit_scale;
-    int extent_rule;  // 0: scaled extent's rectangle; 1: plain rectangle (ellipse test at emission)
+    int extent_rule;  // 0, 2: scaled extent's rectangle (rule 2: oriented box at emission);
+                      // 1: plain rectangle (ellipse test at emission)
     double K, lut_depth_max;
     float lut[kLutBins];
     double shc[16];  // real-SH normalisation constants, see preprocess.hip
@@ -154,8 +155,8 @@ hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
                                const uint32_t *tiles_touched, int n, int extent_rule, int64_t cap,
                                int64_t *num_pairs, const Workspace &ws, hipStream_t s);
 // The pair-writing part of launch_emit, after launch_emit_prepare: whole
-// rectangles (extent rule 0) or each rectangle row's ellipse span (rule 1,
-// recomputed from the splat records).
+// rectangles (extent rule 0) or each rectangle row's ellipse (rule 1) or
+// oriented-box (rule 2) span, recomputed from the splat records.
 hipError_t launch_emit_pairs(const float *splats, const uint64_t *rects, int tiles_x,
                              int extent_rule, uint32_t *pair_tiles, uint32_t *pair_gids,
                              int64_t cap, const int64_t *num_pairs, const Workspace &ws,

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
                         keep = false;  // Sec. 3.3: negligible for this view
                     } else {
                         sc = a.force_unit_scale ? 1.0 : sqrt(log(sigma / th) / log(sigma / kTau));
-                        if (a.extent_rule == 0) ext = ext * sc;  // rule 1: Th enters at pair generation
+                        if (a.extent_rule != 1) ext = ext * sc;  // rule 1: Th enters at pair generation
                     }
                 }
             }

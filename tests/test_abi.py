@@ -92,7 +92,7 @@ def test_invalid_arguments_rejected_on_host(G):
     assert b"K" in L.gs_last_error()
     m = G.mode_struct(adagscale=True, K=0.1, t_upper=[2.0] * 20)
     assert L.gs_preprocess(C.byref(sc), C.byref(cam), C.byref(m), P(1), P(1), P(1), None) == 1
-    m = G.mode_struct(extent_rule=2)
+    m = G.mode_struct(extent_rule=3)
     assert L.gs_preprocess(C.byref(sc), C.byref(cam), C.byref(m), P(1), P(1), P(1), None) == 1
     assert b"extent_rule" in L.gs_last_error()
     # unknown extent rule at emission and binning

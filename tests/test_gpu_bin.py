@@ -40,7 +40,7 @@ CASES = ["tiny128", "tiny128_ada", "ragged_257x129", "ragged_300x301", "mid_1920
          "wide_4112x4112"]
 
 
-@pytest.mark.parametrize("rule", [0, 1], ids=["rect", "ellipse"])
+@pytest.mark.parametrize("rule", [0, 1, 2], ids=["rect", "ellipse", "obb"])
 @pytest.mark.parametrize("name", CASES)
 def test_bin_equals_staged_and_oracle(O, name, rule):
     """Under the ellipse rule every case takes the emit-then-sort route, with

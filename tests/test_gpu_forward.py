@@ -26,6 +26,10 @@ MODES = [
     ("ada_ell_K1", dict(adagscale=True, K=1.0, extent_rule=1)),
     ("ada_ell_lut", dict(adagscale=True, K=0.3, t_upper=np.linspace(1.0, 0.05, 20),
                          lut_depth_max=8.0, extent_rule=1)),
+    # the oriented-box tile test (extent rule 2)
+    ("plain_obb", dict(extent_rule=2)),
+    ("ada_obb_K0.1", dict(adagscale=True, K=0.1, extent_rule=2)),
+    ("ada_obb_unit", dict(adagscale=True, K=1.0, force_unit_scale=True, extent_rule=2)),
 ]
 
 
@@ -67,7 +71,7 @@ def test_mid_scene_subsample(O):
     1920x1080: spans thousands of tiles, several sort blocks and ragged tails."""
     sc, cam = scenes.mid_scene(n=60_000, seed=1)
     for mode in ({}, dict(adagscale=True, K=1.0), dict(extent_rule=1),
-                 dict(adagscale=True, K=1.0, extent_rule=1)):
+                 dict(adagscale=True, K=1.0, extent_rule=1), dict(adagscale=True, K=1.0, extent_rule=2)):
         g = gpu_frame(sc, cam, mode)
         fr = O.render(sc, cam, oracle_mode(O, mode),
                       tiles=np.arange(0, O.num_tiles(cam), 37, dtype=np.int32))
@@ -104,12 +108,12 @@ def test_non_finite_and_degenerate_inputs(O):
     sc.opacity_logits[30:40] = -30.0     # opacity ~ 0
     sc.opacity_logits[40:50] = 30.0      # opacity ~ 1, alpha clamps at 0.99
     for mode in ({}, dict(adagscale=True, K=0.5), dict(extent_rule=1),
-                 dict(adagscale=True, K=0.5, extent_rule=1)):
+                 dict(adagscale=True, K=0.5, extent_rule=1), dict(extent_rule=2)):
         _full_check(O, sc, cam, mode)
 
 
 @pytest.mark.parametrize("staged", [False, True], ids=["bin", "staged"])
-@pytest.mark.parametrize("rule", [0, 1], ids=["rect", "ellipse"])
+@pytest.mark.parametrize("rule", [0, 1, 2], ids=["rect", "ellipse", "obb"])
 def test_capacity_overflow_reports_required_count(O, rule, staged):
     """An undersized pair buffer: emit reports the required count, the stages
     after it stay in bounds, and a regrown buffer gives the full result."""

@@ -45,9 +45,9 @@ def _omode(O, mode):
 
 
 def _pairs(O, pre, cam):
-    """The oracle's emitted pairs under the ellipse rule (None under the
-    rectangle rule, whose lists follow from the rectangles)."""
-    return O.emit(pre, cam) if pre.extent_rule == 1 else None
+    """The oracle's emitted pairs under the ellipse and oriented-box rules
+    (None under the rectangle rule, whose lists follow from the rectangles)."""
+    return O.emit(pre, cam) if pre.extent_rule != 0 else None
 
 
 def check_sampled(O, pre, cam, fb, tiles, n, check_records=True, pairs=None):
@@ -89,8 +89,9 @@ def check_sampled(O, pre, cam, fb, tiles, n, check_records=True, pairs=None):
 
 
 @pytest.mark.parametrize("mode", [{}, dict(adagscale=True, K=CITY_K), dict(extent_rule=1),
-                                  dict(adagscale=True, K=CITY_K, extent_rule=1)],
-                         ids=["plain", "ada", "plain_ellipse", "ada_ellipse"])
+                                  dict(adagscale=True, K=CITY_K, extent_rule=1),
+                                  dict(adagscale=True, K=CITY_K, extent_rule=2)],
+                         ids=["plain", "ada", "plain_ellipse", "ada_ellipse", "ada_obb"])
 def test_city_6M_4608x3456(O, mode):
     import torch
     sc, cam = _city()

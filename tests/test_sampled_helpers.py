@@ -29,7 +29,7 @@ def test_tile_shortcuts_match_full_pipeline(O, case):
         cam = dict(cam, width=100, height=37)
         mode = O.Mode()
     fr = O.render(sc, cam, mode)
-    if mode.extent_rule == 1:
+    if mode.extent_rule != 0:
         pairs = O.emit(fr.pre, cam)
     counts = tile_counts(fr.pre, cam, pairs)
     np.testing.assert_array_equal(counts, fr.ranges[:, 1] - fr.ranges[:, 0])
