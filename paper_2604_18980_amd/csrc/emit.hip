@@ -356,6 +356,11 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// mean span length from which a step's spans are written one at a time
+#ifndef GSR_LONG_SPAN
+#define GSR_LONG_SPAN 16
+#endif
+
 // Writes one step's spans (lane l's span: len pairs from output index k, tiles
 // t0, t0 + 1, ..., Gaussian gid).  Long spans are written one after another by
 // the whole wave (the span's values read from its lane, consecutive lanes on
@@ -374,7 +379,7 @@ __device__ __forceinline__ void wave_write_spans(SpanTable &st, uint32_t len, ui
     }
     const uint32_t total = lane_u32(x, kWave - 1);
     const uint64_t spans = __ballot(len > 0u);
-    if (total >= 16u * (uint32_t)__popcll(spans)) {  // long spans: one at a time
+    if (total >= (uint32_t)GSR_LONG_SPAN * (uint32_t)__popcll(spans)) {  // long spans: one at a time
         for (uint64_t m = spans; m; m &= m - 1) {  // wave-uniform
             const int src = __ffsll((long long)m) - 1;
             const uint32_t n = lane_u32(len, src), tb = lane_u32(t0, src), gb = lane_u32(gid, src);
