@@ -661,13 +661,24 @@ static double skip_weight(const skip_t *sk, uint32_t g, double T) {
     return sk->lut[bin];
 }
 
+/* Contribution profile (Sec. 2.4, Fig. 4(b)): per bin of the Mahalanobis
+ * distance m = sqrt(d^T Sigma2^-1 d) between the pixel and the Gaussian's
+ * mean, bin = min(floor(m / bin_width), nbins - 1), the sum and the number of
+ * the contributions alpha T of the blends made. */
+typedef struct {
+    int nbins;
+    double bin_width;
+    double *sums;
+    int64_t *counts;
+} profile_t;
+
 /* max_t (nullable, [n]): per Gaussian, the largest transmittance in front of
  * it at a pixel where it is blended (the max(T^i) of Sec. 3.2).  sk
  * (nullable): the contribution-skip rule above; skipped blends count in
- * *skipped (nullable). */
-static void blend_pixel_skip(double px, double py, const uint32_t *list, int64_t len,
+ * *skipped (nullable).  pf (nullable): the contribution profile. */
+static void blend_pixel_prof(double px, double py, const uint32_t *list, int64_t len,
                              const double *rec, pix_t *o, double *max_t, const skip_t *sk,
-                             int64_t *skipped) {
+                             int64_t *skipped, const profile_t *pf) {
     double T = 1.0, C[3] = {0.0, 0.0, 0.0}, margin = INFINITY;
     int64_t last = 0, blended = 0, ev = 0;
     uint64_t sig = 1469598103934665603ull;
@@ -698,6 +709,13 @@ static void blend_pixel_skip(double px, double py, const uint32_t *list, int64_t
         if (Tn < T_STOP) break;
         for (int ch = 0; ch < 3; ++ch) C[ch] += alpha * T * g[6 + ch];
         if (max_t && T > max_t[list[j]]) max_t[list[j]] = T;
+        if (pf) {
+            double m = sqrt(g[2] * uu * uu + g[4] * dy * dy);
+            double fb = floor(m / pf->bin_width);
+            int bin = fb >= (double)(pf->nbins - 1) ? pf->nbins - 1 : (int)fb;
+            pf->sums[bin] += alpha * T;
+            pf->counts[bin] += 1;
+        }
         T = Tn;
         last = j + 1;
         ++blended;
@@ -707,9 +725,15 @@ static void blend_pixel_skip(double px, double py, const uint32_t *list, int64_t
     o->T = T; o->last = last; o->blended = blended; o->evaluated = ev; o->margin = margin; o->sig = sig;
 }
 
+static void blend_pixel_skip(double px, double py, const uint32_t *list, int64_t len,
+                             const double *rec, pix_t *o, double *max_t, const skip_t *sk,
+                             int64_t *skipped) {
+    blend_pixel_prof(px, py, list, len, rec, o, max_t, sk, skipped, NULL);
+}
+
 static void blend_pixel(double px, double py, const uint32_t *list, int64_t len, const double *rec,
                         pix_t *o, double *max_t) {
-    blend_pixel_skip(px, py, list, len, rec, o, max_t, NULL, NULL);
+    blend_pixel_prof(px, py, list, len, rec, o, max_t, NULL, NULL, NULL);
 }
 
 static void store_pixel(const pix_t *o, int64_t idx, int64_t npix, const double *bg, double *image,
@@ -774,6 +798,25 @@ void orc_blend_skip(int width, int height, const int64_t *ranges, const uint32_t
                                  ranges[2 * t + 1] - ranges[2 * t], rec, &o, NULL, &sk, skipped);
                 store_pixel(&o, (int64_t)py * width + px, npix, bg, image, final_T, n_contrib,
                             margin, NULL, NULL, blended);
+            }
+    }
+}
+
+/* Contribution profile of the whole frame (orc_blend's walk): sums[nbins]
+ * and counts[nbins] are overwritten. */
+void orc_contrib_profile(int width, int height, const int64_t *ranges, const uint32_t *sorted_vals,
+                         const double *rec, int nbins, double bin_width, double *sums,
+                         int64_t *counts) {
+    profile_t pf = {nbins, bin_width, sums, counts};
+    for (int b = 0; b < nbins; ++b) { sums[b] = 0.0; counts[b] = 0; }
+    int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
+    for (int t = 0; t < TX * TY; ++t) {
+        int tx = t % TX, ty = t / TX;
+        for (int py = ty * TILE; py < (ty + 1) * TILE && py < height; ++py)
+            for (int px = tx * TILE; px < (tx + 1) * TILE && px < width; ++px) {
+                pix_t o;
+                blend_pixel_prof((double)px, (double)py, sorted_vals + ranges[2 * t],
+                                 ranges[2 * t + 1] - ranges[2 * t], rec, &o, NULL, NULL, NULL, &pf);
             }
     }
 }

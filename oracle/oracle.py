@@ -68,6 +68,7 @@ def lib():
         L.orc_ranges.argtypes = [C.c_int64, P, C.c_int, P]
         L.orc_blend.argtypes = [C.c_int, C.c_int, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P]
         L.orc_t_upper_accumulate.argtypes = [C.c_int64, P, P, C.c_double, P]
+        L.orc_contrib_profile.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int, C.c_double, P, P]
         L.orc_blend_skip.argtypes = ([C.c_int, C.c_int, P, P, P, P, P, C.c_int64, C.c_int,
                                       C.c_double, P, P, P, C.c_double] + [P] * 6)
         L.orc_blend_bruteforce.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_int, P, P, P, P, P, P,
@@ -321,6 +322,18 @@ def blend_skip(frame: "Frame", cam, kind, theta, weight=None, lut=None, lut_dept
                          float(theta), _p(w), _p(d32), _p(lt), float(lut_depth_max), _p(img),
                          _p(T), _p(nc), _p(mg), _p(bl), _p(sk))
     return img, T, nc, mg, bl, int(sk[0])
+
+
+def contrib_profile(frame: "Frame", cam, nbins=34, bin_width=0.1, rec=None):
+    """Fig. 4(b): per bin of the Mahalanobis distance between pixel and mean,
+    the sum and count of the contributions alpha T of the frame's blends."""
+    rec = np.ascontiguousarray(frame.pre.record() if rec is None else rec, np.float64)
+    sums = np.zeros(nbins)
+    counts = np.zeros(nbins, np.int64)
+    lib().orc_contrib_profile(cam["width"], cam["height"], _p(np.ascontiguousarray(frame.ranges, np.int64)),
+                              _p(np.ascontiguousarray(frame.sorted_vals, np.uint32)), _p(rec),
+                              int(nbins), float(bin_width), _p(sums), _p(counts))
+    return sums, counts
 
 
 def max_transmittance(frame: "Frame", cam, rec=None):

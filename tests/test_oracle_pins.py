@@ -948,3 +948,23 @@ def test_rule2_pairs_cover_the_extent_ellipse(O, adagscale, K):
         inrect = (px // 16 >= x0) & (px // 16 < x1) & (py // 16 >= y0) & (py // 16 < y1)
         inside = (q <= (3 * s) ** 2 * (1 - 1e-9)) & inrect
         assert set(((py[inside] // 16) * TX + px[inside] // 16).tolist()) <= tiles
+
+
+def test_contrib_profile_single_gaussian_closed_form(O):
+    """One Gaussian alone (T = 1 in front of it): every blend's contribution is
+    alpha = opacity exp(-m^2 / 2), so each bin's mean lies between the values
+    at its edges, the total count is the number of pixels with alpha >= tau,
+    and the counts sum to the blends of the frame."""
+    cam = scenes.make_camera(np.eye(3), np.zeros(3), 48, 48)
+    g = (20.3, 22.7, 1 / 36.0, 0.3, 1 / 25.0, 0.8, 1, 1, 1)
+    fr, rec = _frame_of(O, [g], cam)
+    sums, counts = O.contrib_profile(fr, cam, rec=rec)
+    _, bl, _ = O.blend_counts(fr, cam, rec=rec)
+    assert counts.sum() == bl.sum() > 100
+    op = float(np.float32(0.8))
+    for b in np.nonzero(counts)[0]:
+        lo, hi = 0.1 * b, 0.1 * (b + 1)
+        mean = sums[b] / counts[b]
+        assert op * math.exp(-hi * hi / 2) - 1e-12 <= mean <= op * math.exp(-lo * lo / 2) + 1e-12
+    # alpha >= 1/255 ends at m = sqrt(2 ln(255 opacity))
+    assert counts[int(math.floor(10 * math.sqrt(2 * math.log(255 * op)))) + 1:].sum() == 0
