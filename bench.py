@@ -407,7 +407,7 @@ SKIP_FRACTIONS = (0.2, 0.4, 0.5, 0.6, 0.8)
 
 
 def bench_contrib(args):
-    """The contribution analysis of Sec. 2.4 (Fig. 4(a)) and Sec. 3.2 (Fig. 5)
+    """The contribution analysis of Sec. 2.4 (Fig. 4(a), 4(b)) and Sec. 3.2 (Fig. 5)
     on synthetic scenes: PSNR of a render that skips the lowest-contribution
     blend operations, against the full render, versus the fraction skipped,
     for the exact contribution alpha T (eq. 3) and its approximations alpha
@@ -415,7 +415,9 @@ def bench_contrib(args):
     16-view calibrated table).  For each target fraction theta is bisected in
     log space until the skipped fraction is within 0.005 of it (the exact
     rule's fraction depends on theta through T, so each step is a render).
-    Plain 3D-GS pair lists; every render runs in gs_rasterize_skip."""
+    Plain 3D-GS pair lists; every render runs in gs_rasterize_skip.  Also the
+    mean contribution per bin of the Mahalanobis distance between pixel and
+    mean (gs_contribution_profile)."""
     import torch
     from paper_2604_18980_amd import calib, gsr, render as R, scenes
     dev = torch.device("cuda:0")
@@ -480,8 +482,18 @@ def bench_contrib(args):
                             "psnr_db": psnr_t(torch, img, ref)})
             curves[kname] = pts
             log(f"  {kname}: " + ", ".join(f"{p['skipped']:.2f}->{p['psnr_db']:.1f} dB" for p in pts))
+        # Fig. 4(b): mean contribution alpha T per 0.1-wide bin of the
+        # Mahalanobis distance between pixel and mean
+        psum = torch.zeros(34, dtype=torch.float32, device=dev)
+        pcnt = torch.zeros(34, dtype=torch.int64, device=dev)
+        gsr.gs_contribution_profile(fb.splats, fb.n, fb.sorted_gids, fb.ranges, cam_s, 34, 0.1, psum,
+                                    pcnt)
+        ps, pc = psum.cpu().numpy().astype(np.float64), pcnt.cpu().numpy()
+        profile = [{"m_lo": round(0.1 * b, 1), "blends": int(pc[b]),
+                    "mean_contribution": float(ps[b] / pc[b]) if pc[b] else None} for b in range(34)]
         out[name] = {"pairs": int(fb.num_pairs.item()), "skip_render_ms": ev[0].elapsed_time(ev[1]) / 5,
-                     "t_upper": [float(x) for x in table], "lut_depth_max": dmax, "curves": curves}
+                     "t_upper": [float(x) for x in table], "lut_depth_max": dmax, "curves": curves,
+                     "contribution_vs_mahalanobis_distance": profile}
         del fb, scene
         torch.cuda.empty_cache()
     return {"metric": "PSNR (dB, against the full render) versus skipped fraction of blend operations, "

@@ -287,6 +287,19 @@ gs_status gs_rasterize_skip(const float *splats, int64_t n, const uint32_t *sort
                             float lut_depth_max, float *image, float *final_T, uint32_t *n_contrib,
                             unsigned long long *counts, void *stream);
 
+/* Contribution profile (Sec. 2.4, Fig. 4(b)): the default rasterizer's walk
+ * over these lists without writing pixels; every blend (alpha >= 1/255, not a
+ * stopping entry) adds its contribution alpha T to sums[bin] and 1 to
+ * counts[bin], bin = min(floor(m / bin_width), nbins - 1) of the Mahalanobis
+ * distance m = sqrt(d^T Sigma2^-1 d) between the pixel and the Gaussian's
+ * mean (float32).  sums (device float[nbins]) and counts (device
+ * uint64[nbins]) are added to (the caller zeroes them).  1 <= nbins <= 64,
+ * bin_width > 0 (else GS_ERR_INVALID_ARGUMENT). */
+gs_status gs_contribution_profile(const float *splats, int64_t n, const uint32_t *sorted_gids,
+                                  const uint32_t *ranges, const gs_camera *cam, int nbins,
+                                  float bin_width, float *sums, unsigned long long *counts,
+                                  void *stream);
+
 /* Adjoint of stage 4 with the pair set and every blend decision of the
  * forward pass frozen.  Walks each pixel's list back to front from n_contrib,
  * recovering T_i = T_{i+1} / (1 - alpha_i) from final_T instead of storing

@@ -376,6 +376,7 @@ gs_status gs_rasterize(const float *splats, int64_t n, const uint32_t *sorted_gi
     a.work = nullptr;
     a.lut_bits = a.max_t_bits = nullptr;
     a.skip_kind = -1;
+    a.prof_sum = nullptr;
     a.lut_depth_max = 0.0;
     return hip_check(launch_raster(a, c, (hipStream_t)stream), "gs_rasterize");
 }
@@ -403,6 +404,7 @@ gs_status gs_raster_work(const float *splats, int64_t n, const uint32_t *sorted_
     a.work = reinterpret_cast<unsigned long long *>(work);
     a.lut_bits = a.max_t_bits = nullptr;
     a.skip_kind = -1;
+    a.prof_sum = nullptr;
     a.lut_depth_max = 0.0;
     const gs_raster_cfg c = {64, 4, 64};
     return hip_check(launch_raster(a, c, (hipStream_t)stream), "gs_raster_work");
@@ -435,6 +437,7 @@ gs_status gs_calibrate_t_upper(const float *splats, int64_t n, const uint32_t *s
     a.max_t_bits = max_t_bits;
     a.lut_depth_max = (double)lut_depth_max;
     a.skip_kind = -1;
+    a.prof_sum = nullptr;
     const gs_raster_cfg c = {64, 4, 64};
     return hip_check(launch_raster(a, c, (hipStream_t)stream), "gs_calibrate_t_upper");
 }
@@ -476,11 +479,49 @@ gs_status gs_rasterize_skip(const float *splats, int64_t n, const uint32_t *sort
     a.lut_bits = a.max_t_bits = nullptr;
     a.lut_depth_max = kind == 2 ? (double)lut_depth_max : 1.0;
     a.skip_kind = kind;
+    a.prof_sum = nullptr;
     a.skip_theta = theta;
     a.skip_weight = weight;
     for (int i = 0; i < GS_LUT_BINS; ++i) a.skip_lut[i] = kind == 2 ? t_upper[i] : 1.0f;
     const gs_raster_cfg c = {64, 4, 64};
     return hip_check(launch_raster(a, c, (hipStream_t)stream), "gs_rasterize_skip");
+}
+
+gs_status gs_contribution_profile(const float *splats, int64_t n, const uint32_t *sorted_gids,
+                                  const uint32_t *ranges, const gs_camera *cam, int nbins,
+                                  float bin_width, float *sums, unsigned long long *counts,
+                                  void *stream) {
+    gs_status st;
+    if ((st = check_camera(cam)) != GS_OK) return st;
+    if (n < 0) return fail(GS_ERR_INVALID_ARGUMENT, "n < 0");
+    if (!ranges || !sums || !counts) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (n > 0 && (!splats || !sorted_gids)) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (nbins < 1 || nbins > kProfBins)
+        return fail(GS_ERR_INVALID_ARGUMENT, "nbins must be in [1, %d]", kProfBins);
+    if (!(bin_width > 0.0f) || !finite_f(bin_width))
+        return fail(GS_ERR_INVALID_ARGUMENT, "bin_width must be finite and > 0");
+    RasterArgs a;
+    a.splats = splats;
+    a.gids = sorted_gids;
+    a.ranges = ranges;
+    a.width = cam->width;
+    a.height = cam->height;
+    a.tiles_x = tiles_x(cam);
+    a.tiles_y = tiles_y(cam);
+    for (int i = 0; i < 3; ++i) a.bg[i] = 0.0f;
+    a.image = a.final_T = nullptr;
+    a.n_contrib = nullptr;
+    a.n_evaluated = nullptr;
+    a.work = nullptr;
+    a.lut_bits = a.max_t_bits = nullptr;
+    a.lut_depth_max = 1.0;
+    a.skip_kind = -1;
+    a.prof_sum = sums;
+    a.prof_cnt = counts;
+    a.prof_bins = nbins;
+    a.prof_inv_width = 1.0f / bin_width;
+    const gs_raster_cfg c = {64, 4, 64};
+    return hip_check(launch_raster(a, c, (hipStream_t)stream), "gs_contribution_profile");
 }
 
 gs_status gs_rasterize_backward(const float *splats, int64_t n, const uint32_t *sorted_gids,

@@ -199,7 +199,15 @@ struct RasterArgs {
     float skip_theta;
     const float *skip_weight;
     float skip_lut[kLutBins];
+    // contribution profile (prof_sum set; no pixels written): per bin of the
+    // Mahalanobis distance m between pixel and mean, bin = min(floor(m /
+    // width), prof_bins - 1), the sum and count of the blends' alpha T (added)
+    float *prof_sum;
+    unsigned long long *prof_cnt;
+    int prof_bins;  // 1 .. kProfBins
+    float prof_inv_width;
 };
+constexpr int kProfBins = 64;
 hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStream_t s);
 
 struct ViewsArgs {

@@ -122,6 +122,9 @@ __device__ __forceinline__ float wave_max(float v) {
 // blends, the largest transmittance in front of it over the tile's pixels,
 // raised into its depth bin (per-wave maxima in LDS, flushed at the end of
 // the tile) and, if requested, into the Gaussian's own entry.
+// MODE 5: write no pixels; the contribution profile (Sec. 2.4, Fig. 4(b)):
+// each blend's alpha T added to its Mahalanobis-distance bin (per-wave LDS
+// histograms, flushed at the end of the tile).
 // MODE 4: the renderer with the contribution-skip rule of the analysis
 // experiments (Sec. 2.4, 3.2): a blend whose contribution alpha x (T, the
 // Gaussian's weight, or T_up of its depth bin) is below a.skip_theta is
@@ -137,6 +140,8 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
     __shared__ uint32_t s_cgid[MODE == 3 ? 4 : 1][64];  // MODE 3: Gaussian id of each slot
     __shared__ uint32_t s_lut[MODE == 3 ? 4 : 1][kLutBins];
     __shared__ float s_w[MODE == 4 ? 4 : 1][64];          // MODE 4: weight of each slot
+    __shared__ float s_ps[MODE == 5 ? 4 : 1][kProfBins];  // MODE 5: per-wave profile sums
+    __shared__ uint32_t s_pc[MODE == 5 ? 4 : 1][kProfBins];  // and counts
     const int wid = threadIdx.x / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
@@ -166,6 +171,10 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
     uint32_t w_strips = 0, w_blended = 0, w_loaded = 0;  // MODE 2 (w_blended also MODE 4)
     uint32_t w_skipped = 0;                              // MODE 4
     if (MODE == 3 && lane < kLutBins) s_lut[wid][lane] = 0u;
+    if (MODE == 5) {
+        s_ps[wid][lane] = 0.0f;
+        s_pc[wid][lane] = 0u;
+    }
 
     for (uint32_t base = start; base < end; base += kWave) {
         uint32_t alive = 0;
@@ -264,6 +273,14 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
                     T[k] = Tk;
                     last[k] = lk;
                     if (CNT) w_blended += skip ? 0u : 1u;
+                    if (MODE == 5 && w != 0.0f) {
+                        // blended (not the stopping entry): its alpha T, binned by
+                        // the Mahalanobis distance sqrt(q), q = e2 / (-log2(e) / 2)
+                        const float m = __builtin_sqrtf(e2 * (1.0f / kNegHalfLog2e));
+                        const int bin = min((int)(m * a.prof_inv_width), a.prof_bins - 1);
+                        atomicAdd(&s_ps[wid][bin], w);
+                        atomicAdd(&s_pc[wid][bin], 1u);
+                    }
                 }
             }
             if (MODE == 3) {
@@ -302,6 +319,13 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
     }
     if (MODE == 3) {
         if (lane < kLutBins && s_lut[wid][lane] != 0u) atomicMax(a.lut_bits + lane, s_lut[wid][lane]);
+        return;
+    }
+    if (MODE == 5) {
+        if (lane < a.prof_bins && s_pc[wid][lane] != 0u) {
+            atomicAdd(a.prof_sum + lane, s_ps[wid][lane]);
+            atomicAdd(a.prof_cnt + lane, (unsigned long long)s_pc[wid][lane]);
+        }
         return;
     }
     if (MODE == 2) {
@@ -357,6 +381,8 @@ hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStrea
     const unsigned tiles = (unsigned)a.tiles_x * (unsigned)a.tiles_y;
     if (a.lut_bits) {
         k_raster_wave<3><<<(tiles + 3) / 4, 256, 0, s>>>(a);
+    } else if (a.prof_sum) {
+        k_raster_wave<5><<<(tiles + 3) / 4, 256, 0, s>>>(a);
     } else if (a.skip_kind >= 0) {
         k_raster_wave<4><<<(tiles + 3) / 4, 256, 0, s>>>(a);
     } else if (a.work) {
@@ -402,6 +428,7 @@ __device__ __forceinline__ RasterArgs view_args(const ViewsArgs &q, int view) {
     a.work = nullptr;
     a.lut_bits = a.max_t_bits = nullptr;
     a.skip_kind = -1;
+    a.prof_sum = nullptr;
     a.lut_depth_max = 0.0;
     return a;
 }

@@ -21,6 +21,7 @@ TILE = 16
 
 EXPORTS = ("gs_workspace_size", "gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_bin_pairs",
            "gs_rasterize", "gs_raster_work", "gs_calibrate_t_upper", "gs_rasterize_skip",
+           "gs_contribution_profile",
            "gs_rasterize_backward", "gs_preprocess_backward", "gs_views_workspace_size",
            "gs_rasterize_views", "gs_wall_clock_khz", "gs_status_string", "gs_last_error",
            "gs_version")
@@ -82,10 +83,11 @@ def load():
     L.gs_calibrate_t_upper.argtypes = [P, I64, P, P, P, C.c_float, P, P, P]
     L.gs_rasterize_skip.argtypes = [P, I64, P, P, P, P, I, C.c_float, P, P, C.c_float, P, P, P, P,
                                     P]
+    L.gs_contribution_profile.argtypes = [P, I64, P, P, P, I, C.c_float, P, P, P]
     L.gs_rasterize_backward.argtypes = [P, I64, P, P, P, P, P, P, P, P, P]
     L.gs_preprocess_backward.argtypes = [P, P, P, P, P, P]
     for f in ("gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_bin_pairs", "gs_rasterize",
-              "gs_raster_work", "gs_calibrate_t_upper", "gs_rasterize_skip",
+              "gs_raster_work", "gs_calibrate_t_upper", "gs_rasterize_skip", "gs_contribution_profile",
               "gs_rasterize_backward", "gs_preprocess_backward"):
         getattr(L, f).restype = C.c_int
     L.gs_status_string.argtypes = [I]
@@ -222,6 +224,13 @@ def gs_rasterize_skip(splats, n, sorted_gids, ranges, cam: GsCamera, bg, kind, t
                                     C.byref(cam), bgv, int(kind), float(theta), _ptr(weight), lut,
                                     float(lut_depth_max), _ptr(image), _ptr(final_T),
                                     _ptr(n_contrib), _ptr(counts), _stream(stream)))
+
+
+def gs_contribution_profile(splats, n, sorted_gids, ranges, cam: GsCamera, nbins, bin_width, sums,
+                            counts, stream=None):
+    _check(load().gs_contribution_profile(_ptr(splats), int(n), _ptr(sorted_gids), _ptr(ranges),
+                                          C.byref(cam), int(nbins), float(bin_width), _ptr(sums),
+                                          _ptr(counts), _stream(stream)))
 
 
 def gs_rasterize_backward(splats, n, sorted_gids, ranges, cam: GsCamera, bg, final_T, n_contrib,

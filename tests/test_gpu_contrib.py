@@ -106,3 +106,35 @@ def test_skip_rejects_bad_arguments(O):
                                P(1), P(1), P(1), None, None) == 1
     assert L.gs_rasterize_skip(P(1), 1, P(1), P(1), C.byref(cam), bg, 2, 0.1, None, None, 1.0,
                                P(1), P(1), P(1), None, None) == 1
+
+
+@pytest.mark.parametrize("name", ["tiny", "mid"])
+def test_contribution_profile_matches_oracle(O, name):
+    """Fig. 4(b) profile: the same blends in total as the oracle's walk, each
+    distance bin's count and contribution sum equal up to the blends whose
+    distance sits at a bin edge in float32 (and the float sums' rounding)."""
+    import torch
+    from paper_2604_18980_amd import gsr, render as R
+    sc, cam, _ = _case(name)
+    ds = R.DeviceScene.from_host(sc)
+    fb = R.render(ds, cam)
+    sums = torch.zeros(34, dtype=torch.float32, device="cuda")
+    counts = torch.zeros(34, dtype=torch.int64, device="cuda")
+    gsr.gs_contribution_profile(fb.splats, fb.n, fb.sorted_gids, fb.ranges, gsr.camera_struct(cam),
+                                34, 0.1, sums, counts)
+    torch.cuda.synchronize()
+    fr = O.render(sc, cam)
+    o_sums, o_counts = O.contrib_profile(fr, cam, nbins=34, bin_width=float(np.float32(0.1)))
+    g_counts = counts.cpu().numpy()
+    g_sums = sums.cpu().numpy().astype(np.float64)
+    n_amb = int((fr.margin < 1e-4).sum())
+    total = int(o_counts.sum())
+    print(f"  blends {int(g_counts.sum())} (oracle {total}), ambiguous pixels {n_amb}", flush=True)
+    assert abs(int(g_counts.sum()) - total) <= 4 * n_amb
+    assert np.abs(g_counts - o_counts).max() <= max(8, total * 1e-4)
+    np.testing.assert_allclose(g_sums, o_sums, rtol=1e-3, atol=1e-3 * o_sums.max())
+    # contributions fall off with distance (Fig. 4(b)): mean per blend in the
+    # first bins well above the last populated ones
+    mean = o_sums / np.maximum(o_counts, 1)
+    live = np.nonzero(o_counts)[0]
+    assert mean[live[:3]].mean() > 5 * mean[live[-3:]].mean()
