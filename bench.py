@@ -155,7 +155,7 @@ def raster_traffic(rule):
     import hashlib
     src = os.path.join(ROOT, "paper_2604_18980_amd", "csrc", "raster.hip")
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    return RASTER_TRAFFIC["bytes"][rule] if h == RASTER_TRAFFIC["source_sha256_16"] else None
+    return RASTER_TRAFFIC["bytes"].get(rule) if h == RASTER_TRAFFIC["source_sha256_16"] else None
 
 
 def graph_frames(torch, R, scene, cam_s, mode_s, fb, steps, warmup):

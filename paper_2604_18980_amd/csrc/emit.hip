@@ -16,9 +16,10 @@
 //                                       scan of its Gaussians' tile counts
 //   k_emit_spans                        extent rules 1 and 2: per wave 64
 //                                       Gaussians' row spans (tile_shapes.hpp),
+//                                       64 (Gaussian, row) items per step,
 //                                       written by the whole wave
-//                                       (Gaussians with long row bands: one at a
-//                                       time by the whole wave, a row per lane)
+#include <type_traits>
+
 #include "tile_shapes.hpp"
 #include "gsr_internal.hpp"
 
@@ -106,86 +107,129 @@ __global__ __launch_bounds__(256) void k_vis_compact(const uint32_t *tiles_touch
     if (threadIdx.x == 0 && b == (int64_t)gridDim.x - 1) *num_vis = (int64_t)(before + tot);
 }
 
-// Broadcast of one lane's shape and row range to the whole wave.
-template <class Shape>
-struct WaveShape {
-    Shape e;
-    int x0, x1, ra, rb;
-};
-template <class Shape>
-__device__ __forceinline__ WaveShape<Shape> wave_broadcast(const Shape &e, int x0, int x1, int ra, int rb,
-                                                           int src) {
-    WaveShape<Shape> w;
-    w.e = e;
-    w.e.broadcast(src);
-    w.x0 = lane_i32(x0, src);
-    w.x1 = lane_i32(x1, src);
-    w.ra = lane_i32(ra, src);
-    w.rb = lane_i32(rb, src);
-    return w;
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Pairs of each depth-sorted visible Gaussian (one per thread), added to the
-// total of its chunk of 4096 (cleared by k_vis_count): the rectangle's area
-// (tiles_touched) under extent rule 0, the count of its tiles that meet the
-// ellipse under rule 1.  The visible Gaussians are dense here, so the FP64
-// span arithmetic of rule 1 keeps the lanes busy.  A Gaussian whose row band
-// is longer than kSmallRows is counted afterwards by its whole wave, one row
-// per lane, so no lane walks a giant's rows alone.
+// Inclusive prefix sum over the wave in DPP lane moves, no LDS round trip:
+// shifts by 1, 2, 4 and 8 lanes inside each row of 16 lanes (lanes shifted in
+// from outside the row read 0), then lane 15's sum added to row 1 and lane
+// 47's to row 3 (row_bcast:15 on rows 1 and 3), then lane 31's to rows 2 and
+// 3 (row_bcast:31).
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
+// Exclusive prefix over the wave of one value per lane, and the wave's total.
+__device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, uint32_t &total) {
+    const uint32_t x = wave_inclusive_sum(v);
+    total = lane_u32(x, kWave - 1);
+    return x - v;
+}
+
+// One wave's Gaussians for the flattened row walk of the span kernels.  The
+// rows of the wave's 64 Gaussians (lane-major: lane 0's band, then lane 1's,
+// ...) are numbered 0 .. total-1 and taken 64 per step, one per lane, so every
+// lane computes a span whatever the lengths of the bands; item q belongs to
+// the last lane whose band prefix p is <= q, and is row ra + q - p of its band.
+template <class Shape>
+struct RowTable {
+    Shape sh[kWave];
+    int x0[kWave], x1[kWave], ra[kWave], rb[kWave];
+    uint32_t p[kWave];    // exclusive prefix of the band lengths
+    uint32_t acc[kWave];  // the count's pair totals; the emission's prefix at the first row
+    uint64_t k[kWave];    // output index of the Gaussian's first pair
+    uint32_t g[kWave];
+};
+
+__device__ __forceinline__ int row_owner(const uint32_t *p, uint32_t q) {
+    int lo = 0, hi = kWave - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (p[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Loads this lane's Gaussian into the wave's table: shape, columns [x0, x1),
+// row band [ra, rb) (empty when the shape has no tiles).  Returns the number
+// of items (rows) of the whole wave.  Contains wave barriers.
+template <class Shape>
+__device__ __forceinline__ uint32_t row_table_fill(RowTable<Shape> &tb, const Shape &e, int x0, int x1,
+                                                   int ra, int rb, uint64_t k, uint32_t g) {
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t total;
+    const uint32_t p = wave_exclusive_scan((uint32_t)(rb - ra), total);
+    tb.sh[lane] = e;
+    tb.x0[lane] = x0;
+    tb.x1[lane] = x1;
+    tb.ra[lane] = ra;
+    tb.rb[lane] = rb;
+    tb.p[lane] = p;
+    tb.acc[lane] = 0u;
+    tb.k[lane] = k;
+    tb.g[lane] = g;
+    wave_sync_lds();
+    return total;
+}
+
+// Span of flattened item q (< total): the tile row and its inclusive column
+// span [a, b] in the owner's shape; false when the row misses the shape.
+template <class Shape>
+__device__ __forceinline__ bool row_item_span(const RowTable<Shape> &tb, uint32_t q, int &o, int &ty,
+                                              int &a, int &b) {
+    o = row_owner(tb.p, q);
+    ty = tb.ra[o] + (int)(q - tb.p[o]);
+    return ty < tb.rb[o] && tb.sh[o].row_span(ty, tb.x0[o], tb.x1[o] - 1, a, b);
+}
+
 // Pair count of one visible Gaussian under a shape rule: its tiles meeting the
-// shape, or the whole wave's long-band Gaussians afterwards (see below).
+// shape, the spans of the wave's rows summed per Gaussian in LDS.
 template <class Shape>
 __device__ __forceinline__ uint64_t shape_pair_count(const float *splats, const uint64_t *rects,
-                                                     uint32_t g, bool valid) {
+                                                     uint32_t g, bool valid, RowTable<Shape> &tb) {
     const int lane = threadIdx.x & (kWave - 1);
-    Shape e;
+    Shape e{};
     int x0 = 0, x1 = 0, ra = 0, rb = 0;
-    bool big = false;
-    uint64_t c = 0;
     if (valid) {
         const uint64_t r = rects[g];
         if (e.setup(splats + (size_t)g * 12)) {
             x0 = (int)(r & 0xffff);
             x1 = (int)((r >> 32) & 0xffff);
             e.row_band((int)((r >> 16) & 0xffff), (int)(r >> 48), ra, rb);
-            big = rb - ra > kSmallRows;
-            if (!big) {
-                for (int ty = ra; ty < rb; ++ty) {
-                    int a, b;
-                    if (e.row_span(ty, x0, x1 - 1, a, b)) c += (uint64_t)(b - a + 1);
-                }
-            }
         }
     }
-    // the wave's long-band Gaussians, one at a time, a row per lane
-    for (uint64_t m = __ballot(big); m; m &= m - 1) {  // wave-uniform
-        const int src = __ffsll((long long)m) - 1;
-        const WaveShape<Shape> w = wave_broadcast(e, x0, x1, ra, rb, src);
-        uint32_t part = 0;
-        for (int ty = w.ra + lane; ty < w.rb; ty += kWave) {
-            int a, b;
-            if (w.e.row_span(ty, w.x0, w.x1 - 1, a, b)) part += (uint32_t)(b - a + 1);
-        }
-#pragma unroll
-        for (int o = kWave / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
-        if (lane == src) c = part;
+    const uint32_t total = row_table_fill(tb, e, x0, x1, ra, rb, 0ull, g);
+    for (uint32_t q0 = 0; q0 < total; q0 += kWave) {  // wave-uniform
+        const uint32_t q = q0 + (uint32_t)lane;
+        int o, ty, a, b;
+        if (q < total && row_item_span(tb, q, o, ty, a, b)) atomicAdd(&tb.acc[o], (uint32_t)(b - a + 1));
     }
-    return c;
+    wave_sync_lds();
+    return tb.acc[lane];
 }
 
 // Pairs of each depth-sorted visible Gaussian (one per thread), added to the
 // total of its chunk of 4096 (cleared by k_vis_count): the rectangle's area
 // (tiles_touched) under extent rule 0, the count of its tiles that meet the
 // ellipse (rule 1) or the oriented box (rule 2).  The visible Gaussians are
-// dense here, so the FP64 span arithmetic keeps the lanes busy.  A Gaussian
-// whose row band is longer than kSmallRows is counted afterwards by its whole
-// wave, one row per lane, so no lane walks a giant's rows alone.
+// dense here, and the flattened row walk keeps every lane on a span.
 template <int RULE>
 __global__ __launch_bounds__(256) void k_pair_counts(const uint32_t *sorted_ids, const int64_t *num_vis,
                                                      const uint32_t *tiles_touched, const float *splats,
                                                      const uint64_t *rects, uint64_t *cnt,
                                                      uint64_t *chunk_tot) {
     __shared__ uint64_t wt[4];
+    using Shape = typename std::conditional<RULE == 2, OrientedBox, Ellipse>::type;
+    __shared__ RowTable<Shape> s_rows[RULE == 0 ? 1 : 4];
     const int64_t V = *num_vis;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if ((int64_t)blockIdx.x * 256 >= V) return;  // uniform
@@ -193,10 +237,8 @@ __global__ __launch_bounds__(256) void k_pair_counts(const uint32_t *sorted_ids,
     const uint32_t g = j < V ? sorted_ids[j] : 0u;
     if constexpr (RULE == 0) {
         if (j < V) c = tiles_touched[g];
-    } else if constexpr (RULE == 1) {
-        c = shape_pair_count<Ellipse>(splats, rects, g, j < V);
     } else {
-        c = shape_pair_count<OrientedBox>(splats, rects, g, j < V);
+        c = shape_pair_count<Shape>(splats, rects, g, j < V, s_rows[threadIdx.x / kWave]);
     }
     if (j < V) cnt[j] = c;
     uint64_t tot;
@@ -334,86 +376,45 @@ hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
     return hipGetLastError();
 }
 
-// Extent rule 1: each wave takes 64 consecutive depth-sorted visible
-// Gaussians, one per lane.  Those with short row bands are walked in lockstep:
-// per step every lane recomputes the ellipse span of its next row (exactly as
-// k_pair_counts counted it), a wave prefix sum lays the spans end to end, and
-// the whole wave writes them -- lane l takes pairs l, l + 64, ..., finding the
-// span that holds each by binary search over the 64 span starts in LDS.  Then
-// the long-band Gaussians follow one at a time, 64 of their rows per step, one
-// row per lane, written the same way.  Pairs at or beyond the capacity are not
-// written.
-struct SpanTable {
-    uint32_t start[kWave];  // exclusive prefix of the step's span lengths
-    uint64_t k[kWave];      // output index of each span's first pair
-    uint32_t t0[kWave];     // tile id of each span's first tile
-    uint32_t gid[kWave];
-};
+// Extent rules 1 and 2: each wave takes 64 consecutive depth-sorted visible
+// Gaussians, one per lane, and walks their rows flattened, 64 (Gaussian, row)
+// items per step (RowTable): every lane recomputes the span of its item
+// exactly as k_pair_counts counted it, the item's first pair follows the
+// Gaussian's earlier rows (a wave prefix sum over the steps, less its value at
+// the Gaussian's first row), and the whole wave writes the step's spans.
+// Pairs at or beyond the capacity are not written.
 
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// mean span length from which a step's spans are written one at a time
-#ifndef GSR_LONG_SPAN
-#define GSR_LONG_SPAN 16
+// spans of up to this many pairs are written by their own lanes
+#ifndef GSR_SHORT_SPAN
+#define GSR_SHORT_SPAN 16
 #endif
 
 // Writes one step's spans (lane l's span: len pairs from output index k, tiles
-// t0, t0 + 1, ..., Gaussian gid).  Long spans are written one after another by
-// the whole wave (the span's values read from its lane, consecutive lanes on
-// consecutive pairs); many short ones together, each lane finding the span of
-// its pair by binary search over the span starts in LDS.  Contains wave
-// barriers.
-__device__ __forceinline__ void wave_write_spans(SpanTable &st, uint32_t len, uint64_t k, uint32_t t0,
-                                                 uint32_t gid, uint32_t *pair_tiles,
-                                                 uint32_t *pair_gids, int64_t cap) {
+// t0, t0 + 1, ..., Gaussian gid).  Short spans by their own lanes, pair i of
+// every short span in iteration i (the step's spans lie end to end, so each
+// store covers a short stretch of the output); longer ones one after another
+// by the whole wave, consecutive lanes on consecutive pairs.
+__device__ __forceinline__ void wave_write_spans(uint32_t len, uint64_t k, uint32_t t0, uint32_t gid,
+                                                 uint32_t *pair_tiles, uint32_t *pair_gids, int64_t cap) {
     const int lane = threadIdx.x & (kWave - 1);
-    uint32_t x = len;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, kWave);
-        if (lane >= o) x += y;
+    const bool short_span = len <= (uint32_t)GSR_SHORT_SPAN;
+    for (uint32_t i = 0; __ballot(short_span && i < len); ++i) {  // wave-uniform
+        if (short_span && i < len && k + i < (uint64_t)cap) {
+            pair_tiles[k + i] = t0 + i;
+            pair_gids[k + i] = gid;
+        }
     }
-    const uint32_t total = lane_u32(x, kWave - 1);
-    const uint64_t spans = __ballot(len > 0u);
-    if (total >= (uint32_t)GSR_LONG_SPAN * (uint32_t)__popcll(spans)) {  // long spans: one at a time
-        for (uint64_t m = spans; m; m &= m - 1) {  // wave-uniform
-            const int src = __ffsll((long long)m) - 1;
-            const uint32_t n = lane_u32(len, src), tb = lane_u32(t0, src), gb = lane_u32(gid, src);
-            const uint64_t kb = lane_u64(k, src);
-            for (uint32_t i = (uint32_t)lane; i < n; i += kWave) {
-                if (kb + i < (uint64_t)cap) {
-                    pair_tiles[kb + i] = tb + i;
-                    pair_gids[kb + i] = gb;
-                }
+    for (uint64_t m = __ballot(!short_span); m; m &= m - 1) {  // wave-uniform
+        const int src = __ffsll((long long)m) - 1;
+        const uint32_t n = lane_u32(len, src), tb = lane_u32(t0, src), gb = lane_u32(gid, src);
+        const uint64_t kb = lane_u64(k, src);
+        for (uint32_t i = (uint32_t)lane; i < n; i += kWave) {
+            if (kb + i < (uint64_t)cap) {
+                pair_tiles[kb + i] = tb + i;
+                pair_gids[kb + i] = gb;
             }
         }
-        return;
     }
-    st.start[lane] = x - len;
-    st.k[lane] = k;
-    st.t0[lane] = t0;
-    st.gid[lane] = gid;
-    wave_sync_lds();
-    for (uint32_t i = (uint32_t)lane; i < total; i += kWave) {
-        // the span holding pair i: the last lane whose start is <= i (a lane
-        // with an empty span shares its start with the next lane)
-        int lo = 0, hi = kWave - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (st.start[mid] <= i) lo = mid; else hi = mid - 1;
-        }
-        const uint32_t m = i - st.start[lo];
-        const uint64_t kk = st.k[lo] + m;
-        if (kk < (uint64_t)cap) {
-            pair_tiles[kk] = st.t0[lo] + m;
-            pair_gids[kk] = st.gid[lo];
-        }
-    }
-    wave_sync_lds();  // every lane has read the table before it is rewritten
 }
 
 template <class Shape>
@@ -422,72 +423,49 @@ __global__ __launch_bounds__(256) void k_emit_spans(const uint32_t *sorted_ids, 
                                                     const uint64_t *off, int tiles_x,
                                                     uint32_t *pair_tiles, uint32_t *pair_gids,
                                                     int64_t cap) {
-    __shared__ SpanTable s_tab[4];
+    __shared__ RowTable<Shape> s_rows[4];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int64_t V = *num_vis;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if ((int64_t)blockIdx.x * 256 + wid * kWave >= V) return;  // wave-uniform
-    SpanTable &st = s_tab[wid];
-    bool live = false, big = false;
+    RowTable<Shape> &tb = s_rows[wid];
     uint64_t k = 0;
     uint32_t g = 0;
     int ra = 0, rb = 0, x0 = 0, x1 = 0;
-    Shape e;
+    Shape e{};
     if (j < V) {
         k = off[j];
         g = sorted_ids[j];
         const uint64_t r = rects[g];
         x0 = (int)(r & 0xffff);
         x1 = (int)((r >> 32) & 0xffff);
-        const float *rec = splats + (size_t)g * 12;
-        if (k < (uint64_t)cap && e.setup(rec)) {
+        if (k < (uint64_t)cap && e.setup(splats + (size_t)g * 12))
             e.row_band((int)((r >> 16) & 0xffff), (int)(r >> 48), ra, rb);
-            big = rb - ra > kSmallRows;
-            live = !big;
-        }
     }
-    // short bands: every lane its own rows, in lockstep
-    uint64_t ks = k;
-    for (int ty = ra;;) {
-        const bool act = live && ty < rb;
-        if (!__ballot(act)) break;  // wave-uniform
+    const uint32_t total = row_table_fill(tb, e, x0, x1, ra, rb, k, g);
+    uint32_t carry = 0;  // pairs of the earlier steps
+    for (uint32_t q0 = 0; q0 < total; q0 += kWave) {  // wave-uniform
+        const uint32_t q = q0 + (uint32_t)lane;
+        const bool item = q < total;
         uint32_t len = 0, t0 = 0;
-        if (act) {
-            int a, b;
-            if (e.row_span(ty, x0, x1 - 1, a, b)) {
-                len = (uint32_t)(b - a + 1);
-                t0 = (uint32_t)ty * (uint32_t)tiles_x + (uint32_t)a;
-            }
-            ++ty;
+        int o = 0, ty, a, b;
+        if (item && row_item_span(tb, q, o, ty, a, b)) {
+            len = (uint32_t)(b - a + 1);
+            t0 = (uint32_t)ty * (uint32_t)tiles_x + (uint32_t)a;
         }
-        wave_write_spans(st, len, ks, t0, g, pair_tiles, pair_gids, cap);
-        ks += len;
-    }
-    // long bands: one Gaussian at a time, a row per lane
-    for (uint64_t m = __ballot(big); m; m &= m - 1) {  // wave-uniform
-        const int src = __ffsll((long long)m) - 1;
-        const WaveShape<Shape> w = wave_broadcast(e, x0, x1, ra, rb, src);
-        uint64_t kb = lane_u64(k, src);
-        const uint32_t gb = lane_u32(g, src);
-        for (int t = w.ra; t < w.rb; t += kWave) {  // wave-uniform
-            const int ty = t + lane;
-            uint32_t len = 0, t0 = 0;
-            int a, b;
-            if (ty < w.rb && w.e.row_span(ty, w.x0, w.x1 - 1, a, b)) {
-                len = (uint32_t)(b - a + 1);
-                t0 = (uint32_t)ty * (uint32_t)tiles_x + (uint32_t)a;
-            }
-            // this lane's row starts after the rows of the lanes below it
-            uint32_t x = len;
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const uint32_t y = __shfl_up(x, o, kWave);
-                if (lane >= o) x += y;
-            }
-            const uint32_t total = lane_u32(x, kWave - 1);
-            wave_write_spans(st, len, kb + (x - len), t0, gb, pair_tiles, pair_gids, cap);
-            kb += total;
+        uint32_t step;
+        const uint32_t G = carry + wave_exclusive_scan(len, step);
+        if (item && q == tb.p[o]) tb.acc[o] = G;  // the Gaussian's first row
+        wave_sync_lds();
+        uint64_t kk = 0;
+        uint32_t gid = 0;
+        if (item) {
+            kk = tb.k[o] + (uint64_t)(G - tb.acc[o]);
+            gid = tb.g[o];
         }
+        wave_write_spans(len, kk, t0, gid, pair_tiles, pair_gids, cap);
+        wave_sync_lds();  // the table's reads before the next step's writes
+        carry += step;
     }
 }
 

@@ -81,12 +81,6 @@ constexpr int kSortChunk = kSortThreads * kSortItems;     // 4096 items per bloc
 constexpr int kEmitChunk = kSortChunk;
 // depth presort: blocks per group of the two-level digit offsets
 constexpr int kDepthGroup = 32;
-// ellipse rule: a Gaussian whose row band spans more tile rows than this is
-// counted and emitted by its whole wave (one row per lane), not by its lane
-#ifndef GSR_SMALL_ROWS
-#define GSR_SMALL_ROWS 16
-#endif
-constexpr int kSmallRows = GSR_SMALL_ROWS;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanChunk = kScanThreads * kScanItems;     // 4096 elements per block

@@ -321,8 +321,10 @@ __global__ void k_fill_u32(uint32_t *p, int64_t m, uint32_t v) {
 
 // Thread i tests the boundary between items i-1 and i, for four consecutive i
 // per thread (one 16-byte load plus the item before).
+// Tile ids at or beyond the tile count (none from the emitters) write nothing.
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *tiles, const int64_t *count,
-                                                     int64_t cap, uint32_t *ranges, int empty_if_over) {
+                                                     int64_t cap, uint32_t *ranges, uint32_t ntiles,
+                                                     int empty_if_over) {
     const int64_t n = live_count(count, cap, empty_if_over);
     const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
     if (i0 >= n) return;
@@ -339,11 +341,14 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *tiles, cons
         const int64_t i = i0 + k;
         if (i >= n) break;
         if (t[k + 1] != t[k]) {
-            ranges[2 * (int64_t)t[k + 1]] = (uint32_t)i;
-            if (i > 0) ranges[2 * (int64_t)t[k] + 1] = (uint32_t)i;
+            if (t[k + 1] < ntiles) ranges[2 * (int64_t)t[k + 1]] = (uint32_t)i;
+            if (i > 0 && t[k] < ntiles) ranges[2 * (int64_t)t[k] + 1] = (uint32_t)i;
         }
     }
-    if (i0 + 4 >= n && i0 < n) ranges[2 * (int64_t)tiles[n - 1] + 1] = (uint32_t)n;
+    if (i0 + 4 >= n && i0 < n) {
+        const uint32_t last = tiles[n - 1];
+        if (last < ntiles) ranges[2 * (int64_t)last + 1] = (uint32_t)n;
+    }
 }
 
 hipError_t launch_tile_ranges(const uint32_t *sorted_tiles, const int64_t *num_pairs, int64_t cap,
@@ -352,7 +357,7 @@ hipError_t launch_tile_ranges(const uint32_t *sorted_tiles, const int64_t *num_p
     k_fill_u32<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(ranges, m, 0u);
     if (cap > 0)
         k_tile_ranges<<<(unsigned)((cap + 1023) / 1024), 256, 0, s>>>(sorted_tiles, num_pairs, cap, ranges,
-                                                                      empty_if_over);
+                                                                      (uint32_t)num_tiles, empty_if_over);
     return hipGetLastError();
 }
 
