@@ -128,6 +128,17 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
     return x;
 }
 
+// Inclusive running maximum over the wave, the same DPP lane moves.
+__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t x) {
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false));
+    return x;
+}
+
 // Exclusive prefix over the wave of one value per lane, and the wave's total.
 __device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, uint32_t &total) {
     const uint32_t x = wave_inclusive_sum(v);
@@ -138,36 +149,33 @@ __device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, uint32_t &to
 // One wave's Gaussians for the flattened row walk of the span kernels.  The
 // rows of the wave's 64 Gaussians (lane-major: lane 0's band, then lane 1's,
 // ...) are numbered 0 .. total-1 and taken 64 per step, one per lane, so every
-// lane computes a span whatever the lengths of the bands; item q belongs to
-// the last lane whose band prefix p is <= q, and is row ra + q - p of its band.
+// lane computes a span whatever the lengths of the bands.  Item q belongs to
+// the last lane whose band prefix p is <= q and is row ra + q - p of its band:
+// per step each Gaussian whose band starts in the step marks that item's slot
+// (tagged with the step), and a running maximum over the lanes hands every
+// item the last mark at or before it; items before the step's first mark
+// continue the previous step's last Gaussian.
 template <class Shape>
 struct RowTable {
     Shape sh[kWave];
     int x0[kWave], x1[kWave], ra[kWave], rb[kWave];
-    uint32_t p[kWave];    // exclusive prefix of the band lengths
-    uint32_t acc[kWave];  // the count's pair totals; the emission's prefix at the first row
-    uint64_t k[kWave];    // output index of the Gaussian's first pair
+    uint32_t p[kWave];     // exclusive prefix of the band lengths
+    uint32_t acc[kWave];   // the count's pair totals; the emission's prefix at the first row
+    uint32_t mark[kWave];  // step << 8 | (lane + 1) of the Gaussian whose band starts here
+    uint64_t k[kWave];     // output index of the Gaussian's first pair
     uint32_t g[kWave];
 };
 
-__device__ __forceinline__ int row_owner(const uint32_t *p, uint32_t q) {
-    int lo = 0, hi = kWave - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (p[mid] <= q) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 // Loads this lane's Gaussian into the wave's table: shape, columns [x0, x1),
 // row band [ra, rb) (empty when the shape has no tiles).  Returns the number
-// of items (rows) of the whole wave.  Contains wave barriers.
+// of items (rows) of the whole wave; p = this lane's band prefix.  Contains
+// wave barriers.
 template <class Shape>
 __device__ __forceinline__ uint32_t row_table_fill(RowTable<Shape> &tb, const Shape &e, int x0, int x1,
-                                                   int ra, int rb, uint64_t k, uint32_t g) {
+                                                   int ra, int rb, uint64_t k, uint32_t g, uint32_t &p) {
     const int lane = threadIdx.x & (kWave - 1);
     uint32_t total;
-    const uint32_t p = wave_exclusive_scan((uint32_t)(rb - ra), total);
+    p = wave_exclusive_scan((uint32_t)(rb - ra), total);
     tb.sh[lane] = e;
     tb.x0[lane] = x0;
     tb.x1[lane] = x1;
@@ -175,20 +183,40 @@ __device__ __forceinline__ uint32_t row_table_fill(RowTable<Shape> &tb, const Sh
     tb.rb[lane] = rb;
     tb.p[lane] = p;
     tb.acc[lane] = 0u;
+    tb.mark[lane] = 0xffffffffu;  // a step tag no step has
     tb.k[lane] = k;
     tb.g[lane] = g;
     wave_sync_lds();
     return total;
 }
 
-// Span of flattened item q (< total): the tile row and its inclusive column
-// span [a, b] in the owner's shape; false when the row misses the shape.
+// Owner (lane) of item q0 + lane of the step starting at item q0; `carry` is
+// the owner of the previous step's last item and is advanced to this step's.
+// This lane's Gaussian has band prefix p and nb rows.  Called by the whole
+// wave; contains wave barriers.
 template <class Shape>
-__device__ __forceinline__ bool row_item_span(const RowTable<Shape> &tb, uint32_t q, int &o, int &ty,
+__device__ __forceinline__ int step_owner(RowTable<Shape> &tb, uint32_t q0, uint32_t p, uint32_t nb,
+                                          int &carry) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t tag = q0 / kWave;
+    if (nb > 0u && p >= q0 && p - q0 < (uint32_t)kWave) tb.mark[p - q0] = (tag << 8) | (uint32_t)(lane + 1);
+    wave_sync_lds();
+    const uint32_t m = tb.mark[lane];
+    const uint32_t last = wave_inclusive_max((m >> 8) == tag ? (m & 0xffu) : 0u);
+    const int o = last ? (int)last - 1 : carry;
+    carry = lane_i32(o, kWave - 1);
+    return o;
+}
+
+// Span of item q of Gaussian (lane) o: the tile row and its inclusive column
+// span [a, b]; false when the row misses the shape or q is not in o's band.
+template <class Shape>
+__device__ __forceinline__ bool row_item_span(const RowTable<Shape> &tb, uint32_t q, int o, int &ty,
                                               int &a, int &b) {
-    o = row_owner(tb.p, q);
-    ty = tb.ra[o] + (int)(q - tb.p[o]);
-    return ty < tb.rb[o] && tb.sh[o].row_span(ty, tb.x0[o], tb.x1[o] - 1, a, b);
+    const uint32_t r = q - tb.p[o];
+    if (r >= (uint32_t)(tb.rb[o] - tb.ra[o])) return false;
+    ty = tb.ra[o] + (int)r;
+    return tb.sh[o].row_span(ty, tb.x0[o], tb.x1[o] - 1, a, b);
 }
 
 // Pair count of one visible Gaussian under a shape rule: its tiles meeting the
@@ -207,10 +235,13 @@ __device__ __forceinline__ uint64_t shape_pair_count(const float *splats, const 
             e.row_band((int)((r >> 16) & 0xffff), (int)(r >> 48), ra, rb);
         }
     }
-    const uint32_t total = row_table_fill(tb, e, x0, x1, ra, rb, 0ull, g);
+    uint32_t p;
+    const uint32_t total = row_table_fill(tb, e, x0, x1, ra, rb, 0ull, g, p);
+    int carry = 0;
     for (uint32_t q0 = 0; q0 < total; q0 += kWave) {  // wave-uniform
         const uint32_t q = q0 + (uint32_t)lane;
-        int o, ty, a, b;
+        const int o = step_owner(tb, q0, p, (uint32_t)(rb - ra), carry);
+        int ty, a, b;
         if (q < total && row_item_span(tb, q, o, ty, a, b)) atomicAdd(&tb.acc[o], (uint32_t)(b - a + 1));
     }
     wave_sync_lds();
@@ -442,13 +473,16 @@ __global__ __launch_bounds__(256) void k_emit_spans(const uint32_t *sorted_ids, 
         if (k < (uint64_t)cap && e.setup(splats + (size_t)g * 12))
             e.row_band((int)((r >> 16) & 0xffff), (int)(r >> 48), ra, rb);
     }
-    const uint32_t total = row_table_fill(tb, e, x0, x1, ra, rb, k, g);
+    uint32_t p;
+    const uint32_t total = row_table_fill(tb, e, x0, x1, ra, rb, k, g, p);
     uint32_t carry = 0;  // pairs of the earlier steps
+    int carry_owner = 0;
     for (uint32_t q0 = 0; q0 < total; q0 += kWave) {  // wave-uniform
         const uint32_t q = q0 + (uint32_t)lane;
         const bool item = q < total;
+        const int o = step_owner(tb, q0, p, (uint32_t)(rb - ra), carry_owner);
         uint32_t len = 0, t0 = 0;
-        int o = 0, ty, a, b;
+        int ty, a, b;
         if (item && row_item_span(tb, q, o, ty, a, b)) {
             len = (uint32_t)(b - a + 1);
             t0 = (uint32_t)ty * (uint32_t)tiles_x + (uint32_t)a;
