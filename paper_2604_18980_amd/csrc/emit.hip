@@ -160,7 +160,7 @@ struct RowTable {
     Shape sh[kWave];
     int x0[kWave], x1[kWave], ra[kWave], rb[kWave];
     uint32_t p[kWave];     // exclusive prefix of the band lengths
-    uint32_t acc[kWave];   // the count's pair totals; the emission's prefix at the first row
+    uint32_t acc[kWave];   // the count's pair totals
     uint32_t mark[kWave];  // step << 8 | (lane + 1) of the Gaussian whose band starts here
     uint64_t k[kWave];     // output index of the Gaussian's first pair
     uint32_t g[kWave];
@@ -191,18 +191,20 @@ __device__ __forceinline__ uint32_t row_table_fill(RowTable<Shape> &tb, const Sh
 }
 
 // Owner (lane) of item q0 + lane of the step starting at item q0; `carry` is
-// the owner of the previous step's last item and is advanced to this step's.
-// This lane's Gaussian has band prefix p and nb rows.  Called by the whole
-// wave; contains wave barriers.
+// the owner of the previous step's last item and is advanced to this step's;
+// `first` tells whether the item is its Gaussian's first row.  This lane's
+// Gaussian has band prefix p and nb rows.  Called by the whole wave; contains
+// wave barriers.
 template <class Shape>
 __device__ __forceinline__ int step_owner(RowTable<Shape> &tb, uint32_t q0, uint32_t p, uint32_t nb,
-                                          int &carry) {
+                                          int &carry, bool &first) {
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t tag = q0 / kWave;
     if (nb > 0u && p >= q0 && p - q0 < (uint32_t)kWave) tb.mark[p - q0] = (tag << 8) | (uint32_t)(lane + 1);
     wave_sync_lds();
     const uint32_t m = tb.mark[lane];
-    const uint32_t last = wave_inclusive_max((m >> 8) == tag ? (m & 0xffu) : 0u);
+    first = (m >> 8) == tag;
+    const uint32_t last = wave_inclusive_max(first ? (m & 0xffu) : 0u);
     const int o = last ? (int)last - 1 : carry;
     carry = lane_i32(o, kWave - 1);
     return o;
@@ -240,7 +242,8 @@ __device__ __forceinline__ uint64_t shape_pair_count(const float *splats, const 
     int carry = 0;
     for (uint32_t q0 = 0; q0 < total; q0 += kWave) {  // wave-uniform
         const uint32_t q = q0 + (uint32_t)lane;
-        const int o = step_owner(tb, q0, p, (uint32_t)(rb - ra), carry);
+        bool first;
+        const int o = step_owner(tb, q0, p, (uint32_t)(rb - ra), carry, first);
         int ty, a, b;
         if (q < total && row_item_span(tb, q, o, ty, a, b)) atomicAdd(&tb.acc[o], (uint32_t)(b - a + 1));
     }
@@ -411,8 +414,9 @@ hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
 // Gaussians, one per lane, and walks their rows flattened, 64 (Gaussian, row)
 // items per step (RowTable): every lane recomputes the span of its item
 // exactly as k_pair_counts counted it, the item's first pair follows the
-// Gaussian's earlier rows (a wave prefix sum over the steps, less its value at
-// the Gaussian's first row), and the whole wave writes the step's spans.
+// Gaussian's earlier rows (a wave prefix sum carried over the steps, less its
+// value at the Gaussian's first row), and the whole wave writes the step's
+// spans.
 // Pairs at or beyond the capacity are not written.
 
 // spans of up to this many pairs are written by their own lanes
@@ -477,10 +481,12 @@ __global__ __launch_bounds__(256) void k_emit_spans(const uint32_t *sorted_ids, 
     const uint32_t total = row_table_fill(tb, e, x0, x1, ra, rb, k, g, p);
     uint32_t carry = 0;  // pairs of the earlier steps
     int carry_owner = 0;
+    uint32_t carry_g0 = 0;  // prefix at the first row of the previous step's last Gaussian
     for (uint32_t q0 = 0; q0 < total; q0 += kWave) {  // wave-uniform
         const uint32_t q = q0 + (uint32_t)lane;
         const bool item = q < total;
-        const int o = step_owner(tb, q0, p, (uint32_t)(rb - ra), carry_owner);
+        bool first;
+        const int o = step_owner(tb, q0, p, (uint32_t)(rb - ra), carry_owner, first);
         uint32_t len = 0, t0 = 0;
         int ty, a, b;
         if (item && row_item_span(tb, q, o, ty, a, b)) {
@@ -489,12 +495,15 @@ __global__ __launch_bounds__(256) void k_emit_spans(const uint32_t *sorted_ids, 
         }
         uint32_t step;
         const uint32_t G = carry + wave_exclusive_scan(len, step);
-        if (item && q == tb.p[o]) tb.acc[o] = G;  // the Gaussian's first row
-        wave_sync_lds();
+        // the prefix at the Gaussian's first row: the prefix never decreases
+        // along the items, so it is the running maximum over the first rows
+        const uint32_t f = wave_inclusive_max(first ? G + 1u : 0u);
+        const uint32_t G0 = f ? f - 1u : carry_g0;
+        carry_g0 = lane_u32(G0, kWave - 1);
         uint64_t kk = 0;
         uint32_t gid = 0;
         if (item) {
-            kk = tb.k[o] + (uint64_t)(G - tb.acc[o]);
+            kk = tb.k[o] + (uint64_t)(G - G0);
             gid = tb.g[o];
         }
         wave_write_spans(len, kk, t0, gid, pair_tiles, pair_gids, cap);
