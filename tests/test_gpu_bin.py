@@ -33,11 +33,19 @@ def _case(name):
     if name == "wide_4112x4112":     # 257 x 257 = 66049 tiles: fallback route
         sc, cam = scenes.mid_scene(n=20_000, seed=4, width=4112, height=4112)
         return sc, cam, {}
+    if name == "giants_1024x2048":   # 64 x 128 tiles; 40 Gaussians up to the whole image
+        # bands beyond 64 tile rows (one Gaussian's rows over several steps of
+        # the span kernels' row walk) and spans beyond 16 tiles, among small ones
+        sc, cam = scenes.tiny_scene(n=3000, seed=26)
+        ls = sc.log_scales.copy()
+        ls[:, :40] = np.log(np.linspace(0.3, 2.5, 40, dtype=np.float32))[None, :]
+        sc = scenes.Scene(sc.means, ls, sc.quats, sc.opacity_logits, sc.sh, sc.sh_degree)
+        return sc, scenes.make_camera(np.eye(3), np.zeros(3), 1024, 2048), {}
     raise KeyError(name)
 
 
 CASES = ["tiny128", "tiny128_ada", "ragged_257x129", "ragged_300x301", "mid_1920x1080",
-         "wide_4112x4112"]
+         "wide_4112x4112", "giants_1024x2048"]
 
 
 @pytest.mark.parametrize("rule", [0, 1, 2], ids=["rect", "ellipse", "obb"])
@@ -82,7 +90,7 @@ def test_bin_empty_and_culled(O):
 
 
 @pytest.mark.parametrize("rule", [0, 1], ids=["rect", "ellipse"])
-@pytest.mark.parametrize("name", ["tiny128", "ragged_300x301", "wide_4112x4112"])
+@pytest.mark.parametrize("name", ["tiny128", "ragged_300x301", "wide_4112x4112", "giants_1024x2048"])
 def test_bin_overflow_bins_nothing(O, name, rule):
     """Capacity below the pair count: the required count is reported, no list
     is produced (every range empty, image = background), and a regrown buffer
