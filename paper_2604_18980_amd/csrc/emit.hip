@@ -433,21 +433,25 @@ __device__ __forceinline__ void wave_write_spans(uint32_t len, uint64_t k, uint3
                                                  uint32_t *pair_tiles, uint32_t *pair_gids, int64_t cap) {
     const int lane = threadIdx.x & (kWave - 1);
     const bool short_span = len <= (uint32_t)GSR_SHORT_SPAN;
-    for (uint32_t i = 0; __ballot(short_span && i < len); ++i) {  // wave-uniform
-        if (short_span && i < len && k + i < (uint64_t)cap) {
-            pair_tiles[k + i] = t0 + i;
-            pair_gids[k + i] = gid;
+    // the span's pairs below the capacity
+    const uint64_t room = k < (uint64_t)cap ? (uint64_t)cap - k : 0ull;
+    const uint32_t n = room < (uint64_t)len ? (uint32_t)room : len;
+    const uint32_t ns = short_span ? n : 0u;
+    uint32_t *pt = pair_tiles + (ns ? k : 0ull), *pg = pair_gids + (ns ? k : 0ull);
+    for (uint32_t i = 0; __ballot(i < ns); ++i) {  // wave-uniform
+        if (i < ns) {
+            pt[i] = t0 + i;
+            pg[i] = gid;
         }
     }
-    for (uint64_t m = __ballot(!short_span); m; m &= m - 1) {  // wave-uniform
+    for (uint64_t m = __ballot(!short_span && n > 0u); m; m &= m - 1) {  // wave-uniform
         const int src = __ffsll((long long)m) - 1;
-        const uint32_t n = lane_u32(len, src), tb = lane_u32(t0, src), gb = lane_u32(gid, src);
+        const uint32_t nn = lane_u32(n, src), tb = lane_u32(t0, src), gb = lane_u32(gid, src);
         const uint64_t kb = lane_u64(k, src);
-        for (uint32_t i = (uint32_t)lane; i < n; i += kWave) {
-            if (kb + i < (uint64_t)cap) {
-                pair_tiles[kb + i] = tb + i;
-                pair_gids[kb + i] = gb;
-            }
+        uint32_t *ptb = pair_tiles + kb, *pgb = pair_gids + kb;
+        for (uint32_t i = (uint32_t)lane; i < nn; i += kWave) {
+            ptb[i] = tb + i;
+            pgb[i] = gb;
         }
     }
 }
