@@ -40,11 +40,19 @@ PEAK_HBM_GBS = 8000.0
 # gfx950 (measured: ~2.5 cycles per dependent-free v_fma_f32 including loop
 # overhead), so no packed-FP32 instructions are needed to reach it.
 PEAK_FP32_TFLOPS = 157.3
-# FLOP of one evaluation of eq. (1)-(2) at one pixel, in two parts.  Test:
-# dx, dy (2), u = dx + beta dy (2), A u^2 (2), gamma dy^2 (2), their sum (1),
-# the live-and-alpha >= tau test on the exponent (1) = 10.  Blend, where it
-# passes: exp (1), times opacity (1), clamp (1), alpha T (1), T - alpha T (1),
-# the stop test (1), three colour FMAs (6) = 12.
+# FLOP of the plain algorithm per list evaluation E (per pixel, one list entry
+# up to and including the one that stops the pixel): the offset dx, dy (2),
+# the quadratic form of eq. (1) as A (dx + beta dy)^2 + gamma dy^2 (6), the
+# exponential (1), times opacity (1), the 0.99 clamp (1), the alpha >= tau
+# test (1) = 12; per blended evaluation (alpha >= tau, not the stopping one):
+# T (1 - alpha) (2), the stop test (1), alpha T (1), three colour FMAs (6) = 10.
+# The roofline divides these over E and the blended count by the raster time.
+FLOP_EVAL = 12
+FLOP_BLEND_EVAL = 10
+# The same work as this design executes it: 10 FLOP per pixel of every strip
+# evaluation its per-strip bound did not rule out (dx, dy, u, A u^2, gamma dy^2,
+# sum, test) and 12 per blend (exp, opacity, clamp, alpha T, T - alpha T, stop
+# test, three colour FMAs); reported beside the roofline, labelled.
 FLOP_TEST = 10
 FLOP_BLEND = 12
 PSNR_TARGET_DB = 29.8
@@ -72,7 +80,9 @@ def parse():
     p.add_argument("--height", type=int, default=3456)
     p.add_argument("--K", type=float, default=None, help="fixed K (skip the search)")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample-tiles", type=int, default=1024)
+    p.add_argument("--cpu-sample-tiles", type=int, default=4096)
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the K sweep, the offline K calibration and the mid-scene line")
     p.add_argument("--workload", choices=("city", "diff", "batched", "contrib"), default="city",
                    help="city: the headline FPS line; diff: forward+backward on the 1M "
                         "differentiable workload; batched: 64 views in one graph; contrib: "
@@ -239,11 +249,40 @@ def search_K(torch, R, gsr, scene, cam, cam_s, fb_plain, fb, stream, **mode):
     return float(np.float32(best))
 
 
+def host_cpu():
+    """nproc and the CPU model of this host (lscpu), for the CPU baseline."""
+    import subprocess
+    try:
+        nproc = int(subprocess.run(["nproc"], capture_output=True, text=True).stdout.strip())
+    except (OSError, ValueError):
+        nproc = os.cpu_count()
+    model = None
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return nproc, model
+
+
 def cpu_baseline(args, scene_h, cam, K, n_tiles_sample, t_upper=None, lut_depth_max=100.0,
                  extent_rule=0):
-    """The oracle (single-threaded FP64 C) on a bounded sample of the same
-    frame, scaled to one whole frame."""
+    """The oracle (FP64 C, its OpenMP build: the per-Gaussian preprocess and
+    the per-tile blend on all the host's threads; emission and sort
+    single-threaded) on a bounded sample of the same frame, scaled to one
+    whole frame."""
     from oracle import oracle as O
+    O.use_openmp(True)
+    try:
+        return _cpu_baseline(O, args, scene_h, cam, K, n_tiles_sample, t_upper, lut_depth_max,
+                             extent_rule)
+    finally:
+        O.use_openmp(False)
+
+
+def _cpu_baseline(O, args, scene_h, cam, K, n_tiles_sample, t_upper, lut_depth_max, extent_rule):
     mode = O.Mode(adagscale=True, K=K, t_upper=t_upper, lut_depth_max=lut_depth_max,
                   extent_rule=extent_rule)
     t0 = time.perf_counter()
@@ -291,12 +330,16 @@ def cpu_baseline(args, scene_h, cam, K, n_tiles_sample, t_upper=None, lut_depth_
     O.blend(fr, cam, tiles=tiles, rec=rec)
     t_bl = (time.perf_counter() - t0) * (TX * TY) / len(tiles)
     t_frame = t_pre + t_es + t_bl
-    return {"value": 1.0 / t_frame, "unit": "FPS", "cores": 1, "kind": "oracle",
+    threads = O.threads()
+    nproc, model = host_cpu()
+    return {"value": 1.0 / t_frame, "unit": "FPS", "cores": threads, "kind": "oracle",
+            "nproc": nproc, "cpu_model": model,
+            "stage_s": {"preprocess": t_pre, "emit_sort": t_es, "blend": t_bl},
             "sample": (f"AdaGScale K={K:g}, {('rectangle', 'ellipse', 'oriented-box')[extent_rule]} tile test: "
-                       f"full preprocess of {scene_h.n} Gaussians ({t_pre:.1f} s), "
-                       f"emit+sort of a 1/64 sample of visible Gaussians scaled x64 ({t_es:.1f} s), "
-                       f"blend of {len(tiles)} random tiles scaled to {TX * TY} tiles ({t_bl:.1f} s); "
-                       f"single-threaded FP64 C, -O2")}
+                       f"full preprocess of {scene_h.n} Gaussians ({t_pre:.2f} s, {threads} threads), "
+                       f"emit+sort of a 1/64 sample of visible Gaussians scaled x64 ({t_es:.2f} s, "
+                       f"1 thread), blend of {len(tiles)} random tiles scaled to {TX * TY} tiles "
+                       f"({t_bl:.2f} s, {threads} threads); FP64 C, -O2 -fopenmp")}
 
 
 def bench_diff(args):
@@ -534,6 +577,94 @@ def measure(torch, R, scene, cam_s, mode_s, fb, P, args, stream, staged_too=Fals
     return out
 
 
+K_SWEEP = (0.0, 0.3, 1.0, 3.0, 10.0, 30.0)
+
+
+def k_sweep(torch, R, gsr, scene, cam, cam_s, ref, rule, ada, args):
+    """FPS, pairs and PSNR(AdaGScale vs plain) at fixed K values, each frame
+    replayed from a HIP graph."""
+    out, fb = [], None
+    for K in K_SWEEP:
+        fb = R.render(scene, cam, adagscale=True, K=K, fb=fb, slack=1.05, extent_rule=rule, **ada)
+        torch.cuda.synchronize()
+        P = int(fb.num_pairs.item())
+        mode = gsr.mode_struct(adagscale=True, K=K, extent_rule=rule, **ada)
+        ms, _ = graph_frames(torch, R, scene, cam_s, mode, fb, max(5, args.steps // 2), args.warmup)
+        out.append({"K": K, "pairs": P, "psnr_db_vs_plain": psnr_t(torch, fb.image, ref),
+                    "fps": 1000.0 / ms, "ms_p50": ms})
+        log(f"K sweep {K}: pairs {P} psnr {out[-1]['psnr_db_vs_plain']:.2f} fps {out[-1]['fps']:.1f}")
+    del fb
+    return out
+
+
+def offline_k(torch, R, gsr, calib, scene, cam, cam_s, ref, cal_cams, rule, ada, args, K_view):
+    """Sec. 3.4's offline calibration of K: binary search on the calibration
+    views for the largest K whose mean PSNR(AdaGScale vs plain) stays at the
+    target, then the measured view (not among them) rendered at that K: its
+    actual PSNR, pairs and FPS, beside the K tuned on the measured view."""
+    t0 = time.perf_counter()
+    K_cal, p_cal = calib.search_k(scene, cal_cams, PSNR_TARGET_DB, lo=1e-2, hi=1e5, iters=16,
+                                  extent_rule=rule, **ada)
+    torch.cuda.synchronize()
+    t_k = time.perf_counter() - t0
+    fb = R.render(scene, cam, adagscale=True, K=K_cal, slack=1.05, extent_rule=rule, **ada)
+    torch.cuda.synchronize()
+    P = int(fb.num_pairs.item())
+    mode = gsr.mode_struct(adagscale=True, K=K_cal, extent_rule=rule, **ada)
+    ms, _ = graph_frames(torch, R, scene, cam_s, mode, fb, args.steps, args.warmup)
+    res = {"views": len(cal_cams), "target_psnr_db": PSNR_TARGET_DB, "K": K_cal,
+           "calibration_views_mean_psnr_db": p_cal, "seconds": t_k,
+           "measured_view_psnr_db": psnr_t(torch, fb.image, ref), "pairs": P,
+           "fps": 1000.0 / ms, "K_tuned_on_measured_view": K_view}
+    log(f"offline K: {K_cal} (mean {p_cal:.2f} dB on {len(cal_cams)} views, {t_k:.1f} s); measured "
+        f"view {res['measured_view_psnr_db']:.2f} dB, {P} pairs, {res['fps']:.1f} FPS")
+    del fb
+    return res
+
+
+def mid_line(torch, R, gsr, calib, scenes, args):
+    """The clustered mid scene (500K, 1920x1080), where the 16-view T_upper
+    table falls below 1: AdaGScale with the calibrated table against the
+    trivial bound, each with K searched on the view to the PSNR target, and
+    both at one fixed K (the table's effect at equal K)."""
+    dev = torch.device("cuda:0")
+    scene_h, cam = scenes.mid_scene()
+    scene = R.DeviceScene.from_host(scene_h, dev)
+    cam_s = gsr.camera_struct(cam)
+    dmax = 150.0
+    t0 = time.perf_counter()
+    table, _ = calib.t_upper_table(scene, scenes.mid_calibration_cameras(CALIB_VIEWS), dmax)
+    torch.cuda.synchronize()
+    t_cal = time.perf_counter() - t0
+    fb_p = R.render(scene, cam, slack=1.05)
+    torch.cuda.synchronize()
+    ref = fb_p.image.clone()
+    P_plain = int(fb_p.num_pairs.item())
+    ms_p, _ = graph_frames(torch, R, scene, cam_s, gsr.mode_struct(), fb_p, args.steps, args.warmup)
+    out = {"workload": "mid 500K 1920x1080, SH degree 3", "t_upper": [float(x) for x in table],
+           "lut_depth_max": dmax, "calibration_seconds": t_cal,
+           "plain": {"pairs": P_plain, "fps": 1000.0 / ms_p}}
+    fb = R.FrameBuffers(scene.n, cam["width"], cam["height"], int(P_plain * 1.05) + 1024, dev)
+    for name, t_up, dm in (("calibrated", table, dmax), ("trivial_bound", None, 100.0)):
+        mode = dict(t_upper=t_up, lut_depth_max=dm)
+        K = search_K(torch, R, gsr, scene, cam, cam_s, fb_p, fb, None, **mode)
+        R.render(scene, cam, adagscale=True, K=K, fb=fb, **mode)
+        torch.cuda.synchronize()
+        P = int(fb.num_pairs.item())
+        p = psnr_t(torch, fb.image, ref)
+        ms, _ = graph_frames(torch, R, scene, cam_s, gsr.mode_struct(adagscale=True, K=K, **mode),
+                             fb, args.steps, args.warmup)
+        R.render(scene, cam, adagscale=True, K=1.0, fb=fb, **mode)
+        torch.cuda.synchronize()
+        out[name] = {"K": K, "pairs": P, "psnr_db_vs_plain": p, "fps": 1000.0 / ms,
+                     "pairs_at_K1": int(fb.num_pairs.item())}
+        log(f"mid {name}: K={K} pairs {P} psnr {p:.2f} fps {1000.0 / ms:.1f}; "
+            f"pairs at K=1 {out[name]['pairs_at_K1']}")
+    del fb, fb_p, scene
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -669,8 +800,10 @@ def main():
         res_pe.update(psnr_db_vs_plain=psnr_pe, raster_work=raster_work(R, fb_pe, cam_s))
     # dominant kernel: the rasterizer (one kernel per frame, timed by its events)
     raster_ms = st_a["raster"]
-    flops = FLOP_TEST * 64 * W_ada["strip_evaluations"] + FLOP_BLEND * W_ada["blended"]
+    flops = FLOP_EVAL * W_ada["list_evaluations"] + FLOP_BLEND_EVAL * W_ada["blended"]
     achieved = flops / (raster_ms * 1e-3) / 1e12
+    flops_exec = FLOP_TEST * 64 * W_ada["strip_evaluations"] + FLOP_BLEND * W_ada["blended"]
+    achieved_exec = flops_exec / (raster_ms * 1e-3) / 1e12
     # HBM-bound stages: algorithmic bytes of this design
     n = scene.n
     vis = int((fb_a.tiles_touched > 0).sum().item())
@@ -725,6 +858,7 @@ def main():
                    "sh_degree": 3,
                    "mode": (f"adagscale, {rule_name[rule]} tile test, "
                             + ("T_upper = 1" if args.uncalibrated else cal)),
+                   "extent_rule": rule_name[rule],
                    "K": K, "psnr_target_db": PSNR_TARGET_DB},
         "calibration": None if args.uncalibrated else {
             "views": CALIB_VIEWS, "lut_depth_max": LUT_DEPTH_MAX,
@@ -748,9 +882,17 @@ def main():
         "roofline": {"kernel": "k_raster_wave", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": raster_traffic(rule),
-                     "basis": f"{FLOP_TEST} FLOP x 64 pixels x {W_ada['strip_evaluations']} executed "
-                              f"strip evaluations + {FLOP_BLEND} FLOP x {W_ada['blended']} blended "
-                              f"pixel evaluations of eq. (1)-(2); peak = FP32 vector FMA rate"},
+                     "basis": f"{FLOP_EVAL} FLOP x {W_ada['list_evaluations']} list evaluations E "
+                              f"(per pixel, entries up to its stop) + {FLOP_BLEND_EVAL} FLOP x "
+                              f"{W_ada['blended']} blended evaluations of eq. (1)-(2), over the "
+                              f"raster kernel's time ({raster_ms * 1e3:.1f} us, HIP events); peak = "
+                              f"FP32 vector FMA rate",
+                     "executed_lanes": {
+                         "achieved": achieved_exec, "frac": achieved_exec / PEAK_FP32_TFLOPS,
+                         "basis": f"the work as this design executes it: {FLOP_TEST} FLOP x 64 "
+                                  f"pixels x {W_ada['strip_evaluations']} strip evaluations its "
+                                  f"per-strip bound did not rule out + {FLOP_BLEND} FLOP x "
+                                  f"{W_ada['blended']} blends"}},
     }
     if not args.ada_only:
         out["plain"] = res_p
@@ -759,11 +901,20 @@ def main():
         out["speedup_vs_plain_ellipse"] = res_pe["ms_p50"] / ms_a
         out["pair_ratio"] = P_ada / max(P_plain, 1)
         out["pair_reduction_vs_plain_ellipse"] = 1.0 - P_ada / max(P_pe, 1)
-    if not args.no_cpu_baseline:
+    if not args.ada_only and not args.no_extras:
+        out["k_sweep"] = k_sweep(torch, R, gsr, scene, cam, cam_s, ref, rule, ada, args)
+        if not args.uncalibrated:
+            out["offline_K"] = offline_k(torch, R, gsr, calib, scene, cam, cam_s, ref, cal_cams, rule,
+                                         ada, args, K)
+    if not args.ada_only and not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(args, scene_h, cam, K, args.cpu_sample_tiles,
                                            t_upper=ada["t_upper"], lut_depth_max=ada["lut_depth_max"],
                                            extent_rule=rule)
+    if not args.ada_only and not args.no_extras:
+        del fb_a, fb_p, fb_pe, scene
+        torch.cuda.empty_cache()
+        out["mid_scene"] = mid_line(torch, R, gsr, calib, scenes, args)
     print(json.dumps(out))
 
 

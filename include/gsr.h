@@ -55,6 +55,10 @@
 #include <stddef.h>
 #include <stdint.h>
 
+/* Only the entry points declared here are exported from libgsr.so (it is
+ * built with hidden visibility by default). */
+#define GS_API __attribute__((visibility("default")))
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -148,7 +152,7 @@ typedef struct {
 /* Bytes of scratch ("workspace") that gs_emit_pairs, gs_sort and gs_bin_pairs
  * need for n Gaussians, pair_capacity pairs and a width x height image.  The
  * same workspace may be reused by consecutive calls on one stream. */
-size_t gs_workspace_size(int64_t n, int64_t pair_capacity, int width, int height);
+GS_API size_t gs_workspace_size(int64_t n, int64_t pair_capacity, int width, int height);
 
 /* Stage 1 (Sec. 2.1 preprocessing; Sec. 3.3 AdaGScale preprocessing).
  * One thread per Gaussian: near-plane cull (z <= 0.2), EWA projection of the
@@ -160,7 +164,7 @@ size_t gs_workspace_size(int64_t n, int64_t pair_capacity, int width, int height
  * double precision.
  * Out: splats [n][12], rects [n], tiles_touched [n] = the rectangle's area
  * (0 = no pairs; under rule 1 an upper bound of the pairs). */
-gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_mode *mode,
+GS_API gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_mode *mode,
                         float *splats, uint64_t *rects, uint32_t *tiles_touched, void *stream);
 
 /* Stage 2 (Sec. 2.1 Gaussian-tile pair generation; Sec. 3.3: the rectangle
@@ -178,7 +182,7 @@ gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_mo
  * caller must grow the buffers and run the frame again (stages 3-4 then see a
  * truncated list and their output is meaningless).
  * ws: workspace of at least gs_workspace_size(n, pair_capacity, W, H) bytes. */
-gs_status gs_emit_pairs(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
+GS_API gs_status gs_emit_pairs(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
                         int64_t n, const gs_camera *cam, int extent_rule, uint32_t *pair_tiles,
                         uint32_t *pair_gids, int64_t pair_capacity, int64_t *num_pairs, void *ws,
                         size_t ws_bytes, void *stream);
@@ -190,7 +194,7 @@ gs_status gs_emit_pairs(const float *splats, const uint64_t *rects, const uint32
  * ids to sorted_tiles and the Gaussian ids to sorted_gids (both distinct from
  * the inputs, pair_capacity entries each), and ranges [num_tiles][2] as
  * (start, end), (0, 0) for a tile with no pairs. */
-gs_status gs_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids, const int64_t *num_pairs,
+GS_API gs_status gs_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids, const int64_t *num_pairs,
                   int64_t pair_capacity, const gs_camera *cam, uint32_t *sorted_tiles,
                   uint32_t *sorted_gids, uint32_t *ranges, void *ws, size_t ws_bytes,
                   void *stream);
@@ -214,7 +218,7 @@ gs_status gs_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids, const i
  * buffers and run the frame again.
  * ws: workspace of at least gs_workspace_size(n, pair_capacity, W, H) bytes for
  * this camera's W x H. */
-gs_status gs_bin_pairs(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
+GS_API gs_status gs_bin_pairs(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
                        int64_t n, const gs_camera *cam, int extent_rule, uint32_t *sorted_gids,
                        uint32_t *sorted_tiles, uint32_t *ranges, int64_t pair_capacity,
                        int64_t *num_pairs, void *ws, size_t ws_bytes, void *stream);
@@ -227,7 +231,7 @@ gs_status gs_bin_pairs(const float *splats, const uint64_t *rects, const uint32_
  * position of the last blended Gaussian, 0 if none).  n_evaluated (nullable,
  * uint32 [H][W]) receives the number of list entries the pixel evaluated: up
  * to and including the one that stopped it, else the whole list. */
-gs_status gs_rasterize(const float *splats, int64_t n, const uint32_t *sorted_gids,
+GS_API gs_status gs_rasterize(const float *splats, int64_t n, const uint32_t *sorted_gids,
                        const uint32_t *ranges, const gs_camera *cam, const float *bg,
                        const gs_raster_cfg *cfg, float *image, float *final_T,
                        uint32_t *n_contrib, uint32_t *n_evaluated, void *stream);
@@ -245,7 +249,7 @@ gs_status gs_rasterize(const float *splats, int64_t n, const uint32_t *sorted_gi
  *       pixel, not the stopping one);
  *   [3] list entries loaded (read and bounded before the tile finished).
  * Same argument rules as gs_rasterize. */
-gs_status gs_raster_work(const float *splats, int64_t n, const uint32_t *sorted_gids,
+GS_API gs_status gs_raster_work(const float *splats, int64_t n, const uint32_t *sorted_gids,
                          const uint32_t *ranges, const gs_camera *cam, uint64_t *work,
                          void *stream);
 
@@ -262,7 +266,7 @@ gs_status gs_raster_work(const float *splats, int64_t n, const uint32_t *sorted_
  * Both are raised with atomic max and never cleared: the caller zeroes them
  * once and calls once per calibration view.  A bin left at 0 saw no blended
  * Gaussian (take 1.0, the trivial bound, for it).  lut_depth_max > 0. */
-gs_status gs_calibrate_t_upper(const float *splats, int64_t n, const uint32_t *sorted_gids,
+GS_API gs_status gs_calibrate_t_upper(const float *splats, int64_t n, const uint32_t *sorted_gids,
                                const uint32_t *ranges, const gs_camera *cam, float lut_depth_max,
                                uint32_t *t_upper_bits, uint32_t *max_t_bits, void *stream);
 
@@ -281,7 +285,7 @@ gs_status gs_calibrate_t_upper(const float *splats, int64_t n, const uint32_t *s
  * uint64[2]) is added to: [0] skipped blends, [1] kept blends (the caller
  * zeroes it).  theta must be finite and >= 0, kind 0..2 (else
  * GS_ERR_INVALID_ARGUMENT). */
-gs_status gs_rasterize_skip(const float *splats, int64_t n, const uint32_t *sorted_gids,
+GS_API gs_status gs_rasterize_skip(const float *splats, int64_t n, const uint32_t *sorted_gids,
                             const uint32_t *ranges, const gs_camera *cam, const float *bg,
                             int kind, float theta, const float *weight, const float *t_upper,
                             float lut_depth_max, float *image, float *final_T, uint32_t *n_contrib,
@@ -295,7 +299,7 @@ gs_status gs_rasterize_skip(const float *splats, int64_t n, const uint32_t *sort
  * mean (float32).  sums (device float[nbins]) and counts (device
  * uint64[nbins]) are added to (the caller zeroes them).  1 <= nbins <= 64,
  * bin_width > 0 (else GS_ERR_INVALID_ARGUMENT). */
-gs_status gs_contribution_profile(const float *splats, int64_t n, const uint32_t *sorted_gids,
+GS_API gs_status gs_contribution_profile(const float *splats, int64_t n, const uint32_t *sorted_gids,
                                   const uint32_t *ranges, const gs_camera *cam, int nbins,
                                   float bin_width, float *sums, unsigned long long *counts,
                                   void *stream);
@@ -307,7 +311,7 @@ gs_status gs_contribution_profile(const float *splats, int64_t n, const uint32_t
  * splat record's offsets, d mean x, d mean y, d A, d beta, d gamma,
  * d opacity, d red, d green, d blue (other slots 0).  grad_splats is
  * overwritten. */
-gs_status gs_rasterize_backward(const float *splats, int64_t n, const uint32_t *sorted_gids,
+GS_API gs_status gs_rasterize_backward(const float *splats, int64_t n, const uint32_t *sorted_gids,
                                 const uint32_t *ranges, const gs_camera *cam, const float *bg,
                                 const float *final_T, const uint32_t *n_contrib,
                                 const float *dL_dimage, float *grad_splats, void *stream);
@@ -317,7 +321,7 @@ gs_status gs_rasterize_backward(const float *splats, int64_t n, const uint32_t *
  * quaternion normalisation, the scale exponential, the opacity sigmoid and
  * the SH colour (clamped channels pass no gradient).  The tile extent (and
  * with it Th and s) passes no gradient. */
-gs_status gs_preprocess_backward(const gs_scene *scene, const gs_camera *cam,
+GS_API gs_status gs_preprocess_backward(const gs_scene *scene, const gs_camera *cam,
                                  const uint32_t *tiles_touched, const float *grad_splats,
                                  const gs_scene_grads *out, void *stream);
 
@@ -344,7 +348,7 @@ typedef struct {
 } gs_view_target;
 
 /* Workspace bytes for gs_rasterize_views over total_tiles (view, tile) items. */
-size_t gs_views_workspace_size(int n_views, int64_t total_tiles);
+GS_API size_t gs_views_workspace_size(int n_views, int64_t total_tiles);
 
 /* Rasterize n_views views (1..GS_MAX_VIEWS) in one persistent launch.
  * views: HOST array (validated, and used to size the work queue); d_views: the
@@ -355,18 +359,71 @@ size_t gs_views_workspace_size(int n_views, int64_t total_tiles);
  * launch, [1 + v] the clock when view v's last tile finished (the clock runs
  * at hipDeviceAttributeWallClockRate kHz).  Results are identical to calling
  * gs_rasterize once per view. */
-gs_status gs_rasterize_views(const gs_view_target *views, const gs_view_target *d_views,
+GS_API gs_status gs_rasterize_views(const gs_view_target *views, const gs_view_target *d_views,
                              int n_views, const float *bg, const gs_raster_cfg *cfg,
                              uint64_t *clock, void *ws, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * A whole batched frame in one call: for every view, the preprocess (Sec. 2.1
+ * preprocessing; AdaGScale Sec. 3.2-3.3) and the fused pair generation, sort
+ * and tile ranges of gs_bin_pairs, then the rasterization (eq. 1-2, dual size
+ * Sec. 3.3) of every view's tiles in ONE persistent launch over a longest-first
+ * (view, tile) queue, as gs_rasterize_views.  The views' preprocess and
+ * binning chains are independent, so they are spread over `lanes` streams
+ * the library owns (created on the first call on a device, default priority),
+ * forked from and joined back to `stream` with events; the whole call is
+ * graph-capturable (no allocation, no host synchronisation, no memset nodes).
+ * Make the first call on a device outside graph capture (it creates the
+ * streams and events).  Calls that overlap on one device share those streams
+ * and must be serialised by the caller.
+ * ------------------------------------------------------------------------- */
+
+/* One view of a batched frame (host struct; every pointer is device memory,
+ * caller-owned, laid out as for gs_preprocess / gs_bin_pairs /
+ * gs_rasterize).  num_pairs (device int64) receives the view's REQUIRED pair
+ * count; when it exceeds pair_capacity the view's ranges are empty (its image
+ * is the background) and the caller grows that view's buffers and renders
+ * again.  ws: gs_workspace_size(scene n, pair_capacity, W, H) bytes. */
+typedef struct {
+    gs_camera cam;
+    float *splats;           /* [n][12] */
+    uint64_t *rects;         /* [n] */
+    uint32_t *tiles_touched; /* [n] */
+    uint32_t *sorted_gids;   /* [pair_capacity] */
+    uint32_t *ranges;        /* [tiles][2] */
+    int64_t pair_capacity;   /* 0 .. 2^32 - 1 */
+    int64_t *num_pairs;
+    void *ws;
+    size_t ws_bytes;
+    float *image;            /* [3][H][W] */
+    float *final_T;          /* [H][W] */
+    uint32_t *n_contrib;     /* [H][W] */
+} gs_view_frame;
+
+/* Workspace bytes of gs_render_views for n_views views of total_tiles
+ * (view, tile) items in all (the per-view binning workspaces are separate). */
+GS_API size_t gs_render_views_workspace_size(int n_views, int64_t total_tiles);
+
+/* Render n_views (1..GS_MAX_VIEWS) views of one scene with one method switch
+ * (mode, as for gs_preprocess; its extent_rule also applies to the binning).
+ * views: HOST array of n_views gs_view_frame.  bg: host float[3].  cfg: raster
+ * geometry as for gs_rasterize.  lanes: 1..8 streams for the per-view chains
+ * (1 runs everything on `stream`).  clock: as for gs_rasterize_views
+ * (nullable).  ws: gs_render_views_workspace_size bytes.  Results equal
+ * gs_preprocess + gs_bin_pairs + gs_rasterize per view. */
+GS_API gs_status gs_render_views(const gs_scene *scene, const gs_mode *mode,
+                                 const gs_view_frame *views, int n_views, const float *bg,
+                                 const gs_raster_cfg *cfg, int lanes, uint64_t *clock, void *ws,
+                                 size_t ws_bytes, void *stream);
+
 /* Frequency of the device wall clock stamped by gs_rasterize_views, in kHz
  * (0 if the query fails). */
-int gs_wall_clock_khz(int device);
+GS_API int gs_wall_clock_khz(int device);
 
-const char *gs_status_string(gs_status s);
-const char *gs_last_error(void);
+GS_API const char *gs_status_string(gs_status s);
+GS_API const char *gs_last_error(void);
 /* Library version string, e.g. "gsr 0.1 gfx950". */
-const char *gs_version(void);
+GS_API const char *gs_version(void);
 
 #ifdef __cplusplus
 }

@@ -28,6 +28,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define TILE 16
 #define TAU (1.0 / 255.0)        /* alpha threshold, Sec. 2.1 */
@@ -365,9 +368,11 @@ int orc_ellipse_spans(double u, double v, double A, double beta, double gamma, d
 /* Inputs are float32 structure-of-arrays, [C][N]; cam[0..11] is the          */
 /* row-major [R|t] world-to-camera matrix, cam[12..15] = fx, fy, cx, cy.      */
 /* Outputs (double, [N][k]): mean2d[2], conic[3] (inverse 2D covariance      */
-/* entries A, B, C: d^T Sigma2^-1 d = A dx^2 + 2 B dx dy + C dy^2), quad[3]   */
-/* (the same form as a sum of squares, A (dx + beta dy)^2 + gamma dy^2, with  */
-/* A = c/det, beta = -b/c, gamma = 1/c), opacity, rgb[3], depth, cov2d[3]     */
+/* entries Cxx, Cxy, Cyy: d^T Sigma2^-1 d = Cxx dx^2 + 2 Cxy dx dy + Cyy dy^2, */
+/* what the blend of eq. (1) evaluates), quad[3] (the same form as a sum of   */
+/* squares, A (dx + beta dy)^2 + gamma dy^2 with A = c/det, beta = -b/c,      */
+/* gamma = 1/c: the parametrisation the ellipse and oriented-box tile tests   */
+/* take, and the splat record's storage form), opacity, rgb[3], depth, cov2d[3] */
 /* (dilated a, b, c), extent (plain v), th, scale, rect[4] (x0, y0, x1, y1    */
 /* half-open, tiles), tiles_touched, radius (int).                           */
 /* flags: 0 culled, 1 projected (finite, in front), 2 projected with tiles.   */
@@ -398,6 +403,9 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
     double campos[3];
     for (int j = 0; j < 3; ++j) campos[j] = -(W[0][j] * t[0] + W[1][j] * t[1] + W[2][j] * t[2]);
 
+    /* Gaussians are independent: the OpenMP build (timing only) splits them
+       over threads; each iteration writes only its own entries. */
+#pragma omp parallel for schedule(static)
     for (int64_t g = 0; g < n; ++g) {
         flags[g] = 0; tiles_touched[g] = 0; radius[g] = 0;
         for (int k = 0; k < 4; ++k) rect[4 * g + k] = 0;
@@ -415,8 +423,8 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
         double q[4] = {quats[g], quats[n + g], quats[2 * n + g], quats[3 * n + g]};
         double qn = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
         if (qn > 0.0) {
-            double ir = 1.0 / sqrt(qn);
-            for (int k = 0; k < 4; ++k) q[k] = q[k] * ir;
+            double qlen = sqrt(qn);
+            for (int k = 0; k < 4; ++k) q[k] = q[k] / qlen;
         } else {
             q[0] = 1.0; q[1] = q[2] = q[3] = 0.0;
         }
@@ -439,15 +447,15 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
            perspective map at the clamped point) */
         double limx = FRUSTUM_SLACK * ((0.5 * width) / fx);
         double limy = FRUSTUM_SLACK * ((0.5 * height) / fy);
-        double ipz = 1.0 / p[2];
-        double txz = p[0] * ipz, tyz = p[1] * ipz;
+        double txz = p[0] / p[2], tyz = p[1] / p[2];
         if (txz < -limx) txz = -limx;
         if (txz > limx) txz = limx;
         if (tyz < -limy) tyz = -limy;
         if (tyz > limy) tyz = limy;
         double xc = txz * p[2], yc = tyz * p[2];
-        double J[2][3] = {{fx * ipz, 0.0, -(fx * xc) * (ipz * ipz)},
-                          {0.0, fy * ipz, -(fy * yc) * (ipz * ipz)}};
+        double zz = p[2] * p[2];
+        double J[2][3] = {{fx / p[2], 0.0, -(fx * xc) / zz},
+                          {0.0, fy / p[2], -(fy * yc) / zz}};
         double T[2][3], U[2][3], S2[2][2];
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 3; ++j) {
@@ -471,8 +479,8 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
 
         /* determinant, conic (eq. 1 uses the inverse of G_cov), mean, depth */
         double det = a * c - b * b;
-        double u = fx * (p[0] * ipz) + cx;
-        double v = fy * (p[1] * ipz) + cy;
+        double u = fx * (p[0] / p[2]) + cx;
+        double v = fy * (p[1] / p[2]) + cy;
         if (!(is_finite(u) && is_finite(v) && is_finite(a) && is_finite(b) && is_finite(c))) continue;
         if (!(det > 0.0)) continue;
         double sigma = 1.0 / (1.0 + exp(-(double)opacity_logits[g]));
@@ -481,10 +489,9 @@ void orc_preprocess(int64_t n, const float *means, const float *log_scales, cons
         conic[3 * g] = c / det;
         conic[3 * g + 1] = -b / det;
         conic[3 * g + 2] = a / det;
-        double ic = 1.0 / c;
         quad[3 * g] = c / det;
-        quad[3 * g + 1] = -b * ic;
-        quad[3 * g + 2] = ic;
+        quad[3 * g + 1] = -b / c;
+        quad[3 * g + 2] = 1.0 / c;
         cov2d[3 * g] = a; cov2d[3 * g + 1] = b; cov2d[3 * g + 2] = c;
         opacity[g] = sigma;
         depth[g] = p[2];
@@ -615,18 +622,45 @@ void orc_ranges(int64_t np, const uint64_t *keys, int num_tiles, int64_t *ranges
 /* ------------------------------------------------------------------------ */
 /* Blending of one pixel, eq. (1)-(2), front to back.                        */
 /*                                                                           */
-/* rec[g*9 .. g*9+8] = mean x, mean y, A, beta, gamma, opacity, r, g, b (the  */
-/* float32 record values, here in double).  For each listed Gaussian, with   */
-/* dx = mean x - px, dy = mean y - py:                                       */
-/*   power = -(A (dx + beta dy)^2 + gamma dy^2)/2 = -d^T Sigma2^-1 d / 2;     */
-/*   skipped if power > 0 (never, as both terms are squares);                */
+/* rec[g*9 .. g*9+8] = mean x, mean y, the inverse 2D covariance (conic) as  */
+/* Cxx, Cxy, Cyy, opacity, r, g, b.  For each listed Gaussian, with          */
+/* dx = mean x - px, dy = mean y - py, eq. (1) as written:                   */
+/*   power = -(Cxx dx^2 + 2 Cxy dx dy + Cyy dy^2)/2 = -d^T Sigma2^-1 d / 2;   */
+/*   skipped if power > 0 (the original 3D-GS guard);                        */
 /*   alpha = min(0.99, opacity * exp(power)); skipped if alpha < tau;        */
 /*   if T (1 - alpha) < 1e-4 the pixel stops before adding this Gaussian;    */
 /*   otherwise colour += alpha T rgb and T *= 1 - alpha.                     */
-/* margin receives the smallest relative distance of any decision to its     */
-/* threshold (used to flag pixels whose float32 result may legitimately      */
-/* take the other branch).                                                    */
+/*                                                                           */
+/* Decision margins.  A float32 renderer may take the other branch of a     */
+/* decision when the double value lies within float32 rounding of its       */
+/* threshold.  Model of such a renderer: mean, inverse covariance, opacity   */
+/* and colour stored in float32 (unit roundoff U = 2^-24), the offset (dx,   */
+/* dy) formed in float32 and the quadratic form evaluated as a sum of        */
+/* non-negative terms (no cancellation).  To first order its alpha then has  */
+/* relative error at most                                                     */
+/*   e_alpha = U (32 + 6 q + 2 sqrt(q) G),  q = d^T Sigma2^-1 d,             */
+/*   G = sqrt(Cxx) |dx| + sqrt(Cyy) |dy|                                     */
+/* (the offset's rounding moves q by 2 sqrt(q) G U at most; stored values,   */
+/* products and the exponential by a few U each), and the relative error of */
+/* T after blends j = 1..k is at most sum_j (alpha_j e_alpha,j + U) /        */
+/* (1 - alpha_j) (each factor 1 - alpha_j and each product).  A pixel's       */
+/* margin is the smallest ratio, over its decisions, of the relative        */
+/* distance to the threshold (|alpha - tau| / tau, |T' - 1e-4| / 1e-4,       */
+/* |c - theta| / theta) to that bound; a margin below 1 means a float32      */
+/* renderer may legitimately decide differently.                             */
 /* ------------------------------------------------------------------------ */
+#define U32 5.9604644775390625e-08 /* 2^-24, the float32 unit roundoff */
+
+static double quad_form(const double *g, double dx, double dy) {
+    return g[2] * dx * dx + 2.0 * g[3] * dx * dy + g[4] * dy * dy;
+}
+
+static double alpha_err(const double *g, double dx, double dy, double q) {
+    double G = sqrt(g[2]) * fabs(dx) + sqrt(g[4]) * fabs(dy);
+    double sq = q > 0.0 ? sqrt(q) : 0.0;
+    return U32 * (32.0 + 6.0 * q + 2.0 * sq * G);
+}
+
 typedef struct {
     double color[3];
     double T;
@@ -672,31 +706,70 @@ typedef struct {
     int64_t *counts;
 } profile_t;
 
+/* First-order bound on the image error of a float32 renderer of the model
+ * above (orc_blend's `bound` output).  Per channel, the alpha errors move
+ * the colour by sum_k |dC/dalpha_k| alpha_k e_alpha,k with
+ *   dC/dalpha_k = T_k c_k - B_k / (1 - alpha_k),
+ *   B_k = sum_{j>k} alpha_j T_j c_j + T_final bg   (the colour behind k),
+ * the rounding of each product T (1 - alpha) by B_{k} U / (1 - alpha_k), and
+ * the colour sum's own roundings by U (blends + 2) (sum_k alpha_k T_k |c_k| +
+ * T_final |bg|).  Scratch arrays hold the blended entries of the pixel. */
+typedef struct {
+    const double *bg;
+    double *al, *Tk, *ea;
+    int64_t *gid;
+    double out[3];
+} bound_t;
+
+static void pixel_bound(const double *rec, int64_t nb, double T, bound_t *b) {
+    double behind[3], absum[3];
+    for (int ch = 0; ch < 3; ++ch) {
+        behind[ch] = T * b->bg[ch];
+        absum[ch] = T * fabs(b->bg[ch]);
+        b->out[ch] = 0.0;
+    }
+    for (int64_t k = nb - 1; k >= 0; --k) {
+        const double *g = rec + 9 * b->gid[k];
+        double a = b->al[k], Ti = b->Tk[k];
+        for (int ch = 0; ch < 3; ++ch) {
+            double dCda = Ti * g[6 + ch] - behind[ch] / (1.0 - a);
+            b->out[ch] += fabs(dCda) * a * b->ea[k] + fabs(behind[ch]) * U32 / (1.0 - a);
+            behind[ch] += a * Ti * g[6 + ch];
+            absum[ch] += a * Ti * fabs(g[6 + ch]);
+        }
+    }
+    for (int ch = 0; ch < 3; ++ch) b->out[ch] += U32 * (double)(nb + 2) * absum[ch];
+}
+
 /* max_t (nullable, [n]): per Gaussian, the largest transmittance in front of
  * it at a pixel where it is blended (the max(T^i) of Sec. 3.2).  sk
  * (nullable): the contribution-skip rule above; skipped blends count in
- * *skipped (nullable).  pf (nullable): the contribution profile. */
+ * *skipped (nullable).  pf (nullable): the contribution profile.  bd
+ * (nullable): the error bound above. */
 static void blend_pixel_prof(double px, double py, const uint32_t *list, int64_t len,
                              const double *rec, pix_t *o, double *max_t, const skip_t *sk,
-                             int64_t *skipped, const profile_t *pf) {
+                             int64_t *skipped, const profile_t *pf, bound_t *bd) {
     double T = 1.0, C[3] = {0.0, 0.0, 0.0}, margin = INFINITY;
+    double eT = 0.0; /* relative error bound of T so far */
     int64_t last = 0, blended = 0, ev = 0;
     uint64_t sig = 1469598103934665603ull;
     for (int64_t j = 0; j < len; ++j) {
         const double *g = rec + 9 * (int64_t)list[j];
         ++ev;
         double dx = g[0] - px, dy = g[1] - py;
-        double uu = dx + g[3] * dy;
-        double power = -0.5 * (g[2] * uu * uu + g[4] * dy * dy);
+        double q = quad_form(g, dx, dy);
+        double power = -0.5 * q;
         if (power > 0.0) continue;
         double alpha = g[5] * exp(power);
         if (alpha > ALPHA_MAX) alpha = ALPHA_MAX;
-        double ma = fabs(alpha - TAU) / TAU;
+        double ea = alpha_err(g, dx, dy, q);
+        double ma = fabs(alpha - TAU) / TAU / ea;
         if (ma < margin) margin = ma;
         if (alpha < TAU) continue;
         if (sk && sk->theta > 0.0) {
             double c = alpha * skip_weight(sk, list[j], T);
-            double mc = fabs(c - sk->theta) / sk->theta;
+            double ec = ea + (sk->kind == 0 ? eT : 0.0) + U32;
+            double mc = fabs(c - sk->theta) / sk->theta / ec;
             if (mc < margin) margin = mc;
             if (c < sk->theta) {
                 if (skipped) ++*skipped;
@@ -704,36 +777,39 @@ static void blend_pixel_prof(double px, double py, const uint32_t *list, int64_t
             }
         }
         double Tn = T * (1.0 - alpha);
-        double mt = fabs(Tn - T_STOP) / T_STOP;
+        double eTn = eT + (alpha * ea + U32) / (1.0 - alpha) + U32;
+        double mt = fabs(Tn - T_STOP) / T_STOP / eTn;
         if (mt < margin) margin = mt;
         if (Tn < T_STOP) break;
         for (int ch = 0; ch < 3; ++ch) C[ch] += alpha * T * g[6 + ch];
         if (max_t && T > max_t[list[j]]) max_t[list[j]] = T;
         if (pf) {
-            double m = sqrt(g[2] * uu * uu + g[4] * dy * dy);
+            double m = sqrt(q);
             double fb = floor(m / pf->bin_width);
             int bin = fb >= (double)(pf->nbins - 1) ? pf->nbins - 1 : (int)fb;
             pf->sums[bin] += alpha * T;
             pf->counts[bin] += 1;
         }
+        if (bd) {
+            bd->al[blended] = alpha;
+            bd->Tk[blended] = T;
+            bd->ea[blended] = ea;
+            bd->gid[blended] = list[j];
+        }
         T = Tn;
+        eT = eTn - U32;
         last = j + 1;
         ++blended;
         sig = (sig ^ (uint64_t)j) * 1099511628211ull;
     }
     for (int ch = 0; ch < 3; ++ch) o->color[ch] = C[ch];
     o->T = T; o->last = last; o->blended = blended; o->evaluated = ev; o->margin = margin; o->sig = sig;
-}
-
-static void blend_pixel_skip(double px, double py, const uint32_t *list, int64_t len,
-                             const double *rec, pix_t *o, double *max_t, const skip_t *sk,
-                             int64_t *skipped) {
-    blend_pixel_prof(px, py, list, len, rec, o, max_t, sk, skipped, NULL);
+    if (bd) pixel_bound(rec, blended, T, bd);
 }
 
 static void blend_pixel(double px, double py, const uint32_t *list, int64_t len, const double *rec,
                         pix_t *o, double *max_t) {
-    blend_pixel_prof(px, py, list, len, rec, o, max_t, NULL, NULL, NULL);
+    blend_pixel_prof(px, py, list, len, rec, o, max_t, NULL, NULL, NULL, NULL);
 }
 
 static void store_pixel(const pix_t *o, int64_t idx, int64_t npix, const double *bg, double *image,
@@ -748,31 +824,60 @@ static void store_pixel(const pix_t *o, int64_t idx, int64_t npix, const double 
     if (blended) blended[idx] = o->blended;
 }
 
+static int64_t longest_list(const int64_t *ranges, int num_tiles) {
+    int64_t cap = 0;
+    for (int t = 0; t < num_tiles; ++t) {
+        int64_t len = ranges[2 * t + 1] - ranges[2 * t];
+        if (len > cap) cap = len;
+    }
+    return cap;
+}
+
 /* Tile-list rasterizer: pixel (px, py) lies in tile (px/16, py/16) and blends
  * that tile's sorted list.  tiles: optional subset of tile ids (n_sel >= 0);
  * n_sel < 0 blends every tile.  Outputs are [3][H][W] and [H][W]; margin,
- * evals, sig, blended (Gaussians blended per pixel) and max_t (per Gaussian,
+ * evals, sig, blended (Gaussians blended per pixel), max_t (per Gaussian,
  * raised to the transmittance in front of it where it blends; caller
- * initialises) may be NULL. */
+ * initialises) and bound ([3][H][W], the first-order float32 error bound
+ * above) may be NULL. */
 void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *sorted_vals,
                const double *rec, const double *bg, const int32_t *tiles, int64_t n_sel,
                double *image, double *final_T, int64_t *n_contrib, double *margin, int64_t *evals,
-               uint64_t *sig, int64_t *blended, double *max_t) {
+               uint64_t *sig, int64_t *blended, double *max_t, double *bound) {
     int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
     int64_t npix = (int64_t)width * height;
     int64_t count = n_sel >= 0 ? n_sel : (int64_t)TX * TY;
+    bound_t bd, *pbd = NULL;
+    if (bound) {
+        int64_t cap = longest_list(ranges, TX * TY) + 1;
+        bd.bg = bg;
+        bd.al = (double *)malloc(sizeof(double) * (size_t)cap);
+        bd.Tk = (double *)malloc(sizeof(double) * (size_t)cap);
+        bd.ea = (double *)malloc(sizeof(double) * (size_t)cap);
+        bd.gid = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+        pbd = &bd;
+    }
+    /* Pixels are independent: the OpenMP build (timing only) splits the
+       tiles over threads when nothing is shared between pixels (no max_t, no
+       bound scratch). */
+#pragma omp parallel for schedule(dynamic, 4) if (!max_t && !bound)
     for (int64_t s = 0; s < count; ++s) {
         int t = n_sel >= 0 ? tiles[s] : (int)s;
         int tx = t % TX, ty = t / TX;
         for (int py = ty * TILE; py < (ty + 1) * TILE && py < height; ++py)
             for (int px = tx * TILE; px < (tx + 1) * TILE && px < width; ++px) {
                 pix_t o;
-                blend_pixel((double)px, (double)py, sorted_vals + ranges[2 * t],
-                            ranges[2 * t + 1] - ranges[2 * t], rec, &o, max_t);
-                store_pixel(&o, (int64_t)py * width + px, npix, bg, image, final_T, n_contrib,
-                            margin, evals, sig, blended);
+                blend_pixel_prof((double)px, (double)py, sorted_vals + ranges[2 * t],
+                                 ranges[2 * t + 1] - ranges[2 * t], rec, &o, max_t, NULL, NULL,
+                                 NULL, pbd);
+                int64_t idx = (int64_t)py * width + px;
+                store_pixel(&o, idx, npix, bg, image, final_T, n_contrib, margin, evals, sig,
+                            blended);
+                if (bound)
+                    for (int ch = 0; ch < 3; ++ch) bound[ch * npix + idx] = bd.out[ch];
             }
     }
+    if (bound) { free(bd.al); free(bd.Tk); free(bd.ea); free(bd.gid); }
 }
 
 /* orc_blend with the contribution-skip rule (kind, theta, weight / depth and
@@ -794,8 +899,9 @@ void orc_blend_skip(int width, int height, const int64_t *ranges, const uint32_t
         for (int py = ty * TILE; py < (ty + 1) * TILE && py < height; ++py)
             for (int px = tx * TILE; px < (tx + 1) * TILE && px < width; ++px) {
                 pix_t o;
-                blend_pixel_skip((double)px, (double)py, sorted_vals + ranges[2 * t],
-                                 ranges[2 * t + 1] - ranges[2 * t], rec, &o, NULL, &sk, skipped);
+                blend_pixel_prof((double)px, (double)py, sorted_vals + ranges[2 * t],
+                                 ranges[2 * t + 1] - ranges[2 * t], rec, &o, NULL, &sk, skipped,
+                                 NULL, NULL);
                 store_pixel(&o, (int64_t)py * width + px, npix, bg, image, final_T, n_contrib,
                             margin, NULL, NULL, blended);
             }
@@ -816,7 +922,8 @@ void orc_contrib_profile(int width, int height, const int64_t *ranges, const uin
             for (int px = tx * TILE; px < (tx + 1) * TILE && px < width; ++px) {
                 pix_t o;
                 blend_pixel_prof((double)px, (double)py, sorted_vals + ranges[2 * t],
-                                 ranges[2 * t + 1] - ranges[2 * t], rec, &o, NULL, NULL, NULL, &pf);
+                                 ranges[2 * t + 1] - ranges[2 * t], rec, &o, NULL, NULL, NULL, &pf,
+                                 NULL);
             }
     }
 }
@@ -836,7 +943,6 @@ static int di_cmp(const void *a, const void *b) {
 void orc_blend_bruteforce(int mode, int64_t n, int width, int height, const int32_t *rect,
                           const int32_t *flags, const float *depth_f32, const double *rec,
                           const double *bg, double *image, double *final_T, int64_t *n_contrib) {
-    int TX = (width + TILE - 1) / TILE;
     int64_t npix = (int64_t)width * height;
     di_t *cand = (di_t *)malloc(sizeof(di_t) * (size_t)(n > 0 ? n : 1));
     uint32_t *list = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
@@ -859,7 +965,6 @@ void orc_blend_bruteforce(int mode, int64_t n, int width, int height, const int3
             blend_pixel((double)px, (double)py, list, m, rec, &o, NULL);
             store_pixel(&o, (int64_t)py * width + px, npix, bg, image, final_T, n_contrib, NULL,
                         NULL, NULL, NULL);
-            (void)TX;
         }
     free(cand);
     free(list);
@@ -872,8 +977,11 @@ void orc_blend_bruteforce(int mode, int64_t n, int width, int height, const int3
 /*   dC/dc_i     = alpha_i T_i                                               */
 /*   dC/dalpha_i = T_i c_i - (sum_{j>i} alpha_j T_j c_j + T_{n+1} bg)/(1-alpha_i) */
 /* alpha = min(0.99, sigma e^power): a clamped alpha has zero derivative;     */
-/* otherwise dalpha/dsigma = e^power and dalpha/dpower = alpha.              */
-/* Outputs accumulate into g2d[g*9 + (mx, my, A, beta, gamma, sigma, r, g, b)]. */
+/* otherwise dalpha/dsigma = e^power and dalpha/dpower = alpha, with          */
+/* power = -(Cxx dx^2 + 2 Cxy dx dy + Cyy dy^2)/2 and dx = mean x - px:       */
+/*   dpower/dCxx = -dx^2/2, dpower/dCxy = -dx dy, dpower/dCyy = -dy^2/2,     */
+/*   dpower/d(mean x) = -(Cxx dx + Cxy dy), dpower/d(mean y) = -(Cxy dx + Cyy dy). */
+/* Outputs accumulate into g2d[g*9 + (mx, my, Cxx, Cxy, Cyy, sigma, r, g, b)].  */
 /* tiles (n_sel >= 0): only those tiles' pixels are differentiated (the others  */
 /* are taken to have zero dL/dimage).                                          */
 /* ------------------------------------------------------------------------ */
@@ -882,11 +990,7 @@ void orc_blend_backward(int width, int height, const int64_t *ranges, const uint
                         const int32_t *tiles, int64_t n_sel) {
     int TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
     int64_t npix = (int64_t)width * height;
-    int64_t cap = 0;
-    for (int t = 0; t < TX * TY; ++t) {
-        int64_t len = ranges[2 * t + 1] - ranges[2 * t];
-        if (len > cap) cap = len;
-    }
+    int64_t cap = longest_list(ranges, TX * TY);
     int64_t count = n_sel >= 0 ? n_sel : (int64_t)TX * TY;
     int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cap + 1));
     double *al = (double *)malloc(sizeof(double) * (size_t)(cap + 1));
@@ -906,8 +1010,7 @@ void orc_blend_backward(int width, int height, const int64_t *ranges, const uint
                 for (int64_t j = 0; j < len; ++j) {
                     const double *g = rec + 9 * (int64_t)list[j];
                     double dx = g[0] - px, dy = g[1] - py;
-                    double uu = dx + g[3] * dy;
-                    double power = -0.5 * (g[2] * uu * uu + g[4] * dy * dy);
+                    double power = -0.5 * quad_form(g, dx, dy);
                     if (power > 0.0) continue;
                     double e = exp(power);
                     double alpha = g[5] * e;
@@ -937,15 +1040,14 @@ void orc_blend_backward(int width, int height, const int64_t *ranges, const uint
                     }
                     for (int ch = 0; ch < 3; ++ch) behind[ch] += a * Ti * g[6 + ch];
                     if (cl[k]) continue;
-                    double dx = g[0] - px, dy = g[1] - py, uu = dx + g[3] * dy;
+                    double dx = g[0] - px, dy = g[1] - py;
                     o[5] += dLda * ex[k];
                     double dLdp = dLda * a;
-                    /* power = -(A u^2 + gamma dy^2)/2, u = dx + beta dy */
-                    o[2] += dLdp * (-0.5 * uu * uu);
-                    o[3] += dLdp * (-g[2] * uu * dy);
+                    o[2] += dLdp * (-0.5 * dx * dx);
+                    o[3] += dLdp * (-dx * dy);
                     o[4] += dLdp * (-0.5 * dy * dy);
-                    o[0] += dLdp * (-g[2] * uu);
-                    o[1] += dLdp * (-(g[2] * uu * g[3] + g[4] * dy));
+                    o[0] += dLdp * (-(g[2] * dx + g[3] * dy));
+                    o[1] += dLdp * (-(g[3] * dx + g[4] * dy));
                 }
             }
     }
@@ -953,9 +1055,10 @@ void orc_blend_backward(int width, int height, const int64_t *ranges, const uint
 }
 
 /* ------------------------------------------------------------------------ */
-/* Adjoint of the preprocess (per Gaussian), from g2d to the scene           */
-/* parameters.  Frozen: the tile extent (no gradient through Th, s or the    */
-/* rectangle), the EWA clamp branch and the colour clamp at 0.               */
+/* Adjoint of the preprocess (per Gaussian), from g2d (gradients of mean x, */
+/* mean y, Cxx, Cxy, Cyy, opacity, r, g, b) to the scene parameters.        */
+/* Frozen: the tile extent (no gradient through Th, s or the rectangle), the */
+/* EWA clamp branch and the colour clamp at 0.                               */
 /* Outputs are [C][N] like the inputs; d_sh is [(d+1)^2][3][N].               */
 /* ------------------------------------------------------------------------ */
 static void rot_partials(const double q[4], double dR[4][3][3]) {
@@ -1019,16 +1122,15 @@ void orc_preprocess_backward(int64_t n, const float *means, const float *log_sca
                 for (int k = 0; k < 3; ++k) S3[i][j] += M[i][k] * M[j][k];
             }
         double limx = FRUSTUM_SLACK * ((0.5 * width) / fx), limy = FRUSTUM_SLACK * ((0.5 * height) / fy);
-        double ipz = 1.0 / p[2];
-        double txz = p[0] * ipz, tyz = p[1] * ipz;
+        double txz = p[0] / p[2], tyz = p[1] / p[2];
         int clx = 0, cly = 0;
         if (txz < -limx) { txz = -limx; clx = -1; }
         if (txz > limx) { txz = limx; clx = 1; }
         if (tyz < -limy) { tyz = -limy; cly = -1; }
         if (tyz > limy) { tyz = limy; cly = 1; }
         double xc = txz * p[2], yc = tyz * p[2];
-        double J[2][3] = {{fx * ipz, 0.0, -(fx * xc) * (ipz * ipz)},
-                          {0.0, fy * ipz, -(fy * yc) * (ipz * ipz)}};
+        double J[2][3] = {{fx / p[2], 0.0, -(fx * xc) / (p[2] * p[2])},
+                          {0.0, fy / p[2], -(fy * yc) / (p[2] * p[2])}};
         double T[2][3];
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 3; ++j) {
@@ -1051,11 +1153,12 @@ void orc_preprocess_backward(int64_t n, const float *means, const float *log_sca
         dp[1] += G[1] * fy / p[2];
         dp[2] += -G[0] * fx * p[0] / (p[2] * p[2]) - G[1] * fy * p[1] / (p[2] * p[2]);
 
-        /* A = c/det, beta = -b/c, gamma = 1/c  ->  dL/d(a, b, c) */
-        double gA = G[2], gbeta = G[3], ggam = G[4];
-        double ga = gA * (-c * c / d2);
-        double gb = gA * (2.0 * b * c / d2) + gbeta * (-1.0 / c);
-        double gc = gA * (-b * b / d2) + gbeta * (b / (c * c)) + ggam * (-1.0 / (c * c));
+        /* conic = (Cxx, Cxy, Cyy) = (c, -b, a) / det, det = a c - b^2  ->  dL/d(a, b, c) */
+        double gxx = G[2], gxy = G[3], gyy = G[4];
+        double ga = gxx * (-c * c / d2) + gxy * (b * c / d2) + gyy * (-b * b / d2);
+        double gb = gxx * (2.0 * b * c / d2) + gxy * (-(det + 2.0 * b * b) / d2) +
+                    gyy * (2.0 * a * b / d2);
+        double gc = gxx * (-b * b / d2) + gxy * (a * b / d2) + gyy * (-a * a / d2);
         /* symmetric matrix gradient of Sigma2 (b occupies both off-diagonals) */
         double G2[2][2] = {{ga, 0.5 * gb}, {0.5 * gb, gc}};
         /* dL/dSigma3 = T^T G2 T ; dL/dT = 2 G2 T Sigma3 */
@@ -1171,6 +1274,16 @@ void orc_t_upper_accumulate(int64_t n, const float *depth, const double *max_t, 
         const int bin = f >= LUT_BINS - 1 ? LUT_BINS - 1 : (int)floor(f);
         if (max_t[i] > lut[bin]) lut[bin] = max_t[i];
     }
+}
+
+/* Threads the blend and preprocess loops run on: 1 in the plain build, the
+   OpenMP team size in the OpenMP build used for timing. */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 void orc_constants(double *out) {

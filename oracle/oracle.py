@@ -25,6 +25,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "gs_oracle.c")
 LIB = os.path.join(HERE, "libgs_oracle.so")
+# The same source built with OpenMP: the per-Gaussian preprocess loop and the
+# per-tile blend loop run on all the host's threads.  Used only to time the
+# oracle as a CPU baseline; parity runs use the single-threaded build.
+LIB_OMP = os.path.join(HERE, "libgs_oracle_omp.so")
 
 TAU = 1.0 / 255.0
 T_STOP = 1e-4
@@ -32,22 +36,45 @@ TILE = 16
 LUT_BINS = 20
 
 
+def _compile(out, openmp):
+    cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", SRC, "-o", out, "-lm"]
+    if openmp:
+        cmd.insert(1, "-fopenmp")
+    subprocess.check_call(cmd)
+
+
 def build(force: bool = True) -> str:
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-ffp-contract=off",
-                               "-fno-fast-math", "-fPIC", "-shared", SRC, "-o", LIB, "-lm"])
+    for out, omp in ((LIB, False), (LIB_OMP, True)):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+            _compile(out, omp)
     return LIB
 
 
 _lib = None
+_openmp = False
+
+
+def use_openmp(on: bool = True):
+    """Switch the wrappers to the OpenMP build (timing) or back to the
+    single-threaded one (parity, the default)."""
+    global _lib, _openmp
+    if bool(on) != _openmp:
+        _openmp = bool(on)
+        _lib = None
+
+
+def threads() -> int:
+    return int(lib().orc_threads())
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build()
-        L = C.CDLL(LIB)
+        path = LIB_OMP if _openmp else LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
+            _compile(path, _openmp)
+        L = C.CDLL(path)
         P = C.c_void_p
         L.orc_sh_basis.argtypes = [C.c_int, P, P, P]
         L.orc_plain_extent.argtypes = [C.c_double] * 3
@@ -66,7 +93,8 @@ def lib():
         L.orc_emit.restype = C.c_int64
         L.orc_sort.argtypes = [C.c_int64, P, P]
         L.orc_ranges.argtypes = [C.c_int64, P, C.c_int, P]
-        L.orc_blend.argtypes = [C.c_int, C.c_int, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P]
+        L.orc_blend.argtypes = [C.c_int, C.c_int, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P,
+                                P]
         L.orc_t_upper_accumulate.argtypes = [C.c_int64, P, P, C.c_double, P]
         L.orc_contrib_profile.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int, C.c_double, P, P]
         L.orc_blend_skip.argtypes = ([C.c_int, C.c_int, P, P, P, P, P, C.c_int64, C.c_int,
@@ -75,6 +103,7 @@ def lib():
                                            P, P]
         L.orc_blend_backward.argtypes = [C.c_int, C.c_int, P, P, P, P, P, P, P, C.c_int64]
         L.orc_constants.argtypes = [P]
+        L.orc_threads.restype = C.c_int
         L.orc_preprocess_backward.argtypes = [C.c_int64, P, P, P, P, P, C.c_int, P, C.c_int,
                                               C.c_int, P, P, P, P, P, P, P]
         _lib = L
@@ -133,15 +162,39 @@ class Preproc:
     flags: np.ndarray
     extent_rule: int = 0
 
-    def record(self, round_to_f32: bool = True) -> np.ndarray:
-        """Per-Gaussian record used by the blend: mean x, mean y, A, beta, gamma
-        (the inverse covariance as A (dx + beta dy)^2 + gamma dy^2), opacity, r, g, b.  The renderer stores it in float32, so by default the
-        values are rounded to float32 (and widened back to double); gradient
-        checks keep the unrounded double values."""
-        rec = np.concatenate([self.mean2d, self.quad, self.opacity[:, None], self.rgb], axis=1)
-        if round_to_f32:
-            rec = rec.astype(np.float32)
-        return np.ascontiguousarray(rec.astype(np.float64))
+    def record(self, kind: str = "stored") -> np.ndarray:
+        """Per-Gaussian record the blend reads, [n][9]: mean x, mean y, the
+        conic of eq. (1) (Cxx, Cxy, Cyy: d^T Sigma2^-1 d = Cxx dx^2 + 2 Cxy dx dy
+        + Cyy dy^2), opacity, r, g, b, in double.
+
+        kind "stored": the values of the renderer's float32 splat record.  The
+          mean, opacity and colour are rounded to float32, and so are the
+          record's sum-of-squares fields A = Cxx, beta = Cxy / Cxx,
+          gamma = Cyy - Cxy^2 / Cxx; the conic is then formed from those
+          float32 values in double (Cxx = A, Cxy = A beta, Cyy = A beta^2 +
+          gamma).
+        kind "exact": nothing rounded but the mean, which the interface keeps
+          as float32 pixel coordinates; the conic and every other value are
+          the double-precision preprocess outputs (the inverse of the
+          projected covariance, eq. 1).
+        kind "double": nothing rounded (gradient checks)."""
+        if kind == "stored":
+            q = self.quad.astype(np.float32).astype(np.float64)
+            A, beta, gamma = q[:, 0], q[:, 1], q[:, 2]
+            conic = np.stack([A, A * beta, (A * beta) * beta + gamma], axis=1)
+            mean = self.mean2d.astype(np.float32).astype(np.float64)
+            att = np.concatenate([self.opacity[:, None], self.rgb], axis=1)
+            att = att.astype(np.float32).astype(np.float64)
+        elif kind in ("exact", "double"):
+            conic = self.conic
+            mean = self.mean2d
+            if kind == "exact":
+                mean = mean.astype(np.float32).astype(np.float64)
+            att = np.concatenate([self.opacity[:, None], self.rgb], axis=1)
+        else:
+            raise ValueError(f"record kind {kind!r}")
+        rec = np.concatenate([mean, conic, att], axis=1)
+        return np.ascontiguousarray(rec, np.float64)
 
     @property
     def depth_f32(self):
@@ -245,10 +298,14 @@ class Frame:
     sig: np.ndarray = None
 
 
-def blend(frame_or_parts, cam, bg=(0.0, 0.0, 0.0), tiles=None, rec=None):
+def blend(frame_or_parts, cam, bg=(0.0, 0.0, 0.0), tiles=None, rec=None, bound=False):
     """Blend every tile (or the tile ids in ``tiles``).  Returns image [3][H][W],
-    final_T [H][W], n_contrib [H][W], per-pixel decision margin, evaluation
-    counts and blend signatures; pixels outside the selected tiles are 0."""
+    final_T [H][W], n_contrib [H][W], per-pixel decision margin (distance to
+    the nearest threshold in units of a float32 renderer's first-order error
+    bound; below 1 the float32 decision may differ), evaluation counts and
+    blend signatures; pixels outside the selected tiles are 0.  With
+    ``bound``, also the per-pixel first-order float32 error bound of the
+    image, [3][H][W], appended to the tuple."""
     f = frame_or_parts
     W, H = cam["width"], cam["height"]
     if rec is None:
@@ -267,8 +324,11 @@ def blend(frame_or_parts, cam, bg=(0.0, 0.0, 0.0), tiles=None, rec=None):
     else:
         sel = np.ascontiguousarray(tiles, np.int32)
         nsel = sel.size
+    bd = np.zeros((3, H, W)) if bound else None
     lib().orc_blend(W, H, _p(rg), _p(sv), _p(rec), _p(bgv), _p(sel), nsel, _p(img), _p(T),
-                    _p(nc), _p(mg), _p(ev), _p(sg), None, None)
+                    _p(nc), _p(mg), _p(ev), _p(sg), None, None, _p(bd))
+    if bound:
+        return img, T, nc, mg, ev, sg, bd
     return img, T, nc, mg, ev, sg
 
 
@@ -290,7 +350,7 @@ def blend_counts(frame: "Frame", cam, tiles=None, rec=None):
     sel = None if tiles is None else np.ascontiguousarray(tiles, np.int32)
     nsel = -1 if sel is None else sel.size
     lib().orc_blend(W, H, _p(rg), _p(sv), _p(rec), _p(bgv), _p(sel), nsel, _p(img), _p(T),
-                    _p(nc), _p(mg), _p(ev), None, _p(bl), None)
+                    _p(nc), _p(mg), _p(ev), None, _p(bl), None, None)
     return ev, bl, mg
 
 
@@ -352,7 +412,7 @@ def max_transmittance(frame: "Frame", cam, rec=None):
     rg = np.ascontiguousarray(frame.ranges, np.int64)
     sv = np.ascontiguousarray(frame.sorted_vals, np.uint32)
     lib().orc_blend(W, H, _p(rg), _p(sv), _p(np.ascontiguousarray(rec, np.float64)), _p(np.zeros(3)),
-                    None, -1, _p(img), _p(T), _p(nc), _p(mg), None, None, None, _p(mt))
+                    None, -1, _p(img), _p(T), _p(nc), _p(mg), None, None, None, _p(mt), None)
     return mt[:n], mg
 
 
@@ -398,9 +458,10 @@ def blend_bruteforce(pre: Preproc, cam, mode_id=1, bg=(0.0, 0.0, 0.0)):
 
 
 def blend_backward(frame: Frame, cam, dL_dimage, bg=(0.0, 0.0, 0.0), rec=None, tiles=None):
-    """Per-Gaussian gradients of the blend: [N][9] = d(mean x, mean y, A, beta,
-    gamma, opacity, r, g, b).  With ``tiles``, only those tiles' pixels are
-    differentiated (dL/dimage is taken as zero elsewhere)."""
+    """Per-Gaussian gradients of the blend: [N][9] = d(mean x, mean y, Cxx,
+    Cxy, Cyy, opacity, r, g, b), the record's entries (see Preproc.record).
+    With ``tiles``, only those tiles' pixels are differentiated (dL/dimage is
+    taken as zero elsewhere)."""
     n = frame.pre.rect.shape[0]
     if rec is None:
         rec = frame.pre.record()

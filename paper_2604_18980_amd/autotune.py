@@ -90,7 +90,7 @@ def tune_views(mv, reps=3, force=False):
     pairs = sum(int(fb.num_pairs.item()) for fb in mv.fbs)
 
     def run(cfg):
-        gsr.gs_rasterize_views(mv.views, mv.d_views, mv.n_views, mv.bg, cfg, mv.clock, mv.ws)
+        mv.rasterize(cfg)
 
     cfg, times = tune(run, [(c["width"], c["height"]) for c in mv.cams], pairs, mv.total_tiles,
                       reps, force)

@@ -5,7 +5,8 @@
 Each .hip file is compiled to an object in parallel, then linked into
 ``paper_2604_18980_amd/libgsr.so``.  Flags: -O3, no FP contraction (the
 preprocess' decision geometry must round exactly as written; hot loops use
-explicit fmaf), and packed FP32 instructions disabled.
+explicit fmaf), packed FP32 instructions disabled, and hidden symbol
+visibility (only the entry points that ``include/gsr.h`` marks are exported).
 """
 from __future__ import annotations
 
@@ -24,7 +25,8 @@ BUILD = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("GSR_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", f"--offload-arch={ARCH}",
+         "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument", f"-I{INCLUDE}", f"-I{CSRC}"]
 

@@ -47,16 +47,20 @@ def psnr(a: torch.Tensor, b: torch.Tensor) -> float:
 
 
 def search_k(scene: "R.DeviceScene", cams, target_psnr_db: float, t_upper=None,
-             lut_depth_max: float = 100.0, lo: float = 1e-3, hi: float = 1e3, iters: int = 14):
+             lut_depth_max: float = 100.0, lo: float = 1e-3, hi: float = 1e3, iters: int = 14,
+             extent_rule: int = 0):
     """Largest K (to float32) with mean PSNR(AdaGScale vs plain) over ``cams``
-    at or above the target; returns (K, mean PSNR at K)."""
+    at or above the target (Sec. 3.4's offline binary search on calibration
+    views); returns (K, mean PSNR at K).  The plain references use the tile
+    rectangle; the AdaGScale renders use ``extent_rule``."""
     refs, fb = [], None
     for cam in cams:  # plain references
         if fb is not None and (fb.width, fb.height) != (cam["width"], cam["height"]):
             fb = None
         fb = R.render(scene, cam, fb=fb, slack=1.05)
         refs.append(fb.image.clone())
-    mode = dict(adagscale=True, t_upper=t_upper, lut_depth_max=lut_depth_max)
+    mode = dict(adagscale=True, t_upper=t_upper, lut_depth_max=lut_depth_max,
+                extent_rule=extent_rule)
     # AdaGScale pairs never exceed plain ones: the last plain buffers serve
     # every view of the same size (grown if a larger view needs it)
 

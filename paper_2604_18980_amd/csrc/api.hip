@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 #include "gsr_internal.hpp"
@@ -105,6 +106,59 @@ gs_status check_scene(const gs_scene *sc) {
         return fail(GS_ERR_INVALID_ARGUMENT, "sh is not 16-byte aligned");
     return GS_OK;
 }
+
+gs_status check_mode(const gs_mode *mode) {
+    if (!mode) return fail(GS_ERR_INVALID_ARGUMENT, "mode is NULL");
+    if (mode->adagscale != 0 && mode->adagscale != 1)
+        return fail(GS_ERR_INVALID_ARGUMENT, "mode.adagscale must be 0 or 1");
+    if (mode->adagscale) {
+        if (!(mode->K >= 0.0f) || !finite_f(mode->K))
+            return fail(GS_ERR_INVALID_ARGUMENT, "mode.K must be finite and >= 0");
+        if (!(mode->lut_depth_max > 0.0f) || !finite_f(mode->lut_depth_max))
+            return fail(GS_ERR_INVALID_ARGUMENT, "mode.lut_depth_max must be finite and > 0");
+        for (int i = 0; i < GS_LUT_BINS; ++i)
+            if (!(mode->t_upper[i] >= 0.0f && mode->t_upper[i] <= 1.0f))
+                return fail(GS_ERR_INVALID_ARGUMENT, "mode.t_upper[%d] outside [0, 1]", i);
+    }
+    if (mode->extent_rule < 0 || mode->extent_rule > 2)
+        return fail(GS_ERR_INVALID_ARGUMENT, "mode.extent_rule must be 0, 1 or 2");
+    return GS_OK;
+}
+
+// The scene and method parts of the preprocess arguments (validated).
+void fill_preprocess_args(const gs_scene *scene, const gs_mode *mode, gsr::PreprocessArgs *a) {
+    memset(a, 0, sizeof *a);
+    a->means = scene->means;
+    a->log_scales = scene->log_scales;
+    a->quats = scene->quats;
+    a->opacity_logits = scene->opacity_logits;
+    a->sh = scene->sh;
+    a->n = (int)scene->n;
+    a->sh_degree = scene->sh_degree;
+    a->adagscale = mode->adagscale;
+    a->force_unit_scale = mode->force_unit_scale ? 1 : 0;
+    a->extent_rule = mode->extent_rule;
+    a->K = mode->K;
+    a->lut_depth_max = mode->lut_depth_max;
+    for (int i = 0; i < GS_LUT_BINS; ++i) a->lut[i] = mode->t_upper[i];
+    sh_constants(a->shc);
+    for (int i = 0; i < 16; ++i) a->shcf[i] = (float)a->shc[i];
+}
+
+// The camera part (validated camera).
+void set_preprocess_camera(const gs_camera *cam, gsr::PreprocessArgs *a) {
+    camera_to_double(cam, a->R, a->t, a->campos);
+    a->fx = cam->fx;
+    a->fy = cam->fy;
+    a->cx = cam->cx;
+    a->cy = cam->cy;
+    a->limx = 1.3 * ((0.5 * cam->width) / a->fx);
+    a->limy = 1.3 * ((0.5 * cam->height) / a->fy);
+    a->width = cam->width;
+    a->height = cam->height;
+    a->tiles_x = tiles_x(cam);
+    a->tiles_y = tiles_y(cam);
+}
 }  // namespace
 
 __global__ void k_set_count(int64_t *p, int64_t v) { *p = v; }
@@ -176,7 +230,145 @@ bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws, int tx,
 }
 }  // namespace gsr
 
+
 using namespace gsr;
+
+namespace {
+struct ViewsWs {
+    uint32_t *key[3], *val[3], *hist, *next, *view_left;
+    uint64_t *parts;
+    int64_t nblocks;
+    size_t bytes;
+};
+void views_layout(int n_views, int64_t total, void *base, ViewsWs *w) {
+    size_t off = 0;
+    char *b = static_cast<char *>(base);
+    auto take = [&](size_t bytes) -> char * {
+        off = align256(off);
+        char *p = b ? b + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const size_t m = (size_t)(total > 0 ? total : 1);
+    for (int i = 0; i < 3; ++i) {
+        w->key[i] = (uint32_t *)take(4 * m);
+        w->val[i] = (uint32_t *)take(4 * m);
+    }
+    w->nblocks = (int64_t)((m + kSortChunk - 1) / kSortChunk);
+    w->hist = (uint32_t *)take(4 * 256 * (size_t)w->nblocks);
+    w->parts = (uint64_t *)take(8 * (size_t)((256 * w->nblocks + kScanChunk - 1) / kScanChunk + 1));
+    w->next = (uint32_t *)take(4);
+    w->view_left = (uint32_t *)take(4 * (size_t)(n_views > 0 ? n_views : 1));
+    w->bytes = align256(off) + 256;  // + room for the item count
+}
+
+// The views' raster targets, written into the workspace by one kernel whose
+// argument carries them (a captured graph replays the kernel with the values
+// baked in; no host-to-device copy).
+struct ViewTable {
+    gs_view_target v[GS_MAX_VIEWS];
+    int n_views;
+};
+constexpr size_t kViewTableBytes = (sizeof(gs_view_target) * GS_MAX_VIEWS + 255) & ~(size_t)255;
+static_assert(sizeof(ViewTable) <= 4000, "kernel argument limit");
+
+__global__ void k_view_table(const ViewTable t, gs_view_target *dst) {
+    const int v = threadIdx.x;
+    if (v < t.n_views) dst[v] = t.v[v];
+}
+
+hipError_t launch_view_table(const ViewTable &t, gs_view_target *dst, hipStream_t s) {
+    k_view_table<<<1, GS_MAX_VIEWS, 0, s>>>(t, dst);
+    return hipGetLastError();
+}
+
+// Streams and events of gs_render_views' per-view chains, one set per device,
+// created on first use and kept for the life of the process.
+constexpr int kMaxLanes = 8;
+constexpr int kMaxDevices = 64;
+struct LaneSet {
+    hipStream_t s[kMaxLanes];
+    hipEvent_t fork, join[kMaxLanes];
+};
+std::mutex g_lane_mutex;
+LaneSet *g_lanes[kMaxDevices];
+
+gs_status lane_set(LaneSet **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_check(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(GS_ERR_UNSUPPORTED, "device %d", dev);
+    std::lock_guard<std::mutex> lock(g_lane_mutex);
+    if (!g_lanes[dev]) {
+        LaneSet *ls = new LaneSet();
+        for (int l = 0; l < kMaxLanes && e == hipSuccess; ++l) {
+            e = hipStreamCreateWithFlags(&ls->s[l], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ls->join[l], hipEventDisableTiming);
+        }
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ls->fork, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_check(e, "gs_render_views lane streams");
+        g_lanes[dev] = ls;
+    }
+    *out = g_lanes[dev];
+    return GS_OK;
+}
+
+gs_status rasterize_views(const gs_view_target *views, const gs_view_target *d_views, int n_views,
+                          const float *bg, const gs_raster_cfg *cfg, uint64_t *clock, void *ws,
+                          size_t ws_bytes, hipStream_t s, const char *who) {
+    if (!views || !d_views || !bg) return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (n_views < 1 || n_views > GS_MAX_VIEWS)
+        return fail(GS_ERR_INVALID_ARGUMENT, "n_views %d outside 1..%d", n_views, GS_MAX_VIEWS);
+    ViewsPlan p;
+    memset(&p, 0, sizeof p);
+    p.n_views = n_views;
+    int64_t total = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const gs_view_target &t = views[v];
+        if (t.width < 1 || t.height < 1 || t.width > GS_MAX_IMAGE_SIDE || t.height > GS_MAX_IMAGE_SIDE)
+            return fail(GS_ERR_INVALID_ARGUMENT, "view %d: image size %dx%d", v, t.width, t.height);
+        if (!t.ranges || !t.image || !t.final_T || !t.n_contrib)
+            return fail(GS_ERR_INVALID_ARGUMENT, "view %d: NULL array", v);
+        p.tile_off[v] = (uint32_t)total;
+        p.tiles_x[v] = (uint32_t)((t.width + GS_TILE - 1) / GS_TILE);
+        total += (int64_t)p.tiles_x[v] * ((t.height + GS_TILE - 1) / GS_TILE);
+    }
+    if (total >= ((int64_t)1 << 26)) return fail(GS_ERR_INVALID_ARGUMENT, "more than 2^26 tiles");
+    p.tile_off[n_views] = (uint32_t)total;
+    gs_raster_cfg c = {64, 4, 64};
+    if (cfg && (cfg->threads_per_tile || cfg->pixels_per_thread || cfg->lds_batch)) {
+        c = *cfg;
+        if (!geometry_built(c))
+            return fail(GS_ERR_UNSUPPORTED, "raster geometry %d/%d/%d not built", c.threads_per_tile,
+                        c.pixels_per_thread, c.lds_batch);
+    }
+    ViewsWs w;
+    views_layout(n_views, total, ws, &w);
+    if (!ws || ws_bytes < w.bytes)
+        return fail(GS_ERR_CAPACITY, "workspace of %zu bytes, %zu needed", ws_bytes, w.bytes);
+    int64_t *count = (int64_t *)((char *)ws + w.bytes - 256);
+    hipError_t e = launch_views_plan(p, d_views, w.key[0], w.val[0], w.next, w.view_left, clock, s);
+    if (e == hipSuccess) {
+        // the item count is a host-known constant; the sort reads it from device memory
+        k_set_count<<<1, 1, 0, s>>>(count, total);
+        e = radix_sort_u32(w.key[0], w.val[0], w.key[1], w.val[1], w.key[2], w.val[2], count, total,
+                           24, w.hist, w.nblocks, w.parts, s);
+    }
+    if (e != hipSuccess) return hip_check(e, who);
+    ViewsArgs q;
+    q.views = d_views;
+    for (int i = 0; i < 3; ++i) q.bg[i] = bg[i];
+    q.items = w.val[1];
+    q.n_items = total;
+    q.next = w.next;
+    q.view_left = w.view_left;
+    q.clock = clock;
+    static thread_local int grid_cache[4] = {0, 0, 0, 0};
+    const int gi = c.threads_per_tile == 256 ? (c.lds_batch == 64 ? 1 : c.lds_batch == 128 ? 2 : 3) : 0;
+    if (!grid_cache[gi]) grid_cache[gi] = raster_views_grid(c);
+    return hip_check(launch_raster_views(q, c, grid_cache[gi], s), who);
+}
+}  // namespace
 
 extern "C" {
 
@@ -210,50 +402,12 @@ gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_mo
     gs_status st;
     if ((st = check_scene(scene)) != GS_OK) return st;
     if ((st = check_camera(cam)) != GS_OK) return st;
-    if (!mode) return fail(GS_ERR_INVALID_ARGUMENT, "mode is NULL");
-    if (mode->adagscale != 0 && mode->adagscale != 1)
-        return fail(GS_ERR_INVALID_ARGUMENT, "mode.adagscale must be 0 or 1");
-    if (mode->adagscale) {
-        if (!(mode->K >= 0.0f) || !finite_f(mode->K))
-            return fail(GS_ERR_INVALID_ARGUMENT, "mode.K must be finite and >= 0");
-        if (!(mode->lut_depth_max > 0.0f) || !finite_f(mode->lut_depth_max))
-            return fail(GS_ERR_INVALID_ARGUMENT, "mode.lut_depth_max must be finite and > 0");
-        for (int i = 0; i < GS_LUT_BINS; ++i)
-            if (!(mode->t_upper[i] >= 0.0f && mode->t_upper[i] <= 1.0f))
-                return fail(GS_ERR_INVALID_ARGUMENT, "mode.t_upper[%d] outside [0, 1]", i);
-    }
-    if (mode->extent_rule < 0 || mode->extent_rule > 2)
-        return fail(GS_ERR_INVALID_ARGUMENT, "mode.extent_rule must be 0, 1 or 2");
+    if ((st = check_mode(mode)) != GS_OK) return st;
     if (scene->n > 0 && (!splats || !rects || !tiles_touched))
         return fail(GS_ERR_INVALID_ARGUMENT, "output array is NULL");
     PreprocessArgs a;
-    memset(&a, 0, sizeof a);
-    a.means = scene->means;
-    a.log_scales = scene->log_scales;
-    a.quats = scene->quats;
-    a.opacity_logits = scene->opacity_logits;
-    a.sh = scene->sh;
-    a.n = (int)scene->n;
-    a.sh_degree = scene->sh_degree;
-    camera_to_double(cam, a.R, a.t, a.campos);
-    a.fx = cam->fx;
-    a.fy = cam->fy;
-    a.cx = cam->cx;
-    a.cy = cam->cy;
-    a.limx = 1.3 * ((0.5 * cam->width) / a.fx);
-    a.limy = 1.3 * ((0.5 * cam->height) / a.fy);
-    a.width = cam->width;
-    a.height = cam->height;
-    a.tiles_x = tiles_x(cam);
-    a.tiles_y = tiles_y(cam);
-    a.adagscale = mode->adagscale;
-    a.force_unit_scale = mode->force_unit_scale ? 1 : 0;
-    a.extent_rule = mode->extent_rule;
-    a.K = mode->K;
-    a.lut_depth_max = mode->lut_depth_max;
-    for (int i = 0; i < GS_LUT_BINS; ++i) a.lut[i] = mode->t_upper[i];
-    sh_constants(a.shc);
-    for (int i = 0; i < 16; ++i) a.shcf[i] = (float)a.shc[i];
+    fill_preprocess_args(scene, mode, &a);
+    set_preprocess_camera(cam, &a);
     a.splats = splats;
     a.rects = rects;
     a.tiles_touched = tiles_touched;
@@ -589,35 +743,6 @@ gs_status gs_preprocess_backward(const gs_scene *scene, const gs_camera *cam,
     return hip_check(launch_preprocess_backward(a, (hipStream_t)stream), "gs_preprocess_backward");
 }
 
-namespace {
-struct ViewsWs {
-    uint32_t *key[3], *val[3], *hist, *next, *view_left;
-    uint64_t *parts;
-    int64_t nblocks;
-    size_t bytes;
-};
-void views_layout(int n_views, int64_t total, void *base, ViewsWs *w) {
-    size_t off = 0;
-    char *b = static_cast<char *>(base);
-    auto take = [&](size_t bytes) -> char * {
-        off = align256(off);
-        char *p = b ? b + off : nullptr;
-        off += bytes;
-        return p;
-    };
-    const size_t m = (size_t)(total > 0 ? total : 1);
-    for (int i = 0; i < 3; ++i) {
-        w->key[i] = (uint32_t *)take(4 * m);
-        w->val[i] = (uint32_t *)take(4 * m);
-    }
-    w->nblocks = (int64_t)((m + kSortChunk - 1) / kSortChunk);
-    w->hist = (uint32_t *)take(4 * 256 * (size_t)w->nblocks);
-    w->parts = (uint64_t *)take(8 * (size_t)((256 * w->nblocks + kScanChunk - 1) / kScanChunk + 1));
-    w->next = (uint32_t *)take(4);
-    w->view_left = (uint32_t *)take(4 * (size_t)(n_views > 0 ? n_views : 1));
-    w->bytes = align256(off) + 256;  // + room for the item count
-}
-}  // namespace
 
 int gs_wall_clock_khz(int device) {
     int v = 0;
@@ -635,58 +760,107 @@ size_t gs_views_workspace_size(int n_views, int64_t total_tiles) {
 gs_status gs_rasterize_views(const gs_view_target *views, const gs_view_target *d_views,
                              int n_views, const float *bg, const gs_raster_cfg *cfg,
                              uint64_t *clock, void *ws, size_t ws_bytes, void *stream) {
-    if (!views || !d_views || !bg) return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    return rasterize_views(views, d_views, n_views, bg, cfg, clock, ws, ws_bytes,
+                           (hipStream_t)stream, "gs_rasterize_views");
+}
+
+size_t gs_render_views_workspace_size(int n_views, int64_t total_tiles) {
+    if (n_views < 0 || total_tiles < 0) return 0;
+    ViewsWs w;
+    views_layout(n_views, total_tiles, nullptr, &w);
+    return kViewTableBytes + w.bytes;
+}
+
+gs_status gs_render_views(const gs_scene *scene, const gs_mode *mode, const gs_view_frame *views,
+                          int n_views, const float *bg, const gs_raster_cfg *cfg, int lanes,
+                          uint64_t *clock, void *ws, size_t ws_bytes, void *stream) {
+    gs_status st;
+    if ((st = check_scene(scene)) != GS_OK) return st;
+    if ((st = check_mode(mode)) != GS_OK) return st;
+    if (!views || !bg) return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
     if (n_views < 1 || n_views > GS_MAX_VIEWS)
         return fail(GS_ERR_INVALID_ARGUMENT, "n_views %d outside 1..%d", n_views, GS_MAX_VIEWS);
-    ViewsPlan p;
-    memset(&p, 0, sizeof p);
-    p.n_views = n_views;
+    if (lanes < 1 || lanes > kMaxLanes)
+        return fail(GS_ERR_INVALID_ARGUMENT, "lanes %d outside 1..%d", lanes, kMaxLanes);
+    const int64_t n = scene->n;
+    ViewTable table;
+    memset(&table, 0, sizeof table);
+    table.n_views = n_views;
     int64_t total = 0;
     for (int v = 0; v < n_views; ++v) {
-        const gs_view_target &t = views[v];
-        if (t.width < 1 || t.height < 1 || t.width > GS_MAX_IMAGE_SIDE || t.height > GS_MAX_IMAGE_SIDE)
-            return fail(GS_ERR_INVALID_ARGUMENT, "view %d: image size %dx%d", v, t.width, t.height);
-        if (!t.ranges || !t.image || !t.final_T || !t.n_contrib)
-            return fail(GS_ERR_INVALID_ARGUMENT, "view %d: NULL array", v);
-        p.tile_off[v] = (uint32_t)total;
-        p.tiles_x[v] = (uint32_t)((t.width + GS_TILE - 1) / GS_TILE);
-        total += (int64_t)p.tiles_x[v] * ((t.height + GS_TILE - 1) / GS_TILE);
+        const gs_view_frame &f = views[v];
+        if ((st = check_camera(&f.cam)) != GS_OK)
+            return fail(st, "view %d: %s", v, g_last_error.c_str());
+        if (f.pair_capacity < 0 || f.pair_capacity > (int64_t)0xffffffffLL)
+            return fail(GS_ERR_INVALID_ARGUMENT, "view %d: pair_capacity outside [0, 2^32)", v);
+        if (!f.num_pairs || !f.ranges || !f.image || !f.final_T || !f.n_contrib)
+            return fail(GS_ERR_INVALID_ARGUMENT, "view %d: NULL output array", v);
+        if (n > 0 && (!f.splats || !f.rects || !f.tiles_touched))
+            return fail(GS_ERR_INVALID_ARGUMENT, "view %d: NULL per-Gaussian array", v);
+        if (f.pair_capacity > 0 && !f.sorted_gids)
+            return fail(GS_ERR_INVALID_ARGUMENT, "view %d: sorted_gids is NULL", v);
+        Workspace w;
+        workspace_layout(n, f.pair_capacity, f.ws, &w, tiles_x(&f.cam), tiles_y(&f.cam));
+        if (!f.ws || f.ws_bytes < w.bytes)
+            return fail(GS_ERR_CAPACITY, "view %d: workspace of %zu bytes, %zu needed", v,
+                        f.ws_bytes, w.bytes);
+        gs_view_target &t = table.v[v];
+        t.splats = f.splats;
+        t.sorted_gids = f.sorted_gids;
+        t.ranges = f.ranges;
+        t.image = f.image;
+        t.final_T = f.final_T;
+        t.n_contrib = f.n_contrib;
+        t.width = f.cam.width;
+        t.height = f.cam.height;
+        total += (int64_t)tiles_x(&f.cam) * tiles_y(&f.cam);
     }
-    if (total >= ((int64_t)1 << 26)) return fail(GS_ERR_INVALID_ARGUMENT, "more than 2^26 tiles");
-    p.tile_off[n_views] = (uint32_t)total;
-    gs_raster_cfg c = {64, 4, 64};
-    if (cfg && (cfg->threads_per_tile || cfg->pixels_per_thread || cfg->lds_batch)) {
-        c = *cfg;
-        if (!geometry_built(c))
-            return fail(GS_ERR_UNSUPPORTED, "raster geometry %d/%d/%d not built", c.threads_per_tile,
-                        c.pixels_per_thread, c.lds_batch);
+    const size_t need = gs_render_views_workspace_size(n_views, total);
+    if (!ws || ws_bytes < need)
+        return fail(GS_ERR_CAPACITY, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    hipStream_t main = (hipStream_t)stream;
+    LaneSet *ls = nullptr;
+    if (lanes > 1 && (st = lane_set(&ls)) != GS_OK) return st;
+    gs_view_target *d_table = static_cast<gs_view_target *>(ws);
+    hipError_t e = launch_view_table(table, d_table, main);
+    if (e != hipSuccess) return hip_check(e, "gs_render_views table");
+    // fork: every lane starts after the work already on `stream`
+    if (lanes > 1) {
+        if ((e = hipEventRecord(ls->fork, main)) != hipSuccess) return hip_check(e, "gs_render_views fork");
+        for (int l = 0; l < lanes; ++l)
+            if ((e = hipStreamWaitEvent(ls->s[l], ls->fork, 0)) != hipSuccess)
+                return hip_check(e, "gs_render_views fork");
     }
-    ViewsWs w;
-    views_layout(n_views, total, ws, &w);
-    if (!ws || ws_bytes < w.bytes)
-        return fail(GS_ERR_CAPACITY, "workspace of %zu bytes, %zu needed", ws_bytes, w.bytes);
-    hipStream_t s = (hipStream_t)stream;
-    int64_t *count = (int64_t *)((char *)ws + w.bytes - 256);
-    hipError_t e = launch_views_plan(p, d_views, w.key[0], w.val[0], w.next, w.view_left, clock, s);
-    if (e == hipSuccess) {
-        // the item count is a host-known constant; the sort reads it from device memory
-        k_set_count<<<1, 1, 0, s>>>(count, total);
-        e = radix_sort_u32(w.key[0], w.val[0], w.key[1], w.val[1], w.key[2], w.val[2], count, total,
-                           24, w.hist, w.nblocks, w.parts, s);
+    PreprocessArgs pa;
+    fill_preprocess_args(scene, mode, &pa);
+    hipError_t err = hipSuccess;
+    for (int v = 0; v < n_views && err == hipSuccess; ++v) {
+        const gs_view_frame &f = views[v];
+        hipStream_t s = lanes > 1 ? ls->s[v % lanes] : main;
+        set_preprocess_camera(&f.cam, &pa);
+        pa.splats = f.splats;
+        pa.rects = f.rects;
+        pa.tiles_touched = f.tiles_touched;
+        err = launch_preprocess(pa, s);
+        if (err != hipSuccess) break;
+        Workspace w;
+        workspace_layout(n, f.pair_capacity, f.ws, &w, tiles_x(&f.cam), tiles_y(&f.cam));
+        err = launch_bin(f.splats, f.rects, f.tiles_touched, (int)n, tiles_x(&f.cam),
+                         tiles_y(&f.cam), mode->extent_rule, f.sorted_gids, nullptr, f.ranges,
+                         f.pair_capacity, f.num_pairs, w, s);
     }
-    if (e != hipSuccess) return hip_check(e, "gs_rasterize_views plan");
-    ViewsArgs q;
-    q.views = d_views;
-    for (int i = 0; i < 3; ++i) q.bg[i] = bg[i];
-    q.items = w.val[1];
-    q.n_items = total;
-    q.next = w.next;
-    q.view_left = w.view_left;
-    q.clock = clock;
-    static thread_local int grid_cache[4] = {0, 0, 0, 0};
-    const int gi = c.threads_per_tile == 256 ? (c.lds_batch == 64 ? 1 : c.lds_batch == 128 ? 2 : 3) : 0;
-    if (!grid_cache[gi]) grid_cache[gi] = raster_views_grid(c);
-    return hip_check(launch_raster_views(q, c, grid_cache[gi], s), "gs_rasterize_views");
+    // join, whatever happened above, so a capture stays well formed
+    if (lanes > 1) {
+        for (int l = 0; l < lanes; ++l) {
+            hipError_t j = hipEventRecord(ls->join[l], ls->s[l]);
+            if (j == hipSuccess) j = hipStreamWaitEvent(main, ls->join[l], 0);
+            if (j != hipSuccess && err == hipSuccess) err = j;
+        }
+    }
+    if (err != hipSuccess) return hip_check(err, "gs_render_views");
+    return rasterize_views(table.v, d_table, n_views, bg, cfg, clock,
+                           static_cast<char *>(ws) + kViewTableBytes, ws_bytes - kViewTableBytes,
+                           main, "gs_render_views");
 }
 
 }  // extern "C"

@@ -301,14 +301,17 @@ __global__ __launch_bounds__(128) void k_preprocess_backward(const PreprocessBwd
             const float *G = a.grad_splats + (size_t)g * 12;
             const double gmx = G[0], gmy = G[1], gA = G[2], gbeta = G[3], ggam = G[4], gsig = G[5];
             const float grgb[3] = {G[8], G[9], G[10]};
-            const double mx = a.means[g], my = a.means[n + g], mz = a.means[2 * n + g];
+            const double mx = a.means[g], my = a.means[plane_at(1, n, g)],
+                         mz = a.means[plane_at(2, n, g)];
             const double *R = a.R;
             const double p0 = R[0] * mx + R[1] * my + R[2] * mz + a.t[0];
             const double p1 = R[3] * mx + R[4] * my + R[5] * mz + a.t[1];
             const double p2 = R[6] * mx + R[7] * my + R[8] * mz + a.t[2];
-            const double s[3] = {exp((double)a.log_scales[g]), exp((double)a.log_scales[n + g]),
-                                 exp((double)a.log_scales[2 * n + g])};
-            const double q0[4] = {a.quats[g], a.quats[n + g], a.quats[2 * n + g], a.quats[3 * n + g]};
+            const double s[3] = {exp((double)a.log_scales[g]),
+                                 exp((double)a.log_scales[plane_at(1, n, g)]),
+                                 exp((double)a.log_scales[plane_at(2, n, g)])};
+            const double q0[4] = {a.quats[g], a.quats[plane_at(1, n, g)],
+                                  a.quats[plane_at(2, n, g)], a.quats[plane_at(3, n, g)]};
             const double qn = q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3];
             const bool qdeg = !(qn > 0.0);
             const double iqr = qdeg ? 1.0 : 1.0 / sqrt(qn);
@@ -455,10 +458,10 @@ __global__ __launch_bounds__(128) void k_preprocess_backward(const PreprocessBwd
                            R[6 + e] * dp[2];
         }
         for (int e = 0; e < 3; ++e) {
-            a.d_means[(size_t)e * n + g] = (float)dmean[e];
-            a.d_log_scales[(size_t)e * n + g] = (float)dls[e];
+            a.d_means[plane_at(e, n, g)] = (float)dmean[e];
+            a.d_log_scales[plane_at(e, n, g)] = (float)dls[e];
         }
-        for (int e = 0; e < 4; ++e) a.d_quats[(size_t)e * n + g] = (float)dq[e];
+        for (int e = 0; e < 4; ++e) a.d_quats[plane_at(e, n, g)] = (float)dq[e];
         a.d_opacity_logits[g] = (float)dop;
     }
     __syncthreads();

@@ -251,6 +251,12 @@ struct PreprocessBwdArgs {
 };
 hipError_t launch_preprocess_backward(const PreprocessBwdArgs &a, hipStream_t s);
 
+// Offset of element g of plane k of a [C][n] structure-of-arrays parameter,
+// computed in 64 bits: k n + g passes 2^31 for n above about 7.2e8 (k = 3).
+__host__ __device__ __forceinline__ size_t plane_at(int k, int n, int g) {
+    return (size_t)k * (size_t)n + (size_t)g;
+}
+
 // ------------------------------------------------------------ device helpers
 // An empty asm that claims to modify x: the value must exist in a register at
 // this point, so the compiler neither sinks its computation nor recomputes it.

@@ -11,7 +11,7 @@
 //
 // The inverse covariance is stored as the sum of squares
 //     d^T Sigma2^-1 d = A (dx + beta dy)^2 + gamma dy^2,
-//     A = c / det, beta = -b (1 / c), gamma = 1 / c  (Sigma2 = [[a, b], [b, c]]),
+//     A = c / det, beta = -b / c, gamma = 1 / c  (Sigma2 = [[a, b], [b, c]]),
 // which is exact algebra (block LDL^T of Sigma2^-1) and has no cancellation:
 // the expanded A dx^2 + 2B dx dy + C dy^2 of a thin Gaussian evaluated far
 // from its centre loses most of its float32 digits.
@@ -78,9 +78,11 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
     // Every per-Gaussian parameter is loaded at once (one memory round trip);
     // the near cull below discards few Gaussians of a real view, so this
     // fetches almost nothing the cull would have saved.
-    const float fmx = a.means[g], fmy = a.means[n + g], fmz = a.means[2 * n + g];
-    float fl0 = a.log_scales[g], fl1 = a.log_scales[n + g], fl2 = a.log_scales[2 * n + g];
-    float fqw = a.quats[g], fqx = a.quats[n + g], fqy = a.quats[2 * n + g], fqz = a.quats[3 * n + g];
+    const float fmx = a.means[g], fmy = a.means[plane_at(1, n, g)], fmz = a.means[plane_at(2, n, g)];
+    float fl0 = a.log_scales[g], fl1 = a.log_scales[plane_at(1, n, g)],
+          fl2 = a.log_scales[plane_at(2, n, g)];
+    float fqw = a.quats[g], fqx = a.quats[plane_at(1, n, g)], fqy = a.quats[plane_at(2, n, g)],
+          fqz = a.quats[plane_at(3, n, g)];
     float fop = a.opacity_logits[g];
     // Pin the loads here: left alone, the compiler sinks them below the near
     // cull, which costs a second dependent trip to memory.
@@ -101,8 +103,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
         double qw = fqw, qx = fqx, qy = fqy, qz = fqz;
         const double qn = qw * qw + qx * qx + qy * qy + qz * qz;
         if (qn > 0.0) {
-            const double ir = 1.0 / sqrt(qn);
-            qw = qw * ir; qx = qx * ir; qy = qy * ir; qz = qz * ir;
+            const double ql = sqrt(qn);
+            qw = qw / ql; qx = qx / ql; qy = qy / ql; qz = qz / ql;
         } else {
             qw = 1.0; qx = 0.0; qy = 0.0; qz = 0.0;
         }
@@ -123,14 +125,17 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
         const double s12 = m10 * m20 + m11 * m21 + m12 * m22;
         const double s22 = m20 * m20 + m21 * m21 + m22 * m22;
 
-        // EWA: Jacobian of the perspective map at the clamped point, T = J W
-        const double ipz = 1.0 / pz;
-        double txz = px * ipz, tyz = py * ipz;
+        // EWA: Jacobian of the perspective map at the clamped point, T = J W.
+        // Divisions as the definitions are written (x / z, f / z, f x / z^2):
+        // multiplying by a rounded 1/z instead moves the float32 record of
+        // about one Gaussian in 10^5 by an ulp.
+        const double pxz = px / pz, pyz = py / pz, zz = pz * pz;
+        double txz = pxz, tyz = pyz;
         txz = txz < -a.limx ? -a.limx : (txz > a.limx ? a.limx : txz);
         tyz = tyz < -a.limy ? -a.limy : (tyz > a.limy ? a.limy : tyz);
         const double xc = txz * pz, yc = tyz * pz;
-        const double j00 = a.fx * ipz, j02 = -(a.fx * xc) * (ipz * ipz);
-        const double j11 = a.fy * ipz, j12 = -(a.fy * yc) * (ipz * ipz);
+        const double j00 = a.fx / pz, j02 = -(a.fx * xc) / zz;
+        const double j11 = a.fy / pz, j12 = -(a.fy * yc) / zz;
         const double t00 = j00 * a.R[0] + j02 * a.R[6];
         const double t01 = j00 * a.R[1] + j02 * a.R[7];
         const double t02 = j00 * a.R[2] + j02 * a.R[8];
@@ -149,8 +154,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
         const double cc = (u10 * t10 + u11 * t11 + u12 * t12) + kDilation;
 
         const double det = ca * cc - cb * cb;
-        const double u = a.fx * (px * ipz) + a.cx;
-        const double v = a.fy * (py * ipz) + a.cy;
+        const double u = a.fx * pxz + a.cx;
+        const double v = a.fy * pyz + a.cy;
         const bool finite = isfinite(u) && isfinite(v) && isfinite(ca) && isfinite(cb) && isfinite(cc);
         if (finite && det > 0.0) {
             const double sigma = 1.0 / (1.0 + exp(-(double)fop));
@@ -227,10 +232,9 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
                         acc += 0.5f;
                         rgb[ch] = acc < 0.0f ? 0.0f : acc;
                     }
-                    const double icc = 1.0 / cc;
                     store_splat(a.splats + (size_t)g * 12,
-                                make_float4((float)u, (float)v, (float)(cc / det), (float)(-cb * icc)),
-                                make_float4((float)icc, (float)sigma, (float)pz, (float)th),
+                                make_float4((float)u, (float)v, (float)(cc / det), (float)(-cb / cc)),
+                                make_float4((float)(1.0 / cc), (float)sigma, (float)pz, (float)th),
                                 make_float4(rgb[0], rgb[1], rgb[2], (float)sc));
                 }
             }

@@ -23,8 +23,8 @@ EXPORTS = ("gs_workspace_size", "gs_preprocess", "gs_emit_pairs", "gs_sort", "gs
            "gs_rasterize", "gs_raster_work", "gs_calibrate_t_upper", "gs_rasterize_skip",
            "gs_contribution_profile",
            "gs_rasterize_backward", "gs_preprocess_backward", "gs_views_workspace_size",
-           "gs_rasterize_views", "gs_wall_clock_khz", "gs_status_string", "gs_last_error",
-           "gs_version")
+           "gs_rasterize_views", "gs_render_views_workspace_size", "gs_render_views",
+           "gs_wall_clock_khz", "gs_status_string", "gs_last_error", "gs_version")
 
 
 class GsrError(RuntimeError):
@@ -86,6 +86,8 @@ def load():
     L.gs_contribution_profile.argtypes = [P, I64, P, P, P, I, C.c_float, P, P, P]
     L.gs_rasterize_backward.argtypes = [P, I64, P, P, P, P, P, P, P, P, P]
     L.gs_preprocess_backward.argtypes = [P, P, P, P, P, P]
+    L.gs_render_views.argtypes = [P, P, P, I, P, P, I, P, P, C.c_size_t, P]
+    L.gs_render_views.restype = C.c_int
     for f in ("gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_bin_pairs", "gs_rasterize",
               "gs_raster_work", "gs_calibrate_t_upper", "gs_rasterize_skip", "gs_contribution_profile",
               "gs_rasterize_backward", "gs_preprocess_backward"):
@@ -271,6 +273,36 @@ def gs_rasterize_views(views_host, d_views, n_views, bg, cfg, clock, ws, stream=
     _check(L.gs_rasterize_views(C.cast(views_host, C.c_void_p), _ptr(d_views), int(n_views), bgv,
                                 C.byref(cfg) if cfg is not None else None, _ptr(clock), _ptr(ws),
                                 int(ws.numel() * ws.element_size()), _stream(stream)))
+
+
+class GsViewFrame(C.Structure):
+    _fields_ = [("cam", GsCamera), ("splats", C.c_void_p), ("rects", C.c_void_p),
+                ("tiles_touched", C.c_void_p), ("sorted_gids", C.c_void_p),
+                ("ranges", C.c_void_p), ("pair_capacity", C.c_int64), ("num_pairs", C.c_void_p),
+                ("ws", C.c_void_p), ("ws_bytes", C.c_size_t), ("image", C.c_void_p),
+                ("final_T", C.c_void_p), ("n_contrib", C.c_void_p)]
+
+
+def gs_render_views_workspace_size(n_views, total_tiles) -> int:
+    L = load()
+    L.gs_render_views_workspace_size.argtypes = [C.c_int, C.c_int64]
+    L.gs_render_views_workspace_size.restype = C.c_size_t
+    return int(L.gs_render_views_workspace_size(int(n_views), int(total_tiles)))
+
+
+def gs_render_views(scene: GsScene, mode: GsMode, frames, n_views, bg, cfg, lanes, clock, ws,
+                    stream=None):
+    """frames: ctypes array of GsViewFrame (host)."""
+    L = load()
+    L.gs_render_views.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                  C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_size_t,
+                                  C.c_void_p]
+    L.gs_render_views.restype = C.c_int
+    bgv = (C.c_float * 3)(*[float(x) for x in bg])
+    _check(L.gs_render_views(C.byref(scene), C.byref(mode), C.cast(frames, C.c_void_p),
+                             int(n_views), bgv, C.byref(cfg) if cfg is not None else None,
+                             int(lanes), _ptr(clock), _ptr(ws),
+                             int(ws.numel() * ws.element_size()), _stream(stream)))
 
 
 def gs_wall_clock_khz(device=0) -> int:

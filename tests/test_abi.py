@@ -36,6 +36,71 @@ def test_exports_every_declared_symbol(G):
     assert set(names) == set(G.EXPORTS)
 
 
+def exported_symbols():
+    """Names in libgsr.so's dynamic symbol table that it defines."""
+    import subprocess
+    from paper_2604_18980_amd import gsr
+    out = subprocess.run(["nm", "-D", "--defined-only", gsr.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    return {line.split()[-1] for line in out.splitlines() if line.strip()}
+
+
+def test_exported_c_symbols_equal_header(G):
+    """The C-linkage symbols libgsr.so exports are exactly the entry points
+    gsr.h declares (hidden visibility by default).  Everything else it exports
+    is a kernel handle (C++-mangled, the HIP runtime looks kernels up by name)
+    or a compiler-generated compilation-unit id."""
+    syms = exported_symbols()
+    c_syms = {s for s in syms if not s.startswith("_Z") and not s.startswith("__hip_cuid_")}
+    assert c_syms == set(declared()), sorted(c_syms ^ set(declared()))
+    mangled = {s for s in syms if s.startswith("_Z")}
+    # every mangled export is a __global__ function of the gsr kernels (k_...)
+    assert all("k_" in s for s in mangled), sorted(s for s in mangled if "k_" not in s)
+
+
+def test_plane_offsets_are_64_bit(tmp_path):
+    """The structure-of-arrays plane offset k n + g the preprocess kernels and
+    their adjoint index with, evaluated on the host (hipcc, no GPU) at the
+    largest n the interface accepts: exact, where 32-bit arithmetic wraps for
+    n above about 7.2e8."""
+    import subprocess
+    src = tmp_path / "plane.cpp"
+    src.write_text(
+        '#include "gsr_internal.hpp"\n#include <stdio.h>\n'
+        "int main() {\n"
+        "  const int n = 2147483647, g = n - 1;\n"
+        "  for (int k = 0; k < 4; ++k) {\n"
+        "    unsigned long long want = (unsigned long long)k * 2147483647ull + 2147483646ull;\n"
+        "    if (gsr::plane_at(k, n, g) != want) { printf(\"bad %d\\n\", k); return 1; }\n"
+        "  }\n"
+        "  printf(\"ok\\n\");\n  return 0;\n}\n")
+    exe = tmp_path / "plane"
+    cmd = ["/opt/rocm/bin/hipcc", "-std=c++17", "-I" + os.path.join(ROOT, "include"),
+           "-I" + os.path.join(ROOT, "paper_2604_18980_amd", "csrc"), str(src), "-o", str(exe)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout
+
+
+def test_scene_size_limit(G):
+    """n is accepted below 2^31 (ids are 32-bit) and rejected from 2^31 on,
+    before anything is enqueued."""
+    L = G.load()
+    P = C.c_void_p
+    cam = _cam(G)
+    mode = G.mode_struct()
+    sc = G.GsScene()
+    for p in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        setattr(sc, p, 4096)
+    sc.n = 1 << 31
+    assert L.gs_preprocess(C.byref(sc), C.byref(cam), C.byref(mode), P(1), P(1), P(1), None) == 1
+    assert b"2^31" in L.gs_last_error()
+    grads = G.GsSceneGrads(4096, 4096, 4096, 4096, 4096)
+    assert L.gs_preprocess_backward(C.byref(sc), C.byref(cam), P(1), P(1), C.byref(grads),
+                                    None) == 1
+
+
 def test_version_and_status_strings(G):
     assert "gfx950" in G.gs_version()
     L = G.load()
@@ -124,3 +189,40 @@ def test_binding_raises_with_message(G):
         sc = G.GsScene()
         sc.n = 5
         G.gs_preprocess(sc, cam, G.mode_struct(), None, None, None, stream=0)
+
+
+def test_render_views_rejects_bad_arguments(G):
+    L = G.load()
+    P = C.c_void_p
+    sc = G.GsScene()
+    sc.n = 10
+    sc.sh_degree = 0
+    for p in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        setattr(sc, p, 4096)
+    mode = G.mode_struct()
+    frames = (G.GsViewFrame * 2)()
+    for f in frames:
+        f.cam = _cam(G)
+        f.splats = f.rects = f.tiles_touched = f.sorted_gids = f.ranges = 4096
+        f.num_pairs = f.image = f.final_T = f.n_contrib = f.ws = 4096
+        f.pair_capacity = 100
+        f.ws_bytes = 1 << 40
+    bg = (C.c_float * 3)()
+    args = lambda n, lanes, ws_bytes: (C.byref(sc), C.byref(mode), C.cast(frames, P), n, bg, None,
+                                       lanes, None, P(4096), ws_bytes, None)
+    assert L.gs_render_views(*args(0, 1, 1 << 40)) == 1
+    assert L.gs_render_views(*args(65, 1, 1 << 40)) == 1
+    assert L.gs_render_views(*args(2, 0, 1 << 40)) == 1
+    assert L.gs_render_views(*args(2, 9, 1 << 40)) == 1
+    assert b"lanes" in L.gs_last_error()
+    assert L.gs_render_views(*args(2, 1, 16)) == 2          # views workspace too small
+    frames[1].ws_bytes = 16
+    assert L.gs_render_views(*args(2, 1, 1 << 40)) == 2     # view 1's binning workspace
+    assert b"view 1" in L.gs_last_error()
+    frames[1].ws_bytes = 1 << 40
+    frames[0].pair_capacity = 1 << 33
+    assert L.gs_render_views(*args(2, 1, 1 << 40)) == 1
+    frames[0].pair_capacity = 100
+    frames[1].cam.width = 0
+    assert L.gs_render_views(*args(2, 1, 1 << 40)) == 1
+    assert G.gs_render_views_workspace_size(64, 1_400_960) > G.gs_views_workspace_size(64, 1_400_960)

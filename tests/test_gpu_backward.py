@@ -7,6 +7,8 @@ import pytest
 
 from paper_2604_18980_amd import scenes
 
+from gpu_util import EXEMPT_MARGIN, conic_grads
+
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
@@ -51,7 +53,7 @@ def test_raster_backward_matches_oracle(O, mode):
     fr = O.render(sc, cam, O.Mode(adagscale=mode.get("adagscale", False), K=mode.get("K", 0.0)),
                   bg=(0.1, 0.2, 0.3))
     # skip the (rare) pixels whose forward decisions are ambiguous in float32
-    amb = fr.margin < 1e-4
+    amb = fr.margin < EXEMPT_MARGIN
     dLo = dL.astype(np.float64).copy()
     dLo[:, amb] = 0.0
     if amb.any():
@@ -63,9 +65,10 @@ def test_raster_backward_matches_oracle(O, mode):
         torch.cuda.synchronize()
         g = grad.cpu().numpy()
     g2d = O.blend_backward(fr, cam, dLo, bg=(0.1, 0.2, 0.3))
-    for name, cols_g, cols_o in [("mean", [0, 1], [0, 1]), ("A,beta,gamma", [2, 3, 4], [2, 3, 4]),
-                                 ("opacity", [5], [5]), ("rgb", [8, 9, 10], [6, 7, 8])]:
-        r = _rel(g[:, cols_g], g2d[:, cols_o])
+    gc = conic_grads(g, fb.splats.cpu().numpy())
+    for name, cols in [("mean", [0, 1]), ("conic", [2, 3, 4]), ("opacity", [5]),
+                       ("rgb", [6, 7, 8])]:
+        r = _rel(gc[:, cols], g2d[:, cols])
         print(f"{name}: rel {r:.2e}")
         assert r < TOL, (name, r)
     assert np.all(g[:, [6, 7, 11]] == 0)
@@ -87,7 +90,11 @@ def test_preprocess_backward_matches_oracle(O):
     gsr.gs_preprocess_backward(ds.struct(), gsr.camera_struct(cam), fb.tiles_touched,
                                torch.from_numpy(gs).cuda(), gsr.GsSceneGrads(*[t.data_ptr() for t in out]))
     torch.cuda.synchronize()
-    ref = O.preprocess_backward(sc, cam, fr.pre, g2d32.astype(np.float64))
+    # the same gradients on the oracle's record (Cxx, Cxy, Cyy), by the chain
+    # rule at the double-precision (A, beta)
+    sp = np.zeros((sc.n, 12))
+    sp[:, 2:4] = fr.pre.quad[:, 0:2]
+    ref = O.preprocess_backward(sc, cam, fr.pre, conic_grads(gs, sp))
     for name, t in zip(("means", "log_scales", "quats", "opacity_logits", "sh"), out):
         r = _rel(_host(name, t), ref[name])
         print(f"{name}: rel {r:.2e}")
@@ -107,7 +114,7 @@ def test_autograd_end_to_end(O, mode):
               for a in (sc.means, sc.log_scales, sc.quats, sc.opacity_logits,
                         sh_to_device_layout(sc.sh))]
     fr = O.render(sc, cam, O.Mode(adagscale=mode.get("adagscale", False), K=mode.get("K", 0.0)))
-    keep = (fr.margin >= 1e-4).astype(np.float32)  # drop float32-ambiguous pixels from the loss
+    keep = (fr.margin >= EXEMPT_MARGIN).astype(np.float32)  # drop float32-ambiguous pixels
     img = rasterize(*params, sc.sh_degree, cam, bg=(0.0, 0.0, 0.0), **mode)
     loss = ((img - torch.from_numpy(target).cuda()).abs() * torch.from_numpy(keep).cuda()).sum() / img.numel()
     loss.backward()

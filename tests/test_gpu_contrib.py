@@ -9,7 +9,7 @@ import pytest
 
 from paper_2604_18980_amd import scenes
 
-from gpu_util import check_image, to_np
+from gpu_util import EXEMPT_MARGIN, check_image, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -127,7 +127,7 @@ def test_contribution_profile_matches_oracle(O, name):
     o_sums, o_counts = O.contrib_profile(fr, cam, nbins=34, bin_width=float(np.float32(0.1)))
     g_counts = counts.cpu().numpy()
     g_sums = sums.cpu().numpy().astype(np.float64)
-    n_amb = int((fr.margin < 1e-4).sum())
+    n_amb = int((fr.margin < EXEMPT_MARGIN).sum())
     total = int(o_counts.sum())
     print(f"  blends {int(g_counts.sum())} (oracle {total}), ambiguous pixels {n_amb}", flush=True)
     assert abs(int(g_counts.sum()) - total) <= 4 * n_amb

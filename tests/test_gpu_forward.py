@@ -8,8 +8,8 @@ import pytest
 
 from paper_2604_18980_amd import scenes
 
-from gpu_util import (EXEMPT_MARGIN, check_emission_order, check_image, check_pairs,
-                      check_preprocess, check_sorted, gpu_frame, oracle_mode)
+from gpu_util import (EXEMPT_MARGIN, check_emission_order, check_image, check_image_exact,
+                      check_pairs, check_preprocess, check_sorted, gpu_frame, oracle_mode)
 
 pytestmark = pytest.mark.gpu
 
@@ -42,7 +42,9 @@ def _full_check(O, sc, cam, mode, bg=(0.0, 0.0, 0.0)):
     check_emission_order(g)
     check_sorted(fr, g, O.num_tiles(cam))
     n_ex = check_image(fr, g)
-    print(f"  pairs={g['num_pairs']} exempt_pixels={n_ex}", flush=True)
+    n_ex2, worst = check_image_exact(O, fr, g, cam, bg)
+    print(f"  pairs={g['num_pairs']} exempt_pixels={n_ex} (exact record: {n_ex2}, "
+          f"largest diff / bound {worst:.2f})", flush=True)
     return g, fr
 
 
@@ -84,7 +86,12 @@ def test_mid_scene_subsample(O):
         for t in range(0, O.num_tiles(cam), 37):
             ty, tx = divmod(t, TX)
             mask[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16] = True
-        check_image(fr, g, mask=mask)
+        n_ex = check_image(fr, g, mask=mask)
+        n_ex2, worst = check_image_exact(O, fr, g, cam,
+                                         tiles=np.arange(0, O.num_tiles(cam), 37, dtype=np.int32),
+                                         mask=mask)
+        print(f"  mid {mode}: exempt {n_ex} / {int(mask.sum())} (exact record: {n_ex2}, "
+              f"largest diff / bound {worst:.2f})", flush=True)
 
 
 def test_empty_and_culled_scenes(O):
@@ -183,7 +190,7 @@ def test_evaluation_counts_match_oracle(O):
     R.run_raster(fb, gsr.camera_struct(cam), (0.0, 0.0, 0.0), n_evaluated=ne)
     torch.cuda.synchronize()
     fr = O.render(sc, cam, O.Mode(adagscale=True, K=0.1))
-    ok = fr.margin >= 1e-4
+    ok = fr.margin >= EXEMPT_MARGIN
     np.testing.assert_array_equal(ne.cpu().numpy()[ok], fr.evals[ok])
 
 
@@ -212,7 +219,7 @@ def test_raster_work_counts(O, which):
     assert w["list_evaluations"] == int(ne.to(torch.int64).sum().item())
     fr = O.render(sc, cam, mode)
     ev, bl, mg = O.blend_counts(fr, cam)
-    amb = mg < 1e-4
+    amb = mg < EXEMPT_MARGIN
     lens = (fr.ranges[:, 1] - fr.ranges[:, 0]).max()
     slack = int(amb.sum()) * int(lens)
     assert abs(w["list_evaluations"] - int(ev.sum())) <= slack
@@ -254,7 +261,7 @@ def test_raster_geometries_match_oracle(O, geom, which):
             ty, tx = divmod(int(t), TX)
             mask[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16] = True
     n_ex = check_image(fr, g, mask=mask)
-    ok = (fr.margin >= 1e-4) & (mask if mask is not None else True)
+    ok = (fr.margin >= EXEMPT_MARGIN) & (mask if mask is not None else True)
     np.testing.assert_array_equal(ne.cpu().numpy()[ok], fr.evals[ok])
     print(f"geometry {geom}: exempt {n_ex}")
 

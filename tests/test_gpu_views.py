@@ -98,3 +98,40 @@ def test_views_graph_replay(O):
         for fb, r in zip(mv.fbs, ref):
             np.testing.assert_array_equal(fb.image.cpu().numpy(), r)
         _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+
+
+def test_render_views_lanes_and_overflow(O):
+    """gs_render_views gives the same frame on 1, 3 and 8 lane streams; a view
+    whose pair buffer is too small reports its required count and renders only
+    the background, while the other views are unaffected."""
+    import torch
+    from paper_2604_18980_amd import render as R
+    from paper_2604_18980_amd.views import MultiView
+    sc, _ = scenes.tiny_scene(n=2500, seed=23, sh_degree=3)
+    ds = R.DeviceScene.from_host(sc)
+    cams = _cams()
+    mode = dict(adagscale=True, K=0.1, extent_rule=1)
+    bg = (0.25, 0.5, 0.75)
+    ref = None
+    for lanes in (1, 3, 8):
+        mv = MultiView(ds, cams, mode=mode, bg=bg, lanes=lanes)
+        mv.enqueue()
+        torch.cuda.synchronize()
+        imgs = [fb.image.cpu().numpy().copy() for fb in mv.fbs]
+        if ref is None:
+            ref = imgs
+        for a, b in zip(imgs, ref):
+            np.testing.assert_array_equal(a, b)
+    need = int(mv.fbs[2].num_pairs.item())
+    assert need > 8
+    mv.fbs[2].set_capacity(need // 2)
+    mv._frames()
+    mv.enqueue()
+    torch.cuda.synchronize()
+    assert int(mv.fbs[2].num_pairs.item()) == need
+    img = mv.fbs[2].image.cpu().numpy()
+    for ch in range(3):
+        assert np.all(img[ch] == np.float32(bg[ch]))
+    for v, fb in enumerate(mv.fbs):
+        if v != 2:
+            np.testing.assert_array_equal(fb.image.cpu().numpy(), ref[v])

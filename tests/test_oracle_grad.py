@@ -21,7 +21,7 @@ def _scene(n, seed, sh_degree):
 
 def _forward(O, sc, cam, frame, mode, w, bg):
     pre = O.preprocess(sc, cam, mode)
-    rec = pre.record(round_to_f32=False)
+    rec = pre.record("double")
     img, T, nc, mg, ev, sig = O.blend(frame, cam, bg, rec=rec)
     return float((w * img).sum()), sig, pre.flags
 
@@ -34,7 +34,7 @@ def test_adjoint_matches_central_differences(O, sh_degree, adagscale):
     frame = O.render(sc, cam, mode, bg)
     rng = np.random.default_rng(0)
     w = rng.normal(size=frame.image.shape)
-    rec = frame.pre.record(round_to_f32=False)
+    rec = frame.pre.record("double")
     g2d = O.blend_backward(frame, cam, w, bg, rec=rec)
     grads = O.preprocess_backward(sc, cam, frame.pre, g2d)
     L0, sig0, flags0 = _forward(O, sc, cam, frame, mode, w, bg)

@@ -263,13 +263,16 @@ def test_lut_bin_lookup(O):
 # --------------------------------------------------------------------------- blend closed forms
 def _pipeline_single(O, gaussians, cam, bg=(0, 0, 0)):
     """Build a Frame from explicit 2D records (mean x, mean y, A, beta, gamma,
-    opacity, r, g, b), where the inverse covariance is
-    [[A, A beta], [A beta, A beta^2 + gamma]]."""
+    opacity, r, g, b), rounded to float32, where the inverse covariance is
+    [[A, A beta], [A beta, A beta^2 + gamma]]; the blend reads it as the conic
+    (Cxx, Cxy, Cyy) of that matrix."""
     n = len(gaussians)
     rec = np.zeros((n, 9))
     for i, g in enumerate(gaussians):
         rec[i] = g
     rec = rec.astype(np.float32).astype(np.float64)
+    A, beta, gamma = rec[:, 2].copy(), rec[:, 3].copy(), rec[:, 4].copy()
+    rec[:, 2], rec[:, 3], rec[:, 4] = A, A * beta, A * beta * beta + gamma
     ntiles = O.num_tiles(cam)
     sv = np.arange(n, dtype=np.uint32)
     rg = np.zeros((ntiles, 2), np.int64)
@@ -793,9 +796,9 @@ def _numpy_skip_blend(pre, fr, cam, thr_of):
             T = 1.0
             col = np.zeros(3)
             for i in fr.sorted_vals[fr.ranges[t, 0]:fr.ranges[t, 1]]:
-                mx, my, A, beta, gam, op = rec[i, :6]
+                mx, my, cxx, cxy, cyy, op = rec[i, :6]
                 dx, dy = mx - px, my - py
-                q = A * (dx + beta * dy) ** 2 + gam * dy * dy
+                q = np.array([dx, dy]) @ np.array([[cxx, cxy], [cxy, cyy]]) @ np.array([dx, dy])
                 alpha = min(0.99, op * math.exp(-0.5 * q))
                 if alpha < 1 / 255 or thr_of(i, alpha):
                     continue
