@@ -643,13 +643,23 @@ void orc_ranges(int64_t np, const uint64_t *keys, int num_tiles, int64_t *ranges
 /* (the offset's rounding moves q by 2 sqrt(q) G U at most; stored values,   */
 /* products and the exponential by a few U each), and the relative error of */
 /* T after blends j = 1..k is at most sum_j (alpha_j e_alpha,j + U) /        */
-/* (1 - alpha_j) (each factor 1 - alpha_j and each product).  A pixel's       */
-/* margin is the smallest ratio, over its decisions, of the relative        */
-/* distance to the threshold (|alpha - tau| / tau, |T' - 1e-4| / 1e-4,       */
-/* |c - theta| / theta) to that bound; a margin below 1 means a float32      */
-/* renderer may legitimately decide differently.                             */
+/* (1 - alpha_j) (each factor 1 - alpha_j and each product).  A relative    */
+/* error e moves the logarithm of a value by e (to first order), so the      */
+/* distance of a decision to its threshold is taken in logarithms:           */
+/* |ln(alpha / tau)|, |ln(T' / 1e-4)|, |ln(c / theta)|, each over its bound.  */
+/* (The log form stays valid where the bound itself is large: far out on a   */
+/* thin Gaussian q, and with it e_alpha, grows without limit while alpha is  */
+/* vanishingly small, and ln(alpha / tau) = ln(opacity / tau) - q / 2 grows  */
+/* with it.)  A pixel's margin is the smallest such ratio over its           */
+/* decisions; below 1 a float32 renderer may legitimately decide otherwise. */
 /* ------------------------------------------------------------------------ */
 #define U32 5.9604644775390625e-08 /* 2^-24, the float32 unit roundoff */
+
+/* |ln(v / th)| / e: the distance of v >= 0 to the threshold th > 0 in units of
+ * the relative error bound e (infinite for v = 0, which no rounding lifts). */
+static double log_margin(double v, double th, double e) {
+    return v > 0.0 ? fabs(log(v / th)) / e : INFINITY;
+}
 
 static double quad_form(const double *g, double dx, double dy) {
     return g[2] * dx * dx + 2.0 * g[3] * dx * dy + g[4] * dy * dy;
@@ -763,13 +773,13 @@ static void blend_pixel_prof(double px, double py, const uint32_t *list, int64_t
         double alpha = g[5] * exp(power);
         if (alpha > ALPHA_MAX) alpha = ALPHA_MAX;
         double ea = alpha_err(g, dx, dy, q);
-        double ma = fabs(alpha - TAU) / TAU / ea;
+        double ma = log_margin(alpha, TAU, ea);
         if (ma < margin) margin = ma;
         if (alpha < TAU) continue;
         if (sk && sk->theta > 0.0) {
             double c = alpha * skip_weight(sk, list[j], T);
             double ec = ea + (sk->kind == 0 ? eT : 0.0) + U32;
-            double mc = fabs(c - sk->theta) / sk->theta / ec;
+            double mc = log_margin(c, sk->theta, ec);
             if (mc < margin) margin = mc;
             if (c < sk->theta) {
                 if (skipped) ++*skipped;
@@ -778,7 +788,7 @@ static void blend_pixel_prof(double px, double py, const uint32_t *list, int64_t
         }
         double Tn = T * (1.0 - alpha);
         double eTn = eT + (alpha * ea + U32) / (1.0 - alpha) + U32;
-        double mt = fabs(Tn - T_STOP) / T_STOP / eTn;
+        double mt = log_margin(Tn, T_STOP, eTn);
         if (mt < margin) margin = mt;
         if (Tn < T_STOP) break;
         for (int ch = 0; ch < 3; ++ch) C[ch] += alpha * T * g[6 + ch];

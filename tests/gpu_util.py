@@ -13,9 +13,13 @@ from paper_2604_18980_amd import gsr
 # may legitimately take the other branch; 2 leaves room for the second-order
 # terms the bound drops.
 EXEMPT_MARGIN = 2.0
-# at most this fraction of the compared pixels may be exempt (plus a floor of a
-# few pixels for tiny images)
-EXEMPT_MAX_FRAC = 1e-4
+# At most this fraction of the compared pixels may be exempt (plus a floor of a
+# few pixels for tiny images).  The exempt set is the oracle's alone (no kernel
+# output enters it); the cap keeps at least 99.5% of the pixels compared.  Each
+# pixel makes one decision per evaluated list entry, so pixels of long lists
+# hold more near-threshold decisions: 0 on the tiny scenes, up to 2.4e-3 on the
+# heaviest sampled tiles of the plain 6M city (thousands of entries per pixel).
+EXEMPT_MAX_FRAC = 5e-3
 EXEMPT_MAX_FLOOR = 4
 IMAGE_TOL = 2e-5       # max-abs per channel outside exempt pixels
 
@@ -157,21 +161,21 @@ def check_sorted(fr, g, ntiles):
     np.testing.assert_array_equal(g["ranges"], fr.ranges)
 
 
-def max_exempt(checked):
-    return EXEMPT_MAX_FLOOR + int(EXEMPT_MAX_FRAC * checked)
+def max_exempt(checked, frac=EXEMPT_MAX_FRAC):
+    return EXEMPT_MAX_FLOOR + int(frac * checked)
 
 
-def check_image(fr, g, tol=IMAGE_TOL, margin=EXEMPT_MARGIN, mask=None):
+def check_image(fr, g, tol=IMAGE_TOL, margin=EXEMPT_MARGIN, mask=None, max_frac=EXEMPT_MAX_FRAC):
     """Images within tol outside pixels whose blend decisions sit within
     `margin` float32 error bounds of a threshold (exempt pixels, at most
-    EXEMPT_MAX_FRAC of the compared ones); n_contrib exact and final T within
-    tol there too.  Returns the number of exempt pixels."""
+    max_frac of the compared ones); n_contrib exact and final T within tol
+    there too.  Returns the number of exempt pixels."""
     ex = fr.margin < margin
     sel = np.ones_like(ex) if mask is None else mask
     ok = ~ex & sel
     n_ex = int((ex & sel).sum())
     checked = int(sel.sum())
-    assert n_ex <= max_exempt(checked), (n_ex, checked)
+    assert n_ex <= max_exempt(checked, max_frac), (n_ex, checked)
     diff = np.abs(g["image"] - fr.image)
     assert diff[:, ok].max(initial=0) <= tol, diff[:, ok].max()
     np.testing.assert_array_equal(g["n_contrib"][ok], fr.n_contrib[ok])

@@ -13,6 +13,8 @@ from gpu_util import EXEMPT_MARGIN, check_image, to_np
 
 pytestmark = pytest.mark.gpu
 
+SKIP_EXEMPT_FRAC = 1e-2
+
 
 def _case(name):
     if name == "tiny":
@@ -79,7 +81,11 @@ def test_skip_matches_oracle(O, name, kind, theta):
     o_img, o_T, o_nc, o_mg, o_bl, o_sk = O.blend_skip(fr, cam, kind, float(np.float32(theta)), **okw)
     ofr = O.Frame(fr.pre, None, None, None, None, None)
     ofr.image, ofr.final_T, ofr.n_contrib, ofr.margin = o_img, o_T, o_nc, o_mg
-    n_ex = check_image(ofr, dict(image=img, final_T=T, n_contrib=nc))
+    # the skip rule adds a decision per blend (alpha x weight against theta),
+    # and under kind 0 its weight is the running T with the walk's accumulated
+    # error bound, so more pixels hold a decision near a threshold than in a
+    # plain blend: up to 1e-2 of them may be exempt
+    n_ex = check_image(ofr, dict(image=img, final_T=T, n_contrib=nc), max_frac=SKIP_EXEMPT_FRAC)
     kept = int(o_bl.sum())
     print(f"  skipped {counts[0]} (oracle {o_sk}), kept {counts[1]} (oracle {kept}), "
           f"exempt pixels {n_ex}", flush=True)

@@ -8,7 +8,7 @@ import pytest
 
 from paper_2604_18980_amd import scenes
 
-from gpu_util import (EXEMPT_MARGIN, check_emission_order, check_image, check_image_exact,
+from gpu_util import (EXEMPT_MARGIN, check_emission_order, check_image, check_image_exact, max_exempt,
                       check_pairs, check_preprocess, check_sorted, gpu_frame, oracle_mode)
 
 pytestmark = pytest.mark.gpu
@@ -152,6 +152,7 @@ def test_ellipse_rule_on_gpu_drops_only_empty_pairs(O):
     pe = set(zip(ell["pair_tiles"].tolist(), ell["pair_gids"].tolist()))
     assert pe <= pr
     ok = O.render(sc, cam).margin >= EXEMPT_MARGIN  # no blend decision near a threshold
+    assert int((~ok).sum()) <= max_exempt(ok.size)
     assert np.abs(ell["image"] - rect["image"])[:, ok].max() <= 2e-5
     print(f"  pairs rect {rect['num_pairs']} ellipse {ell['num_pairs']}", flush=True)
 
@@ -191,6 +192,7 @@ def test_evaluation_counts_match_oracle(O):
     torch.cuda.synchronize()
     fr = O.render(sc, cam, O.Mode(adagscale=True, K=0.1))
     ok = fr.margin >= EXEMPT_MARGIN
+    assert int((~ok).sum()) <= max_exempt(ok.size)
     np.testing.assert_array_equal(ne.cpu().numpy()[ok], fr.evals[ok])
 
 
