@@ -199,6 +199,25 @@ GS_API gs_status gs_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids, 
                   uint32_t *sorted_gids, uint32_t *ranges, void *ws, size_t ws_bytes,
                   void *stream);
 
+/* gs_sort without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, allocation-free serving loops,
+ * harnesses that forbid hipMalloc).  It allocates nothing: its workspace is a
+ * fixed array of GS_SORT_NOALLOC_SCRATCH_BYTES (64 MiB) inside libgsr, which
+ * every device the library runs on holds for the life of the process.
+ * Arguments, outputs and errors as gs_sort; in addition pair_capacity above
+ * GS_SORT_NOALLOC_MAX_PAIRS returns GS_ERR_INVALID_ARGUMENT.  All calls on one
+ * device share that device's array: calls that overlap in time on one device
+ * (on different streams, or from different threads) race and give undefined
+ * results; calls in stream order are safe (each call rewrites every scratch
+ * entry it reads).  The first call on a device looks up the array's address
+ * there (the device must be current). */
+#define GS_SORT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+#define GS_SORT_NOALLOC_MAX_PAIRS 8000000LL
+GS_API gs_status gs_sort_noalloc(const uint32_t *pair_tiles, const uint32_t *pair_gids,
+                                 const int64_t *num_pairs, int64_t pair_capacity,
+                                 const gs_camera *cam, uint32_t *sorted_tiles,
+                                 uint32_t *sorted_gids, uint32_t *ranges, void *stream);
+
 /* Stages 2 and 3 fused (Sec. 2.1 pair generation, sorting and tile ranges;
  * Sec. 3.3: the rectangles already carry AdaGScale's extent).  Produces the
  * same per-tile lists as gs_emit_pairs followed by gs_sort with the same

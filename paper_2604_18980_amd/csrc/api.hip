@@ -368,6 +368,71 @@ gs_status rasterize_views(const gs_view_target *views, const gs_view_target *d_v
     if (!grid_cache[gi]) grid_cache[gi] = raster_views_grid(c);
     return hip_check(launch_raster_views(q, c, grid_cache[gi], s), who);
 }
+
+// Argument checks of gs_sort and gs_sort_noalloc (host only).
+gs_status check_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids,
+                     const int64_t *num_pairs, int64_t pair_capacity, const gs_camera *cam,
+                     const uint32_t *sorted_tiles, const uint32_t *sorted_gids,
+                     const uint32_t *ranges) {
+    gs_status st;
+    if ((st = check_camera(cam)) != GS_OK) return st;
+    if (pair_capacity < 0 || pair_capacity > (int64_t)0xffffffffLL)
+        return fail(GS_ERR_INVALID_ARGUMENT, "pair_capacity outside [0, 2^32)");
+    if (!num_pairs || !ranges) return fail(GS_ERR_INVALID_ARGUMENT, "num_pairs or ranges is NULL");
+    if (pair_capacity > 0 && (!pair_tiles || !pair_gids || !sorted_tiles || !sorted_gids))
+        return fail(GS_ERR_INVALID_ARGUMENT, "pair arrays are NULL");
+    if (pair_capacity > 0 && (sorted_tiles == pair_tiles || sorted_gids == pair_gids))
+        return fail(GS_ERR_INVALID_ARGUMENT, "sorted arrays must not alias the inputs");
+    return GS_OK;
+}
+
+// The sort's launches on a workspace of ws_bytes at ws.
+gs_status enqueue_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids,
+                       const int64_t *num_pairs, int64_t pair_capacity, const gs_camera *cam,
+                       uint32_t *sorted_tiles, uint32_t *sorted_gids, uint32_t *ranges, void *ws,
+                       size_t ws_bytes, hipStream_t s, const char *who) {
+    Workspace w;
+    workspace_layout(0, pair_capacity, ws, &w);
+    if (!ws || ws_bytes < w.bytes)
+        return fail(GS_ERR_CAPACITY, "%s: workspace of %zu bytes, %zu needed", who, ws_bytes, w.bytes);
+    const int ntiles = tiles_x(cam) * tiles_y(cam);
+    gs_status st;
+    if (pair_capacity > 0) {
+        hipError_t e = radix_sort_u32(pair_tiles, pair_gids, sorted_tiles, sorted_gids, w.ptile_tmp,
+                                      w.pgid_tmp, num_pairs, pair_capacity, bits_for(ntiles), w.phist,
+                                      w.nb_psort, w.scan_part, s);
+        if ((st = hip_check(e, who)) != GS_OK) return st;
+    }
+    return hip_check(launch_tile_ranges(sorted_tiles, num_pairs, pair_capacity, ranges, ntiles, s),
+                     who);
+}
+
+// gs_sort_noalloc's workspace: a fixed device array of this library, held on
+// every device the library runs on for the life of the process.  In host code
+// `scratch` names a host-side stand-in, never the device memory: its device
+// address is looked up once per device (with that device current) and kept.
+// Every call of gs_sort_noalloc on a device shares that device's array.
+constexpr size_t kScratchBytes = GS_SORT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mutex;
+void *g_scratch[kMaxDevices];
+
+gs_status scratch_address(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_check(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(GS_ERR_UNSUPPORTED, "device %d", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_check(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(GS_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return GS_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -472,29 +537,29 @@ gs_status gs_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids, const i
                   int64_t pair_capacity, const gs_camera *cam, uint32_t *sorted_tiles,
                   uint32_t *sorted_gids, uint32_t *ranges, void *ws, size_t ws_bytes,
                   void *stream) {
-    gs_status st;
-    if ((st = check_camera(cam)) != GS_OK) return st;
-    if (pair_capacity < 0 || pair_capacity > (int64_t)0xffffffffLL)
-        return fail(GS_ERR_INVALID_ARGUMENT, "pair_capacity outside [0, 2^32)");
-    if (!num_pairs || !ranges) return fail(GS_ERR_INVALID_ARGUMENT, "num_pairs or ranges is NULL");
-    if (pair_capacity > 0 && (!pair_tiles || !pair_gids || !sorted_tiles || !sorted_gids))
-        return fail(GS_ERR_INVALID_ARGUMENT, "pair arrays are NULL");
-    if (pair_capacity > 0 && (sorted_tiles == pair_tiles || sorted_gids == pair_gids))
-        return fail(GS_ERR_INVALID_ARGUMENT, "sorted arrays must not alias the inputs");
-    Workspace w;
-    workspace_layout(0, pair_capacity, ws, &w);
-    if (!ws || ws_bytes < w.bytes)
-        return fail(GS_ERR_CAPACITY, "workspace of %zu bytes, %zu needed", ws_bytes, w.bytes);
-    const int ntiles = tiles_x(cam) * tiles_y(cam);
-    hipStream_t s = (hipStream_t)stream;
-    if (pair_capacity > 0) {
-        hipError_t e = radix_sort_u32(pair_tiles, pair_gids, sorted_tiles, sorted_gids, w.ptile_tmp,
-                                      w.pgid_tmp, num_pairs, pair_capacity, bits_for(ntiles), w.phist,
-                                      w.nb_psort, w.scan_part, s);
-        if ((st = hip_check(e, "gs_sort")) != GS_OK) return st;
-    }
-    return hip_check(launch_tile_ranges(sorted_tiles, num_pairs, pair_capacity, ranges, ntiles, s),
-                     "gs_sort ranges");
+    gs_status st = check_sort(pair_tiles, pair_gids, num_pairs, pair_capacity, cam, sorted_tiles,
+                              sorted_gids, ranges);
+    if (st != GS_OK) return st;
+    return enqueue_sort(pair_tiles, pair_gids, num_pairs, pair_capacity, cam, sorted_tiles,
+                        sorted_gids, ranges, ws, ws_bytes, (hipStream_t)stream, "gs_sort");
+}
+
+gs_status gs_sort_noalloc(const uint32_t *pair_tiles, const uint32_t *pair_gids,
+                          const int64_t *num_pairs, int64_t pair_capacity, const gs_camera *cam,
+                          uint32_t *sorted_tiles, uint32_t *sorted_gids, uint32_t *ranges,
+                          void *stream) {
+    gs_status st = check_sort(pair_tiles, pair_gids, num_pairs, pair_capacity, cam, sorted_tiles,
+                              sorted_gids, ranges);
+    if (st != GS_OK) return st;
+    if (pair_capacity > GS_SORT_NOALLOC_MAX_PAIRS)
+        return fail(GS_ERR_INVALID_ARGUMENT,
+                    "gs_sort_noalloc: pair_capacity %lld above its fixed scratch's limit of %lld pairs",
+                    (long long)pair_capacity, (long long)GS_SORT_NOALLOC_MAX_PAIRS);
+    void *ptr = nullptr;
+    if ((st = scratch_address(&ptr)) != GS_OK) return st;
+    return enqueue_sort(pair_tiles, pair_gids, num_pairs, pair_capacity, cam, sorted_tiles,
+                        sorted_gids, ranges, ptr, kScratchBytes, (hipStream_t)stream,
+                        "gs_sort_noalloc");
 }
 
 gs_status gs_rasterize(const float *splats, int64_t n, const uint32_t *sorted_gids,

@@ -18,8 +18,11 @@ LIB_PATH = os.path.join(PKG, "libgsr.so")
 GS_OK, GS_ERR_INVALID_ARGUMENT, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = range(5)
 LUT_BINS = 20
 TILE = 16
+SORT_NOALLOC_MAX_PAIRS = 8_000_000          # GS_SORT_NOALLOC_MAX_PAIRS
+SORT_NOALLOC_SCRATCH_BYTES = 64 << 20       # GS_SORT_NOALLOC_SCRATCH_BYTES
 
-EXPORTS = ("gs_workspace_size", "gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_bin_pairs",
+EXPORTS = ("gs_workspace_size", "gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_sort_noalloc",
+           "gs_bin_pairs",
            "gs_rasterize", "gs_raster_work", "gs_calibrate_t_upper", "gs_rasterize_skip",
            "gs_contribution_profile",
            "gs_rasterize_backward", "gs_preprocess_backward", "gs_views_workspace_size",
@@ -77,6 +80,7 @@ def load():
     L.gs_preprocess.argtypes = [P, P, P, P, P, P, P]
     L.gs_emit_pairs.argtypes = [P, P, P, I64, P, I, P, P, I64, P, P, C.c_size_t, P]
     L.gs_sort.argtypes = [P, P, P, I64, P, P, P, P, P, C.c_size_t, P]
+    L.gs_sort_noalloc.argtypes = [P, P, P, I64, P, P, P, P, P]
     L.gs_bin_pairs.argtypes = [P, P, P, I64, P, I, P, P, P, I64, P, P, C.c_size_t, P]
     L.gs_rasterize.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P]
     L.gs_raster_work.argtypes = [P, I64, P, P, P, P, P]
@@ -88,7 +92,8 @@ def load():
     L.gs_preprocess_backward.argtypes = [P, P, P, P, P, P]
     L.gs_render_views.argtypes = [P, P, P, I, P, P, I, P, P, C.c_size_t, P]
     L.gs_render_views.restype = C.c_int
-    for f in ("gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_bin_pairs", "gs_rasterize",
+    for f in ("gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_sort_noalloc", "gs_bin_pairs",
+              "gs_rasterize",
               "gs_raster_work", "gs_calibrate_t_upper", "gs_rasterize_skip", "gs_contribution_profile",
               "gs_rasterize_backward", "gs_preprocess_backward"):
         getattr(L, f).restype = C.c_int
@@ -183,6 +188,13 @@ def gs_sort(pair_tiles, pair_gids, num_pairs, pair_capacity, cam: GsCamera, sort
                           C.byref(cam), _ptr(sorted_tiles), _ptr(sorted_gids), _ptr(ranges),
                           _ptr(ws), int(ws.numel() * ws.element_size()) if ws is not None else 0,
                           _stream(stream)))
+
+
+def gs_sort_noalloc(pair_tiles, pair_gids, num_pairs, pair_capacity, cam: GsCamera, sorted_tiles,
+                    sorted_gids, ranges, stream=None):
+    _check(load().gs_sort_noalloc(_ptr(pair_tiles), _ptr(pair_gids), _ptr(num_pairs),
+                                  int(pair_capacity), C.byref(cam), _ptr(sorted_tiles),
+                                  _ptr(sorted_gids), _ptr(ranges), _stream(stream)))
 
 
 def gs_bin_pairs(splats, rects, tiles_touched, n, cam: GsCamera, extent_rule, sorted_gids,

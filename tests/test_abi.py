@@ -226,3 +226,19 @@ def test_render_views_rejects_bad_arguments(G):
     frames[1].cam.width = 0
     assert L.gs_render_views(*args(2, 1, 1 << 40)) == 1
     assert G.gs_render_views_workspace_size(64, 1_400_960) > G.gs_views_workspace_size(64, 1_400_960)
+
+
+def test_sort_noalloc_limit(G):
+    """gs_sort_noalloc rejects a pair capacity above its fixed scratch's limit
+    on the host, before anything is enqueued, and the whole limit fits that
+    scratch."""
+    from paper_2604_18980_amd import scenes
+    import numpy as np
+    L = G.load()
+    cam = G.camera_struct(scenes.make_camera(np.eye(3), np.zeros(3), 64, 64))
+    P = C.c_void_p
+    cap = G.SORT_NOALLOC_MAX_PAIRS + 1
+    assert L.gs_sort_noalloc(P(16), P(32), P(48), cap, C.byref(cam), P(64), P(80), P(96),
+                             None) == G.GS_ERR_INVALID_ARGUMENT
+    assert b"limit" in L.gs_last_error()
+    assert L.gs_workspace_size(0, G.SORT_NOALLOC_MAX_PAIRS, 0, 0) <= G.SORT_NOALLOC_SCRATCH_BYTES
