@@ -161,9 +161,11 @@ GS_API size_t gs_workspace_size(int64_t n, int64_t pair_capacity, int width, int
  * max(0, SH(view direction) + 0.5), plain extent 3 sqrt(lambda_max) or the
  * AdaGScale-scaled extent (extent_rule 0; rule 1 keeps the plain extent), and
  * the tile rectangle.  Geometry that decides discrete outputs is evaluated in
- * double precision.
+ * double precision (a float32 prefilter with error bounds only skips that
+ * work for Gaussians it proves get no tiles).
  * Out: splats [n][12], rects [n], tiles_touched [n] = the rectangle's area
- * (0 = no pairs; under rule 1 an upper bound of the pairs). */
+ * (0 = no pairs; under rule 1 an upper bound of the pairs).  The record and
+ * the rectangle of a Gaussian with tiles_touched == 0 are unspecified. */
 GS_API gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_mode *mode,
                         float *splats, uint64_t *rects, uint32_t *tiles_touched, void *stream);
 

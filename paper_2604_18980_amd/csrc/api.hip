@@ -140,6 +140,8 @@ void fill_preprocess_args(const gs_scene *scene, const gs_mode *mode, gsr::Prepr
     a->extent_rule = mode->extent_rule;
     a->K = mode->K;
     a->lut_depth_max = mode->lut_depth_max;
+    a->Kf = mode->K;
+    a->lut_depth_maxf = mode->lut_depth_max;
     for (int i = 0; i < GS_LUT_BINS; ++i) a->lut[i] = mode->t_upper[i];
     sh_constants(a->shc);
     for (int i = 0; i < 16; ++i) a->shcf[i] = (float)a->shc[i];
@@ -158,6 +160,14 @@ void set_preprocess_camera(const gs_camera *cam, gsr::PreprocessArgs *a) {
     a->height = cam->height;
     a->tiles_x = tiles_x(cam);
     a->tiles_y = tiles_y(cam);
+    for (int i = 0; i < 9; ++i) a->Rf[i] = (float)a->R[i];
+    for (int i = 0; i < 3; ++i) a->tf[i] = (float)a->t[i];
+    a->fxf = (float)a->fx;
+    a->fyf = (float)a->fy;
+    a->cxf = (float)a->cx;
+    a->cyf = (float)a->cy;
+    a->limxf = (float)a->limx;
+    a->limyf = (float)a->limy;
 }
 }  // namespace
 
@@ -197,12 +207,11 @@ bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws, int tx,
     ws->counters = (int64_t *)take(sizeof(int64_t) * 4);
     const size_t sort_bytes = align256(off);
     // emit region
-    ws->nb_dgroups = (ws->nb_dsort + kDepthGroup - 1) / kDepthGroup;
+    ws->nb_dpass = depth_pass_blocks(n);
+    ws->nb_dgroups = depth_pass_groups(n);
     ws->vis_count = (uint32_t *)take(sizeof(uint32_t) * (size_t)ws->nb_dsort);
     ws->pair_tot = (uint64_t *)take(sizeof(uint64_t) * (size_t)ws->nb_dsort);
-    // group sums then totals, one region (cleared together)
-    ws->dgsum = (uint32_t *)take(sizeof(uint32_t) * 4 * 256 * (size_t)(ws->nb_dgroups + 1));
-    ws->dtot = ws->dgsum ? ws->dgsum + 4 * 256 * ws->nb_dgroups : nullptr;
+    ws->dgsum = (uint32_t *)take(sizeof(uint32_t) * 4 * 256 * (size_t)ws->nb_dgroups);
     ws->pair_cnt = (uint64_t *)take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     ws->pair_off = (uint64_t *)take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     ws->slice_start = (uint32_t *)take(sizeof(uint32_t) * (size_t)(cap / kEmitChunk + 2));
@@ -210,7 +219,7 @@ bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws, int tx,
         ws->dkey[i] = (uint32_t *)take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
         ws->dval[i] = (uint32_t *)take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
     }
-    ws->dhist = (uint32_t *)take(sizeof(uint32_t) * 256 * (size_t)ws->nb_dsort);
+    ws->dhist = (uint32_t *)take(sizeof(uint32_t) * 256 * (size_t)ws->nb_dpass);
     const size_t emit_bytes = align256(off);
     if (!bin) {
         ws->bytes = n > 0 ? emit_bytes : sort_bytes;

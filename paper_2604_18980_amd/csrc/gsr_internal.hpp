@@ -24,6 +24,8 @@ struct PreprocessArgs {
                       // 1: plain rectangle (ellipse test at emission)
     double K, lut_depth_max;
     float lut[kLutBins];
+    // float32 copies for the preprocess' float32 prefilter (proves culls)
+    float Rf[9], tf[3], fxf, fyf, cxf, cyf, limxf, limyf, Kf, lut_depth_maxf;
     double shc[16];  // real-SH normalisation constants, see preprocess.hip
     float shcf[16];  // the same, rounded to float32 (colour is evaluated in float32)
     float *splats;
@@ -36,15 +38,15 @@ struct Workspace {
     // emit
     uint32_t *vis_count;   // [nb_dsort] visible Gaussians per chunk of 4096 ids
     uint64_t *pair_tot;    // [nb_dsort] pairs per chunk of 4096 depth-sorted visible Gaussians
-    uint32_t *dgsum;       // [4][256][groups of 32 blocks] depth-pass digit sums per block group
-    uint32_t *dtot;        // [4][256] depth-pass digit totals
-    int64_t nb_dgroups;
+    uint32_t *dgsum;       // [4][256][nb_dgroups] depth-pass digit sums per block group
+    int64_t nb_dpass;      // blocks of the depth passes' grid (depth_pass_blocks)
+    int64_t nb_dgroups;    // group sums per digit row (depth_pass_groups)
     uint64_t *pair_cnt;    // [n] pairs of each depth-sorted visible Gaussian
     uint64_t *pair_off;    // [n] their exclusive prefix
     uint32_t *slice_start; // [cap / emit chunk + 1] first Gaussian of each emission slice
     uint32_t *dkey[3];     // [n] depth keys: input, sorted output, pass scratch
     uint32_t *dval[3];     // [n] Gaussian ids, same roles
-    uint32_t *dhist;       // [256][nb_dsort]
+    uint32_t *dhist;       // [256][nb_dpass]
     // sort
     uint32_t *ptile_tmp;   // [cap]
     uint32_t *pgid_tmp;    // [cap]
@@ -79,8 +81,6 @@ constexpr int kSortChunk = kSortThreads * kSortItems;     // 4096 items per bloc
 // pairs per emission slice (one workgroup each); slice_start[b] is the
 // depth-sorted Gaussian that owns pair b * kEmitChunk
 constexpr int kEmitChunk = kSortChunk;
-// depth presort: blocks per group of the two-level digit offsets
-constexpr int kDepthGroup = 32;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanChunk = kScanThreads * kScanItems;     // 4096 elements per block
@@ -148,6 +148,9 @@ hipError_t launch_emit(const float *splats, const uint64_t *rects, const uint32_
 // device memory) into dkey/dval[1]: four 8-bit LSD passes of two kernels
 // each (digit offsets from block-group sums, no device-wide scan kernels).
 hipError_t depth_sort(const Workspace &ws, const int64_t *count, hipStream_t s);
+// Grid of the depth passes and the group sums per digit, for n keys at most.
+int64_t depth_pass_blocks(int64_t n);
+int64_t depth_pass_groups(int64_t n);
 hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
                                const uint32_t *tiles_touched, int n, int extent_rule, int64_t cap,
                                int64_t *num_pairs, const Workspace &ws, hipStream_t s);

@@ -15,9 +15,18 @@
 // which is exact algebra (block LDL^T of Sigma2^-1) and has no cancellation:
 // the expanded A dx^2 + 2B dx dy + C dy^2 of a thin Gaussian evaluated far
 // from its centre loses most of its float32 digits.
+//
+// Most Gaussians of a view get no tiles: under AdaGScale their threshold Th
+// reaches their opacity (Sec. 3.3), or they project outside the image.  A
+// float32 prefilter with error bounds proves that for most of them, and only
+// the rest (kept in an LDS queue, so the double-precision lanes stay busy)
+// take the double-precision path, which alone decides every output.  A
+// Gaussian the prefilter drops is one the double-precision path would give no
+// tiles; its rectangle is not written (unspecified when tiles_touched is 0).
 #include <math.h>
 
 #include "gsr_internal.hpp"
+#include "prefilter.hpp"
 
 namespace gsr {
 
@@ -65,12 +74,9 @@ __device__ __forceinline__ void sh_eval(int degree, R x, R y, R z, const R *c, R
 }
 }  // namespace
 
-// DEG is the SH degree (0..3), a template parameter so the colour loads of all
-// (DEG+1)^2 x 3 coefficients are issued together rather than one per loop trip.
+// The double-precision path for Gaussian g: every output of the stage.
 template <int DEG>
-__global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.n) return;
+__device__ __forceinline__ void preprocess_exact(const PreprocessArgs &a, const int g) {
     const int n = a.n;
     uint32_t tiles = 0;
     uint64_t rect = 0;
@@ -244,10 +250,55 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
     a.tiles_touched[g] = tiles;
 }
 
+constexpr int kPreRounds = 4;                  // Gaussians per thread in the float32 pass
+constexpr int kPreChunk = 256 * kPreRounds;    // Gaussians per block
+
+// DEG is the SH degree (0..3), a template parameter so the colour loads of all
+// (DEG+1)^2 x 3 coefficients are issued together rather than one per loop trip.
+// Each block takes kPreChunk consecutive Gaussians: the float32 prefilter
+// writes tiles_touched = 0 for those it drops and queues the rest in LDS;
+// then the block's threads run the double-precision path on the queue.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
+    __shared__ uint32_t queue[kPreChunk];
+    __shared__ uint32_t qn;
+    if (threadIdx.x == 0) qn = 0u;
+    __syncthreads();
+    const int n = a.n;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t base = (int64_t)blockIdx.x * kPreChunk;
+    for (int r = 0; r < kPreRounds; ++r) {
+        const int64_t g64 = base + (int64_t)r * 256 + threadIdx.x;
+        bool cand = false;
+        if (g64 < n) {
+            const int g = (int)g64;
+            const float mx = a.means[g], my = a.means[plane_at(1, n, g)], mz = a.means[plane_at(2, n, g)];
+            const float l0 = a.log_scales[g], l1 = a.log_scales[plane_at(1, n, g)],
+                        l2 = a.log_scales[plane_at(2, n, g)];
+            const float qw = a.quats[g], qx = a.quats[plane_at(1, n, g)], qy = a.quats[plane_at(2, n, g)],
+                        qz = a.quats[plane_at(3, n, g)];
+            const float op = a.opacity_logits[g];
+            if (surely_no_tiles(a, mx, my, mz, l0, l1, l2, qw, qx, qy, qz, op))
+                a.tiles_touched[g] = 0u;
+            else
+                cand = true;
+        }
+        const uint64_t m = __ballot(cand);
+        if (m) {  // wave-uniform: every lane joins the atomic, lane 0 adding the count
+            const uint32_t old = atomicAdd(&qn, lane == 0 ? (uint32_t)__popcll(m) : 0u);
+            const uint32_t wbase = (uint32_t)__builtin_amdgcn_readlane((int)old, 0);
+            if (cand) queue[wbase + (uint32_t)__popcll(m & lanemask_lt())] = (uint32_t)(base + r * 256 + threadIdx.x);
+        }
+    }
+    __syncthreads();
+    const uint32_t nq = qn;
+    for (uint32_t i = threadIdx.x; i < nq; i += 256) preprocess_exact<DEG>(a, (int)queue[i]);
+}
+
 hipError_t launch_preprocess(const PreprocessArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     const int threads = 256;
-    const int blocks = (a.n + threads - 1) / threads;
+    const int blocks = (a.n + kPreChunk - 1) / kPreChunk;
     switch (a.sh_degree) {
         case 0: k_preprocess<0><<<blocks, threads, 0, s>>>(a); break;
         case 1: k_preprocess<1><<<blocks, threads, 0, s>>>(a); break;

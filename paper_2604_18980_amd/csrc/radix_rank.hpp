@@ -1,9 +1,10 @@
 // Stable block-level ranking by one 8-bit digit, shared by the radix sort's
 // scatter and by the fused binning passes.
 //
-// A block of kSortThreads threads holds kSortChunk items in registers,
-// assigned wave-striped -- wave w owns chunk positions [w*kPerWave,
-// (w+1)*kPerWave) and in step i lane l holds position w*kPerWave + i*64 + l --
+// A block of kSortThreads threads holds ITEMS items per thread in registers
+// (kSortItems unless stated), assigned wave-striped -- wave w owns chunk
+// positions [w*P, (w+1)*P), P = 64 ITEMS, and in step i lane l holds position
+// w*P + i*64 + l --
 // so lane order, then step order, then wave order is the input order.  Each
 // wave ranks its items with eight ballots per step (the lanes sharing the
 // digit) and a running per-digit count in LDS; per-digit wave prefixes and a
@@ -16,7 +17,6 @@
 namespace gsr {
 
 constexpr int kRankWaves = kSortThreads / kWave;
-constexpr int kRankPerWave = kSortChunk / kRankWaves;
 
 struct RankSmem {
     uint32_t wcnt[kRankWaves][256];  // per-wave running digit counts, then wave prefixes
@@ -30,32 +30,34 @@ __device__ __forceinline__ void rank_init(RankSmem &sm) {
     for (int i = threadIdx.x; i < kRankWaves * 256; i += kSortThreads) (&sm.wcnt[0][0])[i] = 0;
 }
 
-// Chunk position of item i of this thread.
+// Chunk position of item i of this thread, for blocks that hold ITEMS items
+// per thread (ITEMS * kSortThreads per block).
+template <int ITEMS = kSortItems>
 __device__ __forceinline__ int rank_pos(int i) {
-    return (threadIdx.x / kWave) * kRankPerWave + i * kWave + (threadIdx.x & (kWave - 1));
+    return (threadIdx.x / kWave) * (ITEMS * kWave) + i * kWave + (threadIdx.x & (kWave - 1));
 }
 
 // Ranks the block's items by digit (key >> shift) & 255 and, for each valid
 // item, computes payload = fetch(key, val) and calls store(dst, key, payload),
 // where dst = gbase[digit] + the item's stable rank within its digit.  Every
 // thread runs all its fetches (loads may be in flight together) before its
-// stores.  Items at positions >= cnt are invalid.  skey / sval: kSortChunk-entry
+// stores.  Items at positions >= cnt are invalid.  skey / sval: ITEMS*256-entry
 // LDS staging arrays, which may alias memory the caller no longer reads (item
 // generation must be complete).  Contains barriers; the caller must have run
 // rank_init, set gbase and issued a barrier.
 // sval may be null when the values are not needed (fetch then gets 0).
 // Output positions are below 2^32 (capacities are 32-bit).
-template <class Fetch, class Store>
-__device__ __forceinline__ void rank_stage_write(const uint32_t (&key)[kSortItems],
-                                                 const uint32_t (&val)[kSortItems], int cnt,
+template <int ITEMS, class Fetch, class Store>
+__device__ __forceinline__ void rank_stage_write(const uint32_t (&key)[ITEMS],
+                                                 const uint32_t (&val)[ITEMS], int cnt,
                                                  int shift, RankSmem &sm, uint32_t *skey,
                                                  uint32_t *sval, Fetch fetch, Store store) {
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    uint32_t rank[kSortItems];
+    uint32_t rank[ITEMS];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-        const bool valid = rank_pos(i) < cnt;
+    for (int i = 0; i < ITEMS; ++i) {
+        const bool valid = rank_pos<ITEMS>(i) < cnt;
         const uint32_t d = (key[i] >> shift) & 255u;
         // lanes whose digit differs from this lane's in some bit: per bit the
         // ballot XOR this lane's bit spread over 32 bits, OR-accumulated in the
@@ -90,7 +92,7 @@ __device__ __forceinline__ void rank_stage_write(const uint32_t (&key)[kSortItem
     sm.dstart[threadIdx.x] = block_exclusive_scan<kSortThreads, uint32_t>(tot_d, sm.wt, &all);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         if (rank[i] == 0xffffffffu) continue;
         const uint32_t d = (key[i] >> shift) & 255u;
         const uint32_t p = sm.dstart[d] + sm.wcnt[wid][d] + rank[i];
@@ -100,9 +102,9 @@ __device__ __forceinline__ void rank_stage_write(const uint32_t (&key)[kSortItem
     __syncthreads();
     // position p = threadIdx.x + i * kSortThreads: consecutive threads take
     // consecutive staged items, so each digit's run is stored contiguously
-    uint32_t k[kSortItems], pay[kSortItems], dst[kSortItems];
+    uint32_t k[ITEMS], pay[ITEMS], dst[ITEMS];
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const int p = threadIdx.x + i * kSortThreads;
         if (p < cnt) {
             k[i] = skey[p];
@@ -112,7 +114,7 @@ __device__ __forceinline__ void rank_stage_write(const uint32_t (&key)[kSortItem
         }
     }
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i)
+    for (int i = 0; i < ITEMS; ++i)
         if (threadIdx.x + i * kSortThreads < cnt) store((int64_t)dst[i], k[i], pay[i]);
 }
 

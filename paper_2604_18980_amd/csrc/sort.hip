@@ -214,83 +214,118 @@ void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32
 }
 
 // ---------------------------------------------------------- depth presort
-// The same LSD passes without the device-wide scan kernels: the histogram
-// kernel also adds each block's digit counts to per-digit totals and to sums
-// over groups of kDepthGroup blocks, and each scatter block forms its digit
-// offsets itself -- the exclusive scan of the totals over digits, plus the
-// sums of the earlier groups, plus the counts of the earlier blocks of its
-// own group (at most nb / kDepthGroup + kDepthGroup - 1 reads per digit).
-__global__ __launch_bounds__(kSortThreads) void k_dhist(const uint32_t *keys, const int64_t *count,
-                                                        int shift, uint32_t *hist, int64_t nb,
-                                                        uint32_t *gsum, int64_t ngroups,
-                                                        uint32_t *tot) {
-    __shared__ uint32_t h[kSortThreads / kWave][256];
-    const int wid = threadIdx.x / kWave;
-    for (int i = threadIdx.x; i < (kSortThreads / kWave) * 256; i += kSortThreads) (&h[0][0])[i] = 0;
-    __syncthreads();
-    const int64_t n = *count;
-    const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+// The same LSD passes without device-wide scan kernels and without atomics
+// that many blocks aim at one address (global atomics on one address
+// serialise, about 50 ns each).  The histogram kernel stores each block's
+// digit counts (digit-major) and adds them to sums over groups of blocks
+// (DepthRegime::group blocks per sum, so an address takes that many atomics);
+// each scatter block forms its offsets from its group's earlier counts and
+// every group sum: the sum over all groups is the digit's total, the sum over
+// the earlier groups plus the earlier blocks of its own group its start
+// within the digit.  Up to kDepthSmallMax visible keys the blocks hold 1024
+// keys (about one block per compute unit at a few hundred thousand keys, so
+// the per-block ranking, which is bound by LDS latency, runs on the whole
+// chip); above, 4096.  The regime is chosen on the device from the count,
+// uniformly for all blocks; the grid is sized for the small blocks.
+constexpr int64_t kDepthSmallMax = 512 * 1024;
+template <int ITEMS>
+struct DepthRegime {
+    static constexpr int items = ITEMS;
+    static constexpr int64_t chunk = (int64_t)ITEMS * kSortThreads;
+    static constexpr int group = ITEMS == 4 ? 16 : 32;  // blocks per group sum
+};
+using DepthSmall = DepthRegime<4>;
+using DepthLarge = DepthRegime<16>;
+static_assert(DepthLarge::chunk == kSortChunk, "LDS staging is sized for the large blocks");
+static_assert(kDepthSmallMax / DepthSmall::chunk <= 32 * DepthSmall::group,
+              "small regime: at most 32 group sums");
+
+template <class Rg>
+__device__ __forceinline__ void dhist_body(const uint32_t *keys, int64_t n, int shift,
+                                           uint32_t *hist, int64_t nb, uint32_t *gsum,
+                                           int64_t ngroups, uint32_t (*h)[256]) {
+    const int64_t b = blockIdx.x, base = b * Rg::chunk;
     if (base >= n) return;  // uniform
+    const int wid = threadIdx.x / kWave;
+    uint32_t k[Rg::items];
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < Rg::items; ++i) {
         const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
-        if (idx < n) atomicAdd(&h[wid][(keys[idx] >> shift) & 255u], 1u);
+        k[i] = idx < n ? keys[idx] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < Rg::items; ++i) {
+        const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&h[wid][(k[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
     const int d = threadIdx.x;
     uint32_t c = 0;
 #pragma unroll
     for (int w = 0; w < kSortThreads / kWave; ++w) c += h[w][d];
-    hist[(int64_t)d * nb + blockIdx.x] = c;
-    if (c) {
-        atomicAdd(gsum + (int64_t)d * ngroups + blockIdx.x / kDepthGroup, c);
-        atomicAdd(tot + d, c);
-    }
+    hist[(int64_t)d * nb + b] = c;
+    if (c) atomicAdd(gsum + (int64_t)d * ngroups + b / Rg::group, c);
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_dscatter(const uint32_t *kin, const uint32_t *vin,
-                                                           uint32_t *kout, uint32_t *vout,
-                                                           const int64_t *count, int shift,
-                                                           const uint32_t *hist, int64_t nb,
-                                                           const uint32_t *gsum, int64_t ngroups,
-                                                           const uint32_t *tot) {
-    __shared__ RankSmem sm;
-    __shared__ uint32_t skey[kSortChunk];
-    __shared__ uint32_t sval[kSortChunk];
-    __shared__ uint32_t s_wt[kSortThreads / kWave];
-    rank_init(sm);
+__global__ __launch_bounds__(kSortThreads) void k_dhist(const uint32_t *keys, const int64_t *count,
+                                                        int shift, uint32_t *hist, int64_t nb,
+                                                        uint32_t *gsum, int64_t ngroups) {
+    __shared__ uint32_t h[kSortThreads / kWave][256];
+    for (int i = threadIdx.x; i < (kSortThreads / kWave) * 256; i += kSortThreads) (&h[0][0])[i] = 0;
+    __syncthreads();
     const int64_t n = *count;
-    const int64_t b = blockIdx.x;
-    const int64_t base = b * kSortChunk;
+    if (n <= kDepthSmallMax)
+        dhist_body<DepthSmall>(keys, n, shift, hist, nb, gsum, ngroups, h);
+    else
+        dhist_body<DepthLarge>(keys, n, shift, hist, nb, gsum, ngroups, h);
+}
+
+template <class Rg>
+__device__ __forceinline__ void dscatter_body(const uint32_t *kin, const uint32_t *vin,
+                                              uint32_t *kout, uint32_t *vout, int64_t n, int shift,
+                                              const uint32_t *hist, int64_t nb, const uint32_t *gsum,
+                                              int64_t ngroups, RankSmem &sm, uint32_t *skey,
+                                              uint32_t *sval, uint32_t *s_wt) {
+    const int64_t b = blockIdx.x, base = b * Rg::chunk;
     if (base >= n) return;  // uniform
-    // the chunk's keys, the digit totals and this block's earlier counts are
-    // all requested before any of them is used (one round trip, mostly to
-    // other XCDs' writes)
-    const int cnt = (int)(n - base < kSortChunk ? n - base : kSortChunk);
-    uint32_t key[kSortItems], val[kSortItems];
+    // the chunk's keys and this digit's counts are all requested before any
+    // of them is used (one round trip, mostly to other XCDs' writes)
+    const int cnt = (int)(n - base < Rg::chunk ? n - base : Rg::chunk);
+    uint32_t key[Rg::items], val[Rg::items];
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-        const int p = rank_pos(i);
+    for (int i = 0; i < Rg::items; ++i) {
+        const int p = rank_pos<Rg::items>(i);
         key[i] = p < cnt ? kin[base + p] : 0u;
         val[i] = p < cnt ? vin[base + p] : 0u;
     }
     const int d = threadIdx.x;
-    const int64_t g = b / kDepthGroup;
-    const uint32_t t = tot[d];
-    uint32_t pre = 0;
-    const uint32_t *hrow = hist + (int64_t)d * nb + g * kDepthGroup;
-    const int in_group = (int)(b - g * kDepthGroup);
-#pragma unroll
-    for (int i = 0; i < kDepthGroup - 1; ++i) pre += i < in_group ? hrow[i] : 0u;
+    const int64_t live = (n + Rg::chunk - 1) / Rg::chunk;
+    const int64_t lg = (live + Rg::group - 1) / Rg::group, g = b / Rg::group;
+    const int in_group = (int)(b - g * Rg::group);
+    const uint32_t *hrow = hist + (int64_t)d * nb + g * Rg::group;
     const uint32_t *grow = gsum + (int64_t)d * ngroups;
-    for (int64_t i0 = 0; i0 < g; i0 += 8) {
+    uint32_t pre = 0, t = 0;
+    constexpr int kBatch = Rg::items == DepthSmall::items ? 32 : 16;
+    for (int64_t i0 = 0; i0 < lg; i0 += kBatch) {  // one batch in the small regime
+        uint32_t c[kBatch], e[Rg::group - 1];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) pre += i0 + i < g ? grow[i0 + i] : 0u;
+        for (int i = 0; i < kBatch; ++i) c[i] = i0 + i < lg ? grow[i0 + i] : 0u;
+        if (i0 == 0) {
+#pragma unroll
+            for (int i = 0; i < Rg::group - 1; ++i) e[i] = i < in_group ? hrow[i] : 0u;
+#pragma unroll
+            for (int i = 0; i < Rg::group - 1; ++i) pre += e[i];
+        }
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            t += c[i];
+            pre += i0 + i < g ? c[i] : 0u;
+        }
     }
     uint32_t all;
     sm.gbase[d] = block_exclusive_scan<kSortThreads, uint32_t>(t, s_wt, &all) + pre;
     __syncthreads();
-    rank_stage_write(
+    rank_stage_write<Rg::items>(
         key, val, cnt, shift, sm, skey, sval, [](uint32_t, uint32_t v) { return v; },
         [&](int64_t dst, uint32_t k, uint32_t v) {
             kout[dst] = k;
@@ -298,17 +333,41 @@ __global__ __launch_bounds__(kSortThreads) void k_dscatter(const uint32_t *kin, 
         });
 }
 
+__global__ __launch_bounds__(kSortThreads) void k_dscatter(const uint32_t *kin, const uint32_t *vin,
+                                                           uint32_t *kout, uint32_t *vout,
+                                                           const int64_t *count, int shift,
+                                                           const uint32_t *hist, int64_t nb,
+                                                           const uint32_t *gsum, int64_t ngroups) {
+    __shared__ RankSmem sm;
+    __shared__ uint32_t skey[kSortChunk];
+    __shared__ uint32_t sval[kSortChunk];
+    __shared__ uint32_t s_wt[kSortThreads / kWave];
+    rank_init(sm);
+    const int64_t n = *count;
+    if (n <= kDepthSmallMax)
+        dscatter_body<DepthSmall>(kin, vin, kout, vout, n, shift, hist, nb, gsum, ngroups, sm, skey,
+                                  sval, s_wt);
+    else
+        dscatter_body<DepthLarge>(kin, vin, kout, vout, n, shift, hist, nb, gsum, ngroups, sm, skey,
+                                  sval, s_wt);
+}
+
+int64_t depth_pass_blocks(int64_t n) { return n > 0 ? (n + DepthSmall::chunk - 1) / DepthSmall::chunk : 1; }
+int64_t depth_pass_groups(int64_t n) {
+    return (depth_pass_blocks(n) + DepthSmall::group - 1) / DepthSmall::group;
+}
+
 hipError_t depth_sort(const Workspace &ws, const int64_t *count, hipStream_t s) {
     // 0 -> 2 -> 1 -> 2 -> 1: the fourth pass lands in buffer 1
     const int src[4] = {0, 2, 1, 2}, dst[4] = {2, 1, 2, 1};
-    const unsigned nb = (unsigned)ws.nb_dsort;
+    const unsigned nb = (unsigned)ws.nb_dpass;
     for (int p = 0; p < 4; ++p) {
-        uint32_t *gsum = ws.dgsum + (int64_t)p * 256 * ws.nb_dgroups, *tot = ws.dtot + 256 * p;
-        k_dhist<<<nb, kSortThreads, 0, s>>>(ws.dkey[src[p]], count, 8 * p, ws.dhist, ws.nb_dsort, gsum,
-                                           ws.nb_dgroups, tot);
+        uint32_t *gsum = ws.dgsum + (int64_t)p * 256 * ws.nb_dgroups;
+        k_dhist<<<nb, kSortThreads, 0, s>>>(ws.dkey[src[p]], count, 8 * p, ws.dhist, ws.nb_dpass, gsum,
+                                           ws.nb_dgroups);
         k_dscatter<<<nb, kSortThreads, 0, s>>>(ws.dkey[src[p]], ws.dval[src[p]], ws.dkey[dst[p]],
-                                              ws.dval[dst[p]], count, 8 * p, ws.dhist, ws.nb_dsort,
-                                              gsum, ws.nb_dgroups, tot);
+                                              ws.dval[dst[p]], count, 8 * p, ws.dhist, ws.nb_dpass,
+                                              gsum, ws.nb_dgroups);
     }
     return hipGetLastError();
 }
