@@ -141,7 +141,7 @@ void fill_preprocess_args(const gs_scene *scene, const gs_mode *mode, gsr::Prepr
     a->K = mode->K;
     a->lut_depth_max = mode->lut_depth_max;
     a->Kf = mode->K;
-    a->lut_depth_maxf = mode->lut_depth_max;
+    a->lut_scalef = (float)((double)GS_LUT_BINS / (double)mode->lut_depth_max);
     for (int i = 0; i < GS_LUT_BINS; ++i) a->lut[i] = mode->t_upper[i];
     sh_constants(a->shc);
     for (int i = 0; i < 16; ++i) a->shcf[i] = (float)a->shc[i];

@@ -107,12 +107,6 @@ __global__ __launch_bounds__(256) void k_vis_compact(const uint32_t *tiles_touch
     if (threadIdx.x == 0 && b == (int64_t)gridDim.x - 1) *num_vis = (int64_t)(before + tot);
 }
 
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Inclusive prefix sum over the wave in DPP lane moves, no LDS round trip:
 // shifts by 1, 2, 4 and 8 lanes inside each row of 16 lanes (lanes shifted in
 // from outside the row read 0), then lane 15's sum added to row 1 and lane

@@ -25,7 +25,7 @@ struct PreprocessArgs {
     double K, lut_depth_max;
     float lut[kLutBins];
     // float32 copies for the preprocess' float32 prefilter (proves culls)
-    float Rf[9], tf[3], fxf, fyf, cxf, cyf, limxf, limyf, Kf, lut_depth_maxf;
+    float Rf[9], tf[3], fxf, fyf, cxf, cyf, limxf, limyf, Kf, lut_scalef;  // lut_scalef = 20 / D_max
     double shc[16];  // real-SH normalisation constants, see preprocess.hip
     float shcf[16];  // the same, rounded to float32 (colour is evaluated in float32)
     float *splats;
@@ -264,6 +264,13 @@ __host__ __device__ __forceinline__ size_t plane_at(int k, int n, int g) {
 // An empty asm that claims to modify x: the value must exist in a register at
 // this point, so the compiler neither sinks its computation nor recomputes it.
 __device__ __forceinline__ void pin_vgpr(float &x) { __asm__ volatile("" : "+v"(x)); }
+
+// The wave's LDS writes before this point are visible to its reads after it.
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }

@@ -7,17 +7,54 @@
 
 namespace gsr {
 
+// Hardware approximations on the device (reciprocal and square root within
+// about one ulp, exponential through exp2 of the scaled argument); the
+// libm functions on the host, which are at least as accurate.
+__host__ __device__ __forceinline__ float gs_rcpf(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+__host__ __device__ __forceinline__ float gs_sqrtf(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
+__host__ __device__ __forceinline__ float gs_expf(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return __expf(x);
+#else
+    return expf(x);
+#endif
+}
+
 // Float32 proof that the preprocess' double-precision path gives a Gaussian
 // no tiles: true only when that is certain -- its depth is clearly behind the
 // near plane, or its determinant clearly not positive, or (AdaGScale) its Th
 // of eq. (10) clearly reaches its opacity, or a bound of its 3-sigma
 // rectangle lies clearly outside the image.  Every bound below majorises the
 // difference between the float32 value and the double path's value (U =
-// 2^-24; the double path's own rounding is far smaller than the slack); a
-// NaN or infinity anywhere makes every test false.
-__host__ __device__ __forceinline__ bool surely_no_tiles(const PreprocessArgs &a, float mx, float my, float mz,
-                                                float l0, float l1, float l2, float qw, float qx,
-                                                float qy, float qz, float op) {
+// 2^-24; hardware reciprocals, square roots and exponentials are charged a few
+// U, the exponential also its argument's rounding; the double path's own
+// rounding is far smaller than the slack); a NaN or infinity anywhere makes
+// every test false.  Two tiers share the first part:
+//   cheap: no rotation.  With M = J W Sigma3 W^T J^T (Sigma2 = M + 0.3 I),
+//     tr M <= ||J||_F^2 lambda_1 and det M <= det(J J^T) lambda_1 lambda_2
+//     (the compression of Sigma3 to a plane has eigenvalues at most its two
+//     largest, lambda_i = s_i^2 sorted, by interlacing), and det Sigma2 =
+//     det M + 0.3 tr M + 0.09 <= (tr Sigma2 / 2)^2.
+//   full: Sigma3 from the rotation, Sigma2 and its determinant with bounds.
+// lut: the T_up table (kLutBins floats).  Returns 0 when undecided, else the
+// tier that proved it (1 cheap, 2 full); TIERS = 1 runs the cheap tier alone.
+template <int TIERS = 2>
+__host__ __device__ __forceinline__ int surely_no_tiles(const PreprocessArgs &a, const float *lut,
+                                                        float mx, float my, float mz, float l0,
+                                                        float l1, float l2, float qw, float qx,
+                                                        float qy, float qz, float op) {
     constexpr float U = 5.9604645e-8f;
     const float *W = a.Rf, *t = a.tf;
     // camera-space position; e: absolute error bounds (the camera's float32
@@ -30,20 +67,79 @@ __host__ __device__ __forceinline__ bool surely_no_tiles(const PreprocessArgs &a
         e[i] = 16.0f * U * (((fabsf(x0) + fabsf(x1)) + fabsf(x2)) + fabsf(t[i]));
     }
     const float pz = p[2], ez = e[2];
-    if (pz + ez < 0.19999f) return true;  // near cull: the double path needs pz > 0.2
-    if (!(pz - ez > 0.2f)) return false;  // too close to the near plane to tell
+    if (pz + ez < 0.19999f) return 1;  // near cull: the double path needs pz > 0.2
+    if (!(pz - ez > 0.2f)) return 0;   // too close to the near plane to tell
     const float pzl = pz - ez;
-    if (!(fabsf(l0) < 60.0f && fabsf(l1) < 60.0f && fabsf(l2) < 60.0f)) return false;
-    const float qn = qw * qw + qx * qx + qy * qy + qz * qz;
-    if (!(qn > 1e-30f && qn < 1e30f)) return false;  // the double path normalises any qn > 0
+    if (!(fabsf(l0) < 40.0f && fabsf(l1) < 40.0f && fabsf(l2) < 40.0f)) return 0;
     // projected mean (double path: u = fx px / pz + cx) and its error
-    const float rz = 1.0f / pz;
+    const float rz = gs_rcpf(pz), rzl = gs_rcpf(pzl) * (1.0f + 4.0f * U);
     const float txz = p[0] * rz, tyz = p[1] * rz;
-    const float etx = (e[0] + fabsf(txz) * ez) / pzl + 4.0f * U * fabsf(txz);
-    const float ety = (e[1] + fabsf(tyz) * ez) / pzl + 4.0f * U * fabsf(tyz);
+    const float etx = (e[0] + fabsf(txz) * ez) * rzl + 8.0f * U * fabsf(txz);
+    const float ety = (e[1] + fabsf(tyz) * ez) * rzl + 8.0f * U * fabsf(tyz);
     const float u = a.fxf * txz + a.cxf, v = a.fyf * tyz + a.cyf;
     const float eu = a.fxf * etx + 8.0f * U * (fabsf(a.fxf * txz) + fabsf(a.cxf));
     const float ev = a.fyf * ety + 8.0f * U * (fabsf(a.fyf * tyz) + fabsf(a.cyf));
+    // Jacobian rows at the clamped point: (j00, 0, j02), (0, j11, j12), with
+    // j02 = -j00 clamp(x / z) (the double path's -fx xc / z^2); d0, d1 bound
+    // each row's error relative to j00, j11 (pz's and the ratios' errors)
+    const float lx = a.limxf, ly = a.limyf;
+    const float cxz = fminf(fmaxf(txz, -lx), lx), cyz = fminf(fmaxf(tyz, -ly), ly);
+    const float j00 = a.fxf * rz, j11 = a.fyf * rz;
+    const float dz = ez * rzl + 8.0f * U;
+    const float d0 = dz * (1.0f + lx) + etx + 8.0f * U * (1.0f + lx);
+    const float d1 = dz * (1.0f + ly) + ety + 8.0f * U * (1.0f + ly);
+    // opacity from above, and the largest T_up over the depth bins pz may fall in
+    float sig_hi = 0.0f, tu = 1.0f;
+    bool ada = a.adagscale != 0;
+    if (ada) {
+        const float eo = gs_expf(-op);
+        // exp(-op) to (2 |op| + 4) U (exp2 of the rounded scaled argument),
+        // the reciprocal and the sum a few U more
+        sig_hi = gs_rcpf(1.0f + eo) * (1.0f + (2.5f * fminf(fabsf(op), 200.0f) + 24.0f) * U);
+        const float f_lo = (pzl * a.lut_scalef) * (1.0f - 8.0f * U);
+        const float f_hi = ((pz + ez) * a.lut_scalef) * (1.0f + 8.0f * U);
+        const int b_lo = f_lo >= (float)(kLutBins - 1) ? kLutBins - 1 : (int)floorf(fmaxf(f_lo, 0.0f));
+        const int b_hi = f_hi >= (float)(kLutBins - 1) ? kLutBins - 1 : (int)floorf(fmaxf(f_hi, 0.0f));
+        if (b_hi - b_lo <= 2) {
+            tu = 0.0f;
+            for (int b = b_lo; b <= b_hi; ++b) tu = fmaxf(tu, lut[b]);
+            if (!(tu > 0.0f)) return 1;  // every possible bin drops it
+        } else {
+            ada = false;  // pz too uncertain to pick the bin: no AdaGScale test
+        }
+    }
+    const float X = 16.0f * (float)a.tiles_x, Y = 16.0f * (float)a.tiles_y;
+    {   // cheap tier
+        const float lmax = fmaxf(fmaxf(l0, l1), l2);
+        const float lmid = fmaxf(fminf(l0, l1), fminf(fmaxf(l0, l1), l2));  // the median, exactly
+        // |2 lmax| < 80 (exact doubling): exp to 2 * 80 + 4 U; |2 (lmax +
+        // lmid)| < 160 plus the sum's rounding (80 U in the argument)
+        const float lam1 = gs_expf(2.0f * lmax) * (1.0f + 200.0f * U);
+        const float lam12 = gs_expf(2.0f * (lmax + lmid)) * (1.0f + 600.0f * U);
+        const float FJ = 1.0f + 4.0f * (d0 + d1) * (1.0f + lx + ly) + 64.0f * U;
+        const float c2 = cxz * cxz, d2 = cyz * cyz;
+        const float jr = (j00 * j00) * (1.0f + c2) + (j11 * j11) * (1.0f + d2);  // ||J||_F^2
+        const float jd = (j00 * j11) * (j00 * j11) * ((1.0f + c2) + d2);       // det(J J^T)
+        const float trM = jr * lam1 * FJ;
+        const float detM = jd * lam12 * (FJ * FJ);
+        const float tr_hi = trM + 0.6f * (1.0f + 4.0f * U);
+        if (ada) {
+            const float det_hi = fminf((0.5f * tr_hi) * (0.5f * tr_hi), (detM + 0.3f * trM) + 0.09f) *
+                                 (1.0f + 16.0f * U);
+            const float den = (tu * 6.2831855f) * gs_sqrtf(det_hi) * (1.0f + 16.0f * U);
+            const float th_lo = (a.Kf * gs_rcpf(den)) * (1.0f - 8.0f * U) + 0.0039215642f;
+            if (th_lo >= sig_hi) return 1;
+        }
+        const float r_hi = 3.0f * gs_sqrtf(tr_hi + 0.02f) * (1.0f + 8.0f * U) + 1.0f;
+        const float sx = 8.0f * U * (fabsf(u) + eu + r_hi + X) + 1e-3f;
+        const float sy = 8.0f * U * (fabsf(v) + ev + r_hi + Y) + 1e-3f;
+        if (u + eu + r_hi + sx < 1.0f || u - eu - r_hi - sx >= X) return 1;
+        if (v + ev + r_hi + sy < 1.0f || v - ev - r_hi - sy >= Y) return 1;
+    }
+    if (TIERS == 1) return 0;
+    // full tier
+    const float qn = qw * qw + qx * qx + qy * qy + qz * qz;
+    if (!(qn > 1e-30f && qn < 1e30f)) return 0;  // the double path normalises any qn > 0
     // Sigma3 = M M^T, M = R(q) diag(s); every entry is at most S2 = tr Sigma3
     // in magnitude and within 40 U S2 of the double path's
     const float s0 = expf(l0), s1 = expf(l1), s2 = expf(l2);
@@ -62,16 +158,7 @@ __host__ __device__ __forceinline__ bool surely_no_tiles(const PreprocessArgs &a
     const float c00 = m00 * m00 + m01 * m01 + m02 * m02, c01 = m00 * m10 + m01 * m11 + m02 * m12,
                 c02 = m00 * m20 + m01 * m21 + m02 * m22, c11 = m10 * m10 + m11 * m11 + m12 * m12,
                 c12 = m10 * m20 + m11 * m21 + m12 * m22, c22 = m20 * m20 + m21 * m21 + m22 * m22;
-    // Jacobian rows at the clamped point: (j00, 0, j02), (0, j11, j12), with
-    // j02 = -j00 clamp(x / z) (the double path's -fx xc / z^2); d0, d1 bound
-    // each row's error relative to j00, j11 (pz's and the ratios' errors)
-    const float lx = a.limxf, ly = a.limyf;
-    const float cxz = fminf(fmaxf(txz, -lx), lx), cyz = fminf(fmaxf(tyz, -ly), ly);
-    const float j00 = a.fxf * rz, j11 = a.fyf * rz;
     const float j02 = -j00 * cxz, j12 = -j11 * cyz;
-    const float dz = ez / pzl + 4.0f * U;
-    const float d0 = dz * (1.0f + lx) + etx + 8.0f * U * (1.0f + lx);
-    const float d1 = dz * (1.0f + ly) + ety + 8.0f * U * (1.0f + ly);
     // T = J W: rows t0 = j00 W0 + j02 W2, t1 = j11 W1 + j12 W2; G_i bounds
     // sum_k |t_ik| and the errors sum_k |dt_ik| <= E_i = (d_i + 6U) G_i
     const float t00 = j00 * W[0] + j02 * W[6], t01 = j00 * W[1] + j02 * W[7], t02 = j00 * W[2] + j02 * W[8];
@@ -95,33 +182,20 @@ __host__ __device__ __forceinline__ bool surely_no_tiles(const PreprocessArgs &a
     // float32 expression's own rounding
     const float ah = ca + ea, ch = cc + ec, bl = fmaxf(fabsf(cb) - eb, 0.0f);
     const float det_hi = (ah * ch - bl * bl) + 4.0f * U * (ah * ch + bl * bl);
-    if (det_hi <= 0.0f) return true;  // the double path needs det > 0
-    if (a.adagscale) {
-        // Th >= K / (T_up,max 2 pi sqrt(det_hi)) + tau over the depth bins pz may
-        // fall in; the opacity sigma(op) from above
-        const float sig_hi = (1.0f / (1.0f + expf(-op))) * (1.0f + 16.0f * U);
-        const float f_lo = (pzl * (float)kLutBins / a.lut_depth_maxf) * (1.0f - 8.0f * U);
-        const float f_hi = ((pz + ez) * (float)kLutBins / a.lut_depth_maxf) * (1.0f + 8.0f * U);
-        const int b_lo = f_lo >= (float)(kLutBins - 1) ? kLutBins - 1 : (int)floorf(fmaxf(f_lo, 0.0f));
-        const int b_hi = f_hi >= (float)(kLutBins - 1) ? kLutBins - 1 : (int)floorf(fmaxf(f_hi, 0.0f));
-        if (b_hi - b_lo <= 2) {
-            float tu = 0.0f;
-            for (int b = b_lo; b <= b_hi; ++b) tu = fmaxf(tu, a.lut[b]);
-            if (!(tu > 0.0f)) return true;  // every possible bin drops it
-            const float den = (tu * 6.2831855f) * sqrtf(det_hi) * (1.0f + 8.0f * U);
-            const float th_lo = (a.Kf / den) * (1.0f - 8.0f * U) + 0.0039215642f;
-            if (th_lo >= sig_hi) return true;  // Th >= sigma: dropped (Sec. 3.3)
-        }
+    if (det_hi <= 0.0f) return 2;  // the double path needs det > 0
+    if (ada) {  // Th >= K / (T_up,max 2 pi sqrt(det_hi)) + tau
+        const float den = (tu * 6.2831855f) * sqrtf(det_hi) * (1.0f + 8.0f * U);
+        const float th_lo = (a.Kf / den) * (1.0f - 8.0f * U) + 0.0039215642f;
+        if (th_lo >= sig_hi) return 2;  // Th >= sigma: dropped (Sec. 3.3)
     }
     // the rectangle of any radius r <= ceil(3 sqrt(a + c + 0.3163)) is empty
     // when u + r < 1 or u - r >= 16 TX (and likewise in y)
     const float r_hi = 3.0f * sqrtf((ah + ch) + 0.32f) * (1.0f + 8.0f * U) + 1.0f;
-    const float X = 16.0f * (float)a.tiles_x, Y = 16.0f * (float)a.tiles_y;
     const float sx = 8.0f * U * (fabsf(u) + eu + r_hi + X) + 1e-3f;
     const float sy = 8.0f * U * (fabsf(v) + ev + r_hi + Y) + 1e-3f;
-    if (u + eu + r_hi + sx < 1.0f || u - eu - r_hi - sx >= X) return true;
-    if (v + ev + r_hi + sy < 1.0f || v - ev - r_hi - sy >= Y) return true;
-    return false;
+    if (u + eu + r_hi + sx < 1.0f || u - eu - r_hi - sx >= X) return 2;
+    if (v + ev + r_hi + sy < 1.0f || v - ev - r_hi - sy >= Y) return 2;
+    return 0;
 }
 
 }  // namespace gsr

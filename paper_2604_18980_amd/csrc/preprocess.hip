@@ -74,26 +74,16 @@ __device__ __forceinline__ void sh_eval(int degree, R x, R y, R z, const R *c, R
 }
 }  // namespace
 
-// The double-precision path for Gaussian g: every output of the stage.
+// The double-precision path for Gaussian g (parameters as loaded): every
+// output of the stage.
 template <int DEG>
-__device__ __forceinline__ void preprocess_exact(const PreprocessArgs &a, const int g) {
-    const int n = a.n;
+__device__ __forceinline__ void preprocess_exact(const PreprocessArgs &a, const int g, const float fmx,
+                                                 const float fmy, const float fmz, const float fl0,
+                                                 const float fl1, const float fl2, const float fqw,
+                                                 const float fqx, const float fqy, const float fqz,
+                                                 const float fop) {
     uint32_t tiles = 0;
     uint64_t rect = 0;
-
-    // Every per-Gaussian parameter is loaded at once (one memory round trip);
-    // the near cull below discards few Gaussians of a real view, so this
-    // fetches almost nothing the cull would have saved.
-    const float fmx = a.means[g], fmy = a.means[plane_at(1, n, g)], fmz = a.means[plane_at(2, n, g)];
-    float fl0 = a.log_scales[g], fl1 = a.log_scales[plane_at(1, n, g)],
-          fl2 = a.log_scales[plane_at(2, n, g)];
-    float fqw = a.quats[g], fqx = a.quats[plane_at(1, n, g)], fqy = a.quats[plane_at(2, n, g)],
-          fqz = a.quats[plane_at(3, n, g)];
-    float fop = a.opacity_logits[g];
-    // Pin the loads here: left alone, the compiler sinks them below the near
-    // cull, which costs a second dependent trip to memory.
-    pin_vgpr(fl0); pin_vgpr(fl1); pin_vgpr(fl2);
-    pin_vgpr(fqw); pin_vgpr(fqx); pin_vgpr(fqy); pin_vgpr(fqz); pin_vgpr(fop);
 
     // view transform: p = R mu + t
     const double mx = fmx, my = fmy, mz = fmz;
@@ -250,60 +240,196 @@ __device__ __forceinline__ void preprocess_exact(const PreprocessArgs &a, const 
     a.tiles_touched[g] = tiles;
 }
 
-constexpr int kPreRounds = 4;                  // Gaussians per thread in the float32 pass
-constexpr int kPreChunk = 256 * kPreRounds;    // Gaussians per block
+constexpr int kPreRounds = 2;                  // Gaussians per thread in the float32 pass
+constexpr int kPreChunk = 256 * kPreRounds;    // Gaussians per prefilter block and list
+constexpr int kPreSub = kPreChunk / kWave;     // 64-Gaussian chunks per list
 
-// DEG is the SH degree (0..3), a template parameter so the colour loads of all
-// (DEG+1)^2 x 3 coefficients are issued together rather than one per loop trip.
-// Each block takes kPreChunk consecutive Gaussians: the float32 prefilter
-// writes tiles_touched = 0 for those it drops and queues the rest in LDS;
-// then the block's threads run the double-precision path on the queue.
-template <int DEG>
-__global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a) {
-    __shared__ uint32_t queue[kPreChunk];
-    __shared__ uint32_t qn;
-    if (threadIdx.x == 0) qn = 0u;
+// List L holds the 64-Gaussian chunks c = L + k nlists (k = 0 .. kPreSub - 1,
+// those below the chunk count): spread over the whole index range, so each
+// list gets about the same share of the view's visible Gaussians however the
+// scene orders them, while each wave still loads 64 consecutive floats per
+// plane.  Slot i of a list is Gaussian i % 64 of its chunk k = i / 64; only
+// the scene's last chunk can be partial, and it is its list's last.
+__host__ __device__ __forceinline__ int64_t list_chunk(int64_t L, int k, int64_t nlists) {
+    return L + (int64_t)k * nlists;
+}
+
+// A queued Gaussian: its id and its eleven parameters, 48 bytes.
+struct PreEntry {
+    float4 a, b, c;  // (id bits, mean x, y, z), (log-scales, q w), (q x, y, z, opacity logit)
+};
+
+// Appends this lane's entry when keep (wave ballot, one LDS atomic per wave).
+__device__ __forceinline__ void queue_push(bool keep, const PreEntry &e, PreEntry *queue, uint32_t *qn) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t m = __ballot(keep);
+    if (m) {  // wave-uniform: lane 0 reserves the wave's slots
+        uint32_t old = 0u;
+        if (lane == 0) old = atomicAdd(qn, (uint32_t)__popcll(m));
+        const uint32_t wbase = (uint32_t)__builtin_amdgcn_readlane((int)old, 0);
+        if (keep) queue[wbase + (uint32_t)__popcll(m & lanemask_lt())] = e;
+    }
+}
+
+// The 48-byte splat record slot of list L's slot i (where its entries live).
+__device__ __forceinline__ float4 *list_slot(const PreprocessArgs &a, int64_t L, uint32_t i, int64_t nlists) {
+    const int64_t g = list_chunk(L, (int)(i / kWave), nlists) * kWave + (i % kWave);
+    return reinterpret_cast<float4 *>(a.splats + g * 12);
+}
+
+// Pass 1: the float32 prefilter over one list per block, each parameter
+// loaded once.  The cheap tier runs on every Gaussian; those it leaves
+// undecided are queued in LDS with their parameters and the full tier runs on
+// the queue (dense lanes), compacting it in place; a Gaussian either tier
+// drops gets tiles_touched = 0.  The rest (candidates) are written, id and
+// parameters, into the list's slots (the splat records of its own Gaussians,
+// 48 bytes each, so they hold all of them), and their count into the rects
+// entry of the list's first Gaussian; pass 2 reads a list in full before it
+// writes any output.
+__global__ __launch_bounds__(256) void k_prefilter(const PreprocessArgs a, int64_t nlists) {
+    __shared__ PreEntry q[kPreChunk];
+    __shared__ uint32_t n1, n2;
+    __shared__ float lut[kLutBins];
+    if (threadIdx.x == 0) n1 = n2 = 0u;
+    if (threadIdx.x < kLutBins) lut[threadIdx.x] = a.lut[threadIdx.x];
     __syncthreads();
     const int n = a.n;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t base = (int64_t)blockIdx.x * kPreChunk;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int64_t L = blockIdx.x;
+    // round r, wave w: chunk k = r * 4 + w; every round's parameters are
+    // requested before any is used
+    float f[kPreRounds][11];
+    int64_t gr[kPreRounds];
+#pragma unroll
     for (int r = 0; r < kPreRounds; ++r) {
-        const int64_t g64 = base + (int64_t)r * 256 + threadIdx.x;
-        bool cand = false;
+        gr[r] = list_chunk(L, r * 4 + wid, nlists) * kWave + lane;
+        const int g = gr[r] < n ? (int)gr[r] : 0;
+        f[r][0] = a.means[g]; f[r][1] = a.means[plane_at(1, n, g)]; f[r][2] = a.means[plane_at(2, n, g)];
+        f[r][3] = a.log_scales[g]; f[r][4] = a.log_scales[plane_at(1, n, g)];
+        f[r][5] = a.log_scales[plane_at(2, n, g)];
+        f[r][6] = a.quats[g]; f[r][7] = a.quats[plane_at(1, n, g)]; f[r][8] = a.quats[plane_at(2, n, g)];
+        f[r][9] = a.quats[plane_at(3, n, g)];
+        f[r][10] = a.opacity_logits[g];
+    }
+#pragma unroll
+    for (int r = 0; r < kPreRounds; ++r) {
+        const int64_t g64 = gr[r];
+        bool undecided = false;
         if (g64 < n) {
-            const int g = (int)g64;
-            const float mx = a.means[g], my = a.means[plane_at(1, n, g)], mz = a.means[plane_at(2, n, g)];
-            const float l0 = a.log_scales[g], l1 = a.log_scales[plane_at(1, n, g)],
-                        l2 = a.log_scales[plane_at(2, n, g)];
-            const float qw = a.quats[g], qx = a.quats[plane_at(1, n, g)], qy = a.quats[plane_at(2, n, g)],
-                        qz = a.quats[plane_at(3, n, g)];
-            const float op = a.opacity_logits[g];
-            if (surely_no_tiles(a, mx, my, mz, l0, l1, l2, qw, qx, qy, qz, op))
-                a.tiles_touched[g] = 0u;
+            if (surely_no_tiles<1>(a, lut, f[r][0], f[r][1], f[r][2], f[r][3], f[r][4], f[r][5], f[r][6],
+                                   f[r][7], f[r][8], f[r][9], f[r][10]))
+                a.tiles_touched[g64] = 0u;
             else
-                cand = true;
+                undecided = true;
         }
-        const uint64_t m = __ballot(cand);
-        if (m) {  // wave-uniform: every lane joins the atomic, lane 0 adding the count
-            const uint32_t old = atomicAdd(&qn, lane == 0 ? (uint32_t)__popcll(m) : 0u);
-            const uint32_t wbase = (uint32_t)__builtin_amdgcn_readlane((int)old, 0);
-            if (cand) queue[wbase + (uint32_t)__popcll(m & lanemask_lt())] = (uint32_t)(base + r * 256 + threadIdx.x);
-        }
+        const PreEntry e{make_float4(__uint_as_float((uint32_t)g64), f[r][0], f[r][1], f[r][2]),
+                         make_float4(f[r][3], f[r][4], f[r][5], f[r][6]),
+                         make_float4(f[r][7], f[r][8], f[r][9], f[r][10])};
+        queue_push(undecided, e, q, &n1);
     }
     __syncthreads();
-    const uint32_t nq = qn;
-    for (uint32_t i = threadIdx.x; i < nq; i += 256) preprocess_exact<DEG>(a, (int)queue[i]);
+    const uint32_t c1 = n1;
+    for (uint32_t i0 = 0; i0 < c1; i0 += 256) {  // block-uniform
+        const uint32_t i = i0 + threadIdx.x;
+        bool keep = false;
+        PreEntry e{};
+        if (i < c1) {
+            e = q[i];
+            const uint32_t g = __float_as_uint(e.a.x);
+            if (surely_no_tiles<2>(a, lut, e.a.y, e.a.z, e.a.w, e.b.x, e.b.y, e.b.z, e.b.w, e.c.x, e.c.y,
+                                   e.c.z, e.c.w))
+                a.tiles_touched[g] = 0u;
+            else
+                keep = true;
+        }
+        // compaction in place: this round's kept entries land below i0 + 256,
+        // after every entry of the round has been read
+        __syncthreads();
+        queue_push(keep, e, q, &n2);
+        __syncthreads();
+    }
+    const uint32_t cnt = n2;
+    for (uint32_t i = threadIdx.x; i < cnt; i += 256) {
+        float4 *o = list_slot(a, L, i, nlists);
+        o[0] = q[i].a;
+        o[1] = q[i].b;
+        o[2] = q[i].c;
+    }
+    if (threadIdx.x == 0) reinterpret_cast<uint32_t *>(a.rects + L * kWave)[0] = cnt;
+}
+
+// Pass 2: the double-precision path over kListsPerBlock consecutive
+// prefilter lists per block.  A list is copied to LDS in full (every load has
+// returned at the barrier) before any output overwrites it.  When the lists'
+// candidates fit the LDS queue together (the common case: few Gaussians of a
+// view get tiles, and the lists share them evenly) they are staged at once and
+// run as one dense set; otherwise list by list.
+constexpr int kListsPerBlock = 16;
+
+template <int DEG>
+__device__ __forceinline__ void run_staged(const PreprocessArgs &a, const PreEntry *q, uint32_t cnt) {
+    for (uint32_t i = threadIdx.x; i < cnt; i += 256) {
+        const PreEntry e = q[i];
+        preprocess_exact<DEG>(a, (int)__float_as_uint(e.a.x), e.a.y, e.a.z, e.a.w, e.b.x, e.b.y, e.b.z,
+                              e.b.w, e.c.x, e.c.y, e.c.z, e.c.w);
+    }
+}
+
+__device__ __forceinline__ void stage_list(const PreprocessArgs &a, int64_t L, uint32_t cnt, int64_t nlists,
+                                           PreEntry *dst) {
+    for (uint32_t i = threadIdx.x; i < cnt; i += 256) {
+        const float4 *in = list_slot(a, L, i, nlists);
+        dst[i] = PreEntry{in[0], in[1], in[2]};
+    }
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a, int64_t nlists) {
+    __shared__ PreEntry q[kPreChunk];
+    __shared__ uint32_t s_cnt[kListsPerBlock], s_off[kListsPerBlock + 1];
+    const int64_t L0 = (int64_t)blockIdx.x * kListsPerBlock;
+    if (threadIdx.x < kListsPerBlock) {
+        const int64_t L = L0 + threadIdx.x;
+        s_cnt[threadIdx.x] = L < nlists ? reinterpret_cast<const uint32_t *>(a.rects + L * kWave)[0] : 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int l = 0; l < kListsPerBlock; ++l) {
+            s_off[l] = acc;
+            acc += s_cnt[l];
+        }
+        s_off[kListsPerBlock] = acc;
+    }
+    __syncthreads();
+    const uint32_t total = s_off[kListsPerBlock];
+    if (total <= (uint32_t)kPreChunk) {  // block-uniform
+        for (int l = 0; l < kListsPerBlock; ++l)
+            if (s_cnt[l]) stage_list(a, L0 + l, s_cnt[l], nlists, q + s_off[l]);
+        __syncthreads();
+        run_staged<DEG>(a, q, total);
+    } else {
+        for (int l = 0; l < kListsPerBlock; ++l) {
+            if (!s_cnt[l]) continue;  // block-uniform
+            stage_list(a, L0 + l, s_cnt[l], nlists, q);
+            __syncthreads();
+            run_staged<DEG>(a, q, s_cnt[l]);
+            __syncthreads();
+        }
+    }
 }
 
 hipError_t launch_preprocess(const PreprocessArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    const int threads = 256;
-    const int blocks = (a.n + kPreChunk - 1) / kPreChunk;
+    const int64_t nchunks = ((int64_t)a.n + kWave - 1) / kWave;
+    const int64_t nlists = (nchunks + kPreSub - 1) / kPreSub;
+    const unsigned blocks = (unsigned)((nlists + kListsPerBlock - 1) / kListsPerBlock);
+    k_prefilter<<<(unsigned)nlists, 256, 0, s>>>(a, nlists);
     switch (a.sh_degree) {
-        case 0: k_preprocess<0><<<blocks, threads, 0, s>>>(a); break;
-        case 1: k_preprocess<1><<<blocks, threads, 0, s>>>(a); break;
-        case 2: k_preprocess<2><<<blocks, threads, 0, s>>>(a); break;
-        default: k_preprocess<3><<<blocks, threads, 0, s>>>(a); break;
+        case 0: k_preprocess<0><<<blocks, 256, 0, s>>>(a, nlists); break;
+        case 1: k_preprocess<1><<<blocks, 256, 0, s>>>(a, nlists); break;
+        case 2: k_preprocess<2><<<blocks, 256, 0, s>>>(a, nlists); break;
+        default: k_preprocess<3><<<blocks, 256, 0, s>>>(a, nlists); break;
     }
     return hipGetLastError();
 }

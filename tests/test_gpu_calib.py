@@ -103,3 +103,25 @@ def test_calibrated_table_in_adagscale(O):
     np.testing.assert_array_equal(tt.astype(np.int64), pre.tiles_touched.astype(np.int64))
     live = pre.tiles_touched > 0
     np.testing.assert_array_equal(dec[live].astype(np.int64), pre.rect[live].astype(np.int64))
+
+
+def test_search_k_meets_target():
+    """Sec. 3.4's offline K search on calibration views: the returned K keeps
+    the mean PSNR(AdaGScale vs plain) over the views at or above the target,
+    and a K four times larger falls below it (the search stopped near the
+    boundary, not at a trivially small K)."""
+    import torch
+    from paper_2604_18980_amd import calib, render as R
+    sc, _ = scenes.mid_scene(n=40_000, seed=8, width=640, height=360)
+    cams = scenes.mid_calibration_cameras(4, width=640, height=360)
+    ds = R.DeviceScene.from_host(sc)
+    target = 36.0
+    for rule in (0, 1):
+        K, p = calib.search_k(ds, cams, target, lo=1e-3, hi=1e3, iters=12, extent_rule=rule)
+        torch.cuda.synchronize()
+        print(f"  rule {rule}: K {K:.4g}, mean PSNR {p:.2f} dB", flush=True)
+        assert p >= target
+        refs = [R.render(ds, c, slack=1.05).image.clone() for c in cams]
+        worse = [calib.psnr(R.render(ds, c, adagscale=True, K=4 * K, extent_rule=rule,
+                                     slack=1.2).image, r) for c, r in zip(cams, refs)]
+        assert float(np.mean(worse)) < target

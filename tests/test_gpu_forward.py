@@ -161,9 +161,13 @@ def test_deterministic(O):
     sc, cam = scenes.tiny_scene(seed=12)
     a = gpu_frame(sc, cam, dict(adagscale=True, K=0.2))
     b = gpu_frame(sc, cam, dict(adagscale=True, K=0.2))
-    for k in ("splats", "pair_tiles", "pair_gids", "sorted_gids", "ranges", "image", "final_T",
+    for k in ("tiles", "pair_tiles", "pair_gids", "sorted_gids", "ranges", "image", "final_T",
               "n_contrib"):
         np.testing.assert_array_equal(a[k], b[k])
+    # records and rectangles are specified for the Gaussians with tiles
+    vis = a["tiles"] > 0
+    np.testing.assert_array_equal(a["splats"][vis], b["splats"][vis])
+    np.testing.assert_array_equal(a["rects"][vis], b["rects"][vis])
 
 
 def test_adagscale_subset_on_gpu(O):

@@ -23,7 +23,7 @@ PROG = r'''
 // stdin: n, then camera viewmat[12] fx fy cx cy (float32), width height
 // (int32), adagscale (int32), K, lut_depth_max (float32), lut[20] (float32),
 // then means [3][n], log_scales [3][n], quats [4][n], opacity_logits [n]
-// (float32); stdout: one byte per Gaussian, 1 where the prefilter drops it.
+// (float32); stdout: one byte per Gaussian, the tier that drops it (0: kept).
 int main() {
     long long n;
     float cam[16], K, dmax, lut[20];
@@ -49,13 +49,13 @@ int main() {
     a.tiles_y = (wh[1] + 15) / 16;
     a.adagscale = ada;
     a.Kf = K;
-    a.lut_depth_maxf = dmax;
+    a.lut_scalef = (float)(20.0 / (double)dmax);
     for (int i = 0; i < 20; ++i) a.lut[i] = lut[i];
     std::vector<unsigned char> out((size_t)n);
     const float *m = d.data(), *l = m + 3 * n, *q = l + 3 * n, *o = q + 4 * n;
     for (long long g = 0; g < n; ++g)
-        out[g] = gsr::surely_no_tiles(a, m[g], m[n + g], m[2 * n + g], l[g], l[n + g], l[2 * n + g],
-                                      q[g], q[n + g], q[2 * n + g], q[3 * n + g], o[g]) ? 1 : 0;
+        out[g] = gsr::surely_no_tiles(a, a.lut, m[g], m[n + g], m[2 * n + g], l[g], l[n + g], l[2 * n + g],
+                                      q[g], q[n + g], q[2 * n + g], q[3 * n + g], o[g]);
     fwrite(out.data(), 1, out.size(), stdout);
     return 0;
 }
@@ -88,12 +88,13 @@ def prefilter(tmp_path_factory):
                         np.ascontiguousarray(sc.opacity_logits, np.float32).tobytes()])
         r = subprocess.run([str(exe)], input=buf, capture_output=True)
         assert r.returncode == 0, r.stderr
-        return np.frombuffer(r.stdout, np.uint8).astype(bool)
+        return np.frombuffer(r.stdout, np.uint8)
     return run
 
 
 def _check(O, run, sc, cam, **mode):
-    drop = run(sc, cam, **mode)
+    tier = run(sc, cam, **mode)
+    drop = tier > 0
     om = O.Mode(adagscale=mode.get("adagscale", False), K=mode.get("K", 0.0),
                 t_upper=mode.get("lut"), lut_depth_max=mode.get("dmax", 100.0),
                 extent_rule=mode.get("extent_rule", 0))
@@ -102,7 +103,8 @@ def _check(O, run, sc, cam, **mode):
     bad = np.nonzero(drop & ~none)[0]
     assert bad.size == 0, f"prefilter dropped {bad.size} Gaussians with tiles, e.g. {bad[:5]}"
     frac = drop.sum() / max(int(none.sum()), 1)
-    print(f"  dropped {int(drop.sum())} of {int(none.sum())} tile-less ({frac:.3f}), n={sc.n}")
+    print(f"  dropped {int(drop.sum())} of {int(none.sum())} tile-less ({frac:.3f}; cheap tier "
+          f"{int((tier == 1).sum())}), n={sc.n}")
     return frac
 
 
