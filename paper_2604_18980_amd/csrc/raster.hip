@@ -20,7 +20,9 @@
 //   uniform-address (broadcast) LDS read per 16 bytes -- the next record's
 //   read overlapping the current evaluation -- and evaluates only the hit
 //   strips.  A skipped strip has alpha < tau at every pixel, so results are
-//   unchanged.  No barriers: waves run and retire independently.
+//   unchanged.  A strip whose last live pixel stops leaves the batch's hit
+//   masks at once (its remaining hits would only evaluate stopped pixels).
+//   No barriers: waves run and retire independently.
 #include "gsr_internal.hpp"
 #include "raster_cull.hpp"
 
@@ -240,47 +242,54 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
                 // rounded product, so e2 is the same as without the offset; a
                 // stopped pixel gets -inf and fails the test below
                 const float e2 = fmaf(sA2 * u, u, fmaf(sG2 * dy, dy, off[k]));
-                // live pixel and opacity * 2^e2 >= tau, decided on the exponent
-                // so the exponential is only taken where it is used
-                if (e2 >= selim) {
-                    float alpha = fminf(kAlphaMaxF, ssig * __builtin_amdgcn_exp2f(e2));
-                    bool skip = false;
-                    if (MODE == 4) {
-                        // contribution below theta: blend nothing (alpha 0 leaves
-                        // T, the colour and the stop test untouched)
-                        skip = alpha * (a.skip_kind == 0 ? T[k] : swt) < a.skip_theta;
-                        alpha = skip ? 0.0f : alpha;
-                        w_skipped += skip ? 1u : 0u;
+                // live pixel and opacity * 2^e2 >= tau, decided on the exponent;
+                // a strip where no lane blends is skipped (wave-uniform), the
+                // other lanes of a blending strip take alpha = 0 (no change)
+                const bool bl = e2 >= selim;
+                if (__ballot(bl) == 0ull) continue;
+                float alpha = bl ? fminf(kAlphaMaxF, ssig * __builtin_amdgcn_exp2f(e2)) : 0.0f;
+                bool skip = false;
+                if (MODE == 4) {
+                    // contribution below theta: blend nothing (alpha 0 leaves
+                    // T, the colour and the stop test untouched)
+                    skip = bl && alpha * (a.skip_kind == 0 ? T[k] : swt) < a.skip_theta;
+                    alpha = skip ? 0.0f : alpha;
+                    w_skipped += skip ? 1u : 0u;
+                }
+                const float wa = alpha * T[k];
+                const float Tn = T[k] - wa;  // T (1 - alpha)
+                if (MODE == 3 && bl && !(Tn < kStopF)) tmax = fmaxf(tmax, T[k]);
+                float w = wa, Tk = Tn;
+                uint32_t lk = (bl && !skip) ? pos : last[k];
+                if (__ballot(Tn < kStopF) != 0ull) {
+                    // rare: some lane stops here (not blended; the pixel is done)
+                    const bool stop = Tn < kStopF;
+                    w = stop ? 0.0f : wa;
+                    Tk = stop ? T[k] : Tn;
+                    lk = stop ? last[k] : lk;
+                    if (EV) ev[k] = stop ? pos : ev[k];
+                    if (CNT) w_blended -= stop ? 1u : 0u;
+                    off[k] = stop ? -INFINITY : off[k];
+                    if (__ballot(off[k] == 0.0f) == 0ull) {
+                        // strip k has no live pixel left: the rest of the
+                        // batch skips it (its pixels blend nothing more)
+                        m[k] = 0ull;
+                        any &= (m[0] | m[1]) | (m[2] | m[3]);
                     }
-                    const float wa = alpha * T[k];
-                    const float Tn = T[k] - wa;     // T (1 - alpha)
-                    if (MODE == 3 && !(Tn < kStopF)) tmax = fmaxf(tmax, T[k]);
-                    float w = wa, Tk = Tn;
-                    uint32_t lk = skip ? last[k] : pos;
-                    if (__ballot(Tn < kStopF) != 0ull) {
-                        // rare: some lane stops here (not blended; the pixel is done)
-                        const bool stop = Tn < kStopF;
-                        w = stop ? 0.0f : wa;
-                        Tk = stop ? T[k] : Tn;
-                        lk = stop ? last[k] : lk;
-                        if (EV) ev[k] = stop ? pos : ev[k];
-                        if (CNT) w_blended -= stop ? 1u : 0u;
-                        off[k] = stop ? -INFINITY : off[k];
-                    }
-                    cr[k] = fmaf(w, sr, cr[k]);
-                    cg[k] = fmaf(w, sg, cg[k]);
-                    cb[k] = fmaf(w, sb, cb[k]);
-                    T[k] = Tk;
-                    last[k] = lk;
-                    if (CNT) w_blended += skip ? 0u : 1u;
-                    if (MODE == 5 && w != 0.0f) {
-                        // blended (not the stopping entry): its alpha T, binned by
-                        // the Mahalanobis distance sqrt(q), q = e2 / (-log2(e) / 2)
-                        const float m = __builtin_sqrtf(e2 * (1.0f / kNegHalfLog2e));
-                        const int bin = min((int)(m * a.prof_inv_width), a.prof_bins - 1);
-                        atomicAdd(&s_ps[wid][bin], w);
-                        atomicAdd(&s_pc[wid][bin], 1u);
-                    }
+                }
+                cr[k] = fmaf(w, sr, cr[k]);
+                cg[k] = fmaf(w, sg, cg[k]);
+                cb[k] = fmaf(w, sb, cb[k]);
+                T[k] = Tk;
+                last[k] = lk;
+                if (CNT) w_blended += (bl && !skip) ? 1u : 0u;
+                if (MODE == 5 && w != 0.0f) {
+                    // blended (not the stopping entry): its alpha T, binned by
+                    // the Mahalanobis distance sqrt(q), q = e2 / (-log2(e) / 2)
+                    const float mq = __builtin_sqrtf(e2 * (1.0f / kNegHalfLog2e));
+                    const int bin = min((int)(mq * a.prof_inv_width), a.prof_bins - 1);
+                    atomicAdd(&s_ps[wid][bin], w);
+                    atomicAdd(&s_pc[wid][bin], 1u);
                 }
             }
             if (MODE == 3) {
