@@ -358,12 +358,12 @@ __global__ __launch_bounds__(256) void k_prefilter(const PreprocessArgs a, int64
     if (threadIdx.x == 0) reinterpret_cast<uint32_t *>(a.rects + L * kWave)[0] = cnt;
 }
 
-// Pass 2: the double-precision path over kListsPerBlock consecutive
-// prefilter lists per block.  A list is copied to LDS in full (every load has
-// returned at the barrier) before any output overwrites it.  When the lists'
-// candidates fit the LDS queue together (the common case: few Gaussians of a
-// view get tiles, and the lists share them evenly) they are staged at once and
-// run as one dense set; otherwise list by list.
+// Pass 2: the double-precision path over `per` consecutive prefilter lists
+// per block (at most kListsPerBlock).  A list is copied to LDS in full (every
+// load has returned at the barrier) before any output overwrites it.  When
+// the lists' candidates fit the LDS queue together (AdaGScale frames: few
+// Gaussians of a view get tiles, and the lists share them evenly) they are
+// staged at once and run as one dense set; otherwise list by list.
 constexpr int kListsPerBlock = 16;
 
 template <int DEG>
@@ -384,13 +384,14 @@ __device__ __forceinline__ void stage_list(const PreprocessArgs &a, int64_t L, u
 }
 
 template <int DEG>
-__global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a, int64_t nlists) {
+__global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a, int64_t nlists, int per) {
     __shared__ PreEntry q[kPreChunk];
     __shared__ uint32_t s_cnt[kListsPerBlock], s_off[kListsPerBlock + 1];
-    const int64_t L0 = (int64_t)blockIdx.x * kListsPerBlock;
+    const int64_t L0 = (int64_t)blockIdx.x * per;
     if (threadIdx.x < kListsPerBlock) {
         const int64_t L = L0 + threadIdx.x;
-        s_cnt[threadIdx.x] = L < nlists ? reinterpret_cast<const uint32_t *>(a.rects + L * kWave)[0] : 0u;
+        s_cnt[threadIdx.x] =
+            (threadIdx.x < per && L < nlists) ? reinterpret_cast<const uint32_t *>(a.rects + L * kWave)[0] : 0u;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -419,17 +420,50 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a, int6
     }
 }
 
+// Plain 3D-GS: one thread per Gaussian straight through the double-precision
+// path (no prefilter: without AdaGScale's cull most of a view's Gaussians in
+// front of the camera get tiles, and queueing them costs more than the
+// off-screen ones the prefilter would prove).  Every parameter is requested
+// at once, before the near cull.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess_direct(const PreprocessArgs a) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.n) return;
+    const int n = a.n;
+    const float mx = a.means[g], my = a.means[plane_at(1, n, g)], mz = a.means[plane_at(2, n, g)];
+    float l0 = a.log_scales[g], l1 = a.log_scales[plane_at(1, n, g)], l2 = a.log_scales[plane_at(2, n, g)];
+    float qw = a.quats[g], qx = a.quats[plane_at(1, n, g)], qy = a.quats[plane_at(2, n, g)],
+          qz = a.quats[plane_at(3, n, g)];
+    float op = a.opacity_logits[g];
+    // left alone, the compiler sinks these loads below the near cull, which
+    // costs a second dependent trip to memory
+    pin_vgpr(l0); pin_vgpr(l1); pin_vgpr(l2);
+    pin_vgpr(qw); pin_vgpr(qx); pin_vgpr(qy); pin_vgpr(qz); pin_vgpr(op);
+    preprocess_exact<DEG>(a, g, mx, my, mz, l0, l1, l2, qw, qx, qy, qz, op);
+}
+
 hipError_t launch_preprocess(const PreprocessArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
+    if (!a.adagscale) {
+        const unsigned blocks = (unsigned)(((int64_t)a.n + 255) / 256);
+        switch (a.sh_degree) {
+            case 0: k_preprocess_direct<0><<<blocks, 256, 0, s>>>(a); break;
+            case 1: k_preprocess_direct<1><<<blocks, 256, 0, s>>>(a); break;
+            case 2: k_preprocess_direct<2><<<blocks, 256, 0, s>>>(a); break;
+            default: k_preprocess_direct<3><<<blocks, 256, 0, s>>>(a); break;
+        }
+        return hipGetLastError();
+    }
     const int64_t nchunks = ((int64_t)a.n + kWave - 1) / kWave;
     const int64_t nlists = (nchunks + kPreSub - 1) / kPreSub;
-    const unsigned blocks = (unsigned)((nlists + kListsPerBlock - 1) / kListsPerBlock);
+    const int per = kListsPerBlock;
+    const unsigned blocks = (unsigned)((nlists + per - 1) / per);
     k_prefilter<<<(unsigned)nlists, 256, 0, s>>>(a, nlists);
     switch (a.sh_degree) {
-        case 0: k_preprocess<0><<<blocks, 256, 0, s>>>(a, nlists); break;
-        case 1: k_preprocess<1><<<blocks, 256, 0, s>>>(a, nlists); break;
-        case 2: k_preprocess<2><<<blocks, 256, 0, s>>>(a, nlists); break;
-        default: k_preprocess<3><<<blocks, 256, 0, s>>>(a, nlists); break;
+        case 0: k_preprocess<0><<<blocks, 256, 0, s>>>(a, nlists, per); break;
+        case 1: k_preprocess<1><<<blocks, 256, 0, s>>>(a, nlists, per); break;
+        case 2: k_preprocess<2><<<blocks, 256, 0, s>>>(a, nlists, per); break;
+        default: k_preprocess<3><<<blocks, 256, 0, s>>>(a, nlists, per); break;
     }
     return hipGetLastError();
 }
