@@ -214,7 +214,7 @@ GS_API gs_status gs_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids, 
  * entry it reads).  The first call on a device looks up the array's address
  * there (the device must be current). */
 #define GS_SORT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
-#define GS_SORT_NOALLOC_MAX_PAIRS 8000000LL
+#define GS_SORT_NOALLOC_MAX_PAIRS 7000000LL
 GS_API gs_status gs_sort_noalloc(const uint32_t *pair_tiles, const uint32_t *pair_gids,
                                  const int64_t *num_pairs, int64_t pair_capacity,
                                  const gs_camera *cam, uint32_t *sorted_tiles,

@@ -202,16 +202,17 @@ bool workspace_layout(int64_t n, int64_t cap, void *base, Workspace *ws, int tx,
     // sort region
     ws->ptile_tmp = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
     ws->pgid_tmp = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
-    ws->phist = (uint32_t *)take(sizeof(uint32_t) * 256 * (size_t)ws->nb_psort);
+    ws->phist = (uint32_t *)take(sizeof(uint32_t) * 256 * (size_t)lsd_pass_blocks(cap));
+    ws->psum = (uint32_t *)take(sizeof(uint32_t) * 2 * 256 * (size_t)lsd_pass_groups(cap));
     ws->scan_part = (uint64_t *)take(sizeof(uint64_t) * (size_t)ws->max_parts);
     ws->counters = (int64_t *)take(sizeof(int64_t) * 4);
     const size_t sort_bytes = align256(off);
     // emit region
-    ws->nb_dpass = depth_pass_blocks(n);
-    ws->nb_dgroups = depth_pass_groups(n);
+    ws->nb_dpass = lsd_pass_blocks(n);
+    ws->nb_dgroups = lsd_pass_groups(n);
     ws->vis_count = (uint32_t *)take(sizeof(uint32_t) * (size_t)ws->nb_dsort);
     ws->pair_tot = (uint64_t *)take(sizeof(uint64_t) * (size_t)ws->nb_dsort);
-    ws->dgsum = (uint32_t *)take(sizeof(uint32_t) * 4 * 256 * (size_t)ws->nb_dgroups);
+    ws->dgsum = (uint32_t *)take(sizeof(uint32_t) * 2 * 256 * (size_t)ws->nb_dgroups);
     ws->pair_cnt = (uint64_t *)take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     ws->pair_off = (uint64_t *)take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     ws->slice_start = (uint32_t *)take(sizeof(uint32_t) * (size_t)(cap / kEmitChunk + 2));
@@ -244,9 +245,7 @@ using namespace gsr;
 
 namespace {
 struct ViewsWs {
-    uint32_t *key[3], *val[3], *hist, *next, *view_left;
-    uint64_t *parts;
-    int64_t nblocks;
+    uint32_t *key[3], *val[3], *hist, *gsum, *next, *view_left;
     size_t bytes;
 };
 void views_layout(int n_views, int64_t total, void *base, ViewsWs *w) {
@@ -263,9 +262,8 @@ void views_layout(int n_views, int64_t total, void *base, ViewsWs *w) {
         w->key[i] = (uint32_t *)take(4 * m);
         w->val[i] = (uint32_t *)take(4 * m);
     }
-    w->nblocks = (int64_t)((m + kSortChunk - 1) / kSortChunk);
-    w->hist = (uint32_t *)take(4 * 256 * (size_t)w->nblocks);
-    w->parts = (uint64_t *)take(8 * (size_t)((256 * w->nblocks + kScanChunk - 1) / kScanChunk + 1));
+    w->hist = (uint32_t *)take(4 * 256 * (size_t)lsd_pass_blocks((int64_t)m));
+    w->gsum = (uint32_t *)take(4 * 2 * 256 * (size_t)lsd_pass_groups((int64_t)m));
     w->next = (uint32_t *)take(4);
     w->view_left = (uint32_t *)take(4 * (size_t)(n_views > 0 ? n_views : 1));
     w->bytes = align256(off) + 256;  // + room for the item count
@@ -361,7 +359,7 @@ gs_status rasterize_views(const gs_view_target *views, const gs_view_target *d_v
         // the item count is a host-known constant; the sort reads it from device memory
         k_set_count<<<1, 1, 0, s>>>(count, total);
         e = radix_sort_u32(w.key[0], w.val[0], w.key[1], w.val[1], w.key[2], w.val[2], count, total,
-                           24, w.hist, w.nblocks, w.parts, s);
+                           24, w.hist, w.gsum, s);
     }
     if (e != hipSuccess) return hip_check(e, who);
     ViewsArgs q;
@@ -409,7 +407,7 @@ gs_status enqueue_sort(const uint32_t *pair_tiles, const uint32_t *pair_gids,
     if (pair_capacity > 0) {
         hipError_t e = radix_sort_u32(pair_tiles, pair_gids, sorted_tiles, sorted_gids, w.ptile_tmp,
                                       w.pgid_tmp, num_pairs, pair_capacity, bits_for(ntiles), w.phist,
-                                      w.nb_psort, w.scan_part, s);
+                                      w.psum, s);
         if ((st = hip_check(e, who)) != GS_OK) return st;
     }
     return hip_check(launch_tile_ranges(sorted_tiles, num_pairs, pair_capacity, ranges, ntiles, s),

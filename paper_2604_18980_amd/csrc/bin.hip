@@ -13,7 +13,7 @@
 //   scan
 //   k_bin_scatter1   regenerate the slice, rank by the low byte (radix_rank.hpp),
 //                    write (tile >> 8) << 24 | depth rank j
-//   radix_hist       high-byte histogram of the packed words, scan
+//   k_bin_hist2      high-byte histogram of the packed words, scan
 //   k_bin_scatter2   rank by the high byte, write sorted_gids = id of rank j
 //                    (and, optionally, the tile id: high byte from the word, low
 //                    byte from the pass-1 bucket that held it)
@@ -408,7 +408,7 @@ hipError_t launch_bin(const float *splats, const uint64_t *rects, const uint32_t
         e = launch_emit_pairs(splats, rects, tiles_x, extent_rule, ek, ev, cap, num_pairs, ws, s);
         if (e != hipSuccess) return e;
         e = radix_sort_u32(ek, ev, kout, sorted_gids, ws.ptile_tmp, ws.pgid_tmp, num_pairs, cap,
-                           bits, ws.phist, nb, ws.scan_part, s, 0, 1);
+                           bits, ws.phist, ws.psum, s, 0, 1);
         if (e != hipSuccess) return e;
         return launch_tile_ranges(kout, num_pairs, cap, ranges, (int)ntiles, s, 1);
     }

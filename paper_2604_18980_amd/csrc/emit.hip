@@ -42,7 +42,7 @@ __device__ __forceinline__ T sum_before(const T *tot, int64_t b, T *wt) {
 }
 
 // Visible Gaussians per chunk of 4096 ids; also clears the depth passes'
-// group sums (accumulated by k_dhist) and the pair totals per chunk
+// group sums (accumulated by k_lsd_hist) and the pair totals per chunk
 // (accumulated by k_pair_counts).
 __global__ __launch_bounds__(256) void k_vis_count(const uint32_t *tiles_touched, int n,
                                                    uint32_t *vis_count, uint32_t *clear,
@@ -385,7 +385,7 @@ hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
     const unsigned nb = (unsigned)ws.nb_dsort;  // chunks of 4096 (ids, then visible Gaussians)
     // also clears the depth passes' digit group sums
     k_vis_count<<<nb, 256, 0, s>>>(tiles_touched, n, ws.vis_count, ws.dgsum,
-                                   4 * 256 * ws.nb_dgroups, ws.pair_tot, ws.nb_dsort);
+                                   256 * ws.nb_dgroups, ws.pair_tot, ws.nb_dsort);
     k_vis_compact<<<nb, 256, 0, s>>>(tiles_touched, splats, n, ws.vis_count, ws.dkey[0], ws.dval[0],
                                      num_vis);
     hipError_t e = depth_sort(ws, num_vis, s);  // dkey/dval[0] -> [1]

@@ -38,19 +38,20 @@ struct Workspace {
     // emit
     uint32_t *vis_count;   // [nb_dsort] visible Gaussians per chunk of 4096 ids
     uint64_t *pair_tot;    // [nb_dsort] pairs per chunk of 4096 depth-sorted visible Gaussians
-    uint32_t *dgsum;       // [4][256][nb_dgroups] depth-pass digit sums per block group
-    int64_t nb_dpass;      // blocks of the depth passes' grid (depth_pass_blocks)
-    int64_t nb_dgroups;    // group sums per digit row (depth_pass_groups)
+    uint32_t *dgsum;       // [2][nb_dgroups][256] depth-pass digit sums per block group
+    int64_t nb_dpass;      // blocks of the depth passes' grid (lsd_pass_blocks(n))
+    int64_t nb_dgroups;    // group sums per digit row (lsd_pass_groups(n))
     uint64_t *pair_cnt;    // [n] pairs of each depth-sorted visible Gaussian
     uint64_t *pair_off;    // [n] their exclusive prefix
     uint32_t *slice_start; // [cap / emit chunk + 1] first Gaussian of each emission slice
     uint32_t *dkey[3];     // [n] depth keys: input, sorted output, pass scratch
     uint32_t *dval[3];     // [n] Gaussian ids, same roles
-    uint32_t *dhist;       // [256][nb_dpass]
+    uint32_t *dhist;       // [nb_dpass][256]
     // sort
     uint32_t *ptile_tmp;   // [cap]
     uint32_t *pgid_tmp;    // [cap]
-    uint32_t *phist;       // [256][nb_psort]
+    uint32_t *phist;       // [lsd_pass_blocks(cap)][256]
+    uint32_t *psum;        // [2][lsd_pass_groups(cap)][256]
     // fused binning (bin.hip)
     uint32_t *bpacked;     // [cap] pass-1 output: tile >> 8 in bits 24..31, depth rank below
     uint32_t *bhist;       // [256][nb_psort] pass-1 histogram / offsets
@@ -119,22 +120,18 @@ hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t m, uint
 hipError_t scan_exclusive_u64(const uint64_t *in, uint64_t *out, int64_t m, uint64_t *parts,
                               int64_t *total, hipStream_t s, DevExtent ext = DevExtent{});
 
-// stable LSD radix sort of (key, val) pairs by key bits [first_bit, bits),
+// Stable LSD radix sort of (key, val) pairs by key bits [first_bit, bits),
 // count in device memory (clamped to cap, or taken as zero when above cap with
 // empty_if_over).  Reads (kin, vin), leaves them unchanged, and puts the result
-// in (kout, vout); (ktmp, vtmp) is pass scratch distinct from both.  kout may
-// be null when only values are needed and the sort has one pass.
+// in (kout, vout); (ktmp, vtmp) is pass scratch distinct from both.  hist:
+// [lsd_pass_blocks(cap)][256]; gsum: [2][lsd_pass_groups(cap)][256], whose
+// first half the caller may have cleared already (gsum_zeroed).
 hipError_t radix_sort_u32(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
                           uint32_t *ktmp, uint32_t *vtmp, const int64_t *count, int64_t cap,
-                          int bits, uint32_t *hist, int64_t nblocks, uint64_t *parts,
-                          hipStream_t s, int first_bit = 0, int empty_if_over = 0);
-// One pass of it: digit (key >> shift) & 255; and its histogram + scan alone
-// (hist then holds each (digit, live block) output offset, digit-major).
-void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
-                const int64_t *count, int64_t cap, int shift, uint32_t *hist, int64_t nblocks,
-                uint64_t *parts, hipStream_t s, int empty_if_over);
-void radix_hist(const uint32_t *keys, const int64_t *count, int64_t cap, int shift, uint32_t *hist,
-                int64_t nblocks, uint64_t *parts, hipStream_t s, int empty_if_over);
+                          int bits, uint32_t *hist, uint32_t *gsum, hipStream_t s, int first_bit = 0,
+                          int empty_if_over = 0, bool gsum_zeroed = false);
+int64_t lsd_pass_blocks(int64_t cap);
+int64_t lsd_pass_groups(int64_t cap);
 
 hipError_t launch_emit(const float *splats, const uint64_t *rects, const uint32_t *tiles_touched,
                        int n, int tiles_x, int extent_rule, uint32_t *pair_tiles,
@@ -148,9 +145,6 @@ hipError_t launch_emit(const float *splats, const uint64_t *rects, const uint32_
 // device memory) into dkey/dval[1]: four 8-bit LSD passes of two kernels
 // each (digit offsets from block-group sums, no device-wide scan kernels).
 hipError_t depth_sort(const Workspace &ws, const int64_t *count, hipStream_t s);
-// Grid of the depth passes and the group sums per digit, for n keys at most.
-int64_t depth_pass_blocks(int64_t n);
-int64_t depth_pass_groups(int64_t n);
 hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
                                const uint32_t *tiles_touched, int n, int extent_rule, int64_t cap,
                                int64_t *num_pairs, const Workspace &ws, hipStream_t s);

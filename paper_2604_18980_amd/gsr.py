@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(PKG, "libgsr.so")
 GS_OK, GS_ERR_INVALID_ARGUMENT, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = range(5)
 LUT_BINS = 20
 TILE = 16
-SORT_NOALLOC_MAX_PAIRS = 8_000_000          # GS_SORT_NOALLOC_MAX_PAIRS
+SORT_NOALLOC_MAX_PAIRS = 7_000_000          # GS_SORT_NOALLOC_MAX_PAIRS
 SORT_NOALLOC_SCRATCH_BYTES = 64 << 20       # GS_SORT_NOALLOC_SCRATCH_BYTES
 
 EXPORTS = ("gs_workspace_size", "gs_preprocess", "gs_emit_pairs", "gs_sort", "gs_sort_noalloc",
