@@ -136,38 +136,39 @@ template <int MODE>
 __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
     constexpr bool EV = MODE == 1 || MODE == 2;
     constexpr bool CNT = MODE == 2 || MODE == 4;  // counts kept blends
-    __shared__ float4 s0[4][64], s1[4][64];
-    __shared__ float2 s2[4][64];
+    // one 48-byte row per parked record (mean x, mean y, A', beta | gamma',
+    // opacity, exponent limit, red | green, blue), so the three broadcast
+    // reads of a record share one address register
+    __shared__ float4 srec[4][64][3];
     __shared__ uint32_t s_cal[MODE == 3 ? 4 : 1][64];   // MODE 3: depth bin of each slot
     __shared__ uint32_t s_cgid[MODE == 3 ? 4 : 1][64];  // MODE 3: Gaussian id of each slot
     __shared__ uint32_t s_lut[MODE == 3 ? 4 : 1][kLutBins];
     __shared__ float s_w[MODE == 4 ? 4 : 1][64];          // MODE 4: weight of each slot
     __shared__ float s_ps[MODE == 5 ? 4 : 1][kProfBins];  // MODE 5: per-wave profile sums
     __shared__ uint32_t s_pc[MODE == 5 ? 4 : 1][kProfBins];  // and counts
-    const int wid = threadIdx.x / kWave;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
     const int lane = threadIdx.x & (kWave - 1);
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int col = lane & 15, row0 = lane >> 4;
     const int px = tx * kTile + col;
     const float fpx = (float)px;
     const float x_lo = (float)(tx * kTile), x_hi = (float)(tx * kTile + kTile - 1);
-    // Per pixel k: off[k] is 0 while the pixel is live and -inf once it has
-    // stopped (or lies outside the image); it enters the exponent through the
-    // gamma term's FMA, so "live and alpha >= tau" is one compare and the
-    // per-pixel state needs no boolean merges.
-    float fpy[4], T[4], cr[4], cg[4], cb[4], off[4];
+    // Per pixel k: fpy[k] is the pixel row while the pixel is live and NaN
+    // once it has stopped (or lies outside the image); the exponent is then
+    // NaN and fails the alpha >= tau compare, so "live and alpha >= tau" is
+    // one compare and the per-pixel state needs no boolean merges.
+    float fpy[4], T[4], cr[4], cg[4], cb[4];
     uint32_t last[4], ev[4];
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int py = ty * kTile + row0 + 4 * k;
-        fpy[k] = (float)py;
+        fpy[k] = (px < a.width && py < a.height) ? (float)py : __builtin_nanf("");
         pin_vgpr(fpy[k]);  // keep the float; recomputing it costs a convert per evaluation
         T[k] = 1.0f;
         cr[k] = cg[k] = cb[k] = 0.0f;
         last[k] = 0;
         ev[k] = end - start;
-        off[k] = (px < a.width && py < a.height) ? 0.0f : -INFINITY;
     }
     const float4 *spl = reinterpret_cast<const float4 *>(a.splats);
     uint32_t w_strips = 0, w_blended = 0, w_loaded = 0;  // MODE 2 (w_blended also MODE 4)
@@ -182,7 +183,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
         uint32_t alive = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (__ballot(off[k] == 0.0f) != 0ull) alive |= 1u << k;
+            if (__ballot(fpy[k] == fpy[k]) != 0ull) alive |= 1u << k;
         if (!alive) break;
         if (MODE == 2) w_loaded += min(end - base, (uint32_t)kWave);
         const uint32_t j = base + (uint32_t)lane;
@@ -221,9 +222,9 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
             m[k] = ((alive >> k) & 1u) ? __ballot((hit >> k) & 1u) : 0ull;
             any |= m[k];
         }
-        s0[wid][lane] = make_float4(mx, my, A2, beta);
-        s1[wid][lane] = make_float4(G2, sig, elim, r);
-        s2[wid][lane] = make_float2(g, bl);
+        srec[wid][lane][0] = make_float4(mx, my, A2, beta);
+        srec[wid][lane][1] = make_float4(G2, sig, elim, r);
+        srec[wid][lane][2] = make_float4(g, bl, 0.0f, 0.0f);
         auto eval = [&](const float4 r0, const float4 r1, const float2 r2, const int cur) {
             const float smx = r0.x, smy = r0.y, sA2 = r0.z, sbeta = r0.w;
             const float sG2 = r1.x, ssig = r1.y, selim = r1.z, sr = r1.w, sg = r2.x, sb = r2.y;
@@ -237,11 +238,9 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
                 if (MODE == 2) ++w_strips;
                 const float dy = smy - fpy[k];
                 const float u = fmaf(sbeta, dy, dx);
-                // exponent (base 2) plus the pixel's state offset, folded into
-                // the gamma term's FMA: for a live pixel (offset 0) this is the
-                // rounded product, so e2 is the same as without the offset; a
-                // stopped pixel gets -inf and fails the test below
-                const float e2 = fmaf(sA2 * u, u, fmaf(sG2 * dy, dy, off[k]));
+                // exponent (base 2); NaN for a stopped pixel, which fails the
+                // test below
+                const float e2 = fmaf(sA2 * u, u, (sG2 * dy) * dy);
                 // live pixel and opacity * 2^e2 >= tau, decided on the exponent;
                 // a strip where no lane blends is skipped (wave-uniform), the
                 // other lanes of a blending strip take alpha = 0 (no change)
@@ -269,8 +268,8 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
                     lk = stop ? last[k] : lk;
                     if (EV) ev[k] = stop ? pos : ev[k];
                     if (CNT) w_blended -= stop ? 1u : 0u;
-                    off[k] = stop ? -INFINITY : off[k];
-                    if (__ballot(off[k] == 0.0f) == 0ull) {
+                    fpy[k] = stop ? __builtin_nanf("") : fpy[k];
+                    if (__ballot(fpy[k] == fpy[k]) == 0ull) {
                         // strip k has no live pixel left: the rest of the
                         // batch skips it (its pixels blend nothing more)
                         m[k] = 0ull;
@@ -307,20 +306,22 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
             // there is none) so no register copies are needed
             int ja = __ffsll((long long)any) - 1;
             any &= any - 1ull;
-            float4 a0 = s0[wid][ja], a1 = s1[wid][ja];
-            float2 a2 = s2[wid][ja];
+            float4 a0 = srec[wid][ja][0], a1 = srec[wid][ja][1];
+            float2 a2 = make_float2(srec[wid][ja][2].x, srec[wid][ja][2].y);
             for (;;) {
                 const bool hb = any != 0ull;
                 const int jb = hb ? __ffsll((long long)any) - 1 : 0;
                 any &= any - 1ull;
-                const float4 b0 = s0[wid][jb], b1 = s1[wid][jb];
-                const float2 b2 = s2[wid][jb];
+                const float4 b0 = srec[wid][jb][0], b1 = srec[wid][jb][1];
+                const float2 b2 = make_float2(srec[wid][jb][2].x, srec[wid][jb][2].y);
                 eval(a0, a1, a2, ja);
                 if (!hb) break;
                 const bool ha = any != 0ull;
                 ja = ha ? __ffsll((long long)any) - 1 : 0;
                 any &= any - 1ull;
-                a0 = s0[wid][ja]; a1 = s1[wid][ja]; a2 = s2[wid][ja];
+                a0 = srec[wid][ja][0];
+                a1 = srec[wid][ja][1];
+                a2 = make_float2(srec[wid][ja][2].x, srec[wid][ja][2].y);
                 eval(b0, b1, b2, jb);
                 if (!ha) break;
             }
