@@ -17,9 +17,9 @@
 //   that covers float32 rounding); four ballots turn that into 64-bit masks.
 //   The lanes park their records in the wave's own LDS slots, and the wave
 //   walks the set bits in list order, reading each hit record with one
-//   uniform-address (broadcast) LDS read per 16 bytes -- the next record's
-//   read overlapping the current evaluation -- and evaluates only the hit
-//   strips.  A skipped strip has alpha < tau at every pixel, so results are
+//   uniform-address (broadcast) LDS read per 16 bytes, and evaluates only
+//   the hit strips.  The per-lane state fits 63 VGPRs, so eight waves per SIMD
+//   hide the LDS and exponential latencies (no software pipelining needed).  A skipped strip has alpha < tau at every pixel, so results are
 //   unchanged.  A strip whose last live pixel stops leaves the batch's hit
 //   masks at once (its remaining hits would only evaluate stopped pixels).
 //   No barriers: waves run and retire independently.
@@ -300,31 +300,12 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
                 }
             }
         };
-        if (any) {
-            // two record sets in flight: while one hit Gaussian is evaluated the
-            // next one's record is being read (unconditionally, from slot 0 when
-            // there is none) so no register copies are needed
-            int ja = __ffsll((long long)any) - 1;
+        while (any) {
+            const int ja = __ffsll((long long)any) - 1;
             any &= any - 1ull;
-            float4 a0 = srec[wid][ja][0], a1 = srec[wid][ja][1];
-            float2 a2 = make_float2(srec[wid][ja][2].x, srec[wid][ja][2].y);
-            for (;;) {
-                const bool hb = any != 0ull;
-                const int jb = hb ? __ffsll((long long)any) - 1 : 0;
-                any &= any - 1ull;
-                const float4 b0 = srec[wid][jb][0], b1 = srec[wid][jb][1];
-                const float2 b2 = make_float2(srec[wid][jb][2].x, srec[wid][jb][2].y);
-                eval(a0, a1, a2, ja);
-                if (!hb) break;
-                const bool ha = any != 0ull;
-                ja = ha ? __ffsll((long long)any) - 1 : 0;
-                any &= any - 1ull;
-                a0 = srec[wid][ja][0];
-                a1 = srec[wid][ja][1];
-                a2 = make_float2(srec[wid][ja][2].x, srec[wid][ja][2].y);
-                eval(b0, b1, b2, jb);
-                if (!ha) break;
-            }
+            const float4 a0 = srec[wid][ja][0], a1 = srec[wid][ja][1];
+            const float2 a2 = make_float2(srec[wid][ja][2].x, srec[wid][ja][2].y);
+            eval(a0, a1, a2, ja);
         }
     }
     if (MODE == 3) {
