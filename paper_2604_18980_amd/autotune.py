@@ -5,7 +5,12 @@ mapped to the machine: threads per tile, pixels per thread and the number of
 Gaussian records staged per round.  The built geometries are
 
     (64, 4, 64)    one wave per tile, 4 pixels per lane, strip culling
+    (128, 2, 64)   two waves per tile, 2 pixels per lane (each wave a 16x8 half,
+                   walking the list for its own strips)
     (256, 1, B)    one workgroup per tile, 1 pixel per thread, B in {64, 128, 256}
+
+which is every way to cover a 16x16 tile with 64, 128 or 256 threads at 4, 2
+or 1 pixels each.
 
 The tuner times every candidate on the caller's actual work (same sorted
 lists, same views) with HIP events, keeps the fastest, and caches the choice
@@ -21,7 +26,7 @@ import torch
 
 from . import gsr
 
-CANDIDATES = ((64, 4, 64), (256, 1, 64), (256, 1, 128), (256, 1, 256))
+CANDIDATES = ((64, 4, 64), (128, 2, 64), (256, 1, 64), (256, 1, 128), (256, 1, 256))
 
 
 def cache_path() -> str:

@@ -58,12 +58,15 @@ int bits_for(int64_t count) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Raster geometries with a compiled kernel: one wave per tile with 4 pixels
-// per lane, or one 256-thread workgroup per tile staging 64/128/256 records.
+// per lane, two waves per tile with 2 pixels per lane (each wave walks the
+// list in batches of 64 for its 16x8 half), or one 256-thread workgroup per
+// tile staging 64/128/256 records.
 bool geometry_built(const gs_raster_cfg &c) {
     const bool block = c.threads_per_tile == 256 && c.pixels_per_thread == 1 &&
                        (c.lds_batch == 64 || c.lds_batch == 128 || c.lds_batch == 256);
     const bool wave = c.threads_per_tile == 64 && c.pixels_per_thread == 4 && c.lds_batch == 64;
-    return block || wave;
+    const bool half = c.threads_per_tile == 128 && c.pixels_per_thread == 2 && c.lds_batch == 64;
+    return block || wave || half;
 }
 
 // Real-SH normalisation constants (Condon-Shortley phase) for the polynomial
@@ -349,6 +352,7 @@ gs_status rasterize_views(const gs_view_target *views, const gs_view_target *d_v
             return fail(GS_ERR_UNSUPPORTED, "raster geometry %d/%d/%d not built", c.threads_per_tile,
                         c.pixels_per_thread, c.lds_batch);
     }
+    p.parts = c.threads_per_tile == 128 ? 2 : 1;  // half tiles are separate work items
     ViewsWs w;
     views_layout(n_views, total, ws, &w);
     if (!ws || ws_bytes < w.bytes)
@@ -370,8 +374,10 @@ gs_status rasterize_views(const gs_view_target *views, const gs_view_target *d_v
     q.next = w.next;
     q.view_left = w.view_left;
     q.clock = clock;
-    static thread_local int grid_cache[4] = {0, 0, 0, 0};
-    const int gi = c.threads_per_tile == 256 ? (c.lds_batch == 64 ? 1 : c.lds_batch == 128 ? 2 : 3) : 0;
+    static thread_local int grid_cache[5] = {0, 0, 0, 0, 0};
+    const int gi = c.threads_per_tile == 256   ? (c.lds_batch == 64 ? 1 : c.lds_batch == 128 ? 2 : 3)
+                   : c.threads_per_tile == 128 ? 4
+                                               : 0;
     if (!grid_cache[gi]) grid_cache[gi] = raster_views_grid(c);
     return hip_check(launch_raster_views(q, c, grid_cache[gi], s), who);
 }

@@ -138,7 +138,8 @@ __global__ __launch_bounds__(256) void k_raster_backward(const RasterBwdArgs a) 
             mx = g0.x; my = g0.y; A = g0.z; beta = g0.w; gam = g1.x; sig = g1.y; r = g2.x; g = g2.y; bl = g2.z;
             // the forward's blend threshold and strip bound, computed identically
             elim = alpha_tau_elim(sig);
-            hit = strip_hits(mx, my, A, beta, gam, elim, x_lo, x_hi, (float)(ty * kTile));
+            hit = strip_hits(mx, my, A, beta, gam, elim, x_lo, x_hi, (float)(ty * kTile),
+                             (float)(ty * kTile) + 7.5f);
         }
         const float A2 = A * kNegHalfLog2e, G2s = gam * kNegHalfLog2e;
         uint64_t m[4], any = 0;

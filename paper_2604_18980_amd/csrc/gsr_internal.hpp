@@ -215,6 +215,7 @@ int raster_views_grid(const gs_raster_cfg &cfg);
 
 struct ViewsPlan {
     int n_views;
+    int parts;                            // raster work items per tile (1, or 2 half tiles)
     uint32_t tile_off[GS_MAX_VIEWS + 1];  // prefix of tiles per view
     uint32_t tiles_x[GS_MAX_VIEWS];
 };

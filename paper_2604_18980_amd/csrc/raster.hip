@@ -132,8 +132,8 @@ __device__ __forceinline__ float wave_max(float v) {
 // Gaussian's weight, or T_up of its depth bin) is below a.skip_theta is
 // skipped (no colour, no T update, not a contributor); a.work, if set,
 // receives the skipped and kept blend counts.
-template <int MODE>
-__device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
+template <int MODE, int NS = 4>
+__device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile, int part = 0) {
     constexpr bool EV = MODE == 1 || MODE == 2;
     constexpr bool CNT = MODE == 2 || MODE == 4;  // counts kept blends
     // one 48-byte row per parked record (mean x, mean y, A', beta | gamma',
@@ -153,16 +153,17 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
     const int px = tx * kTile + col;
     const float fpx = (float)px;
     const float x_lo = (float)(tx * kTile), x_hi = (float)(tx * kTile + kTile - 1);
+    const int y0 = ty * kTile + part * 4 * NS;  // this wave's first row
     // Per pixel k: fpy[k] is the pixel row while the pixel is live and NaN
     // once it has stopped (or lies outside the image); the exponent is then
     // NaN and fails the alpha >= tau compare, so "live and alpha >= tau" is
     // one compare and the per-pixel state needs no boolean merges.
-    float fpy[4], T[4], cr[4], cg[4], cb[4];
-    uint32_t last[4], ev[4];
+    float fpy[NS], T[NS], cr[NS], cg[NS], cb[NS];
+    uint32_t last[NS], ev[NS];
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int py = ty * kTile + row0 + 4 * k;
+    for (int k = 0; k < NS; ++k) {
+        const int py = y0 + row0 + 4 * k;
         fpy[k] = (px < a.width && py < a.height) ? (float)py : __builtin_nanf("");
         pin_vgpr(fpy[k]);  // keep the float; recomputing it costs a convert per evaluation
         T[k] = 1.0f;
@@ -182,7 +183,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
     for (uint32_t base = start; base < end; base += kWave) {
         uint32_t alive = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < NS; ++k)
             if (__ballot(fpy[k] == fpy[k]) != 0ull) alive |= 1u << k;
         if (!alive) break;
         if (MODE == 2) w_loaded += min(end - base, (uint32_t)kWave);
@@ -198,7 +199,8 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
             A2 = A * kNegHalfLog2e;
             G2 = gam * kNegHalfLog2e;
             elim = alpha_tau_elim(sig);
-            hit = strip_hits(mx, my, A, beta, gam, elim, x_lo, x_hi, (float)(ty * kTile));
+            hit = strip_hits<NS>(mx, my, A, beta, gam, elim, x_lo, x_hi, (float)y0,
+                                 (float)(ty * kTile) + 7.5f);
             if (MODE == 3) {
                 // the record's float32 depth, binned in double as the oracle does
                 const double f = ((double)g1.z * kLutBins) / a.lut_depth_max;
@@ -216,9 +218,9 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
                 s_w[wid][lane] = wv;
             }
         }
-        uint64_t m[4], any = 0;
+        uint64_t m[NS], any = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < NS; ++k) {
             m[k] = ((alive >> k) & 1u) ? __ballot((hit >> k) & 1u) : 0ull;
             any |= m[k];
         }
@@ -233,7 +235,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
             float tmax = 0.0f;  // MODE 3: largest T in front of it where it blends
             const float swt = MODE == 4 ? s_w[wid][cur] : 0.0f;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < NS; ++k) {
                 if (!((m[k] >> cur) & 1ull)) continue;  // uniform: strip k missed
                 if (MODE == 2) ++w_strips;
                 const float dy = smy - fpy[k];
@@ -273,7 +275,10 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
                         // strip k has no live pixel left: the rest of the
                         // batch skips it (its pixels blend nothing more)
                         m[k] = 0ull;
-                        any &= (m[0] | m[1]) | (m[2] | m[3]);
+                        uint64_t rest = 0ull;
+#pragma unroll
+                        for (int kk = 0; kk < NS; ++kk) rest |= m[kk];
+                        any &= rest;
                     }
                 }
                 cr[k] = fmaf(w, sr, cr[k]);
@@ -322,8 +327,8 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
     if (MODE == 2) {
         unsigned long long e = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (px < a.width && ty * kTile + row0 + 4 * k < a.height) e += ev[k];
+        for (int k = 0; k < NS; ++k)
+            if (px < a.width && y0 + row0 + 4 * k < a.height) e += ev[k];
         e = wave_sum_u64(e);
         const unsigned long long b = wave_sum_u64(w_blended);
         if (lane == 0) {
@@ -342,8 +347,8 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile) {
         }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int py = ty * kTile + row0 + 4 * k;
+    for (int k = 0; k < NS; ++k) {
+        const int py = y0 + row0 + 4 * k;
         if (px < a.width && py < a.height) store_pixel(a, px, py, cr[k], cg[k], cb[k], T[k], last[k], ev[k]);
     }
 }
@@ -361,11 +366,15 @@ __global__ __launch_bounds__(256) void k_raster_block(const RasterArgs a) {
 // shared records) measured 1.6x slower on a 6M-Gaussian 4608x3456 frame: the
 // pair load is concentrated in parts of the image, and contiguous bands leave
 // some XCDs with most of the work.
-template <int MODE>
+// NS = 4: one wave per tile; NS = 2: two waves per tile (the geometry with
+// 128 threads and 2 pixels per thread), each walking the list for its half.
+template <int MODE, int NS = 4>
 __global__ __launch_bounds__(256) void k_raster_wave(const RasterArgs a) {
-    const int tile = (int)blockIdx.x * 4 + (int)(threadIdx.x / kWave);
+    constexpr int kParts = 4 / NS;
+    const int w = (int)blockIdx.x * 4 + (int)(threadIdx.x / kWave);
+    const int tile = w / kParts;
     if (tile >= a.tiles_x * a.tiles_y) return;
-    tile_wave<MODE>(a, tile);
+    tile_wave<MODE, NS>(a, tile, w % kParts);
 }
 
 hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStream_t s) {
@@ -384,6 +393,11 @@ hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStrea
             case 128: k_raster_block<128><<<tiles, 256, 0, s>>>(a); break;
             default: k_raster_block<256><<<tiles, 256, 0, s>>>(a); break;
         }
+    } else if (cfg.threads_per_tile == 128) {
+        if (a.n_evaluated)
+            k_raster_wave<1, 2><<<(tiles + 1) / 2, 256, 0, s>>>(a);
+        else
+            k_raster_wave<0, 2><<<(tiles + 1) / 2, 256, 0, s>>>(a);
     } else {
         if (a.n_evaluated)
             k_raster_wave<1><<<(tiles + 3) / 4, 256, 0, s>>>(a);
@@ -445,7 +459,7 @@ __global__ void k_views_init(const ViewsPlan p, uint32_t *next, uint32_t *view_l
         *next = 0u;
         if (clock) clock[0] = wall_clock64();
     }
-    if (v < p.n_views) view_left[v] = p.tile_off[v + 1] - p.tile_off[v];
+    if (v < p.n_views) view_left[v] = (p.tile_off[v + 1] - p.tile_off[v]) * (uint32_t)p.parts;
 }
 
 hipError_t launch_views_plan(const ViewsPlan &p, const gs_view_target *d_views, uint32_t *keys,
@@ -461,16 +475,21 @@ hipError_t launch_views_plan(const ViewsPlan &p, const gs_view_target *d_views, 
 // atomics (lane 0 adds 1, the others 0) and lane 0's result is read with an
 // explicit readlane.  A "lane 0 fetches, then broadcast" form lets the compiler
 // split the loop so that the other lanes re-read a stale ticket without lane 0.
+// With NS = 2 a ticket is a half tile: item t / 2, half t % 2 (view_left then
+// counts halves).
+template <int NS>
 __global__ __launch_bounds__(256) void k_raster_views_wave(const ViewsArgs q) {
+    constexpr int kParts = 4 / NS;
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t one = lane == 0 ? 1u : 0u;
     for (;;) {
         const uint32_t t = atomicAdd(q.next, one);
-        const uint32_t item = (uint32_t)__builtin_amdgcn_readlane((int)t, 0);
+        const uint32_t ticket = (uint32_t)__builtin_amdgcn_readlane((int)t, 0);
+        const uint32_t item = ticket / kParts;
         if ((int64_t)item >= q.n_items) break;
         const uint32_t code = q.items[item];
         const int view = (int)(code >> 26), tile = (int)(code & ((1u << 26) - 1));
-        tile_wave<0>(view_args(q, view), tile);
+        tile_wave<0, NS>(view_args(q, view), tile, (int)(ticket % kParts));
         const uint32_t left = atomicSub(&q.view_left[view], one);
         if (__builtin_amdgcn_readlane((int)left, 0) == 1 && q.clock)
             q.clock[1 + view] = wall_clock64();  // same value from every lane
@@ -501,8 +520,10 @@ hipError_t launch_raster_views(const ViewsArgs &q, const gs_raster_cfg &cfg, int
             case 128: k_raster_views_block<128><<<grid, 256, 0, s>>>(q); break;
             default: k_raster_views_block<256><<<grid, 256, 0, s>>>(q); break;
         }
+    } else if (cfg.threads_per_tile == 128) {
+        k_raster_views_wave<2><<<grid, 256, 0, s>>>(q);
     } else {
-        k_raster_views_wave<<<grid, 256, 0, s>>>(q);
+        k_raster_views_wave<4><<<grid, 256, 0, s>>>(q);
     }
     return hipGetLastError();
 }
@@ -516,8 +537,10 @@ int raster_views_grid(const gs_raster_cfg &cfg) {
         fn = cfg.lds_batch == 64    ? (const void *)k_raster_views_block<64>
              : cfg.lds_batch == 128 ? (const void *)k_raster_views_block<128>
                                     : (const void *)k_raster_views_block<256>;
+    } else if (cfg.threads_per_tile == 128) {
+        fn = (const void *)k_raster_views_wave<2>;
     } else {
-        fn = (const void *)k_raster_views_wave;
+        fn = (const void *)k_raster_views_wave<4>;
     }
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) != hipSuccess || per < 1) per = 1;
     return cus * per;

@@ -16,29 +16,31 @@ __device__ __forceinline__ float alpha_tau_elim(float sig) {
     return kLog2Tau - __builtin_amdgcn_logf(sig);
 }
 
-// Which of the four 16x4 strips of a 16x16 tile (columns [x_lo, x_hi], strip
-// k = rows y0 + 4k .. y0 + 4k + 3) can hold a pixel with alpha >= tau: bit k
-// is set unless the exponent's minimum over the strip, taken per row over the
-// continuous column interval, exceeds the cut.  With u = dx + beta dy the
-// quadratic form is A u^2 + gamma dy^2; over a row u spans
-// [mx - x_hi + beta dy, mx - x_lo + beta dy], whose distance from 0 is
+// Which of the NS 16x4 strips from row y0 of a 16x16 tile (columns [x_lo,
+// x_hi], strip k = rows y0 + 4k .. y0 + 4k + 3) can hold a pixel with
+// alpha >= tau: bit k is set unless the exponent's minimum over the strip,
+// taken per row over the continuous column interval, exceeds the cut.  With
+// u = dx + beta dy the quadratic form is A u^2 + gamma dy^2; over a row u
+// spans [mx - x_hi + beta dy, mx - x_lo + beta dy], whose distance from 0 is
 // max(lo, -hi, 0).  alpha >= tau  <=>  q <= qlim = -2 ln2 elim; the cut adds
 // a margin above the float32 rounding of this test and of the per-pixel
 // evaluation: relative 1e-3, plus a term growing with the distance of the
-// centre from the tile (dx and dy lose digits there).
+// centre from the tile's centre row yc (dx and dy lose digits there).
+template <int NS = 4>
 __device__ __forceinline__ uint32_t strip_hits(float mx, float my, float A, float beta, float gam,
-                                               float elim, float x_lo, float x_hi, float y0) {
+                                               float elim, float x_lo, float x_hi, float y0,
+                                               float yc) {
     const float qlim = kNeg2Ln2 * elim;
     if (!(qlim > -1e-3f)) return 0u;
     const float ql = fmaxf(qlim, 0.0f);
-    const float far = fabsf(mx - (x_lo + 7.5f)) + fabsf(my - (y0 + 7.5f));
+    const float far = fabsf(mx - (x_lo + 7.5f)) + fabsf(my - yc);
     const float qcut = ql + 1e-3f * (1.0f + ql) +
                        1e-5f * far * (1.0f + __builtin_amdgcn_sqrtf((A + gam) * ql));
     const float clo = mx - x_hi, chi = x_lo - mx;  // lo = clo + beta dy, -hi = chi - beta dy
     const float dy0 = my - y0;
     uint32_t hit = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < NS; ++k) {
         float qmin = 3.0e38f;
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {

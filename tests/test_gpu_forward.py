@@ -237,11 +237,12 @@ def test_raster_work_counts(O, which):
     assert nonempty <= w["loaded"] <= P
 
 
-@pytest.mark.parametrize("geom", [(256, 1, 256), (64, 4, 64)], ids=["block", "wave"])
+@pytest.mark.parametrize("geom", [(256, 1, 256), (128, 2, 64), (64, 4, 64)], ids=["block", "half", "wave"])
 @pytest.mark.parametrize("which", ["tiny", "mid"])
 def test_raster_geometries_match_oracle(O, geom, which):
-    """Both built raster geometries (block-per-tile, wave-per-tile with strip
-    culling) against the oracle on the same sorted lists."""
+    """Every built raster geometry (workgroup per tile, two waves per tile,
+    wave per tile; the wave programs with strip culling) against the oracle on
+    the same sorted lists."""
     import torch
     from paper_2604_18980_amd import gsr, render as R
     if which == "tiny":
@@ -270,6 +271,27 @@ def test_raster_geometries_match_oracle(O, geom, which):
     ok = (fr.margin >= EXEMPT_MARGIN) & (mask if mask is not None else True)
     np.testing.assert_array_equal(ne.cpu().numpy()[ok], fr.evals[ok])
     print(f"geometry {geom}: exempt {n_ex}")
+
+
+def test_half_tile_geometry_equals_wave():
+    """Two waves per tile (2 pixels per lane) run the same per-pixel
+    arithmetic in the same list order as one wave per tile, so every output
+    is bit-identical, at a ragged 1000x600 frame of the mid scene."""
+    import torch
+    from paper_2604_18980_amd import gsr, render as R
+    sc, cam = scenes.mid_scene(n=60_000, seed=9, width=1000, height=600)
+    ds = R.DeviceScene.from_host(sc)
+    fb = R.render(ds, cam, adagscale=True, K=0.3, extent_rule=1)
+    out = []
+    for geom in ((64, 4, 64), (128, 2, 64)):
+        ne = torch.empty((cam["height"], cam["width"]), dtype=torch.int32, device="cuda")
+        R.run_raster(fb, gsr.camera_struct(cam), (0.2, 0.1, 0.0), cfg=gsr.GsRasterCfg(*geom),
+                     n_evaluated=ne)
+        torch.cuda.synchronize()
+        out.append([fb.image.cpu().numpy().copy(), fb.final_T.cpu().numpy().copy(),
+                    fb.n_contrib.cpu().numpy().copy(), ne.cpu().numpy()])
+    for a, b in zip(*out):
+        np.testing.assert_array_equal(a, b)
 
 
 def test_single_view_graph_replay(O):

@@ -11,7 +11,7 @@ from paper_2604_18980_amd import scenes
 
 pytestmark = pytest.mark.gpu
 
-GEOMS = [(64, 4, 64), (256, 1, 64), (256, 1, 128), (256, 1, 256)]
+GEOMS = [(64, 4, 64), (128, 2, 64), (256, 1, 64), (256, 1, 128), (256, 1, 256)]
 
 
 def _cams(k=6):
