@@ -148,3 +148,76 @@ def test_bin_reused_workspace_matches_fresh(O):
         assert int(shared.num_pairs.item()) == P
         assert torch.equal(shared.ranges, rg)
         assert torch.equal(shared.image, img)
+
+
+CANARY = -0x5A5A5A5B  # 0xA5A5A5A5 as int32
+
+
+def _cut_capacities(pair_gids, P):
+    """Capacities that stop the emission inside one Gaussian's run of pairs:
+    a third of the pairs, mid-way through a run longer than 16 tiles (a long
+    row span or several rows), and one pair into a short run."""
+    g = pair_gids[:P]
+    starts = np.flatnonzero(np.r_[True, g[1:] != g[:-1]])
+    lens = np.diff(np.r_[starts, P])
+    caps = [P // 3]
+    long_runs = np.flatnonzero(lens > 16)
+    if long_runs.size:
+        i = long_runs[long_runs.size // 2]
+        caps.append(int(starts[i] + lens[i] // 2))
+    short = np.flatnonzero((lens >= 2) & (lens <= 16))
+    if short.size:
+        i = short[short.size // 2]
+        caps.append(int(starts[i] + 1))
+    return sorted(set(c for c in caps if 0 < c < P))
+
+
+@pytest.mark.parametrize("staged", [True, False], ids=["staged", "bin"])
+@pytest.mark.parametrize("rule", [1, 2], ids=["ellipse", "obb"])
+def test_overflow_writes_nothing_past_capacity(O, rule, staged):
+    """Capacity below the pair count, cutting into long and short spans of the
+    giants frame: the pair and sorted arrays are views of larger buffers whose
+    tail past the capacity holds a canary, and no store may reach it.  Staged
+    emission writes exactly the first `capacity` pairs of the full emission,
+    which gs_sort then sorts; gs_bin_pairs bins nothing."""
+    import torch
+    from paper_2604_18980_amd import gsr, render as R
+    sc, cam, mode = _case("giants_1024x2048")
+    mode = dict(mode, extent_rule=rule)
+    full = gpu_frame(sc, cam, mode, staged=True)
+    P = full["num_pairs"]
+    caps = _cut_capacities(full["pair_gids"], P)
+    assert len(caps) >= 3, caps
+    ds = R.DeviceScene.from_host(sc)
+    cam_s, mode_s = gsr.camera_struct(cam), gsr.mode_struct(**mode)
+    tail = 1 << 20  # more than 64 Gaussians covering the whole 64 x 128-tile image
+    for cap in caps:
+        print(f"giants rule {rule} {'staged' if staged else 'bin'}: capacity {cap} of {P}", flush=True)
+        fb = R.FrameBuffers(ds.n, cam["width"], cam["height"], cap)
+        big = {}
+        for name in ("pair_tiles", "pair_gids", "sorted_tiles", "sorted_gids"):
+            big[name] = torch.full((cap + tail,), CANARY, dtype=torch.int32, device="cuda")
+            setattr(fb, name, big[name][:cap])
+        R.run_preprocess(ds, cam_s, mode_s, fb)
+        if staged:
+            R.run_emit(fb, cam_s)
+            R.run_sort(fb, cam_s)
+        else:
+            R.run_bin(fb, cam_s, with_tiles=True)
+        torch.cuda.synchronize()
+        assert int(fb.num_pairs.item()) == P
+        if not staged:  # gs_bin_pairs bins nothing when over capacity
+            assert not fb.ranges.cpu().numpy().any()
+        for name, b in big.items():
+            t = b[cap:].cpu().numpy()
+            assert np.all(t == CANARY), f"{name}: {int((t != CANARY).sum())} stores past capacity {cap}"
+        if staged:
+            # the emitted prefix, and gs_sort's stable sort of it (it reads
+            # min(num_pairs, capacity) pairs)
+            pt = fb.pair_tiles.cpu().numpy().astype(np.uint32).astype(np.int64)
+            pg = fb.pair_gids.cpu().numpy().astype(np.uint32).astype(np.int64)
+            np.testing.assert_array_equal(pt, full["pair_tiles"][:cap])
+            np.testing.assert_array_equal(pg, full["pair_gids"][:cap])
+            order = np.argsort(pt, kind="stable")
+            np.testing.assert_array_equal(fb.sorted_tiles.cpu().numpy().astype(np.uint32), pt[order])
+            np.testing.assert_array_equal(fb.sorted_gids.cpu().numpy().astype(np.uint32), pg[order])
