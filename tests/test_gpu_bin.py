@@ -119,9 +119,10 @@ def test_bin_overflow_bins_nothing(O, name, rule):
 
 
 def test_bin_reused_workspace_matches_fresh(O):
-    """One set of buffers (and so one workspace, whose single-pass look-back
-    state is reset per call) serves frames with many, few and no visible
-    Gaussians in turn; each frame equals a render into fresh buffers."""
+    """One set of buffers (and so one workspace, whose counters and digit
+    group sums each call clears before use) serves frames with many, few and
+    no visible Gaussians in turn; each frame equals a render into fresh
+    buffers."""
     import torch
     from paper_2604_18980_amd import render as R
     sc, cam = scenes.mid_scene(n=40_000, seed=7, width=640, height=360)
