@@ -130,18 +130,17 @@ __global__ __launch_bounds__(256) void k_raster_backward(const RasterBwdArgs a) 
             if (__ballot(last[k] > (uint32_t)lo) != 0ull) alive |= 1u << k;
         const int j = lo + lane;
         float mx = 0.f, my = 0.f, A = 0.f, beta = 0.f, gam = 0.f, sig = 0.f, r = 0.f, g = 0.f, bl = 0.f;
-        float elim = 0.f;
+        BlendCoef kc{0.f, 0.f, 0.f, 0.f};
         uint32_t gid = 0, hit = 0;
         if (j < hi) {
             gid = a.gids[start + j];
             const float4 g0 = spl[3 * (size_t)gid], g1 = spl[3 * (size_t)gid + 1], g2 = spl[3 * (size_t)gid + 2];
             mx = g0.x; my = g0.y; A = g0.z; beta = g0.w; gam = g1.x; sig = g1.y; r = g2.x; g = g2.y; bl = g2.z;
-            // the forward's blend threshold and strip bound, computed identically
-            elim = alpha_tau_elim(sig);
-            hit = strip_hits(mx, my, A, beta, gam, elim, x_lo, x_hi, (float)(ty * kTile),
+            // the forward's exponent coefficients and strip bound, computed identically
+            kc = blend_coef(A, beta, gam, sig);
+            hit = strip_hits(mx, my, A, beta, gam, kLog2Tau - kc.ls, x_lo, x_hi, (float)(ty * kTile),
                              (float)(ty * kTile) + 7.5f);
         }
-        const float A2 = A * kNegHalfLog2e, G2s = gam * kNegHalfLog2e;
         uint64_t m[4], any = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -153,10 +152,12 @@ __global__ __launch_bounds__(256) void k_raster_backward(const RasterBwdArgs a) 
             any &= ~(1ull << jj);
             const float smx = bcast(mx, jj), smy = bcast(my, jj), sA = bcast(A, jj);
             const float sbeta = bcast(beta, jj), sgam = bcast(gam, jj), ssig = bcast(sig, jj);
-            const float sA2 = bcast(A2, jj), sG2 = bcast(G2s, jj), selim = bcast(elim, jj);
+            const float sa = bcast(kc.a, jj), sab = bcast(kc.ab, jj), sc = bcast(kc.c, jj);
+            const float sls = bcast(kc.ls, jj), isig = __builtin_amdgcn_rcpf(ssig);
             const float sr = bcast(r, jj), sg = bcast(g, jj), sb = bcast(bl, jj);
             const uint32_t pos = (uint32_t)(lo + jj);
             const float dx = smx - fpx;
+            const float adx = sa * dx;
             float d[9];
 #pragma unroll
             for (int q = 0; q < 9; ++q) d[q] = 0.0f;
@@ -166,12 +167,12 @@ __global__ __launch_bounds__(256) void k_raster_backward(const RasterBwdArgs a) 
                 if (!((m[k] >> jj) & 1ull)) continue;  // uniform: strip k missed
                 const float dy = smy - fpy[k];
                 const float u = fmaf(sbeta, dy, dx);
-                // the forward's exponent, term for term (its state offset is 0 here)
-                const float e2 = fmaf(sA2 * u, u, fmaf(sG2 * dy, dy, 0.0f));
-                if (pos < last[k] && e2 >= selim) {  // the forward blended it here
+                // the forward's exponent (log2 opacity included), term for term
+                const float e2 = blend_exponent(adx, sab, sc, sls, dy);
+                if (pos < last[k] && e2 >= kLog2Tau) {  // the forward blended it here
                     contrib = true;
-                    const float e = __builtin_amdgcn_exp2f(e2);
-                    const float raw = ssig * e;
+                    const float raw = __builtin_amdgcn_exp2f(e2);  // opacity exp(power)
+                    const float e = raw * isig;                    // exp(power)
                     const float alpha = fminf(kAlphaMaxF, raw);
                     const float iom = 1.0f / (1.0f - alpha);  // one division, four products
                     const float Tb = T[k] * iom;  // transmittance in front of this Gaussian

@@ -136,9 +136,9 @@ template <int MODE, int NS = 4>
 __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile, int part = 0) {
     constexpr bool EV = MODE == 1 || MODE == 2;
     constexpr bool CNT = MODE == 2 || MODE == 4;  // counts kept blends
-    // one 48-byte row per parked record (mean x, mean y, A', beta | gamma',
-    // opacity, exponent limit, red | green, blue), so the three broadcast
-    // reads of a record share one address register
+    // one 48-byte row per parked record (mean x, mean y, a, a beta | c,
+    // log2 opacity, red, green | blue; BlendCoef), so the broadcast reads of a
+    // record share one address register
     __shared__ float4 srec[4][64][3];
     __shared__ uint32_t s_cal[MODE == 3 ? 4 : 1][64];   // MODE 3: depth bin of each slot
     __shared__ uint32_t s_cgid[MODE == 3 ? 4 : 1][64];  // MODE 3: Gaussian id of each slot
@@ -188,17 +188,16 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile, int par
         if (!alive) break;
         if (MODE == 2) w_loaded += min(end - base, (uint32_t)kWave);
         const uint32_t j = base + (uint32_t)lane;
-        float mx = 0.f, my = 0.f, A2 = 0.f, beta = 0.f, G2 = 0.f, sig = 0.f, r = 0.f, g = 0.f, bl = 0.f;
-        float elim = 0.f;  // alpha >= tau  <=>  exponent (base 2) >= elim
+        float mx = 0.f, my = 0.f, r = 0.f, g = 0.f, bl = 0.f;
+        BlendCoef kc{0.f, 0.f, 0.f, 0.f};
         uint32_t hit = 0;
         if (j < end) {
             const size_t gid = a.gids[j];
             const float4 g0 = spl[3 * gid], g1 = spl[3 * gid + 1], g2 = spl[3 * gid + 2];
-            mx = g0.x; my = g0.y; beta = g0.w; sig = g1.y; r = g2.x; g = g2.y; bl = g2.z;
-            const float A = g0.z, gam = g1.x;
-            A2 = A * kNegHalfLog2e;
-            G2 = gam * kNegHalfLog2e;
-            elim = alpha_tau_elim(sig);
+            mx = g0.x; my = g0.y; r = g2.x; g = g2.y; bl = g2.z;
+            const float A = g0.z, beta = g0.w, gam = g1.x;
+            kc = blend_coef(A, beta, gam, g1.y);
+            const float elim = kLog2Tau - kc.ls;  // alpha >= tau <=> e - ls >= elim
             hit = strip_hits<NS>(mx, my, A, beta, gam, elim, x_lo, x_hi, (float)y0,
                                  (float)(ty * kTile) + 7.5f);
             if (MODE == 3) {
@@ -224,13 +223,13 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile, int par
             m[k] = ((alive >> k) & 1u) ? __ballot((hit >> k) & 1u) : 0ull;
             any |= m[k];
         }
-        srec[wid][lane][0] = make_float4(mx, my, A2, beta);
-        srec[wid][lane][1] = make_float4(G2, sig, elim, r);
-        srec[wid][lane][2] = make_float4(g, bl, 0.0f, 0.0f);
-        auto eval = [&](const float4 r0, const float4 r1, const float2 r2, const int cur) {
-            const float smx = r0.x, smy = r0.y, sA2 = r0.z, sbeta = r0.w;
-            const float sG2 = r1.x, ssig = r1.y, selim = r1.z, sr = r1.w, sg = r2.x, sb = r2.y;
-            const float dx = smx - fpx;
+        srec[wid][lane][0] = make_float4(mx, my, kc.a, kc.ab);
+        srec[wid][lane][1] = make_float4(kc.c, kc.ls, r, g);
+        srec[wid][lane][2] = make_float4(bl, 0.0f, 0.0f, 0.0f);
+        auto eval = [&](const float4 r0, const float4 r1, const float r2, const int cur) {
+            const float smx = r0.x, smy = r0.y, sa = r0.z, sab = r0.w;
+            const float sc = r1.x, sls = r1.y, sr = r1.z, sg = r1.w, sb = r2;
+            const float adx = sa * (smx - fpx);
             const uint32_t pos = (base - start) + (uint32_t)cur + 1u;
             float tmax = 0.0f;  // MODE 3: largest T in front of it where it blends
             const float swt = MODE == 4 ? s_w[wid][cur] : 0.0f;
@@ -239,16 +238,15 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile, int par
                 if (!((m[k] >> cur) & 1ull)) continue;  // uniform: strip k missed
                 if (MODE == 2) ++w_strips;
                 const float dy = smy - fpy[k];
-                const float u = fmaf(sbeta, dy, dx);
-                // exponent (base 2); NaN for a stopped pixel, which fails the
-                // test below
-                const float e2 = fmaf(sA2 * u, u, (sG2 * dy) * dy);
-                // live pixel and opacity * 2^e2 >= tau, decided on the exponent;
+                // log2(opacity) + exponent (base 2); NaN for a stopped pixel,
+                // which fails the test below
+                const float e2 = blend_exponent(adx, sab, sc, sls, dy);
+                // live pixel and alpha = 2^e2 >= tau, decided on the exponent;
                 // a strip where no lane blends is skipped (wave-uniform), the
                 // other lanes of a blending strip take alpha = 0 (no change)
-                const bool bl = e2 >= selim;
+                const bool bl = e2 >= kLog2Tau;
                 if (__ballot(bl) == 0ull) continue;
-                float alpha = bl ? fminf(kAlphaMaxF, ssig * __builtin_amdgcn_exp2f(e2)) : 0.0f;
+                float alpha = bl ? fminf(kAlphaMaxF, __builtin_amdgcn_exp2f(e2)) : 0.0f;
                 bool skip = false;
                 if (MODE == 4) {
                     // contribution below theta: blend nothing (alpha 0 leaves
@@ -289,8 +287,8 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile, int par
                 if (CNT) w_blended += (bl && !skip) ? 1u : 0u;
                 if (MODE == 5 && w != 0.0f) {
                     // blended (not the stopping entry): its alpha T, binned by
-                    // the Mahalanobis distance sqrt(q), q = e2 / (-log2(e) / 2)
-                    const float mq = __builtin_sqrtf(e2 * (1.0f / kNegHalfLog2e));
+                    // the Mahalanobis distance sqrt(q), q = (ls - e2) / (log2(e) / 2)
+                    const float mq = __builtin_sqrtf(fmaxf(sls - e2, 0.0f) * (1.0f / kHalfLog2e));
                     const int bin = min((int)(mq * a.prof_inv_width), a.prof_bins - 1);
                     atomicAdd(&s_ps[wid][bin], w);
                     atomicAdd(&s_pc[wid][bin], 1u);
@@ -309,7 +307,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile, int par
             const int ja = __ffsll((long long)any) - 1;
             any &= any - 1ull;
             const float4 a0 = srec[wid][ja][0], a1 = srec[wid][ja][1];
-            const float2 a2 = make_float2(srec[wid][ja][2].x, srec[wid][ja][2].y);
+            const float a2 = srec[wid][ja][2].x;
             eval(a0, a1, a2, ja);
         }
     }

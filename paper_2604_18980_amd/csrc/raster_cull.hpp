@@ -5,15 +5,33 @@
 
 namespace gsr {
 
-constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
-constexpr float kLog2Tau = -7.9943534368588578f;           // log2(1/255)
-constexpr float kNeg2Ln2 = -1.3862943611198906f;           // -2 ln 2
+constexpr float kLog2Tau = -7.9943534368588578f;       // log2(1/255)
+constexpr float kNeg2Ln2 = -1.3862943611198906f;       // -2 ln 2
 
-// alpha = opacity 2^e2 >= tau  <=>  e2 >= elim = log2(tau) - log2(opacity).
-// The hardware log2 (about one ulp); an opacity at or below the smallest
-// normal float gives elim = +inf (never blended: its alpha is far below tau).
-__device__ __forceinline__ float alpha_tau_elim(float sig) {
-    return kLog2Tau - __builtin_amdgcn_logf(sig);
+constexpr float kHalfLog2e = 0.72134752044448170368f;  // log2(e) / 2
+
+// The blend's exponent in base 2 with the opacity folded in.  Per Gaussian
+// a = sqrt(A log2(e)/2), ab = a beta, c = sqrt(gamma log2(e)/2) and
+// ls = log2(opacity) (BlendCoef); per pixel adx = a dx, then
+//   e = -(adx + ab dy)^2 - (c dy)^2 + ls = log2(opacity) - q log2(e) / 2
+// with q = A (dx + beta dy)^2 + gamma dy^2, so alpha = min(0.99, 2^e) and
+// alpha >= tau  <=>  e >= log2(tau).  Both squares are non-negative terms
+// (no cancellation); a NaN offset gives a NaN exponent, which fails the test.
+struct BlendCoef {
+    float a, ab, c, ls;
+};
+__device__ __forceinline__ BlendCoef blend_coef(float A, float beta, float gam, float sig) {
+    BlendCoef k;
+    k.a = __builtin_amdgcn_sqrtf(A * kHalfLog2e);
+    k.ab = k.a * beta;
+    k.c = __builtin_amdgcn_sqrtf(gam * kHalfLog2e);
+    k.ls = __builtin_amdgcn_logf(sig);
+    return k;
+}
+__device__ __forceinline__ float blend_exponent(float adx, float ab, float c, float ls, float dy) {
+    const float u = fmaf(ab, dy, adx);
+    const float t = c * dy;
+    return fmaf(-u, u, fmaf(-t, t, ls));
 }
 
 // Which of the NS 16x4 strips from row y0 of a 16x16 tile (columns [x_lo,
