@@ -378,16 +378,20 @@ hipError_t launch_bin(const float *splats, const uint64_t *rects, const uint32_t
                       uint32_t *sorted_tiles, uint32_t *ranges, int64_t cap, int64_t *num_pairs,
                       const Workspace &ws, hipStream_t s) {
     const int64_t ntiles = (int64_t)tiles_x * tiles_y;
+    const bool packed = bin_packed(n, tiles_x, tiles_y);
+    const bool generic = !packed || extent_rule != 0;
+    // the generic route's tile-sort group sums and ranges are cleared by the
+    // emission preparation's first kernel (no fill launches)
     hipError_t e = launch_emit_prepare(splats, rects, tiles_touched, n, extent_rule, cap, num_pairs,
-                                       ws, s);
+                                       ws, s, generic ? ws.psum : nullptr, 256 * lsd_pass_groups(cap),
+                                       generic ? ranges : nullptr, 2 * ntiles);
     if (e != hipSuccess) return e;
     if (n == 0 || cap == 0) {  // no pairs can be binned: every range empty
         k_zero_ranges<<<(unsigned)((2 * ntiles + 255) / 256), 256, 0, s>>>(ranges, 2 * ntiles);
         return hipGetLastError();
     }
     const int64_t nb = ws.nb_psort;  // slices = sort blocks = ceil(cap / 4096)
-    const bool packed = bin_packed(n, tiles_x, tiles_y);
-    if (!packed || extent_rule != 0) {
+    if (generic) {
         // generic route (and the ellipse and oriented-box rules, whose pairs are
         // not a rectangle enumeration): emit the pairs, sort them by tile
         // (nothing if over), ranges
@@ -408,9 +412,9 @@ hipError_t launch_bin(const float *splats, const uint64_t *rects, const uint32_t
         e = launch_emit_pairs(splats, rects, tiles_x, extent_rule, ek, ev, cap, num_pairs, ws, s);
         if (e != hipSuccess) return e;
         e = radix_sort_u32(ek, ev, kout, sorted_gids, ws.ptile_tmp, ws.pgid_tmp, num_pairs, cap,
-                           bits, ws.phist, ws.psum, s, 0, 1);
+                           bits, ws.phist, ws.psum, s, 0, 1, true);
         if (e != hipSuccess) return e;
-        return launch_tile_ranges(kout, num_pairs, cap, ranges, (int)ntiles, s, 1);
+        return launch_tile_ranges(kout, num_pairs, cap, ranges, (int)ntiles, s, 1, true);
     }
     SliceArgs a;
     a.sorted_ids = ws.dval[1];

@@ -42,15 +42,20 @@ __device__ __forceinline__ T sum_before(const T *tot, int64_t b, T *wt) {
 }
 
 // Visible Gaussians per chunk of 4096 ids; also clears the depth passes'
-// group sums (accumulated by k_lsd_hist) and the pair totals per chunk
-// (accumulated by k_pair_counts).
+// group sums (accumulated by k_lsd_hist), the pair totals per chunk
+// (accumulated by k_pair_counts) and up to two further word ranges.
 __global__ __launch_bounds__(256) void k_vis_count(const uint32_t *tiles_touched, int n,
                                                    uint32_t *vis_count, uint32_t *clear,
                                                    int64_t nclear, uint64_t *clear64,
-                                                   int64_t nclear64) {
+                                                   int64_t nclear64, uint32_t *xclear, int64_t nxclear,
+                                                   uint32_t *xclear2, int64_t nxclear2) {
     __shared__ uint32_t wt[4];
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nclear; i += (int64_t)gridDim.x * 256)
         clear[i] = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nxclear; i += (int64_t)gridDim.x * 256)
+        xclear[i] = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nxclear2; i += (int64_t)gridDim.x * 256)
+        xclear2[i] = 0u;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nclear64; i += (int64_t)gridDim.x * 256)
         clear64[i] = 0ull;
     const int64_t base = (int64_t)blockIdx.x * kSortChunk + threadIdx.x;
@@ -375,7 +380,8 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *sorted_ids, const 
 
 hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
                                const uint32_t *tiles_touched, int n, int extent_rule, int64_t cap,
-                               int64_t *num_pairs, const Workspace &ws, hipStream_t s) {
+                               int64_t *num_pairs, const Workspace &ws, hipStream_t s,
+                               uint32_t *xclear, int64_t nxclear, uint32_t *xclear2, int64_t nxclear2) {
     int64_t *num_vis = ws.counters;
     if (n == 0) {
         k_set_i64<<<1, 1, 0, s>>>(num_pairs, 0);
@@ -385,7 +391,8 @@ hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
     const unsigned nb = (unsigned)ws.nb_dsort;  // chunks of 4096 (ids, then visible Gaussians)
     // also clears the depth passes' digit group sums
     k_vis_count<<<nb, 256, 0, s>>>(tiles_touched, n, ws.vis_count, ws.dgsum,
-                                   256 * ws.nb_dgroups, ws.pair_tot, ws.nb_dsort);
+                                   256 * ws.nb_dgroups, ws.pair_tot, ws.nb_dsort,
+                                   xclear, xclear ? nxclear : 0, xclear2, xclear2 ? nxclear2 : 0);
     k_vis_compact<<<nb, 256, 0, s>>>(tiles_touched, splats, n, ws.vis_count, ws.dkey[0], ws.dval[0],
                                      num_vis);
     hipError_t e = depth_sort(ws, num_vis, s);  // dkey/dval[0] -> [1]

@@ -145,9 +145,13 @@ hipError_t launch_emit(const float *splats, const uint64_t *rects, const uint32_
 // device memory) into dkey/dval[1]: four 8-bit LSD passes of two kernels
 // each (digit offsets from block-group sums, no device-wide scan kernels).
 hipError_t depth_sort(const Workspace &ws, const int64_t *count, hipStream_t s);
+// xclear / xclear2 (nullable): further words its first kernel zeroes (for
+// later kernels of the same call, in place of fill launches).
 hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
                                const uint32_t *tiles_touched, int n, int extent_rule, int64_t cap,
-                               int64_t *num_pairs, const Workspace &ws, hipStream_t s);
+                               int64_t *num_pairs, const Workspace &ws, hipStream_t s,
+                               uint32_t *xclear = nullptr, int64_t nxclear = 0,
+                               uint32_t *xclear2 = nullptr, int64_t nxclear2 = 0);
 // The pair-writing part of launch_emit, after launch_emit_prepare: whole
 // rectangles (extent rule 0) or each rectangle row's ellipse (rule 1) or
 // oriented-box (rule 2) span, recomputed from the splat records.
@@ -162,8 +166,10 @@ hipError_t launch_bin(const float *splats, const uint64_t *rects, const uint32_t
                       uint32_t *sorted_tiles, uint32_t *ranges, int64_t cap, int64_t *num_pairs,
                       const Workspace &ws, hipStream_t s);
 
+// ranges_zeroed: the caller has cleared the ranges (no fill launch).
 hipError_t launch_tile_ranges(const uint32_t *sorted_tiles, const int64_t *num_pairs, int64_t cap,
-                              uint32_t *ranges, int num_tiles, hipStream_t s, int empty_if_over = 0);
+                              uint32_t *ranges, int num_tiles, hipStream_t s, int empty_if_over = 0,
+                              bool ranges_zeroed = false);
 
 struct RasterArgs {
     const float *splats;

@@ -331,9 +331,10 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *tiles, cons
 }
 
 hipError_t launch_tile_ranges(const uint32_t *sorted_tiles, const int64_t *num_pairs, int64_t cap,
-                              uint32_t *ranges, int num_tiles, hipStream_t s, int empty_if_over) {
+                              uint32_t *ranges, int num_tiles, hipStream_t s, int empty_if_over,
+                              bool ranges_zeroed) {
     const int64_t m = 2 * (int64_t)num_tiles;
-    k_fill_u32<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(ranges, m, 0u);
+    if (!ranges_zeroed) k_fill_u32<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(ranges, m, 0u);
     if (cap > 0)
         k_tile_ranges<<<(unsigned)((cap + 1023) / 1024), 256, 0, s>>>(sorted_tiles, num_pairs, cap, ranges,
                                                                       (uint32_t)num_tiles, empty_if_over);
