@@ -14,7 +14,7 @@
 //   k_emit                              each block writes its pairs contiguously,
 //                                       one pair per thread per step, after an LDS
 //                                       scan of its Gaussians' tile counts
-//   k_emit_spans                        extent rules 1 and 2: per wave 64
+//   k_emit_spans                        extent rules 1 and 2: per wave 32
 //                                       Gaussians' row spans (tile_shapes.hpp),
 //                                       64 (Gaussian, row) items per step,
 //                                       written by the whole wave
@@ -255,6 +255,20 @@ __device__ __forceinline__ uint64_t shape_pair_count(const float *splats, const 
 // (tiles_touched) under extent rule 0, the count of its tiles that meet the
 // ellipse (rule 1) or the oriented box (rule 2).  The visible Gaussians are
 // dense here, and the flattened row walk keeps every lane on a span.
+// Gaussians per wave in the span emitter: the flattened walk takes 64 items
+// per step whatever the count, so fewer Gaussians per wave mean more, shorter
+// waves over the visible Gaussians (their steps are latency-bound FP64 chains,
+// and a few hundred thousand Gaussians at 64 per wave leave about four waves
+// per SIMD).  Measured on a 6M city frame (259K visible Gaussians): emission
+// 55 us at 64, 50 at 32, 56 at 16; the pair count is fastest at 64 (its
+// steps are shorter), so it keeps one Gaussian per lane.
+#ifndef GSR_SPAN_LANES
+#define GSR_SPAN_LANES 32
+#endif
+constexpr int kSpanLanes = GSR_SPAN_LANES;
+static_assert(kSpanLanes >= 1 && kSpanLanes <= kWave && kSortChunk % (4 * kSpanLanes) == 0,
+              "a block's Gaussians lie in one 4096-chunk");
+
 template <int RULE>
 __global__ __launch_bounds__(256) void k_pair_counts(const uint32_t *sorted_ids, const int64_t *num_vis,
                                                      const uint32_t *tiles_touched, const float *splats,
@@ -264,20 +278,23 @@ __global__ __launch_bounds__(256) void k_pair_counts(const uint32_t *sorted_ids,
     using Shape = typename std::conditional<RULE == 2, OrientedBox, Ellipse>::type;
     __shared__ RowTable<Shape> s_rows[RULE == 0 ? 1 : 4];
     const int64_t V = *num_vis;
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if ((int64_t)blockIdx.x * 256 >= V) return;  // uniform
+    const int wid = threadIdx.x / kWave;
+    const int64_t j0 = (int64_t)blockIdx.x * 256;
+    if (j0 >= V) return;  // uniform
+    const int64_t j = j0 + threadIdx.x;
+    const bool mine = j < V;
     uint64_t c = 0;
-    const uint32_t g = j < V ? sorted_ids[j] : 0u;
+    const uint32_t g = mine ? sorted_ids[j] : 0u;
     if constexpr (RULE == 0) {
-        if (j < V) c = tiles_touched[g];
+        if (mine) c = tiles_touched[g];
     } else {
-        c = shape_pair_count<Shape>(splats, rects, g, j < V, s_rows[threadIdx.x / kWave]);
+        c = shape_pair_count<Shape>(splats, rects, g, mine, s_rows[wid]);
     }
-    if (j < V) cnt[j] = c;
+    if (mine) cnt[j] = c;
     uint64_t tot;
     block_exclusive_scan<256, uint64_t>(c, wt, &tot);
-    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&chunk_tot[(int64_t)blockIdx.x * 256 / kSortChunk],
-                                           (unsigned long long)tot);
+    if (threadIdx.x == 0 && tot)
+        atomicAdd((unsigned long long *)&chunk_tot[j0 / kSortChunk], (unsigned long long)tot);
 }
 
 // Exclusive prefix of the pair counts (the chunk's offset is the sum of the
@@ -397,11 +414,12 @@ hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
                                      num_vis);
     hipError_t e = depth_sort(ws, num_vis, s);  // dkey/dval[0] -> [1]
     if (e != hipSuccess) return e;
+    const unsigned span_blocks = (unsigned)ws.nb_gauss;
     if (extent_rule == 1)
-        k_pair_counts<1><<<(unsigned)ws.nb_gauss, 256, 0, s>>>(ws.dval[1], num_vis, tiles_touched,
+        k_pair_counts<1><<<span_blocks, 256, 0, s>>>(ws.dval[1], num_vis, tiles_touched,
                                                               splats, rects, ws.pair_cnt, ws.pair_tot);
     else if (extent_rule == 2)
-        k_pair_counts<2><<<(unsigned)ws.nb_gauss, 256, 0, s>>>(ws.dval[1], num_vis, tiles_touched,
+        k_pair_counts<2><<<span_blocks, 256, 0, s>>>(ws.dval[1], num_vis, tiles_touched,
                                                               splats, rects, ws.pair_cnt, ws.pair_tot);
     else
         k_pair_counts<0><<<(unsigned)ws.nb_gauss, 256, 0, s>>>(ws.dval[1], num_vis, tiles_touched,
@@ -411,13 +429,13 @@ hipError_t launch_emit_prepare(const float *splats, const uint64_t *rects,
     return hipGetLastError();
 }
 
-// Extent rules 1 and 2: each wave takes 64 consecutive depth-sorted visible
-// Gaussians, one per lane, and walks their rows flattened, 64 (Gaussian, row)
-// items per step (RowTable): every lane recomputes the span of its item
-// exactly as k_pair_counts counted it, the item's first pair follows the
-// Gaussian's earlier rows (a wave prefix sum carried over the steps, less its
-// value at the Gaussian's first row), and the whole wave writes the step's
-// spans.
+// Extent rules 1 and 2: each wave takes kSpanLanes consecutive depth-sorted
+// visible Gaussians, one per lane (the other lanes hold none), and walks their
+// rows flattened, 64 (Gaussian, row) items per step (RowTable): every lane
+// recomputes the span of its item exactly as k_pair_counts counted it, the
+// item's first pair follows the Gaussian's earlier rows (a wave prefix sum
+// carried over the steps, less its value at the Gaussian's first row), and the
+// whole wave writes the step's spans.
 // Pairs at or beyond the capacity are not written.
 
 // spans of up to this many pairs are written by their own lanes
@@ -466,14 +484,15 @@ __global__ __launch_bounds__(256) void k_emit_spans(const uint32_t *sorted_ids, 
     __shared__ RowTable<Shape> s_rows[4];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int64_t V = *num_vis;
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if ((int64_t)blockIdx.x * 256 + wid * kWave >= V) return;  // wave-uniform
+    const int64_t jw = ((int64_t)blockIdx.x * 4 + wid) * kSpanLanes;  // this wave's first Gaussian
+    if (jw >= V) return;  // wave-uniform
+    const int64_t j = jw + lane;
     RowTable<Shape> &tb = s_rows[wid];
     uint64_t k = 0;
     uint32_t g = 0;
     int ra = 0, rb = 0, x0 = 0, x1 = 0;
     Shape e{};
-    if (j < V) {
+    if (lane < kSpanLanes && j < V) {
         k = off[j];
         g = sorted_ids[j];
         const uint64_t r = rects[g];
@@ -522,11 +541,13 @@ hipError_t launch_emit_pairs(const float *splats, const uint64_t *rects, int til
                              int64_t cap, const int64_t *num_pairs, const Workspace &ws,
                              hipStream_t s) {
     if (cap <= 0) return hipGetLastError();
+    const unsigned span_blocks =
+        (unsigned)(((int64_t)ws.nb_gauss * 256 + 4 * kSpanLanes - 1) / (4 * kSpanLanes));
     if (extent_rule == 1)
-        k_emit_spans<Ellipse><<<(unsigned)ws.nb_gauss, 256, 0, s>>>(
+        k_emit_spans<Ellipse><<<span_blocks, 256, 0, s>>>(
             ws.dval[1], ws.counters, splats, rects, ws.pair_off, tiles_x, pair_tiles, pair_gids, cap);
     else if (extent_rule == 2)
-        k_emit_spans<OrientedBox><<<(unsigned)ws.nb_gauss, 256, 0, s>>>(
+        k_emit_spans<OrientedBox><<<span_blocks, 256, 0, s>>>(
             ws.dval[1], ws.counters, splats, rects, ws.pair_off, tiles_x, pair_tiles, pair_gids, cap);
     else
         k_emit<<<(unsigned)((cap + kEmitChunk - 1) / kEmitChunk), 256, 0, s>>>(
