@@ -379,7 +379,12 @@ __device__ __forceinline__ void stage_list(const PreprocessArgs &a, int64_t L, u
                                            PreEntry *dst) {
     for (uint32_t i = threadIdx.x; i < cnt; i += 256) {
         const float4 *in = list_slot(a, L, i, nlists);
-        dst[i] = PreEntry{in[0], in[1], in[2]};
+        // three loads in flight, then three LDS stores (a PreEntry temporary
+        // here went through scratch memory)
+        const float4 e0 = in[0], e1 = in[1], e2 = in[2];
+        dst[i].a = e0;
+        dst[i].b = e1;
+        dst[i].c = e2;
     }
 }
 
