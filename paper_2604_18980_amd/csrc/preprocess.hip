@@ -410,8 +410,34 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a, int6
     __syncthreads();
     const uint32_t total = s_off[kListsPerBlock];
     if (total <= (uint32_t)kPreChunk) {  // block-uniform
-        for (int l = 0; l < kListsPerBlock; ++l)
-            if (s_cnt[l]) stage_list(a, L0 + l, s_cnt[l], nlists, q + s_off[l]);
+        // every list's entries in one pass: block entry t is entry t - off[l]
+        // of the list l with off[l] <= t < off[l + 1]; both slots' loads are
+        // in flight before either is stored
+        static_assert(kPreChunk == 2 * 256, "two staging slots per thread");
+        float4 e[2][3];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t t = (uint32_t)h * 256u + threadIdx.x;
+            if (t < total) {
+                int l = 0;
+#pragma unroll
+                for (int b = kListsPerBlock / 2; b > 0; b >>= 1)
+                    if (s_off[l + b] <= t) l += b;
+                const float4 *in = list_slot(a, L0 + l, t - s_off[l], nlists);
+                e[h][0] = in[0];
+                e[h][1] = in[1];
+                e[h][2] = in[2];
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t t = (uint32_t)h * 256u + threadIdx.x;
+            if (t < total) {
+                q[t].a = e[h][0];
+                q[t].b = e[h][1];
+                q[t].c = e[h][2];
+            }
+        }
         __syncthreads();
         run_staged<DEG>(a, q, total);
     } else {
