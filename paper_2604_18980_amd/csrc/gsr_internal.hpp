@@ -117,8 +117,6 @@ struct DevExtent {
 // given by ext); if total is non-null the grand total is stored there (as int64).
 hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t m, uint64_t *parts,
                               int64_t *total, hipStream_t s, DevExtent ext = DevExtent{});
-hipError_t scan_exclusive_u64(const uint64_t *in, uint64_t *out, int64_t m, uint64_t *parts,
-                              int64_t *total, hipStream_t s, DevExtent ext = DevExtent{});
 
 // Stable LSD radix sort of (key, val) pairs by key bits [first_bit, bits),
 // count in device memory (clamped to cap, or taken as zero when above cap with

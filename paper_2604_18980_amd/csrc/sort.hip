@@ -93,10 +93,6 @@ hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t m, uint
                               int64_t *total, hipStream_t s, DevExtent ext) {
     return scan_exclusive<uint32_t>(in, out, m, parts, total, ext, s);
 }
-hipError_t scan_exclusive_u64(const uint64_t *in, uint64_t *out, int64_t m, uint64_t *parts,
-                              int64_t *total, hipStream_t s, DevExtent ext) {
-    return scan_exclusive<uint64_t>(in, out, m, parts, total, ext, s);
-}
 
 __global__ void k_fill_u32(uint32_t *p, int64_t m, uint32_t v);
 
