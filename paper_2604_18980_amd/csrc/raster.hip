@@ -8,21 +8,24 @@
 //   (three 16-byte loads per record); a block vote ends the walk once every
 //   pixel has reached the 1e-4 transmittance stop.
 //
-// tile_wave          one wave per tile, four pixels per lane.  Lane l owns
-//   column l % 16 and rows l / 16 + 4k (k = 0..3), so each wave instruction
-//   evaluates one 16x4 strip.  The list is walked 64 records at a time: every
-//   lane gathers one record and decides, for its Gaussian, which strips can
-//   reach alpha >= tau (the exponent's minimum over each strip row, taken over
-//   the continuous column interval, against 2 ln(opacity/tau) plus a margin
-//   that covers float32 rounding); four ballots turn that into 64-bit masks.
-//   The lanes park their records in the wave's own LDS slots, and the wave
-//   walks the set bits in list order, reading each hit record with one
-//   uniform-address (broadcast) LDS read per 16 bytes, and evaluates only
-//   the hit strips.  The per-lane state fits 63 VGPRs, so eight waves per SIMD
-//   hide the LDS and exponential latencies (no software pipelining needed).  A skipped strip has alpha < tau at every pixel, so results are
-//   unchanged.  A strip whose last live pixel stops leaves the batch's hit
-//   masks at once (its remaining hits would only evaluate stopped pixels).
-//   No barriers: waves run and retire independently.
+// tile_wave<MODE, NS>  one wave per tile, four pixels per lane (NS = 4), or
+//   two waves per tile, each a 16x8 half with two pixels per lane (NS = 2).
+//   Lane l owns column l % 16 and rows l / 16 + 4k (k < NS) of its part, so
+//   each wave instruction evaluates one 16x4 strip.  The list is walked 64
+//   records at a time: every lane gathers one record and decides, for its
+//   Gaussian, which strips can reach alpha >= tau (the exponent's minimum over
+//   each strip row, taken over the continuous column interval, against
+//   2 ln(opacity/tau) plus a margin that covers float32 rounding); one ballot
+//   per strip turns that into 64-bit masks.  The lanes park their records
+//   (with the exponent's per-Gaussian coefficients, raster_cull.hpp) in the
+//   wave's own LDS slots, and the wave walks the set bits in list order,
+//   reading each hit record with uniform-address (broadcast) LDS reads, and
+//   evaluates only the hit strips.  A skipped strip has alpha < tau at every
+//   pixel, so results are unchanged.  A strip whose last live pixel stops
+//   leaves the batch's hit masks at once (its remaining hits would only
+//   evaluate stopped pixels).  The per-lane state fits 62 VGPRs, so eight
+//   waves per SIMD hide the LDS and exponential latencies.  No barriers:
+//   waves run and retire independently.
 #include "gsr_internal.hpp"
 #include "raster_cull.hpp"
 
