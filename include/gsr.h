@@ -380,8 +380,9 @@ GS_API size_t gs_views_workspace_size(int n_views, int64_t total_tiles);
  * cfg: raster geometry as for gs_rasterize.  clock (nullable, device uint64
  * [1 + n_views]): [0] receives the device wall clock at the start of the
  * launch, [1 + v] the clock when view v's last tile finished (the clock runs
- * at hipDeviceAttributeWallClockRate kHz).  Results are identical to calling
- * gs_rasterize once per view. */
+ * at hipDeviceAttributeWallClockRate kHz).  The work queue takes the views in
+ * order, each view's longest tile lists first, so views complete one after
+ * another.  Results are identical to calling gs_rasterize once per view. */
 GS_API gs_status gs_rasterize_views(const gs_view_target *views, const gs_view_target *d_views,
                              int n_views, const float *bg, const gs_raster_cfg *cfg,
                              uint64_t *clock, void *ws, size_t ws_bytes, void *stream);

@@ -323,6 +323,10 @@ gs_status lane_set(LaneSet **out) {
     return GS_OK;
 }
 
+// bits of the view index in the views queue's sort key (GS_MAX_VIEWS views)
+constexpr int kViewBits = 6;
+static_assert((1 << kViewBits) >= GS_MAX_VIEWS, "view index fits the key");
+
 gs_status rasterize_views(const gs_view_target *views, const gs_view_target *d_views, int n_views,
                           const float *bg, const gs_raster_cfg *cfg, uint64_t *clock, void *ws,
                           size_t ws_bytes, hipStream_t s, const char *who) {
@@ -363,7 +367,7 @@ gs_status rasterize_views(const gs_view_target *views, const gs_view_target *d_v
         // the item count is a host-known constant; the sort reads it from device memory
         k_set_count<<<1, 1, 0, s>>>(count, total);
         e = radix_sort_u32(w.key[0], w.val[0], w.key[1], w.val[1], w.key[2], w.val[2], count, total,
-                           24, w.hist, w.gsum, s);
+                           24 + kViewBits, w.hist, w.gsum, s);
     }
     if (e != hipSuccess) return hip_check(e, who);
     ViewsArgs q;

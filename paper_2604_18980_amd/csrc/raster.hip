@@ -409,10 +409,10 @@ hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStrea
 }
 
 // ------------------------------------------------------- many views at once
-// Work items are (view, tile) packed as view << 26 | tile, ordered longest
-// tile list first.  Waves (or workgroups) take the next item from a global
-// ticket until the queue is empty; the last item of each view stamps the
-// device clock so per-view latency can be read back.
+// Work items are (view, tile) packed as view << 26 | tile, ordered view by
+// view, each view's longest tile lists first.  Waves (or workgroups) take the
+// next item from a global ticket until the queue is empty; the last item of
+// each view stamps the device clock so per-view latency can be read back.
 
 __device__ __forceinline__ RasterArgs view_args(const ViewsArgs &q, int view) {
     const gs_view_target v = q.views[view];
@@ -439,8 +439,11 @@ __device__ __forceinline__ RasterArgs view_args(const ViewsArgs &q, int view) {
     return a;
 }
 
-// Plan: one item per (view, tile); key = complemented list length (24 bits)
-// so an ascending stable sort puts the longest lists first.
+// Plan: one item per (view, tile); key = view << 24 | complemented list length
+// (24 bits), so an ascending stable sort takes the views in order and each
+// view's longest lists first: views complete one after another (a view's
+// latency is its share of the queue, not the whole batch), and the queue's
+// tail is the last view's shortest lists.
 __global__ __launch_bounds__(256) void k_views_plan(const ViewsPlan p, const gs_view_target *views,
                                                     uint32_t *keys, uint32_t *vals) {
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
@@ -450,7 +453,7 @@ __global__ __launch_bounds__(256) void k_views_plan(const ViewsPlan p, const gs_
     const uint32_t t = i - p.tile_off[v];
     const uint32_t *r = views[v].ranges;
     const uint32_t len = r[2 * t + 1] - r[2 * t];
-    keys[i] = 0xFFFFFFu - (len < 0xFFFFFFu ? len : 0xFFFFFFu);
+    keys[i] = ((uint32_t)v << 24) | (0xFFFFFFu - (len < 0xFFFFFFu ? len : 0xFFFFFFu));
     vals[i] = ((uint32_t)v << 26) | t;
 }
 
