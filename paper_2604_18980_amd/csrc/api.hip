@@ -378,12 +378,16 @@ gs_status rasterize_views(const gs_view_target *views, const gs_view_target *d_v
     q.next = w.next;
     q.view_left = w.view_left;
     q.clock = clock;
-    static thread_local int grid_cache[5] = {0, 0, 0, 0, 0};
+    // persistent grid per (device, geometry), from the occupancy query
+    static thread_local int grid_cache[kMaxDevices][5];
     const int gi = c.threads_per_tile == 256   ? (c.lds_batch == 64 ? 1 : c.lds_batch == 128 ? 2 : 3)
                    : c.threads_per_tile == 128 ? 4
                                                : 0;
-    if (!grid_cache[gi]) grid_cache[gi] = raster_views_grid(c);
-    return hip_check(launch_raster_views(q, c, grid_cache[gi], s), who);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+    int &grid = grid_cache[dev][gi];
+    if (!grid) grid = raster_views_grid(c);
+    return hip_check(launch_raster_views(q, c, grid, s), who);
 }
 
 // Argument checks of gs_sort and gs_sort_noalloc (host only).
