@@ -286,7 +286,8 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_hist2(const uint32_t *pack
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const int k = threadIdx.x + i * kSortThreads;
-        w[i] = k < pb.cnt ? packed[pb.base + k] : 0u;
+        // (an index past the block's items reads the block's first item: pb.cnt >= 1)
+        w[i] = load_or_zero(packed + pb.base, (int64_t)k, (int64_t)pb.cnt);
     }
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i)

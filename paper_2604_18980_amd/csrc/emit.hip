@@ -59,12 +59,11 @@ __global__ __launch_bounds__(256) void k_vis_count(const uint32_t *tiles_touched
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nclear64; i += (int64_t)gridDim.x * 256)
         clear64[i] = 0ull;
     const int64_t base = (int64_t)blockIdx.x * kSortChunk + threadIdx.x;
-    uint32_t c = 0;
+    uint32_t t[kSortItems], c = 0;
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-        const int64_t g = base + (int64_t)i * 256;
-        c += (g < n && tiles_touched[g] > 0u) ? 1u : 0u;
-    }
+    for (int i = 0; i < kSortItems; ++i) t[i] = load_or_zero(tiles_touched, base + (int64_t)i * 256, n);
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) c += t[i] > 0u ? 1u : 0u;
     uint32_t tot;
     block_exclusive_scan<256, uint32_t>(c, wt, &tot);
     if (threadIdx.x == 0) vis_count[blockIdx.x] = tot;
@@ -85,11 +84,12 @@ __global__ __launch_bounds__(256) void k_vis_compact(const uint32_t *tiles_touch
     const int64_t wbase = b * kSortChunk + (int64_t)wid * (kSortItems * kWave) + lane;
     const uint64_t lt = lanemask_lt();
     uint64_t m[kSortItems];
-    uint32_t pos[kSortItems], wc = 0;
+    uint32_t t[kSortItems], pos[kSortItems], wc = 0;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) t[i] = load_or_zero(tiles_touched, wbase + 64 * i, n);
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
-        const int64_t g = wbase + 64 * i;
-        m[i] = __ballot(g < n && tiles_touched[g] > 0u);
+        m[i] = __ballot(t[i] > 0u);
         pos[i] = wc + (uint32_t)__popcll(m[i] & lt);
         wc += (uint32_t)__popcll(m[i]);
     }

@@ -260,6 +260,16 @@ __host__ __device__ __forceinline__ size_t plane_at(int k, int n, int g) {
 }
 
 // ------------------------------------------------------------ device helpers
+// p[i] for i < n, else zero, with the load made unconditionally (from p[0]
+// past the end, so p must hold at least one element): a load under a
+// per-lane condition compiles to a branch that waits for it, so a loop of
+// guarded loads would make one memory round trip per element.
+template <typename T>
+__device__ __forceinline__ T load_or_zero(const T *p, int64_t i, int64_t n) {
+    const T v = p[i < n ? i : 0];
+    return i < n ? v : (T)0;
+}
+
 // An empty asm that claims to modify x: the value must exist in a register at
 // this point, so the compiler neither sinks its computation nor recomputes it.
 __device__ __forceinline__ void pin_vgpr(float &x) { __asm__ volatile("" : "+v"(x)); }

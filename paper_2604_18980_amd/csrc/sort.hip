@@ -20,12 +20,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T *in, int64
         if (threadIdx.x == 0) parts[blockIdx.x] = 0;
         return;
     }
-    T acc = 0;
+    T v[kScanItems], acc = 0;
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        const int64_t idx = base + (int64_t)i * kScanThreads + threadIdx.x;
-        if (idx < m) acc += in[idx];
-    }
+    for (int i = 0; i < kScanItems; ++i) v[i] = load_or_zero(in, base + (int64_t)i * kScanThreads + threadIdx.x, m);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) acc += v[i];
     T tot;
     block_exclusive_scan<kScanThreads, T>(acc, wt, &tot);
     if (threadIdx.x == 0) parts[blockIdx.x] = (uint64_t)tot;
