@@ -101,12 +101,19 @@ __global__ __launch_bounds__(256) void k_vis_compact(const uint32_t *tiles_touch
         woff += w < wid ? s_wcnt[w] : 0u;
         tot += s_wcnt[w];
     }
+    // every depth requested before the first store (lanes without a visible
+    // Gaussian read Gaussian 0's: one line, shared)
+    uint32_t dk[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t g = ((m[i] >> lane) & 1ull) ? wbase + 64 * i : 0;
+        dk[i] = __float_as_uint(splats[(size_t)g * 12 + 6]);  // depth > 0.2: bits order = value order
+    }
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         if ((m[i] >> lane) & 1ull) {
-            const int64_t g = wbase + 64 * i;
-            dkey[woff + pos[i]] = __float_as_uint(splats[(size_t)g * 12 + 6]);  // depth > 0.2: bits order = value order
-            dval[woff + pos[i]] = (uint32_t)g;
+            dkey[woff + pos[i]] = dk[i];
+            dval[woff + pos[i]] = (uint32_t)(wbase + 64 * i);
         }
     }
     if (threadIdx.x == 0 && b == (int64_t)gridDim.x - 1) *num_vis = (int64_t)(before + tot);
