@@ -237,7 +237,9 @@ __device__ __forceinline__ uint64_t shape_pair_count(const float *splats, const 
     int x0 = 0, x1 = 0, ra = 0, rb = 0;
     if (valid) {
         const uint64_t r = rects[g];
-        if (e.setup(splats + (size_t)g * 12)) {
+        SplatRec rec = SplatRec::load(splats + (size_t)g * 12, Shape::kThird);
+        rec.pin(Shape::kThird);
+        if (e.setup(rec)) {
             x0 = (int)(r & 0xffff);
             x1 = (int)((r >> 32) & 0xffff);
             e.row_band((int)((r >> 16) & 0xffff), (int)(r >> 48), ra, rb);
@@ -503,9 +505,11 @@ __global__ __launch_bounds__(256) void k_emit_spans(const uint32_t *sorted_ids, 
         k = off[j];
         g = sorted_ids[j];
         const uint64_t r = rects[g];
+        SplatRec rec = SplatRec::load(splats + (size_t)g * 12, Shape::kThird);
+        rec.pin(Shape::kThird);
         x0 = (int)(r & 0xffff);
         x1 = (int)((r >> 32) & 0xffff);
-        if (k < (uint64_t)cap && e.setup(splats + (size_t)g * 12))
+        if (k < (uint64_t)cap && e.setup(rec))
             e.row_band((int)((r >> 16) & 0xffff), (int)(r >> 48), ra, rb);
     }
     uint32_t p;

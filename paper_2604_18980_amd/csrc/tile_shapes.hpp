@@ -73,16 +73,39 @@ __device__ __forceinline__ void rows_meeting(double ylo, double yhi, int y0, int
     rb = fhi < (double)y1 ? (fhi > (double)ra ? (int)fhi : ra) : y1;
 }
 
+// The fields of a 48-byte splat record a shape reads, requested together:
+// left alone, the compiler splits them over the setup's early exits and
+// sinks them below the caller's conditions, one memory trip each.  `pin`
+// (an empty asm claiming to modify every field) makes them all arrive at one
+// point, after the caller's other loads of the same Gaussian are issued.
+struct SplatRec {
+    float4 q0, q1, q2;  // (u, v, A, beta), (gamma, opacity, depth, threshold), (r, g, b, scale)
+    __device__ __forceinline__ static SplatRec load(const float *rec, bool third) {
+        const float4 *p = reinterpret_cast<const float4 *>(rec);
+        SplatRec r;
+        r.q0 = p[0];
+        r.q1 = p[1];
+        r.q2 = third ? p[2] : make_float4(0.f, 0.f, 0.f, 0.f);
+        return r;
+    }
+    __device__ __forceinline__ void pin(bool third) {
+        __asm__ volatile("" : "+v"(q0.x), "+v"(q0.y), "+v"(q0.z), "+v"(q0.w));
+        __asm__ volatile("" : "+v"(q1.x), "+v"(q1.y), "+v"(q1.w));
+        if (third) __asm__ volatile("" : "+v"(q2.w));
+    }
+};
+
 struct Ellipse {
     double u, v, A, beta, gamma, c, R, w;
+    static constexpr bool kThird = false;  // reads record words 0-7
 
     // False (no tiles) unless every value is finite, A, gamma > 0 and c > 0.
-    __device__ __forceinline__ bool setup(const float *rec) {
-        const double u_ = rec[0], v_ = rec[1], A_ = rec[2], beta_ = rec[3], gamma_ = rec[4];
+    __device__ __forceinline__ bool setup(const SplatRec &rec) {
+        const double u_ = rec.q0.x, v_ = rec.q0.y, A_ = rec.q0.z, beta_ = rec.q0.w, gamma_ = rec.q1.x;
         if (!(finite_d(u_) && finite_d(v_) && finite_d(A_) && finite_d(beta_) && finite_d(gamma_)))
             return false;
         if (!(A_ > 0.0 && gamma_ > 0.0)) return false;
-        const double c_ = 2.0 * log((double)rec[5] / (double)rec[7]);
+        const double c_ = 2.0 * log((double)rec.q1.y / (double)rec.q1.w);
         if (!(c_ > 0.0 && finite_d(c_))) return false;
         const double R_ = sqrt(c_ / gamma_);
         const double w_ = beta_ * sqrt((A_ * c_) / (gamma_ * (gamma_ + A_ * (beta_ * beta_))));
@@ -128,9 +151,11 @@ struct Ellipse {
 
 struct OrientedBox {
     double vx[4], vy[4], k[4], ymin, ymax;
+    static constexpr bool kThird = true;  // also reads word 11 (the scale)
 
-    __device__ __forceinline__ bool setup(const float *rec) {
-        const double u = rec[0], v = rec[1], A = rec[2], beta = rec[3], gamma = rec[4], s = rec[11];
+    __device__ __forceinline__ bool setup(const SplatRec &rec) {
+        const double u = rec.q0.x, v = rec.q0.y, A = rec.q0.z, beta = rec.q0.w, gamma = rec.q1.x,
+                     s = rec.q2.w;
         if (!(finite_d(u) && finite_d(v) && finite_d(A) && finite_d(beta) && finite_d(gamma) &&
               finite_d(s)))
             return false;
