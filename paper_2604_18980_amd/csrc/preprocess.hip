@@ -240,9 +240,18 @@ __device__ __forceinline__ void preprocess_exact(const PreprocessArgs &a, const 
     a.tiles_touched[g] = tiles;
 }
 
-constexpr int kPreRounds = 2;                  // Gaussians per thread in the float32 pass
-constexpr int kPreChunk = 256 * kPreRounds;    // Gaussians per prefilter block and list
-constexpr int kPreSub = kPreChunk / kWave;     // 64-Gaussian chunks per list
+// Threads per prefilter block: each takes kPreChunk / threads Gaussians, all
+// their parameters requested at once.  Measured on the 6M city frame: 256
+// (two per thread) 83 us, 128 (four) 87, 512 (one) 90.
+#ifndef GSR_PRE_THREADS
+#define GSR_PRE_THREADS 256
+#endif
+constexpr int kPreChunk = 512;                       // Gaussians per prefilter block and list
+constexpr int kPreThreads = GSR_PRE_THREADS;         // threads per prefilter block
+constexpr int kPreRounds = kPreChunk / kPreThreads;  // Gaussians per thread in the float32 pass
+constexpr int kPreWaves = kPreThreads / kWave;
+constexpr int kPreSub = kPreChunk / kWave;           // 64-Gaussian chunks per list
+static_assert(kPreChunk % kPreThreads == 0 && kPreThreads % kWave == 0, "whole rounds of whole waves");
 
 // List L holds the 64-Gaussian chunks c = L + k nlists (k = 0 .. kPreSub - 1,
 // those below the chunk count): spread over the whole index range, so each
@@ -286,7 +295,7 @@ __device__ __forceinline__ float4 *list_slot(const PreprocessArgs &a, int64_t L,
 // 48 bytes each, so they hold all of them), and their count into the rects
 // entry of the list's first Gaussian; pass 2 reads a list in full before it
 // writes any output.
-__global__ __launch_bounds__(256) void k_prefilter(const PreprocessArgs a, int64_t nlists) {
+__global__ __launch_bounds__(kPreThreads) void k_prefilter(const PreprocessArgs a, int64_t nlists) {
     __shared__ PreEntry q[kPreChunk];
     __shared__ uint32_t n1, n2;
     __shared__ float lut[kLutBins];
@@ -296,13 +305,13 @@ __global__ __launch_bounds__(256) void k_prefilter(const PreprocessArgs a, int64
     const int n = a.n;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int64_t L = blockIdx.x;
-    // round r, wave w: chunk k = r * 4 + w; every round's parameters are
+    // round r, wave w: chunk k = r * (waves per block) + w; every round's parameters are
     // requested before any is used
     float f[kPreRounds][11];
     int64_t gr[kPreRounds];
 #pragma unroll
     for (int r = 0; r < kPreRounds; ++r) {
-        gr[r] = list_chunk(L, r * 4 + wid, nlists) * kWave + lane;
+        gr[r] = list_chunk(L, r * kPreWaves + wid, nlists) * kWave + lane;
         const int g = gr[r] < n ? (int)gr[r] : 0;
         f[r][0] = a.means[g]; f[r][1] = a.means[plane_at(1, n, g)]; f[r][2] = a.means[plane_at(2, n, g)];
         f[r][3] = a.log_scales[g]; f[r][4] = a.log_scales[plane_at(1, n, g)];
@@ -329,7 +338,7 @@ __global__ __launch_bounds__(256) void k_prefilter(const PreprocessArgs a, int64
     }
     __syncthreads();
     const uint32_t c1 = n1;
-    for (uint32_t i0 = 0; i0 < c1; i0 += 256) {  // block-uniform
+    for (uint32_t i0 = 0; i0 < c1; i0 += kPreThreads) {  // block-uniform
         const uint32_t i = i0 + threadIdx.x;
         bool keep = false;
         PreEntry e{};
@@ -342,14 +351,14 @@ __global__ __launch_bounds__(256) void k_prefilter(const PreprocessArgs a, int64
             else
                 keep = true;
         }
-        // compaction in place: this round's kept entries land below i0 + 256,
+        // compaction in place: this round's kept entries land below i0 + kPreThreads,
         // after every entry of the round has been read
         __syncthreads();
         queue_push(keep, e, q, &n2);
         __syncthreads();
     }
     const uint32_t cnt = n2;
-    for (uint32_t i = threadIdx.x; i < cnt; i += 256) {
+    for (uint32_t i = threadIdx.x; i < cnt; i += kPreThreads) {
         float4 *o = list_slot(a, L, i, nlists);
         o[0] = q[i].a;
         o[1] = q[i].b;
@@ -489,7 +498,7 @@ hipError_t launch_preprocess(const PreprocessArgs &a, hipStream_t s) {
     const int64_t nlists = (nchunks + kPreSub - 1) / kPreSub;
     const int per = kListsPerBlock;
     const unsigned blocks = (unsigned)((nlists + per - 1) / per);
-    k_prefilter<<<(unsigned)nlists, 256, 0, s>>>(a, nlists);
+    k_prefilter<<<(unsigned)nlists, kPreThreads, 0, s>>>(a, nlists);
     switch (a.sh_degree) {
         case 0: k_preprocess<0><<<blocks, 256, 0, s>>>(a, nlists, per); break;
         case 1: k_preprocess<1><<<blocks, 256, 0, s>>>(a, nlists, per); break;
