@@ -284,7 +284,7 @@ hipError_t depth_sort(const Workspace &ws, const int64_t *count, hipStream_t s) 
     // dkey/dval[0] -> [1], [2] as the pass scratch; the group sums were cleared
     // by the visibility count
     return radix_sort_u32(ws.dkey[0], ws.dval[0], ws.dkey[1], ws.dval[1], ws.dkey[2], ws.dval[2], count,
-                          ws.nb_dpass * 1024, 32, ws.dhist, ws.dgsum, s, 0, 0, true);
+                          ws.nb_dpass * LsdSmall::chunk, 32, ws.dhist, ws.dgsum, s, 0, 0, true);
 }
 
 // ------------------------------------------------------------- tile ranges
