@@ -68,7 +68,7 @@ typedef enum {
     GS_ERR_INVALID_ARGUMENT = 1, /* a pointer, size or option is out of range */
     GS_ERR_CAPACITY = 2,         /* a caller buffer is too small */
     GS_ERR_HIP = 3,              /* a HIP runtime call failed (message has the HIP text) */
-    GS_ERR_UNSUPPORTED = 4       /* valid request this build does not implement */
+    GS_ERR_UNSUPPORTED = 4       /* valid request the library does not implement */
 } gs_status;
 
 #define GS_TILE 16
