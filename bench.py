@@ -63,7 +63,7 @@ LUT_DEPTH_MAX = 1200.0
 # HBM bytes of one AdaGScale-frame raster launch per extent rule, from rocprofv3
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (copy-calibrated; profiles/*_hbm_counters.md),
 # valid only for the rasterizer source they were taken with (None: not measured).
-RASTER_TRAFFIC = {"source_sha256_16": "bf48210a8988dc58", "bytes": {0: None, 1: (83.9 + 327.0) * 1e6}}
+RASTER_TRAFFIC = {"source_sha256_16": "c31948f44203c54e", "bytes": {0: None, 1: (85.2 + 327.9) * 1e6}}
 
 
 def log(*a):
@@ -879,7 +879,7 @@ def main():
                   "emission and sort entry points; plain = 3D-GS with the tile rectangle, "
                   "plain_ellipse = 3D-GS with the ellipse tile test",
         "stage_hbm": {k: {"achieved_GBs": v, "frac": v / PEAK_HBM_GBS} for k, v in stage_bw.items()},
-        "roofline": {"kernel": "k_raster_wave", "bound": "alu", "achieved": achieved,
+        "roofline": {"kernel": "k_raster_hybrid", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": raster_traffic(rule),
                      "basis": f"{FLOP_EVAL} FLOP x {W_ada['list_evaluations']} list evaluations E "

@@ -130,7 +130,8 @@ typedef struct {
 } gs_mode;
 
 /* Raster launch geometry.  Tiles stay 16x16 so pair sets are comparable.
- * Built: (64, 4, 64) one wave per tile, 4 pixels per lane (the default);
+ * Built: (64, 4, 64) one wave per tile, 4 pixels per lane (the default; the
+ * grid's last twentieth of the tiles, dispatched last, get two waves each);
  * (128, 2, 64) two waves per tile, 2 pixels per lane, each wave walking the
  * list for its 16x8 half; (256, 1, B) one 256-thread workgroup per tile
  * staging B in {64, 128, 256} records.  A zeroed struct (or NULL) selects the

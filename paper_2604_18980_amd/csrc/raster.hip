@@ -25,7 +25,10 @@
 //   leaves the batch's hit masks at once (its remaining hits would only
 //   evaluate stopped pixels).  The per-lane state fits 62 VGPRs, so eight
 //   waves per SIMD hide the LDS and exponential latencies.  No barriers:
-//   waves run and retire independently.
+//   waves run and retire independently.  The one-wave geometry's grid
+//   renders its last twentieth of the tiles (dispatched last) with two waves
+//   per tile, so the grid's final round holds shorter waves and ends closer
+//   together (k_raster_hybrid).
 #include "gsr_internal.hpp"
 #include "raster_cull.hpp"
 
@@ -135,6 +138,10 @@ __device__ __forceinline__ float wave_max(float v) {
 // Gaussian's weight, or T_up of its depth bin) is below a.skip_theta is
 // skipped (no colour, no T update, not a contributor); a.work, if set,
 // receives the skipped and kept blend counts.
+// The parked records of a block's four waves: one allocation shared by every
+// geometry a kernel instantiates.
+__shared__ float4 g_srec[4][64][3];
+
 template <int MODE, int NS = 4>
 __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile, int part = 0) {
     constexpr bool EV = MODE == 1 || MODE == 2;
@@ -142,7 +149,7 @@ __device__ __forceinline__ void tile_wave(const RasterArgs &a, int tile, int par
     // one 48-byte row per parked record (mean x, mean y, a, a beta | c,
     // log2 opacity, red, green | blue; BlendCoef), so the broadcast reads of a
     // record share one address register
-    __shared__ float4 srec[4][64][3];
+    float4 (&srec)[4][64][3] = g_srec;
     __shared__ uint32_t s_cal[MODE == 3 ? 4 : 1][64];   // MODE 3: depth bin of each slot
     __shared__ uint32_t s_cgid[MODE == 3 ? 4 : 1][64];  // MODE 3: Gaussian id of each slot
     __shared__ uint32_t s_lut[MODE == 3 ? 4 : 1][kLutBins];
@@ -378,6 +385,29 @@ __global__ __launch_bounds__(256) void k_raster_wave(const RasterArgs a) {
     tile_wave<MODE, NS>(a, tile, w % kParts);
 }
 
+// One wave per tile for tiles [0, t_split), two waves per tile (16x8 halves)
+// for the rest.  Blocks dispatch in index order, so the split tiles run last:
+// measured on the 6M city frame with the last twentieth split, 295 against
+// 300 us over five paired runs (a tenth or a fifth: no better).  Outputs are
+// those of either geometry, bit for bit.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_raster_hybrid(const RasterArgs a, int t_split) {
+    const int nt = a.tiles_x * a.tiles_y;
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int b1 = (t_split + 3) / 4;  // blocks of whole-tile waves
+    if ((int)blockIdx.x < b1) {        // block-uniform
+        const int tile = (int)blockIdx.x * 4 + wid;
+        if (tile >= t_split) return;
+        tile_wave<MODE, 4>(a, tile, 0);
+    } else {
+        const int w = ((int)blockIdx.x - b1) * 4 + wid;
+        const int tile = t_split + w / 2;
+        if (tile >= nt) return;
+        tile_wave<MODE, 2>(a, tile, w % 2);
+    }
+}
+constexpr int kHybridSplitDiv = 20;  // the last 1/20 of the tiles get two waves each
+
 hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStream_t s) {
     const unsigned tiles = (unsigned)a.tiles_x * (unsigned)a.tiles_y;
     if (a.lut_bits) {
@@ -400,10 +430,12 @@ hipError_t launch_raster(const RasterArgs &a, const gs_raster_cfg &cfg, hipStrea
         else
             k_raster_wave<0, 2><<<(tiles + 1) / 2, 256, 0, s>>>(a);
     } else {
+        const unsigned t_split = tiles - tiles / kHybridSplitDiv;
+        const unsigned grid = (t_split + 3) / 4 + ((tiles - t_split) * 2 + 3) / 4;
         if (a.n_evaluated)
-            k_raster_wave<1><<<(tiles + 3) / 4, 256, 0, s>>>(a);
+            k_raster_hybrid<1><<<grid, 256, 0, s>>>(a, (int)t_split);
         else
-            k_raster_wave<0><<<(tiles + 3) / 4, 256, 0, s>>>(a);
+            k_raster_hybrid<0><<<grid, 256, 0, s>>>(a, (int)t_split);
     }
     return hipGetLastError();
 }
